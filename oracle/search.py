@@ -1,0 +1,233 @@
+"""FP64 oracle of the global grid-correlation search (Sec. IV of the paper).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg may use this module; the HIP path never does.
+
+Readings of the paper taken here (each listed in the design notes):
+  * the deep-penetration value is -rho with rho = 50 (a penalty);
+  * S(y) = 1 iff min_i f_p(T_i^{-1} y) <= 0 (inside-inclusive);
+  * the score is the correlation C[d] = sum_k O[k] S[k + d] of Eq. (xcorr),
+    whose FFT form is F^{-1}(conj(F(O)) * F(S));
+  * the correlation is circular on the n^3 canvas (no anti-wrap padding);
+  * the swept grid is the one rotated: S_w is built once on a world lattice and
+    trilinearly resampled per rotation, while O and its spectrum stay fixed;
+  * anchor a = mean of the mesh vertices; canvas x_k = a + h (k - n/2);
+  * ties: lowest flat index (kz*n + ky)*n + kx inside a rotation, lowest
+    rotation index across rotations.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _clib
+
+
+@dataclass
+class GridParams:
+    """Table I values: tau_out1 = 0.5 mm, tau_in1 = 0.2 mm, penalty 50."""
+    tau_out1: float = 0.5
+    tau_in1: float = 0.2
+    rho: float = 50.0
+
+
+# ---------------------------------------------------------------- probe
+
+def probe_sdf(x, y, z, r: float, L: float):
+    """Capped-cylinder SDF f_p in the probe frame (tip disk at the origin, axis
+    +z, length L, radius r); negative inside.  Vectorised over numpy arrays."""
+    x, y, z = np.asarray(x, float), np.asarray(y, float), np.asarray(z, float)
+    q1 = np.hypot(x, y) - r
+    q2 = np.abs(z - 0.5 * L) - 0.5 * L
+    return np.minimum(np.maximum(q1, q2), 0.0) + np.hypot(np.maximum(q1, 0.0), np.maximum(q2, 0.0))
+
+
+def quat_to_mat(q) -> np.ndarray:
+    """R(q / |q|) for a quaternion (w, x, y, z)."""
+    q = np.asarray(q, dtype=np.float64)
+    w, x, y, z = q / np.linalg.norm(q)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+# ---------------------------------------------------------------- grids
+
+def anchor(vertices) -> np.ndarray:
+    """Geometry centre a: the mean of the mesh vertices (FP64)."""
+    return np.asarray(vertices, dtype=np.float64).mean(axis=0)
+
+
+def canvas_points(n: int, h: float, a) -> np.ndarray:
+    """x_k = a + h (k - n/2) for k in {0..n-1}^3, rows in flat order (kz, ky, kx)."""
+    k = np.arange(n, dtype=np.float64) - n / 2
+    kz, ky, kx = np.meshgrid(k, k, k, indexing="ij")
+    return np.stack([a[0] + h * kx, a[1] + h * ky, a[2] + h * kz], axis=-1).reshape(-1, 3)
+
+
+def lattice_edge(n: int) -> int:
+    """m = 2 ceil((sqrt(3) n + 2)/2): every rotated canvas point and its trilinear
+    taps fall inside the m^3 lattice."""
+    return 2 * math.ceil((math.sqrt(3.0) * n + 2.0) / 2.0)
+
+
+def object_points(vertices, faces, touchable, pts, prm: GridParams = GridParams()):
+    """O(x), f_o(x), d(x) at arbitrary points, brute force over every face;
+    inside = generalised winding number >= 1/2 (Sec. IV-A)."""
+    V = np.ascontiguousarray(vertices, dtype=np.float32)
+    F = np.ascontiguousarray(faces, dtype=np.int32)
+    T = None if touchable is None else np.ascontiguousarray(touchable, dtype=np.uint8)
+    P = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+    O = np.empty(len(P))
+    fo = np.empty(len(P))
+    d = np.empty(len(P))
+    _clib.lib().orc_object_points(_clib.ptr(V), len(V), _clib.ptr(F), len(F), _clib.ptr(T),
+                                  _clib.ptr(P), len(P), prm.tau_out1, prm.tau_in1, prm.rho,
+                                  _clib.ptr(O), _clib.ptr(fo), _clib.ptr(d))
+    return O, fo, d
+
+
+def object_grid(vertices, faces, touchable, n: int, h: float, prm: GridParams = GridParams(),
+                band: float | None = None):
+    """O[k] on the canvas (shape (n,n,n), index [kz,ky,kx]) with f_o and d.
+    Exact wherever the distances lie inside the band (default tau_out1 + h)."""
+    V = np.ascontiguousarray(vertices, dtype=np.float32)
+    F = np.ascontiguousarray(faces, dtype=np.int32)
+    T = None if touchable is None else np.ascontiguousarray(touchable, dtype=np.uint8)
+    a = np.ascontiguousarray(anchor(V))
+    band = prm.tau_out1 + h if band is None else band
+    O = np.empty(n ** 3)
+    fo = np.empty(n ** 3)
+    d = np.empty(n ** 3)
+    _clib.lib().orc_object_grid(_clib.ptr(V), len(V), _clib.ptr(F), len(F), _clib.ptr(T), n, h,
+                                _clib.ptr(a), prm.tau_out1, prm.tau_in1, prm.rho, band,
+                                _clib.ptr(O), _clib.ptr(fo), _clib.ptr(d))
+    sh = (n, n, n)
+    return O.reshape(sh), fo.reshape(sh), d.reshape(sh)
+
+
+def swept_points(poses, r: float, L: float, pts) -> np.ndarray:
+    """min_i f_p(T_i^{-1} y) at arbitrary world points, brute force (Sec. IV-A)."""
+    Pz = np.ascontiguousarray(poses, dtype=np.float32)
+    P = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+    out = np.empty(len(P))
+    _clib.lib().orc_swept_points(_clib.ptr(Pz), len(Pz), r, L, _clib.ptr(P), len(P), _clib.ptr(out))
+    return out
+
+
+def lattice_points(m: int, h: float, wc) -> np.ndarray:
+    """y_j = wc + h (j - m/2), rows in flat order (jz, jy, jx)."""
+    k = np.arange(m, dtype=np.float64) - m / 2
+    jz, jy, jx = np.meshgrid(k, k, k, indexing="ij")
+    return np.stack([wc[0] + h * jx, wc[1] + h * jy, wc[2] + h * jz], axis=-1).reshape(-1, 3)
+
+
+def swept_lattice(poses, r: float, L: float, m: int, h: float, wc, margin: float | None = None):
+    """min_i f_p on the m^3 world lattice (shape (m,m,m)); exact wherever it is
+    below `margin` (default h), +inf marks points farther than that from every
+    pose.  S_w = (result <= 0)."""
+    Pz = np.ascontiguousarray(poses, dtype=np.float32)
+    w = np.ascontiguousarray(wc, dtype=np.float64)
+    out = np.empty(m ** 3)
+    _clib.lib().orc_swept_lattice(_clib.ptr(Pz), len(Pz), r, L, m, h, _clib.ptr(w),
+                                  h if margin is None else margin, _clib.ptr(out))
+    return out.reshape(m, m, m)
+
+
+def swept_occupancy(minf) -> np.ndarray:
+    """S = 1 where the swept probe covers the point (f_p <= 0)."""
+    return (np.asarray(minf) <= 0.0).astype(np.float64)
+
+
+# ------------------------------------------------------ per-rotation score
+
+def resample(S_w: np.ndarray, q, n: int, h: float, a, wc) -> np.ndarray:
+    """S_r[k] = S_w at the world point R (x_k - a) + wc, trilinear on the
+    lattice y_j = wc + h (j - m/2), taps outside the lattice count as 0
+    (Sec. IV-D: rotate and resample by trilinear interpolation)."""
+    m = S_w.shape[0]
+    R = quat_to_mat(q)
+    k = np.arange(n, dtype=np.float64) - n / 2
+    kz, ky, kx = np.meshgrid(k, k, k, indexing="ij")
+    X = h * np.stack([kx, ky, kz], axis=-1).reshape(-1, 3)         # x_k - a
+    Y = X @ R.T + np.asarray(wc, dtype=np.float64)                 # world points
+    y0 = np.asarray(wc, dtype=np.float64) - h * (m / 2)
+    U = (Y - y0) / h                                               # lattice coords (x,y,z)
+    I = np.floor(U).astype(np.int64)
+    Fr = U - I
+    out = np.zeros(len(U))
+    for cz in (0, 1):
+        for cy in (0, 1):
+            for cx in (0, 1):
+                ix, iy, iz = I[:, 0] + cx, I[:, 1] + cy, I[:, 2] + cz
+                w = ((Fr[:, 0] if cx else 1 - Fr[:, 0]) * (Fr[:, 1] if cy else 1 - Fr[:, 1])
+                     * (Fr[:, 2] if cz else 1 - Fr[:, 2]))
+                ok = (ix >= 0) & (ix < m) & (iy >= 0) & (iy < m) & (iz >= 0) & (iz < m)
+                val = np.zeros(len(U))
+                val[ok] = S_w[iz[ok], iy[ok], ix[ok]]
+                out += w * val
+    return out.reshape(n, n, n)
+
+
+def correlate(O: np.ndarray, S: np.ndarray) -> np.ndarray:
+    """C[d] = sum_k O[k] S[(k + d) mod n], circular, unnormalised, computed as
+    F^{-1}(conj(F(O)) * F(S)) with numpy's FFT."""
+    n = O.shape
+    return np.fft.irfftn(np.conj(np.fft.rfftn(O)) * np.fft.rfftn(S), s=n, axes=(0, 1, 2))
+
+
+def correlate_direct(O: np.ndarray, S: np.ndarray) -> np.ndarray:
+    """The same correlation by its definition (Eq. xcorr), O(n^6): tiny grids only."""
+    n = O.shape[0]
+    C = np.zeros(O.shape)
+    for dz in range(n):
+        for dy in range(n):
+            for dx in range(n):
+                C[dz, dy, dx] = np.sum(O * np.roll(S, shift=(-dz, -dy, -dx), axis=(0, 1, 2)))
+    return C
+
+
+def peak(C: np.ndarray):
+    """(max score, lowest flat index among the maxima, signed shift (dx,dy,dz))."""
+    n = C.shape[0]
+    flat = int(np.argmax(C.ravel()))      # numpy returns the first maximum
+    kz, ky, kx = np.unravel_index(flat, C.shape)
+    d = np.array([kx, ky, kz], dtype=np.int64)
+    d = np.where(d >= n // 2, d - n, d)
+    return float(C.ravel()[flat]), flat, d
+
+
+def pose_from_shift(q, delta, a, wc, h: float):
+    """Object pose x -> R x + t of a peak: R = R(q), t = wc - R a + h R delta.
+    It turns sum_x O(x) S_w(R x + t) into sum_k O[k] S_r[k + delta] and reduces
+    to the translation of Sec. IV-B at R = I."""
+    R = quat_to_mat(q)
+    t = np.asarray(wc, float) - R @ np.asarray(a, float) + h * (R @ np.asarray(delta, float))
+    return R, t
+
+
+def score_rotation(O, S_w, q, n, h, a, wc):
+    """One rotation of the global search: resample, correlate, take the peak."""
+    C = correlate(O, resample(S_w, q, n, h, a, wc))
+    return peak(C)
+
+
+def score_rotations(O, S_w, so3, n, h, a, wc, indices=None):
+    """Scores, flat peak indices and signed shifts for the selected rotations."""
+    idx = range(len(so3)) if indices is None else indices
+    sc, fl, sh = [], [], []
+    for r in idx:
+        s, f, d = score_rotation(O, S_w, so3[r], n, h, a, wc)
+        sc.append(s)
+        fl.append(f)
+        sh.append(d)
+    return np.array(sc), np.array(fl, dtype=np.int64), np.array(sh, dtype=np.int64).reshape(-1, 3)
+
+
+def top_k(scores, K: int):
+    """Rotation indices of the K best scores: score descending, index ascending."""
+    s = np.asarray(scores, dtype=np.float64)
+    order = np.lexsort((np.arange(len(s)), -s))
+    return order[:K]
