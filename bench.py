@@ -1,0 +1,159 @@
+#!/usr/bin/env python3
+"""Throughput of the global SO(3) search on one MI355X.
+
+A step is one registration request through the whole hot path with its inputs
+already in HBM: object grid and spectrum, swept occupancy, every SO(3) sample
+scored (rotate + voxelise, forward FFT, spectral product, inverse FFT, argmax),
+poses, top-16.  Default workload: 128^3 canvas at 0.12 mm, 4096 SO(3) samples,
+2000 noisy probe poses, 10242-vertex perturbed-sphere mesh (synthetic).
+
+Prints one JSON line: value = rotations scored per second over the timed steps;
+roofline = the dominant per-rotation kernel's algorithmic HBM bytes per launch
+over its mean launch time (HIP events on the library's stream); cpu_baseline =
+the FP64 oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "SO(3) rotations scored/sec at 128^3 (GB/s vs HBM peak); p50/p99 request latency"
+KERNELS = {0: "k_rotvox_fwd_xy", 1: "k_zpass", 2: "k_inv_xy_argmax"}
+
+
+def workload_name(p, cfg):
+    return (f"config {cfg}: {p.n}^3 canvas, h {p.h} mm, {len(p.so3)} SO(3) samples, {len(p.poses)} probe poses, "
+            f"{len(p.vertices)}-vertex mesh")
+
+
+def cpu_baseline(p, n_sample: int):
+    """The FP64 oracle on its own: setup grids + n_sample strided rotations,
+    extrapolated linearly to the full rotation set."""
+    from oracle import search as S
+    t0 = time.perf_counter()
+    O, _, _ = S.object_grid(p.vertices, p.faces, p.touchable, p.n, p.h)
+    Sw = S.swept_occupancy(S.swept_lattice(p.poses, p.radius, p.length, S.lattice_edge(p.n), p.h, p.center))
+    t1 = time.perf_counter()
+    a = S.anchor(p.vertices)
+    M = len(p.so3)
+    idx = list(range(0, M, max(1, M // n_sample)))[:n_sample]
+    for r in idx:
+        S.score_rotation(O, Sw, p.so3[r], p.n, p.h, a, p.center)
+    t2 = time.perf_counter()
+    per_rot = (t2 - t1) / len(idx)
+    full = (t1 - t0) + M * per_rot
+    return {"value": M / full, "unit": "rotations/s", "cores": 1, "kind": "oracle",
+            "sample": (f"object grid + swept lattice ({t1 - t0:.2f} s) and {len(idx)} of {M} rotations "
+                       f"({per_rot:.3f} s each, single thread, numpy FFT in FP64), extrapolated to all {M}")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=8, help="oracle rotations in the CPU baseline (0: skip)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}); the search shards by rotation "
+              "range across GPUs, which this build does not launch.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2605_21398_amd as rd
+    import synth
+
+    rd.load_library()
+    torch.cuda.set_device(0)
+    p = synth.config_problem(args.config)
+    dev = lambda x, dt: torch.from_numpy(np.ascontiguousarray(x)).to("cuda", dt)
+    V, F, T = dev(p.vertices, torch.float32), dev(p.faces, torch.int32), dev(p.touchable, torch.uint8)
+    P, Q = dev(p.poses, torch.float32), dev(p.so3, torch.float32)
+    M = len(p.so3)
+    K_TOP = 16
+    stats = {k: [0.0, 0, 0] for k in KERNELS}
+    info = {}
+
+    def step(timing: bool):
+        h = rd.register_init(V, F, T, P, Q, p.n, p.h, p.center, p.radius, p.length)
+        if timing:
+            rd.register_set_timing(h, True)
+        sc, sh, po = rd.score_rotations(h)
+        top = rd.register_top_k(h, sc, K_TOP)
+        if timing:
+            for k, (ms, la, ro) in rd.register_get_timing(h).items():
+                stats[k][0] += ms
+                stats[k][1] += la
+                stats[k][2] += ro
+        info.update(rd.register_info(h))
+        rd.register_free(h)
+        return sc, top
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        step(True)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - s0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    value = args.steps * M / wall
+
+    H8 = info["spectrum_elems"] * 8
+    B = info["batch"]
+    per_rot = {0: H8, 1: 2 * H8, 2: H8}       # algorithmic HBM bytes per rotation
+    per_launch_extra = {0: 0, 1: H8, 2: 0}     # W read once per launch
+    kern = {}
+    for k, (ms, la, ro) in stats.items():
+        if la == 0:
+            continue
+        bytes_per_launch = (per_rot[k] * ro + per_launch_extra[k] * la) / la
+        avg_s = ms / la / 1e3
+        kern[KERNELS[k]] = {"avg_launch_ms": ms / la, "launches": la, "rotations_per_launch": ro / la,
+                            "algorithmic_bytes_per_launch": bytes_per_launch,
+                            "achieved_GBps": bytes_per_launch / avg_s / 1e9, "share_of_kernel_time": ms}
+    tot = sum(v["share_of_kernel_time"] for v in kern.values())
+    for v in kern.values():
+        v["share_of_kernel_time"] = v["share_of_kernel_time"] / tot
+    dom = max(kern, key=lambda k: kern[k]["share_of_kernel_time"])
+    d = kern[dom]
+    score_s = tot / 1e3 / args.steps
+    model_bytes = (4 * H8 + H8 / B) * M
+    out = {
+        "metric": METRIC, "value": value, "unit": "rotations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": workload_name(p, args.config), "n": p.n, "h_mm": p.h, "rotations": M,
+                   "poses": len(p.poses), "faces": len(p.faces), "batch": B, "top_k": K_TOP},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["achieved_GBps"], "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": d["achieved_GBps"] / HBM_PEAK_GBPS, "traffic": None},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)) * 1e3, "p99": float(np.percentile(lat, 99)) * 1e3,
+                       "mode": "serial, one request at a time"},
+        "score_phase": {"ms_per_step": score_s * 1e3, "rotations_per_s": M / score_s,
+                        "model_GBps": model_bytes / score_s / 1e9},
+        "kernels": kern,
+    }
+    if args.cpu_sample > 0:
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

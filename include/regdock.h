@@ -1,0 +1,172 @@
+/*
+ * regdock -- probe-aware contact registration by complementary-shape docking,
+ * global grid-correlation search on AMD MI355X (gfx950).
+ *
+ * Problem (Sec. III of the paper): a rigid probe of known shape is swept along
+ * a trajectory of N poses T_i in SE(3) near an object whose mesh is known; some
+ * poses touch the surface, none is known to.  Find the object pose T = (R, t)
+ * (body -> world) that best docks the object against the probe's swept volume.
+ *
+ * The search (Sec. IV): the object grid O = min(O_t, O_m) rewards voxels near
+ * the touchable surface, tolerates shallow penetration and penalises deep
+ * penetration; the swept occupancy S marks every voxel the probe covered.  For
+ * each SO(3) sample the swept grid is rotated by trilinear resampling, the
+ * circular correlation C[d] = sum_k O[k] S[k + d] (Eq. xcorr) is evaluated by
+ * 3D FFTs, and its maximum gives the best translation for that rotation.
+ *
+ * Conventions
+ *   - Every array argument is a DEVICE pointer (HBM) unless stated otherwise;
+ *     the caller owns it and may free it as soon as the call has returned and
+ *     the given stream has reached the call.  The library copies what it keeps.
+ *   - Quaternions are (w, x, y, z), scalar first.  Poses are rows
+ *     (qw, qx, qy, qz, tx, ty, tz) in millimetres.
+ *   - Grids are [z][y][x], x fastest; a canvas flat index is (kz*n + ky)*n + kx.
+ *   - Calls are enqueued on the handle's HIP stream; results are ready when the
+ *     stream reaches them.  A handle must not be used by two threads at once.
+ *   - Errors return a negative reg_status; register_last_error() gives a
+ *     thread-local message.  After REG_EDEVICE the handle is poisoned: every
+ *     later call on it returns REG_EDEVICE.
+ */
+#ifndef REGDOCK_H
+#define REGDOCK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    REG_OK = 0,
+    REG_EINVAL = -1,    /* bad argument: null pointer, size, non-finite value, non-unit quaternion */
+    REG_ENOMEM = -2,    /* device allocation failed */
+    REG_EDEVICE = -3,   /* a HIP call failed; the handle is poisoned */
+    REG_EBUSY = -4,     /* admission refused (server) */
+    REG_ENOTSUP = -5,   /* canvas edge n without a compiled plan */
+    REG_EAGAIN = -6,    /* result not ready (server poll) */
+    REG_ECANCELED = -7  /* request cancelled or timed out (server) */
+} reg_status;
+
+typedef struct reg_handle reg_handle;
+
+/* Object mesh in its body frame (Sec. IV-A: a watertight mesh for
+ * inside/outside and a touchable subset for the surface mask).
+ * vertices: n_vertices x 3 float (mm).  faces: n_faces x 3 int32 vertex ids,
+ * counter-clockwise seen from outside.  touchable: n_faces uint8 flags, NULL
+ * meaning every face is touchable. */
+typedef struct {
+    const float* vertices;
+    int32_t n_vertices;
+    const int32_t* faces;
+    int32_t n_faces;
+    const uint8_t* touchable;
+} reg_mesh;
+
+/* Flat-ended cylindrical probe (Sec. VI: cylindrical probe / bur).  In the
+ * probe frame the tip disk is centred at the origin and the axis is +z. */
+typedef struct {
+    double radius_mm;
+    double length_mm;
+} reg_probe;
+
+/* Common canvas of edge n at spacing h (Sec. IV-A/B).  The object canvas is
+ * x_k = a + h (k - n/2) with a the mean of the mesh vertices; the swept
+ * lattice is y_j = center_world + h (j - m/2), m = 2 ceil((sqrt(3) n + 2)/2).
+ * n must be one of 16, 32, 48, 60, 64, 80, 96, 120, 128, 160. */
+typedef struct {
+    int32_t n;
+    double h_mm;
+    double center_world[3];
+} reg_grid_spec;
+
+/* Zero (or a NULL params pointer) selects the default, Table I of the paper:
+ * tau_out1 0.5 mm, tau_in1 0.2 mm, deep-penetration penalty rho 50 (a deep voxel
+ * gets -rho), tau_out2 0.2 mm, tau_in2 0.03 mm, k 15, lambda 1e-3; bounds
+ * b_t 0.5 mm and b_r 0.2 rad and the query cutoff eps 0.25 mm are not given by
+ * the paper.  batch = rotations per batched launch (0: chosen from n). */
+typedef struct {
+    double tau_out1, tau_in1, rho;
+    double tau_out2, tau_in2, k, lambda;
+    double b_t, b_r, eps;
+    int32_t max_iters;
+    int32_t batch;
+} reg_params;
+
+/* Build a registration problem (Sec. IV-A): the object grid O and its spectrum
+ * conj(F(O))/n^3 (kept resident), the swept occupancy S_w of the trajectory on
+ * the world lattice, and the rotation matrices of the n_rot SO(3) samples.
+ *   poses: n_poses x 7 float, probe-local -> world.  so3: n_rot x 4 float unit
+ *   quaternions, object body -> world.  hip_stream: a hipStream_t, or NULL for
+ *   a stream the handle creates.  On success *out receives a new handle.
+ * Blocks until the input checks (finite values, face ids in range, quaternion
+ * norms within 1 +- 1e-3) have run on the device.
+ * Errors: REG_EINVAL, REG_ENOTSUP, REG_ENOMEM, REG_EDEVICE. */
+int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* poses, int32_t n_poses,
+                  const float* so3, int32_t n_rot, const reg_grid_spec* grid, const reg_params* params,
+                  void* hip_stream, reg_handle** out);
+
+/* Score SO(3) samples [first, first + count) (Sec. IV-B and IV-D).  For each
+ * rotation R: S_r[k] = trilinear S_w at R (x_k - a) + center_world; C = circular
+ * correlation of O with S_r; score = max C; d* = the lowest flat index among
+ * the maxima; shift = d* with components >= n/2 reduced by n.
+ *   out_score: count float.  out_shift: count x 3 int32 (x, y, z) or NULL.
+ *   out_pose: count x 7 double (unit quaternion, t) or NULL, with
+ *   t = center_world - R a + h R shift, so that x -> R x + t maps the object
+ *   body frame to world.  Asynchronous on the handle's stream.
+ * Errors: REG_EINVAL (range or null out_score), REG_EDEVICE. */
+int score_rotations(reg_handle* h, int32_t first, int32_t count, float* out_score, int32_t* out_shift,
+                    double* out_pose);
+
+/* The K best rotations of a score vector (score descending, index ascending),
+ * computed on the device.  scores: count float; out_idx: K int32.
+ * Errors: REG_EINVAL, REG_EDEVICE. */
+int register_top_k(reg_handle* h, const float* scores, int32_t count, int32_t K, int32_t* out_idx);
+
+/* Release a handle and every device buffer it owns (NULL is a no-op). */
+void register_free(reg_handle* h);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* register_last_error(void);
+
+/* Canvas edge, swept-lattice edge, spectrum elements per rotation, rotations
+ * per batched launch and number of rotations of a handle (any pointer may be
+ * NULL).  Host pointers. */
+int register_info(const reg_handle* h, int32_t* n, int32_t* m, int64_t* spectrum_elems, int32_t* batch, int32_t* n_rot);
+
+/* ---- measurement: per-kernel durations from HIP events ---- */
+
+/* enable != 0 records a HIP event pair around every launch of the three
+ * per-rotation kernels (0: rotate + voxelise + forward FFT in x and y;
+ * 1: z FFT, spectral product, inverse z FFT; 2: inverse FFT in y and x +
+ * argmax) on the handle's stream; any call resets the record.  Host call,
+ * synchronises the stream. */
+int register_set_timing(reg_handle* h, int32_t enable);
+
+/* Sums over the recorded launches since register_set_timing: ms[k] total
+ * milliseconds, launches[k] launch count, rotations[k] rotations processed, for
+ * k = 0, 1, 2 (host arrays of 3).  Synchronises the stream. */
+int register_get_timing(reg_handle* h, double* ms, int64_t* launches, int64_t* rotations);
+
+/* ---- test hooks: inspect or replace the per-problem grids ---- */
+
+/* Copy the object grid O (n^3 float) and its signed distance f_o (n^3 float,
+ * may be NULL) to device buffers. */
+int register_debug_object_grid(reg_handle* h, float* out_O, float* out_fo);
+
+/* Copy the swept occupancy S_w (m^3 uint8, 0/1) to a device buffer. */
+int register_debug_swept(reg_handle* h, uint8_t* out_Sw);
+
+/* Full correlation C (n^3 float) of SO(3) sample `rot` into a device buffer. */
+int register_debug_correlation(reg_handle* h, int32_t rot, float* out_C);
+
+/* Replace O (n^3 float, device) and/or S_w (m^3 uint8 0/1, device) of a
+ * handle by given grids (NULL keeps the current one); the spectrum and the
+ * corner masks are rebuilt.  Isolates the per-rotation path from threshold
+ * decisions taken while building the grids. */
+int register_set_grids(reg_handle* h, const float* O, const uint8_t* Sw);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REGDOCK_H */

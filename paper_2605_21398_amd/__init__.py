@@ -1,0 +1,244 @@
+"""Python binding of libregdock: the MI355X global search of probe-aware
+contact registration by complementary-shape docking (arxiv 2605.21398).
+
+The functions carry the names of the C ABI (include/regdock.h) and only
+marshal arguments: every step runs in the HIP kernels of libregdock.so.
+PyTorch provides device memory and the HIP stream.  There is no fallback:
+if the library is not built, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libregdock.so")
+
+REG_OK, REG_EINVAL, REG_ENOMEM, REG_EDEVICE, REG_EBUSY, REG_ENOTSUP, REG_EAGAIN, REG_ECANCELED = 0, -1, -2, -3, -4, -5, -6, -7
+_NAMES = {-1: "REG_EINVAL", -2: "REG_ENOMEM", -3: "REG_EDEVICE", -4: "REG_EBUSY", -5: "REG_ENOTSUP",
+          -6: "REG_EAGAIN", -7: "REG_ECANCELED"}
+
+# every entry point the header declares
+EXPORTS = ["register_init", "score_rotations", "register_top_k", "register_free", "register_last_error",
+           "register_info", "register_debug_object_grid", "register_debug_swept", "register_debug_correlation",
+           "register_set_grids", "register_set_timing", "register_get_timing"]
+
+
+class RegError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class reg_mesh(ctypes.Structure):
+    _fields_ = [("vertices", ctypes.c_void_p), ("n_vertices", ctypes.c_int32), ("faces", ctypes.c_void_p),
+                ("n_faces", ctypes.c_int32), ("touchable", ctypes.c_void_p)]
+
+
+class reg_probe(ctypes.Structure):
+    _fields_ = [("radius_mm", ctypes.c_double), ("length_mm", ctypes.c_double)]
+
+
+class reg_grid_spec(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("h_mm", ctypes.c_double), ("center_world", ctypes.c_double * 3)]
+
+
+class reg_params(ctypes.Structure):
+    _fields_ = [("tau_out1", ctypes.c_double), ("tau_in1", ctypes.c_double), ("rho", ctypes.c_double),
+                ("tau_out2", ctypes.c_double), ("tau_in2", ctypes.c_double), ("k", ctypes.c_double),
+                ("lambda_", ctypes.c_double), ("b_t", ctypes.c_double), ("b_r", ctypes.c_double),
+                ("eps", ctypes.c_double), ("max_iters", ctypes.c_int32), ("batch", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libregdock.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2605_21398_amd.build`")
+    L = ctypes.CDLL(path)
+    p, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.register_init.restype = ctypes.c_int
+    L.register_init.argtypes = [ctypes.POINTER(reg_mesh), ctypes.POINTER(reg_probe), p, i32, p, i32,
+                                ctypes.POINTER(reg_grid_spec), ctypes.POINTER(reg_params), p, ctypes.POINTER(p)]
+    L.score_rotations.restype = ctypes.c_int
+    L.score_rotations.argtypes = [p, i32, i32, p, p, p]
+    L.register_top_k.restype = ctypes.c_int
+    L.register_top_k.argtypes = [p, p, i32, i32, p]
+    L.register_free.restype = None
+    L.register_free.argtypes = [p]
+    L.register_last_error.restype = ctypes.c_char_p
+    L.register_last_error.argtypes = []
+    L.register_info.restype = ctypes.c_int
+    L.register_info.argtypes = [p, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64),
+                                ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.register_debug_object_grid.restype = ctypes.c_int
+    L.register_debug_object_grid.argtypes = [p, p, p]
+    L.register_debug_swept.restype = ctypes.c_int
+    L.register_debug_swept.argtypes = [p, p]
+    L.register_debug_correlation.restype = ctypes.c_int
+    L.register_debug_correlation.argtypes = [p, i32, p]
+    L.register_set_grids.restype = ctypes.c_int
+    L.register_set_grids.argtypes = [p, p, p]
+    L.register_set_timing.restype = ctypes.c_int
+    L.register_set_timing.argtypes = [p, i32]
+    L.register_get_timing.restype = ctypes.c_int
+    L.register_get_timing.argtypes = [p, p, p, p]
+    _lib = L
+    return L
+
+
+def register_last_error() -> str:
+    return load_library().register_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != REG_OK:
+        raise RegError(rc, register_last_error())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev(x, dtype):
+    """A contiguous device tensor of the given dtype (copies host data in)."""
+    torch = _torch()
+    if x is None:
+        return None
+    if not isinstance(x, torch.Tensor):
+        x = torch.from_numpy(np.ascontiguousarray(x))
+    return x.to(device="cuda", dtype=dtype).contiguous()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+@dataclass
+class Handle:
+    ptr: ctypes.c_void_p
+    n: int
+    m: int
+    H: int
+    batch: int
+    n_rot: int
+    stream: object
+
+    def __del__(self):
+        try:
+            if self.ptr:
+                load_library().register_free(self.ptr)
+                self.ptr = None
+        except Exception:
+            pass
+
+
+def register_init(vertices, faces, touchable, poses, so3, n: int, h_mm: float, center=(0.0, 0.0, 0.0),
+                  radius_mm: float = 0.5, length_mm: float = 8.0, params: dict | None = None, stream=None) -> Handle:
+    """Build a registration problem on the device (see register_init in the header)."""
+    torch = _torch()
+    L = load_library()
+    V = _dev(vertices, torch.float32)
+    F = _dev(faces, torch.int32)
+    T = _dev(touchable, torch.uint8)
+    P = _dev(poses, torch.float32)
+    Q = _dev(so3, torch.float32)
+    mesh = reg_mesh(_ptr(V).value, V.shape[0], _ptr(F).value, F.shape[0], _ptr(T).value if T is not None else None)
+    probe = reg_probe(radius_mm, length_mm)
+    grid = reg_grid_spec(n, h_mm, (ctypes.c_double * 3)(*[float(c) for c in center]))
+    prm = reg_params()
+    for k, v in (params or {}).items():
+        setattr(prm, "lambda_" if k == "lambda" else k, v)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    out = ctypes.c_void_p()
+    _check(L.register_init(ctypes.byref(mesh), ctypes.byref(probe), _ptr(P), P.shape[0], _ptr(Q), Q.shape[0],
+                           ctypes.byref(grid), ctypes.byref(prm), ctypes.c_void_p(st.cuda_stream), ctypes.byref(out)))
+    n_, m_, b_, r_ = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    H_ = ctypes.c_int64()
+    _check(L.register_info(out, ctypes.byref(n_), ctypes.byref(m_), ctypes.byref(H_), ctypes.byref(b_), ctypes.byref(r_)))
+    return Handle(out, n_.value, m_.value, H_.value, b_.value, r_.value, st)
+
+
+def score_rotations(h: Handle, first: int = 0, count: int | None = None, shift: bool = True, pose: bool = True,
+                    out=None):
+    """(scores f32 [count], shifts i32 [count,3] | None, poses f64 [count,7] | None) on the device."""
+    torch = _torch()
+    count = h.n_rot - first if count is None else count
+    if out is None:
+        sc = torch.empty(count, dtype=torch.float32, device="cuda")
+        sh = torch.empty((count, 3), dtype=torch.int32, device="cuda") if shift else None
+        po = torch.empty((count, 7), dtype=torch.float64, device="cuda") if pose else None
+    else:
+        sc, sh, po = out
+    _check(load_library().score_rotations(h.ptr, first, count, _ptr(sc), _ptr(sh), _ptr(po)))
+    return sc, sh, po
+
+
+def register_top_k(h: Handle, scores, K: int):
+    torch = _torch()
+    s = _dev(scores, torch.float32)
+    out = torch.empty(K, dtype=torch.int32, device="cuda")
+    _check(load_library().register_top_k(h.ptr, _ptr(s), s.shape[0], K, _ptr(out)))
+    return out
+
+
+def register_free(h: Handle):
+    if h.ptr:
+        load_library().register_free(h.ptr)
+        h.ptr = None
+
+
+def register_info(h: Handle) -> dict:
+    return dict(n=h.n, m=h.m, spectrum_elems=h.H, batch=h.batch, n_rot=h.n_rot)
+
+
+def register_debug_object_grid(h: Handle):
+    torch = _torch()
+    O = torch.empty((h.n,) * 3, dtype=torch.float32, device="cuda")
+    fo = torch.empty((h.n,) * 3, dtype=torch.float32, device="cuda")
+    _check(load_library().register_debug_object_grid(h.ptr, _ptr(O), _ptr(fo)))
+    return O, fo
+
+
+def register_debug_swept(h: Handle):
+    torch = _torch()
+    S = torch.empty((h.m,) * 3, dtype=torch.uint8, device="cuda")
+    _check(load_library().register_debug_swept(h.ptr, _ptr(S)))
+    return S
+
+
+def register_debug_correlation(h: Handle, rot: int):
+    torch = _torch()
+    C = torch.empty((h.n,) * 3, dtype=torch.float32, device="cuda")
+    _check(load_library().register_debug_correlation(h.ptr, rot, _ptr(C)))
+    return C
+
+
+def register_set_grids(h: Handle, O=None, Sw=None):
+    torch = _torch()
+    Ot = _dev(O, torch.float32) if O is not None else None
+    St = _dev(Sw, torch.uint8) if Sw is not None else None
+    _check(load_library().register_set_grids(h.ptr, _ptr(Ot), _ptr(St)))
+    torch.cuda.current_stream().synchronize()
+
+
+def register_set_timing(h: Handle, enable: bool = True):
+    _check(load_library().register_set_timing(h.ptr, 1 if enable else 0))
+
+
+def register_get_timing(h: Handle) -> dict:
+    """{kernel id: (total ms, launches, rotations)} for kernels 0, 1, 2."""
+    ms = (ctypes.c_double * 3)()
+    la = (ctypes.c_int64 * 3)()
+    ro = (ctypes.c_int64 * 3)()
+    _check(load_library().register_get_timing(h.ptr, ms, la, ro))
+    return {k: (ms[k], la[k], ro[k]) for k in range(3)}

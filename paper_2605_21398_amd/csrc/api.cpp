@@ -1,0 +1,401 @@
+// C ABI of libregdock: handles, validation, device buffers and the batched
+// launch sequence of the global search.  See include/regdock.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "regdock.h"
+#include "search_kernels.h"
+
+using namespace regdock;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int lattice_edge(int n) { return 2 * (int)std::ceil((std::sqrt(3.0) * n + 2.0) / 2.0); }
+
+}  // namespace
+
+struct reg_handle {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool poisoned = false;
+    int n = 0, m = 0, mp = 0, n_rot = 0, n_poses = 0, nv = 0, nf = 0, batch = 0;
+    size_t H = 0;
+    double h = 0, wc[3] = {0, 0, 0};
+    reg_probe probe{};
+    reg_params prm{};
+    // device buffers
+    float* V = nullptr;
+    int32_t* F = nullptr;
+    uint8_t* touch = nullptr;
+    float* poses = nullptr;
+    float* so3 = nullptr;
+    float* rots = nullptr;
+    float* pose_prep = nullptr;
+    double* anchor = nullptr;
+    float* O = nullptr;
+    float* fo = nullptr;
+    float2* W = nullptr;
+    float2* spec = nullptr;
+    unsigned long long* keys = nullptr;
+    uint8_t* Sw = nullptr;
+    uint8_t* cm = nullptr;
+    float2* tw = nullptr;
+    int* err = nullptr;
+    std::vector<void*> owned;
+    // optional per-kernel timing with HIP events on the handle's stream
+    bool timing = false;
+    struct Timed {
+        hipEvent_t a, b;
+        int kernel;
+        int rotations;
+    };
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> event_pool;
+    size_t pool_used = 0;
+    hipEvent_t next_event() {
+        if (pool_used == event_pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            event_pool.push_back(e);
+        }
+        return event_pool[pool_used++];
+    }
+
+    template <class T>
+    hipError_t alloc(T** p, size_t count) {
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, count * sizeof(T) > 0 ? count * sizeof(T) : 1);
+        if (e == hipSuccess) {
+            owned.push_back(q);
+            *p = (T*)q;
+        }
+        return e;
+    }
+    ~reg_handle() {
+        for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+        for (void* p : owned) (void)hipFree(p);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+#define DEV_TRY(hd, expr)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess) {                                                                  \
+            if (hd) (hd)->poisoned = true;                                                       \
+            return fail(REG_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));            \
+        }                                                                                        \
+    } while (0)
+
+#define ALLOC_TRY(hd, ptr, count)                                                                \
+    do {                                                                                         \
+        hipError_t e_ = (hd)->alloc(&(ptr), (count));                                            \
+        if (e_ != hipSuccess) {                                                                  \
+            (void)hipGetLastError();                                                             \
+            return fail(REG_ENOMEM, "device allocation of %zu elements for %s failed: %s",       \
+                        (size_t)(count), #ptr, hipGetErrorString(e_));                           \
+        }                                                                                        \
+    } while (0)
+
+static void fill_defaults(reg_params& p) {
+    if (p.tau_out1 <= 0) p.tau_out1 = 0.5;
+    if (p.tau_in1 <= 0) p.tau_in1 = 0.2;
+    if (p.rho <= 0) p.rho = 50.0;
+    if (p.tau_out2 <= 0) p.tau_out2 = 0.2;
+    if (p.tau_in2 <= 0) p.tau_in2 = 0.03;
+    if (p.k <= 0) p.k = 15.0;
+    if (p.lambda <= 0) p.lambda = 1e-3;
+    if (p.b_t <= 0) p.b_t = 0.5;
+    if (p.b_r <= 0) p.b_r = 0.2;
+    if (p.eps <= 0) p.eps = 0.25;
+    if (p.max_iters <= 0) p.max_iters = 200;
+}
+
+static int default_batch(int n, size_t H, int n_rot) {
+    // about 256 MB of spectrum work buffer, a multiple of 8 for the XCD mapping
+    size_t b = (256u << 20) / (H * sizeof(float2));
+    if (b < 8) b = 8;
+    if (b > 4096) b = 4096;
+    size_t need = ((size_t)n_rot + 7) / 8 * 8;
+    if (b > need) b = need;
+    b = (b + 7) / 8 * 8;
+    (void)n;
+    return (int)b;
+}
+
+static int build_spectrum(reg_handle* h) {
+    DEV_TRY(h, object_spectrum(h->n, h->O, h->spec, h->W, h->tw, h->stream));
+    return REG_OK;
+}
+
+extern "C" {
+
+const char* register_last_error(void) { return g_err.c_str(); }
+
+int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* poses, int32_t n_poses, const float* so3,
+                  int32_t n_rot, const reg_grid_spec* grid, const reg_params* params, void* hip_stream, reg_handle** out) {
+    g_err.clear();
+    if (!out) return fail(REG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!mesh || !probe || !poses || !so3 || !grid) return fail(REG_EINVAL, "NULL argument");
+    if (!mesh->vertices || !mesh->faces || mesh->n_vertices < 3 || mesh->n_faces < 1)
+        return fail(REG_EINVAL, "mesh needs >= 3 vertices and >= 1 face");
+    if (n_poses < 1 || n_rot < 1) return fail(REG_EINVAL, "n_poses and n_rot must be >= 1");
+    if (!(probe->radius_mm > 0) || !(probe->length_mm > 0) || !std::isfinite(probe->radius_mm) ||
+        !std::isfinite(probe->length_mm))
+        return fail(REG_EINVAL, "probe radius and length must be finite and > 0");
+    if (!(grid->h_mm > 0) || !std::isfinite(grid->h_mm)) return fail(REG_EINVAL, "grid h must be finite and > 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(grid->center_world[a])) return fail(REG_EINVAL, "grid center must be finite");
+    if (!canvas_supported(grid->n)) return fail(REG_ENOTSUP, "canvas edge n=%d has no compiled plan", grid->n);
+
+    reg_handle* h = new reg_handle();
+    struct Guard {
+        reg_handle*& p;
+        ~Guard() { delete p; }
+    } guard{h};
+
+    h->n = grid->n;
+    h->h = grid->h_mm;
+    for (int a = 0; a < 3; ++a) h->wc[a] = grid->center_world[a];
+    h->m = lattice_edge(h->n);
+    h->mp = (h->m + 3) / 4 * 4;
+    h->probe = *probe;
+    if (params) h->prm = *params;
+    fill_defaults(h->prm);
+    h->n_rot = n_rot;
+    h->n_poses = n_poses;
+    h->nv = mesh->n_vertices;
+    h->nf = mesh->n_faces;
+    h->H = spectrum_elems(h->n);
+    h->batch = h->prm.batch > 0 ? (h->prm.batch + 7) / 8 * 8 : default_batch(h->n, h->H, n_rot);
+
+    if (hip_stream) {
+        h->stream = (hipStream_t)hip_stream;
+    } else {
+        DEV_TRY(h, hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+        h->own_stream = true;
+    }
+    const size_t n3 = (size_t)h->n * h->n * h->n;
+    const size_t m3 = (size_t)h->m * h->m * h->m;
+    const size_t mp3 = (size_t)h->mp * h->mp * h->mp;
+    ALLOC_TRY(h, h->V, 3 * (size_t)h->nv);
+    ALLOC_TRY(h, h->F, 3 * (size_t)h->nf);
+    ALLOC_TRY(h, h->touch, (size_t)h->nf);
+    ALLOC_TRY(h, h->poses, 7 * (size_t)n_poses);
+    ALLOC_TRY(h, h->so3, 4 * (size_t)n_rot);
+    ALLOC_TRY(h, h->rots, 9 * (size_t)n_rot);
+    ALLOC_TRY(h, h->pose_prep, 12 * (size_t)n_poses);
+    ALLOC_TRY(h, h->anchor, 3);
+    ALLOC_TRY(h, h->O, n3);
+    ALLOC_TRY(h, h->fo, n3);
+    ALLOC_TRY(h, h->W, h->H);
+    ALLOC_TRY(h, h->spec, h->H * (size_t)h->batch);
+    ALLOC_TRY(h, h->keys, (size_t)h->batch);
+    ALLOC_TRY(h, h->Sw, m3);
+    ALLOC_TRY(h, h->cm, mp3);
+    ALLOC_TRY(h, h->tw, (size_t)h->n);
+    ALLOC_TRY(h, h->err, 1);
+
+    hipStream_t s = h->stream;
+    DEV_TRY(h, hipMemcpyAsync(h->V, mesh->vertices, 12 * (size_t)h->nv, hipMemcpyDeviceToDevice, s));
+    DEV_TRY(h, hipMemcpyAsync(h->F, mesh->faces, 12 * (size_t)h->nf, hipMemcpyDeviceToDevice, s));
+    if (mesh->touchable)
+        DEV_TRY(h, hipMemcpyAsync(h->touch, mesh->touchable, (size_t)h->nf, hipMemcpyDeviceToDevice, s));
+    else
+        DEV_TRY(h, hipMemsetAsync(h->touch, 1, (size_t)h->nf, s));
+    DEV_TRY(h, hipMemcpyAsync(h->poses, poses, 28 * (size_t)n_poses, hipMemcpyDeviceToDevice, s));
+    DEV_TRY(h, hipMemcpyAsync(h->so3, so3, 16 * (size_t)n_rot, hipMemcpyDeviceToDevice, s));
+
+    // twiddles exp(-2 pi i t / n) in double, rounded to float
+    std::vector<float2> tw(h->n);
+    for (int t = 0; t < h->n; ++t) {
+        const double ang = -2.0 * M_PI * (double)t / (double)h->n;
+        tw[t] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    DEV_TRY(h, hipMemcpyAsync(h->tw, tw.data(), sizeof(float2) * h->n, hipMemcpyHostToDevice, s));
+
+    // input checks on the device, then wait for them
+    DEV_TRY(h, hipMemsetAsync(h->err, 0, sizeof(int), s));
+    DEV_TRY(h, validate_inputs(h->V, h->nv, h->F, h->nf, h->poses, n_poses, h->err, s));
+    DEV_TRY(h, setup_rotations(h->so3, n_rot, h->rots, h->err, s));
+    int herr = 0;
+    DEV_TRY(h, hipMemcpyAsync(&herr, h->err, sizeof(int), hipMemcpyDeviceToHost, s));
+    DEV_TRY(h, hipStreamSynchronize(s));
+    if (herr & REGK_ERR_NONFINITE) return fail(REG_EINVAL, "non-finite vertex or pose value");
+    if (herr & REGK_ERR_FACE) return fail(REG_EINVAL, "face vertex index out of range");
+    if (herr & REGK_ERR_QUAT) return fail(REG_EINVAL, "quaternion norm outside 1 +- 1e-3 (or not finite)");
+
+    // object grid and spectrum (per object), swept occupancy (per request)
+    DEV_TRY(h, setup_anchor(h->V, h->nv, h->anchor, s));
+    DEV_TRY(h, setup_object_grid(h->V, h->F, h->touch, h->nf, h->n, h->h, h->anchor, (float)h->prm.tau_out1,
+                                 (float)h->prm.tau_in1, (float)h->prm.rho, h->O, h->fo, s));
+    int rc = build_spectrum(h);
+    if (rc) return rc;
+    DEV_TRY(h, setup_swept(h->poses, n_poses, (float)probe->radius_mm, (float)probe->length_mm, h->m, h->mp, h->h, h->wc,
+                           h->pose_prep, h->Sw, h->cm, s));
+    *out = h;
+    h = nullptr;  // release the guard
+    return REG_OK;
+}
+
+void register_free(reg_handle* h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    delete h;
+}
+
+int register_info(const reg_handle* h, int32_t* n, int32_t* m, int64_t* spectrum_elems_out, int32_t* batch, int32_t* n_rot) {
+    if (!h) return fail(REG_EINVAL, "NULL handle");
+    if (n) *n = h->n;
+    if (m) *m = h->m;
+    if (spectrum_elems_out) *spectrum_elems_out = (int64_t)h->H;
+    if (batch) *batch = h->batch;
+    if (n_rot) *n_rot = h->n_rot;
+    return REG_OK;
+}
+
+static int run_batches(reg_handle* h, int first, int count, float* out_score, int32_t* out_shift, double* out_pose,
+                       float* corr_out) {
+    for (int b0 = 0; b0 < count; b0 += h->batch) {
+        const int cnt = count - b0 < h->batch ? count - b0 : h->batch;
+        SearchBatchArgs a{};
+        a.cmask = h->cm;
+        a.m = h->m;
+        a.mp = h->mp;
+        a.rots = h->rots + 9 * (size_t)(first + b0);
+        a.count = cnt;
+        a.tw = h->tw;
+        a.spec = h->spec;
+        a.W = h->W;
+        a.keys = h->keys;
+        a.corr_out = corr_out;
+        a.stream = h->stream;
+        for (int pass = 0; pass < 3; ++pass) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (h->timing) {
+                e0 = h->next_event();
+                e1 = h->next_event();
+                if (!e0 || !e1) return fail(REG_EDEVICE, "hipEventCreate failed");
+                DEV_TRY(h, hipEventRecord(e0, h->stream));
+            }
+            DEV_TRY(h, search_pass(h->n, pass, a));
+            if (h->timing) {
+                DEV_TRY(h, hipEventRecord(e1, h->stream));
+                h->timed.push_back({e0, e1, pass, cnt});
+            }
+        }
+        DEV_TRY(h, finalize_batch(h->keys, cnt, h->so3 + 4 * (size_t)(first + b0), h->n, h->h, h->anchor, h->wc,
+                                  out_score ? out_score + b0 : nullptr, out_shift ? out_shift + 3 * (size_t)b0 : nullptr,
+                                  out_pose ? out_pose + 7 * (size_t)b0 : nullptr, h->stream));
+    }
+    return REG_OK;
+}
+
+int score_rotations(reg_handle* h, int32_t first, int32_t count, float* out_score, int32_t* out_shift, double* out_pose) {
+    g_err.clear();
+    if (!h) return fail(REG_EINVAL, "NULL handle");
+    if (h->poisoned) return fail(REG_EDEVICE, "handle poisoned by an earlier device error");
+    if (!out_score) return fail(REG_EINVAL, "out_score is NULL");
+    if (first < 0 || count < 0 || (int64_t)first + count > h->n_rot)
+        return fail(REG_EINVAL, "rotation range [%d, %d) outside [0, %d)", first, first + count, h->n_rot);
+    if (count == 0) return REG_OK;
+    return run_batches(h, first, count, out_score, out_shift, out_pose, nullptr);
+}
+
+int register_set_timing(reg_handle* h, int32_t enable) {
+    if (!h) return fail(REG_EINVAL, "NULL handle");
+    if (h->stream) DEV_TRY(h, hipStreamSynchronize(h->stream));
+    h->timing = enable != 0;
+    h->timed.clear();
+    h->pool_used = 0;
+    return REG_OK;
+}
+
+int register_get_timing(reg_handle* h, double* ms, int64_t* launches, int64_t* rotations) {
+    if (!h || !ms || !launches || !rotations) return fail(REG_EINVAL, "NULL argument");
+    DEV_TRY(h, hipStreamSynchronize(h->stream));
+    for (int k = 0; k < 3; ++k) {
+        ms[k] = 0;
+        launches[k] = 0;
+        rotations[k] = 0;
+    }
+    for (const auto& t : h->timed) {
+        float e = 0;
+        DEV_TRY(h, hipEventElapsedTime(&e, t.a, t.b));
+        ms[t.kernel] += e;
+        launches[t.kernel] += 1;
+        rotations[t.kernel] += t.rotations;
+    }
+    return REG_OK;
+}
+
+int register_top_k(reg_handle* h, const float* scores, int32_t count, int32_t K, int32_t* out_idx) {
+    g_err.clear();
+    if (!h) return fail(REG_EINVAL, "NULL handle");
+    if (h->poisoned) return fail(REG_EDEVICE, "handle poisoned by an earlier device error");
+    if (!scores || !out_idx || count < 1 || K < 1) return fail(REG_EINVAL, "bad top-k arguments");
+    DEV_TRY(h, top_k(scores, count, K, out_idx, h->stream));
+    return REG_OK;
+}
+
+int register_debug_object_grid(reg_handle* h, float* out_O, float* out_fo) {
+    if (!h || !out_O) return fail(REG_EINVAL, "NULL argument");
+    if (h->poisoned) return fail(REG_EDEVICE, "handle poisoned by an earlier device error");
+    const size_t n3 = (size_t)h->n * h->n * h->n;
+    DEV_TRY(h, hipMemcpyAsync(out_O, h->O, n3 * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    if (out_fo) DEV_TRY(h, hipMemcpyAsync(out_fo, h->fo, n3 * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    return REG_OK;
+}
+
+int register_debug_swept(reg_handle* h, uint8_t* out_Sw) {
+    if (!h || !out_Sw) return fail(REG_EINVAL, "NULL argument");
+    if (h->poisoned) return fail(REG_EDEVICE, "handle poisoned by an earlier device error");
+    const size_t m3 = (size_t)h->m * h->m * h->m;
+    DEV_TRY(h, hipMemcpyAsync(out_Sw, h->Sw, m3, hipMemcpyDeviceToDevice, h->stream));
+    return REG_OK;
+}
+
+int register_debug_correlation(reg_handle* h, int32_t rot, float* out_C) {
+    if (!h || !out_C) return fail(REG_EINVAL, "NULL argument");
+    if (h->poisoned) return fail(REG_EDEVICE, "handle poisoned by an earlier device error");
+    if (rot < 0 || rot >= h->n_rot) return fail(REG_EINVAL, "rotation %d outside [0, %d)", rot, h->n_rot);
+    return run_batches(h, rot, 1, nullptr, nullptr, nullptr, out_C);
+}
+
+int register_set_grids(reg_handle* h, const float* O, const uint8_t* Sw) {
+    if (!h) return fail(REG_EINVAL, "NULL handle");
+    if (h->poisoned) return fail(REG_EDEVICE, "handle poisoned by an earlier device error");
+    if (O) {
+        const size_t n3 = (size_t)h->n * h->n * h->n;
+        DEV_TRY(h, hipMemcpyAsync(h->O, O, n3 * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+        int rc = build_spectrum(h);
+        if (rc) return rc;
+    }
+    if (Sw) {
+        const size_t m3 = (size_t)h->m * h->m * h->m;
+        DEV_TRY(h, hipMemcpyAsync(h->Sw, Sw, m3, hipMemcpyDeviceToDevice, h->stream));
+        DEV_TRY(h, setup_cellmask(h->Sw, h->m, h->mp, h->cm, h->stream));
+    }
+    return REG_OK;
+}
+
+}  // extern "C"

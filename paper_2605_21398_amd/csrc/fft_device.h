@@ -1,0 +1,225 @@
+// Mixed-radix (2, 3, 4, 5, 8) complex FFTs on LDS-resident batches, for gfx950.
+//
+// The docking score of Sec. IV-B is a circular cross-correlation evaluated
+// through 3D FFTs (Eq. xcorr and the FFT identity that follows it).  This
+// header holds the building blocks: radix codelets in registers and a
+// Stockham autosort pass over a batch of transforms that live in LDS.
+//
+// A pass reads every butterfly input of the thread into registers, applies the
+// twiddles and the radix-R DFT, waits at a barrier and writes the outputs back
+// to the same LDS buffer, so a transform needs no second buffer.  All sizes are
+// compile-time constants; the per-thread butterfly loop is fully unrolled.
+//
+// Twiddles come from one table per canvas edge N: w[t] = exp(-2 pi i t / N),
+// t in [0, N), computed in double on the host and rounded to float.  A length
+// L that divides N reads w[t * (N / L)].
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace regdock {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 mul_mi(float2 a) {
+    return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// ---------------------------------------------------------------- codelets
+// DFT_R: X[k] = sum_r x[r] exp(-+2 pi i r k / R), sign - forward, + inverse.
+
+template <int R, bool INV> struct Dft;
+
+template <bool INV> struct Dft<2, INV> {
+    __device__ __forceinline__ static void run(float2* v) {
+        float2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+
+template <bool INV> struct Dft<3, INV> {
+    __device__ __forceinline__ static void run(float2* v) {
+        const float s3 = 0.866025403784438647f;  // sin(2 pi / 3)
+        float2 t1 = cadd(v[1], v[2]);
+        float2 t2 = csub(v[1], v[2]);
+        float2 x0 = v[0];
+        v[0] = cadd(x0, t1);
+        float2 m1 = make_float2(x0.x - 0.5f * t1.x, x0.y - 0.5f * t1.y);
+        float2 m2 = mul_mi<INV>(cscale(t2, s3));
+        v[1] = cadd(m1, m2);
+        v[2] = csub(m1, m2);
+    }
+};
+
+template <bool INV> struct Dft<4, INV> {
+    __device__ __forceinline__ static void run(float2* v) {
+        float2 t0 = cadd(v[0], v[2]);
+        float2 t1 = csub(v[0], v[2]);
+        float2 t2 = cadd(v[1], v[3]);
+        float2 t3 = mul_mi<INV>(csub(v[1], v[3]));
+        v[0] = cadd(t0, t2);
+        v[2] = csub(t0, t2);
+        v[1] = cadd(t1, t3);
+        v[3] = csub(t1, t3);
+    }
+};
+
+template <bool INV> struct Dft<5, INV> {
+    __device__ __forceinline__ static void run(float2* v) {
+        const float c1 = 0.309016994374947424f;   // cos(2 pi / 5)
+        const float c2 = -0.809016994374947424f;  // cos(4 pi / 5)
+        const float s1 = 0.951056516295153572f;   // sin(2 pi / 5)
+        const float s2 = 0.587785252292473129f;   // sin(4 pi / 5)
+        float2 x0 = v[0];
+        float2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+        float2 t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+        float2 a1 = make_float2(x0.x + c1 * t1.x + c2 * t2.x, x0.y + c1 * t1.y + c2 * t2.y);
+        float2 a2 = make_float2(x0.x + c2 * t1.x + c1 * t2.x, x0.y + c2 * t1.y + c1 * t2.y);
+        float2 b1 = make_float2(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y);
+        float2 b2 = make_float2(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y);
+        float2 ib1 = mul_mi<INV>(b1), ib2 = mul_mi<INV>(b2);
+        v[0] = cadd(x0, cadd(t1, t2));
+        v[1] = cadd(a1, ib1);
+        v[4] = csub(a1, ib1);
+        v[2] = cadd(a2, ib2);
+        v[3] = csub(a2, ib2);
+    }
+};
+
+template <bool INV> struct Dft<8, INV> {
+    // radix-2 butterflies on (x_j, x_{j+4}), twiddle W8^j on the differences,
+    // then a radix-4 DFT on each half: sums give even outputs, differences odd.
+    __device__ __forceinline__ static void run(float2* v) {
+        const float h = 0.707106781186547524f;
+        float2 a[4], b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            a[j] = cadd(v[j], v[j + 4]);
+            b[j] = csub(v[j], v[j + 4]);
+        }
+        // W8^1 = h (1 -+ i), W8^2 = -+ i, W8^3 = h (-1 -+ i)
+        b[1] = INV ? make_float2(h * (b[1].x - b[1].y), h * (b[1].x + b[1].y))
+                   : make_float2(h * (b[1].x + b[1].y), h * (b[1].y - b[1].x));
+        b[2] = mul_mi<INV>(b[2]);
+        b[3] = INV ? make_float2(-h * (b[3].x + b[3].y), h * (b[3].x - b[3].y))
+                   : make_float2(h * (b[3].y - b[3].x), -h * (b[3].x + b[3].y));
+        Dft<4, INV>::run(a);
+        Dft<4, INV>::run(b);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[2 * k] = a[k];
+            v[2 * k + 1] = b[k];
+        }
+    }
+};
+
+// ------------------------------------------------------- factorisation plan
+
+__host__ __device__ constexpr int fft_radix(int L, int p) {
+    // greedy: 8s, then a 4, then a 2, then 5s, then 3s
+    int i = 0;
+    while (L > 1) {
+        int r = (L % 8 == 0) ? 8 : (L % 4 == 0) ? 4 : (L % 2 == 0) ? 2 : (L % 5 == 0) ? 5 : (L % 3 == 0) ? 3 : 0;
+        if (r == 0) return 0;
+        if (i == p) return r;
+        L /= r;
+        ++i;
+    }
+    return 1;
+}
+
+__host__ __device__ constexpr int fft_npass(int L) {
+    int n = 0;
+    while (fft_radix(L, n) > 1) ++n;
+    return n;
+}
+
+__host__ __device__ constexpr bool fft_supported(int L) {
+    int n = 0;
+    while (L > 1) {
+        int r = fft_radix(L, 0);
+        if (r == 0) return false;
+        L /= r;
+        if (++n > 16) return false;
+    }
+    return true;
+}
+
+// ------------------------------------------------------------ Stockham pass
+//
+// Batch of NB transforms of length L in LDS: element e of transform b is at
+// buf[b * BS + e * ES].  Pass p (radix R, span NS = product of earlier radices)
+// maps butterfly j in [0, L/R):
+//   v[r] = x[j + r L/R] * w_{NS R}^{(j mod NS) r}
+//   v = DFT_R(v)
+//   x[(j / NS) NS R + (j mod NS) + r NS] = v[r]
+// BATCH_FAST selects which index varies fastest across consecutive threads:
+// the batch (columns of a row-major plane) or the butterfly (rows).
+
+template <int L, int R, int NS, bool INV, int NB, int NT, bool BATCH_FAST, int TWN>
+__device__ __forceinline__ void stockham_pass(float2* buf, int ES, int BS, const float2* __restrict__ tw) {
+    constexpr int NBF = L / R;
+    constexpr int TOT = NB * NBF;
+    constexpr int PER = (TOT + NT - 1) / NT;
+    constexpr int TWSTEP = (TWN / L) * (L / (NS * R));  // table stride per (j mod NS) * r
+    float2 v[PER][R];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int b = tid + i * NT;
+        if (PER * NT == TOT || b < TOT) {
+            const int bat = BATCH_FAST ? (b % NB) : (b / NBF);
+            const int j = BATCH_FAST ? (b / NB) : (b % NBF);
+            const float2* src = buf + bat * BS;
+            const int jm = j % NS;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float2 x = src[(j + r * NBF) * ES];
+                if (NS > 1 && r > 0) {
+                    const float2 w = tw[(jm * r * TWSTEP) % TWN];
+                    x = INV ? cmulc(x, w) : cmul(x, w);
+                }
+                v[i][r] = x;
+            }
+            Dft<R, INV>::run(v[i]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int b = tid + i * NT;
+        if (PER * NT == TOT || b < TOT) {
+            const int bat = BATCH_FAST ? (b % NB) : (b / NBF);
+            const int j = BATCH_FAST ? (b / NB) : (b % NBF);
+            float2* dst = buf + bat * BS;
+            const int jm = j % NS;
+            const int base = (j / NS) * NS * R + jm;
+#pragma unroll
+            for (int r = 0; r < R; ++r) dst[(base + r * NS) * ES] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <int L, bool INV, int NB, int NT, bool BATCH_FAST, int TWN, int P = 0, int NS = 1>
+__device__ __forceinline__ void fft_lds(float2* buf, int ES, int BS, const float2* __restrict__ tw) {
+    if constexpr (P < fft_npass(L)) {
+        constexpr int R = fft_radix(L, P);
+        stockham_pass<L, R, NS, INV, NB, NT, BATCH_FAST, TWN>(buf, ES, BS, tw);
+        fft_lds<L, INV, NB, NT, BATCH_FAST, TWN, P + 1, NS * R>(buf, ES, BS, tw);
+    }
+}
+
+}  // namespace regdock

@@ -1,0 +1,53 @@
+// Host-side launchers of the global-search kernels (internal to libregdock).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace regdock {
+
+enum : int {
+    REGK_ERR_NONFINITE = 1,
+    REGK_ERR_QUAT = 2,
+    REGK_ERR_FACE = 4,
+};
+
+struct SearchBatchArgs {
+    const uint8_t* cmask;      // bricked corner masks, mp^3 bytes
+    int m, mp;                 // lattice edge and its multiple-of-4 padding
+    const float* rots;         // [count][9] rotation matrices of this batch
+    int count;                 // rotations in this batch
+    const float2* tw;          // twiddles w[t] = exp(-2 pi i t / n), n entries
+    float2* spec;              // [count][H] spectrum work buffer
+    const float2* W;           // conj(F(O)) / n^3 in the tiled layout, H entries
+    unsigned long long* keys;  // [count] packed (score bits, ~flat index)
+    float* corr_out;           // optional: full correlation of a 1-rotation batch
+    hipStream_t stream;
+};
+
+bool canvas_supported(int n);
+size_t spectrum_elems(int n);
+int tile_width(int n);
+
+// pass 0: rotate+voxelise+FFT xy; 1: z FFT * W * z IFFT; 2: IFFT yx + argmax
+hipError_t search_pass(int n, int pass, const SearchBatchArgs& a);
+hipError_t object_spectrum(int n, const float* O, float2* spec_tmp, float2* W, const float2* tw, hipStream_t s);
+hipError_t setup_anchor(const float* V, int nv, double* anchor, hipStream_t s);
+hipError_t setup_object_grid(const float* V, const int32_t* F, const uint8_t* touch, int nf, int n, double h,
+                             const double* anchor, float tau_out1, float tau_in1, float rho, float* O, float* fo,
+                             hipStream_t s);
+hipError_t setup_swept(const float* poses, int np, float r, float L, int m, int mp, double h, const double* wc,
+                       float* pose_tmp, uint8_t* Sw, uint8_t* cm, hipStream_t s);
+hipError_t setup_cellmask(const uint8_t* Sw, int m, int mp, uint8_t* cm, hipStream_t s);
+hipError_t setup_rotations(const float* so3, int M, float* rots, int* err, hipStream_t s);
+hipError_t validate_inputs(const float* V, int nv, const int32_t* F, int nf, const float* poses, int np, int* err,
+                           hipStream_t s);
+hipError_t finalize_batch(const unsigned long long* keys, int count, const float* quats, int n, double h,
+                          const double* anchor, const double* wc, float* out_score, int32_t* out_shift, double* out_pose,
+                          hipStream_t s);
+
+}  // namespace regdock
+
+namespace regdock {
+hipError_t top_k(const float* scores, int count, int K, int32_t* out, hipStream_t s);
+}

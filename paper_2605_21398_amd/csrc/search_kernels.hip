@@ -1,0 +1,783 @@
+// HIP kernels of the global grid-correlation search (Sec. IV), for gfx950.
+//
+// Per registration problem (setup, off the per-rotation path):
+//   k_anchor         geometry centre a = mean of the mesh vertices (FP64)
+//   k_object_grid    O[k] = min(O_t, O_m) on the n^3 canvas x_k = a + h(k - n/2)
+//                    (Sec. IV-A: banded template of the signed distance, surface
+//                    mask of the touchable distance, element-wise minimum)
+//   k_pose_prep      probe poses -> rotation matrix + position (float)
+//   k_swept          S_w[j] = 1 iff min_i f_p(T_i^{-1} y_j) <= 0 on the m^3 world
+//                    lattice y_j = wc + h(j - m/2) (Sec. IV-A, swept occupancy)
+//   k_cellmask       8-bit corner masks of S_w, 4x4x4-bricked, so one byte load
+//                    gives all eight trilinear taps of a cell
+//   k_rot_prep       SO(3) samples -> rotation matrices; input validation
+//   pass1 + pass2(spectrum mode) on O   -> W = conj(F(O)) / n^3, kept resident
+//
+// Per rotation (the hot path; Sec. IV-B and IV-D):
+//   pass1  k_rotvox_fwd_xy   per (rotation, z-plane): rotate-and-voxelise the
+//                            swept grid by trilinear resampling, real-to-complex
+//                            FFT along x (half-length complex trick), complex FFT
+//                            along y, all in LDS; writes the plane into the
+//                            pencil-tiled spectrum layout
+//   pass2  k_zpass           per (rotation, tile of T z-pencils): FFT along z,
+//                            multiply by W, inverse FFT along z, in LDS
+//   pass3  k_inv_xy_argmax   per (rotation, z-plane): inverse FFT along y,
+//                            complex-to-real along x, plane max with the lowest
+//                            flat index; one 64-bit atomicMax per workgroup into
+//                            the rotation's key (orderable score bits, ~index)
+//   k_finalize               key -> score, shift, pose (FP64)
+//
+// Spectrum layout of one rotation (complex64, H = n (n/2 + 1) n elements):
+//   tile t in [0, n * (n/2)/T): ky = t / (n/2/T), kx in [(t % (n/2/T)) T, +T)
+//   tile t in [n (n/2)/T, +n/T): the Nyquist column kx = n/2, ky in a T-range
+//   inside a tile: [z][T] -- T consecutive complex per z (one 128-byte segment
+//   at T = 16), so pass 2 reads and writes whole tiles contiguously while pass 1
+//   and pass 3 move T-element segments per (row, plane).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_device.h"
+#include "search_kernels.h"
+
+namespace regdock {
+
+// ------------------------------------------------------------ canvas traits
+
+__host__ __device__ constexpr int largest_divisor_le(int v, int cap) {
+    for (int d = cap; d >= 1; --d)
+        if (v % d == 0) return d;
+    return 1;
+}
+
+template <int N> struct Canvas {
+    static constexpr int N2 = N / 2;
+    static constexpr int P = N2 + 1;                      // LDS row pitch (complex)
+    static constexpr int T = largest_divisor_le(N2, 16);  // tile width (complex)
+    static constexpr int NT2 = N2 / T;                    // main tiles per ky row
+    static constexpr int TILES = N * NT2 + N / T;         // tiles per rotation
+    static constexpr size_t H = (size_t)N * P * N;        // complex per rotation
+    static constexpr int NT = 256;                        // threads per workgroup
+    static_assert(N % 2 == 0, "canvas edge must be even");
+    static_assert(fft_supported(N) && fft_supported(N2), "edge must be 2^a 3^b 5^c");
+    static_assert((size_t)N * P * 8 <= 160 * 1024, "plane must fit in LDS");
+};
+
+// Workgroup -> (rotation, plane).  Workgroups are dealt round-robin to the 8
+// XCDs; when the batch is a multiple of 8, every plane of a rotation lands on
+// the same XCD so its L2 keeps that rotation's lattice footprint.
+__device__ __forceinline__ void map_plane_block(int bid, int count, int n, int& rot, int& z) {
+    if ((count & 7) == 0) {
+        const int xcd = bid & 7, local = bid >> 3;
+        rot = (local / n) * 8 + xcd;
+        z = local % n;
+    } else {
+        rot = bid / n;
+        z = bid % n;
+    }
+}
+
+// float -> unsigned bits whose unsigned order is the float order
+__device__ __forceinline__ uint32_t ordered_bits(float f) {
+    uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__host__ __device__ __forceinline__ float unordered_float(uint32_t o) {
+    uint32_t b = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+#ifdef __HIP_DEVICE_COMPILE__
+    return __uint_as_float(b);
+#else
+    float f;
+    __builtin_memcpy(&f, &b, 4);
+    return f;
+#endif
+}
+
+__device__ __forceinline__ size_t brick_index(int ix, int iy, int iz, int mb) {
+    return ((((size_t)(iz >> 2) * mb + (iy >> 2)) * mb + (ix >> 2)) << 6) + ((iz & 3) << 4) + ((iy & 3) << 2) + (ix & 3);
+}
+
+// Trilinear value of a binary lattice from the corner mask of the cell
+// (bit cx + 2 cy + 4 cz is the lattice value at (i + cx, j + cy, k + cz)).
+__device__ __forceinline__ float trilinear_mask(uint32_t mk, float fx, float fy, float fz) {
+    const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
+    const float b0 = (float)(mk & 1u), b1 = (float)((mk >> 1) & 1u), b2 = (float)((mk >> 2) & 1u), b3 = (float)((mk >> 3) & 1u);
+    const float b4 = (float)((mk >> 4) & 1u), b5 = (float)((mk >> 5) & 1u), b6 = (float)((mk >> 6) & 1u), b7 = (float)((mk >> 7) & 1u);
+    const float c00 = b0 * gx + b1 * fx, c10 = b2 * gx + b3 * fx;
+    const float c01 = b4 * gx + b5 * fx, c11 = b6 * gx + b7 * fx;
+    const float c0 = c00 * gy + c10 * fy, c1 = c01 * gy + c11 * fy;
+    return c0 * gz + c1 * fz;
+}
+
+// ------------------------------------------------------------- plane FFTs
+// The plane lives in LDS as [y][kx] with pitch P = N/2 + 1 complex.
+
+// Rows hold z[j] = s[2j] + i s[2j+1]; after the length-N/2 FFT, turn each row
+// into X[k], k in [0, N/2], of the length-N real FFT:
+//   X[k] = ((Z[k] + conj Z[N/2-k]) - i w^k (Z[k] - conj Z[N/2-k])) / 2.
+template <int N>
+__device__ __forceinline__ void r2c_post(float2* plane, const float2* tw) {
+    using C = Canvas<N>;
+    constexpr int Q = C::N2 / 2 + 1;
+    for (int e = threadIdx.x; e < N * Q; e += C::NT) {
+        const int y = e / Q, k = e % Q;
+        float2* row = plane + y * C::P;
+        if (k == 0) {
+            const float2 z0 = row[0];
+            row[0] = make_float2(z0.x + z0.y, 0.0f);
+            row[C::N2] = make_float2(z0.x - z0.y, 0.0f);
+        } else {
+            const int kk = C::N2 - k;
+            const float2 a = row[k], b = row[kk];
+            // pair k
+            float2 s = cadd(a, cconj(b)), d = csub(a, cconj(b));
+            float2 wd = cmul(tw[k], d);
+            float2 xk = make_float2(0.5f * (s.x + wd.y), 0.5f * (s.y - wd.x));
+            // pair N/2 - k
+            float2 s2 = cadd(b, cconj(a)), d2 = csub(b, cconj(a));
+            float2 wd2 = cmul(tw[kk], d2);
+            float2 xkk = make_float2(0.5f * (s2.x + wd2.y), 0.5f * (s2.y - wd2.x));
+            row[k] = xk;
+            row[kk] = xkk;
+        }
+    }
+    __syncthreads();
+}
+
+// Inverse of r2c_post (up to the factor 2 that makes the length-N/2 inverse
+// FFT below equal the unnormalised length-N inverse real FFT):
+//   Z[k] = (X[k] + conj X[N/2-k]) + i conj(w^k) (X[k] - conj X[N/2-k]).
+template <int N>
+__device__ __forceinline__ void c2r_pre(float2* plane, const float2* tw) {
+    using C = Canvas<N>;
+    constexpr int Q = C::N2 / 2 + 1;
+    for (int e = threadIdx.x; e < N * Q; e += C::NT) {
+        const int y = e / Q, k = e % Q;
+        float2* row = plane + y * C::P;
+        const int kk = C::N2 - k;
+        const float2 a = row[k], b = row[kk];
+        float2 s = cadd(a, cconj(b)), d = csub(a, cconj(b));
+        float2 wd = cmulc(d, tw[k]);
+        float2 zk = make_float2(s.x - wd.y, s.y + wd.x);
+        if (k == 0) {
+            row[0] = zk;
+        } else {
+            float2 s2 = cadd(b, cconj(a)), d2 = csub(b, cconj(a));
+            float2 wd2 = cmulc(d2, tw[kk]);
+            row[kk] = make_float2(s2.x - wd2.y, s2.y + wd2.x);
+            row[k] = zk;
+        }
+    }
+    __syncthreads();
+}
+
+// forward 2D real FFT of the packed plane (x then y) and write to the tiled spectrum
+template <int N>
+__device__ __forceinline__ void plane_forward_and_store(float2* plane, const float2* tw, float2* __restrict__ spec_rot, int z) {
+    using C = Canvas<N>;
+    fft_lds<C::N2, false, N, C::NT, false, N>(plane, 1, C::P, tw);
+    r2c_post<N>(plane, tw);
+    fft_lds<N, false, C::P, C::NT, true, N>(plane, C::P, 1, tw);
+    for (int e = threadIdx.x; e < N * C::N2; e += C::NT) {
+        const int ky = e / C::N2, kx = e % C::N2;
+        spec_rot[((size_t)(ky * C::NT2 + kx / C::T) * N + z) * C::T + (kx % C::T)] = plane[ky * C::P + kx];
+    }
+    float2* nyq = spec_rot + (size_t)N * C::N2 * N;
+    for (int ky = threadIdx.x; ky < N; ky += C::NT)
+        nyq[((size_t)(ky / C::T) * N + z) * C::T + (ky % C::T)] = plane[ky * C::P + C::N2];
+}
+
+// ------------------------------------------------------------------ pass 1
+
+template <int N>
+__global__ __launch_bounds__(256) void k_rotvox_fwd_xy(const uint8_t* __restrict__ cmask, int m, int mb,
+                                                       const float* __restrict__ rots, int count,
+                                                       const float2* __restrict__ twg, float2* __restrict__ spec,
+                                                       unsigned long long* __restrict__ keys) {
+    using C = Canvas<N>;
+    __shared__ float2 plane[N * C::P];
+    __shared__ float2 tw[N];
+    int rot, z;
+    map_plane_block(blockIdx.x, count, N, rot, z);
+    for (int i = threadIdx.x; i < N; i += C::NT) tw[i] = twg[i];
+    if (z == 0 && threadIdx.x == 0) keys[rot] = 0ull;
+    const float* R = rots + rot * 9;
+    const float r00 = R[0], r01 = R[1], r02 = R[2], r10 = R[3], r11 = R[4], r12 = R[5], r20 = R[6], r21 = R[7], r22 = R[8];
+    // u = R (k - N/2) + m/2 = x R e_x + y R e_y + base
+    const float hm = 0.5f * m, hn = 0.5f * N, zc = (float)z - hn;
+    const float bx = hm - hn * (r00 + r01) + zc * r02;
+    const float by = hm - hn * (r10 + r11) + zc * r12;
+    const float bz = hm - hn * (r20 + r21) + zc * r22;
+    for (int e = threadIdx.x; e < N * C::N2; e += C::NT) {
+        const int y = e / C::N2, j = e % C::N2;
+        float vals[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const float x = (float)(2 * j + s), yy = (float)y;
+            const float ux = fmaf(x, r00, fmaf(yy, r01, bx));
+            const float uy = fmaf(x, r10, fmaf(yy, r11, by));
+            const float uz = fmaf(x, r20, fmaf(yy, r21, bz));
+            const float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
+            const int ix = (int)fx0, iy = (int)fy0, iz = (int)fz0;
+            float v = 0.0f;
+            if (ix >= 0 && iy >= 0 && iz >= 0 && ix < m && iy < m && iz < m) {
+                const uint32_t mk = cmask[brick_index(ix, iy, iz, mb)];
+                v = trilinear_mask(mk, ux - fx0, uy - fy0, uz - fz0);
+            }
+            vals[s] = v;
+        }
+        plane[y * C::P + j] = make_float2(vals[0], vals[1]);
+    }
+    __syncthreads();
+    plane_forward_and_store<N>(plane, tw, spec + (size_t)rot * C::H, z);
+}
+
+// pass 1 on a real grid (the object grid O): same transform, no rotation
+template <int N>
+__global__ __launch_bounds__(256) void k_grid_fwd_xy(const float* __restrict__ grid, const float2* __restrict__ twg,
+                                                     float2* __restrict__ spec) {
+    using C = Canvas<N>;
+    __shared__ float2 plane[N * C::P];
+    __shared__ float2 tw[N];
+    const int z = blockIdx.x;
+    for (int i = threadIdx.x; i < N; i += C::NT) tw[i] = twg[i];
+    for (int e = threadIdx.x; e < N * C::N2; e += C::NT) {
+        const int y = e / C::N2, j = e % C::N2;
+        const float* row = grid + ((size_t)z * N + y) * N;
+        plane[y * C::P + j] = make_float2(row[2 * j], row[2 * j + 1]);
+    }
+    __syncthreads();
+    plane_forward_and_store<N>(plane, tw, spec, z);
+}
+
+// ------------------------------------------------------------------ pass 2
+// MODE 0: x <- IFFT_z(FFT_z(x) * W);  MODE 1: W <- conj(FFT_z(x)) * scale
+
+template <int N, int MODE>
+__global__ __launch_bounds__(256) void k_zpass(float2* __restrict__ spec, const float2* __restrict__ W, float2* __restrict__ wout,
+                                               const float2* __restrict__ twg, float scale) {
+    using C = Canvas<N>;
+    constexpr int E = N * C::T;
+    __shared__ float2 buf[E];
+    __shared__ float2 tw[N];
+    const int tile = blockIdx.x % C::TILES, rot = blockIdx.x / C::TILES;
+    float2* src = spec + (size_t)rot * C::H + (size_t)tile * E;
+    for (int i = threadIdx.x; i < N; i += C::NT) tw[i] = twg[i];
+    for (int i = threadIdx.x; i < E; i += C::NT) buf[i] = src[i];
+    __syncthreads();
+    fft_lds<N, false, C::T, C::NT, true, N>(buf, C::T, 1, tw);
+    if (MODE == 0) {
+        const float2* w = W + (size_t)tile * E;
+        for (int i = threadIdx.x; i < E; i += C::NT) buf[i] = cmul(buf[i], w[i]);
+        __syncthreads();
+        fft_lds<N, true, C::T, C::NT, true, N>(buf, C::T, 1, tw);
+        for (int i = threadIdx.x; i < E; i += C::NT) src[i] = buf[i];
+    } else {
+        float2* dst = wout + (size_t)tile * E;
+        for (int i = threadIdx.x; i < E; i += C::NT) dst[i] = cscale(cconj(buf[i]), scale);
+    }
+}
+
+// ------------------------------------------------------------------ pass 3
+
+template <int N>
+__global__ __launch_bounds__(256) void k_inv_xy_argmax(const float2* __restrict__ spec, int count, const float2* __restrict__ twg,
+                                                       unsigned long long* __restrict__ keys, float* __restrict__ corr_out) {
+    using C = Canvas<N>;
+    __shared__ float2 plane[N * C::P];
+    __shared__ float2 tw[N];
+    __shared__ unsigned long long wbest[C::NT / 64];
+    int rot, z;
+    map_plane_block(blockIdx.x, count, N, rot, z);
+    for (int i = threadIdx.x; i < N; i += C::NT) tw[i] = twg[i];
+    const float2* spec_rot = spec + (size_t)rot * C::H;
+    for (int e = threadIdx.x; e < N * C::N2; e += C::NT) {
+        const int ky = e / C::N2, kx = e % C::N2;
+        plane[ky * C::P + kx] = spec_rot[((size_t)(ky * C::NT2 + kx / C::T) * N + z) * C::T + (kx % C::T)];
+    }
+    const float2* nyq = spec_rot + (size_t)N * C::N2 * N;
+    for (int ky = threadIdx.x; ky < N; ky += C::NT)
+        plane[ky * C::P + C::N2] = nyq[((size_t)(ky / C::T) * N + z) * C::T + (ky % C::T)];
+    __syncthreads();
+    fft_lds<N, true, C::P, C::NT, true, N>(plane, C::P, 1, tw);
+    c2r_pre<N>(plane, tw);
+    fft_lds<C::N2, true, N, C::NT, false, N>(plane, 1, C::P, tw);
+    unsigned long long best = 0ull;
+    for (int e = threadIdx.x; e < N * C::N2; e += C::NT) {
+        const int y = e / C::N2, j = e % C::N2;
+        const float2 v = plane[y * C::P + j];
+        const uint32_t flat0 = (uint32_t)(((z * N) + y) * N + 2 * j);
+        const unsigned long long k0 = ((unsigned long long)ordered_bits(v.x) << 32) | (0xffffffffu - flat0);
+        const unsigned long long k1 = ((unsigned long long)ordered_bits(v.y) << 32) | (0xffffffffu - (flat0 + 1));
+        best = k0 > best ? k0 : best;
+        best = k1 > best ? k1 : best;
+        if (corr_out) {
+            corr_out[flat0] = v.x;
+            corr_out[flat0 + 1] = v.y;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(best, off, 64);
+        best = o > best ? o : best;
+    }
+    if ((threadIdx.x & 63) == 0) wbest[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long b = wbest[0];
+        for (int w = 1; w < C::NT / 64; ++w) b = wbest[w] > b ? wbest[w] : b;
+        atomicMax(keys + rot, b);
+    }
+}
+
+// ------------------------------------------------------------- finalize
+
+__global__ void k_finalize(const unsigned long long* __restrict__ keys, int count, const float* __restrict__ quats, int n,
+                           double h, const double* __restrict__ anchor, double wc0, double wc1, double wc2,
+                           float* __restrict__ out_score, int32_t* __restrict__ out_shift, double* __restrict__ out_pose) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const unsigned long long key = keys[i];
+    const float score = unordered_float((uint32_t)(key >> 32));
+    const uint32_t flat = 0xffffffffu - (uint32_t)(key & 0xffffffffu);
+    int d[3] = {(int)(flat % n), (int)((flat / n) % n), (int)(flat / ((uint32_t)n * n))};
+    for (int a = 0; a < 3; ++a)
+        if (d[a] >= n / 2) d[a] -= n;
+    if (out_score) out_score[i] = score;
+    if (out_shift) {
+        out_shift[3 * i] = d[0];
+        out_shift[3 * i + 1] = d[1];
+        out_shift[3 * i + 2] = d[2];
+    }
+    if (out_pose) {
+        double q[4] = {quats[4 * i], quats[4 * i + 1], quats[4 * i + 2], quats[4 * i + 3]};
+        const double nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        for (int a = 0; a < 4; ++a) q[a] /= nq;
+        const double w = q[0], x = q[1], y = q[2], zq = q[3];
+        const double Rm[9] = {1 - 2 * (y * y + zq * zq), 2 * (x * y - w * zq), 2 * (x * zq + w * y),
+                              2 * (x * y + w * zq), 1 - 2 * (x * x + zq * zq), 2 * (y * zq - w * x),
+                              2 * (x * zq - w * y), 2 * (y * zq + w * x), 1 - 2 * (x * x + y * y)};
+        const double wc[3] = {wc0, wc1, wc2};
+        double* o = out_pose + 7 * i;
+        for (int a = 0; a < 4; ++a) o[a] = q[a];
+        for (int r = 0; r < 3; ++r) {
+            double ra = 0, rd = 0;
+            for (int c = 0; c < 3; ++c) {
+                ra += Rm[3 * r + c] * anchor[c];
+                rd += Rm[3 * r + c] * (double)d[c];
+            }
+            o[4 + r] = wc[r] - ra + h * rd;
+        }
+    }
+}
+
+// ----------------------------------------------------------- setup kernels
+
+// a = mean of the vertices, one workgroup, fixed-order reduction in double
+__global__ __launch_bounds__(256) void k_anchor(const float* __restrict__ V, int nv, double* __restrict__ anchor) {
+    __shared__ double acc[3][256];
+    double s[3] = {0, 0, 0};
+    for (int i = threadIdx.x; i < nv; i += 256)
+        for (int a = 0; a < 3; ++a) s[a] += (double)V[3 * i + a];
+    for (int a = 0; a < 3; ++a) acc[a][threadIdx.x] = s[a];
+    __syncthreads();
+    for (int st = 128; st >= 1; st >>= 1) {
+        if (threadIdx.x < st)
+            for (int a = 0; a < 3; ++a) acc[a][threadIdx.x] += acc[a][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) anchor[threadIdx.x] = acc[threadIdx.x][0] / (double)nv;
+}
+
+// squared distance from p to triangle abc (closest-point case analysis of
+// Ericson, Real-Time Collision Detection, Sec. 5.1.5), float
+__device__ __forceinline__ float tri_dist2(float3 p, float3 a, float3 b, float3 c) {
+    const float3 ab = make_float3(b.x - a.x, b.y - a.y, b.z - a.z);
+    const float3 ac = make_float3(c.x - a.x, c.y - a.y, c.z - a.z);
+    const float3 ap = make_float3(p.x - a.x, p.y - a.y, p.z - a.z);
+    const float d1 = ab.x * ap.x + ab.y * ap.y + ab.z * ap.z;
+    const float d2 = ac.x * ap.x + ac.y * ap.y + ac.z * ap.z;
+    float3 q;
+    if (d1 <= 0.f && d2 <= 0.f) {
+        q = a;
+    } else {
+        const float3 bp = make_float3(p.x - b.x, p.y - b.y, p.z - b.z);
+        const float d3 = ab.x * bp.x + ab.y * bp.y + ab.z * bp.z;
+        const float d4 = ac.x * bp.x + ac.y * bp.y + ac.z * bp.z;
+        const float3 cp = make_float3(p.x - c.x, p.y - c.y, p.z - c.z);
+        const float d5 = ab.x * cp.x + ab.y * cp.y + ab.z * cp.z;
+        const float d6 = ac.x * cp.x + ac.y * cp.y + ac.z * cp.z;
+        const float vc = d1 * d4 - d3 * d2;
+        const float vb = d5 * d2 - d1 * d6;
+        const float va = d3 * d6 - d5 * d4;
+        if (d3 >= 0.f && d4 <= d3) {
+            q = b;
+        } else if (vc <= 0.f && d1 >= 0.f && d3 <= 0.f) {
+            const float v = d1 / (d1 - d3);
+            q = make_float3(a.x + v * ab.x, a.y + v * ab.y, a.z + v * ab.z);
+        } else if (d6 >= 0.f && d5 <= d6) {
+            q = c;
+        } else if (vb <= 0.f && d2 >= 0.f && d6 <= 0.f) {
+            const float w = d2 / (d2 - d6);
+            q = make_float3(a.x + w * ac.x, a.y + w * ac.y, a.z + w * ac.z);
+        } else if (va <= 0.f && (d4 - d3) >= 0.f && (d5 - d6) >= 0.f) {
+            const float w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+            q = make_float3(b.x + w * (c.x - b.x), b.y + w * (c.y - b.y), b.z + w * (c.z - b.z));
+        } else {
+            const float den = 1.0f / (va + vb + vc);
+            const float v = vb * den, w = vc * den;
+            q = make_float3(a.x + ab.x * v + ac.x * w, a.y + ab.y * v + ac.y * w, a.z + ab.z * v + ac.z * w);
+        }
+    }
+    const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// signed solid angle of abc seen from p (Van Oosterom & Strackee, 1983)
+__device__ __forceinline__ float solid_angle(float3 p, float3 a, float3 b, float3 c) {
+    const float3 ra = make_float3(a.x - p.x, a.y - p.y, a.z - p.z);
+    const float3 rb = make_float3(b.x - p.x, b.y - p.y, b.z - p.z);
+    const float3 rc = make_float3(c.x - p.x, c.y - p.y, c.z - p.z);
+    const float la = sqrtf(ra.x * ra.x + ra.y * ra.y + ra.z * ra.z);
+    const float lb = sqrtf(rb.x * rb.x + rb.y * rb.y + rb.z * rb.z);
+    const float lc = sqrtf(rc.x * rc.x + rc.y * rc.y + rc.z * rc.z);
+    const float num = ra.x * (rb.y * rc.z - rb.z * rc.y) + ra.y * (rb.z * rc.x - rb.x * rc.z) + ra.z * (rb.x * rc.y - rb.y * rc.x);
+    const float den = la * lb * lc + (ra.x * rb.x + ra.y * rb.y + ra.z * rb.z) * lc +
+                      (ra.x * rc.x + ra.y * rc.y + ra.z * rc.z) * lb + (rb.x * rc.x + rb.y * rc.y + rb.z * rc.z) * la;
+    return 2.0f * atan2f(num, den);
+}
+
+// banded template, surface mask and their minimum (Sec. IV-A)
+__device__ __forceinline__ float object_value(float fo, float dt, float tau_out1, float tau_in1, float rho) {
+    float ot;
+    if (fo >= 0.f && fo < tau_out1) ot = 1.0f - fo / tau_out1;
+    else if (fo < 0.f && fo > -tau_in1) ot = 1.0f + fo / tau_in1;
+    else if (fo <= -tau_in1) ot = -rho;
+    else ot = 0.0f;
+    const float om = fmaxf(0.0f, 1.0f - fabsf(dt) / tau_out1);
+    return fminf(ot, om);
+}
+
+// One voxel per thread; faces staged through LDS in chunks; brute force over
+// every face: nearest distance, nearest touchable distance, winding number.
+__global__ __launch_bounds__(256) void k_object_grid(const float* __restrict__ V, const int32_t* __restrict__ F,
+                                                     const uint8_t* __restrict__ touch, int nf, int n, double h,
+                                                     const double* __restrict__ anchor, float tau_out1, float tau_in1,
+                                                     float rho, float* __restrict__ O, float* __restrict__ fo_out) {
+    constexpr int CH = 256;
+    __shared__ float sv[CH][9];
+    __shared__ uint8_t st[CH];
+    const size_t n3 = (size_t)n * n * n;
+    const size_t id = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const bool live = id < n3;
+    const int kx = (int)(id % n), ky = (int)((id / n) % n), kz = (int)(id / ((size_t)n * n));
+    const double hn = 0.5 * n;
+    const float3 p = make_float3((float)(anchor[0] + h * (kx - hn)), (float)(anchor[1] + h * (ky - hn)),
+                                 (float)(anchor[2] + h * (kz - hn)));
+    float dmin = 3.0e38f, dtmin = 3.0e38f, omega = 0.0f;
+    for (int f0 = 0; f0 < nf; f0 += CH) {
+        __syncthreads();
+        const int f = f0 + threadIdx.x;
+        if (f < nf) {
+            for (int v = 0; v < 3; ++v) {
+                const int vi = F[3 * f + v];
+                sv[threadIdx.x][3 * v] = V[3 * vi];
+                sv[threadIdx.x][3 * v + 1] = V[3 * vi + 1];
+                sv[threadIdx.x][3 * v + 2] = V[3 * vi + 2];
+            }
+            st[threadIdx.x] = touch ? touch[f] : (uint8_t)1;
+        }
+        __syncthreads();
+        const int cnt = min(CH, nf - f0);
+        if (live) {
+            for (int i = 0; i < cnt; ++i) {
+                const float3 a = make_float3(sv[i][0], sv[i][1], sv[i][2]);
+                const float3 b = make_float3(sv[i][3], sv[i][4], sv[i][5]);
+                const float3 c = make_float3(sv[i][6], sv[i][7], sv[i][8]);
+                const float d2 = tri_dist2(p, a, b, c);
+                dmin = fminf(dmin, d2);
+                if (st[i]) dtmin = fminf(dtmin, d2);
+                omega += solid_angle(p, a, b, c);
+            }
+        }
+    }
+    if (!live) return;
+    const float dm = sqrtf(dmin), dt = sqrtf(dtmin);
+    const bool inside = omega >= 6.283185307179586f;  // winding number >= 1/2
+    const float fo = inside ? -dm : dm;
+    O[id] = object_value(fo, dt, tau_out1, tau_in1, rho);
+    if (fo_out) fo_out[id] = fo;
+}
+
+// poses (qw qx qy qz tx ty tz) -> R (row-major, from the normalised quaternion
+// in double) and p, 12 floats per pose
+__global__ void k_pose_prep(const float* __restrict__ poses, int np, float* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    double q[4] = {poses[7 * i], poses[7 * i + 1], poses[7 * i + 2], poses[7 * i + 3]};
+    const double nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const double w = q[0] / nq, x = q[1] / nq, y = q[2] / nq, z = q[3] / nq;
+    float* o = out + 12 * i;
+    o[0] = (float)(1 - 2 * (y * y + z * z)); o[1] = (float)(2 * (x * y - w * z)); o[2] = (float)(2 * (x * z + w * y));
+    o[3] = (float)(2 * (x * y + w * z)); o[4] = (float)(1 - 2 * (x * x + z * z)); o[5] = (float)(2 * (y * z - w * x));
+    o[6] = (float)(2 * (x * z - w * y)); o[7] = (float)(2 * (y * z + w * x)); o[8] = (float)(1 - 2 * (x * x + y * y));
+    o[9] = poses[7 * i + 4]; o[10] = poses[7 * i + 5]; o[11] = poses[7 * i + 6];
+}
+
+__device__ __forceinline__ float probe_sdf(float x, float y, float z, float r, float L) {
+    const float q1 = sqrtf(x * x + y * y) - r;
+    const float q2 = fabsf(z - 0.5f * L) - 0.5f * L;
+    const float a = fmaxf(q1, 0.f), b = fmaxf(q2, 0.f);
+    return fminf(fmaxf(q1, q2), 0.f) + sqrtf(a * a + b * b);
+}
+
+// S_w on the m^3 lattice; poses staged through LDS; one point per thread
+__global__ __launch_bounds__(256) void k_swept(const float* __restrict__ pz, int np, float r, float L, int m, double h,
+                                               double wc0, double wc1, double wc2, uint8_t* __restrict__ Sw) {
+    constexpr int CH = 256;
+    __shared__ float sp[CH][12];
+    const size_t m3 = (size_t)m * m * m;
+    const size_t id = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const bool live = id < m3;
+    const int jx = (int)(id % m), jy = (int)((id / m) % m), jz = (int)(id / ((size_t)m * m));
+    const double hm = 0.5 * m;
+    const float yx = (float)(wc0 + h * (jx - hm)), yy = (float)(wc1 + h * (jy - hm)), yz = (float)(wc2 + h * (jz - hm));
+    bool hit = false;
+    for (int p0 = 0; p0 < np; p0 += CH) {
+        __syncthreads();
+        if (p0 + threadIdx.x < np)
+            for (int a = 0; a < 12; ++a) sp[threadIdx.x][a] = pz[12 * (p0 + threadIdx.x) + a];
+        __syncthreads();
+        const int cnt = min(CH, np - p0);
+        if (live && !hit) {
+            for (int i = 0; i < cnt; ++i) {
+                const float* P = sp[i];
+                const float dx = yx - P[9], dy = yy - P[10], dz = yz - P[11];
+                const float lx = P[0] * dx + P[3] * dy + P[6] * dz;
+                const float ly = P[1] * dx + P[4] * dy + P[7] * dz;
+                const float lz = P[2] * dx + P[5] * dy + P[8] * dz;
+                if (probe_sdf(lx, ly, lz, r, L) <= 0.f) {
+                    hit = true;
+                    break;
+                }
+            }
+        }
+    }
+    if (live) Sw[id] = hit ? 1 : 0;
+}
+
+// corner masks over the padded, bricked lattice; taps beyond the lattice are 0
+__global__ void k_cellmask(const uint8_t* __restrict__ Sw, int m, int mp, uint8_t* __restrict__ cm) {
+    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t mp3 = (size_t)mp * mp * mp;
+    if (id >= mp3) return;
+    const int ix = (int)(id % mp), iy = (int)((id / mp) % mp), iz = (int)(id / ((size_t)mp * mp));
+    uint32_t mk = 0;
+    for (int c = 0; c < 8; ++c) {
+        const int x = ix + (c & 1), y = iy + ((c >> 1) & 1), z = iz + ((c >> 2) & 1);
+        if (x < m && y < m && z < m && Sw[((size_t)z * m + y) * m + x]) mk |= 1u << c;
+    }
+    cm[brick_index(ix, iy, iz, mp / 4)] = (uint8_t)mk;
+}
+
+// SO(3) samples -> rotation matrices (double math, float storage) + checks
+__global__ void k_rot_prep(const float* __restrict__ so3, int M, float* __restrict__ rots, int* __restrict__ err) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    double q[4] = {so3[4 * i], so3[4 * i + 1], so3[4 * i + 2], so3[4 * i + 3]};
+    const double n2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    const double nq = sqrt(n2);
+    if (!(nq >= 1.0 - 1e-3 && nq <= 1.0 + 1e-3)) atomicOr(err, REGK_ERR_QUAT);
+    const double w = q[0] / nq, x = q[1] / nq, y = q[2] / nq, z = q[3] / nq;
+    float* o = rots + 9 * i;
+    o[0] = (float)(1 - 2 * (y * y + z * z)); o[1] = (float)(2 * (x * y - w * z)); o[2] = (float)(2 * (x * z + w * y));
+    o[3] = (float)(2 * (x * y + w * z)); o[4] = (float)(1 - 2 * (x * x + z * z)); o[5] = (float)(2 * (y * z - w * x));
+    o[6] = (float)(2 * (x * z - w * y)); o[7] = (float)(2 * (y * z + w * x)); o[8] = (float)(1 - 2 * (x * x + y * y));
+}
+
+// finite vertices and poses, face indices in range, pose quaternions near unit
+__global__ void k_validate(const float* __restrict__ V, int nv, const int32_t* __restrict__ F, int nf,
+                           const float* __restrict__ poses, int np, int* __restrict__ err) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nv)
+        for (int a = 0; a < 3; ++a)
+            if (!isfinite(V[3 * i + a])) atomicOr(err, REGK_ERR_NONFINITE);
+    if (i < nf)
+        for (int a = 0; a < 3; ++a)
+            if (F[3 * i + a] < 0 || F[3 * i + a] >= nv) atomicOr(err, REGK_ERR_FACE);
+    if (i < np) {
+        double s = 0;
+        for (int a = 0; a < 7; ++a) {
+            if (!isfinite(poses[7 * i + a])) atomicOr(err, REGK_ERR_NONFINITE);
+            if (a < 4) s += (double)poses[7 * i + a] * poses[7 * i + a];
+        }
+        const double nq = sqrt(s);
+        if (!(nq >= 1.0 - 1e-3 && nq <= 1.0 + 1e-3)) atomicOr(err, REGK_ERR_QUAT);
+    }
+}
+
+// ------------------------------------------------------------- launchers
+
+template <int N>
+static hipError_t launch_search_pass(int pass, const SearchBatchArgs& a) {
+    using C = Canvas<N>;
+    if (pass == 0)
+        hipLaunchKernelGGL(k_rotvox_fwd_xy<N>, dim3(a.count * N), dim3(C::NT), 0, a.stream, a.cmask, a.m, a.mp / 4, a.rots,
+                           a.count, a.tw, a.spec, a.keys);
+    else if (pass == 1)
+        hipLaunchKernelGGL((k_zpass<N, 0>), dim3(a.count * C::TILES), dim3(C::NT), 0, a.stream, a.spec, a.W, nullptr, a.tw,
+                           1.0f);
+    else
+        hipLaunchKernelGGL(k_inv_xy_argmax<N>, dim3(a.count * N), dim3(C::NT), 0, a.stream, a.spec, a.count, a.tw, a.keys,
+                           a.corr_out);
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_object_spectrum(const float* O, float2* spec_tmp, float2* W, const float2* tw, hipStream_t s) {
+    using C = Canvas<N>;
+    hipLaunchKernelGGL(k_grid_fwd_xy<N>, dim3(N), dim3(C::NT), 0, s, O, tw, spec_tmp);
+    hipLaunchKernelGGL((k_zpass<N, 1>), dim3(C::TILES), dim3(C::NT), 0, s, spec_tmp, nullptr, W, tw,
+                       (float)(1.0 / ((double)N * N * N)));
+    return hipGetLastError();
+}
+
+#define REGDOCK_FOR_EACH_N(X) X(16) X(32) X(48) X(60) X(64) X(80) X(96) X(120) X(128) X(160)
+
+bool canvas_supported(int n) {
+    switch (n) {
+#define CASE(N) case N: return true;
+        REGDOCK_FOR_EACH_N(CASE)
+#undef CASE
+        default: return false;
+    }
+}
+
+size_t spectrum_elems(int n) {
+    switch (n) {
+#define CASE(N) case N: return Canvas<N>::H;
+        REGDOCK_FOR_EACH_N(CASE)
+#undef CASE
+        default: return 0;
+    }
+}
+
+int tile_width(int n) {
+    switch (n) {
+#define CASE(N) case N: return Canvas<N>::T;
+        REGDOCK_FOR_EACH_N(CASE)
+#undef CASE
+        default: return 0;
+    }
+}
+
+hipError_t search_pass(int n, int pass, const SearchBatchArgs& a) {
+    switch (n) {
+#define CASE(N) case N: return launch_search_pass<N>(pass, a);
+        REGDOCK_FOR_EACH_N(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t object_spectrum(int n, const float* O, float2* spec_tmp, float2* W, const float2* tw, hipStream_t s) {
+    switch (n) {
+#define CASE(N) case N: return launch_object_spectrum<N>(O, spec_tmp, W, tw, s);
+        REGDOCK_FOR_EACH_N(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t setup_object_grid(const float* V, const int32_t* F, const uint8_t* touch, int nf, int n, double h,
+                             const double* anchor, float tau_out1, float tau_in1, float rho, float* O, float* fo,
+                             hipStream_t s) {
+    const size_t n3 = (size_t)n * n * n;
+    hipLaunchKernelGGL(k_object_grid, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, V, F, touch, nf, n, h, anchor,
+                       tau_out1, tau_in1, rho, O, fo);
+    return hipGetLastError();
+}
+
+hipError_t setup_anchor(const float* V, int nv, double* anchor, hipStream_t s) {
+    hipLaunchKernelGGL(k_anchor, dim3(1), dim3(256), 0, s, V, nv, anchor);
+    return hipGetLastError();
+}
+
+hipError_t setup_swept(const float* poses, int np, float r, float L, int m, int mp, double h, const double* wc,
+                       float* pose_tmp, uint8_t* Sw, uint8_t* cm, hipStream_t s) {
+    hipLaunchKernelGGL(k_pose_prep, dim3((np + 255) / 256), dim3(256), 0, s, poses, np, pose_tmp);
+    const size_t m3 = (size_t)m * m * m;
+    hipLaunchKernelGGL(k_swept, dim3((unsigned)((m3 + 255) / 256)), dim3(256), 0, s, pose_tmp, np, r, L, m, h, wc[0], wc[1],
+                       wc[2], Sw);
+    const size_t mp3 = (size_t)mp * mp * mp;
+    hipLaunchKernelGGL(k_cellmask, dim3((unsigned)((mp3 + 255) / 256)), dim3(256), 0, s, Sw, m, mp, cm);
+    return hipGetLastError();
+}
+
+hipError_t setup_cellmask(const uint8_t* Sw, int m, int mp, uint8_t* cm, hipStream_t s) {
+    const size_t mp3 = (size_t)mp * mp * mp;
+    hipLaunchKernelGGL(k_cellmask, dim3((unsigned)((mp3 + 255) / 256)), dim3(256), 0, s, Sw, m, mp, cm);
+    return hipGetLastError();
+}
+
+hipError_t setup_rotations(const float* so3, int M, float* rots, int* err, hipStream_t s) {
+    hipLaunchKernelGGL(k_rot_prep, dim3((M + 255) / 256), dim3(256), 0, s, so3, M, rots, err);
+    return hipGetLastError();
+}
+
+hipError_t validate_inputs(const float* V, int nv, const int32_t* F, int nf, const float* poses, int np, int* err,
+                           hipStream_t s) {
+    const int mx = nv > nf ? (nv > np ? nv : np) : (nf > np ? nf : np);
+    hipLaunchKernelGGL(k_validate, dim3((mx + 255) / 256), dim3(256), 0, s, V, nv, F, nf, poses, np, err);
+    return hipGetLastError();
+}
+
+hipError_t finalize_batch(const unsigned long long* keys, int count, const float* quats, int n, double h,
+                          const double* anchor, const double* wc, float* out_score, int32_t* out_shift, double* out_pose,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3((count + 127) / 128), dim3(128), 0, s, keys, count, quats, n, h, anchor, wc[0], wc[1],
+                       wc[2], out_score, out_shift, out_pose);
+    return hipGetLastError();
+}
+
+}  // namespace regdock
+
+namespace regdock {
+
+// K best of a score vector: K rounds of a block-wide maximum over packed keys
+// (orderable score bits, ~index), each round taking the largest key below the
+// previous one.  Keys are unique, so the order is score descending, index
+// ascending.  Slots beyond count receive -1.
+__global__ __launch_bounds__(1024) void k_topk(const float* __restrict__ scores, int count, int K, int32_t* __restrict__ out) {
+    __shared__ unsigned long long wb[16];
+    __shared__ unsigned long long sel;
+    unsigned long long last = ~0ull;
+    for (int r = 0; r < K; ++r) {
+        unsigned long long best = 0ull;
+        for (int i = threadIdx.x; i < count; i += 1024) {
+            const unsigned long long key = ((unsigned long long)ordered_bits(scores[i]) << 32) | (0xffffffffu - (uint32_t)i);
+            if (key < last && key > best) best = key;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const unsigned long long o = __shfl_xor(best, off, 64);
+            best = o > best ? o : best;
+        }
+        if ((threadIdx.x & 63) == 0) wb[threadIdx.x >> 6] = best;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long b = wb[0];
+            for (int w = 1; w < 16; ++w) b = wb[w] > b ? wb[w] : b;
+            sel = b;
+            out[r] = (r < count) ? (int32_t)(0xffffffffu - (uint32_t)(b & 0xffffffffu)) : -1;
+        }
+        __syncthreads();
+        last = sel;
+    }
+}
+
+hipError_t top_k(const float* scores, int count, int K, int32_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, s, scores, count, K, out);
+    return hipGetLastError();
+}
+
+}  // namespace regdock
