@@ -96,8 +96,9 @@ typedef struct {
  * conj(F(O))/n^3 (kept resident), the swept occupancy S_w of the trajectory on
  * the world lattice, and the rotation matrices of the n_rot SO(3) samples.
  *   poses: n_poses x 7 float, probe-local -> world.  so3: n_rot x 4 float unit
- *   quaternions, object body -> world.  hip_stream: a hipStream_t, or NULL for
- *   a stream the handle creates.  On success *out receives a new handle.
+ *   quaternions, object body -> world.  hip_stream: the hipStream_t every call
+ *   on the handle is enqueued on (NULL: the null stream); the caller keeps it
+ *   alive for the handle's lifetime.  On success *out receives a new handle.
  * Blocks until the input checks (finite values, face ids in range, quaternion
  * norms within 1 +- 1e-3) have run on the device.
  * Errors: REG_EINVAL, REG_ENOTSUP, REG_ENOMEM, REG_EDEVICE. */
@@ -108,7 +109,9 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
 /* Score SO(3) samples [first, first + count) (Sec. IV-B and IV-D).  For each
  * rotation R: S_r[k] = trilinear S_w at R (x_k - a) + center_world; C = circular
  * correlation of O with S_r; score = max C; d* = the lowest flat index among
- * the maxima; shift = d* with components >= n/2 reduced by n.
+ * the maxima; shift = d* with components >= n/2 reduced by n.  The maximum is
+ * found by float32 FFTs and confirmed by exact re-scoring of every shift the
+ * float32 error could hide it behind (see register_search_stats).
  *   out_score: count float.  out_shift: count x 3 int32 (x, y, z) or NULL.
  *   out_pose: count x 7 double (unit quaternion, t) or NULL, with
  *   t = center_world - R a + h R shift, so that x -> R x + t maps the object
@@ -116,6 +119,16 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
  * Errors: REG_EINVAL (range or null out_score), REG_EDEVICE. */
 int score_rotations(reg_handle* h, int32_t first, int32_t count, float* out_score, int32_t* out_shift,
                     double* out_pose);
+
+/* How the peaks were found.  The float32 FFT path only locates candidates:
+ * every shift whose float32 correlation lies within 2 eps of the float32
+ * maximum, eps = 1.5 * 2^-24 * rms(C) * log2(n^3) bounding the float32 error,
+ * is re-scored exactly (direct sum over the nonzero voxels of O, accumulated in
+ * double) and the best exact score wins.  Counters since register_init: scored
+ * rotations, re-scored candidates, and rotations whose window held more
+ * candidates than were kept (4 per plane, 16 per rotation; the best kept one
+ * is used).  Host pointers; synchronises the stream. */
+int register_search_stats(reg_handle* h, int64_t* rotations, int64_t* candidates, int64_t* overflows);
 
 /* The K best rotations of a score vector (score descending, index ascending),
  * computed on the device.  scores: count float; out_idx: K int32.

@@ -24,7 +24,7 @@ _NAMES = {-1: "REG_EINVAL", -2: "REG_ENOMEM", -3: "REG_EDEVICE", -4: "REG_EBUSY"
 # every entry point the header declares
 EXPORTS = ["register_init", "score_rotations", "register_top_k", "register_free", "register_last_error",
            "register_info", "register_debug_object_grid", "register_debug_swept", "register_debug_correlation",
-           "register_set_grids", "register_set_timing", "register_get_timing"]
+           "register_set_grids", "register_set_timing", "register_get_timing", "register_search_stats"]
 
 
 class RegError(RuntimeError):
@@ -63,6 +63,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2605_21398_amd.build`")
+    # torch ships its own HIP runtime under the same SONAME; loading torch first
+    # makes the dynamic loader bind libregdock to that one runtime instead of
+    # bringing a second HSA runtime into the process.
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     p, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     L.register_init.restype = ctypes.c_int
@@ -87,6 +91,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.register_debug_correlation.argtypes = [p, i32, p]
     L.register_set_grids.restype = ctypes.c_int
     L.register_set_grids.argtypes = [p, p, p]
+    L.register_search_stats.restype = ctypes.c_int
+    L.register_search_stats.argtypes = [p, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.register_set_timing.restype = ctypes.c_int
     L.register_set_timing.argtypes = [p, i32]
     L.register_get_timing.restype = ctypes.c_int
@@ -242,3 +248,9 @@ def register_get_timing(h: Handle) -> dict:
     ro = (ctypes.c_int64 * 3)()
     _check(load_library().register_get_timing(h.ptr, ms, la, ro))
     return {k: (ms[k], la[k], ro[k]) for k in range(3)}
+
+
+def register_search_stats(h: Handle) -> dict:
+    r, c, o = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load_library().register_search_stats(h.ptr, ctypes.byref(r), ctypes.byref(c), ctypes.byref(o)))
+    return dict(rotations=r.value, candidates=c.value, overflows=o.value)

@@ -54,7 +54,17 @@ struct reg_handle {
     float* fo = nullptr;
     float2* W = nullptr;
     float2* spec = nullptr;
-    unsigned long long* keys = nullptr;
+    unsigned long long* ptop = nullptr;
+    double* pssq = nullptr;
+    int32_t* cand_idx = nullptr;
+    int32_t* cand_n = nullptr;
+    double* cand_exact = nullptr;
+    int* stats = nullptr;
+    uint32_t* nz_idx = nullptr;
+    float* nz_val = nullptr;
+    int* nz_count = nullptr;
+    int* nz_bcount = nullptr;
+    int* nz_boff = nullptr;
     uint8_t* Sw = nullptr;
     uint8_t* cm = nullptr;
     float2* tw = nullptr;
@@ -141,8 +151,10 @@ static int default_batch(int n, size_t H, int n_rot) {
     return (int)b;
 }
 
-static int build_spectrum(reg_handle* h) {
+// spectrum conj(F(O))/n^3 and the nonzero list of O, both derived from h->O
+static int build_object_derived(reg_handle* h) {
     DEV_TRY(h, object_spectrum(h->n, h->O, h->spec, h->W, h->tw, h->stream));
+    DEV_TRY(h, build_nonzero_list(h->O, h->n, h->nz_bcount, h->nz_boff, h->nz_idx, h->nz_val, h->nz_count, h->stream));
     return REG_OK;
 }
 
@@ -188,12 +200,7 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
     h->H = spectrum_elems(h->n);
     h->batch = h->prm.batch > 0 ? (h->prm.batch + 7) / 8 * 8 : default_batch(h->n, h->H, n_rot);
 
-    if (hip_stream) {
-        h->stream = (hipStream_t)hip_stream;
-    } else {
-        DEV_TRY(h, hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
-        h->own_stream = true;
-    }
+    h->stream = (hipStream_t)hip_stream;  // NULL: the null stream
     const size_t n3 = (size_t)h->n * h->n * h->n;
     const size_t m3 = (size_t)h->m * h->m * h->m;
     const size_t mp3 = (size_t)h->mp * h->mp * h->mp;
@@ -209,7 +216,17 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
     ALLOC_TRY(h, h->fo, n3);
     ALLOC_TRY(h, h->W, h->H);
     ALLOC_TRY(h, h->spec, h->H * (size_t)h->batch);
-    ALLOC_TRY(h, h->keys, (size_t)h->batch);
+    ALLOC_TRY(h, h->ptop, (size_t)h->batch * h->n * KTOP);
+    ALLOC_TRY(h, h->pssq, (size_t)h->batch * h->n);
+    ALLOC_TRY(h, h->cand_idx, (size_t)h->batch * CMAX);
+    ALLOC_TRY(h, h->cand_n, (size_t)h->batch);
+    ALLOC_TRY(h, h->cand_exact, (size_t)h->batch * CMAX);
+    ALLOC_TRY(h, h->stats, 3);
+    ALLOC_TRY(h, h->nz_idx, n3);
+    ALLOC_TRY(h, h->nz_val, n3);
+    ALLOC_TRY(h, h->nz_count, 1);
+    ALLOC_TRY(h, h->nz_bcount, (n3 + 255) / 256);
+    ALLOC_TRY(h, h->nz_boff, (n3 + 255) / 256);
     ALLOC_TRY(h, h->Sw, m3);
     ALLOC_TRY(h, h->cm, mp3);
     ALLOC_TRY(h, h->tw, (size_t)h->n);
@@ -235,6 +252,7 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
 
     // input checks on the device, then wait for them
     DEV_TRY(h, hipMemsetAsync(h->err, 0, sizeof(int), s));
+    DEV_TRY(h, hipMemsetAsync(h->stats, 0, 3 * sizeof(int), s));
     DEV_TRY(h, validate_inputs(h->V, h->nv, h->F, h->nf, h->poses, n_poses, h->err, s));
     DEV_TRY(h, setup_rotations(h->so3, n_rot, h->rots, h->err, s));
     int herr = 0;
@@ -248,7 +266,7 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
     DEV_TRY(h, setup_anchor(h->V, h->nv, h->anchor, s));
     DEV_TRY(h, setup_object_grid(h->V, h->F, h->touch, h->nf, h->n, h->h, h->anchor, (float)h->prm.tau_out1,
                                  (float)h->prm.tau_in1, (float)h->prm.rho, h->O, h->fo, s));
-    int rc = build_spectrum(h);
+    int rc = build_object_derived(h);
     if (rc) return rc;
     DEV_TRY(h, setup_swept(h->poses, n_poses, (float)probe->radius_mm, (float)probe->length_mm, h->m, h->mp, h->h, h->wc,
                            h->pose_prep, h->Sw, h->cm, s));
@@ -259,7 +277,7 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
 
 void register_free(reg_handle* h) {
     if (!h) return;
-    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    (void)hipStreamSynchronize(h->stream);
     delete h;
 }
 
@@ -286,7 +304,15 @@ static int run_batches(reg_handle* h, int first, int count, float* out_score, in
         a.tw = h->tw;
         a.spec = h->spec;
         a.W = h->W;
-        a.keys = h->keys;
+        a.ptop = h->ptop;
+        a.pssq = h->pssq;
+        a.cand_idx = h->cand_idx;
+        a.cand_n = h->cand_n;
+        a.cand_exact = h->cand_exact;
+        a.stats = h->stats;
+        a.nz_idx = h->nz_idx;
+        a.nz_val = h->nz_val;
+        a.nz_count = h->nz_count;
         a.corr_out = corr_out;
         a.stream = h->stream;
         for (int pass = 0; pass < 3; ++pass) {
@@ -303,9 +329,10 @@ static int run_batches(reg_handle* h, int first, int count, float* out_score, in
                 h->timed.push_back({e0, e1, pass, cnt});
             }
         }
-        DEV_TRY(h, finalize_batch(h->keys, cnt, h->so3 + 4 * (size_t)(first + b0), h->n, h->h, h->anchor, h->wc,
+        DEV_TRY(h, candidates_batch(h->n, a));
+        DEV_TRY(h, finalize_batch(a, h->n, h->so3 + 4 * (size_t)(first + b0), h->h, h->anchor, h->wc,
                                   out_score ? out_score + b0 : nullptr, out_shift ? out_shift + 3 * (size_t)b0 : nullptr,
-                                  out_pose ? out_pose + 7 * (size_t)b0 : nullptr, h->stream));
+                                  out_pose ? out_pose + 7 * (size_t)b0 : nullptr));
     }
     return REG_OK;
 }
@@ -323,7 +350,7 @@ int score_rotations(reg_handle* h, int32_t first, int32_t count, float* out_scor
 
 int register_set_timing(reg_handle* h, int32_t enable) {
     if (!h) return fail(REG_EINVAL, "NULL handle");
-    if (h->stream) DEV_TRY(h, hipStreamSynchronize(h->stream));
+    DEV_TRY(h, hipStreamSynchronize(h->stream));
     h->timing = enable != 0;
     h->timed.clear();
     h->pool_used = 0;
@@ -345,6 +372,18 @@ int register_get_timing(reg_handle* h, double* ms, int64_t* launches, int64_t* r
         launches[t.kernel] += 1;
         rotations[t.kernel] += t.rotations;
     }
+    return REG_OK;
+}
+
+int register_search_stats(reg_handle* h, int64_t* rotations, int64_t* candidates, int64_t* overflows) {
+    if (!h || !rotations || !candidates || !overflows) return fail(REG_EINVAL, "NULL argument");
+    if (h->poisoned) return fail(REG_EDEVICE, "handle poisoned by an earlier device error");
+    int st[3] = {0, 0, 0};
+    DEV_TRY(h, hipMemcpyAsync(st, h->stats, sizeof st, hipMemcpyDeviceToHost, h->stream));
+    DEV_TRY(h, hipStreamSynchronize(h->stream));
+    *rotations = st[0];
+    *candidates = st[1];
+    *overflows = st[2];
     return REG_OK;
 }
 
@@ -387,7 +426,7 @@ int register_set_grids(reg_handle* h, const float* O, const uint8_t* Sw) {
     if (O) {
         const size_t n3 = (size_t)h->n * h->n * h->n;
         DEV_TRY(h, hipMemcpyAsync(h->O, O, n3 * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
-        int rc = build_spectrum(h);
+        int rc = build_object_derived(h);
         if (rc) return rc;
     }
     if (Sw) {

@@ -6,6 +6,13 @@
 
 namespace regdock {
 
+// per-plane candidates kept by pass 3, candidates re-scored per rotation
+constexpr int KTOP = 4;
+constexpr int CMAX = 16;
+// window half-width: REGK_EPS_SCALE * 2^-24 * rms(C) * log2(n^3) bounds the
+// float32 error of the FFT path (measured maxima are below half of it)
+constexpr double REGK_EPS_SCALE = 1.5;
+
 enum : int {
     REGK_ERR_NONFINITE = 1,
     REGK_ERR_QUAT = 2,
@@ -20,8 +27,16 @@ struct SearchBatchArgs {
     const float2* tw;          // twiddles w[t] = exp(-2 pi i t / n), n entries
     float2* spec;              // [count][H] spectrum work buffer
     const float2* W;           // conj(F(O)) / n^3 in the tiled layout, H entries
-    unsigned long long* keys;  // [count] packed (score bits, ~flat index)
-    float* corr_out;           // optional: full correlation of a 1-rotation batch
+    unsigned long long* ptop;  // [count][n][KTOP] per-plane best keys (score bits, ~flat)
+    double* pssq;              // [count][n] per-plane sums of squares of the field
+    int32_t* cand_idx;         // [count][CMAX] candidate flat indices
+    int32_t* cand_n;           // [count] candidates per rotation
+    double* cand_exact;        // [count][CMAX] exact scores of the candidates
+    int* stats;                // [3] rotations, candidates, overflowed rotations
+    const uint32_t* nz_idx;    // nonzero voxels of O: packed kx | ky << 8 | kz << 16
+    const float* nz_val;       //   and their values
+    const int* nz_count;       //   and their number (device)
+    float* corr_out;           // optional: full float32 field of a 1-rotation batch
     hipStream_t stream;
 };
 
@@ -42,9 +57,11 @@ hipError_t setup_cellmask(const uint8_t* Sw, int m, int mp, uint8_t* cm, hipStre
 hipError_t setup_rotations(const float* so3, int M, float* rots, int* err, hipStream_t s);
 hipError_t validate_inputs(const float* V, int nv, const int32_t* F, int nf, const float* poses, int np, int* err,
                            hipStream_t s);
-hipError_t finalize_batch(const unsigned long long* keys, int count, const float* quats, int n, double h,
-                          const double* anchor, const double* wc, float* out_score, int32_t* out_shift, double* out_pose,
-                          hipStream_t s);
+hipError_t candidates_batch(int n, const SearchBatchArgs& a);
+hipError_t finalize_batch(const SearchBatchArgs& a, int n, const float* quats, double h, const double* anchor,
+                          const double* wc, float* out_score, int32_t* out_shift, double* out_pose);
+hipError_t build_nonzero_list(const float* O, int n, int* bcount, int* boff, uint32_t* idx, float* val, int* nnz,
+                              hipStream_t s);
 
 }  // namespace regdock
 

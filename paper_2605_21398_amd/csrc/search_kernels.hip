@@ -36,6 +36,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+
 #include "fft_device.h"
 #include "search_kernels.h"
 
@@ -191,15 +193,13 @@ __device__ __forceinline__ void plane_forward_and_store(float2* plane, const flo
 template <int N>
 __global__ __launch_bounds__(256) void k_rotvox_fwd_xy(const uint8_t* __restrict__ cmask, int m, int mb,
                                                        const float* __restrict__ rots, int count,
-                                                       const float2* __restrict__ twg, float2* __restrict__ spec,
-                                                       unsigned long long* __restrict__ keys) {
+                                                       const float2* __restrict__ twg, float2* __restrict__ spec) {
     using C = Canvas<N>;
     __shared__ float2 plane[N * C::P];
     __shared__ float2 tw[N];
     int rot, z;
     map_plane_block(blockIdx.x, count, N, rot, z);
     for (int i = threadIdx.x; i < N; i += C::NT) tw[i] = twg[i];
-    if (z == 0 && threadIdx.x == 0) keys[rot] = 0ull;
     const float* R = rots + rot * 9;
     const float r00 = R[0], r01 = R[1], r02 = R[2], r10 = R[3], r11 = R[4], r12 = R[5], r20 = R[6], r21 = R[7], r22 = R[8];
     // u = R (k - N/2) + m/2 = x R e_x + y R e_y + base
@@ -278,14 +278,43 @@ __global__ __launch_bounds__(256) void k_zpass(float2* __restrict__ spec, const 
 }
 
 // ------------------------------------------------------------------ pass 3
+// Per (rotation, plane): inverse FFT along y, complex-to-real along x, then the
+// plane's four largest keys (orderable score bits, ~flat index) and its sum of
+// squares.  The float32 field only locates candidates; their scores are
+// recomputed exactly by k_rescore.
+
+__device__ __forceinline__ void top4_insert(unsigned long long k, unsigned long long& t0, unsigned long long& t1,
+                                            unsigned long long& t2, unsigned long long& t3) {
+    if (k > t3) {
+        if (k > t2) {
+            t3 = t2;
+            if (k > t1) {
+                t2 = t1;
+                if (k > t0) {
+                    t1 = t0;
+                    t0 = k;
+                } else {
+                    t1 = k;
+                }
+            } else {
+                t2 = k;
+            }
+        } else {
+            t3 = k;
+        }
+    }
+}
 
 template <int N>
 __global__ __launch_bounds__(256) void k_inv_xy_argmax(const float2* __restrict__ spec, int count, const float2* __restrict__ twg,
-                                                       unsigned long long* __restrict__ keys, float* __restrict__ corr_out) {
+                                                       unsigned long long* __restrict__ ptop, double* __restrict__ pssq,
+                                                       float* __restrict__ corr_out) {
     using C = Canvas<N>;
+    constexpr int NW = C::NT / 64;
     __shared__ float2 plane[N * C::P];
     __shared__ float2 tw[N];
-    __shared__ unsigned long long wbest[C::NT / 64];
+    __shared__ unsigned long long wtop[NW][KTOP];
+    __shared__ double wss[NW];
     int rot, z;
     map_plane_block(blockIdx.x, count, N, rot, z);
     for (int i = threadIdx.x; i < N; i += C::NT) tw[i] = twg[i];
@@ -301,48 +330,202 @@ __global__ __launch_bounds__(256) void k_inv_xy_argmax(const float2* __restrict_
     fft_lds<N, true, C::P, C::NT, true, N>(plane, C::P, 1, tw);
     c2r_pre<N>(plane, tw);
     fft_lds<C::N2, true, N, C::NT, false, N>(plane, 1, C::P, tw);
-    unsigned long long best = 0ull;
+    unsigned long long t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+    float ss = 0.0f;
     for (int e = threadIdx.x; e < N * C::N2; e += C::NT) {
         const int y = e / C::N2, j = e % C::N2;
         const float2 v = plane[y * C::P + j];
         const uint32_t flat0 = (uint32_t)(((z * N) + y) * N + 2 * j);
-        const unsigned long long k0 = ((unsigned long long)ordered_bits(v.x) << 32) | (0xffffffffu - flat0);
-        const unsigned long long k1 = ((unsigned long long)ordered_bits(v.y) << 32) | (0xffffffffu - (flat0 + 1));
-        best = k0 > best ? k0 : best;
-        best = k1 > best ? k1 : best;
+        top4_insert(((unsigned long long)ordered_bits(v.x) << 32) | (0xffffffffu - flat0), t0, t1, t2, t3);
+        top4_insert(((unsigned long long)ordered_bits(v.y) << 32) | (0xffffffffu - (flat0 + 1)), t0, t1, t2, t3);
+        ss = fmaf(v.x, v.x, fmaf(v.y, v.y, ss));
         if (corr_out) {
             corr_out[flat0] = v.x;
             corr_out[flat0 + 1] = v.y;
         }
     }
+    // wave: merge the 64 sorted lists by four rounds of a wave maximum
+    int ptr = 0;
+    unsigned long long wt[KTOP];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const unsigned long long o = __shfl_xor(best, off, 64);
-        best = o > best ? o : best;
+    for (int r = 0; r < KTOP; ++r) {
+        const unsigned long long head = ptr == 0 ? t0 : ptr == 1 ? t1 : ptr == 2 ? t2 : ptr == 3 ? t3 : 0ull;
+        unsigned long long mx = head;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const unsigned long long o = __shfl_xor(mx, off, 64);
+            mx = o > mx ? o : mx;
+        }
+        if (head == mx && mx != 0ull) ++ptr;  // keys are unique: one lane advances
+        wt[r] = mx;
     }
-    if ((threadIdx.x & 63) == 0) wbest[threadIdx.x >> 6] = best;
+    double ds = (double)ss;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) ds += __shfl_xor(ds, off, 64);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int r = 0; r < KTOP; ++r) wtop[wave][r] = wt[r];
+        wss[wave] = ds;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long b = wbest[0];
-        for (int w = 1; w < C::NT / 64; ++w) b = wbest[w] > b ? wbest[w] : b;
-        atomicMax(keys + rot, b);
+        unsigned long long b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+        double tot = 0.0;
+        for (int w = 0; w < NW; ++w) {
+            for (int r = 0; r < KTOP; ++r) top4_insert(wtop[w][r], b0, b1, b2, b3);
+            tot += wss[w];
+        }
+        unsigned long long* o = ptop + ((size_t)rot * N + z) * KTOP;
+        o[0] = b0;
+        o[1] = b1;
+        o[2] = b2;
+        o[3] = b3;
+        pssq[(size_t)rot * N + z] = tot;
     }
 }
 
-// ------------------------------------------------------------- finalize
+// Per rotation: the float32 maximum v and the field's RMS E (from the plane sums
+// of squares); every key with value >= v - 2 eps becomes a candidate, where
+// eps = REGK_EPS_SCALE * 2^-24 * E * log2(n^3) bounds the float32 error of the
+// FFT path.  If a plane's fourth key is still inside the window the plane may
+// hold more candidates than were kept: the rotation is counted as overflowed.
+__global__ __launch_bounds__(256) void k_select(const unsigned long long* __restrict__ ptop, const double* __restrict__ pssq,
+                                                int n, double eps_per_rms, int32_t* __restrict__ cand_idx,
+                                                int32_t* __restrict__ cand_n, int* __restrict__ stats) {
+    __shared__ unsigned long long red[4];
+    __shared__ double thr_s;
+    __shared__ int cnt;
+    __shared__ unsigned long long list[CMAX];
+    __shared__ int overflow;
+    const int rot = blockIdx.x;
+    const unsigned long long* T = ptop + (size_t)rot * n * KTOP;
+    unsigned long long mx = 0;
+    for (int zz = threadIdx.x; zz < n; zz += 256) mx = T[zz * KTOP] > mx ? T[zz * KTOP] : mx;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(mx, off, 64);
+        mx = o > mx ? o : mx;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    if (threadIdx.x == 0) {
+        cnt = 0;
+        overflow = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long b = red[0];
+        for (int w = 1; w < 4; ++w) b = red[w] > b ? red[w] : b;
+        double ssq = 0.0;
+        for (int zz = 0; zz < n; ++zz) ssq += pssq[(size_t)rot * n + zz];
+        const double rms = sqrt(ssq / ((double)n * n * n));
+        thr_s = (double)unordered_float((uint32_t)(b >> 32)) - 2.0 * eps_per_rms * rms;
+    }
+    __syncthreads();
+    const double thr = thr_s;
+    for (int i = threadIdx.x; i < n * KTOP; i += 256) {
+        const unsigned long long k = T[i];
+        if (k != 0ull && (double)unordered_float((uint32_t)(k >> 32)) >= thr) {
+            const int slot = atomicAdd(&cnt, 1);
+            if (slot < CMAX) list[slot] = k;
+            if ((i % KTOP) == KTOP - 1) overflow = 1;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int c = cnt;
+        if (c > CMAX) {
+            overflow = 1;
+            c = CMAX;
+        }
+        // descending key order (insertion sort of at most CMAX keys)
+        for (int a = 1; a < c; ++a) {
+            const unsigned long long k = list[a];
+            int b = a - 1;
+            while (b >= 0 && list[b] < k) {
+                list[b + 1] = list[b];
+                --b;
+            }
+            list[b + 1] = k;
+        }
+        for (int a = 0; a < c; ++a) cand_idx[(size_t)rot * CMAX + a] = (int32_t)(0xffffffffu - (uint32_t)(list[a] & 0xffffffffu));
+        cand_n[rot] = c;
+        atomicAdd(stats + 0, 1);
+        atomicAdd(stats + 1, c);
+        if (overflow) atomicAdd(stats + 2, 1);
+    }
+}
 
-__global__ void k_finalize(const unsigned long long* __restrict__ keys, int count, const float* __restrict__ quats, int n,
+// Exact score of one candidate shift d of one rotation:
+//   sum over the nonzero voxels k of O of O[k] * S_r[(k + d) mod n]
+// with S_r resampled exactly as in pass 1 and the sum accumulated in double.
+__global__ __launch_bounds__(256) void k_rescore(const uint32_t* __restrict__ nz_idx, const float* __restrict__ nz_val,
+                                                 const int* __restrict__ nz_count, int n, const uint8_t* __restrict__ cmask,
+                                                 int m, int mb, const float* __restrict__ rots,
+                                                 const int32_t* __restrict__ cand_idx, const int32_t* __restrict__ cand_n,
+                                                 double* __restrict__ cand_exact) {
+    __shared__ double red[4];
+    const int rot = blockIdx.x / CMAX, c = blockIdx.x % CMAX;
+    if (c >= cand_n[rot]) return;
+    const uint32_t flat = (uint32_t)cand_idx[(size_t)rot * CMAX + c];
+    const int dx = (int)(flat % n), dy = (int)((flat / n) % n), dz = (int)(flat / ((uint32_t)n * n));
+    const float* R = rots + rot * 9;
+    const float r00 = R[0], r01 = R[1], r02 = R[2], r10 = R[3], r11 = R[4], r12 = R[5], r20 = R[6], r21 = R[7], r22 = R[8];
+    const float hm = 0.5f * m, hn = 0.5f * n;
+    const int nnz = *nz_count;
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < nnz; j += 256) {
+        const uint32_t k = nz_idx[j];
+        int x = (int)(k & 0xffu) + dx, y = (int)((k >> 8) & 0xffu) + dy, zz = (int)(k >> 16) + dz;
+        x -= x >= n ? n : 0;
+        y -= y >= n ? n : 0;
+        zz -= zz >= n ? n : 0;
+        const float zc = (float)zz - hn;
+        const float bx = hm - hn * (r00 + r01) + zc * r02;
+        const float by = hm - hn * (r10 + r11) + zc * r12;
+        const float bz = hm - hn * (r20 + r21) + zc * r22;
+        const float xf = (float)x, yf = (float)y;
+        const float ux = fmaf(xf, r00, fmaf(yf, r01, bx));
+        const float uy = fmaf(xf, r10, fmaf(yf, r11, by));
+        const float uz = fmaf(xf, r20, fmaf(yf, r21, bz));
+        const float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
+        const int ix = (int)fx0, iy = (int)fy0, iz = (int)fz0;
+        if (ix >= 0 && iy >= 0 && iz >= 0 && ix < m && iy < m && iz < m) {
+            const uint32_t mk = cmask[brick_index(ix, iy, iz, mb)];
+            if (mk) acc += (double)nz_val[j] * (double)trilinear_mask(mk, ux - fx0, uy - fy0, uz - fz0);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) cand_exact[(size_t)rot * CMAX + c] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// ------------------------------------------------------------- finalize
+// best candidate by exact score (ties: lowest flat index) -> score, shift, pose
+
+__global__ void k_finalize(const int32_t* __restrict__ cand_idx, const int32_t* __restrict__ cand_n,
+                           const double* __restrict__ cand_exact, int count, const float* __restrict__ quats, int n,
                            double h, const double* __restrict__ anchor, double wc0, double wc1, double wc2,
                            float* __restrict__ out_score, int32_t* __restrict__ out_shift, double* __restrict__ out_pose) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    const unsigned long long key = keys[i];
-    const float score = unordered_float((uint32_t)(key >> 32));
-    const uint32_t flat = 0xffffffffu - (uint32_t)(key & 0xffffffffu);
+    const int cn = cand_n[i];
+    double best = -1.0e308;
+    uint32_t flat = 0xffffffffu;
+    for (int c = 0; c < cn; ++c) {
+        const double v = cand_exact[(size_t)i * CMAX + c];
+        const uint32_t f = (uint32_t)cand_idx[(size_t)i * CMAX + c];
+        if (v > best || (v == best && f < flat)) {
+            best = v;
+            flat = f;
+        }
+    }
     int d[3] = {(int)(flat % n), (int)((flat / n) % n), (int)(flat / ((uint32_t)n * n))};
     for (int a = 0; a < 3; ++a)
         if (d[a] >= n / 2) d[a] -= n;
-    if (out_score) out_score[i] = score;
+    if (out_score) out_score[i] = (float)best;
     if (out_shift) {
         out_shift[3 * i] = d[0];
         out_shift[3 * i + 1] = d[1];
@@ -367,6 +550,65 @@ __global__ void k_finalize(const unsigned long long* __restrict__ keys, int coun
             }
             o[4 + r] = wc[r] - ra + h * rd;
         }
+    }
+}
+
+// ------------------------------------------- nonzero list of the object grid
+// (ascending flat index, so the exact sums run in a fixed order)
+
+__global__ void k_nz_count(const float* __restrict__ O, size_t n3, int* __restrict__ bcount) {
+    __shared__ int wc[4];
+    const size_t id = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const bool nz = id < n3 && O[id] != 0.0f;
+    const unsigned long long b = __ballot(nz);
+    if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = __popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) bcount[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
+}
+
+__global__ __launch_bounds__(1024) void k_nz_scan(const int* __restrict__ bcount, int nb, int* __restrict__ boff,
+                                                  int* __restrict__ total) {
+    __shared__ int part[1024];
+    const int per = (nb + 1023) / 1024;
+    const int b0 = threadIdx.x * per, b1 = min(nb, b0 + per);
+    int s = 0;
+    for (int b = b0; b < b1; ++b) s += bcount[b];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int t = 0; t < 1024; ++t) {
+            const int v = part[t];
+            part[t] = run;
+            run += v;
+        }
+        *total = run;
+    }
+    __syncthreads();
+    int run = part[threadIdx.x];
+    for (int b = b0; b < b1; ++b) {
+        boff[b] = run;
+        run += bcount[b];
+    }
+}
+
+__global__ void k_nz_write(const float* __restrict__ O, size_t n3, int n, const int* __restrict__ boff,
+                           uint32_t* __restrict__ idx, float* __restrict__ val) {
+    __shared__ int wc[4];
+    const size_t id = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const float v = id < n3 ? O[id] : 0.0f;
+    const bool nz = v != 0.0f;
+    const unsigned long long b = __ballot(nz);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) wc[wave] = __popcll(b);
+    __syncthreads();
+    int base = boff[blockIdx.x];
+    for (int w = 0; w < wave; ++w) base += wc[w];
+    if (nz) {
+        const int r = base + __popcll(b & ((1ull << lane) - 1ull));
+        const uint32_t kx = (uint32_t)(id % n), ky = (uint32_t)((id / n) % n), kz = (uint32_t)(id / ((size_t)n * n));
+        idx[r] = kx | (ky << 8) | (kz << 16);
+        val[r] = v;
     }
 }
 
@@ -622,13 +864,13 @@ static hipError_t launch_search_pass(int pass, const SearchBatchArgs& a) {
     using C = Canvas<N>;
     if (pass == 0)
         hipLaunchKernelGGL(k_rotvox_fwd_xy<N>, dim3(a.count * N), dim3(C::NT), 0, a.stream, a.cmask, a.m, a.mp / 4, a.rots,
-                           a.count, a.tw, a.spec, a.keys);
+                           a.count, a.tw, a.spec);
     else if (pass == 1)
         hipLaunchKernelGGL((k_zpass<N, 0>), dim3(a.count * C::TILES), dim3(C::NT), 0, a.stream, a.spec, a.W, nullptr, a.tw,
                            1.0f);
     else
-        hipLaunchKernelGGL(k_inv_xy_argmax<N>, dim3(a.count * N), dim3(C::NT), 0, a.stream, a.spec, a.count, a.tw, a.keys,
-                           a.corr_out);
+        hipLaunchKernelGGL(k_inv_xy_argmax<N>, dim3(a.count * N), dim3(C::NT), 0, a.stream, a.spec, a.count, a.tw, a.ptop,
+                           a.pssq, a.corr_out);
     return hipGetLastError();
 }
 
@@ -731,11 +973,29 @@ hipError_t validate_inputs(const float* V, int nv, const int32_t* F, int nf, con
     return hipGetLastError();
 }
 
-hipError_t finalize_batch(const unsigned long long* keys, int count, const float* quats, int n, double h,
-                          const double* anchor, const double* wc, float* out_score, int32_t* out_shift, double* out_pose,
-                          hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3((count + 127) / 128), dim3(128), 0, s, keys, count, quats, n, h, anchor, wc[0], wc[1],
-                       wc[2], out_score, out_shift, out_pose);
+hipError_t candidates_batch(int n, const SearchBatchArgs& a) {
+    const double eps_per_rms = REGK_EPS_SCALE * std::ldexp(1.0, -24) * std::log2((double)n * n * n);
+    hipLaunchKernelGGL(k_select, dim3(a.count), dim3(256), 0, a.stream, a.ptop, a.pssq, n, eps_per_rms, a.cand_idx,
+                       a.cand_n, a.stats);
+    hipLaunchKernelGGL(k_rescore, dim3(a.count * CMAX), dim3(256), 0, a.stream, a.nz_idx, a.nz_val, a.nz_count, n, a.cmask,
+                       a.m, a.mp / 4, a.rots, a.cand_idx, a.cand_n, a.cand_exact);
+    return hipGetLastError();
+}
+
+hipError_t finalize_batch(const SearchBatchArgs& a, int n, const float* quats, double h, const double* anchor,
+                          const double* wc, float* out_score, int32_t* out_shift, double* out_pose) {
+    hipLaunchKernelGGL(k_finalize, dim3((a.count + 127) / 128), dim3(128), 0, a.stream, a.cand_idx, a.cand_n, a.cand_exact,
+                       a.count, quats, n, h, anchor, wc[0], wc[1], wc[2], out_score, out_shift, out_pose);
+    return hipGetLastError();
+}
+
+hipError_t build_nonzero_list(const float* O, int n, int* bcount, int* boff, uint32_t* idx, float* val, int* nnz,
+                              hipStream_t s) {
+    const size_t n3 = (size_t)n * n * n;
+    const int nb = (int)((n3 + 255) / 256);
+    hipLaunchKernelGGL(k_nz_count, dim3(nb), dim3(256), 0, s, O, n3, bcount);
+    hipLaunchKernelGGL(k_nz_scan, dim3(1), dim3(1024), 0, s, bcount, nb, boff, nnz);
+    hipLaunchKernelGGL(k_nz_write, dim3(nb), dim3(256), 0, s, O, n3, n, boff, idx, val);
     return hipGetLastError();
 }
 

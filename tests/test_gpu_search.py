@@ -22,6 +22,12 @@ pytestmark = pytest.mark.gpu
 TOL_REL = 1e-4
 
 
+def eps_bound(C_ref, n):
+    """The float32 error bound the library's candidate window assumes:
+    1.5 * 2^-24 * rms(C) * log2(n^3)."""
+    return 1.5 * 2.0 ** -24 * math.sqrt(float(np.mean(C_ref ** 2))) * math.log2(n ** 3)
+
+
 def _lib():
     import paper_2605_21398_amd as rd
     rd.load_library()
@@ -103,10 +109,13 @@ def test_correlation_field_matches_oracle(n, h, M, batch):
     ref = np.array([f.max() for f in fields])
     tol = TOL_REL * np.abs(ref).max()
     _check_scores(sc, _flat_from_shift(sh, n), ref, fields, tol)
-    # full field of two rotations element by element
+    # the float32 field of two rotations, element by element, inside the error
+    # bound that sizes the library's candidate window
     for r in (0, M - 1):
         Cg = rd.register_debug_correlation(handle, r).cpu().numpy()
-        assert np.abs(Cg - fields[r]).max() <= tol
+        assert np.abs(Cg - fields[r]).max() <= eps_bound(fields[r], n)
+    st = rd.register_search_stats(handle)
+    assert st["overflows"] == 0 and st["candidates"] >= st["rotations"]
     # poses follow from the shifts in FP64
     for r in range(M):
         R, t = S.pose_from_shift(p.so3[r], sh[r], a, p.center, h)
@@ -203,6 +212,9 @@ def _sampled_full_size(cfg, n_samples):
     ref = np.array([f.max() for f in fields])
     tol = TOL_REL * max(np.abs(ref).max(), np.abs(sc2).max())
     _check_scores(sc2[sel], _flat_from_shift(sh2[sel], p.n), ref, fields, tol)
+    Cg = rd.register_debug_correlation(handle, sel[0]).cpu().numpy()
+    assert np.abs(Cg - fields[0]).max() <= eps_bound(fields[0], p.n)
+    assert rd.register_search_stats(handle)["overflows"] == 0
     return p, sc, sh
 
 
