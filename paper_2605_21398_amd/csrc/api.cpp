@@ -68,6 +68,10 @@ struct reg_handle {
     uint8_t* Sw = nullptr;
     uint8_t* cm = nullptr;
     float2* tw = nullptr;
+    double2* tw64 = nullptr;
+    double2* lowT = nullptr;
+    double2* Wlow = nullptr;
+    double2* Plow = nullptr;
     int* err = nullptr;
     std::vector<void*> owned;
     // optional per-kernel timing with HIP events on the handle's stream
@@ -153,7 +157,7 @@ static int default_batch(int n, size_t H, int n_rot) {
 
 // spectrum conj(F(O))/n^3 and the nonzero list of O, both derived from h->O
 static int build_object_derived(reg_handle* h) {
-    DEV_TRY(h, object_spectrum(h->n, h->O, h->spec, h->W, h->tw, h->stream));
+    DEV_TRY(h, object_spectrum(h->n, h->O, h->spec, h->W, h->tw, h->tw64, h->lowT, h->Wlow, h->stream));
     DEV_TRY(h, build_nonzero_list(h->O, h->n, h->nz_bcount, h->nz_boff, h->nz_idx, h->nz_val, h->nz_count, h->stream));
     return REG_OK;
 }
@@ -230,6 +234,10 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
     ALLOC_TRY(h, h->Sw, m3);
     ALLOC_TRY(h, h->cm, mp3);
     ALLOC_TRY(h, h->tw, (size_t)h->n);
+    ALLOC_TRY(h, h->tw64, (size_t)h->n);
+    ALLOC_TRY(h, h->lowT, (size_t)h->batch * h->n * NLOW2);
+    ALLOC_TRY(h, h->Wlow, (size_t)NLOW3);
+    ALLOC_TRY(h, h->Plow, (size_t)h->batch * NLOW3);
     ALLOC_TRY(h, h->err, 1);
 
     hipStream_t s = h->stream;
@@ -244,11 +252,14 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
 
     // twiddles exp(-2 pi i t / n) in double, rounded to float
     std::vector<float2> tw(h->n);
+    std::vector<double2> tw64(h->n);
     for (int t = 0; t < h->n; ++t) {
         const double ang = -2.0 * M_PI * (double)t / (double)h->n;
-        tw[t] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+        tw64[t] = make_double2(std::cos(ang), std::sin(ang));
+        tw[t] = make_float2((float)tw64[t].x, (float)tw64[t].y);
     }
     DEV_TRY(h, hipMemcpyAsync(h->tw, tw.data(), sizeof(float2) * h->n, hipMemcpyHostToDevice, s));
+    DEV_TRY(h, hipMemcpyAsync(h->tw64, tw64.data(), sizeof(double2) * h->n, hipMemcpyHostToDevice, s));
 
     // input checks on the device, then wait for them
     DEV_TRY(h, hipMemsetAsync(h->err, 0, sizeof(int), s));
@@ -304,6 +315,10 @@ static int run_batches(reg_handle* h, int first, int count, float* out_score, in
         a.tw = h->tw;
         a.spec = h->spec;
         a.W = h->W;
+        a.tw64 = h->tw64;
+        a.lowT = h->lowT;
+        a.Wlow = h->Wlow;
+        a.Plow = h->Plow;
         a.ptop = h->ptop;
         a.pssq = h->pssq;
         a.cand_idx = h->cand_idx;

@@ -9,9 +9,17 @@ namespace regdock {
 // per-plane candidates kept by pass 3, candidates re-scored per rotation
 constexpr int KTOP = 4;
 constexpr int CMAX = 16;
-// window half-width: REGK_EPS_SCALE * 2^-24 * rms(C) * log2(n^3) bounds the
-// float32 error of the FFT path (measured maxima are below half of it)
-constexpr double REGK_EPS_SCALE = 1.5;
+// Exact low-frequency block: frequencies with max(|kx|, |ky|, |kz|) <= KLOW are
+// taken out of the float32 FFT path and carried in double (they hold nearly all
+// of the correlation's energy, which the -50 penalty makes huge).
+constexpr int KLOW = 4;
+constexpr int NLX = KLOW + 1;        // kx in [0, KLOW]
+constexpr int NLY = 2 * KLOW + 1;    // ky, kz in [-KLOW, KLOW]
+constexpr int NLOW2 = NLX * NLY;     // (kx, ky) pairs of a plane
+constexpr int NLOW3 = NLOW2 * NLY;   // (kx, ky, kz) of a rotation
+// Window half-width eps = REGK_EPS_SCALE * 2^-24 * rms(C_high) * log2(n^3)
+// bounds the float32 error of the remaining (high-frequency) field.
+constexpr double REGK_EPS_SCALE = 6.0;
 
 enum : int {
     REGK_ERR_NONFINITE = 1,
@@ -27,6 +35,10 @@ struct SearchBatchArgs {
     const float2* tw;          // twiddles w[t] = exp(-2 pi i t / n), n entries
     float2* spec;              // [count][H] spectrum work buffer
     const float2* W;           // conj(F(O)) / n^3 in the tiled layout, H entries
+    const double2* tw64;       // exp(-2 pi i t / n) in double, n entries
+    double2* lowT;             // [count][n][NLOW2] per-plane low 2D DFT of S_r (double)
+    const double2* Wlow;       // [NLOW3] conj(F(O)) / n^3 on the low block (double)
+    double2* Plow;             // [count][NLOW3] exact product on the low block
     unsigned long long* ptop;  // [count][n][KTOP] per-plane best keys (score bits, ~flat)
     double* pssq;              // [count][n] per-plane sums of squares of the field
     int32_t* cand_idx;         // [count][CMAX] candidate flat indices
@@ -46,7 +58,8 @@ int tile_width(int n);
 
 // pass 0: rotate+voxelise+FFT xy; 1: z FFT * W * z IFFT; 2: IFFT yx + argmax
 hipError_t search_pass(int n, int pass, const SearchBatchArgs& a);
-hipError_t object_spectrum(int n, const float* O, float2* spec_tmp, float2* W, const float2* tw, hipStream_t s);
+hipError_t object_spectrum(int n, const float* O, float2* spec_tmp, float2* W, const float2* tw, const double2* tw64,
+                           double2* lowT_tmp, double2* Wlow, hipStream_t s);
 hipError_t setup_anchor(const float* V, int nv, double* anchor, hipStream_t s);
 hipError_t setup_object_grid(const float* V, const int32_t* F, const uint8_t* touch, int nf, int n, double h,
                              const double* anchor, float tau_out1, float tau_in1, float rho, float* O, float* fo,

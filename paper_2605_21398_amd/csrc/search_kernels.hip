@@ -188,15 +188,104 @@ __device__ __forceinline__ void plane_forward_and_store(float2* plane, const flo
         nyq[((size_t)(ky / C::T) * N + z) * C::T + (ky % C::T)] = plane[ky * C::P + C::N2];
 }
 
+// ---------------------------------------------------- exact low-frequency block
+// The correlation field's energy sits almost entirely in the lowest
+// frequencies (the smooth, huge overlap with the -50 interior).  Those
+// frequencies, max(|kx|, |ky|, |kz|) <= KLOW, are carried in double: pass 1 adds
+// a double-precision 2D DFT of each plane at (kx in [0, KLOW], ky in [-KLOW,
+// KLOW]); k_low_combine finishes the z direction and multiplies by the object's
+// double-precision low block; pass 2 removes the block from the float32
+// product; pass 3 adds the block's field back in double at every voxel.
+
+__host__ __device__ constexpr int pow2floor(int v) {
+    int p = 1;
+    while (p * 2 <= v) p *= 2;
+    return p;
+}
+
+__device__ __forceinline__ double2 dcmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ double2 dcmulc(double2 a, double2 b) {
+    return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ int mod_n(int v, int n) {
+    const int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+// plane holds z[j] = s[2j] + i s[2j+1] per row; out[kx * NLY + ky + KLOW] =
+// sum_{x,y} s[x,y] exp(-2 pi i (kx x + ky y) / N) in double.
+template <int N>
+__device__ __forceinline__ void plane_low_dft(const float2* plane, const double2* __restrict__ tw64, double2* rbuf,
+                                              double2* __restrict__ out) {
+    using C = Canvas<N>;
+    static_assert(N <= C::NT, "one row task set per pass");
+    constexpr int CH = pow2floor(C::NT / N);  // lanes per row, a power of two
+    constexpr int JC = (C::N2 + CH - 1) / CH;
+    const int t = threadIdx.x;
+    if (t < N * CH) {
+        const int y = t / CH, c = t % CH;
+        double2 acc[NLX];
+#pragma unroll
+        for (int k = 0; k < NLX; ++k) acc[k] = make_double2(0.0, 0.0);
+        const int j0 = c * JC, j1 = min(C::N2, j0 + JC);
+        for (int j = j0; j < j1; ++j) {
+            const float2 v = plane[y * C::P + j];
+            const double s0 = (double)v.x, s1 = (double)v.y;
+            const int x0 = 2 * j;
+            acc[0].x += s0 + s1;
+#pragma unroll
+            for (int k = 1; k < NLX; ++k) {
+                const double2 w0 = tw64[(k * x0) % N], w1 = tw64[(k * (x0 + 1)) % N];
+                acc[k].x = fma(s0, w0.x, fma(s1, w1.x, acc[k].x));
+                acc[k].y = fma(s0, w0.y, fma(s1, w1.y, acc[k].y));
+            }
+        }
+#pragma unroll
+        for (int off = CH / 2; off >= 1; off >>= 1)
+#pragma unroll
+            for (int k = 0; k < NLX; ++k) {
+                acc[k].x += __shfl_xor(acc[k].x, off, 64);
+                acc[k].y += __shfl_xor(acc[k].y, off, 64);
+            }
+        if (c == 0)
+#pragma unroll
+            for (int k = 0; k < NLX; ++k) rbuf[y * NLX + k] = acc[k];
+    }
+    __syncthreads();
+    // y direction: four lanes per (kx, ky), each a quarter of the rows
+    constexpr int CB = 4;
+    static_assert(N % CB == 0 && NLOW2 * CB <= C::NT, "low-block y pass layout");
+    double2 part = make_double2(0.0, 0.0);
+    if (t < NLOW2 * CB) {
+        const int o = t / CB, c = t % CB;
+        const int kx = o / NLY, ky = o % NLY - KLOW;
+        for (int y = c * (N / CB); y < (c + 1) * (N / CB); ++y) {
+            const double2 r = rbuf[y * NLX + kx], w = tw64[mod_n(ky * y, N)];
+            part.x = fma(r.x, w.x, fma(-r.y, w.y, part.x));
+            part.y = fma(r.x, w.y, fma(r.y, w.x, part.y));
+        }
+    }
+    part.x += __shfl_xor(part.x, 1, 64);
+    part.y += __shfl_xor(part.y, 1, 64);
+    part.x += __shfl_xor(part.x, 2, 64);
+    part.y += __shfl_xor(part.y, 2, 64);
+    if (t < NLOW2 * CB && (t % CB) == 0) out[t / CB] = part;
+}
+
 // ------------------------------------------------------------------ pass 1
 
 template <int N>
 __global__ __launch_bounds__(256) void k_rotvox_fwd_xy(const uint8_t* __restrict__ cmask, int m, int mb,
                                                        const float* __restrict__ rots, int count,
-                                                       const float2* __restrict__ twg, float2* __restrict__ spec) {
+                                                       const float2* __restrict__ twg, const double2* __restrict__ tw64,
+                                                       float2* __restrict__ spec, double2* __restrict__ lowT) {
     using C = Canvas<N>;
     __shared__ float2 plane[N * C::P];
     __shared__ float2 tw[N];
+    __shared__ double2 rbuf[N * NLX];
     int rot, z;
     map_plane_block(blockIdx.x, count, N, rot, z);
     for (int i = threadIdx.x; i < N; i += C::NT) tw[i] = twg[i];
@@ -228,16 +317,19 @@ __global__ __launch_bounds__(256) void k_rotvox_fwd_xy(const uint8_t* __restrict
         plane[y * C::P + j] = make_float2(vals[0], vals[1]);
     }
     __syncthreads();
+    plane_low_dft<N>(plane, tw64, rbuf, lowT + ((size_t)rot * N + z) * NLOW2);
     plane_forward_and_store<N>(plane, tw, spec + (size_t)rot * C::H, z);
 }
 
 // pass 1 on a real grid (the object grid O): same transform, no rotation
 template <int N>
 __global__ __launch_bounds__(256) void k_grid_fwd_xy(const float* __restrict__ grid, const float2* __restrict__ twg,
-                                                     float2* __restrict__ spec) {
+                                                     const double2* __restrict__ tw64, float2* __restrict__ spec,
+                                                     double2* __restrict__ lowT) {
     using C = Canvas<N>;
     __shared__ float2 plane[N * C::P];
     __shared__ float2 tw[N];
+    __shared__ double2 rbuf[N * NLX];
     const int z = blockIdx.x;
     for (int i = threadIdx.x; i < N; i += C::NT) tw[i] = twg[i];
     for (int e = threadIdx.x; e < N * C::N2; e += C::NT) {
@@ -246,6 +338,7 @@ __global__ __launch_bounds__(256) void k_grid_fwd_xy(const float* __restrict__ g
         plane[y * C::P + j] = make_float2(row[2 * j], row[2 * j + 1]);
     }
     __syncthreads();
+    plane_low_dft<N>(plane, tw64, rbuf, lowT + (size_t)z * NLOW2);
     plane_forward_and_store<N>(plane, tw, spec, z);
 }
 
@@ -267,7 +360,14 @@ __global__ __launch_bounds__(256) void k_zpass(float2* __restrict__ spec, const 
     fft_lds<N, false, C::T, C::NT, true, N>(buf, C::T, 1, tw);
     if (MODE == 0) {
         const float2* w = W + (size_t)tile * E;
-        for (int i = threadIdx.x; i < E; i += C::NT) buf[i] = cmul(buf[i], w[i]);
+        // the low block (max(|kx|,|ky|,|kz|) <= KLOW) is carried exactly elsewhere
+        const int ky = tile / C::NT2;
+        const bool low_tile = tile < N * C::NT2 && (tile % C::NT2) == 0 && (ky <= KLOW || ky >= N - KLOW);
+        for (int i = threadIdx.x; i < E; i += C::NT) {
+            const int kz = i / C::T, kx = i % C::T;
+            const bool low = low_tile && kx <= KLOW && (kz <= KLOW || kz >= N - KLOW);
+            buf[i] = low ? make_float2(0.0f, 0.0f) : cmul(buf[i], w[i]);
+        }
         __syncthreads();
         fft_lds<N, true, C::T, C::NT, true, N>(buf, C::T, 1, tw);
         for (int i = threadIdx.x; i < E; i += C::NT) src[i] = buf[i];
@@ -305,19 +405,48 @@ __device__ __forceinline__ void top4_insert(unsigned long long k, unsigned long 
     }
 }
 
+// key = orderable bits of a double, low 22 bits replaced by ~flat (flat < 2^22)
+__device__ __forceinline__ unsigned long long key64(double v, uint32_t flat) {
+    unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    b = (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+    return (b & ~0x3fffffull) | (unsigned long long)(0x3fffffu - flat);
+}
+__device__ __forceinline__ double key_value(unsigned long long k) {
+    unsigned long long b = k & ~0x3fffffull;
+    b = (b & 0x8000000000000000ull) ? (b & 0x7fffffffffffffffull) : ~b;
+    return __longlong_as_double((long long)b);
+}
+__device__ __forceinline__ uint32_t key_flat(unsigned long long k) { return 0x3fffffu - (uint32_t)(k & 0x3fffffull); }
+
 template <int N>
 __global__ __launch_bounds__(256) void k_inv_xy_argmax(const float2* __restrict__ spec, int count, const float2* __restrict__ twg,
+                                                       const double2* __restrict__ tw64, const double2* __restrict__ Plow,
                                                        unsigned long long* __restrict__ ptop, double* __restrict__ pssq,
                                                        float* __restrict__ corr_out) {
     using C = Canvas<N>;
     constexpr int NW = C::NT / 64;
     __shared__ float2 plane[N * C::P];
     __shared__ float2 tw[N];
+    __shared__ double2 btab[N * NLX];
+    __shared__ double2 az[NLOW2];
     __shared__ unsigned long long wtop[NW][KTOP];
     __shared__ double wss[NW];
     int rot, z;
     map_plane_block(blockIdx.x, count, N, rot, z);
     for (int i = threadIdx.x; i < N; i += C::NT) tw[i] = twg[i];
+    // low block of this plane: az[kx][ky] = sum_kz P[kx][ky][kz] e^{+2 pi i kz z / N}
+    {
+        const double2* P = Plow + (size_t)rot * NLOW3;
+        for (int o = threadIdx.x; o < NLOW2; o += C::NT) {
+            double2 acc = make_double2(0.0, 0.0);
+            for (int kzi = 0; kzi < NLY; ++kzi) {
+                const double2 t = dcmulc(P[o * NLY + kzi], tw64[mod_n((kzi - KLOW) * z, N)]);
+                acc.x += t.x;
+                acc.y += t.y;
+            }
+            az[o] = acc;
+        }
+    }
     const float2* spec_rot = spec + (size_t)rot * C::H;
     for (int e = threadIdx.x; e < N * C::N2; e += C::NT) {
         const int ky = e / C::N2, kx = e % C::N2;
@@ -327,6 +456,17 @@ __global__ __launch_bounds__(256) void k_inv_xy_argmax(const float2* __restrict_
     for (int ky = threadIdx.x; ky < N; ky += C::NT)
         plane[ky * C::P + C::N2] = nyq[((size_t)(ky / C::T) * N + z) * C::T + (ky % C::T)];
     __syncthreads();
+    // btab[y][kx] = sum_ky az[kx][ky] e^{+2 pi i ky y / N}
+    for (int t = threadIdx.x; t < N * NLX; t += C::NT) {
+        const int y = t / NLX, kx = t % NLX;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int kyi = 0; kyi < NLY; ++kyi) {
+            const double2 v = dcmulc(az[kx * NLY + kyi], tw64[mod_n((kyi - KLOW) * y, N)]);
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+        btab[t] = acc;
+    }
     fft_lds<N, true, C::P, C::NT, true, N>(plane, C::P, 1, tw);
     c2r_pre<N>(plane, tw);
     fft_lds<C::N2, true, N, C::NT, false, N>(plane, 1, C::P, tw);
@@ -336,12 +476,23 @@ __global__ __launch_bounds__(256) void k_inv_xy_argmax(const float2* __restrict_
         const int y = e / C::N2, j = e % C::N2;
         const float2 v = plane[y * C::P + j];
         const uint32_t flat0 = (uint32_t)(((z * N) + y) * N + 2 * j);
-        top4_insert(((unsigned long long)ordered_bits(v.x) << 32) | (0xffffffffu - flat0), t0, t1, t2, t3);
-        top4_insert(((unsigned long long)ordered_bits(v.y) << 32) | (0xffffffffu - (flat0 + 1)), t0, t1, t2, t3);
+        // field of the low block at x = 2j, 2j+1: Re b0 + 2 sum_kx Re(b_kx e^{+2 pi i kx x / N})
+        const double2* b = btab + y * NLX;
+        double c0 = b[0].x, c1 = b[0].x;
+#pragma unroll
+        for (int k = 1; k < NLX; ++k) {
+            const double2 bk = b[k];
+            const double2 w0 = tw64[(k * 2 * j) % N], w1 = tw64[(k * (2 * j + 1)) % N];
+            c0 = fma(2.0 * bk.x, w0.x, fma(2.0 * bk.y, w0.y, c0));
+            c1 = fma(2.0 * bk.x, w1.x, fma(2.0 * bk.y, w1.y, c1));
+        }
+        const double v0 = (double)v.x + c0, v1 = (double)v.y + c1;
+        top4_insert(key64(v0, flat0), t0, t1, t2, t3);
+        top4_insert(key64(v1, flat0 + 1), t0, t1, t2, t3);
         ss = fmaf(v.x, v.x, fmaf(v.y, v.y, ss));
         if (corr_out) {
-            corr_out[flat0] = v.x;
-            corr_out[flat0 + 1] = v.y;
+            corr_out[flat0] = (float)v0;
+            corr_out[flat0 + 1] = (float)v1;
         }
     }
     // wave: merge the 64 sorted lists by four rounds of a wave maximum
@@ -419,13 +570,13 @@ __global__ __launch_bounds__(256) void k_select(const unsigned long long* __rest
         double ssq = 0.0;
         for (int zz = 0; zz < n; ++zz) ssq += pssq[(size_t)rot * n + zz];
         const double rms = sqrt(ssq / ((double)n * n * n));
-        thr_s = (double)unordered_float((uint32_t)(b >> 32)) - 2.0 * eps_per_rms * rms;
+        thr_s = key_value(b) - 2.0 * eps_per_rms * rms;
     }
     __syncthreads();
     const double thr = thr_s;
     for (int i = threadIdx.x; i < n * KTOP; i += 256) {
         const unsigned long long k = T[i];
-        if (k != 0ull && (double)unordered_float((uint32_t)(k >> 32)) >= thr) {
+        if (k != 0ull && key_value(k) >= thr) {
             const int slot = atomicAdd(&cnt, 1);
             if (slot < CMAX) list[slot] = k;
             if ((i % KTOP) == KTOP - 1) overflow = 1;
@@ -448,7 +599,7 @@ __global__ __launch_bounds__(256) void k_select(const unsigned long long* __rest
             }
             list[b + 1] = k;
         }
-        for (int a = 0; a < c; ++a) cand_idx[(size_t)rot * CMAX + a] = (int32_t)(0xffffffffu - (uint32_t)(list[a] & 0xffffffffu));
+        for (int a = 0; a < c; ++a) cand_idx[(size_t)rot * CMAX + a] = (int32_t)key_flat(list[a]);
         cand_n[rot] = c;
         atomicAdd(stats + 0, 1);
         atomicAdd(stats + 1, c);
@@ -500,6 +651,25 @@ __global__ __launch_bounds__(256) void k_rescore(const uint32_t* __restrict__ nz
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) cand_exact[(size_t)rot * CMAX + c] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// Finish the low block along z: L[kx][ky][kz] = sum_z lowT[z][kx][ky] e^{-2 pi i kz z / n}.
+// MODE 0 (per rotation): out = L * Wlow.  MODE 1 (object): out = conj(L) * scale.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_low_combine(const double2* __restrict__ lowT, int n, const double2* __restrict__ tw64,
+                                                     const double2* __restrict__ Wlow, double scale, double2* __restrict__ out) {
+    const int rot = blockIdx.x;
+    const double2* T = lowT + (size_t)rot * n * NLOW2;
+    for (int o = threadIdx.x; o < NLOW3; o += 256) {
+        const int kxy = o / NLY, kz = o % NLY - KLOW;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int zz = 0; zz < n; ++zz) {
+            const double2 t = dcmul(T[(size_t)zz * NLOW2 + kxy], tw64[mod_n(kz * zz, n)]);
+            acc.x += t.x;
+            acc.y += t.y;
+        }
+        out[(size_t)rot * NLOW3 + o] = MODE == 0 ? dcmul(acc, Wlow[o]) : make_double2(acc.x * scale, -acc.y * scale);
+    }
 }
 
 // ------------------------------------------------------------- finalize
@@ -864,22 +1034,26 @@ static hipError_t launch_search_pass(int pass, const SearchBatchArgs& a) {
     using C = Canvas<N>;
     if (pass == 0)
         hipLaunchKernelGGL(k_rotvox_fwd_xy<N>, dim3(a.count * N), dim3(C::NT), 0, a.stream, a.cmask, a.m, a.mp / 4, a.rots,
-                           a.count, a.tw, a.spec);
-    else if (pass == 1)
+                           a.count, a.tw, a.tw64, a.spec, a.lowT);
+    else if (pass == 1) {
+        hipLaunchKernelGGL((k_low_combine<0>), dim3(a.count), dim3(256), 0, a.stream, a.lowT, N, a.tw64, a.Wlow, 1.0, a.Plow);
         hipLaunchKernelGGL((k_zpass<N, 0>), dim3(a.count * C::TILES), dim3(C::NT), 0, a.stream, a.spec, a.W, nullptr, a.tw,
                            1.0f);
-    else
-        hipLaunchKernelGGL(k_inv_xy_argmax<N>, dim3(a.count * N), dim3(C::NT), 0, a.stream, a.spec, a.count, a.tw, a.ptop,
-                           a.pssq, a.corr_out);
+    } else {
+        hipLaunchKernelGGL(k_inv_xy_argmax<N>, dim3(a.count * N), dim3(C::NT), 0, a.stream, a.spec, a.count, a.tw, a.tw64,
+                           a.Plow, a.ptop, a.pssq, a.corr_out);
+    }
     return hipGetLastError();
 }
 
 template <int N>
-static hipError_t launch_object_spectrum(const float* O, float2* spec_tmp, float2* W, const float2* tw, hipStream_t s) {
+static hipError_t launch_object_spectrum(const float* O, float2* spec_tmp, float2* W, const float2* tw,
+                                         const double2* tw64, double2* lowT_tmp, double2* Wlow, hipStream_t s) {
     using C = Canvas<N>;
-    hipLaunchKernelGGL(k_grid_fwd_xy<N>, dim3(N), dim3(C::NT), 0, s, O, tw, spec_tmp);
-    hipLaunchKernelGGL((k_zpass<N, 1>), dim3(C::TILES), dim3(C::NT), 0, s, spec_tmp, nullptr, W, tw,
-                       (float)(1.0 / ((double)N * N * N)));
+    const double scale = 1.0 / ((double)N * N * N);
+    hipLaunchKernelGGL(k_grid_fwd_xy<N>, dim3(N), dim3(C::NT), 0, s, O, tw, tw64, spec_tmp, lowT_tmp);
+    hipLaunchKernelGGL((k_zpass<N, 1>), dim3(C::TILES), dim3(C::NT), 0, s, spec_tmp, nullptr, W, tw, (float)scale);
+    hipLaunchKernelGGL((k_low_combine<1>), dim3(1), dim3(256), 0, s, lowT_tmp, N, tw64, nullptr, scale, Wlow);
     return hipGetLastError();
 }
 
@@ -921,9 +1095,10 @@ hipError_t search_pass(int n, int pass, const SearchBatchArgs& a) {
     }
 }
 
-hipError_t object_spectrum(int n, const float* O, float2* spec_tmp, float2* W, const float2* tw, hipStream_t s) {
+hipError_t object_spectrum(int n, const float* O, float2* spec_tmp, float2* W, const float2* tw, const double2* tw64,
+                           double2* lowT_tmp, double2* Wlow, hipStream_t s) {
     switch (n) {
-#define CASE(N) case N: return launch_object_spectrum<N>(O, spec_tmp, W, tw, s);
+#define CASE(N) case N: return launch_object_spectrum<N>(O, spec_tmp, W, tw, tw64, lowT_tmp, Wlow, s);
         REGDOCK_FOR_EACH_N(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;

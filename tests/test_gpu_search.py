@@ -22,10 +22,19 @@ pytestmark = pytest.mark.gpu
 TOL_REL = 1e-4
 
 
+KLOW = 4  # frequencies with max(|kx|,|ky|,|kz|) <= KLOW are carried in double
+
+
 def eps_bound(C_ref, n):
-    """The float32 error bound the library's candidate window assumes:
-    1.5 * 2^-24 * rms(C) * log2(n^3)."""
-    return 1.5 * 2.0 ** -24 * math.sqrt(float(np.mean(C_ref ** 2))) * math.log2(n ** 3)
+    """The error bound the library's candidate window assumes for its float32
+    field, 6 * 2^-24 * rms(C_high) * log2(n^3), where C_high is the field without
+    its exact low-frequency block; plus the float32 rounding of the debug output."""
+    P = np.fft.rfftn(C_ref)
+    k = np.abs(np.fft.fftfreq(n) * n)
+    kz, ky, kx = np.meshgrid(k, k, np.arange(n // 2 + 1), indexing="ij")
+    P[np.maximum(np.maximum(kx, ky), kz) <= KLOW] = 0
+    Ch = np.fft.irfftn(P, s=C_ref.shape, axes=(0, 1, 2))
+    return 6.0 * 2.0 ** -24 * math.sqrt(float(np.mean(Ch ** 2))) * math.log2(n ** 3) + 2.0 ** -23 * np.abs(C_ref)
 
 
 def _lib():
