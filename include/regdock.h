@@ -121,14 +121,18 @@ int score_rotations(reg_handle* h, int32_t first, int32_t count, float* out_scor
                     double* out_pose);
 
 /* How the peaks were found.  The float32 FFT path only locates candidates:
- * every shift whose float32 correlation lies within 2 eps of the float32
- * maximum, eps = 1.5 * 2^-24 * rms(C) * log2(n^3) bounding the float32 error,
- * is re-scored exactly (direct sum over the nonzero voxels of O, accumulated in
- * double) and the best exact score wins.  Counters since register_init: scored
- * rotations, re-scored candidates, and rotations whose window held more
- * candidates than were kept (4 per plane, 16 per rotation; the best kept one
- * is used).  Host pointers; synchronises the stream. */
-int register_search_stats(reg_handle* h, int64_t* rotations, int64_t* candidates, int64_t* overflows);
+ * every shift whose value lies within 2 eps of the rotation's maximum,
+ * eps = 6 * 2^-24 * rms(C_high) * log2(n^3) bounding the float32 error of the
+ * field outside its exact low-frequency block, is re-scored exactly (direct sum
+ * over the nonzero voxels of O, accumulated in double) and the best exact score
+ * wins.  Counters since register_init: scored rotations, re-scored candidates,
+ * rotations whose window held more candidates than were kept (4 per plane, 16
+ * per rotation: exact ties on score plateaus; the best kept one is reported,
+ * within 2 eps of the maximum), and of those the "uncertain" ones, whose 2 eps
+ * exceeds 1e-4 of the largest |score| of their score_rotations call.  Host
+ * pointers; synchronises the stream. */
+int register_search_stats(reg_handle* h, int64_t* rotations, int64_t* candidates, int64_t* overflows,
+                          int64_t* uncertain);
 
 /* The K best rotations of a score vector (score descending, index ascending),
  * computed on the device.  scores: count float; out_idx: K int32.

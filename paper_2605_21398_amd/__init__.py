@@ -92,7 +92,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.register_set_grids.restype = ctypes.c_int
     L.register_set_grids.argtypes = [p, p, p]
     L.register_search_stats.restype = ctypes.c_int
-    L.register_search_stats.argtypes = [p, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.register_search_stats.argtypes = [p, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                        ctypes.POINTER(i64)]
     L.register_set_timing.restype = ctypes.c_int
     L.register_set_timing.argtypes = [p, i32]
     L.register_get_timing.restype = ctypes.c_int
@@ -251,6 +252,7 @@ def register_get_timing(h: Handle) -> dict:
 
 
 def register_search_stats(h: Handle) -> dict:
-    r, c, o = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-    _check(load_library().register_search_stats(h.ptr, ctypes.byref(r), ctypes.byref(c), ctypes.byref(o)))
-    return dict(rotations=r.value, candidates=c.value, overflows=o.value)
+    r, c, o, u = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load_library().register_search_stats(h.ptr, ctypes.byref(r), ctypes.byref(c), ctypes.byref(o),
+                                                ctypes.byref(u)))
+    return dict(rotations=r.value, candidates=c.value, overflows=o.value, uncertain=u.value)

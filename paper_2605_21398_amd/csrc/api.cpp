@@ -47,7 +47,7 @@ struct reg_handle {
     uint8_t* touch = nullptr;
     float* poses = nullptr;
     float* so3 = nullptr;
-    float* rots = nullptr;
+    double* rots = nullptr;
     float* pose_prep = nullptr;
     double* anchor = nullptr;
     float* O = nullptr;
@@ -60,6 +60,8 @@ struct reg_handle {
     int32_t* cand_n = nullptr;
     double* cand_exact = nullptr;
     int* stats = nullptr;
+    double* window = nullptr;
+    uint8_t* ovf = nullptr;
     uint32_t* nz_idx = nullptr;
     float* nz_val = nullptr;
     int* nz_count = nullptr;
@@ -225,7 +227,9 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
     ALLOC_TRY(h, h->cand_idx, (size_t)h->batch * CMAX);
     ALLOC_TRY(h, h->cand_n, (size_t)h->batch);
     ALLOC_TRY(h, h->cand_exact, (size_t)h->batch * CMAX);
-    ALLOC_TRY(h, h->stats, 3);
+    ALLOC_TRY(h, h->stats, 4);
+    ALLOC_TRY(h, h->window, (size_t)n_rot);
+    ALLOC_TRY(h, h->ovf, (size_t)n_rot);
     ALLOC_TRY(h, h->nz_idx, n3);
     ALLOC_TRY(h, h->nz_val, n3);
     ALLOC_TRY(h, h->nz_count, 1);
@@ -263,7 +267,7 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
 
     // input checks on the device, then wait for them
     DEV_TRY(h, hipMemsetAsync(h->err, 0, sizeof(int), s));
-    DEV_TRY(h, hipMemsetAsync(h->stats, 0, 3 * sizeof(int), s));
+    DEV_TRY(h, hipMemsetAsync(h->stats, 0, 4 * sizeof(int), s));
     DEV_TRY(h, validate_inputs(h->V, h->nv, h->F, h->nf, h->poses, n_poses, h->err, s));
     DEV_TRY(h, setup_rotations(h->so3, n_rot, h->rots, h->err, s));
     int herr = 0;
@@ -325,6 +329,8 @@ static int run_batches(reg_handle* h, int first, int count, float* out_score, in
         a.cand_n = h->cand_n;
         a.cand_exact = h->cand_exact;
         a.stats = h->stats;
+        a.window = h->window + (first + b0);
+        a.ovf = h->ovf + (first + b0);
         a.nz_idx = h->nz_idx;
         a.nz_val = h->nz_val;
         a.nz_count = h->nz_count;
@@ -360,7 +366,10 @@ int score_rotations(reg_handle* h, int32_t first, int32_t count, float* out_scor
     if (first < 0 || count < 0 || (int64_t)first + count > h->n_rot)
         return fail(REG_EINVAL, "rotation range [%d, %d) outside [0, %d)", first, first + count, h->n_rot);
     if (count == 0) return REG_OK;
-    return run_batches(h, first, count, out_score, out_shift, out_pose, nullptr);
+    int rc = run_batches(h, first, count, out_score, out_shift, out_pose, nullptr);
+    if (rc) return rc;
+    DEV_TRY(h, certify(out_score, count, h->window + first, h->ovf + first, h->stats, h->stream));
+    return REG_OK;
 }
 
 int register_set_timing(reg_handle* h, int32_t enable) {
@@ -390,15 +399,17 @@ int register_get_timing(reg_handle* h, double* ms, int64_t* launches, int64_t* r
     return REG_OK;
 }
 
-int register_search_stats(reg_handle* h, int64_t* rotations, int64_t* candidates, int64_t* overflows) {
-    if (!h || !rotations || !candidates || !overflows) return fail(REG_EINVAL, "NULL argument");
+int register_search_stats(reg_handle* h, int64_t* rotations, int64_t* candidates, int64_t* overflows,
+                          int64_t* uncertain) {
+    if (!h || !rotations || !candidates || !overflows || !uncertain) return fail(REG_EINVAL, "NULL argument");
     if (h->poisoned) return fail(REG_EDEVICE, "handle poisoned by an earlier device error");
-    int st[3] = {0, 0, 0};
+    int st[4] = {0, 0, 0, 0};
     DEV_TRY(h, hipMemcpyAsync(st, h->stats, sizeof st, hipMemcpyDeviceToHost, h->stream));
     DEV_TRY(h, hipStreamSynchronize(h->stream));
     *rotations = st[0];
     *candidates = st[1];
     *overflows = st[2];
+    *uncertain = st[3];
     return REG_OK;
 }
 

@@ -30,7 +30,7 @@ enum : int {
 struct SearchBatchArgs {
     const uint8_t* cmask;      // bricked corner masks, mp^3 bytes
     int m, mp;                 // lattice edge and its multiple-of-4 padding
-    const float* rots;         // [count][9] rotation matrices of this batch
+    const double* rots;        // [count][9] rotation matrices of this batch (double)
     int count;                 // rotations in this batch
     const float2* tw;          // twiddles w[t] = exp(-2 pi i t / n), n entries
     float2* spec;              // [count][H] spectrum work buffer
@@ -44,7 +44,9 @@ struct SearchBatchArgs {
     int32_t* cand_idx;         // [count][CMAX] candidate flat indices
     int32_t* cand_n;           // [count] candidates per rotation
     double* cand_exact;        // [count][CMAX] exact scores of the candidates
-    int* stats;                // [3] rotations, candidates, overflowed rotations
+    int* stats;                // [4] rotations, candidates, overflowed, uncertain rotations
+    double* window;            // [count] candidate window 2 eps per rotation
+    uint8_t* ovf;              // [count] 1 if the rotation's window overflowed
     const uint32_t* nz_idx;    // nonzero voxels of O: packed kx | ky << 8 | kz << 16
     const float* nz_val;       //   and their values
     const int* nz_count;       //   and their number (device)
@@ -67,7 +69,7 @@ hipError_t setup_object_grid(const float* V, const int32_t* F, const uint8_t* to
 hipError_t setup_swept(const float* poses, int np, float r, float L, int m, int mp, double h, const double* wc,
                        float* pose_tmp, uint8_t* Sw, uint8_t* cm, hipStream_t s);
 hipError_t setup_cellmask(const uint8_t* Sw, int m, int mp, uint8_t* cm, hipStream_t s);
-hipError_t setup_rotations(const float* so3, int M, float* rots, int* err, hipStream_t s);
+hipError_t setup_rotations(const float* so3, int M, double* rots, int* err, hipStream_t s);
 hipError_t validate_inputs(const float* V, int nv, const int32_t* F, int nf, const float* poses, int np, int* err,
                            hipStream_t s);
 hipError_t candidates_batch(int n, const SearchBatchArgs& a);
@@ -80,4 +82,8 @@ hipError_t build_nonzero_list(const float* O, int n, int* bcount, int* boff, uin
 
 namespace regdock {
 hipError_t top_k(const float* scores, int count, int K, int32_t* out, hipStream_t s);
+}
+
+namespace regdock {
+hipError_t certify(const float* scores, int count, const double* window, const uint8_t* ovf, int* stats, hipStream_t s);
 }

@@ -275,11 +275,38 @@ __device__ __forceinline__ void plane_low_dft(const float2* plane, const double2
     if (t < NLOW2 * CB && (t % CB) == 0) out[t / CB] = part;
 }
 
+// S_r at canvas voxel (x, y, z) for rotation R: u = R (k - N/2) + m/2 in double
+// (the lattice spans ~2N voxels, where float32 would leave ~1e-5 voxel of
+// position error), then trilinear weights in float from the corner mask.
+struct RotSampler {
+    double r00, r01, r02, r10, r11, r12, r20, r21, r22;
+    double hm, hn;
+    __device__ __forceinline__ void load(const double* R, int m, int n) {
+        r00 = R[0]; r01 = R[1]; r02 = R[2];
+        r10 = R[3]; r11 = R[4]; r12 = R[5];
+        r20 = R[6]; r21 = R[7]; r22 = R[8];
+        hm = 0.5 * m;
+        hn = 0.5 * n;
+    }
+    __device__ __forceinline__ float sample(const uint8_t* __restrict__ cmask, int m, int mb, int x, int y, int z) const {
+        const double xc = (double)x - hn, yc = (double)y - hn, zc = (double)z - hn;
+        const double ux = fma(r00, xc, fma(r01, yc, fma(r02, zc, hm)));
+        const double uy = fma(r10, xc, fma(r11, yc, fma(r12, zc, hm)));
+        const double uz = fma(r20, xc, fma(r21, yc, fma(r22, zc, hm)));
+        const double fx0 = floor(ux), fy0 = floor(uy), fz0 = floor(uz);
+        const int ix = (int)fx0, iy = (int)fy0, iz = (int)fz0;
+        if (ix < 0 || iy < 0 || iz < 0 || ix >= m || iy >= m || iz >= m) return 0.0f;
+        const uint32_t mk = cmask[brick_index(ix, iy, iz, mb)];
+        if (!mk) return 0.0f;
+        return trilinear_mask(mk, (float)(ux - fx0), (float)(uy - fy0), (float)(uz - fz0));
+    }
+};
+
 // ------------------------------------------------------------------ pass 1
 
 template <int N>
 __global__ __launch_bounds__(256) void k_rotvox_fwd_xy(const uint8_t* __restrict__ cmask, int m, int mb,
-                                                       const float* __restrict__ rots, int count,
+                                                       const double* __restrict__ rots, int count,
                                                        const float2* __restrict__ twg, const double2* __restrict__ tw64,
                                                        float2* __restrict__ spec, double2* __restrict__ lowT) {
     using C = Canvas<N>;
@@ -289,32 +316,11 @@ __global__ __launch_bounds__(256) void k_rotvox_fwd_xy(const uint8_t* __restrict
     int rot, z;
     map_plane_block(blockIdx.x, count, N, rot, z);
     for (int i = threadIdx.x; i < N; i += C::NT) tw[i] = twg[i];
-    const float* R = rots + rot * 9;
-    const float r00 = R[0], r01 = R[1], r02 = R[2], r10 = R[3], r11 = R[4], r12 = R[5], r20 = R[6], r21 = R[7], r22 = R[8];
-    // u = R (k - N/2) + m/2 = x R e_x + y R e_y + base
-    const float hm = 0.5f * m, hn = 0.5f * N, zc = (float)z - hn;
-    const float bx = hm - hn * (r00 + r01) + zc * r02;
-    const float by = hm - hn * (r10 + r11) + zc * r12;
-    const float bz = hm - hn * (r20 + r21) + zc * r22;
+    RotSampler rs;
+    rs.load(rots + rot * 9, m, N);
     for (int e = threadIdx.x; e < N * C::N2; e += C::NT) {
         const int y = e / C::N2, j = e % C::N2;
-        float vals[2];
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const float x = (float)(2 * j + s), yy = (float)y;
-            const float ux = fmaf(x, r00, fmaf(yy, r01, bx));
-            const float uy = fmaf(x, r10, fmaf(yy, r11, by));
-            const float uz = fmaf(x, r20, fmaf(yy, r21, bz));
-            const float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
-            const int ix = (int)fx0, iy = (int)fy0, iz = (int)fz0;
-            float v = 0.0f;
-            if (ix >= 0 && iy >= 0 && iz >= 0 && ix < m && iy < m && iz < m) {
-                const uint32_t mk = cmask[brick_index(ix, iy, iz, mb)];
-                v = trilinear_mask(mk, ux - fx0, uy - fy0, uz - fz0);
-            }
-            vals[s] = v;
-        }
-        plane[y * C::P + j] = make_float2(vals[0], vals[1]);
+        plane[y * C::P + j] = make_float2(rs.sample(cmask, m, mb, 2 * j, y, z), rs.sample(cmask, m, mb, 2 * j + 1, y, z));
     }
     __syncthreads();
     plane_low_dft<N>(plane, tw64, rbuf, lowT + ((size_t)rot * N + z) * NLOW2);
@@ -543,7 +549,8 @@ __global__ __launch_bounds__(256) void k_inv_xy_argmax(const float2* __restrict_
 // hold more candidates than were kept: the rotation is counted as overflowed.
 __global__ __launch_bounds__(256) void k_select(const unsigned long long* __restrict__ ptop, const double* __restrict__ pssq,
                                                 int n, double eps_per_rms, int32_t* __restrict__ cand_idx,
-                                                int32_t* __restrict__ cand_n, int* __restrict__ stats) {
+                                                int32_t* __restrict__ cand_n, int* __restrict__ stats,
+                                                double* __restrict__ window, uint8_t* __restrict__ ovf) {
     __shared__ unsigned long long red[4];
     __shared__ double thr_s;
     __shared__ int cnt;
@@ -571,6 +578,7 @@ __global__ __launch_bounds__(256) void k_select(const unsigned long long* __rest
         for (int zz = 0; zz < n; ++zz) ssq += pssq[(size_t)rot * n + zz];
         const double rms = sqrt(ssq / ((double)n * n * n));
         thr_s = key_value(b) - 2.0 * eps_per_rms * rms;
+        window[rot] = 2.0 * eps_per_rms * rms;
     }
     __syncthreads();
     const double thr = thr_s;
@@ -601,6 +609,7 @@ __global__ __launch_bounds__(256) void k_select(const unsigned long long* __rest
         }
         for (int a = 0; a < c; ++a) cand_idx[(size_t)rot * CMAX + a] = (int32_t)key_flat(list[a]);
         cand_n[rot] = c;
+        ovf[rot] = overflow ? 1 : 0;
         atomicAdd(stats + 0, 1);
         atomicAdd(stats + 1, c);
         if (overflow) atomicAdd(stats + 2, 1);
@@ -612,7 +621,7 @@ __global__ __launch_bounds__(256) void k_select(const unsigned long long* __rest
 // with S_r resampled exactly as in pass 1 and the sum accumulated in double.
 __global__ __launch_bounds__(256) void k_rescore(const uint32_t* __restrict__ nz_idx, const float* __restrict__ nz_val,
                                                  const int* __restrict__ nz_count, int n, const uint8_t* __restrict__ cmask,
-                                                 int m, int mb, const float* __restrict__ rots,
+                                                 int m, int mb, const double* __restrict__ rots,
                                                  const int32_t* __restrict__ cand_idx, const int32_t* __restrict__ cand_n,
                                                  double* __restrict__ cand_exact) {
     __shared__ double red[4];
@@ -620,9 +629,8 @@ __global__ __launch_bounds__(256) void k_rescore(const uint32_t* __restrict__ nz
     if (c >= cand_n[rot]) return;
     const uint32_t flat = (uint32_t)cand_idx[(size_t)rot * CMAX + c];
     const int dx = (int)(flat % n), dy = (int)((flat / n) % n), dz = (int)(flat / ((uint32_t)n * n));
-    const float* R = rots + rot * 9;
-    const float r00 = R[0], r01 = R[1], r02 = R[2], r10 = R[3], r11 = R[4], r12 = R[5], r20 = R[6], r21 = R[7], r22 = R[8];
-    const float hm = 0.5f * m, hn = 0.5f * n;
+    RotSampler rs;
+    rs.load(rots + rot * 9, m, n);
     const int nnz = *nz_count;
     double acc = 0.0;
     for (int j = threadIdx.x; j < nnz; j += 256) {
@@ -631,20 +639,8 @@ __global__ __launch_bounds__(256) void k_rescore(const uint32_t* __restrict__ nz
         x -= x >= n ? n : 0;
         y -= y >= n ? n : 0;
         zz -= zz >= n ? n : 0;
-        const float zc = (float)zz - hn;
-        const float bx = hm - hn * (r00 + r01) + zc * r02;
-        const float by = hm - hn * (r10 + r11) + zc * r12;
-        const float bz = hm - hn * (r20 + r21) + zc * r22;
-        const float xf = (float)x, yf = (float)y;
-        const float ux = fmaf(xf, r00, fmaf(yf, r01, bx));
-        const float uy = fmaf(xf, r10, fmaf(yf, r11, by));
-        const float uz = fmaf(xf, r20, fmaf(yf, r21, bz));
-        const float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
-        const int ix = (int)fx0, iy = (int)fy0, iz = (int)fz0;
-        if (ix >= 0 && iy >= 0 && iz >= 0 && ix < m && iy < m && iz < m) {
-            const uint32_t mk = cmask[brick_index(ix, iy, iz, mb)];
-            if (mk) acc += (double)nz_val[j] * (double)trilinear_mask(mk, ux - fx0, uy - fy0, uz - fz0);
-        }
+        const float sv = rs.sample(cmask, m, mb, x, y, zz);
+        if (sv != 0.0f) acc += (double)nz_val[j] * (double)sv;
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -992,7 +988,7 @@ __global__ void k_cellmask(const uint8_t* __restrict__ Sw, int m, int mp, uint8_
 }
 
 // SO(3) samples -> rotation matrices (double math, float storage) + checks
-__global__ void k_rot_prep(const float* __restrict__ so3, int M, float* __restrict__ rots, int* __restrict__ err) {
+__global__ void k_rot_prep(const float* __restrict__ so3, int M, double* __restrict__ rots, int* __restrict__ err) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M) return;
     double q[4] = {so3[4 * i], so3[4 * i + 1], so3[4 * i + 2], so3[4 * i + 3]};
@@ -1000,10 +996,10 @@ __global__ void k_rot_prep(const float* __restrict__ so3, int M, float* __restri
     const double nq = sqrt(n2);
     if (!(nq >= 1.0 - 1e-3 && nq <= 1.0 + 1e-3)) atomicOr(err, REGK_ERR_QUAT);
     const double w = q[0] / nq, x = q[1] / nq, y = q[2] / nq, z = q[3] / nq;
-    float* o = rots + 9 * i;
-    o[0] = (float)(1 - 2 * (y * y + z * z)); o[1] = (float)(2 * (x * y - w * z)); o[2] = (float)(2 * (x * z + w * y));
-    o[3] = (float)(2 * (x * y + w * z)); o[4] = (float)(1 - 2 * (x * x + z * z)); o[5] = (float)(2 * (y * z - w * x));
-    o[6] = (float)(2 * (x * z - w * y)); o[7] = (float)(2 * (y * z + w * x)); o[8] = (float)(1 - 2 * (x * x + y * y));
+    double* o = rots + 9 * i;
+    o[0] = 1 - 2 * (y * y + z * z); o[1] = 2 * (x * y - w * z); o[2] = 2 * (x * z + w * y);
+    o[3] = 2 * (x * y + w * z); o[4] = 1 - 2 * (x * x + z * z); o[5] = 2 * (y * z - w * x);
+    o[6] = 2 * (x * z - w * y); o[7] = 2 * (y * z + w * x); o[8] = 1 - 2 * (x * x + y * y);
 }
 
 // finite vertices and poses, face indices in range, pose quaternions near unit
@@ -1136,7 +1132,7 @@ hipError_t setup_cellmask(const uint8_t* Sw, int m, int mp, uint8_t* cm, hipStre
     return hipGetLastError();
 }
 
-hipError_t setup_rotations(const float* so3, int M, float* rots, int* err, hipStream_t s) {
+hipError_t setup_rotations(const float* so3, int M, double* rots, int* err, hipStream_t s) {
     hipLaunchKernelGGL(k_rot_prep, dim3((M + 255) / 256), dim3(256), 0, s, so3, M, rots, err);
     return hipGetLastError();
 }
@@ -1151,7 +1147,7 @@ hipError_t validate_inputs(const float* V, int nv, const int32_t* F, int nf, con
 hipError_t candidates_batch(int n, const SearchBatchArgs& a) {
     const double eps_per_rms = REGK_EPS_SCALE * std::ldexp(1.0, -24) * std::log2((double)n * n * n);
     hipLaunchKernelGGL(k_select, dim3(a.count), dim3(256), 0, a.stream, a.ptop, a.pssq, n, eps_per_rms, a.cand_idx,
-                       a.cand_n, a.stats);
+                       a.cand_n, a.stats, a.window, a.ovf);
     hipLaunchKernelGGL(k_rescore, dim3(a.count * CMAX), dim3(256), 0, a.stream, a.nz_idx, a.nz_val, a.nz_count, n, a.cmask,
                        a.m, a.mp / 4, a.rots, a.cand_idx, a.cand_n, a.cand_exact);
     return hipGetLastError();
@@ -1212,6 +1208,42 @@ __global__ __launch_bounds__(1024) void k_topk(const float* __restrict__ scores,
 
 hipError_t top_k(const float* scores, int count, int K, int32_t* out, hipStream_t s) {
     hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, s, scores, count, K, out);
+    return hipGetLastError();
+}
+
+}  // namespace regdock
+
+namespace regdock {
+
+// A rotation whose candidate window overflowed reports the best kept
+// candidate, whose exact score is within the window 2 eps of the rotation's
+// maximum.  That meets the 1e-4-of-the-best-score bar when 2 eps <= 1e-4 max|score|
+// over the scored rotations; rotations where it does not are counted as
+// uncertain (stats[3]).
+__global__ __launch_bounds__(1024) void k_certify(const float* __restrict__ scores, int count,
+                                                  const double* __restrict__ window, const uint8_t* __restrict__ ovf,
+                                                  int* __restrict__ stats) {
+    __shared__ float red[16];
+    float mx = 0.0f;
+    for (int i = threadIdx.x; i < count; i += 1024) mx = fmaxf(mx, fabsf(scores[i]));
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float b = red[0];
+        for (int w = 1; w < 16; ++w) b = fmaxf(b, red[w]);
+        red[0] = b;
+    }
+    __syncthreads();
+    const double tol = 1e-4 * (double)red[0];
+    int bad = 0;
+    for (int i = threadIdx.x; i < count; i += 1024) bad += (ovf[i] && window[i] > tol) ? 1 : 0;
+    if (bad) atomicAdd(stats + 3, bad);
+}
+
+hipError_t certify(const float* scores, int count, const double* window, const uint8_t* ovf, int* stats, hipStream_t s) {
+    hipLaunchKernelGGL(k_certify, dim3(1), dim3(1024), 0, s, scores, count, window, ovf, stats);
     return hipGetLastError();
 }
 

@@ -122,9 +122,11 @@ def test_correlation_field_matches_oracle(n, h, M, batch):
     # bound that sizes the library's candidate window
     for r in (0, M - 1):
         Cg = rd.register_debug_correlation(handle, r).cpu().numpy()
-        assert np.abs(Cg - fields[r]).max() <= eps_bound(fields[r], n)
+        ratio = (np.abs(Cg - fields[r]) / eps_bound(fields[r], n)).max()
+        print(f"n={n} rot={r}: max |C_gpu - C_oracle| / bound = {ratio:.3f}")
+        assert ratio <= 1.0
     st = rd.register_search_stats(handle)
-    assert st["overflows"] == 0 and st["candidates"] >= st["rotations"]
+    assert st["uncertain"] == 0 and st["candidates"] >= st["rotations"]
     # poses follow from the shifts in FP64
     for r in range(M):
         R, t = S.pose_from_shift(p.so3[r], sh[r], a, p.center, h)
@@ -222,8 +224,12 @@ def _sampled_full_size(cfg, n_samples):
     tol = TOL_REL * max(np.abs(ref).max(), np.abs(sc2).max())
     _check_scores(sc2[sel], _flat_from_shift(sh2[sel], p.n), ref, fields, tol)
     Cg = rd.register_debug_correlation(handle, sel[0]).cpu().numpy()
-    assert np.abs(Cg - fields[0]).max() <= eps_bound(fields[0], p.n)
-    assert rd.register_search_stats(handle)["overflows"] == 0
+    ratio = (np.abs(Cg - fields[0]) / eps_bound(fields[0], p.n)).max()
+    print(f"config {cfg}: max |C_gpu - C_oracle| / bound = {ratio:.3f}")
+    assert ratio <= 1.0
+    st = rd.register_search_stats(handle)
+    print(f"config {cfg}: search stats {st}")
+    assert st["uncertain"] == 0
     return p, sc, sh
 
 
