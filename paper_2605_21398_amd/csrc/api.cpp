@@ -52,13 +52,16 @@ struct reg_handle {
     double* anchor = nullptr;
     float* O = nullptr;
     float* fo = nullptr;
+    uint32_t* od2 = nullptr;
+    uint32_t* odt2 = nullptr;
+    uint32_t* opar = nullptr;
     float2* W = nullptr;
     float2* spec = nullptr;
     unsigned long long* ptop = nullptr;
     double* pssq = nullptr;
     int32_t* cand_idx = nullptr;
     int32_t* cand_n = nullptr;
-    double* cand_exact = nullptr;
+    double* cand_part = nullptr;
     int* stats = nullptr;
     double* window = nullptr;
     uint8_t* ovf = nullptr;
@@ -220,13 +223,16 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
     ALLOC_TRY(h, h->anchor, 3);
     ALLOC_TRY(h, h->O, n3);
     ALLOC_TRY(h, h->fo, n3);
+    ALLOC_TRY(h, h->od2, n3);
+    ALLOC_TRY(h, h->odt2, n3);
+    ALLOC_TRY(h, h->opar, (size_t)h->n * h->n * ((h->n + 31) / 32));
     ALLOC_TRY(h, h->W, h->H);
     ALLOC_TRY(h, h->spec, h->H * (size_t)h->batch);
     ALLOC_TRY(h, h->ptop, (size_t)h->batch * h->n * KTOP);
     ALLOC_TRY(h, h->pssq, (size_t)h->batch * h->n);
     ALLOC_TRY(h, h->cand_idx, (size_t)h->batch * CMAX);
     ALLOC_TRY(h, h->cand_n, (size_t)h->batch);
-    ALLOC_TRY(h, h->cand_exact, (size_t)h->batch * CMAX);
+    ALLOC_TRY(h, h->cand_part, (size_t)h->batch * CMAX * rescore_slices(h->n));
     ALLOC_TRY(h, h->stats, 4);
     ALLOC_TRY(h, h->window, (size_t)n_rot);
     ALLOC_TRY(h, h->ovf, (size_t)n_rot);
@@ -280,7 +286,8 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
     // object grid and spectrum (per object), swept occupancy (per request)
     DEV_TRY(h, setup_anchor(h->V, h->nv, h->anchor, s));
     DEV_TRY(h, setup_object_grid(h->V, h->F, h->touch, h->nf, h->n, h->h, h->anchor, (float)h->prm.tau_out1,
-                                 (float)h->prm.tau_in1, (float)h->prm.rho, h->O, h->fo, s));
+                                 (float)h->prm.tau_in1, (float)h->prm.rho, h->O, h->fo,
+                                 ObjectScratch{h->od2, h->odt2, h->opar}, s));
     int rc = build_object_derived(h);
     if (rc) return rc;
     DEV_TRY(h, setup_swept(h->poses, n_poses, (float)probe->radius_mm, (float)probe->length_mm, h->m, h->mp, h->h, h->wc,
@@ -327,7 +334,7 @@ static int run_batches(reg_handle* h, int first, int count, float* out_score, in
         a.pssq = h->pssq;
         a.cand_idx = h->cand_idx;
         a.cand_n = h->cand_n;
-        a.cand_exact = h->cand_exact;
+        a.cand_part = h->cand_part;
         a.stats = h->stats;
         a.window = h->window + (first + b0);
         a.ovf = h->ovf + (first + b0);

@@ -43,7 +43,7 @@ struct SearchBatchArgs {
     double* pssq;              // [count][n] per-plane sums of squares of the field
     int32_t* cand_idx;         // [count][CMAX] candidate flat indices
     int32_t* cand_n;           // [count] candidates per rotation
-    double* cand_exact;        // [count][CMAX] exact scores of the candidates
+    double* cand_part;         // [count][CMAX][rescore_slices(n)] slice sums of the exact scores
     int* stats;                // [4] rotations, candidates, overflowed, uncertain rotations
     double* window;            // [count] candidate window 2 eps per rotation
     uint8_t* ovf;              // [count] 1 if the rotation's window overflowed
@@ -55,6 +55,7 @@ struct SearchBatchArgs {
 };
 
 bool canvas_supported(int n);
+int rescore_slices(int n);
 size_t spectrum_elems(int n);
 int tile_width(int n);
 
@@ -63,9 +64,16 @@ hipError_t search_pass(int n, int pass, const SearchBatchArgs& a);
 hipError_t object_spectrum(int n, const float* O, float2* spec_tmp, float2* W, const float2* tw, const double2* tw64,
                            double2* lowT_tmp, double2* Wlow, hipStream_t s);
 hipError_t setup_anchor(const float* V, int nv, double* anchor, hipStream_t s);
+// scratch of the object-grid build: squared distances (float bits, n^3 each)
+// and the inside-parity bit words of every column (n^2 * ceil(n/32))
+struct ObjectScratch {
+    uint32_t* d2;
+    uint32_t* dt2;
+    uint32_t* par;
+};
 hipError_t setup_object_grid(const float* V, const int32_t* F, const uint8_t* touch, int nf, int n, double h,
                              const double* anchor, float tau_out1, float tau_in1, float rho, float* O, float* fo,
-                             hipStream_t s);
+                             const ObjectScratch& w, hipStream_t s);
 hipError_t setup_swept(const float* poses, int np, float r, float L, int m, int mp, double h, const double* wc,
                        float* pose_tmp, uint8_t* Sw, uint8_t* cm, hipStream_t s);
 hipError_t setup_cellmask(const uint8_t* Sw, int m, int mp, uint8_t* cm, hipStream_t s);

@@ -619,52 +619,89 @@ __global__ __launch_bounds__(256) void k_select(const unsigned long long* __rest
 // Exact score of one candidate shift d of one rotation:
 //   sum over the nonzero voxels k of O of O[k] * S_r[(k + d) mod n]
 // with S_r resampled exactly as in pass 1 and the sum accumulated in double.
+// The nonzero list is cut into `nslice` slices; a grid-stride loop runs over
+// (rotation, candidate, slice) items, skipping empty candidate slots, and each
+// item writes its slice sum; k_finalize adds the slices in a fixed order.
 __global__ __launch_bounds__(256) void k_rescore(const uint32_t* __restrict__ nz_idx, const float* __restrict__ nz_val,
-                                                 const int* __restrict__ nz_count, int n, const uint8_t* __restrict__ cmask,
-                                                 int m, int mb, const double* __restrict__ rots,
+                                                 const int* __restrict__ nz_count, int n, int nslice,
+                                                 const uint8_t* __restrict__ cmask, int m, int mb,
+                                                 const double* __restrict__ rots, int count,
                                                  const int32_t* __restrict__ cand_idx, const int32_t* __restrict__ cand_n,
-                                                 double* __restrict__ cand_exact) {
+                                                 double* __restrict__ cand_part) {
     __shared__ double red[4];
-    const int rot = blockIdx.x / CMAX, c = blockIdx.x % CMAX;
-    if (c >= cand_n[rot]) return;
-    const uint32_t flat = (uint32_t)cand_idx[(size_t)rot * CMAX + c];
-    const int dx = (int)(flat % n), dy = (int)((flat / n) % n), dz = (int)(flat / ((uint32_t)n * n));
-    RotSampler rs;
-    rs.load(rots + rot * 9, m, n);
     const int nnz = *nz_count;
-    double acc = 0.0;
-    for (int j = threadIdx.x; j < nnz; j += 256) {
-        const uint32_t k = nz_idx[j];
-        int x = (int)(k & 0xffu) + dx, y = (int)((k >> 8) & 0xffu) + dy, zz = (int)(k >> 16) + dz;
-        x -= x >= n ? n : 0;
-        y -= y >= n ? n : 0;
-        zz -= zz >= n ? n : 0;
-        const float sv = rs.sample(cmask, m, mb, x, y, zz);
-        if (sv != 0.0f) acc += (double)nz_val[j] * (double)sv;
-    }
+    const int per = (nnz + nslice - 1) / nslice;
+    const int items = count * CMAX * nslice;
+    for (int it = blockIdx.x; it < items; it += gridDim.x) {
+        const int sl = it % nslice, rc = it / nslice;
+        const int rot = rc / CMAX, c = rc % CMAX;
+        if (c >= cand_n[rot]) continue;  // uniform across the workgroup
+        const uint32_t flat = (uint32_t)cand_idx[(size_t)rot * CMAX + c];
+        const int dx = (int)(flat % n), dy = (int)((flat / n) % n), dz = (int)(flat / ((uint32_t)n * n));
+        RotSampler rs;
+        rs.load(rots + rot * 9, m, n);
+        const int j0 = sl * per, j1 = min(nnz, j0 + per);
+        double acc = 0.0;
+        for (int j = j0 + threadIdx.x; j < j1; j += 256) {
+            const uint32_t k = nz_idx[j];
+            int x = (int)(k & 0xffu) + dx, y = (int)((k >> 8) & 0xffu) + dy, zz = (int)(k >> 16) + dz;
+            x -= x >= n ? n : 0;
+            y -= y >= n ? n : 0;
+            zz -= zz >= n ? n : 0;
+            const float sv = rs.sample(cmask, m, mb, x, y, zz);
+            if (sv != 0.0f) acc += (double)nz_val[j] * (double)sv;
+        }
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) cand_exact[(size_t)rot * CMAX + c] = ((red[0] + red[1]) + red[2]) + red[3];
+        for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) cand_part[(size_t)rc * nslice + sl] = ((red[0] + red[1]) + red[2]) + red[3];
+        __syncthreads();
+    }
 }
 
 // Finish the low block along z: L[kx][ky][kz] = sum_z lowT[z][kx][ky] e^{-2 pi i kz z / n}.
+// One workgroup per (rotation, kx, ky): lane z multiplies its plane's value by
+// the NLY phases, then a fixed-order tree sums over z.
 // MODE 0 (per rotation): out = L * Wlow.  MODE 1 (object): out = conj(L) * scale.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_low_combine(const double2* __restrict__ lowT, int n, const double2* __restrict__ tw64,
                                                      const double2* __restrict__ Wlow, double scale, double2* __restrict__ out) {
-    const int rot = blockIdx.x;
-    const double2* T = lowT + (size_t)rot * n * NLOW2;
-    for (int o = threadIdx.x; o < NLOW3; o += 256) {
-        const int kxy = o / NLY, kz = o % NLY - KLOW;
-        double2 acc = make_double2(0.0, 0.0);
-        for (int zz = 0; zz < n; ++zz) {
-            const double2 t = dcmul(T[(size_t)zz * NLOW2 + kxy], tw64[mod_n(kz * zz, n)]);
-            acc.x += t.x;
-            acc.y += t.y;
+    __shared__ double2 red[4][NLY];
+    const int rot = blockIdx.x / NLOW2, kxy = blockIdx.x % NLOW2;
+    const double2* T = lowT + (size_t)rot * n * NLOW2 + kxy;
+    double2 acc[NLY];
+#pragma unroll
+    for (int k = 0; k < NLY; ++k) acc[k] = make_double2(0.0, 0.0);
+    for (int zz = threadIdx.x; zz < n; zz += 256) {
+        const double2 v = T[(size_t)zz * NLOW2];
+#pragma unroll
+        for (int k = 0; k < NLY; ++k) {
+            const double2 t = dcmul(v, tw64[mod_n((k - KLOW) * zz, n)]);
+            acc[k].x += t.x;
+            acc[k].y += t.y;
         }
-        out[(size_t)rot * NLOW3 + o] = MODE == 0 ? dcmul(acc, Wlow[o]) : make_double2(acc.x * scale, -acc.y * scale);
+    }
+#pragma unroll
+    for (int k = 0; k < NLY; ++k)
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            acc[k].x += __shfl_xor(acc[k].x, off, 64);
+            acc[k].y += __shfl_xor(acc[k].y, off, 64);
+        }
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < NLY; ++k) red[threadIdx.x >> 6][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x < NLY) {
+        const int k = threadIdx.x;
+        double2 L = red[0][k];
+        for (int w = 1; w < 4; ++w) {
+            L.x += red[w][k].x;
+            L.y += red[w][k].y;
+        }
+        const int o = kxy * NLY + k;
+        out[(size_t)rot * NLOW3 + o] = MODE == 0 ? dcmul(L, Wlow[o]) : make_double2(L.x * scale, -L.y * scale);
     }
 }
 
@@ -672,7 +709,7 @@ __global__ __launch_bounds__(256) void k_low_combine(const double2* __restrict__
 // best candidate by exact score (ties: lowest flat index) -> score, shift, pose
 
 __global__ void k_finalize(const int32_t* __restrict__ cand_idx, const int32_t* __restrict__ cand_n,
-                           const double* __restrict__ cand_exact, int count, const float* __restrict__ quats, int n,
+                           const double* __restrict__ cand_part, int nslice, int count, const float* __restrict__ quats, int n,
                            double h, const double* __restrict__ anchor, double wc0, double wc1, double wc2,
                            float* __restrict__ out_score, int32_t* __restrict__ out_shift, double* __restrict__ out_pose) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -681,7 +718,9 @@ __global__ void k_finalize(const int32_t* __restrict__ cand_idx, const int32_t* 
     double best = -1.0e308;
     uint32_t flat = 0xffffffffu;
     for (int c = 0; c < cn; ++c) {
-        const double v = cand_exact[(size_t)i * CMAX + c];
+        const double* part = cand_part + ((size_t)i * CMAX + c) * nslice;
+        double v = 0.0;
+        for (int sl = 0; sl < nslice; ++sl) v += part[sl];
         const uint32_t f = (uint32_t)cand_idx[(size_t)i * CMAX + c];
         if (v > best || (v == best && f < flat)) {
             best = v;
@@ -865,55 +904,181 @@ __device__ __forceinline__ float object_value(float fo, float dt, float tau_out1
     return fminf(ot, om);
 }
 
-// One voxel per thread; faces staged through LDS in chunks; brute force over
-// every face: nearest distance, nearest touchable distance, winding number.
-__global__ __launch_bounds__(256) void k_object_grid(const float* __restrict__ V, const int32_t* __restrict__ F,
-                                                     const uint8_t* __restrict__ touch, int nf, int n, double h,
-                                                     const double* __restrict__ anchor, float tau_out1, float tau_in1,
-                                                     float rho, float* __restrict__ O, float* __restrict__ fo_out) {
-    constexpr int CH = 256;
-    __shared__ float sv[CH][9];
-    __shared__ uint8_t st[CH];
-    const size_t n3 = (size_t)n * n * n;
-    const size_t id = (size_t)blockIdx.x * 256 + threadIdx.x;
-    const bool live = id < n3;
-    const int kx = (int)(id % n), ky = (int)((id / n) % n), kz = (int)(id / ((size_t)n * n));
+// capped-cylinder SDF of the probe, float (tip disk at the origin, axis +z)
+__device__ __forceinline__ float probe_sdf(float x, float y, float z, float r, float L) {
+    const float q1 = sqrtf(x * x + y * y) - r;
+    const float q2 = fabsf(z - 0.5f * L) - 0.5f * L;
+    const float a = fmaxf(q1, 0.f), b = fmaxf(q2, 0.f);
+    return fminf(fmaxf(q1, q2), 0.f) + sqrtf(a * a + b * b);
+}
+
+// ---- object grid by scatter (per object) ----------------------------------
+// Distances matter only inside the band (tau_out1 + h): every face updates
+// the voxels of its bounding box grown by the band with atomicMin on float bits
+// (non-negative floats order like their bits), so the minimum is exact there
+// and independent of the order.  Inside/outside comes from +z ray crossing
+// parity: every face toggles, in each column its projection covers, the bits of
+// the voxels below the crossing (atomicXor on per-column bit words), with the
+// same simulation-of-simplicity tie rule at shared edges as the FP64 oracle.
+
+constexpr uint32_t FLT_MAX_BITS = 0x7f7fffffu;
+
+__global__ void k_obj_init(uint32_t* __restrict__ d2, uint32_t* __restrict__ dt2, size_t n3, uint32_t* __restrict__ par,
+                           size_t nwords) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n3) {
+        d2[i] = FLT_MAX_BITS;
+        dt2[i] = FLT_MAX_BITS;
+    }
+    if (i < nwords) par[i] = 0u;
+}
+
+__device__ __forceinline__ void face_box(const double* lo_w, const double* hi_w, const double* anchor, double h, int n,
+                                         int* lo, int* hi) {
+    const double half = 0.5 * n;
+    for (int j = 0; j < 3; ++j) {
+        lo[j] = (int)ceil((lo_w[j] - anchor[j]) / h + half);
+        hi[j] = (int)floor((hi_w[j] - anchor[j]) / h + half);
+        lo[j] = lo[j] < 0 ? 0 : lo[j];
+        hi[j] = hi[j] > n - 1 ? n - 1 : hi[j];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_obj_faces(const float* __restrict__ V, const int32_t* __restrict__ F,
+                                                   const uint8_t* __restrict__ touch, int n, double h,
+                                                   const double* __restrict__ anchor, double band,
+                                                   uint32_t* __restrict__ d2, uint32_t* __restrict__ dt2) {
+    const int f = blockIdx.x;
+    const int i0 = F[3 * f], i1 = F[3 * f + 1], i2 = F[3 * f + 2];
+    const float3 a = make_float3(V[3 * i0], V[3 * i0 + 1], V[3 * i0 + 2]);
+    const float3 b = make_float3(V[3 * i1], V[3 * i1 + 1], V[3 * i1 + 2]);
+    const float3 c = make_float3(V[3 * i2], V[3 * i2 + 1], V[3 * i2 + 2]);
+    const bool tf = touch[f] != 0;
+    const double an[3] = {anchor[0], anchor[1], anchor[2]};
+    double lo_w[3] = {fmin((double)a.x, fmin((double)b.x, (double)c.x)) - band, fmin((double)a.y, fmin((double)b.y, (double)c.y)) - band,
+                      fmin((double)a.z, fmin((double)b.z, (double)c.z)) - band};
+    double hi_w[3] = {fmax((double)a.x, fmax((double)b.x, (double)c.x)) + band, fmax((double)a.y, fmax((double)b.y, (double)c.y)) + band,
+                      fmax((double)a.z, fmax((double)b.z, (double)c.z)) + band};
+    int lo[3], hi[3];
+    face_box(lo_w, hi_w, an, h, n, lo, hi);
+    const int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
+    if (ex <= 0 || ey <= 0 || ez <= 0) return;
+    const int cnt = ex * ey * ez;
+    const float band2 = (float)(band * band);
     const double hn = 0.5 * n;
-    const float3 p = make_float3((float)(anchor[0] + h * (kx - hn)), (float)(anchor[1] + h * (ky - hn)),
-                                 (float)(anchor[2] + h * (kz - hn)));
-    float dmin = 3.0e38f, dtmin = 3.0e38f, omega = 0.0f;
-    for (int f0 = 0; f0 < nf; f0 += CH) {
-        __syncthreads();
-        const int f = f0 + threadIdx.x;
-        if (f < nf) {
-            for (int v = 0; v < 3; ++v) {
-                const int vi = F[3 * f + v];
-                sv[threadIdx.x][3 * v] = V[3 * vi];
-                sv[threadIdx.x][3 * v + 1] = V[3 * vi + 1];
-                sv[threadIdx.x][3 * v + 2] = V[3 * vi + 2];
-            }
-            st[threadIdx.x] = touch ? touch[f] : (uint8_t)1;
-        }
-        __syncthreads();
-        const int cnt = min(CH, nf - f0);
-        if (live) {
-            for (int i = 0; i < cnt; ++i) {
-                const float3 a = make_float3(sv[i][0], sv[i][1], sv[i][2]);
-                const float3 b = make_float3(sv[i][3], sv[i][4], sv[i][5]);
-                const float3 c = make_float3(sv[i][6], sv[i][7], sv[i][8]);
-                const float d2 = tri_dist2(p, a, b, c);
-                dmin = fminf(dmin, d2);
-                if (st[i]) dtmin = fminf(dtmin, d2);
-                omega += solid_angle(p, a, b, c);
-            }
+    for (int q = threadIdx.x; q < cnt; q += 256) {
+        const int kx = lo[0] + q % ex, ky = lo[1] + (q / ex) % ey, kz = lo[2] + q / (ex * ey);
+        const float3 p = make_float3((float)(an[0] + h * (kx - hn)), (float)(an[1] + h * (ky - hn)), (float)(an[2] + h * (kz - hn)));
+        const float dd = tri_dist2(p, a, b, c);
+        if (dd < band2) {
+            const size_t id = ((size_t)kz * n + ky) * n + kx;
+            atomicMin(d2 + id, __float_as_uint(dd));
+            if (tf) atomicMin(dt2 + id, __float_as_uint(dd));
         }
     }
-    if (!live) return;
-    const float dm = sqrtf(dmin), dt = sqrtf(dtmin);
-    const bool inside = omega >= 6.283185307179586f;  // winding number >= 1/2
+}
+
+__device__ __forceinline__ int orient_sos(double ax, double ay, double bx, double by, double px, double py) {
+    const double o = (bx - ax) * (py - ay) - (by - ay) * (px - ax);
+    if (o > 0) return 1;
+    if (o < 0) return -1;
+    if (by != ay) return (ay - by) > 0 ? 1 : -1;
+    if (bx != ax) return (bx - ax) > 0 ? 1 : -1;
+    return 0;
+}
+
+__global__ __launch_bounds__(64) void k_obj_parity(const float* __restrict__ V, const int32_t* __restrict__ F, int n, double h,
+                                                   const double* __restrict__ anchor, int W, uint32_t* __restrict__ par) {
+    const int f = blockIdx.x;
+    const int i0 = F[3 * f], i1 = F[3 * f + 1], i2 = F[3 * f + 2];
+    const double a[3] = {V[3 * i0], V[3 * i0 + 1], V[3 * i0 + 2]};
+    const double b[3] = {V[3 * i1], V[3 * i1 + 1], V[3 * i1 + 2]};
+    const double c[3] = {V[3 * i2], V[3 * i2 + 1], V[3 * i2 + 2]};
+    const double an[3] = {anchor[0], anchor[1], anchor[2]};
+    const double hn = 0.5 * n;
+    int clo[2], chi[2];
+    for (int j = 0; j < 2; ++j) {
+        const double mn = fmin(a[j], fmin(b[j], c[j])), mx = fmax(a[j], fmax(b[j], c[j]));
+        clo[j] = (int)floor((mn - an[j]) / h + hn);
+        chi[j] = (int)ceil((mx - an[j]) / h + hn);
+        clo[j] = clo[j] < 0 ? 0 : clo[j];
+        chi[j] = chi[j] > n - 1 ? n - 1 : chi[j];
+    }
+    const int ex = chi[0] - clo[0] + 1, ey = chi[1] - clo[1] + 1;
+    if (ex <= 0 || ey <= 0) return;
+    for (int q = threadIdx.x; q < ex * ey; q += 64) {
+        const int kx = clo[0] + q % ex, ky = clo[1] + q / ex;
+        const double px = an[0] + h * (kx - hn), py = an[1] + h * (ky - hn);
+        const int s1 = orient_sos(a[0], a[1], b[0], b[1], px, py);
+        const int s2 = orient_sos(b[0], b[1], c[0], c[1], px, py);
+        const int s3 = orient_sos(c[0], c[1], a[0], a[1], px, py);
+        if (!((s1 > 0 && s2 > 0 && s3 > 0) || (s1 < 0 && s2 < 0 && s3 < 0))) continue;
+        const double w1 = (b[0] - a[0]) * (py - a[1]) - (b[1] - a[1]) * (px - a[0]);
+        const double w2 = (c[0] - b[0]) * (py - b[1]) - (c[1] - b[1]) * (px - b[0]);
+        const double w3 = (a[0] - c[0]) * (py - c[1]) - (a[1] - c[1]) * (px - c[0]);
+        const double zi = (w2 * a[2] + w3 * b[2] + w1 * c[2]) / (w1 + w2 + w3);
+        int below = 0;  // voxels of the column with z < zi
+        while (below < n && an[2] + h * (below - hn) < zi) ++below;
+        uint32_t* col = par + ((size_t)ky * n + kx) * W;
+        for (int w = 0; w < W && 32 * w < below; ++w) {
+            const int top = below - 32 * w;
+            atomicXor(col + w, top >= 32 ? 0xffffffffu : ((1u << top) - 1u));
+        }
+    }
+}
+
+__global__ void k_obj_finalize(const uint32_t* __restrict__ d2, const uint32_t* __restrict__ dt2,
+                               const uint32_t* __restrict__ par, int W, int n, float tau_out1, float tau_in1, float rho,
+                               float* __restrict__ O, float* __restrict__ fo_out) {
+    const size_t n3 = (size_t)n * n * n;
+    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n3) return;
+    const int kx = (int)(id % n), ky = (int)((id / n) % n), kz = (int)(id / ((size_t)n * n));
+    const bool inside = (par[((size_t)ky * n + kx) * W + (kz >> 5)] >> (kz & 31)) & 1u;
+    const float dm = d2[id] == FLT_MAX_BITS ? INFINITY : sqrtf(__uint_as_float(d2[id]));
+    const float dt = dt2[id] == FLT_MAX_BITS ? INFINITY : sqrtf(__uint_as_float(dt2[id]));
     const float fo = inside ? -dm : dm;
     O[id] = object_value(fo, dt, tau_out1, tau_in1, rho);
     if (fo_out) fo_out[id] = fo;
+}
+
+// ---- swept occupancy by scatter (per request) -----------------------------
+// Each pose visits the lattice points of its cylinder's bounding box (grown by
+// a small margin) and stores 1 where f_p <= 0; stores are idempotent, so the
+// result does not depend on the order of the poses.
+
+__global__ void k_fill_u8(uint8_t* __restrict__ p, size_t cnt, uint8_t v) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_swept_pose(const float* __restrict__ pz, float r, float L, int m, double h,
+                                                    double wc0, double wc1, double wc2, uint8_t* __restrict__ Sw) {
+    const float* P = pz + 12 * blockIdx.x;
+    const double wc[3] = {wc0, wc1, wc2};
+    const double ax[3] = {P[2], P[5], P[8]};  // probe axis in world
+    const double hm = 0.5 * m;
+    int lo[3], hi[3];
+    for (int j = 0; j < 3; ++j) {
+        const double e = (double)r * sqrt(fmax(0.0, 1.0 - ax[j] * ax[j])) + 1e-3;
+        const double c0 = P[9 + j], c1 = P[9 + j] + (double)L * ax[j];
+        lo[j] = (int)ceil((fmin(c0, c1) - e - wc[j]) / h + hm);
+        hi[j] = (int)floor((fmax(c0, c1) + e - wc[j]) / h + hm);
+        lo[j] = lo[j] < 0 ? 0 : lo[j];
+        hi[j] = hi[j] > m - 1 ? m - 1 : hi[j];
+    }
+    const int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
+    if (ex <= 0 || ey <= 0 || ez <= 0) return;
+    const int cnt = ex * ey * ez;
+    for (int q = threadIdx.x; q < cnt; q += 256) {
+        const int jx = lo[0] + q % ex, jy = lo[1] + (q / ex) % ey, jz = lo[2] + q / (ex * ey);
+        const float yx = (float)(wc0 + h * (jx - hm)), yy = (float)(wc1 + h * (jy - hm)), yz = (float)(wc2 + h * (jz - hm));
+        const float dx = yx - P[9], dy = yy - P[10], dz = yz - P[11];
+        const float lx = P[0] * dx + P[3] * dy + P[6] * dz;
+        const float ly = P[1] * dx + P[4] * dy + P[7] * dz;
+        const float lz = P[2] * dx + P[5] * dy + P[8] * dz;
+        if (probe_sdf(lx, ly, lz, r, L) <= 0.f) Sw[((size_t)jz * m + jy) * m + jx] = 1;
+    }
 }
 
 // poses (qw qx qy qz tx ty tz) -> R (row-major, from the normalised quaternion
@@ -931,47 +1096,6 @@ __global__ void k_pose_prep(const float* __restrict__ poses, int np, float* __re
     o[9] = poses[7 * i + 4]; o[10] = poses[7 * i + 5]; o[11] = poses[7 * i + 6];
 }
 
-__device__ __forceinline__ float probe_sdf(float x, float y, float z, float r, float L) {
-    const float q1 = sqrtf(x * x + y * y) - r;
-    const float q2 = fabsf(z - 0.5f * L) - 0.5f * L;
-    const float a = fmaxf(q1, 0.f), b = fmaxf(q2, 0.f);
-    return fminf(fmaxf(q1, q2), 0.f) + sqrtf(a * a + b * b);
-}
-
-// S_w on the m^3 lattice; poses staged through LDS; one point per thread
-__global__ __launch_bounds__(256) void k_swept(const float* __restrict__ pz, int np, float r, float L, int m, double h,
-                                               double wc0, double wc1, double wc2, uint8_t* __restrict__ Sw) {
-    constexpr int CH = 256;
-    __shared__ float sp[CH][12];
-    const size_t m3 = (size_t)m * m * m;
-    const size_t id = (size_t)blockIdx.x * 256 + threadIdx.x;
-    const bool live = id < m3;
-    const int jx = (int)(id % m), jy = (int)((id / m) % m), jz = (int)(id / ((size_t)m * m));
-    const double hm = 0.5 * m;
-    const float yx = (float)(wc0 + h * (jx - hm)), yy = (float)(wc1 + h * (jy - hm)), yz = (float)(wc2 + h * (jz - hm));
-    bool hit = false;
-    for (int p0 = 0; p0 < np; p0 += CH) {
-        __syncthreads();
-        if (p0 + threadIdx.x < np)
-            for (int a = 0; a < 12; ++a) sp[threadIdx.x][a] = pz[12 * (p0 + threadIdx.x) + a];
-        __syncthreads();
-        const int cnt = min(CH, np - p0);
-        if (live && !hit) {
-            for (int i = 0; i < cnt; ++i) {
-                const float* P = sp[i];
-                const float dx = yx - P[9], dy = yy - P[10], dz = yz - P[11];
-                const float lx = P[0] * dx + P[3] * dy + P[6] * dz;
-                const float ly = P[1] * dx + P[4] * dy + P[7] * dz;
-                const float lz = P[2] * dx + P[5] * dy + P[8] * dz;
-                if (probe_sdf(lx, ly, lz, r, L) <= 0.f) {
-                    hit = true;
-                    break;
-                }
-            }
-        }
-    }
-    if (live) Sw[id] = hit ? 1 : 0;
-}
 
 // corner masks over the padded, bricked lattice; taps beyond the lattice are 0
 __global__ void k_cellmask(const uint8_t* __restrict__ Sw, int m, int mp, uint8_t* __restrict__ cm) {
@@ -1032,7 +1156,8 @@ static hipError_t launch_search_pass(int pass, const SearchBatchArgs& a) {
         hipLaunchKernelGGL(k_rotvox_fwd_xy<N>, dim3(a.count * N), dim3(C::NT), 0, a.stream, a.cmask, a.m, a.mp / 4, a.rots,
                            a.count, a.tw, a.tw64, a.spec, a.lowT);
     else if (pass == 1) {
-        hipLaunchKernelGGL((k_low_combine<0>), dim3(a.count), dim3(256), 0, a.stream, a.lowT, N, a.tw64, a.Wlow, 1.0, a.Plow);
+        hipLaunchKernelGGL((k_low_combine<0>), dim3(a.count * NLOW2), dim3(256), 0, a.stream, a.lowT, N, a.tw64, a.Wlow, 1.0,
+                           a.Plow);
         hipLaunchKernelGGL((k_zpass<N, 0>), dim3(a.count * C::TILES), dim3(C::NT), 0, a.stream, a.spec, a.W, nullptr, a.tw,
                            1.0f);
     } else {
@@ -1049,7 +1174,7 @@ static hipError_t launch_object_spectrum(const float* O, float2* spec_tmp, float
     const double scale = 1.0 / ((double)N * N * N);
     hipLaunchKernelGGL(k_grid_fwd_xy<N>, dim3(N), dim3(C::NT), 0, s, O, tw, tw64, spec_tmp, lowT_tmp);
     hipLaunchKernelGGL((k_zpass<N, 1>), dim3(C::TILES), dim3(C::NT), 0, s, spec_tmp, nullptr, W, tw, (float)scale);
-    hipLaunchKernelGGL((k_low_combine<1>), dim3(1), dim3(256), 0, s, lowT_tmp, N, tw64, nullptr, scale, Wlow);
+    hipLaunchKernelGGL((k_low_combine<1>), dim3(NLOW2), dim3(256), 0, s, lowT_tmp, N, tw64, nullptr, scale, Wlow);
     return hipGetLastError();
 }
 
@@ -1103,10 +1228,16 @@ hipError_t object_spectrum(int n, const float* O, float2* spec_tmp, float2* W, c
 
 hipError_t setup_object_grid(const float* V, const int32_t* F, const uint8_t* touch, int nf, int n, double h,
                              const double* anchor, float tau_out1, float tau_in1, float rho, float* O, float* fo,
-                             hipStream_t s) {
+                             const ObjectScratch& w, hipStream_t s) {
     const size_t n3 = (size_t)n * n * n;
-    hipLaunchKernelGGL(k_object_grid, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, V, F, touch, nf, n, h, anchor,
-                       tau_out1, tau_in1, rho, O, fo);
+    const int W = (n + 31) / 32;
+    const size_t nwords = (size_t)n * n * W;
+    const size_t mx = n3 > nwords ? n3 : nwords;
+    hipLaunchKernelGGL(k_obj_init, dim3((unsigned)((mx + 255) / 256)), dim3(256), 0, s, w.d2, w.dt2, n3, w.par, nwords);
+    hipLaunchKernelGGL(k_obj_faces, dim3(nf), dim3(256), 0, s, V, F, touch, n, h, anchor, (double)tau_out1 + h, w.d2, w.dt2);
+    hipLaunchKernelGGL(k_obj_parity, dim3(nf), dim3(64), 0, s, V, F, n, h, anchor, W, w.par);
+    hipLaunchKernelGGL(k_obj_finalize, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, w.d2, w.dt2, w.par, W, n, tau_out1,
+                       tau_in1, rho, O, fo);
     return hipGetLastError();
 }
 
@@ -1119,8 +1250,8 @@ hipError_t setup_swept(const float* poses, int np, float r, float L, int m, int 
                        float* pose_tmp, uint8_t* Sw, uint8_t* cm, hipStream_t s) {
     hipLaunchKernelGGL(k_pose_prep, dim3((np + 255) / 256), dim3(256), 0, s, poses, np, pose_tmp);
     const size_t m3 = (size_t)m * m * m;
-    hipLaunchKernelGGL(k_swept, dim3((unsigned)((m3 + 255) / 256)), dim3(256), 0, s, pose_tmp, np, r, L, m, h, wc[0], wc[1],
-                       wc[2], Sw);
+    hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)((m3 + 255) / 256)), dim3(256), 0, s, Sw, m3, (uint8_t)0);
+    hipLaunchKernelGGL(k_swept_pose, dim3(np), dim3(256), 0, s, pose_tmp, r, L, m, h, wc[0], wc[1], wc[2], Sw);
     const size_t mp3 = (size_t)mp * mp * mp;
     hipLaunchKernelGGL(k_cellmask, dim3((unsigned)((mp3 + 255) / 256)), dim3(256), 0, s, Sw, m, mp, cm);
     return hipGetLastError();
@@ -1144,18 +1275,27 @@ hipError_t validate_inputs(const float* V, int nv, const int32_t* F, int nf, con
     return hipGetLastError();
 }
 
+int rescore_slices(int n) {
+    const size_t n3 = (size_t)n * n * n;
+    return (int)((n3 + 65535) / 65536);
+}
+
 hipError_t candidates_batch(int n, const SearchBatchArgs& a) {
     const double eps_per_rms = REGK_EPS_SCALE * std::ldexp(1.0, -24) * std::log2((double)n * n * n);
     hipLaunchKernelGGL(k_select, dim3(a.count), dim3(256), 0, a.stream, a.ptop, a.pssq, n, eps_per_rms, a.cand_idx,
                        a.cand_n, a.stats, a.window, a.ovf);
-    hipLaunchKernelGGL(k_rescore, dim3(a.count * CMAX), dim3(256), 0, a.stream, a.nz_idx, a.nz_val, a.nz_count, n, a.cmask,
-                       a.m, a.mp / 4, a.rots, a.cand_idx, a.cand_n, a.cand_exact);
+    const int nslice = rescore_slices(n);
+    const int items = a.count * CMAX * nslice;
+    const int grid = items < 4096 ? items : 4096;
+    hipLaunchKernelGGL(k_rescore, dim3(grid), dim3(256), 0, a.stream, a.nz_idx, a.nz_val, a.nz_count, n, nslice, a.cmask, a.m,
+                       a.mp / 4, a.rots, a.count, a.cand_idx, a.cand_n, a.cand_part);
     return hipGetLastError();
 }
 
 hipError_t finalize_batch(const SearchBatchArgs& a, int n, const float* quats, double h, const double* anchor,
                           const double* wc, float* out_score, int32_t* out_shift, double* out_pose) {
-    hipLaunchKernelGGL(k_finalize, dim3((a.count + 127) / 128), dim3(128), 0, a.stream, a.cand_idx, a.cand_n, a.cand_exact,
+    hipLaunchKernelGGL(k_finalize, dim3((a.count + 127) / 128), dim3(128), 0, a.stream, a.cand_idx, a.cand_n, a.cand_part,
+                       rescore_slices(n),
                        a.count, quats, n, h, anchor, wc[0], wc[1], wc[2], out_score, out_shift, out_pose);
     return hipGetLastError();
 }
