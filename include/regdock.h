@@ -83,13 +83,17 @@ typedef struct {
  * tau_out1 0.5 mm, tau_in1 0.2 mm, deep-penetration penalty rho 50 (a deep voxel
  * gets -rho), tau_out2 0.2 mm, tau_in2 0.03 mm, k 15, lambda 1e-3; bounds
  * b_t 0.5 mm and b_r 0.2 rad and the query cutoff eps 0.25 mm are not given by
- * the paper.  batch = rotations per batched launch (0: chosen from n). */
+ * the paper.  batch = rotations per batched launch (0: chosen from n).
+ * rescore = 1 re-scores the candidates of every rotation exactly; 0 only those
+ * whose float32 error window exceeds the score tolerance (see
+ * register_search_stats). */
 typedef struct {
     double tau_out1, tau_in1, rho;
     double tau_out2, tau_in2, k, lambda;
     double b_t, b_r, eps;
     int32_t max_iters;
     int32_t batch;
+    int32_t rescore;
 } reg_params;
 
 /* Build a registration problem (Sec. IV-A): the object grid O and its spectrum
@@ -120,19 +124,20 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
 int score_rotations(reg_handle* h, int32_t first, int32_t count, float* out_score, int32_t* out_shift,
                     double* out_pose);
 
-/* How the peaks were found.  The float32 FFT path only locates candidates:
- * every shift whose value lies within 2 eps of the rotation's maximum,
- * eps = 6 * 2^-24 * rms(C_high) * log2(n^3) bounding the float32 error of the
- * field outside its exact low-frequency block, is re-scored exactly (direct sum
- * over the nonzero voxels of O, accumulated in double) and the best exact score
- * wins.  Counters since register_init: scored rotations, re-scored candidates,
- * rotations whose window held more candidates than were kept (4 per plane, 16
- * per rotation: exact ties on score plateaus; the best kept one is reported,
- * within 2 eps of the maximum), and of those the "uncertain" ones, whose 2 eps
- * exceeds 1e-4 of the largest |score| of their score_rotations call.  Host
- * pointers; synchronises the stream. */
+/* How the peaks were found.  The field is float32 FFTs plus an exact double
+ * low-frequency block; eps = 6 * 2^-24 * rms(C_high) * log2(n^3) bounds its
+ * error.  Per rotation, every shift within 2 eps of the field maximum is a
+ * candidate (4 kept per plane, 16 per rotation).  After all rotations of a
+ * call, tol = 1e-4 * max |score|: a rotation with 2 eps <= tol keeps the field
+ * maximum (value within eps, index within tol of the best); the others (all,
+ * with params.rescore) have their candidates re-scored exactly -- a direct sum
+ * over the nonzero voxels of O in double -- and the best exact score wins.
+ * Counters since register_init: scored rotations, candidates, rotations whose
+ * window held more candidates than were kept (exact-tie plateaus), "uncertain"
+ * rotations (re-scored, overflowed, and 2 eps > tol), and re-scored rotations.
+ * Host pointers; synchronises the stream. */
 int register_search_stats(reg_handle* h, int64_t* rotations, int64_t* candidates, int64_t* overflows,
-                          int64_t* uncertain);
+                          int64_t* uncertain, int64_t* rescored);
 
 /* The K best rotations of a score vector (score descending, index ascending),
  * computed on the device.  scores: count float; out_idx: K int32.

@@ -50,7 +50,8 @@ class reg_params(ctypes.Structure):
     _fields_ = [("tau_out1", ctypes.c_double), ("tau_in1", ctypes.c_double), ("rho", ctypes.c_double),
                 ("tau_out2", ctypes.c_double), ("tau_in2", ctypes.c_double), ("k", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("b_t", ctypes.c_double), ("b_r", ctypes.c_double),
-                ("eps", ctypes.c_double), ("max_iters", ctypes.c_int32), ("batch", ctypes.c_int32)]
+                ("eps", ctypes.c_double), ("max_iters", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("rescore", ctypes.c_int32)]
 
 
 _lib = None
@@ -92,8 +93,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.register_set_grids.restype = ctypes.c_int
     L.register_set_grids.argtypes = [p, p, p]
     L.register_search_stats.restype = ctypes.c_int
-    L.register_search_stats.argtypes = [p, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
-                                        ctypes.POINTER(i64)]
+    L.register_search_stats.argtypes = [p] + [ctypes.POINTER(i64)] * 5
     L.register_set_timing.restype = ctypes.c_int
     L.register_set_timing.argtypes = [p, i32]
     L.register_get_timing.restype = ctypes.c_int
@@ -252,7 +252,7 @@ def register_get_timing(h: Handle) -> dict:
 
 
 def register_search_stats(h: Handle) -> dict:
-    r, c, o, u = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-    _check(load_library().register_search_stats(h.ptr, ctypes.byref(r), ctypes.byref(c), ctypes.byref(o),
-                                                ctypes.byref(u)))
-    return dict(rotations=r.value, candidates=c.value, overflows=o.value, uncertain=u.value)
+    v = [ctypes.c_int64() for _ in range(5)]
+    _check(load_library().register_search_stats(h.ptr, *[ctypes.byref(x) for x in v]))
+    return dict(rotations=v[0].value, candidates=v[1].value, overflows=v[2].value, uncertain=v[3].value,
+                rescored=v[4].value)

@@ -65,6 +65,10 @@ struct reg_handle {
     int* stats = nullptr;
     double* window = nullptr;
     uint8_t* ovf = nullptr;
+    double* best_val = nullptr;
+    int32_t* best_flat = nullptr;
+    int32_t* need_list = nullptr;
+    int* need_count = nullptr;
     uint32_t* nz_idx = nullptr;
     float* nz_val = nullptr;
     int* nz_count = nullptr;
@@ -230,12 +234,16 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
     ALLOC_TRY(h, h->spec, h->H * (size_t)h->batch);
     ALLOC_TRY(h, h->ptop, (size_t)h->batch * h->n * KTOP);
     ALLOC_TRY(h, h->pssq, (size_t)h->batch * h->n);
-    ALLOC_TRY(h, h->cand_idx, (size_t)h->batch * CMAX);
-    ALLOC_TRY(h, h->cand_n, (size_t)h->batch);
-    ALLOC_TRY(h, h->cand_part, (size_t)h->batch * CMAX * rescore_slices(h->n));
-    ALLOC_TRY(h, h->stats, 4);
+    ALLOC_TRY(h, h->cand_idx, (size_t)n_rot * CMAX);
+    ALLOC_TRY(h, h->cand_n, (size_t)n_rot);
+    ALLOC_TRY(h, h->cand_part, (size_t)n_rot * CMAX * rescore_slices(h->n));
+    ALLOC_TRY(h, h->stats, 5);
     ALLOC_TRY(h, h->window, (size_t)n_rot);
     ALLOC_TRY(h, h->ovf, (size_t)n_rot);
+    ALLOC_TRY(h, h->best_val, (size_t)n_rot);
+    ALLOC_TRY(h, h->best_flat, (size_t)n_rot);
+    ALLOC_TRY(h, h->need_list, (size_t)n_rot);
+    ALLOC_TRY(h, h->need_count, 1);
     ALLOC_TRY(h, h->nz_idx, n3);
     ALLOC_TRY(h, h->nz_val, n3);
     ALLOC_TRY(h, h->nz_count, 1);
@@ -273,7 +281,7 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
 
     // input checks on the device, then wait for them
     DEV_TRY(h, hipMemsetAsync(h->err, 0, sizeof(int), s));
-    DEV_TRY(h, hipMemsetAsync(h->stats, 0, 4 * sizeof(int), s));
+    DEV_TRY(h, hipMemsetAsync(h->stats, 0, 5 * sizeof(int), s));
     DEV_TRY(h, validate_inputs(h->V, h->nv, h->F, h->nf, h->poses, n_poses, h->err, s));
     DEV_TRY(h, setup_rotations(h->so3, n_rot, h->rots, h->err, s));
     int herr = 0;
@@ -315,6 +323,8 @@ int register_info(const reg_handle* h, int32_t* n, int32_t* m, int64_t* spectrum
 
 static int run_batches(reg_handle* h, int first, int count, float* out_score, int32_t* out_shift, double* out_pose,
                        float* corr_out) {
+    const PeakArrays pk{h->cand_idx, h->cand_n, h->window, h->ovf, h->best_val, h->best_flat,
+                        h->need_list, h->need_count, h->cand_part, h->stats};
     for (int b0 = 0; b0 < count; b0 += h->batch) {
         const int cnt = count - b0 < h->batch ? count - b0 : h->batch;
         SearchBatchArgs a{};
@@ -332,15 +342,6 @@ static int run_batches(reg_handle* h, int first, int count, float* out_score, in
         a.Plow = h->Plow;
         a.ptop = h->ptop;
         a.pssq = h->pssq;
-        a.cand_idx = h->cand_idx;
-        a.cand_n = h->cand_n;
-        a.cand_part = h->cand_part;
-        a.stats = h->stats;
-        a.window = h->window + (first + b0);
-        a.ovf = h->ovf + (first + b0);
-        a.nz_idx = h->nz_idx;
-        a.nz_val = h->nz_val;
-        a.nz_count = h->nz_count;
         a.corr_out = corr_out;
         a.stream = h->stream;
         for (int pass = 0; pass < 3; ++pass) {
@@ -357,11 +358,11 @@ static int run_batches(reg_handle* h, int first, int count, float* out_score, in
                 h->timed.push_back({e0, e1, pass, cnt});
             }
         }
-        DEV_TRY(h, candidates_batch(h->n, a));
-        DEV_TRY(h, finalize_batch(a, h->n, h->so3 + 4 * (size_t)(first + b0), h->h, h->anchor, h->wc,
-                                  out_score ? out_score + b0 : nullptr, out_shift ? out_shift + 3 * (size_t)b0 : nullptr,
-                                  out_pose ? out_pose + 7 * (size_t)b0 : nullptr));
+        DEV_TRY(h, select_batch(h->n, a, first + b0, pk));
     }
+    const RescoreInputs ri{h->nz_idx, h->nz_val, h->nz_count, h->cm, h->m, h->mp, h->rots};
+    DEV_TRY(h, finish_call(h->n, first, count, h->prm.rescore != 0, pk, ri, h->so3 + 4 * (size_t)first, h->h, h->anchor,
+                           h->wc, out_score, out_shift, out_pose, h->stream));
     return REG_OK;
 }
 
@@ -373,10 +374,7 @@ int score_rotations(reg_handle* h, int32_t first, int32_t count, float* out_scor
     if (first < 0 || count < 0 || (int64_t)first + count > h->n_rot)
         return fail(REG_EINVAL, "rotation range [%d, %d) outside [0, %d)", first, first + count, h->n_rot);
     if (count == 0) return REG_OK;
-    int rc = run_batches(h, first, count, out_score, out_shift, out_pose, nullptr);
-    if (rc) return rc;
-    DEV_TRY(h, certify(out_score, count, h->window + first, h->ovf + first, h->stats, h->stream));
-    return REG_OK;
+    return run_batches(h, first, count, out_score, out_shift, out_pose, nullptr);
 }
 
 int register_set_timing(reg_handle* h, int32_t enable) {
@@ -407,16 +405,18 @@ int register_get_timing(reg_handle* h, double* ms, int64_t* launches, int64_t* r
 }
 
 int register_search_stats(reg_handle* h, int64_t* rotations, int64_t* candidates, int64_t* overflows,
-                          int64_t* uncertain) {
-    if (!h || !rotations || !candidates || !overflows || !uncertain) return fail(REG_EINVAL, "NULL argument");
+                          int64_t* uncertain, int64_t* rescored) {
+    if (!h || !rotations || !candidates || !overflows || !uncertain || !rescored)
+        return fail(REG_EINVAL, "NULL argument");
     if (h->poisoned) return fail(REG_EDEVICE, "handle poisoned by an earlier device error");
-    int st[4] = {0, 0, 0, 0};
+    int st[5] = {0, 0, 0, 0, 0};
     DEV_TRY(h, hipMemcpyAsync(st, h->stats, sizeof st, hipMemcpyDeviceToHost, h->stream));
     DEV_TRY(h, hipStreamSynchronize(h->stream));
     *rotations = st[0];
     *candidates = st[1];
     *overflows = st[2];
     *uncertain = st[3];
+    *rescored = st[4];
     return REG_OK;
 }
 

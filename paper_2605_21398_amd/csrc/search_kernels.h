@@ -41,15 +41,6 @@ struct SearchBatchArgs {
     double2* Plow;             // [count][NLOW3] exact product on the low block
     unsigned long long* ptop;  // [count][n][KTOP] per-plane best keys (score bits, ~flat)
     double* pssq;              // [count][n] per-plane sums of squares of the field
-    int32_t* cand_idx;         // [count][CMAX] candidate flat indices
-    int32_t* cand_n;           // [count] candidates per rotation
-    double* cand_part;         // [count][CMAX][rescore_slices(n)] slice sums of the exact scores
-    int* stats;                // [4] rotations, candidates, overflowed, uncertain rotations
-    double* window;            // [count] candidate window 2 eps per rotation
-    uint8_t* ovf;              // [count] 1 if the rotation's window overflowed
-    const uint32_t* nz_idx;    // nonzero voxels of O: packed kx | ky << 8 | kz << 16
-    const float* nz_val;       //   and their values
-    const int* nz_count;       //   and their number (device)
     float* corr_out;           // optional: full float32 field of a 1-rotation batch
     hipStream_t stream;
 };
@@ -80,9 +71,32 @@ hipError_t setup_cellmask(const uint8_t* Sw, int m, int mp, uint8_t* cm, hipStre
 hipError_t setup_rotations(const float* so3, int M, double* rots, int* err, hipStream_t s);
 hipError_t validate_inputs(const float* V, int nv, const int32_t* F, int nf, const float* poses, int np, int* err,
                            hipStream_t s);
-hipError_t candidates_batch(int n, const SearchBatchArgs& a);
-hipError_t finalize_batch(const SearchBatchArgs& a, int n, const float* quats, double h, const double* anchor,
-                          const double* wc, float* out_score, int32_t* out_shift, double* out_pose);
+// per-rotation peak bookkeeping, indexed by absolute rotation
+struct PeakArrays {
+    int32_t* cand_idx;   // [n_rot][CMAX] candidate flat indices
+    int32_t* cand_n;     // [n_rot]
+    double* window;      // [n_rot] 2 eps
+    uint8_t* ovf;        // [n_rot] window overflowed
+    double* best_val;    // [n_rot] field maximum (double)
+    int32_t* best_flat;  // [n_rot] its flat index
+    int32_t* need_list;  // [n_rot] rotations (relative to the call) to re-score
+    int* need_count;     // [1]
+    double* cand_part;   // [n_rot][CMAX][rescore_slices(n)] slice sums
+    int* stats;          // [5] rotations, candidates, overflowed, uncertain, re-scored
+};
+// what the exact re-score reads
+struct RescoreInputs {
+    const uint32_t* nz_idx;  // nonzero voxels of O: packed kx | ky << 8 | kz << 16
+    const float* nz_val;
+    const int* nz_count;
+    const uint8_t* cmask;
+    int m, mp;
+    const double* rots;      // all rotations
+};
+hipError_t select_batch(int n, const SearchBatchArgs& a, int base, const PeakArrays& pk);
+hipError_t finish_call(int n, int first, int count, int always, const PeakArrays& pk, const RescoreInputs& ri,
+                       const float* quats, double h, const double* anchor, const double* wc, float* out_score,
+                       int32_t* out_shift, double* out_pose, hipStream_t s);
 hipError_t build_nonzero_list(const float* O, int n, int* bcount, int* boff, uint32_t* idx, float* val, int* nnz,
                               hipStream_t s);
 
@@ -92,6 +106,3 @@ namespace regdock {
 hipError_t top_k(const float* scores, int count, int K, int32_t* out, hipStream_t s);
 }
 
-namespace regdock {
-hipError_t certify(const float* scores, int count, const double* window, const uint8_t* ovf, int* stats, hipStream_t s);
-}

@@ -176,7 +176,7 @@ __device__ __forceinline__ void c2r_pre(float2* plane, const float2* tw) {
 template <int N>
 __device__ __forceinline__ void plane_forward_and_store(float2* plane, const float2* tw, float2* __restrict__ spec_rot, int z) {
     using C = Canvas<N>;
-    fft_lds<C::N2, false, N, C::NT, false, N>(plane, 1, C::P, tw);
+    fft_lds<C::N2, false, N, C::NT, true, N>(plane, 1, C::P, tw);
     r2c_post<N>(plane, tw);
     fft_lds<N, false, C::P, C::NT, true, N>(plane, C::P, 1, tw);
     for (int e = threadIdx.x; e < N * C::N2; e += C::NT) {
@@ -216,9 +216,12 @@ __device__ __forceinline__ int mod_n(int v, int n) {
 }
 
 // plane holds z[j] = s[2j] + i s[2j+1] per row; out[kx * NLY + ky + KLOW] =
-// sum_{x,y} s[x,y] exp(-2 pi i (kx x + ky y) / N) in double.
+// sum_{x,y} s[x,y] exp(-2 pi i (kx x + ky y) / N) in double.  tw64 is the
+// double twiddle table in LDS.  Row sums over x run as second-order Goertzel
+// recurrences per kx (one FMA and one subtraction per sample and frequency, no
+// table reads); each row is split into CH contiguous chunks on CH lanes.
 template <int N>
-__device__ __forceinline__ void plane_low_dft(const float2* plane, const double2* __restrict__ tw64, double2* rbuf,
+__device__ __forceinline__ void plane_low_dft(const float2* plane, const double2* tw64, double2* rbuf,
                                               double2* __restrict__ out) {
     using C = Canvas<N>;
     static_assert(N <= C::NT, "one row task set per pass");
@@ -227,21 +230,37 @@ __device__ __forceinline__ void plane_low_dft(const float2* plane, const double2
     const int t = threadIdx.x;
     if (t < N * CH) {
         const int y = t / CH, c = t % CH;
-        double2 acc[NLX];
-#pragma unroll
-        for (int k = 0; k < NLX; ++k) acc[k] = make_double2(0.0, 0.0);
         const int j0 = c * JC, j1 = min(C::N2, j0 + JC);
+        double coef[NLX], s1[NLX], s2[NLX];
+        double sum0 = 0.0;
+#pragma unroll
+        for (int k = 1; k < NLX; ++k) {
+            coef[k] = 2.0 * tw64[k].x;
+            s1[k] = 0.0;
+            s2[k] = 0.0;
+        }
         for (int j = j0; j < j1; ++j) {
             const float2 v = plane[y * C::P + j];
-            const double s0 = (double)v.x, s1 = (double)v.y;
-            const int x0 = 2 * j;
-            acc[0].x += s0 + s1;
+            const double a = (double)v.x, b = (double)v.y;
+            sum0 += a + b;
 #pragma unroll
             for (int k = 1; k < NLX; ++k) {
-                const double2 w0 = tw64[(k * x0) % N], w1 = tw64[(k * (x0 + 1)) % N];
-                acc[k].x = fma(s0, w0.x, fma(s1, w1.x, acc[k].x));
-                acc[k].y = fma(s0, w0.y, fma(s1, w1.y, acc[k].y));
+                const double u0 = fma(coef[k], s1[k], a - s2[k]);
+                const double u1 = fma(coef[k], u0, b - s1[k]);
+                s2[k] = u0;
+                s1[k] = u1;
             }
+        }
+        double2 acc[NLX];
+        acc[0] = make_double2(sum0, 0.0);
+        const int xl = 2 * j1 - 1;  // last sample of the chunk
+#pragma unroll
+        for (int k = 1; k < NLX; ++k) {
+            // y = s1 - e^{-i w} s2 equals e^{+i w xl} * sum_x s[x] e^{-i w x}
+            const double2 e1 = tw64[k];  // (cos w, -sin w)
+            const double2 yk = make_double2(s1[k] - e1.x * s2[k], -e1.y * s2[k]);
+            acc[k] = dcmul(yk, tw64[(k * xl) % N]);
+            if (j1 <= j0) acc[k] = make_double2(0.0, 0.0);
         }
 #pragma unroll
         for (int off = CH / 2; off >= 1; off >>= 1)
@@ -262,10 +281,14 @@ __device__ __forceinline__ void plane_low_dft(const float2* plane, const double2
     if (t < NLOW2 * CB) {
         const int o = t / CB, c = t % CB;
         const int kx = o / NLY, ky = o % NLY - KLOW;
+        int idx = mod_n(ky * c * (N / CB), N);
+        const int step = mod_n(ky, N);
         for (int y = c * (N / CB); y < (c + 1) * (N / CB); ++y) {
-            const double2 r = rbuf[y * NLX + kx], w = tw64[mod_n(ky * y, N)];
+            const double2 r = rbuf[y * NLX + kx], w = tw64[idx];
             part.x = fma(r.x, w.x, fma(-r.y, w.y, part.x));
             part.y = fma(r.x, w.y, fma(r.y, w.x, part.y));
+            idx += step;
+            idx -= idx >= N ? N : 0;
         }
     }
     part.x += __shfl_xor(part.x, 1, 64);
@@ -288,19 +311,67 @@ struct RotSampler {
         hm = 0.5 * m;
         hn = 0.5 * n;
     }
-    __device__ __forceinline__ float sample(const uint8_t* __restrict__ cmask, int m, int mb, int x, int y, int z) const {
+    // lattice cell (brick address, or -1 outside) and the fractional position
+    __device__ __forceinline__ long locate(int m, int mb, int x, int y, int z, float& fx, float& fy, float& fz) const {
         const double xc = (double)x - hn, yc = (double)y - hn, zc = (double)z - hn;
         const double ux = fma(r00, xc, fma(r01, yc, fma(r02, zc, hm)));
         const double uy = fma(r10, xc, fma(r11, yc, fma(r12, zc, hm)));
         const double uz = fma(r20, xc, fma(r21, yc, fma(r22, zc, hm)));
         const double fx0 = floor(ux), fy0 = floor(uy), fz0 = floor(uz);
         const int ix = (int)fx0, iy = (int)fy0, iz = (int)fz0;
-        if (ix < 0 || iy < 0 || iz < 0 || ix >= m || iy >= m || iz >= m) return 0.0f;
-        const uint32_t mk = cmask[brick_index(ix, iy, iz, mb)];
-        if (!mk) return 0.0f;
-        return trilinear_mask(mk, (float)(ux - fx0), (float)(uy - fy0), (float)(uz - fz0));
+        fx = (float)(ux - fx0);
+        fy = (float)(uy - fy0);
+        fz = (float)(uz - fz0);
+        if (ix < 0 || iy < 0 || iz < 0 || ix >= m || iy >= m || iz >= m) return -1;
+        return (long)brick_index(ix, iy, iz, mb);
+    }
+    __device__ __forceinline__ float sample(const uint8_t* __restrict__ cmask, int m, int mb, int x, int y, int z) const {
+        float fx, fy, fz;
+        const long a = locate(m, mb, x, y, z, fx, fy, fz);
+        if (a < 0) return 0.0f;
+        const uint32_t mk = cmask[a];
+        return mk ? trilinear_mask(mk, fx, fy, fz) : 0.0f;
     }
 };
+
+// Fill the LDS plane with z[j] = S_r[2j] + i S_r[2j+1] for plane z: the
+// corner-mask loads of G elements are issued together before any is used, so
+// each lane keeps 2G gathers in flight.
+template <int N>
+__device__ __forceinline__ void generate_plane(float2* plane, const RotSampler& rs, const uint8_t* __restrict__ cmask, int m,
+                                               int mb, int z) {
+    using C = Canvas<N>;
+    constexpr int TOT = N * C::N2;
+    constexpr int G = 4;
+    for (int e0 = threadIdx.x; e0 < TOT; e0 += C::NT * G) {
+        long addr[2 * G];
+        float fx[2 * G], fy[2 * G], fz[2 * G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int e = e0 + g * C::NT;
+            const int y = e / C::N2, j = e % C::N2;
+            if (e < TOT) {
+                addr[2 * g] = rs.locate(m, mb, 2 * j, y, z, fx[2 * g], fy[2 * g], fz[2 * g]);
+                addr[2 * g + 1] = rs.locate(m, mb, 2 * j + 1, y, z, fx[2 * g + 1], fy[2 * g + 1], fz[2 * g + 1]);
+            } else {
+                addr[2 * g] = addr[2 * g + 1] = -1;
+            }
+        }
+        uint32_t mk[2 * G];
+#pragma unroll
+        for (int q = 0; q < 2 * G; ++q) mk[q] = addr[q] >= 0 ? (uint32_t)cmask[addr[q]] : 0u;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int e = e0 + g * C::NT;
+            if (e < TOT) {
+                const int y = e / C::N2, j = e % C::N2;
+                const float a = mk[2 * g] ? trilinear_mask(mk[2 * g], fx[2 * g], fy[2 * g], fz[2 * g]) : 0.0f;
+                const float b = mk[2 * g + 1] ? trilinear_mask(mk[2 * g + 1], fx[2 * g + 1], fy[2 * g + 1], fz[2 * g + 1]) : 0.0f;
+                plane[y * C::P + j] = make_float2(a, b);
+            }
+        }
+    }
+}
 
 // ------------------------------------------------------------------ pass 1
 
@@ -312,18 +383,19 @@ __global__ __launch_bounds__(256) void k_rotvox_fwd_xy(const uint8_t* __restrict
     using C = Canvas<N>;
     __shared__ float2 plane[N * C::P];
     __shared__ float2 tw[N];
+    __shared__ double2 tws[N];
     __shared__ double2 rbuf[N * NLX];
     int rot, z;
     map_plane_block(blockIdx.x, count, N, rot, z);
-    for (int i = threadIdx.x; i < N; i += C::NT) tw[i] = twg[i];
+    for (int i = threadIdx.x; i < N; i += C::NT) {
+        tw[i] = twg[i];
+        tws[i] = tw64[i];
+    }
     RotSampler rs;
     rs.load(rots + rot * 9, m, N);
-    for (int e = threadIdx.x; e < N * C::N2; e += C::NT) {
-        const int y = e / C::N2, j = e % C::N2;
-        plane[y * C::P + j] = make_float2(rs.sample(cmask, m, mb, 2 * j, y, z), rs.sample(cmask, m, mb, 2 * j + 1, y, z));
-    }
+    generate_plane<N>(plane, rs, cmask, m, mb, z);
     __syncthreads();
-    plane_low_dft<N>(plane, tw64, rbuf, lowT + ((size_t)rot * N + z) * NLOW2);
+    plane_low_dft<N>(plane, tws, rbuf, lowT + ((size_t)rot * N + z) * NLOW2);
     plane_forward_and_store<N>(plane, tw, spec + (size_t)rot * C::H, z);
 }
 
@@ -335,16 +407,20 @@ __global__ __launch_bounds__(256) void k_grid_fwd_xy(const float* __restrict__ g
     using C = Canvas<N>;
     __shared__ float2 plane[N * C::P];
     __shared__ float2 tw[N];
+    __shared__ double2 tws[N];
     __shared__ double2 rbuf[N * NLX];
     const int z = blockIdx.x;
-    for (int i = threadIdx.x; i < N; i += C::NT) tw[i] = twg[i];
+    for (int i = threadIdx.x; i < N; i += C::NT) {
+        tw[i] = twg[i];
+        tws[i] = tw64[i];
+    }
     for (int e = threadIdx.x; e < N * C::N2; e += C::NT) {
         const int y = e / C::N2, j = e % C::N2;
         const float* row = grid + ((size_t)z * N + y) * N;
         plane[y * C::P + j] = make_float2(row[2 * j], row[2 * j + 1]);
     }
     __syncthreads();
-    plane_low_dft<N>(plane, tw64, rbuf, lowT + (size_t)z * NLOW2);
+    plane_low_dft<N>(plane, tws, rbuf, lowT + (size_t)z * NLOW2);
     plane_forward_and_store<N>(plane, tw, spec, z);
 }
 
@@ -389,26 +465,20 @@ __global__ __launch_bounds__(256) void k_zpass(float2* __restrict__ spec, const 
 // squares.  The float32 field only locates candidates; their scores are
 // recomputed exactly by k_rescore.
 
+// branch-free insertion of k into the descending list t0 >= t1 >= t2 >= t3
 __device__ __forceinline__ void top4_insert(unsigned long long k, unsigned long long& t0, unsigned long long& t1,
                                             unsigned long long& t2, unsigned long long& t3) {
-    if (k > t3) {
-        if (k > t2) {
-            t3 = t2;
-            if (k > t1) {
-                t2 = t1;
-                if (k > t0) {
-                    t1 = t0;
-                    t0 = k;
-                } else {
-                    t1 = k;
-                }
-            } else {
-                t2 = k;
-            }
-        } else {
-            t3 = k;
-        }
-    }
+    unsigned long long a;
+    a = t0 > k ? t0 : k;
+    k = t0 > k ? k : t0;
+    t0 = a;
+    a = t1 > k ? t1 : k;
+    k = t1 > k ? k : t1;
+    t1 = a;
+    a = t2 > k ? t2 : k;
+    k = t2 > k ? k : t2;
+    t2 = a;
+    t3 = t3 > k ? t3 : k;
 }
 
 // key = orderable bits of a double, low 22 bits replaced by ~flat (flat < 2^22)
@@ -435,23 +505,14 @@ __global__ __launch_bounds__(256) void k_inv_xy_argmax(const float2* __restrict_
     __shared__ float2 tw[N];
     __shared__ double2 btab[N * NLX];
     __shared__ double2 az[NLOW2];
+    __shared__ double2 tws[N];
     __shared__ unsigned long long wtop[NW][KTOP];
     __shared__ double wss[NW];
     int rot, z;
     map_plane_block(blockIdx.x, count, N, rot, z);
-    for (int i = threadIdx.x; i < N; i += C::NT) tw[i] = twg[i];
-    // low block of this plane: az[kx][ky] = sum_kz P[kx][ky][kz] e^{+2 pi i kz z / N}
-    {
-        const double2* P = Plow + (size_t)rot * NLOW3;
-        for (int o = threadIdx.x; o < NLOW2; o += C::NT) {
-            double2 acc = make_double2(0.0, 0.0);
-            for (int kzi = 0; kzi < NLY; ++kzi) {
-                const double2 t = dcmulc(P[o * NLY + kzi], tw64[mod_n((kzi - KLOW) * z, N)]);
-                acc.x += t.x;
-                acc.y += t.y;
-            }
-            az[o] = acc;
-        }
+    for (int i = threadIdx.x; i < N; i += C::NT) {
+        tw[i] = twg[i];
+        tws[i] = tw64[i];
     }
     const float2* spec_rot = spec + (size_t)rot * C::H;
     for (int e = threadIdx.x; e < N * C::N2; e += C::NT) {
@@ -462,58 +523,109 @@ __global__ __launch_bounds__(256) void k_inv_xy_argmax(const float2* __restrict_
     for (int ky = threadIdx.x; ky < N; ky += C::NT)
         plane[ky * C::P + C::N2] = nyq[((size_t)(ky / C::T) * N + z) * C::T + (ky % C::T)];
     __syncthreads();
+    // low block of this plane: az[kx][ky] = sum_kz P[kx][ky][kz] e^{+2 pi i kz z / N}
+    {
+        const double2* P = Plow + (size_t)rot * NLOW3;
+        for (int o = threadIdx.x; o < NLOW2; o += C::NT) {
+            double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int kzi = 0; kzi < NLY; ++kzi) {
+                const double2 t = dcmulc(P[o * NLY + kzi], tws[mod_n((kzi - KLOW) * z, N)]);
+                acc.x += t.x;
+                acc.y += t.y;
+            }
+            az[o] = acc;
+        }
+    }
+    // az is complete before the first barrier inside the y inverse FFT and is
+    // read only after it
+    fft_lds<N, true, C::P, C::NT, true, N>(plane, C::P, 1, tw);
     // btab[y][kx] = sum_ky az[kx][ky] e^{+2 pi i ky y / N}
     for (int t = threadIdx.x; t < N * NLX; t += C::NT) {
         const int y = t / NLX, kx = t % NLX;
         double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
         for (int kyi = 0; kyi < NLY; ++kyi) {
-            const double2 v = dcmulc(az[kx * NLY + kyi], tw64[mod_n((kyi - KLOW) * y, N)]);
+            const double2 v = dcmulc(az[kx * NLY + kyi], tws[mod_n((kyi - KLOW) * y, N)]);
             acc.x += v.x;
             acc.y += v.y;
         }
         btab[t] = acc;
     }
-    fft_lds<N, true, C::P, C::NT, true, N>(plane, C::P, 1, tw);
     c2r_pre<N>(plane, tw);
-    fft_lds<C::N2, true, N, C::NT, false, N>(plane, 1, C::P, tw);
+    fft_lds<C::N2, true, N, C::NT, true, N>(plane, 1, C::P, tw);
     unsigned long long t0 = 0, t1 = 0, t2 = 0, t3 = 0;
     float ss = 0.0f;
-    for (int e = threadIdx.x; e < N * C::N2; e += C::NT) {
-        const int y = e / C::N2, j = e % C::N2;
-        const float2 v = plane[y * C::P + j];
-        const uint32_t flat0 = (uint32_t)(((z * N) + y) * N + 2 * j);
-        // field of the low block at x = 2j, 2j+1: Re b0 + 2 sum_kx Re(b_kx e^{+2 pi i kx x / N})
-        const double2* b = btab + y * NLX;
-        double c0 = b[0].x, c1 = b[0].x;
+    if constexpr (C::NT % C::N2 == 0) {
+        // every lane keeps the same x = 2j, 2j+1: its low-block phases live in registers
+        const int j = threadIdx.x % C::N2;
+        double2 w0[NLX], w1[NLX];
 #pragma unroll
         for (int k = 1; k < NLX; ++k) {
-            const double2 bk = b[k];
-            const double2 w0 = tw64[(k * 2 * j) % N], w1 = tw64[(k * (2 * j + 1)) % N];
-            c0 = fma(2.0 * bk.x, w0.x, fma(2.0 * bk.y, w0.y, c0));
-            c1 = fma(2.0 * bk.x, w1.x, fma(2.0 * bk.y, w1.y, c1));
+            w0[k] = tws[(k * 2 * j) % N];
+            w1[k] = tws[(k * (2 * j + 1)) % N];
         }
-        const double v0 = (double)v.x + c0, v1 = (double)v.y + c1;
-        top4_insert(key64(v0, flat0), t0, t1, t2, t3);
-        top4_insert(key64(v1, flat0 + 1), t0, t1, t2, t3);
-        ss = fmaf(v.x, v.x, fmaf(v.y, v.y, ss));
-        if (corr_out) {
-            corr_out[flat0] = (float)v0;
-            corr_out[flat0 + 1] = (float)v1;
+        for (int y = threadIdx.x / C::N2; y < N; y += C::NT / C::N2) {
+            const float2 v = plane[y * C::P + j];
+            const uint32_t flat0 = (uint32_t)(((z * N) + y) * N + 2 * j);
+            const double2* b = btab + y * NLX;
+            double c0 = b[0].x, c1 = b[0].x;
+#pragma unroll
+            for (int k = 1; k < NLX; ++k) {
+                const double2 bk = b[k];
+                c0 = fma(2.0 * bk.x, w0[k].x, fma(2.0 * bk.y, w0[k].y, c0));
+                c1 = fma(2.0 * bk.x, w1[k].x, fma(2.0 * bk.y, w1[k].y, c1));
+            }
+            const double v0 = (double)v.x + c0, v1 = (double)v.y + c1;
+            top4_insert(key64(v0, flat0), t0, t1, t2, t3);
+            top4_insert(key64(v1, flat0 + 1), t0, t1, t2, t3);
+            ss = fmaf(v.x, v.x, fmaf(v.y, v.y, ss));
+            if (corr_out) {
+                corr_out[flat0] = (float)v0;
+                corr_out[flat0 + 1] = (float)v1;
+            }
+        }
+    } else {
+        for (int e = threadIdx.x; e < N * C::N2; e += C::NT) {
+            const int y = e / C::N2, j = e % C::N2;
+            const float2 v = plane[y * C::P + j];
+            const uint32_t flat0 = (uint32_t)(((z * N) + y) * N + 2 * j);
+            // field of the low block at x = 2j, 2j+1: Re b0 + 2 sum_kx Re(b_kx e^{+2 pi i kx x / N})
+            const double2* b = btab + y * NLX;
+            double c0 = b[0].x, c1 = b[0].x;
+#pragma unroll
+            for (int k = 1; k < NLX; ++k) {
+                const double2 bk = b[k];
+                const double2 w0 = tws[(k * 2 * j) % N], w1 = tws[(k * (2 * j + 1)) % N];
+                c0 = fma(2.0 * bk.x, w0.x, fma(2.0 * bk.y, w0.y, c0));
+                c1 = fma(2.0 * bk.x, w1.x, fma(2.0 * bk.y, w1.y, c1));
+            }
+            const double v0 = (double)v.x + c0, v1 = (double)v.y + c1;
+            top4_insert(key64(v0, flat0), t0, t1, t2, t3);
+            top4_insert(key64(v1, flat0 + 1), t0, t1, t2, t3);
+            ss = fmaf(v.x, v.x, fmaf(v.y, v.y, ss));
+            if (corr_out) {
+                corr_out[flat0] = (float)v0;
+                corr_out[flat0 + 1] = (float)v1;
+            }
         }
     }
-    // wave: merge the 64 sorted lists by four rounds of a wave maximum
-    int ptr = 0;
+    // wave: merge the 64 sorted lists by four rounds of a wave maximum; the
+    // lane holding the maximum (keys are unique) shifts its list up
     unsigned long long wt[KTOP];
 #pragma unroll
     for (int r = 0; r < KTOP; ++r) {
-        const unsigned long long head = ptr == 0 ? t0 : ptr == 1 ? t1 : ptr == 2 ? t2 : ptr == 3 ? t3 : 0ull;
-        unsigned long long mx = head;
+        unsigned long long mx = t0;
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
             const unsigned long long o = __shfl_xor(mx, off, 64);
             mx = o > mx ? o : mx;
         }
-        if (head == mx && mx != 0ull) ++ptr;  // keys are unique: one lane advances
+        const bool mine = t0 == mx && mx != 0ull;
+        t0 = mine ? t1 : t0;
+        t1 = mine ? t2 : t1;
+        t2 = mine ? t3 : t2;
+        t3 = mine ? 0ull : t3;
         wt[r] = mx;
     }
     double ds = (double)ss;
@@ -542,21 +654,23 @@ __global__ __launch_bounds__(256) void k_inv_xy_argmax(const float2* __restrict_
     }
 }
 
-// Per rotation: the float32 maximum v and the field's RMS E (from the plane sums
-// of squares); every key with value >= v - 2 eps becomes a candidate, where
-// eps = REGK_EPS_SCALE * 2^-24 * E * log2(n^3) bounds the float32 error of the
-// FFT path.  If a plane's fourth key is still inside the window the plane may
-// hold more candidates than were kept: the rotation is counted as overflowed.
+// Per rotation (absolute index base + block): the field maximum v (double,
+// from the keys), the RMS of the float32 part (from the plane sums of squares),
+// the window 2 eps with eps = REGK_EPS_SCALE * 2^-24 * rms * log2(n^3) bounding
+// the float32 error, and every key inside [v - 2 eps, v] as a candidate (at
+// most CMAX, in descending key order).  If a plane's fourth key is still inside
+// the window the plane may hold more: the rotation is marked as overflowed.
 __global__ __launch_bounds__(256) void k_select(const unsigned long long* __restrict__ ptop, const double* __restrict__ pssq,
-                                                int n, double eps_per_rms, int32_t* __restrict__ cand_idx,
-                                                int32_t* __restrict__ cand_n, int* __restrict__ stats,
-                                                double* __restrict__ window, uint8_t* __restrict__ ovf) {
+                                                int n, double eps_per_rms, int base, int32_t* __restrict__ cand_idx,
+                                                int32_t* __restrict__ cand_n, double* __restrict__ window,
+                                                uint8_t* __restrict__ ovf, double* __restrict__ best_val,
+                                                int32_t* __restrict__ best_flat, int* __restrict__ stats) {
     __shared__ unsigned long long red[4];
     __shared__ double thr_s;
     __shared__ int cnt;
     __shared__ unsigned long long list[CMAX];
     __shared__ int overflow;
-    const int rot = blockIdx.x;
+    const int rot = blockIdx.x, r = base + blockIdx.x;
     const unsigned long long* T = ptop + (size_t)rot * n * KTOP;
     unsigned long long mx = 0;
     for (int zz = threadIdx.x; zz < n; zz += 256) mx = T[zz * KTOP] > mx ? T[zz * KTOP] : mx;
@@ -577,8 +691,11 @@ __global__ __launch_bounds__(256) void k_select(const unsigned long long* __rest
         double ssq = 0.0;
         for (int zz = 0; zz < n; ++zz) ssq += pssq[(size_t)rot * n + zz];
         const double rms = sqrt(ssq / ((double)n * n * n));
-        thr_s = key_value(b) - 2.0 * eps_per_rms * rms;
-        window[rot] = 2.0 * eps_per_rms * rms;
+        const double v = key_value(b);
+        thr_s = v - 2.0 * eps_per_rms * rms;
+        window[r] = 2.0 * eps_per_rms * rms;
+        best_val[r] = v;
+        best_flat[r] = (int32_t)key_flat(b);
     }
     __syncthreads();
     const double thr = thr_s;
@@ -598,43 +715,96 @@ __global__ __launch_bounds__(256) void k_select(const unsigned long long* __rest
             c = CMAX;
         }
         // descending key order (insertion sort of at most CMAX keys)
-        for (int a = 1; a < c; ++a) {
-            const unsigned long long k = list[a];
-            int b = a - 1;
+        for (int q = 1; q < c; ++q) {
+            const unsigned long long k = list[q];
+            int b = q - 1;
             while (b >= 0 && list[b] < k) {
                 list[b + 1] = list[b];
                 --b;
             }
             list[b + 1] = k;
         }
-        for (int a = 0; a < c; ++a) cand_idx[(size_t)rot * CMAX + a] = (int32_t)key_flat(list[a]);
-        cand_n[rot] = c;
-        ovf[rot] = overflow ? 1 : 0;
+        for (int q = 0; q < c; ++q) cand_idx[(size_t)r * CMAX + q] = (int32_t)key_flat(list[q]);
+        cand_n[r] = c;
+        ovf[r] = overflow ? 1 : 0;
         atomicAdd(stats + 0, 1);
         atomicAdd(stats + 1, c);
         if (overflow) atomicAdd(stats + 2, 1);
     }
 }
 
+// Which rotations need exact re-scoring.  tol = 1e-4 * max |v| over the call's
+// rotations.  A rotation whose window 2 eps is within tol is settled by the
+// field maximum (value within eps, index within 2 eps <= tol of the best); the
+// others (or all, when asked) are listed, in rotation order, for k_rescore.
+// Listed rotations whose window also overflowed are counted as uncertain.
+__global__ __launch_bounds__(1024) void k_certify(const double* __restrict__ best_val, const double* __restrict__ window,
+                                                  const uint8_t* __restrict__ ovf, int count, int always,
+                                                  int32_t* __restrict__ need_list, int* __restrict__ need_count,
+                                                  int* __restrict__ stats) {
+    __shared__ double red[16];
+    __shared__ int part[1024];
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < count; i += 1024) mx = fmax(mx, fabs(best_val[i]));
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = red[0];
+        for (int w = 1; w < 16; ++w) b = fmax(b, red[w]);
+        red[0] = b;
+    }
+    __syncthreads();
+    const double tol = 1e-4 * red[0];
+    // contiguous chunk per thread, exclusive scan of the chunk counts
+    const int per = (count + 1023) / 1024;
+    const int i0 = threadIdx.x * per, i1 = min(count, i0 + per);
+    int c = 0, bad = 0;
+    for (int i = i0; i < i1; ++i) {
+        const bool wide = window[i] > tol;
+        c += (always || wide) ? 1 : 0;
+        bad += (wide && ovf[i]) ? 1 : 0;
+    }
+    part[threadIdx.x] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int t = 0; t < 1024; ++t) {
+            const int v = part[t];
+            part[t] = run;
+            run += v;
+        }
+        *need_count = run;
+        atomicAdd(stats + 4, run);
+    }
+    __syncthreads();
+    int pos = part[threadIdx.x];
+    for (int i = i0; i < i1; ++i)
+        if (always || window[i] > tol) need_list[pos++] = i;
+    if (bad) atomicAdd(stats + 3, bad);
+}
+
 // Exact score of one candidate shift d of one rotation:
 //   sum over the nonzero voxels k of O of O[k] * S_r[(k + d) mod n]
 // with S_r resampled exactly as in pass 1 and the sum accumulated in double.
 // The nonzero list is cut into `nslice` slices; a grid-stride loop runs over
-// (rotation, candidate, slice) items, skipping empty candidate slots, and each
-// item writes its slice sum; k_finalize adds the slices in a fixed order.
+// (listed rotation, candidate, slice) items, skipping empty candidate slots,
+// and each item writes its slice sum; k_apply adds the slices in a fixed order.
 __global__ __launch_bounds__(256) void k_rescore(const uint32_t* __restrict__ nz_idx, const float* __restrict__ nz_val,
                                                  const int* __restrict__ nz_count, int n, int nslice,
                                                  const uint8_t* __restrict__ cmask, int m, int mb,
-                                                 const double* __restrict__ rots, int count,
-                                                 const int32_t* __restrict__ cand_idx, const int32_t* __restrict__ cand_n,
-                                                 double* __restrict__ cand_part) {
+                                                 const double* __restrict__ rots, const int32_t* __restrict__ need_list,
+                                                 const int* __restrict__ need_count, const int32_t* __restrict__ cand_idx,
+                                                 const int32_t* __restrict__ cand_n, double* __restrict__ cand_part) {
     __shared__ double red[4];
     const int nnz = *nz_count;
     const int per = (nnz + nslice - 1) / nslice;
-    const int items = count * CMAX * nslice;
+    const int items = (*need_count) * CMAX * nslice;
     for (int it = blockIdx.x; it < items; it += gridDim.x) {
-        const int sl = it % nslice, rc = it / nslice;
-        const int rot = rc / CMAX, c = rc % CMAX;
+        const int sl = it % nslice, pc = it / nslice;
+        const int pos = pc / CMAX, c = pc % CMAX;
+        const int rot = need_list[pos];
         if (c >= cand_n[rot]) continue;  // uniform across the workgroup
         const uint32_t flat = (uint32_t)cand_idx[(size_t)rot * CMAX + c];
         const int dx = (int)(flat % n), dy = (int)((flat / n) % n), dz = (int)(flat / ((uint32_t)n * n));
@@ -655,7 +825,7 @@ __global__ __launch_bounds__(256) void k_rescore(const uint32_t* __restrict__ nz
         for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
         __syncthreads();
-        if (threadIdx.x == 0) cand_part[(size_t)rc * nslice + sl] = ((red[0] + red[1]) + red[2]) + red[3];
+        if (threadIdx.x == 0) cand_part[(size_t)pc * nslice + sl] = ((red[0] + red[1]) + red[2]) + red[3];
         __syncthreads();
     }
 }
@@ -706,31 +876,15 @@ __global__ __launch_bounds__(256) void k_low_combine(const double2* __restrict__
 }
 
 // ------------------------------------------------------------- finalize
-// best candidate by exact score (ties: lowest flat index) -> score, shift, pose
+// score, signed shift and FP64 pose of a peak: t = wc - R a + h R shift
 
-__global__ void k_finalize(const int32_t* __restrict__ cand_idx, const int32_t* __restrict__ cand_n,
-                           const double* __restrict__ cand_part, int nslice, int count, const float* __restrict__ quats, int n,
-                           double h, const double* __restrict__ anchor, double wc0, double wc1, double wc2,
-                           float* __restrict__ out_score, int32_t* __restrict__ out_shift, double* __restrict__ out_pose) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    const int cn = cand_n[i];
-    double best = -1.0e308;
-    uint32_t flat = 0xffffffffu;
-    for (int c = 0; c < cn; ++c) {
-        const double* part = cand_part + ((size_t)i * CMAX + c) * nslice;
-        double v = 0.0;
-        for (int sl = 0; sl < nslice; ++sl) v += part[sl];
-        const uint32_t f = (uint32_t)cand_idx[(size_t)i * CMAX + c];
-        if (v > best || (v == best && f < flat)) {
-            best = v;
-            flat = f;
-        }
-    }
+__device__ __forceinline__ void write_peak(int i, double score, uint32_t flat, const float* __restrict__ quats, int n, double h,
+                                           const double* __restrict__ anchor, const double* wc, float* __restrict__ out_score,
+                                           int32_t* __restrict__ out_shift, double* __restrict__ out_pose) {
     int d[3] = {(int)(flat % n), (int)((flat / n) % n), (int)(flat / ((uint32_t)n * n))};
     for (int a = 0; a < 3; ++a)
         if (d[a] >= n / 2) d[a] -= n;
-    if (out_score) out_score[i] = (float)best;
+    if (out_score) out_score[i] = (float)score;
     if (out_shift) {
         out_shift[3 * i] = d[0];
         out_shift[3 * i + 1] = d[1];
@@ -744,7 +898,6 @@ __global__ void k_finalize(const int32_t* __restrict__ cand_idx, const int32_t* 
         const double Rm[9] = {1 - 2 * (y * y + zq * zq), 2 * (x * y - w * zq), 2 * (x * zq + w * y),
                               2 * (x * y + w * zq), 1 - 2 * (x * x + zq * zq), 2 * (y * zq - w * x),
                               2 * (x * zq - w * y), 2 * (y * zq + w * x), 1 - 2 * (x * x + y * y)};
-        const double wc[3] = {wc0, wc1, wc2};
         double* o = out_pose + 7 * i;
         for (int a = 0; a < 4; ++a) o[a] = q[a];
         for (int r = 0; r < 3; ++r) {
@@ -755,6 +908,45 @@ __global__ void k_finalize(const int32_t* __restrict__ cand_idx, const int32_t* 
             }
             o[4 + r] = wc[r] - ra + h * rd;
         }
+    }
+}
+
+// field maxima of a call's rotations -> outputs (arrays offset to the call)
+__global__ void k_finalize(const double* __restrict__ best_val, const int32_t* __restrict__ best_flat, int count,
+                           const float* __restrict__ quats, int n, double h, const double* __restrict__ anchor, double wc0,
+                           double wc1, double wc2, float* __restrict__ out_score, int32_t* __restrict__ out_shift,
+                           double* __restrict__ out_pose) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const double wc[3] = {wc0, wc1, wc2};
+    write_peak(i, best_val[i], (uint32_t)best_flat[i], quats, n, h, anchor, wc, out_score, out_shift, out_pose);
+}
+
+// re-scored rotations: the best exact candidate (ties: lowest flat index)
+// replaces the field maximum
+__global__ void k_apply(const int32_t* __restrict__ need_list, const int* __restrict__ need_count,
+                        const int32_t* __restrict__ cand_idx, const int32_t* __restrict__ cand_n,
+                        const double* __restrict__ cand_part, int nslice, const float* __restrict__ quats, int n, double h,
+                        const double* __restrict__ anchor, double wc0, double wc1, double wc2, float* __restrict__ out_score,
+                        int32_t* __restrict__ out_shift, double* __restrict__ out_pose) {
+    const int nc = *need_count;
+    const double wc[3] = {wc0, wc1, wc2};
+    for (int pos = blockIdx.x * blockDim.x + threadIdx.x; pos < nc; pos += gridDim.x * blockDim.x) {
+        const int i = need_list[pos];
+        const int cn = cand_n[i];
+        double best = -1.0e308;
+        uint32_t flat = 0xffffffffu;
+        for (int c = 0; c < cn; ++c) {
+            const double* part = cand_part + ((size_t)pos * CMAX + c) * nslice;
+            double v = 0.0;
+            for (int sl = 0; sl < nslice; ++sl) v += part[sl];
+            const uint32_t f = (uint32_t)cand_idx[(size_t)i * CMAX + c];
+            if (v > best || (v == best && f < flat)) {
+                best = v;
+                flat = f;
+            }
+        }
+        if (cn > 0) write_peak(i, best, flat, quats, n, h, anchor, wc, out_score, out_shift, out_pose);
     }
 }
 
@@ -1280,23 +1472,27 @@ int rescore_slices(int n) {
     return (int)((n3 + 65535) / 65536);
 }
 
-hipError_t candidates_batch(int n, const SearchBatchArgs& a) {
+hipError_t select_batch(int n, const SearchBatchArgs& a, int base, const PeakArrays& pk) {
     const double eps_per_rms = REGK_EPS_SCALE * std::ldexp(1.0, -24) * std::log2((double)n * n * n);
-    hipLaunchKernelGGL(k_select, dim3(a.count), dim3(256), 0, a.stream, a.ptop, a.pssq, n, eps_per_rms, a.cand_idx,
-                       a.cand_n, a.stats, a.window, a.ovf);
-    const int nslice = rescore_slices(n);
-    const int items = a.count * CMAX * nslice;
-    const int grid = items < 4096 ? items : 4096;
-    hipLaunchKernelGGL(k_rescore, dim3(grid), dim3(256), 0, a.stream, a.nz_idx, a.nz_val, a.nz_count, n, nslice, a.cmask, a.m,
-                       a.mp / 4, a.rots, a.count, a.cand_idx, a.cand_n, a.cand_part);
+    hipLaunchKernelGGL(k_select, dim3(a.count), dim3(256), 0, a.stream, a.ptop, a.pssq, n, eps_per_rms, base, pk.cand_idx,
+                       pk.cand_n, pk.window, pk.ovf, pk.best_val, pk.best_flat, pk.stats);
     return hipGetLastError();
 }
 
-hipError_t finalize_batch(const SearchBatchArgs& a, int n, const float* quats, double h, const double* anchor,
-                          const double* wc, float* out_score, int32_t* out_shift, double* out_pose) {
-    hipLaunchKernelGGL(k_finalize, dim3((a.count + 127) / 128), dim3(128), 0, a.stream, a.cand_idx, a.cand_n, a.cand_part,
-                       rescore_slices(n),
-                       a.count, quats, n, h, anchor, wc[0], wc[1], wc[2], out_score, out_shift, out_pose);
+hipError_t finish_call(int n, int first, int count, int always, const PeakArrays& pk, const RescoreInputs& ri,
+                       const float* quats, double h, const double* anchor, const double* wc, float* out_score,
+                       int32_t* out_shift, double* out_pose, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3((count + 127) / 128), dim3(128), 0, s, pk.best_val + first, pk.best_flat + first,
+                       count, quats, n, h, anchor, wc[0], wc[1], wc[2], out_score, out_shift, out_pose);
+    hipLaunchKernelGGL(k_certify, dim3(1), dim3(1024), 0, s, pk.best_val + first, pk.window + first, pk.ovf + first, count,
+                       always, pk.need_list, pk.need_count, pk.stats);
+    const int nslice = rescore_slices(n);
+    hipLaunchKernelGGL(k_rescore, dim3(2048), dim3(256), 0, s, ri.nz_idx, ri.nz_val, ri.nz_count, n, nslice, ri.cmask, ri.m,
+                       ri.mp / 4, ri.rots + 9 * (size_t)first, pk.need_list, pk.need_count, pk.cand_idx + (size_t)first * CMAX,
+                       pk.cand_n + first, pk.cand_part);
+    hipLaunchKernelGGL(k_apply, dim3(16), dim3(256), 0, s, pk.need_list, pk.need_count, pk.cand_idx + (size_t)first * CMAX,
+                       pk.cand_n + first, pk.cand_part, nslice, quats, n, h, anchor, wc[0], wc[1], wc[2], out_score,
+                       out_shift, out_pose);
     return hipGetLastError();
 }
 
@@ -1353,38 +1549,3 @@ hipError_t top_k(const float* scores, int count, int K, int32_t* out, hipStream_
 
 }  // namespace regdock
 
-namespace regdock {
-
-// A rotation whose candidate window overflowed reports the best kept
-// candidate, whose exact score is within the window 2 eps of the rotation's
-// maximum.  That meets the 1e-4-of-the-best-score bar when 2 eps <= 1e-4 max|score|
-// over the scored rotations; rotations where it does not are counted as
-// uncertain (stats[3]).
-__global__ __launch_bounds__(1024) void k_certify(const float* __restrict__ scores, int count,
-                                                  const double* __restrict__ window, const uint8_t* __restrict__ ovf,
-                                                  int* __restrict__ stats) {
-    __shared__ float red[16];
-    float mx = 0.0f;
-    for (int i = threadIdx.x; i < count; i += 1024) mx = fmaxf(mx, fabsf(scores[i]));
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        float b = red[0];
-        for (int w = 1; w < 16; ++w) b = fmaxf(b, red[w]);
-        red[0] = b;
-    }
-    __syncthreads();
-    const double tol = 1e-4 * (double)red[0];
-    int bad = 0;
-    for (int i = threadIdx.x; i < count; i += 1024) bad += (ovf[i] && window[i] > tol) ? 1 : 0;
-    if (bad) atomicAdd(stats + 3, bad);
-}
-
-hipError_t certify(const float* scores, int count, const double* window, const uint8_t* ovf, int* stats, hipStream_t s) {
-    hipLaunchKernelGGL(k_certify, dim3(1), dim3(1024), 0, s, scores, count, window, ovf, stats);
-    return hipGetLastError();
-}
-
-}  // namespace regdock

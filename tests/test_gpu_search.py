@@ -99,15 +99,17 @@ def test_object_grid_and_swept_match_oracle(cfg, over):
 
 # ------------------------------------------- per-rotation path, grids injected
 
-@pytest.mark.parametrize("n,h,M,batch", [(32, 0.4, 64, 0), (48, 0.3, 13, 8), (60, 0.25, 11, 0), (64, 0.25, 16, 8),
-                                         (80, 0.2, 9, 0), (16, 0.8, 10, 8)])
-def test_correlation_field_matches_oracle(n, h, M, batch):
+@pytest.mark.parametrize("n,h,M,batch,rescore", [(32, 0.4, 64, 0, 0), (32, 0.4, 64, 0, 1), (48, 0.3, 13, 8, 1),
+                                                 (60, 0.25, 11, 0, 0), (64, 0.25, 16, 8, 1), (80, 0.2, 9, 0, 0),
+                                                 (16, 0.8, 10, 8, 1)])
+def test_correlation_field_matches_oracle(n, h, M, batch, rescore):
     """Element-wise correlation field and peak of every rotation, with the
-    oracle's O and S_w injected (several tiles, ragged batches)."""
+    oracle's O and S_w injected (several tiles, ragged batches); rescore=1
+    re-scores every rotation's candidates exactly."""
     rd = _lib()
     p = _problem(1, 1, n=n, h=h, M=max(16, 1 << (M - 1).bit_length()))
     p.so3 = p.so3[:M]
-    handle = _handle(rd, p, params=dict(batch=batch))
+    handle = _handle(rd, p, params=dict(batch=batch, rescore=rescore))
     O, fo, mf = _oracle_grids(p)
     Sw = S.swept_occupancy(mf)
     rd.register_set_grids(handle, O.astype(np.float32), Sw.astype(np.uint8))
@@ -118,6 +120,9 @@ def test_correlation_field_matches_oracle(n, h, M, batch):
     ref = np.array([f.max() for f in fields])
     tol = TOL_REL * np.abs(ref).max()
     _check_scores(sc, _flat_from_shift(sh, n), ref, fields, tol)
+    if rescore:
+        # exact sums over float32 trilinear samples: far inside the tolerance
+        assert np.abs(sc - ref).max() <= 1e-6 * np.abs(ref).max() + 1e-6
     # the float32 field of two rotations, element by element, inside the error
     # bound that sizes the library's candidate window
     for r in (0, M - 1):
@@ -198,10 +203,10 @@ def test_determinism_run_to_run():
 
 # ------------------------------------------------------------- full size
 
-def _sampled_full_size(cfg, n_samples):
+def _sampled_full_size(cfg, n_samples, rescore=0):
     rd = _lib()
     p = _problem(cfg, 0)
-    handle = _handle(rd, p)
+    handle = _handle(rd, p, params=dict(rescore=rescore))
     sc, sh, _ = [t.cpu().numpy() if t is not None else None for t in rd.score_rotations(handle)]
     O, fo, mf = _oracle_grids(p)
     Sw = S.swept_occupancy(mf)
@@ -235,6 +240,10 @@ def _sampled_full_size(cfg, n_samples):
 
 def test_config2_full_size_sampled():
     _sampled_full_size(2, 6)
+
+
+def test_config2_full_size_sampled_exact_rescore():
+    _sampled_full_size(2, 4, rescore=1)
 
 
 def test_config3_full_size_sampled():
