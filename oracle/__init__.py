@@ -12,3 +12,4 @@ the two share no code (the seeded input generators in `synth` feed both).
 """
 from . import search  # noqa: F401
 from .search import GridParams  # noqa: F401
+from . import refine  # noqa: F401

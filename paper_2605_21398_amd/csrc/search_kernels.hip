@@ -334,40 +334,104 @@ struct RotSampler {
     }
 };
 
-// Fill the LDS plane with z[j] = S_r[2j] + i S_r[2j+1] for plane z: the
-// corner-mask loads of G elements are issued together before any is used, so
-// each lane keeps 2G gathers in flight.
+// Fill the LDS plane with z[j] = S_r[2j] + i S_r[2j+1] for plane z.  The
+// corner-mask loads of several elements are issued together before any is
+// used, so each lane keeps many gathers in flight.
+//
+// When every lane owns fixed columns x = 2j, 2j+1 (n/2 divides the workgroup)
+// its lattice coordinates advance by a constant step per row: they are kept in
+// 64-bit fixed point with 32 fractional bits (the integer cell is the high
+// word, the trilinear fraction the low word), so a sample costs three integer
+// additions instead of a double-precision matrix product.  The start and the
+// step are rounded from double once: after n rows the drift is below 1e-8 voxel.
 template <int N>
 __device__ __forceinline__ void generate_plane(float2* plane, const RotSampler& rs, const uint8_t* __restrict__ cmask, int m,
                                                int mb, int z) {
     using C = Canvas<N>;
     constexpr int TOT = N * C::N2;
-    constexpr int G = 4;
-    for (int e0 = threadIdx.x; e0 < TOT; e0 += C::NT * G) {
-        long addr[2 * G];
-        float fx[2 * G], fy[2 * G], fz[2 * G];
+    if constexpr (C::NT % C::N2 == 0) {
+        constexpr int YS = C::NT / C::N2;  // row step of a lane
+        constexpr int G = 4;               // rows per batch of loads
+        const int j = threadIdx.x % C::N2, y0 = threadIdx.x / C::N2;
+        if (y0 >= N) return;
+        const double two32 = 4294967296.0;
+        long long U[2][3], D[3];
+        {
+            const double yc = (double)y0 - rs.hn, zc = (double)z - rs.hn;
+            for (int s2 = 0; s2 < 2; ++s2) {
+                const double xc = (double)(2 * j + s2) - rs.hn;
+                U[s2][0] = __double2ll_rn(fma(rs.r00, xc, fma(rs.r01, yc, fma(rs.r02, zc, rs.hm))) * two32);
+                U[s2][1] = __double2ll_rn(fma(rs.r10, xc, fma(rs.r11, yc, fma(rs.r12, zc, rs.hm))) * two32);
+                U[s2][2] = __double2ll_rn(fma(rs.r20, xc, fma(rs.r21, yc, fma(rs.r22, zc, rs.hm))) * two32);
+            }
+            D[0] = __double2ll_rn((double)YS * rs.r01 * two32);
+            D[1] = __double2ll_rn((double)YS * rs.r11 * two32);
+            D[2] = __double2ll_rn((double)YS * rs.r21 * two32);
+        }
+        const float inv32 = 2.3283064365386963e-10f;  // 2^-32
+        for (int y = y0; y < N; y += YS * G) {
+            int addr[2 * G];
+            float fx[2 * G], fy[2 * G], fz[2 * G];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int e = e0 + g * C::NT;
-            const int y = e / C::N2, j = e % C::N2;
-            if (e < TOT) {
-                addr[2 * g] = rs.locate(m, mb, 2 * j, y, z, fx[2 * g], fy[2 * g], fz[2 * g]);
-                addr[2 * g + 1] = rs.locate(m, mb, 2 * j + 1, y, z, fx[2 * g + 1], fy[2 * g + 1], fz[2 * g + 1]);
-            } else {
-                addr[2 * g] = addr[2 * g + 1] = -1;
+            for (int g = 0; g < G; ++g) {
+#pragma unroll
+                for (int s2 = 0; s2 < 2; ++s2) {
+                    const int q = 2 * g + s2;
+                    const int ix = (int)(U[s2][0] >> 32), iy = (int)(U[s2][1] >> 32), iz = (int)(U[s2][2] >> 32);
+                    fx[q] = (float)(uint32_t)U[s2][0] * inv32;
+                    fy[q] = (float)(uint32_t)U[s2][1] * inv32;
+                    fz[q] = (float)(uint32_t)U[s2][2] * inv32;
+                    const bool in = (unsigned)ix < (unsigned)m && (unsigned)iy < (unsigned)m && (unsigned)iz < (unsigned)m &&
+                                    y + g * YS < N;
+                    addr[q] = in ? (int)brick_index(ix, iy, iz, mb) : -1;
+                    U[s2][0] += D[0];
+                    U[s2][1] += D[1];
+                    U[s2][2] += D[2];
+                }
+            }
+            uint32_t mk[2 * G];
+#pragma unroll
+            for (int q = 0; q < 2 * G; ++q) mk[q] = addr[q] >= 0 ? (uint32_t)cmask[addr[q]] : 0u;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int yy = y + g * YS;
+                if (yy < N) {
+                    const float a = mk[2 * g] ? trilinear_mask(mk[2 * g], fx[2 * g], fy[2 * g], fz[2 * g]) : 0.0f;
+                    const float b =
+                        mk[2 * g + 1] ? trilinear_mask(mk[2 * g + 1], fx[2 * g + 1], fy[2 * g + 1], fz[2 * g + 1]) : 0.0f;
+                    plane[yy * C::P + j] = make_float2(a, b);
+                }
             }
         }
-        uint32_t mk[2 * G];
+    } else {
+        constexpr int G = 4;
+        for (int e0 = threadIdx.x; e0 < TOT; e0 += C::NT * G) {
+            long addr[2 * G];
+            float fx[2 * G], fy[2 * G], fz[2 * G];
 #pragma unroll
-        for (int q = 0; q < 2 * G; ++q) mk[q] = addr[q] >= 0 ? (uint32_t)cmask[addr[q]] : 0u;
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int e = e0 + g * C::NT;
-            if (e < TOT) {
+            for (int g = 0; g < G; ++g) {
+                const int e = e0 + g * C::NT;
                 const int y = e / C::N2, j = e % C::N2;
-                const float a = mk[2 * g] ? trilinear_mask(mk[2 * g], fx[2 * g], fy[2 * g], fz[2 * g]) : 0.0f;
-                const float b = mk[2 * g + 1] ? trilinear_mask(mk[2 * g + 1], fx[2 * g + 1], fy[2 * g + 1], fz[2 * g + 1]) : 0.0f;
-                plane[y * C::P + j] = make_float2(a, b);
+                if (e < TOT) {
+                    addr[2 * g] = rs.locate(m, mb, 2 * j, y, z, fx[2 * g], fy[2 * g], fz[2 * g]);
+                    addr[2 * g + 1] = rs.locate(m, mb, 2 * j + 1, y, z, fx[2 * g + 1], fy[2 * g + 1], fz[2 * g + 1]);
+                } else {
+                    addr[2 * g] = addr[2 * g + 1] = -1;
+                }
+            }
+            uint32_t mk[2 * G];
+#pragma unroll
+            for (int q = 0; q < 2 * G; ++q) mk[q] = addr[q] >= 0 ? (uint32_t)cmask[addr[q]] : 0u;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int e = e0 + g * C::NT;
+                if (e < TOT) {
+                    const int y = e / C::N2, j = e % C::N2;
+                    const float a = mk[2 * g] ? trilinear_mask(mk[2 * g], fx[2 * g], fy[2 * g], fz[2 * g]) : 0.0f;
+                    const float b =
+                        mk[2 * g + 1] ? trilinear_mask(mk[2 * g + 1], fx[2 * g + 1], fy[2 * g + 1], fz[2 * g + 1]) : 0.0f;
+                    plane[y * C::P + j] = make_float2(a, b);
+                }
             }
         }
     }
@@ -577,8 +641,9 @@ __global__ __launch_bounds__(256) void k_inv_xy_argmax(const float2* __restrict_
                 c1 = fma(2.0 * bk.x, w1[k].x, fma(2.0 * bk.y, w1[k].y, c1));
             }
             const double v0 = (double)v.x + c0, v1 = (double)v.y + c1;
-            top4_insert(key64(v0, flat0), t0, t1, t2, t3);
-            top4_insert(key64(v1, flat0 + 1), t0, t1, t2, t3);
+            const unsigned long long k0 = key64(v0, flat0), k1 = key64(v1, flat0 + 1);
+            if (k0 > t3) top4_insert(k0, t0, t1, t2, t3);
+            if (k1 > t3) top4_insert(k1, t0, t1, t2, t3);
             ss = fmaf(v.x, v.x, fmaf(v.y, v.y, ss));
             if (corr_out) {
                 corr_out[flat0] = (float)v0;
@@ -601,8 +666,9 @@ __global__ __launch_bounds__(256) void k_inv_xy_argmax(const float2* __restrict_
                 c1 = fma(2.0 * bk.x, w1.x, fma(2.0 * bk.y, w1.y, c1));
             }
             const double v0 = (double)v.x + c0, v1 = (double)v.y + c1;
-            top4_insert(key64(v0, flat0), t0, t1, t2, t3);
-            top4_insert(key64(v1, flat0 + 1), t0, t1, t2, t3);
+            const unsigned long long k0 = key64(v0, flat0), k1 = key64(v1, flat0 + 1);
+            if (k0 > t3) top4_insert(k0, t0, t1, t2, t3);
+            if (k1 > t3) top4_insert(k1, t0, t1, t2, t3);
             ss = fmaf(v.x, v.x, fmaf(v.y, v.y, ss));
             if (corr_out) {
                 corr_out[flat0] = (float)v0;
