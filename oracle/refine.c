@@ -47,6 +47,57 @@ static void probe_grad(const double *u, double r, double L, double *g)
     g[0] = a * e1[0] / n; g[1] = a * e1[1] / n; g[2] = b * sz / n;
 }
 
+/* Sensitivity direction at the witness u = p0 + s (p1 - p0) + t (p2 - p0).
+ * Where f_p is differentiable it is grad f_p.  Inside the probe, on the ridge
+ * where the side wall and an end cap are equally near (q1 = q2 within
+ * RIDGE_TOL), the face minimum is a min-max of the two branches and its
+ * derivative is g = a grad q1 + (1 - a) grad q2, with a in [0, 1] chosen so
+ * that g has no component along the directions in which the witness can move
+ * (the face plane for an interior witness, the edge for an edge witness).  At a
+ * vertex witness, or when those directions do not fix a, the one-sided
+ * gradient is kept. */
+#define RIDGE_TOL 1e-4
+#define EDGE_TOL 1e-9
+static void witness_gradient(const double *u, const double *p0, const double *p1, const double *p2, double s,
+                             double t, double r, double L, double *g)
+{
+    double rho = sqrt(u[0] * u[0] + u[1] * u[1]);
+    double q1 = rho - r, q2 = fabs(u[2] - 0.5 * L) - 0.5 * L;
+    probe_grad(u, r, L, g);
+    if (!(q1 <= 0 && q2 <= 0 && fabs(q1 - q2) <= RIDGE_TOL && rho > 0)) return;
+    int on_s = s <= EDGE_TOL, on_t = t <= EDGE_TOL, on_st = 1.0 - s - t <= EDGE_TOL;
+    int active = on_s + on_t + on_st;
+    if (active >= 2) return;
+    double g1[3] = {u[0] / rho, u[1] / rho, 0.0};
+    double g2[3] = {0.0, 0.0, u[2] >= 0.5 * L ? 1.0 : -1.0};
+    double db[3] = {g1[0] - g2[0], g1[1] - g2[1], g1[2] - g2[2]};
+    double e1[3], e2[3], a[3], b[3];
+    for (int k = 0; k < 3; k++) { e1[k] = p1[k] - p0[k]; e2[k] = p2[k] - p0[k]; }
+    if (active == 0) {
+        /* project onto the face plane */
+        double N[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        double nn = N[0] * N[0] + N[1] * N[1] + N[2] * N[2];
+        if (!(nn > 0)) return;
+        double ga = (g2[0] * N[0] + g2[1] * N[1] + g2[2] * N[2]) / nn;
+        double gb = (db[0] * N[0] + db[1] * N[1] + db[2] * N[2]) / nn;
+        for (int k = 0; k < 3; k++) { a[k] = g2[k] - ga * N[k]; b[k] = db[k] - gb * N[k]; }
+    } else {
+        /* project onto the active edge */
+        double e[3];
+        for (int k = 0; k < 3; k++) e[k] = on_s ? e2[k] : on_t ? e1[k] : e2[k] - e1[k];
+        double ee = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+        if (!(ee > 0)) return;
+        double ga = (g2[0] * e[0] + g2[1] * e[1] + g2[2] * e[2]) / ee;
+        double gb = (db[0] * e[0] + db[1] * e[1] + db[2] * e[2]) / ee;
+        for (int k = 0; k < 3; k++) { a[k] = ga * e[k]; b[k] = gb * e[k]; }
+    }
+    double bb = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+    if (!(bb > 1e-24)) return;
+    double alpha = -(a[0] * b[0] + a[1] * b[1] + a[2] * b[2]) / bb;
+    alpha = fmin(1.0, fmax(0.0, alpha));
+    for (int k = 0; k < 3; k++) g[k] = g2[k] + alpha * db[k];
+}
+
 static const double INVPHI = 0.6180339887498949;   /* (sqrt 5 - 1) / 2 */
 
 typedef struct { double p0[3], e1[3], e2[3], r, L; } Tri;
@@ -160,7 +211,7 @@ void orc_distance_query(const float *V, const int32_t *F, int nf, const double *
         d_out[i] = best;
         double u[3], g[3];
         for (int a = 0; a < 3; a++) u[a] = bu[0][a] + bs * (bu[1][a] - bu[0][a]) + bt * (bu[2][a] - bu[0][a]);
-        probe_grad(u, r, L, g);
+        witness_gradient(u, bu[0], bu[1], bu[2], bs, bt, r, L, g);
         for (int a = 0; a < 3; a++) {
             /* world = Ri u + pi ; normal = Ri g */
             x_out[3 * i + a] = Ri[3 * a] * u[0] + Ri[3 * a + 1] * u[1] + Ri[3 * a + 2] * u[2] + pi[a];
