@@ -187,6 +187,39 @@ int register_debug_correlation(reg_handle* h, int32_t rot, float* out_C);
  * decisions taken while building the grids. */
 int register_set_grids(reg_handle* h, const float* O, const uint8_t* Sw);
 
+/* Continuous SE(3) refinement of K initial object poses (Sec. V).  Each start
+ * (R0, p0) is refined over the twist xi = (v, w) with |v|_inf <= b_t and
+ * |w|_inf <= b_r, the left perturbation about the anchor a (Eq. se3-exp and
+ * the left pose updates): R = exp(w^) R0, p = p0 + V(w) v + (I - exp(w^)) R0 a.
+ * It minimises J = -sum_i s(d_i) + lambda |xi|^2 (Eq. objective), s the
+ * proximity score of Sec. V-A and d_i the smallest signed probe-mesh distance
+ * at probe pose i (Sec. V-B: faces kept by the bounding-sphere test with the
+ * cutoff eps, d_i = eps when none is), with the analytic contact sensitivities
+ * of Sec. V-C.  Solver: damped Gauss-Newton from xi = 0 with curvature
+ * sum_i max(0, -s''(d_i)) g_i g_i^T + 2 lambda I and an FP64 6x6 Cholesky solve
+ * of (H + mu diag H + 1e-12 I) step = -grad J; a step is kept when J
+ * decreases (mu /= 3), else mu *= 3.  Stops when the projected gradient is
+ * <= 1e-6, a step is <= 1e-9, mu reaches 1e12 or after params.max_iters steps.
+ * Distances are float32, the objective, its derivatives and the solve FP64.
+ *   init_poses: K x 7 double (qw qx qy qz tx ty tz, object body -> world, the
+ *   pose format of score_rotations), device memory; the quaternion norm must be
+ *   within 1 +- 1e-3.  out_poses: K x 7 double (w >= 0), out_J: K double or
+ *   NULL, out_iters: K int32 accepted-step counts or NULL; device memory.
+ * Synchronous: returns when the results are written.
+ * Errors: REG_EINVAL (K < 1, NULL poses, non-finite or non-unit start),
+ * REG_ENOMEM, REG_EDEVICE. */
+int refine_se3(reg_handle* h, const double* init_poses, int32_t K, double* out_poses, double* out_J,
+               int32_t* out_iters);
+
+/* Test hook: the refinement's distance query (Sec. V-B) of every probe pose
+ * against the object mesh placed by x -> R x + p.  R: 9 double row-major, p: 3
+ * double, host memory.  out: n_poses x 8 float, device memory: d, the witness
+ * x* (world), the unit normal n of the probe SDF there (world) and the index of
+ * the face that holds x* (int32 bits; -1 with d = eps when no face was kept).
+ * Faces farther than min(eps, tau_out2) may be skipped, since they cannot
+ * change s, s' or s''.  Synchronous. */
+int register_debug_distance(reg_handle* h, const double* R, const double* p, float* out);
+
 #ifdef __cplusplus
 }
 #endif

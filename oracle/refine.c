@@ -55,9 +55,11 @@ static void probe_grad(const double *u, double r, double L, double *g)
  * that g has no component along the directions in which the witness can move
  * (the face plane for an interior witness, the edge for an edge witness).  At a
  * vertex witness, or when those directions do not fix a, the one-sided
- * gradient is kept. */
+ * gradient is kept.  A witness within EDGE_TOL (barycentric) of an edge counts
+ * as on it: at an interior minimum the combination has no component along any
+ * face direction, the edge's included, so the edge gives the same a. */
 #define RIDGE_TOL 1e-4
-#define EDGE_TOL 1e-9
+#define EDGE_TOL 1e-4
 static void witness_gradient(const double *u, const double *p0, const double *p1, const double *p2, double s,
                              double t, double r, double L, double *g)
 {

@@ -24,7 +24,8 @@ _NAMES = {-1: "REG_EINVAL", -2: "REG_ENOMEM", -3: "REG_EDEVICE", -4: "REG_EBUSY"
 # every entry point the header declares
 EXPORTS = ["register_init", "score_rotations", "register_top_k", "register_free", "register_last_error",
            "register_info", "register_debug_object_grid", "register_debug_swept", "register_debug_correlation",
-           "register_set_grids", "register_set_timing", "register_get_timing", "register_search_stats"]
+           "register_set_grids", "register_set_timing", "register_get_timing", "register_search_stats",
+           "refine_se3", "register_debug_distance"]
 
 
 class RegError(RuntimeError):
@@ -98,6 +99,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.register_set_timing.argtypes = [p, i32]
     L.register_get_timing.restype = ctypes.c_int
     L.register_get_timing.argtypes = [p, p, p, p]
+    L.refine_se3.restype = ctypes.c_int
+    L.refine_se3.argtypes = [p, p, i32, p, p, p]
+    L.register_debug_distance.restype = ctypes.c_int
+    L.register_debug_distance.argtypes = [p, p, p, p]
     _lib = L
     return L
 
@@ -256,3 +261,27 @@ def register_search_stats(h: Handle) -> dict:
     _check(load_library().register_search_stats(h.ptr, *[ctypes.byref(x) for x in v]))
     return dict(rotations=v[0].value, candidates=v[1].value, overflows=v[2].value, uncertain=v[3].value,
                 rescored=v[4].value)
+
+
+def refine_se3(h: Handle, init_poses):
+    """(poses f64 [K,7], J f64 [K], iters i32 [K]) on the device from K x 7 starts."""
+    torch = _torch()
+    ip = _dev(init_poses, torch.float64)
+    K = ip.shape[0]
+    out = torch.empty((K, 7), dtype=torch.float64, device="cuda")
+    J = torch.empty(K, dtype=torch.float64, device="cuda")
+    it = torch.empty(K, dtype=torch.int32, device="cuda")
+    _check(load_library().refine_se3(h.ptr, _ptr(ip), K, _ptr(out), _ptr(J), _ptr(it)))
+    return out, J, it
+
+
+def register_debug_distance(h: Handle, R, p, n_poses: int):
+    """Distance query at the object pose (R, p): float32 [n_poses, 8] on the device
+    (d, witness xyz, normal xyz, face index bits)."""
+    torch = _torch()
+    Rh = np.ascontiguousarray(R, dtype=np.float64).reshape(9)
+    ph = np.ascontiguousarray(p, dtype=np.float64).reshape(3)
+    out = torch.empty((n_poses, 8), dtype=torch.float32, device="cuda")
+    _check(load_library().register_debug_distance(h.ptr, Rh.ctypes.data_as(ctypes.c_void_p),
+                                                  ph.ctypes.data_as(ctypes.c_void_p), _ptr(out)))
+    return out

@@ -2,6 +2,7 @@
 // launch sequence of the global search.  See include/regdock.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -9,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "refine_kernels.h"
 #include "regdock.h"
 #include "search_kernels.h"
 
@@ -82,6 +84,16 @@ struct reg_handle {
     double2* Wlow = nullptr;
     double2* Plow = nullptr;
     int* err = nullptr;
+    // refinement: bounding-sphere hierarchy of the mesh (built on first use)
+    // and per-start solver state
+    bool geo_ready = false;
+    RefineGeometry geo{};
+    RefineState* rst = nullptr;
+    RefineEval* rev = nullptr;
+    RefineHit* rhits = nullptr;
+    int r_cap = 0;
+    int* r_active = nullptr;
+    int* r_active_host = nullptr;  // pinned
     std::vector<void*> owned;
     // optional per-kernel timing with HIP events on the handle's stream
     bool timing = false;
@@ -115,6 +127,7 @@ struct reg_handle {
     ~reg_handle() {
         for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
         for (void* p : owned) (void)hipFree(p);
+        if (r_active_host) (void)hipHostFree(r_active_host);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
 };
@@ -168,6 +181,176 @@ static int default_batch(int n, size_t H, int n_rot) {
 static int build_object_derived(reg_handle* h) {
     DEV_TRY(h, object_spectrum(h->n, h->O, h->spec, h->W, h->tw, h->tw64, h->lowT, h->Wlow, h->stream));
     DEV_TRY(h, build_nonzero_list(h->O, h->n, h->nz_bcount, h->nz_boff, h->nz_idx, h->nz_val, h->nz_count, h->stream));
+    return REG_OK;
+}
+
+// Bounding-sphere hierarchy for the refinement's distance queries: faces in
+// Morton order of their centroids, REF_FANOUT faces per cluster and
+// REF_FANOUT clusters per top node.  A node's radius bounds the distance from
+// its centre to every point of its faces (centroid distance plus the face's
+// own radius), widened by 1e-5 mm so that float32 evaluation stays
+// conservative.  Face centroid and radius follow the body-frame definition of
+// the bounding-sphere test (mean of the three vertices, largest vertex distance).
+static int build_refine_geometry(reg_handle* h) {
+    const int nf = h->nf, nv = h->nv;
+    std::vector<float> V(3 * (size_t)nv);
+    std::vector<int32_t> F(3 * (size_t)nf);
+    DEV_TRY(h, hipMemcpyAsync(V.data(), h->V, V.size() * 4, hipMemcpyDeviceToHost, h->stream));
+    DEV_TRY(h, hipMemcpyAsync(F.data(), h->F, F.size() * 4, hipMemcpyDeviceToHost, h->stream));
+    DEV_TRY(h, hipStreamSynchronize(h->stream));
+    std::vector<double> fc(3 * (size_t)nf), fr(nf);
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int f = 0; f < nf; ++f) {
+        const float* v[3] = {&V[3 * (size_t)F[3 * f]], &V[3 * (size_t)F[3 * f + 1]], &V[3 * (size_t)F[3 * f + 2]]};
+        for (int a = 0; a < 3; ++a) {
+            fc[3 * f + a] = ((double)v[0][a] + (double)v[1][a] + (double)v[2][a]) / 3.0;
+            lo[a] = std::min(lo[a], fc[3 * f + a]);
+            hi[a] = std::max(hi[a], fc[3 * f + a]);
+        }
+        double r = 0;
+        for (int k = 0; k < 3; ++k) {
+            double d2 = 0;
+            for (int a = 0; a < 3; ++a) d2 += ((double)v[k][a] - fc[3 * f + a]) * ((double)v[k][a] - fc[3 * f + a]);
+            r = std::max(r, std::sqrt(d2));
+        }
+        fr[f] = r;
+    }
+    auto spread = [](uint32_t x) {
+        x &= 0x3ff;
+        x = (x | (x << 16)) & 0x030000ff;
+        x = (x | (x << 8)) & 0x0300f00f;
+        x = (x | (x << 4)) & 0x030c30c3;
+        x = (x | (x << 2)) & 0x09249249;
+        return x;
+    };
+    std::vector<std::pair<uint32_t, int>> key(nf);
+    for (int f = 0; f < nf; ++f) {
+        uint32_t q[3];
+        for (int a = 0; a < 3; ++a) {
+            const double ext = hi[a] - lo[a];
+            const double u = ext > 0 ? (fc[3 * f + a] - lo[a]) / ext : 0.0;
+            q[a] = (uint32_t)std::min(1023.0, std::max(0.0, std::floor(u * 1024.0)));
+        }
+        key[f] = {spread(q[0]) | (spread(q[1]) << 1) | (spread(q[2]) << 2), f};
+    }
+    std::sort(key.begin(), key.end());
+    const int n_cl = (nf + REF_FANOUT - 1) / REF_FANOUT;
+    const int n_top = (n_cl + REF_FANOUT - 1) / REF_FANOUT;
+    std::vector<float4> face(4 * (size_t)nf), cl(n_cl), top(n_top);
+    std::vector<int2> cl_range(n_cl), top_range(n_top);
+    std::vector<double> clc(3 * (size_t)n_cl), clr(n_cl);
+    for (int slot = 0; slot < nf; ++slot) {
+        const int f = key[slot].second;
+        const float* v[3] = {&V[3 * (size_t)F[3 * f]], &V[3 * (size_t)F[3 * f + 1]], &V[3 * (size_t)F[3 * f + 2]]};
+        float idx_bits;
+        std::memcpy(&idx_bits, &f, 4);
+        face[4 * (size_t)slot] = make_float4(v[0][0], v[0][1], v[0][2], v[1][0]);
+        face[4 * (size_t)slot + 1] = make_float4(v[1][1], v[1][2], v[2][0], v[2][1]);
+        face[4 * (size_t)slot + 2] = make_float4(v[2][2], (float)fc[3 * f], (float)fc[3 * f + 1], (float)fc[3 * f + 2]);
+        face[4 * (size_t)slot + 3] = make_float4((float)fr[f], idx_bits, 0.0f, 0.0f);
+    }
+    const double slack = 1e-5;
+    for (int c = 0; c < n_cl; ++c) {
+        const int s0 = c * REF_FANOUT, s1 = std::min(nf, s0 + REF_FANOUT);
+        double blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int slot = s0; slot < s1; ++slot) {
+            const int f = key[slot].second;
+            for (int a = 0; a < 3; ++a) {
+                blo[a] = std::min(blo[a], fc[3 * f + a] - fr[f]);
+                bhi[a] = std::max(bhi[a], fc[3 * f + a] + fr[f]);
+            }
+        }
+        double r = 0;
+        for (int a = 0; a < 3; ++a) clc[3 * c + a] = 0.5 * (blo[a] + bhi[a]);
+        for (int slot = s0; slot < s1; ++slot) {
+            const int f = key[slot].second;
+            double d2 = 0;
+            for (int a = 0; a < 3; ++a) d2 += (fc[3 * f + a] - clc[3 * c + a]) * (fc[3 * f + a] - clc[3 * c + a]);
+            r = std::max(r, std::sqrt(d2) + fr[f]);
+        }
+        clr[c] = r * (1 + 1e-6) + slack;
+        cl[c] = make_float4((float)clc[3 * c], (float)clc[3 * c + 1], (float)clc[3 * c + 2], (float)clr[c]);
+        cl_range[c] = make_int2(s0, s1 - s0);
+    }
+    for (int t = 0; t < n_top; ++t) {
+        const int c0 = t * REF_FANOUT, c1 = std::min(n_cl, c0 + REF_FANOUT);
+        double blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY}, tc[3];
+        for (int c = c0; c < c1; ++c)
+            for (int a = 0; a < 3; ++a) {
+                blo[a] = std::min(blo[a], clc[3 * c + a] - clr[c]);
+                bhi[a] = std::max(bhi[a], clc[3 * c + a] + clr[c]);
+            }
+        for (int a = 0; a < 3; ++a) tc[a] = 0.5 * (blo[a] + bhi[a]);
+        double r = 0;
+        for (int c = c0; c < c1; ++c) {
+            double d2 = 0;
+            for (int a = 0; a < 3; ++a) d2 += (clc[3 * c + a] - tc[a]) * (clc[3 * c + a] - tc[a]);
+            r = std::max(r, std::sqrt(d2) + clr[c]);
+        }
+        top[t] = make_float4((float)tc[0], (float)tc[1], (float)tc[2], (float)(r * (1 + 1e-6) + slack));
+        top_range[t] = make_int2(c0, c1 - c0);
+    }
+    float4 *d_face, *d_cl, *d_top;
+    int2 *d_clr, *d_topr;
+    ALLOC_TRY(h, d_face, face.size());
+    ALLOC_TRY(h, d_cl, cl.size());
+    ALLOC_TRY(h, d_top, top.size());
+    ALLOC_TRY(h, d_clr, cl_range.size());
+    ALLOC_TRY(h, d_topr, top_range.size());
+    hipStream_t s = h->stream;
+    DEV_TRY(h, hipMemcpyAsync(d_face, face.data(), face.size() * sizeof(float4), hipMemcpyHostToDevice, s));
+    DEV_TRY(h, hipMemcpyAsync(d_cl, cl.data(), cl.size() * sizeof(float4), hipMemcpyHostToDevice, s));
+    DEV_TRY(h, hipMemcpyAsync(d_top, top.data(), top.size() * sizeof(float4), hipMemcpyHostToDevice, s));
+    DEV_TRY(h, hipMemcpyAsync(d_clr, cl_range.data(), cl_range.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    DEV_TRY(h, hipMemcpyAsync(d_topr, top_range.data(), top_range.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    DEV_TRY(h, hipStreamSynchronize(s));
+    h->geo = RefineGeometry{d_top, d_topr, d_cl, d_clr, d_face, n_top};
+    h->geo_ready = true;
+    return REG_OK;
+}
+
+// solver constants: Table I values, the box, and the device-side stopping rule
+static RefineConst refine_const(const reg_handle* h) {
+    RefineConst c{};
+    c.r = (float)h->probe.radius_mm;
+    c.L = (float)h->probe.length_mm;
+    // faces farther than tau_out2 cannot change s, s' or s''; cull at the
+    // smaller of the cutoff and tau_out2
+    c.cull = (float)std::min(h->prm.eps, h->prm.tau_out2);
+    c.eps = (float)h->prm.eps;
+    c.tau_out2 = h->prm.tau_out2;
+    c.tau_in2 = h->prm.tau_in2;
+    c.k = h->prm.k;
+    c.lambda = h->prm.lambda;
+    c.b_t = h->prm.b_t;
+    c.b_r = h->prm.b_r;
+    c.tol_pg = 1e-6;
+    c.tol_step = 1e-9;
+    c.mu0 = 1e-3;
+    c.max_iters = h->prm.max_iters;
+    return c;
+}
+
+static int ensure_refine_buffers(reg_handle* h, int K) {
+    if (!h->geo_ready) {
+        int rc = build_refine_geometry(h);
+        if (rc) return rc;
+    }
+    if (!h->r_active_host) {
+        if (hipHostMalloc((void**)&h->r_active_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+            h->r_active_host = nullptr;
+            (void)hipGetLastError();
+            return fail(REG_ENOMEM, "pinned host allocation failed");
+        }
+        ALLOC_TRY(h, h->r_active, 1);
+    }
+    if (K > h->r_cap) {
+        const int cap = std::max(K, 16);
+        ALLOC_TRY(h, h->rst, (size_t)cap);
+        ALLOC_TRY(h, h->rev, (size_t)cap);
+        ALLOC_TRY(h, h->rhits, (size_t)cap * h->n_poses);
+        h->r_cap = cap;
+    }
     return REG_OK;
 }
 
@@ -467,6 +650,61 @@ int register_set_grids(reg_handle* h, const float* O, const uint8_t* Sw) {
         DEV_TRY(h, hipMemcpyAsync(h->Sw, Sw, m3, hipMemcpyDeviceToDevice, h->stream));
         DEV_TRY(h, setup_cellmask(h->Sw, h->m, h->mp, h->cm, h->stream));
     }
+    return REG_OK;
+}
+
+int refine_se3(reg_handle* h, const double* init_poses, int32_t K, double* out_poses, double* out_J,
+               int32_t* out_iters) {
+    g_err.clear();
+    if (!h) return fail(REG_EINVAL, "NULL handle");
+    if (h->poisoned) return fail(REG_EDEVICE, "handle poisoned by an earlier device error");
+    if (!init_poses || !out_poses || K < 1) return fail(REG_EINVAL, "refine_se3 needs K >= 1 and non-NULL poses");
+    std::vector<double> init(7 * (size_t)K);
+    DEV_TRY(h, hipMemcpyAsync(init.data(), init_poses, init.size() * 8, hipMemcpyDeviceToHost, h->stream));
+    DEV_TRY(h, hipStreamSynchronize(h->stream));
+    for (int k = 0; k < K; ++k) {
+        const double* q = &init[7 * (size_t)k];
+        for (int j = 0; j < 7; ++j)
+            if (!std::isfinite(q[j])) return fail(REG_EINVAL, "initial pose %d is not finite", k);
+        const double nq = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        if (std::fabs(nq - 1.0) > 1e-3) return fail(REG_EINVAL, "initial pose %d: quaternion norm %g", k, nq);
+    }
+    int rc = ensure_refine_buffers(h, K);
+    if (rc) return rc;
+    const RefineConst c = refine_const(h);
+    hipStream_t s = h->stream;
+    DEV_TRY(h, refine_start(init_poses, K, h->anchor, c, h->rst, s));
+    // one evaluation per round; every start needs at most one per trial step
+    // and the damping can grow 3x at most 51 times in a row
+    const long max_rounds = 1 + (long)(c.max_iters + 1) * 52;
+    for (long round = 0; round < max_rounds; ++round) {
+        DEV_TRY(h, refine_round(h->rst, K, h->geo, h->poses, h->n_poses, c, h->rhits, h->rev, h->r_active, s));
+        if (round % 4 == 3 || round + 1 == max_rounds) {
+            DEV_TRY(h, hipMemcpyAsync(h->r_active_host, h->r_active, sizeof(int), hipMemcpyDeviceToHost, s));
+            DEV_TRY(h, hipStreamSynchronize(s));
+            if (*h->r_active_host == 0) break;
+        }
+    }
+    DEV_TRY(h, refine_finish(h->rst, K, out_poses, out_J, out_iters, s));
+    DEV_TRY(h, hipStreamSynchronize(s));
+    return REG_OK;
+}
+
+int register_debug_distance(reg_handle* h, const double* R, const double* p, float* out) {
+    g_err.clear();
+    if (!h || !R || !p || !out) return fail(REG_EINVAL, "NULL argument");
+    if (h->poisoned) return fail(REG_EDEVICE, "handle poisoned by an earlier device error");
+    int rc = ensure_refine_buffers(h, 1);
+    if (rc) return rc;
+    RefineState st{};
+    for (int j = 0; j < 9; ++j) st.R[j] = R[j];
+    for (int j = 0; j < 3; ++j) st.p[j] = p[j];
+    st.status = 1;
+    const RefineConst c = refine_const(h);
+    DEV_TRY(h, hipMemcpyAsync(h->rst, &st, sizeof st, hipMemcpyHostToDevice, h->stream));
+    DEV_TRY(h, refine_query_only(h->rst, h->geo, h->poses, h->n_poses, c, h->rhits, h->stream));
+    DEV_TRY(h, hipMemcpyAsync(out, h->rhits, sizeof(RefineHit) * h->n_poses, hipMemcpyDeviceToDevice, h->stream));
+    DEV_TRY(h, hipStreamSynchronize(h->stream));
     return REG_OK;
 }
 

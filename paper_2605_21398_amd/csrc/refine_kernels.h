@@ -1,0 +1,65 @@
+// Device side of the continuous SE(3) refinement (Sec. V): distance queries of
+// the probe poses against the moved object mesh (Sec. V-B), the objective with
+// its analytic contact sensitivities (Sec. V-A, V-C) and a damped Gauss-Newton
+// (Levenberg-Marquardt) step on the box-bounded twist with an FP64 6x6 solve.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+// Bounding-sphere hierarchy of the body-frame mesh (Sec. V-B keeps a node when
+// the probe SDF at its centre is below its radius plus the cutoff): top-level
+// nodes hold up to REF_FANOUT clusters, clusters hold up to REF_FANOUT faces
+// (faces in Morton order of their centroids).
+constexpr int REF_FANOUT = 32;
+
+struct RefineGeometry {
+    const float4* top;        // n_top spheres (centre, radius)
+    const int2* top_range;    // first cluster, cluster count
+    const float4* cluster;    // n_cluster spheres
+    const int2* cluster_range;  // first face slot, face count
+    const float4* face;       // 4 float4 per face slot: v0 v1 v2 (body), centroid, radius, original index
+    int n_top;
+};
+
+struct RefineConst {
+    float r, L;               // probe radius and length (mm)
+    float cull;               // cutoff margin of the node/face test (mm)
+    float eps;                // d reported when no face is kept
+    double tau_out2, tau_in2, k, lambda, b_t, b_r;
+    double tol_pg, tol_step, mu0;
+    int max_iters;
+};
+
+// Per-start solver state, FP64.  status: 0 = evaluation at xi = 0 pending,
+// 1 = trial step pending, 2 = finished.
+struct RefineState {
+    double R0[9], p0[3], a[3];
+    double xi[6], xe[6], step[6];
+    double J, g[6], H[36];
+    double mu;
+    double R[9], p[3], V[9], D[9], c[3];  // pose at xe and its Jacobians
+    int it, status, pad0, pad1;
+};
+
+// Objective, gradient and Gauss-Newton curvature at xe (upper triangle of H).
+struct RefineEval {
+    double J, g[6], H[21];
+};
+
+// One distance-query result: {d, x*} and {n, face index bits}.
+struct RefineHit {
+    float4 dx, nf;
+};
+
+hipError_t refine_start(const double* init_poses, int K, const double* anchor, const RefineConst& c,
+                        RefineState* st, hipStream_t s);
+// One evaluation round for every unfinished start: pose at xe, distance
+// queries, FP64 assembly, LM decision; *active receives the unfinished count.
+hipError_t refine_round(RefineState* st, int K, const RefineGeometry& geo, const float* poses, int n_poses,
+                        const RefineConst& c, RefineHit* hits, RefineEval* ev, int* active, hipStream_t s);
+hipError_t refine_finish(const RefineState* st, int K, double* out_poses, double* out_J, int32_t* out_iters,
+                         hipStream_t s);
+// Distance queries of all poses at the object pose in st[0] (R, p set).
+hipError_t refine_query_only(RefineState* st, const RefineGeometry& geo, const float* poses, int n_poses,
+                             const RefineConst& c, RefineHit* hits, hipStream_t s);
