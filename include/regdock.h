@@ -211,6 +211,12 @@ int register_set_grids(reg_handle* h, const float* O, const uint8_t* Sw);
 int refine_se3(reg_handle* h, const double* init_poses, int32_t K, double* out_poses, double* out_J,
                int32_t* out_iters);
 
+/* Work of the last refine_se3 call on the handle: evaluation rounds launched
+ * (all unfinished starts are evaluated together in a round) and evaluations
+ * made (one per unfinished start per round: a trial step, or the start
+ * itself).  Host pointers. */
+int register_refine_stats(reg_handle* h, int64_t* rounds, int64_t* evaluations);
+
 /* Test hook: the refinement's distance query (Sec. V-B) of every probe pose
  * against the object mesh placed by x -> R x + p.  R: 9 double row-major, p: 3
  * double, host memory.  out: n_poses x 8 float, device memory: d, the witness

@@ -23,6 +23,9 @@ Readings taken (listed in the design notes):
     D = d(V(w) v)/dw is taken by central differences as the paper does;
   * the solver is damped Gauss-Newton (Levenberg-Marquardt) on the box with an
     FP64 6x6 solve in place of L-BFGS-B; curvature sum_i max(0, -s'') g g^T.
+    Like L-BFGS-B it keeps an active set: a coordinate at its bound whose
+    gradient points out of the box is held there and the step solves for the
+    others (a clamped full step stalls along the box faces).
 """
 from __future__ import annotations
 
@@ -220,6 +223,26 @@ def solve6(A, b):
     return np.linalg.solve(A, b)
 
 
+def active_bounds(xi, g, prm: RefineParams):
+    """Coordinates held at their bound: at the bound (within 1e-12 of it) with
+    the gradient pointing out of the box, so that a descent step would leave it."""
+    b = np.array([prm.b_t] * 3 + [prm.b_r] * 3)
+    return ((xi >= b - 1e-12) & (g < 0)) | ((xi <= -b + 1e-12) & (g > 0))
+
+
+def lm_step(H, g, mu, active):
+    """Damped Gauss-Newton step on the free coordinates, zero on the active ones:
+    (H + mu diag H + 1e-12 I) restricted to the free set, solved in FP64."""
+    A = H + mu * np.diag(np.diag(H)) + 1e-12 * np.eye(6)
+    rhs = -np.asarray(g, dtype=np.float64).copy()
+    A = A.copy()
+    A[active, :] = 0.0
+    A[:, active] = 0.0
+    A[active, active] = 1.0
+    rhs[active] = 0.0
+    return solve6(A, rhs)
+
+
 @dataclass
 class RefineResult:
     R: np.ndarray
@@ -230,7 +253,9 @@ class RefineResult:
 
 
 def refine(pb: Problem, prm: RefineParams = RefineParams()) -> RefineResult:
-    """Damped Gauss-Newton on the box from xi = 0 (Sec. V-C; solver per the readings)."""
+    """Damped Gauss-Newton on the box from xi = 0 (Sec. V-C; solver per the
+    readings): each iteration solves for the free coordinates, projects onto the
+    box, keeps the step if J decreases (mu / 3) and otherwise retries with 3 mu."""
     xi = np.zeros(6)
     mu = prm.mu0
     J, g, H = evaluate(xi, pb, prm)
@@ -242,9 +267,9 @@ def refine(pb: Problem, prm: RefineParams = RefineParams()) -> RefineResult:
         it += 1
         accepted = False
         step = np.zeros(6)
+        active = active_bounds(xi, g, prm)
         while mu < 1e12:
-            A = H + mu * np.diag(np.diag(H)) + 1e-12 * np.eye(6)
-            step = solve6(A, -g)
+            step = lm_step(H, g, mu, active)
             xn = project_box(xi + step, prm)
             Jn, _, _ = evaluate(xn, pb, prm, want_grad=False)
             if Jn < J:

@@ -25,7 +25,7 @@ _NAMES = {-1: "REG_EINVAL", -2: "REG_ENOMEM", -3: "REG_EDEVICE", -4: "REG_EBUSY"
 EXPORTS = ["register_init", "score_rotations", "register_top_k", "register_free", "register_last_error",
            "register_info", "register_debug_object_grid", "register_debug_swept", "register_debug_correlation",
            "register_set_grids", "register_set_timing", "register_get_timing", "register_search_stats",
-           "refine_se3", "register_debug_distance"]
+           "refine_se3", "register_debug_distance", "register_refine_stats"]
 
 
 class RegError(RuntimeError):
@@ -103,6 +103,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.refine_se3.argtypes = [p, p, i32, p, p, p]
     L.register_debug_distance.restype = ctypes.c_int
     L.register_debug_distance.argtypes = [p, p, p, p]
+    L.register_refine_stats.restype = ctypes.c_int
+    L.register_refine_stats.argtypes = [p, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     _lib = L
     return L
 
@@ -285,3 +287,10 @@ def register_debug_distance(h: Handle, R, p, n_poses: int):
     _check(load_library().register_debug_distance(h.ptr, Rh.ctypes.data_as(ctypes.c_void_p),
                                                   ph.ctypes.data_as(ctypes.c_void_p), _ptr(out)))
     return out
+
+
+def register_refine_stats(h: Handle) -> dict:
+    """Rounds and evaluations of the last refine_se3 call on the handle."""
+    r, e = ctypes.c_int64(), ctypes.c_int64()
+    _check(load_library().register_refine_stats(h.ptr, ctypes.byref(r), ctypes.byref(e)))
+    return dict(rounds=r.value, evaluations=e.value)

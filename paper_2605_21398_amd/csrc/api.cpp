@@ -89,11 +89,14 @@ struct reg_handle {
     bool geo_ready = false;
     RefineGeometry geo{};
     RefineState* rst = nullptr;
+    RefineTrial* rtr = nullptr;
     RefineEval* rev = nullptr;
     RefineHit* rhits = nullptr;
+    RefineScratch rw{};
     int r_cap = 0;
-    int* r_active = nullptr;
-    int* r_active_host = nullptr;  // pinned
+    int* r_active = nullptr;       // [unfinished starts, evaluations]
+    int* r_active_host = nullptr;  // pinned copy of r_active
+    int64_t r_rounds = 0, r_evals = 0;  // of the last refine_se3 call
     std::vector<void*> owned;
     // optional per-kernel timing with HIP events on the handle's stream
     bool timing = false;
@@ -239,8 +242,10 @@ static int build_refine_geometry(reg_handle* h) {
     std::vector<float4> face(4 * (size_t)nf), cl(n_cl), top(n_top);
     std::vector<int2> cl_range(n_cl), top_range(n_top);
     std::vector<double> clc(3 * (size_t)n_cl), clr(n_cl);
+    std::vector<int> slot_of(nf);
     for (int slot = 0; slot < nf; ++slot) {
         const int f = key[slot].second;
+        slot_of[f] = slot;
         const float* v[3] = {&V[3 * (size_t)F[3 * f]], &V[3 * (size_t)F[3 * f + 1]], &V[3 * (size_t)F[3 * f + 2]]};
         float idx_bits;
         std::memcpy(&idx_bits, &f, 4);
@@ -292,6 +297,8 @@ static int build_refine_geometry(reg_handle* h) {
     }
     float4 *d_face, *d_cl, *d_top;
     int2 *d_clr, *d_topr;
+    int* d_slot;
+    ALLOC_TRY(h, d_slot, slot_of.size());
     ALLOC_TRY(h, d_face, face.size());
     ALLOC_TRY(h, d_cl, cl.size());
     ALLOC_TRY(h, d_top, top.size());
@@ -303,8 +310,9 @@ static int build_refine_geometry(reg_handle* h) {
     DEV_TRY(h, hipMemcpyAsync(d_top, top.data(), top.size() * sizeof(float4), hipMemcpyHostToDevice, s));
     DEV_TRY(h, hipMemcpyAsync(d_clr, cl_range.data(), cl_range.size() * sizeof(int2), hipMemcpyHostToDevice, s));
     DEV_TRY(h, hipMemcpyAsync(d_topr, top_range.data(), top_range.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    DEV_TRY(h, hipMemcpyAsync(d_slot, slot_of.data(), slot_of.size() * sizeof(int), hipMemcpyHostToDevice, s));
     DEV_TRY(h, hipStreamSynchronize(s));
-    h->geo = RefineGeometry{d_top, d_topr, d_cl, d_clr, d_face, n_top};
+    h->geo = RefineGeometry{d_top, d_topr, d_cl, d_clr, d_face, d_slot, n_top, n_cl};
     h->geo_ready = true;
     return REG_OK;
 }
@@ -337,18 +345,30 @@ static int ensure_refine_buffers(reg_handle* h, int K) {
         if (rc) return rc;
     }
     if (!h->r_active_host) {
-        if (hipHostMalloc((void**)&h->r_active_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        if (hipHostMalloc((void**)&h->r_active_host, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
             h->r_active_host = nullptr;
             (void)hipGetLastError();
             return fail(REG_ENOMEM, "pinned host allocation failed");
         }
-        ALLOC_TRY(h, h->r_active, 1);
+        ALLOC_TRY(h, h->r_active, 2);
     }
     if (K > h->r_cap) {
         const int cap = std::max(K, 16);
         ALLOC_TRY(h, h->rst, (size_t)cap);
-        ALLOC_TRY(h, h->rev, (size_t)cap);
-        ALLOC_TRY(h, h->rhits, (size_t)cap * h->n_poses);
+        ALLOC_TRY(h, h->rtr, (size_t)cap * REF_TMAX);
+        ALLOC_TRY(h, h->rev, (size_t)cap * REF_TMAX);
+        ALLOC_TRY(h, h->rhits, (size_t)cap * REF_TMAX * h->n_poses);
+        // pairs: 16 per query on average (about 3 are needed); a query whose
+        // pairs do not fit is searched by itself
+        const size_t nq = (size_t)cap * REF_TMAX * h->n_poses;
+        ALLOC_TRY(h, h->rw.xf, 12 * nq);
+        ALLOC_TRY(h, h->rw.qkey, nq);
+        ALLOC_TRY(h, h->rw.qflag, nq);
+        ALLOC_TRY(h, h->rw.qst, nq);
+        ALLOC_TRY(h, h->rw.pairs, 16 * nq);
+        ALLOC_TRY(h, h->rw.pres, 16 * nq);
+        if (!h->rw.pair_count) ALLOC_TRY(h, h->rw.pair_count, 1);
+        h->rw.pair_cap = (int)std::min<size_t>(16 * nq, 1u << 30);
         h->r_cap = cap;
     }
     return REG_OK;
@@ -673,20 +693,35 @@ int refine_se3(reg_handle* h, const double* init_poses, int32_t K, double* out_p
     if (rc) return rc;
     const RefineConst c = refine_const(h);
     hipStream_t s = h->stream;
-    DEV_TRY(h, refine_start(init_poses, K, h->anchor, c, h->rst, s));
-    // one evaluation per round; every start needs at most one per trial step
-    // and the damping can grow 3x at most 51 times in a row
+    DEV_TRY(h, refine_start(init_poses, K, h->anchor, c, h->rst, h->rtr, h->r_active, h->rw, s));
+    // every round evaluates the next trials of each unfinished start and
+    // settles at least one of its trial steps; a start takes at most
+    // max_iters accepted steps and the damping can grow 3x at most 51 times
+    // in a row
     const long max_rounds = 1 + (long)(c.max_iters + 1) * 52;
-    for (long round = 0; round < max_rounds; ++round) {
-        DEV_TRY(h, refine_round(h->rst, K, h->geo, h->poses, h->n_poses, c, h->rhits, h->rev, h->r_active, s));
-        if (round % 4 == 3 || round + 1 == max_rounds) {
-            DEV_TRY(h, hipMemcpyAsync(h->r_active_host, h->r_active, sizeof(int), hipMemcpyDeviceToHost, s));
+    long round = 0;
+    while (round < max_rounds) {
+        DEV_TRY(h, refine_round(h->rst, h->rtr, K, h->geo, h->poses, h->n_poses, c, h->rw, h->rhits, h->rev,
+                                h->r_active, s));
+        ++round;
+        if (round % 4 == 0 || round == max_rounds) {
+            DEV_TRY(h, hipMemcpyAsync(h->r_active_host, h->r_active, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
             DEV_TRY(h, hipStreamSynchronize(s));
-            if (*h->r_active_host == 0) break;
+            if (h->r_active_host[0] == 0) break;
         }
     }
     DEV_TRY(h, refine_finish(h->rst, K, out_poses, out_J, out_iters, s));
+    DEV_TRY(h, hipMemcpyAsync(h->r_active_host, h->r_active, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     DEV_TRY(h, hipStreamSynchronize(s));
+    h->r_rounds = round;
+    h->r_evals = h->r_active_host[1];
+    return REG_OK;
+}
+
+int register_refine_stats(reg_handle* h, int64_t* rounds, int64_t* evaluations) {
+    if (!h || !rounds || !evaluations) return fail(REG_EINVAL, "NULL argument");
+    *rounds = h->r_rounds;
+    *evaluations = h->r_evals;
     return REG_OK;
 }
 
@@ -696,13 +731,13 @@ int register_debug_distance(reg_handle* h, const double* R, const double* p, flo
     if (h->poisoned) return fail(REG_EDEVICE, "handle poisoned by an earlier device error");
     int rc = ensure_refine_buffers(h, 1);
     if (rc) return rc;
-    RefineState st{};
-    for (int j = 0; j < 9; ++j) st.R[j] = R[j];
-    for (int j = 0; j < 3; ++j) st.p[j] = p[j];
-    st.status = 1;
+    RefineTrial tr{};
+    for (int j = 0; j < 9; ++j) tr.R[j] = R[j];
+    for (int j = 0; j < 3; ++j) tr.p[j] = p[j];
+    tr.valid = 1;
     const RefineConst c = refine_const(h);
-    DEV_TRY(h, hipMemcpyAsync(h->rst, &st, sizeof st, hipMemcpyHostToDevice, h->stream));
-    DEV_TRY(h, refine_query_only(h->rst, h->geo, h->poses, h->n_poses, c, h->rhits, h->stream));
+    DEV_TRY(h, hipMemcpyAsync(h->rtr, &tr, sizeof tr, hipMemcpyHostToDevice, h->stream));
+    DEV_TRY(h, refine_query_only(h->rtr, h->geo, h->poses, h->n_poses, c, h->rw, h->rhits, h->r_active, h->stream));
     DEV_TRY(h, hipMemcpyAsync(out, h->rhits, sizeof(RefineHit) * h->n_poses, hipMemcpyDeviceToDevice, h->stream));
     DEV_TRY(h, hipStreamSynchronize(h->stream));
     return REG_OK;

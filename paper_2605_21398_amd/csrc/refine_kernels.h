@@ -19,7 +19,21 @@ struct RefineGeometry {
     const float4* cluster;    // n_cluster spheres
     const int2* cluster_range;  // first face slot, face count
     const float4* face;       // 4 float4 per face slot: v0 v1 v2 (body), centroid, radius, original index
+    const int* slot_of;       // original face index -> slot
     int n_top;
+    int n_cluster;
+};
+
+// Work buffers of the distance query, per (start, probe pose) query q.
+struct RefineScratch {
+    float* xf;                  // 12 floats per query: body -> probe frame (A row-major, c)
+    unsigned long long* qkey;   // best (value, face index) key
+    int* qflag;                 // 0: no face kept, 1: key valid, 2: pair list overflowed
+    float2* qst;                // barycentric witness of the winning search (-1: a vertex won)
+    int2* pairs;                // (query, face slot) pairs for a golden-section search
+    float4* pres;               // per pair: minimum, s, t
+    int* pair_count;
+    int pair_cap;
 };
 
 struct RefineConst {
@@ -32,17 +46,28 @@ struct RefineConst {
 };
 
 // Per-start solver state, FP64.  status: 0 = evaluation at xi = 0 pending,
-// 1 = trial step pending, 2 = finished.
+// 1 = trial steps pending, 2 = finished.
 struct RefineState {
     double R0[9], p0[3], a[3];
-    double xi[6], xe[6], step[6];
+    double xi[6];
     double J, g[6], H[36];
     double mu;
-    double R[9], p[3], V[9], D[9], c[3];  // pose at xe and its Jacobians
     int it, status, pad0, pad1;
 };
 
-// Objective, gradient and Gauss-Newton curvature at xe (upper triangle of H).
+// Trial slots per start: one round evaluates the trial steps the damped
+// Gauss-Newton iteration would try next (damping mu, 3 mu, 9 mu, ...), so a
+// rejected step does not cost a round of its own.
+constexpr int REF_TMAX = 4;
+
+// One trial point of a start, FP64: twist, step, damping, pose and Jacobians.
+struct RefineTrial {
+    double xe[6], step[6], mu;
+    double R[9], p[3], V[9], D[9], c[3];
+    int valid, pad;
+};
+
+// Objective, gradient and Gauss-Newton curvature at a trial (upper triangle of H).
 struct RefineEval {
     double J, g[6], H[21];
 };
@@ -52,14 +77,18 @@ struct RefineHit {
     float4 dx, nf;
 };
 
+// counters[0]: unfinished starts, counters[1]: evaluations so far (device)
 hipError_t refine_start(const double* init_poses, int K, const double* anchor, const RefineConst& c,
-                        RefineState* st, hipStream_t s);
-// One evaluation round for every unfinished start: pose at xe, distance
-// queries, FP64 assembly, LM decision; *active receives the unfinished count.
-hipError_t refine_round(RefineState* st, int K, const RefineGeometry& geo, const float* poses, int n_poses,
-                        const RefineConst& c, RefineHit* hits, RefineEval* ev, int* active, hipStream_t s);
+                        RefineState* st, RefineTrial* tr, int* counters, const RefineScratch& w, hipStream_t s);
+// One evaluation round for every unfinished start: distance queries at its
+// trial poses, FP64 assembly, the damped Gauss-Newton decision and the next
+// trials; updates counters.
+hipError_t refine_round(RefineState* st, RefineTrial* tr, int K, const RefineGeometry& geo, const float* poses,
+                        int n_poses, const RefineConst& c, const RefineScratch& w, RefineHit* hits, RefineEval* ev,
+                        int* counters, hipStream_t s);
 hipError_t refine_finish(const RefineState* st, int K, double* out_poses, double* out_J, int32_t* out_iters,
                          hipStream_t s);
-// Distance queries of all poses at the object pose in st[0] (R, p set).
-hipError_t refine_query_only(RefineState* st, const RefineGeometry& geo, const float* poses, int n_poses,
-                             const RefineConst& c, RefineHit* hits, hipStream_t s);
+// Distance queries of all poses at the object pose of trial slot 0 (R, p set, valid).
+hipError_t refine_query_only(const RefineTrial* tr, const RefineGeometry& geo, const float* poses, int n_poses,
+                             const RefineConst& c, const RefineScratch& w, RefineHit* hits, int* counters,
+                             hipStream_t s);

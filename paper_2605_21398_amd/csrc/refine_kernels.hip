@@ -3,18 +3,23 @@
 // Every start (an initial object pose from the global search) is refined by a
 // damped Gauss-Newton iteration on the twist xi = (v, w), one evaluation round
 // per trial step for all unfinished starts at once:
-//   k_ref_pose    FP64: R = exp(w^) R0, p = p0 + V(w) v + (I - exp(w^)) R0 a
-//                 (Eq. se3-exp and the left updates), V(w), D = d(V v)/dw and
-//                 the pivot c = p0 + V v + R0 a;
-//   k_ref_query   FP32: per (start, probe pose) the smallest signed distance d,
+//   k_ref_cull, k_ref_pairs, k_ref_winner, k_ref_resolve
+//                 FP32: per (start, probe pose) the smallest signed distance d,
 //                 its witness x* and the probe normal n (Sec. V-B);
-//   k_ref_reduce  FP64: J = -sum s(d) + lambda |xi|^2, grad J and the
-//                 curvature sum max(0, -s'') g g^T + 2 lambda I, g the contact
-//                 sensitivities (Sec. V-C), in a fixed summation order;
-//   k_ref_step    FP64: accept or reject the trial, update the damping and
-//                 solve (H + mu diag H + 1e-12 I) step = -grad by Cholesky.
+//   k_ref_eval    FP64, one block per trial: J = -sum s(d) + lambda |xi|^2,
+//                 grad J and the curvature sum max(0, -s'') g g^T + 2 lambda I
+//                 with g the contact sensitivities (Sec. V-C), in a fixed
+//                 summation order;
+//   k_ref_decide  FP64, one block per start: accept or reject the trials in
+//                 the order the sequential iteration tries them, update the
+//                 damping, solve (H + mu diag H + 1e-12 I) step = -grad by
+//                 Cholesky for the next trials, and set up their poses
+//                 R = exp(w^) R0, p = p0 + V(w) v + (I - exp(w^)) R0 a
+//                 (Eq. se3-exp and the left updates) with V(w), the coupling
+//                 D = d(V v)/dw and the pivot c = p0 + V v + R0 a.
 #include "refine_kernels.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace {
@@ -23,6 +28,8 @@ constexpr float GOLD_TOL = 1e-5f;         // barycentric bracket width of the fa
 constexpr float RIDGE_TOL = 1e-4f;        // |q1 - q2| below which a witness is on the side/cap ridge
 constexpr float EDGE_TOL = 1e-4f;         // barycentric distance below which a witness is on an edge
 constexpr float INVPHI_F = 0.618033988749894848f;
+constexpr float BOUND_SLACK = 1e-5f;      // float32 rounding allowance of the face bounds (mm)
+constexpr float VERTEX_GAP = 2e-6f;       // bounds this close: the best vertex is the face minimum (mm)
 
 // ------------------------------------------------------------ FP64 rotations
 
@@ -73,13 +80,39 @@ __device__ double clampd(double x, double b) { return fmin(b, fmax(-b, x)); }
 
 // ------------------------------------------------------------ FP32 probe SDF
 
+// hardware square root (v_sqrt_f32, about 1 ulp): the correctly rounded
+// sqrtf adds a dozen dependent instructions, which the sequential face
+// searches pay on every evaluation; 1 ulp of a radius is ~1e-7 of it
+__device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // capped cylinder, tip disk at the origin, axis +z, length L (negative inside)
 __device__ __forceinline__ float sdf_f(float x, float y, float z, float r, float L) {
-    const float q1 = sqrtf(x * x + y * y) - r;
+    const float q1 = hw_sqrt(x * x + y * y) - r;
     const float q2 = fabsf(z - 0.5f * L) - 0.5f * L;
     const float in = fminf(fmaxf(q1, q2), 0.0f);
     const float a = fmaxf(q1, 0.0f), b = fmaxf(q2, 0.0f);
-    return in + sqrtf(a * a + b * b);
+    return in + hw_sqrt(a * a + b * b);
+}
+
+// f_p and a subgradient (the gradient where f_p is differentiable; on the
+// inner ridge the gradient of the larger branch)
+__device__ __forceinline__ float sdf_grad_f(float3 u, float r, float L, float3& g) {
+    const float rho = hw_sqrt(u.x * u.x + u.y * u.y);
+    const float q1 = rho - r, q2 = fabsf(u.z - 0.5f * L) - 0.5f * L;
+    const float sz = u.z >= 0.5f * L ? 1.0f : -1.0f;
+    const float ex = rho > 0 ? u.x / rho : 1.0f, ey = rho > 0 ? u.y / rho : 0.0f;
+    if (q1 <= 0 && q2 <= 0) {
+        if (q1 >= q2) {
+            g = make_float3(ex, ey, 0.0f);
+            return q1;
+        }
+        g = make_float3(0.0f, 0.0f, sz);
+        return q2;
+    }
+    const float a = fmaxf(q1, 0.0f), b = fmaxf(q2, 0.0f);
+    const float n = hw_sqrt(a * a + b * b);
+    g = make_float3(a * ex / n, a * ey / n, b * sz / n);
+    return n;
 }
 
 struct Xf {  // body -> probe frame, u = A b + c
@@ -194,39 +227,23 @@ __device__ float3 witness_gradient(float3 u, const Tri& T, float s, float t) {
 
 // ------------------------------------------------------------------ kernels
 
-__global__ void k_ref_start(const double* __restrict__ init, int K, const double* __restrict__ anchor, double mu0,
-                            RefineState* __restrict__ st) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= K) return;
-    RefineState& S = st[k];
-    const double* P = init + 7 * k;
-    quat_mat(P[0], P[1], P[2], P[3], S.R0);
-    for (int a = 0; a < 3; ++a) {
-        S.p0[a] = P[4 + a];
-        S.a[a] = anchor[a];
-    }
-    for (int j = 0; j < 6; ++j) S.xi[j] = S.xe[j] = S.step[j] = 0.0;
-    S.mu = mu0;
-    S.it = 0;
-    S.status = 0;
-}
-
-// pose of the twist xe and the Jacobians the sensitivities need
-__device__ void pose_at(RefineState& S, const double* x) {
+// pose of the twist x about the start's anchor and the Jacobians the
+// sensitivities need, into the trial T
+__device__ void pose_at(const RefineState& S, const double* x, RefineTrial& T) {
     const double v[3] = {x[0], x[1], x[2]}, w[3] = {x[3], x[4], x[5]};
     double dR[9], V[9], Ra[3], Vv[3];
     so3_exp(w, dR);
     left_jac(w, V);
-    mat3_mul(dR, S.R0, S.R);
+    mat3_mul(dR, S.R0, T.R);
     mat3_vec(S.R0, S.a, Ra);
     mat3_vec(V, v, Vv);
     double dRa[3];
     mat3_vec(dR, Ra, dRa);
     for (int i = 0; i < 3; ++i) {
-        S.p[i] = S.p0[i] + Vv[i] + Ra[i] - dRa[i];
-        S.c[i] = S.p0[i] + Vv[i] + Ra[i];
+        T.p[i] = S.p0[i] + Vv[i] + Ra[i] - dRa[i];
+        T.c[i] = S.p0[i] + Vv[i] + Ra[i];
     }
-    for (int i = 0; i < 9; ++i) S.V[i] = V[i];
+    for (int i = 0; i < 9; ++i) T.V[i] = V[i];
     // D = d(V(w) v)/dw by central differences (step 1e-7)
     const double hh = 1e-7;
     for (int j = 0; j < 3; ++j) {
@@ -238,115 +255,380 @@ __device__ void pose_at(RefineState& S, const double* x) {
         left_jac(wm, Vm);
         mat3_vec(Vp, v, a);
         mat3_vec(Vm, v, b);
-        for (int i = 0; i < 3; ++i) S.D[3 * i + j] = (a[i] - b[i]) / (2 * hh);
+        for (int i = 0; i < 3; ++i) T.D[3 * i + j] = (a[i] - b[i]) / (2 * hh);
     }
 }
 
-__global__ void k_ref_pose(RefineState* __restrict__ st, int K) {
+__global__ void k_ref_start(const double* __restrict__ init, int K, const double* __restrict__ anchor, double mu0,
+                            RefineState* __restrict__ st, RefineTrial* __restrict__ tr, int* __restrict__ counters,
+                            int* __restrict__ pair_count) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= K || st[k].status == 2) return;
-    pose_at(st[k], st[k].xe);
+    if (k == 0) {
+        counters[0] = K;
+        counters[1] = 0;
+        *pair_count = 0;
+    }
+    if (k >= K) return;
+    RefineState& S = st[k];
+    const double* P = init + 7 * k;
+    quat_mat(P[0], P[1], P[2], P[3], S.R0);
+    for (int a = 0; a < 3; ++a) {
+        S.p0[a] = P[4 + a];
+        S.a[a] = anchor[a];
+    }
+    for (int j = 0; j < 6; ++j) S.xi[j] = 0.0;
+    S.mu = mu0;
+    S.it = 0;
+    S.status = 0;
+    // the first round evaluates xi = 0 alone
+    for (int j = 0; j < REF_TMAX; ++j) tr[k * REF_TMAX + j].valid = 0;
+    RefineTrial& T = tr[k * REF_TMAX];
+    for (int j = 0; j < 6; ++j) T.xe[j] = T.step[j] = 0.0;
+    T.mu = mu0;
+    pose_at(S, T.xe, T);
+    T.valid = 1;
 }
 
-// One thread per (start, probe pose): smallest signed distance over the faces
-// kept by the bounding-sphere test, by branch and bound (a face whose lower
-// bound f_p(centroid) - radius exceeds the best vertex value cannot hold the
-// minimum), ties to the lowest face index.
-__global__ __launch_bounds__(64) void k_ref_query(const RefineState* __restrict__ st, int K, RefineGeometry geo,
-                                                  const float* __restrict__ poses, int N, RefineConst c,
-                                                  RefineHit* __restrict__ hits) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= K * N) return;
-    const int k = q / N, i = q - k * N;
-    const RefineState& S = st[k];
-    if (S.status == 2) return;
+// ------------------------------------------------- distance query (Sec. V-B)
+//
+// Three passes per round:
+//   k_ref_cull     one thread per (start, probe pose): the body -> probe frame,
+//                  the bounding-sphere tests down to the faces, and per kept
+//                  face the bounds ub (best vertex value) and lb (supporting
+//                  planes of the convex f_p at the vertices).  Faces with lb
+//                  above the best ub cannot hold the minimum; faces whose bounds
+//                  meet are settled at their best vertex; the rest go to a pair
+//                  list for a golden-section search.
+//   k_ref_pairs    one thread per (query, face) pair: the face minimum, folded
+//                  into the query's key (value, face index) by atomicMin, so
+//                  the order of the pairs does not matter.
+//   k_ref_resolve  one thread per query: the winning face's witness, the
+//                  normal and the world coordinates.
+
+// orderable 64-bit key: float value bits (monotone), then the face index
+__device__ unsigned long long face_key(float v, int idx) {
+    unsigned int b = __float_as_uint(v);
+    b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+    return ((unsigned long long)b << 32) | (unsigned int)idx;
+}
+
+__device__ float key_value(unsigned long long key) {
+    unsigned int b = (unsigned int)(key >> 32);
+    b = (b & 0x80000000u) ? (b & 0x7fffffffu) : ~b;
+    return __uint_as_float(b);
+}
+
+struct FaceBounds {
+    float3 u0, u1, u2;
+    float lb, ub;
+    int vbest;
+};
+
+// ub: the best vertex value; lb = max_j [f(v_j) + min_k g_j . (v_k - v_j)]
+// (exact where f_p is linear on the face, e.g. under the flat tip disk)
+__device__ FaceBounds face_bounds(const Xf& X, const float4& a0, const float4& a1, const float4& a2, float r, float L) {
+    FaceBounds B;
+    B.u0 = X.apply(a0.x, a0.y, a0.z);
+    B.u1 = X.apply(a0.w, a1.x, a1.y);
+    B.u2 = X.apply(a1.z, a1.w, a2.x);
+    float3 g0, g1, g2;
+    const float f0 = sdf_grad_f(B.u0, r, L, g0), f1 = sdf_grad_f(B.u1, r, L, g1), f2 = sdf_grad_f(B.u2, r, L, g2);
+    const float3 d01 = make_float3(B.u1.x - B.u0.x, B.u1.y - B.u0.y, B.u1.z - B.u0.z);
+    const float3 d02 = make_float3(B.u2.x - B.u0.x, B.u2.y - B.u0.y, B.u2.z - B.u0.z);
+    const float3 d12 = make_float3(B.u2.x - B.u1.x, B.u2.y - B.u1.y, B.u2.z - B.u1.z);
+    const float l0 = f0 + fminf(0.0f, fminf(dot3(g0, d01), dot3(g0, d02)));
+    const float l1 = f1 + fminf(0.0f, fminf(-dot3(g1, d01), dot3(g1, d12)));
+    const float l2 = f2 + fminf(0.0f, fminf(-dot3(g2, d02), -dot3(g2, d12)));
+    B.lb = fmaxf(l0, fmaxf(l1, l2));
+    B.ub = f0;
+    B.vbest = 0;
+    if (f1 < B.ub) { B.ub = f1; B.vbest = 1; }
+    if (f2 < B.ub) { B.ub = f2; B.vbest = 2; }
+    return B;
+}
+
+__device__ Tri make_tri(const FaceBounds& B, float r, float L) {
+    Tri T;
+    T.p0 = B.u0;
+    T.e1 = make_float3(B.u1.x - B.u0.x, B.u1.y - B.u0.y, B.u1.z - B.u0.z);
+    T.e2 = make_float3(B.u2.x - B.u0.x, B.u2.y - B.u0.y, B.u2.z - B.u0.z);
+    T.r = r;
+    T.L = L;
+    return T;
+}
+
+// minimum over one face: the best vertex when the bounds meet, else golden
+__device__ float face_minimum(const FaceBounds& B, const Tri& T, float& s, float& t) {
+    if (B.ub - B.lb <= VERTEX_GAP) {
+        s = B.vbest == 1 ? 1.0f : 0.0f;
+        t = B.vbest == 2 ? 1.0f : 0.0f;
+        return B.ub;
+    }
+    return face_min(T, s, t);
+}
+
+__device__ Xf load_xf(const float* __restrict__ xf, int q) {
+    Xf X;
+    for (int j = 0; j < 9; ++j) X.a[j] = xf[12 * q + j];
+    for (int j = 0; j < 3; ++j) X.c[j] = xf[12 * q + 9 + j];
+    return X;
+}
+
+__device__ __forceinline__ bool sphere_kept(const Xf& X, const float4& sp, float r, float L, float cull) {
+    const float3 u = X.apply(sp.x, sp.y, sp.z);
+    return sdf_f(u.x, u.y, u.z, r, L) < sp.w + cull;
+}
+
+// every kept face in hierarchy order: fn(slot, a0, a1, a2, a3)
+template <class Fn>
+__device__ void for_kept_faces(const Xf& X, const RefineGeometry& geo, float r, float L, float cull, Fn&& fn) {
+    for (int tn = 0; tn < geo.n_top; ++tn) {
+        if (!sphere_kept(X, geo.top[tn], r, L, cull)) continue;
+        const int2 cr = geo.top_range[tn];
+        for (int cl = cr.x; cl < cr.x + cr.y; ++cl) {
+            if (!sphere_kept(X, geo.cluster[cl], r, L, cull)) continue;
+            const int2 fr = geo.cluster_range[cl];
+            for (int f = fr.x; f < fr.x + fr.y; ++f) {
+                const float4 a2 = geo.face[4 * f + 2], a3 = geo.face[4 * f + 3];
+                const float3 u = X.apply(a2.y, a2.z, a2.w);
+                if (!(sdf_f(u.x, u.y, u.z, r, L) < a3.x + cull)) continue;
+                fn(f, geo.face[4 * f], geo.face[4 * f + 1], a2, a3);
+            }
+        }
+    }
+}
+
+__device__ void probe_frame(const float* __restrict__ poses, int i, double* Ri, double* pi) {
     const float* P = poses + 7 * i;
-    double Ri[9];
     quat_mat(P[0], P[1], P[2], P[3], Ri);
-    const double pi[3] = {P[4], P[5], P[6]};
+    pi[0] = P[4];
+    pi[1] = P[5];
+    pi[2] = P[6];
+}
+
+__global__ void k_ref_reset(int* __restrict__ pair_count) { *pair_count = 0; }
+
+__device__ __forceinline__ float wave_min_f(float v) {
+    for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned lo = __shfl_xor((unsigned)(v & 0xffffffffu), off, 64);
+        const unsigned hi = __shfl_xor((unsigned)(v >> 32), off, 64);
+        const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+constexpr int CULL_WAVES = 4;  // queries per 256-thread block, one wavefront each
+
+// Kept faces of one query, spread over the lanes of its wavefront: the
+// cluster spheres are tested 64 at a time, then each kept cluster's faces
+// (at most REF_FANOUT = 32) take half a wavefront.  fn(lane_has_face, slot, a0..a3)
+// is called by every lane at the same points (uniform control flow).
+template <class Fn>
+__device__ void wave_kept_faces(const Xf& X, const RefineGeometry& geo, int n_cluster, float r, float L, float cull,
+                                int lane, Fn&& fn) {
+    for (int c0 = 0; c0 < n_cluster; c0 += 64) {
+        const int cl = c0 + lane;
+        const bool keep = cl < n_cluster && sphere_kept(X, geo.cluster[cl], r, L, cull);
+        unsigned long long mask = __ballot(keep);
+        while (mask) {
+            const int a = __ffsll((long long)mask) - 1;
+            mask &= mask - 1;
+            int b = -1;
+            if (mask) {
+                b = __ffsll((long long)mask) - 1;
+                mask &= mask - 1;
+            }
+            const int mine = lane < 32 ? a : b;
+            bool has = false;
+            int f = 0;
+            float4 a0 = make_float4(0, 0, 0, 0), a1 = a0, a2 = a0, a3 = a0;
+            if (mine >= 0) {
+                const int2 fr = geo.cluster_range[c0 + mine];
+                if ((lane & 31) < fr.y) {
+                    f = fr.x + (lane & 31);
+                    a2 = geo.face[4 * f + 2];
+                    a3 = geo.face[4 * f + 3];
+                    const float3 u = X.apply(a2.y, a2.z, a2.w);
+                    has = sdf_f(u.x, u.y, u.z, r, L) < a3.x + cull;
+                    if (has) {
+                        a0 = geo.face[4 * f];
+                        a1 = geo.face[4 * f + 1];
+                    }
+                }
+            }
+            fn(has, f, a0, a1, a2, a3);
+        }
+    }
+}
+
+__global__ __launch_bounds__(64 * CULL_WAVES) void k_ref_cull(const RefineTrial* __restrict__ tr, int K,
+                                                              RefineGeometry geo, int n_cluster,
+                                                              const float* __restrict__ poses, int N, RefineConst c,
+                                                              RefineScratch w, int* __restrict__ active) {
+    const int lane = threadIdx.x & 63;
+    const int q = blockIdx.x * CULL_WAVES + (threadIdx.x >> 6);
+    if (blockIdx.x == 0 && threadIdx.x == 0) active[0] = 0;  // counted again by k_ref_decide
+    if (q >= K * N) return;  // whole wavefronts
+    const int k = q / N, i = q - k * N;
+    const RefineTrial& S = tr[k];
+    if (!S.valid) return;
+    double Ri[9], pi[3];
+    probe_frame(poses, i, Ri, pi);
     Xf X;
     for (int a = 0; a < 3; ++a) {
         for (int b = 0; b < 3; ++b)
             X.a[3 * a + b] = (float)(Ri[a] * S.R[b] + Ri[3 + a] * S.R[3 + b] + Ri[6 + a] * S.R[6 + b]);
         X.c[a] = (float)(Ri[a] * (S.p[0] - pi[0]) + Ri[3 + a] * (S.p[1] - pi[1]) + Ri[6 + a] * (S.p[2] - pi[2]));
     }
-    const float r = c.r, L = c.L, cull = c.cull;
-    auto sdf_body = [&](float bx, float by, float bz) {
-        const float3 u = X.apply(bx, by, bz);
-        return sdf_f(u.x, u.y, u.z, r, L);
-    };
+    if (lane < 12) w.xf[12 * q + lane] = lane < 9 ? X.a[lane] : X.c[lane - 9];
+    if (lane == 0) w.qst[q] = make_float2(-1.0f, -1.0f);
+    const float r = c.r, L = c.L;
 
-    // pass 1: best vertex value over the kept faces
+    // pass 1: the best vertex value over the kept faces
     float best_ub = INFINITY;
-    int kept = 0;
-    for (int tn = 0; tn < geo.n_top; ++tn) {
-        const float4 sp = geo.top[tn];
-        if (!(sdf_body(sp.x, sp.y, sp.z) < sp.w + cull)) continue;
-        const int2 cr = geo.top_range[tn];
-        for (int cl = cr.x; cl < cr.x + cr.y; ++cl) {
-            const float4 cs = geo.cluster[cl];
-            if (!(sdf_body(cs.x, cs.y, cs.z) < cs.w + cull)) continue;
-            const int2 fr = geo.cluster_range[cl];
-            for (int f = fr.x; f < fr.x + fr.y; ++f) {
-                const float4 a0 = geo.face[4 * f], a1 = geo.face[4 * f + 1], a2 = geo.face[4 * f + 2],
-                             a3 = geo.face[4 * f + 3];
-                if (!(sdf_body(a2.y, a2.z, a2.w) < a3.x + cull)) continue;
-                ++kept;
-                const float v = fminf(sdf_body(a0.x, a0.y, a0.z),
-                                      fminf(sdf_body(a0.w, a1.x, a1.y), sdf_body(a1.z, a1.w, a2.x)));
-                best_ub = fminf(best_ub, v);
-            }
+    bool any = false;
+    wave_kept_faces(X, geo, n_cluster, r, L, c.cull, lane,
+                    [&](bool has, int, const float4& a0, const float4& a1, const float4& a2, const float4&) {
+                        if (has) {
+                            any = true;
+                            best_ub = fminf(best_ub, face_bounds(X, a0, a1, a2, r, L).ub);
+                        }
+                    });
+    if (!__ballot(any)) {
+        if (lane == 0) {
+            w.qkey[q] = ~0ull;
+            w.qflag[q] = 0;
         }
+        return;
     }
+    best_ub = wave_min_f(best_ub);
+
+    // pass 2: settle faces whose bounds meet; queue the others for a search
+    unsigned long long best = ~0ull;
+    bool overflow = false;
+    wave_kept_faces(X, geo, n_cluster, r, L, c.cull, lane,
+                    [&](bool has, int f, const float4& a0, const float4& a1, const float4& a2, const float4& a3) {
+                        bool need = false;
+                        if (has) {
+                            const FaceBounds B = face_bounds(X, a0, a1, a2, r, L);
+                            if (B.lb <= best_ub + BOUND_SLACK) {
+                                if (B.ub - B.lb <= VERTEX_GAP) {
+                                    const unsigned long long key = face_key(B.ub, __float_as_int(a3.y));
+                                    best = key < best ? key : best;
+                                } else {
+                                    need = true;
+                                }
+                            }
+                        }
+                        const unsigned long long nm = __ballot(need);
+                        if (nm) {
+                            const int leader = __ffsll((long long)nm) - 1;
+                            int base = 0;
+                            if (lane == leader) base = atomicAdd(w.pair_count, __popcll(nm));
+                            base = __shfl(base, leader, 64);
+                            if (need) {
+                                const int slot = base + __popcll(nm & ((1ull << lane) - 1));
+                                if (slot < w.pair_cap) w.pairs[slot] = make_int2(q, f);
+                                else overflow = true;
+                            }
+                        }
+                    });
+    best = wave_min_u64(best);
+    const bool ovf = __ballot(overflow) != 0;
+    if (lane == 0) {
+        w.qkey[q] = best;
+        w.qflag[q] = ovf ? 2 : 1;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ref_pairs(RefineGeometry geo, RefineConst c, RefineScratch w) {
+    const int n = min(*w.pair_count, w.pair_cap);
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+        const int2 pr = w.pairs[j];
+        const Xf X = load_xf(w.xf, pr.x);
+        const int f = pr.y;
+        const FaceBounds B = face_bounds(X, geo.face[4 * f], geo.face[4 * f + 1], geo.face[4 * f + 2], c.r, c.L);
+        float s, t;
+        const float m = face_min(make_tri(B, c.r, c.L), s, t);
+        w.pres[j] = make_float4(m, s, t, 0.0f);
+        atomicMin(&w.qkey[pr.x], face_key(m, __float_as_int(geo.face[4 * f + 3].y)));
+    }
+}
+
+// the pair that holds its query's minimum hands over its barycentric witness
+__global__ __launch_bounds__(256) void k_ref_winner(RefineGeometry geo, RefineScratch w) {
+    const int n = min(*w.pair_count, w.pair_cap);
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+        const int2 pr = w.pairs[j];
+        const float4 res = w.pres[j];
+        if (face_key(res.x, __float_as_int(geo.face[4 * pr.y + 3].y)) == w.qkey[pr.x])
+            w.qst[pr.x] = make_float2(res.y, res.z);
+    }
+}
+
+__global__ __launch_bounds__(64) void k_ref_resolve(const RefineTrial* __restrict__ tr, int K, RefineGeometry geo,
+                                                    const float* __restrict__ poses, int N, RefineConst c,
+                                                    RefineScratch w, RefineHit* __restrict__ hits) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= K * N) return;
+    const int k = q / N, i = q - k * N;
+    if (!tr[k].valid) return;
     RefineHit out;
-    if (kept == 0) {
+    // the face that holds the best vertex value always passes the bounds test,
+    // so a query with kept faces has a key; an empty key is treated as none kept
+    const int flag = w.qflag[q] == 1 && w.qkey[q] == ~0ull ? 0 : w.qflag[q];
+    if (flag == 0) {
         out.dx = make_float4(c.eps, 0.0f, 0.0f, 0.0f);
         out.nf = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));
         hits[q] = out;
         return;
     }
-
-    // pass 2: minimise the faces whose lower bound does not exceed best_ub
+    const Xf X = load_xf(w.xf, q);
+    const float r = c.r, L = c.L;
     float best = INFINITY, bs = 0.0f, bt = 0.0f;
     int bidx = 0x7fffffff;
     Tri BT{};
-    BT.r = r;
-    BT.L = L;
-    for (int tn = 0; tn < geo.n_top; ++tn) {
-        const float4 sp = geo.top[tn];
-        if (!(sdf_body(sp.x, sp.y, sp.z) < sp.w + cull)) continue;
-        const int2 cr = geo.top_range[tn];
-        for (int cl = cr.x; cl < cr.x + cr.y; ++cl) {
-            const float4 cs = geo.cluster[cl];
-            if (!(sdf_body(cs.x, cs.y, cs.z) < cs.w + cull)) continue;
-            const int2 fr = geo.cluster_range[cl];
-            for (int f = fr.x; f < fr.x + fr.y; ++f) {
-                const float4 a0 = geo.face[4 * f], a1 = geo.face[4 * f + 1], a2 = geo.face[4 * f + 2],
-                             a3 = geo.face[4 * f + 3];
-                const float fc = sdf_body(a2.y, a2.z, a2.w);
-                if (!(fc < a3.x + cull)) continue;
-                if (fc - a3.x > best_ub + 1e-5f) continue;
-                const int idx = __float_as_int(a3.y);
-                const float3 u0 = X.apply(a0.x, a0.y, a0.z), u1 = X.apply(a0.w, a1.x, a1.y),
-                             u2 = X.apply(a1.z, a1.w, a2.x);
-                Tri T;
-                T.p0 = u0;
-                T.e1 = make_float3(u1.x - u0.x, u1.y - u0.y, u1.z - u0.z);
-                T.e2 = make_float3(u2.x - u0.x, u2.y - u0.y, u2.z - u0.z);
-                T.r = r;
-                T.L = L;
-                float s, t;
-                const float m = face_min(T, s, t);
-                if (m < best || (m == best && idx < bidx)) {
-                    best = m;
-                    bidx = idx;
-                    bs = s;
-                    bt = t;
-                    BT = T;
-                }
+    if (flag == 2) {
+        // the pair list overflowed: search this query's faces here
+        float best_ub = INFINITY;
+        for_kept_faces(X, geo, r, L, c.cull, [&](int, const float4& a0, const float4& a1, const float4& a2, const float4&) {
+            best_ub = fminf(best_ub, face_bounds(X, a0, a1, a2, r, L).ub);
+        });
+        for_kept_faces(X, geo, r, L, c.cull, [&](int, const float4& a0, const float4& a1, const float4& a2, const float4& a3) {
+            const FaceBounds B = face_bounds(X, a0, a1, a2, r, L);
+            if (B.lb > best_ub + BOUND_SLACK) return;
+            const Tri T = make_tri(B, r, L);
+            float s, t;
+            const float m = face_minimum(B, T, s, t);
+            const int idx = __float_as_int(a3.y);
+            if (m < best || (m == best && idx < bidx)) {
+                best = m; bidx = idx; bs = s; bt = t; BT = T;
             }
+        });
+    } else {
+        const unsigned long long key = w.qkey[q];
+        bidx = (int)(unsigned int)(key & 0xffffffffu);
+        best = key_value(key);
+        const int f = geo.slot_of[bidx];
+        const FaceBounds B = face_bounds(X, geo.face[4 * f], geo.face[4 * f + 1], geo.face[4 * f + 2], r, L);
+        BT = make_tri(B, r, L);
+        const float2 st2 = w.qst[q];
+        if (st2.x >= 0.0f) {  // found by a golden-section search
+            bs = st2.x;
+            bt = st2.y;
+        } else {              // settled at the face's best vertex
+            bs = B.vbest == 1 ? 1.0f : 0.0f;
+            bt = B.vbest == 2 ? 1.0f : 0.0f;
         }
     }
+    double Ri[9], pi[3];
+    probe_frame(poses, i, Ri, pi);
     const float3 u = make_float3(BT.p0.x + bs * BT.e1.x + bt * BT.e2.x, BT.p0.y + bs * BT.e1.y + bt * BT.e2.y,
                                  BT.p0.z + bs * BT.e1.z + bt * BT.e2.z);
     const float3 gl = witness_gradient(u, BT, bs, bt);
@@ -386,11 +668,48 @@ __device__ void proximity(double d, const RefineConst& c, double& s, double& ds,
 constexpr int RED_T = 128;
 constexpr int NACC = 28;  // J, grad (6), H upper triangle (21)
 
-__global__ __launch_bounds__(RED_T) void k_ref_reduce(const RefineState* __restrict__ st, const RefineHit* __restrict__ hits,
-                                                     int N, RefineConst c, RefineEval* __restrict__ ev) {
+// Cholesky solve of the SPD 6x6 system A x = b; false if A is not positive definite
+__device__ bool chol6(double* A, const double* b, double* x) {
+    for (int j = 0; j < 6; ++j) {
+        double s = A[6 * j + j];
+        for (int k = 0; k < j; ++k) s -= A[6 * j + k] * A[6 * j + k];
+        if (!(s > 0)) return false;
+        const double l = sqrt(s);
+        A[6 * j + j] = l;
+        for (int i = j + 1; i < 6; ++i) {
+            double t = A[6 * i + j];
+            for (int k = 0; k < j; ++k) t -= A[6 * i + k] * A[6 * j + k];
+            A[6 * i + j] = t / l;
+        }
+    }
+    double y[6];
+    for (int i = 0; i < 6; ++i) {
+        double t = b[i];
+        for (int k = 0; k < i; ++k) t -= A[6 * i + k] * y[k];
+        y[i] = t / A[6 * i + i];
+    }
+    for (int i = 5; i >= 0; --i) {
+        double t = y[i];
+        for (int k = i + 1; k < 6; ++k) t -= A[6 * k + i] * x[k];
+        x[i] = t / A[6 * i + i];
+    }
+    return true;
+}
+
+__device__ double maxabs6(const double* v) {
+    double m = 0;
+    for (int j = 0; j < 6; ++j) m = fmax(m, fabs(v[j]));
+    return m;
+}
+
+// One block per valid trial slot: J, grad J and the curvature in FP64 over
+// the probe poses in a fixed order.  counters[1] counts the evaluations.
+__global__ __launch_bounds__(RED_T) void k_ref_eval(const RefineTrial* __restrict__ tr, const RefineHit* __restrict__ hits,
+                                                   int N, RefineConst c, RefineEval* __restrict__ ev,
+                                                   int* __restrict__ counters) {
     const int k = blockIdx.x;
-    const RefineState& S = st[k];
-    if (S.status == 2) return;
+    const RefineTrial& S = tr[k];
+    if (!S.valid) return;
     __shared__ double red[NACC][RED_T];
     double V[9], D[9], cc[3];
     for (int j = 0; j < 9; ++j) {
@@ -437,118 +756,121 @@ __global__ __launch_bounds__(RED_T) void k_ref_reduce(const RefineState* __restr
         int o = 0;
         for (int a = 0; a < 6; ++a)
             for (int b = a; b < 6; ++b, ++o) E.H[o] = red[7 + o][0] + (a == b ? 2 * c.lambda : 0.0);
+        atomicAdd(&counters[1], 1);
     }
 }
 
-// Cholesky solve of the SPD 6x6 system A x = b; false if A is not positive definite
-__device__ bool chol6(double* A, const double* b, double* x) {
+// Trial step with damping mu from (xi, g, H): a coordinate at its bound whose
+// gradient points out of the box is held there (its row and column replaced
+// by the identity, its right-hand side zero); false if the system is not
+// positive definite.
+__device__ bool trial_step(const RefineState& S, double mu, const RefineConst& c, RefineTrial& T) {
+    bool act[6];
     for (int j = 0; j < 6; ++j) {
-        double s = A[6 * j + j];
-        for (int k = 0; k < j; ++k) s -= A[6 * j + k] * A[6 * j + k];
-        if (!(s > 0)) return false;
-        const double l = sqrt(s);
-        A[6 * j + j] = l;
-        for (int i = j + 1; i < 6; ++i) {
-            double t = A[6 * i + j];
-            for (int k = 0; k < j; ++k) t -= A[6 * i + k] * A[6 * j + k];
-            A[6 * i + j] = t / l;
-        }
+        const double b = j < 3 ? c.b_t : c.b_r;
+        act[j] = (S.xi[j] >= b - 1e-12 && S.g[j] < 0) || (S.xi[j] <= -b + 1e-12 && S.g[j] > 0);
     }
-    double y[6];
-    for (int i = 0; i < 6; ++i) {
-        double t = b[i];
-        for (int k = 0; k < i; ++k) t -= A[6 * i + k] * y[k];
-        y[i] = t / A[6 * i + i];
+    double A[36], rhs[6], step[6];
+    for (int a = 0; a < 6; ++a) {
+        for (int b = 0; b < 6; ++b) A[6 * a + b] = (act[a] || act[b]) ? 0.0 : S.H[6 * a + b];
+        A[6 * a + a] = act[a] ? 1.0 : A[6 * a + a] + mu * S.H[6 * a + a] + 1e-12;
+        rhs[a] = act[a] ? 0.0 : -S.g[a];
     }
-    for (int i = 5; i >= 0; --i) {
-        double t = y[i];
-        for (int k = i + 1; k < 6; ++k) t -= A[6 * k + i] * x[k];
-        x[i] = t / A[6 * i + i];
+    if (!chol6(A, rhs, step)) return false;
+    for (int j = 0; j < 6; ++j) {
+        T.step[j] = step[j];
+        T.xe[j] = clampd(S.xi[j] + step[j], j < 3 ? c.b_t : c.b_r);
     }
+    T.mu = mu;
     return true;
 }
 
-__device__ double maxabs6(const double* v) {
-    double m = 0;
-    for (int j = 0; j < 6; ++j) m = fmax(m, fabs(v[j]));
-    return m;
-}
-
-// next trial from (xi, g, H, mu); false when no positive-definite system is left
-__device__ bool make_trial(RefineState& S, const RefineConst& c) {
-    while (S.mu < 1e12) {
-        double A[36], rhs[6], step[6];
-        for (int a = 0; a < 6; ++a) {
-            for (int b = 0; b < 6; ++b) A[6 * a + b] = S.H[6 * a + b];
-            A[6 * a + a] += S.mu * S.H[6 * a + a] + 1e-12;
-            rhs[a] = -S.g[a];
-        }
-        if (chol6(A, rhs, step)) {
-            for (int j = 0; j < 6; ++j) {
-                S.step[j] = step[j];
-                S.xe[j] = clampd(S.xi[j] + step[j], j < 3 ? c.b_t : c.b_r);
-            }
-            S.status = 1;
-            return true;
-        }
-        S.mu *= 3.0;
-    }
-    return false;
-}
-
-// continue from an accepted point: projected-gradient test, iteration cap, trial
-__device__ void next_iteration(RefineState& S, const RefineConst& c) {
-    double pg = 0;
-    for (int j = 0; j < 6; ++j) {
-        const double b = j < 3 ? c.b_t : c.b_r;
-        pg = fmax(pg, fabs(S.xi[j] - clampd(S.xi[j] - S.g[j], b)));
-    }
-    if (pg <= c.tol_pg || S.it >= c.max_iters) {
-        S.status = 2;
-        return;
-    }
-    S.it += 1;
-    if (!make_trial(S, c)) S.status = 2;
-}
-
-__global__ void k_ref_step(RefineState* __restrict__ st, int K, const RefineEval* __restrict__ ev, RefineConst c,
-                           int* __restrict__ active) {
-    int mine = 0;
-    for (int k = threadIdx.x; k < K; k += blockDim.x) {
-        RefineState& S = st[k];
-        if (S.status != 2) {
-            const RefineEval& E = ev[k];
-            bool take = S.status == 0 || E.J < S.J;
-            if (take) {
-                const bool first = S.status == 0;
-                for (int j = 0; j < 6; ++j) {
-                    S.xi[j] = S.xe[j];
-                    S.g[j] = E.g[j];
-                }
-                S.J = E.J;
-                int o = 0;
-                for (int a = 0; a < 6; ++a)
-                    for (int b = a; b < 6; ++b, ++o) S.H[6 * a + b] = S.H[6 * b + a] = E.H[o];
-                if (!first) S.mu = fmax(S.mu / 3.0, 1e-12);
-                if (!first && maxabs6(S.step) <= c.tol_step) S.status = 2;
-                else next_iteration(S, c);
-            } else {
-                S.mu *= 3.0;
-                if (S.mu >= 1e12 || maxabs6(S.step) <= c.tol_step || !make_trial(S, c)) S.status = 2;
-            }
-        }
-        mine += S.status != 2;
-    }
-    // the number of unfinished starts, summed over the block (blockDim.x <= 1024)
-    __shared__ int part[16];
-    int v = mine;
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
-    __syncthreads();
+// One block per start (REF_TMAX or more threads).  Thread 0 replays the
+// damped Gauss-Newton decisions over the evaluated trials in the order the
+// sequential iteration would try them: the first trial that lowers J is
+// taken (mu = max(mu / 3, 1e-12)); a rejected trial multiplies mu by 3 and
+// ends the start when mu reaches 1e12 or its step was below tol_step.  At an
+// accepted point the projected-gradient test and the iteration cap apply.
+// Then the block's threads set up the next round's trials in parallel: one
+// after a first-try acceptance, two after an acceptance that needed a
+// rejection, REF_TMAX after a round of rejections.
+__global__ void k_ref_decide(RefineState* __restrict__ st, RefineTrial* __restrict__ tr,
+                             const RefineEval* __restrict__ ev, RefineConst c, int* __restrict__ pair_count,
+                             int* __restrict__ counters) {
+    const int k = blockIdx.x;
+    if (k == 0 && threadIdx.x == 0) *pair_count = 0;  // for the next round's queries
+    RefineState& S = st[k];
+    if (S.status == 2) return;
+    __shared__ int ntrial;
     if (threadIdx.x == 0) {
-        int sum = 0;
-        for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) sum += part[w];
-        *active = sum;
+        int next = 0;
+        int taken = -1;
+        bool stop = false;
+        double mu_next = S.mu;
+        for (int j = 0; j < REF_TMAX; ++j) {
+            const RefineTrial& T = tr[k * REF_TMAX + j];
+            if (!T.valid) break;
+            const RefineEval& E = ev[k * REF_TMAX + j];
+            if (S.status == 0 || E.J < S.J) {
+                taken = j;
+                break;
+            }
+            mu_next = 3.0 * T.mu;
+            if (mu_next >= 1e12 || maxabs6(T.step) <= c.tol_step) {
+                stop = true;
+                break;
+            }
+        }
+        if (taken >= 0) {
+            const RefineTrial& T = tr[k * REF_TMAX + taken];
+            const RefineEval& E = ev[k * REF_TMAX + taken];
+            const bool first = S.status == 0;
+            for (int j = 0; j < 6; ++j) {
+                S.xi[j] = T.xe[j];
+                S.g[j] = E.g[j];
+            }
+            S.J = E.J;
+            int o = 0;
+            for (int a = 0; a < 6; ++a)
+                for (int b = a; b < 6; ++b, ++o) S.H[6 * a + b] = S.H[6 * b + a] = E.H[o];
+            if (!first) S.mu = fmax(T.mu / 3.0, 1e-12);
+            S.status = 1;
+            if (!first && maxabs6(T.step) <= c.tol_step) {
+                S.status = 2;
+            } else {
+                double pg = 0;
+                for (int j = 0; j < 6; ++j) {
+                    const double b = j < 3 ? c.b_t : c.b_r;
+                    pg = fmax(pg, fabs(S.xi[j] - clampd(S.xi[j] - S.g[j], b)));
+                }
+                if (pg <= c.tol_pg || S.it >= c.max_iters) {
+                    S.status = 2;
+                } else {
+                    S.it += 1;
+                    next = taken == 0 ? 1 : 2;
+                }
+            }
+        } else if (stop || !tr[k * REF_TMAX].valid) {
+            S.status = 2;    // (no valid trial: no positive-definite system was left)
+        } else {
+            S.mu = mu_next;  // every trial of the round was rejected
+            next = REF_TMAX;
+        }
+        ntrial = next;
+        if (next > 0) atomicAdd(&counters[0], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < REF_TMAX) {
+        RefineTrial& T = tr[k * REF_TMAX + threadIdx.x];
+        T.valid = 0;
+        if ((int)threadIdx.x < ntrial) {
+            double mu = S.mu;
+            for (unsigned j = 0; j < threadIdx.x; ++j) mu *= 3.0;
+            if (mu < 1e12 && trial_step(S, mu, c, T)) {
+                pose_at(S, T.xe, T);
+                T.valid = 1;
+            }
+        }
     }
 }
 
@@ -556,9 +878,10 @@ __global__ void k_ref_finish(const RefineState* __restrict__ st, int K, double* 
                              double* __restrict__ out_J, int32_t* __restrict__ out_iters) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= K) return;
-    RefineState S = st[k];
-    pose_at(S, S.xi);
-    const double* R = S.R;
+    const RefineState& S = st[k];
+    RefineTrial T;
+    pose_at(S, S.xi, T);
+    const double* R = T.R;
     double w, x, y, z;
     const double tr = R[0] + R[4] + R[8];
     if (tr > 0) {
@@ -577,7 +900,7 @@ __global__ void k_ref_finish(const RefineState* __restrict__ st, int K, double* 
     const double sg = w < 0 ? -1.0 : 1.0;
     double* o = out_poses + 7 * k;
     o[0] = sg * w; o[1] = sg * x; o[2] = sg * y; o[3] = sg * z;
-    o[4] = S.p[0]; o[5] = S.p[1]; o[6] = S.p[2];
+    o[4] = T.p[0]; o[5] = T.p[1]; o[6] = T.p[2];
     if (out_J) out_J[k] = S.J;
     if (out_iters) out_iters[k] = S.it;
 }
@@ -585,18 +908,33 @@ __global__ void k_ref_finish(const RefineState* __restrict__ st, int K, double* 
 }  // namespace
 
 hipError_t refine_start(const double* init_poses, int K, const double* anchor, const RefineConst& c, RefineState* st,
-                        hipStream_t s) {
-    k_ref_start<<<(K + 63) / 64, 64, 0, s>>>(init_poses, K, anchor, c.mu0, st);
+                        RefineTrial* tr, int* counters, const RefineScratch& w, hipStream_t s) {
+    k_ref_start<<<(K + 63) / 64, 64, 0, s>>>(init_poses, K, anchor, c.mu0, st, tr, counters, w.pair_count);
     return hipGetLastError();
 }
 
-hipError_t refine_round(RefineState* st, int K, const RefineGeometry& geo, const float* poses, int n_poses,
-                        const RefineConst& c, RefineHit* hits, RefineEval* ev, int* active, hipStream_t s) {
-    k_ref_pose<<<(K + 63) / 64, 64, 0, s>>>(st, K);
-    const long long q = (long long)K * n_poses;
-    k_ref_query<<<(unsigned)((q + 63) / 64), 64, 0, s>>>(st, K, geo, poses, n_poses, c, hits);
-    k_ref_reduce<<<K, RED_T, 0, s>>>(st, hits, n_poses, c, ev);
-    k_ref_step<<<1, 256, 0, s>>>(st, K, ev, c, active);
+// distance queries of `slots` trial poses x N probe poses: cull, pair
+// searches, winners, resolve
+static void launch_queries(const RefineTrial* tr, int slots, const RefineGeometry& geo, const float* poses, int N,
+                           const RefineConst& c, const RefineScratch& w, RefineHit* hits, int* counters,
+                           hipStream_t s) {
+    const long long q = (long long)slots * N;
+    k_ref_cull<<<(unsigned)((q + CULL_WAVES - 1) / CULL_WAVES), 64 * CULL_WAVES, 0, s>>>(tr, slots, geo, geo.n_cluster,
+                                                                                      poses, N, c, w, counters);
+    // about 3 searches per query are needed; the kernels stride over the rest
+    const unsigned pb = (unsigned)std::min<long long>(2048, std::max<long long>(1, (4 * q + 255) / 256));
+    k_ref_pairs<<<pb, 256, 0, s>>>(geo, c, w);
+    k_ref_winner<<<pb, 256, 0, s>>>(geo, w);
+    k_ref_resolve<<<(unsigned)((q + 63) / 64), 64, 0, s>>>(tr, slots, geo, poses, N, c, w, hits);
+}
+
+hipError_t refine_round(RefineState* st, RefineTrial* tr, int K, const RefineGeometry& geo, const float* poses,
+                        int n_poses, const RefineConst& c, const RefineScratch& w, RefineHit* hits, RefineEval* ev,
+                        int* counters, hipStream_t s) {
+    const int slots = K * REF_TMAX;
+    launch_queries(tr, slots, geo, poses, n_poses, c, w, hits, counters, s);
+    k_ref_eval<<<slots, RED_T, 0, s>>>(tr, hits, n_poses, c, ev, counters);
+    k_ref_decide<<<K, 64, 0, s>>>(st, tr, ev, c, w.pair_count, counters);
     return hipGetLastError();
 }
 
@@ -606,8 +944,10 @@ hipError_t refine_finish(const RefineState* st, int K, double* out_poses, double
     return hipGetLastError();
 }
 
-hipError_t refine_query_only(RefineState* st, const RefineGeometry& geo, const float* poses, int n_poses,
-                             const RefineConst& c, RefineHit* hits, hipStream_t s) {
-    k_ref_query<<<(n_poses + 63) / 64, 64, 0, s>>>(st, 1, geo, poses, n_poses, c, hits);
+hipError_t refine_query_only(const RefineTrial* tr, const RefineGeometry& geo, const float* poses, int n_poses,
+                             const RefineConst& c, const RefineScratch& w, RefineHit* hits, int* counters,
+                             hipStream_t s) {
+    k_ref_reset<<<1, 1, 0, s>>>(w.pair_count);
+    launch_queries(tr, 1, geo, poses, n_poses, c, w, hits, counters, s);
     return hipGetLastError();
 }

@@ -217,3 +217,22 @@ def test_refine_abi_errors(cfg1):
         assert torch.isfinite(out).all()
     finally:
         rd.register_free(h)
+
+
+def test_refine_config3_from_search_peak_matches_oracle():
+    """The 128^3 workload (2000 noisy probe poses, 20480 faces): the search's
+    best rotation refined on the GPU and by the oracle."""
+    rd = _lib()
+    p = synth.config_problem(3, 0)
+    h = _handle(rd, p)
+    try:
+        sc, _, po = rd.score_rotations(h)
+        top = rd.register_top_k(h, sc, 1).cpu().numpy()
+        q = po.cpu().numpy()[top[0]]
+    finally:
+        rd.register_free(h)
+    start = (synth.quat_to_mat(q[:4]), q[4:])
+    (ce, ang, Jg, Jo, itg, ito), = _refine_pair(rd, p, [start])
+    print(f"\nanchor {ce:.2e} mm, angle {ang:.2e} deg, J gpu {Jg:.6f} oracle {Jo:.6f}, iters {itg}/{ito}")
+    assert ce <= POS_TOL and ang <= ANG_TOL
+    assert abs(Jg - Jo) <= 1e-3 * abs(Jo)

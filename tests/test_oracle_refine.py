@@ -237,3 +237,32 @@ def test_noise_free_recovery_of_a_known_pose(small_problem):
     re = np.degrees(Rotation.from_matrix(res.R.T @ Rg).magnitude())
     assert ce < 1e-5 and re < 1e-4
     assert res.J == pytest.approx(-float(p.contact.sum()), abs=1e-3)
+
+
+def test_lm_step_free_set_matches_reduced_solve():
+    """The active-set step equals the solve of the free coordinates' own block
+    (written here as a sub-matrix solve, not by the row/column replacement the
+    oracle uses), is zero on the active ones, and is the full solve with none."""
+    g = np.random.default_rng(5)
+    B = g.normal(size=(6, 6))
+    H = B @ B.T + 0.1 * np.eye(6)
+    grad = g.normal(size=6)
+    mu = 0.3
+    full = np.linalg.solve(H + mu * np.diag(np.diag(H)) + 1e-12 * np.eye(6), -grad)
+    assert np.allclose(Rf.lm_step(H, grad, mu, np.zeros(6, bool)), full, rtol=1e-12, atol=1e-14)
+    act = np.array([False, True, False, False, True, False])
+    free = ~act
+    Hf = H[np.ix_(free, free)]
+    ref = np.linalg.solve(Hf + mu * np.diag(np.diag(Hf)) + 1e-12 * np.eye(free.sum()), -grad[free])
+    st = Rf.lm_step(H, grad, mu, act)
+    assert np.all(st[act] == 0.0)
+    assert np.allclose(st[free], ref, rtol=1e-12, atol=1e-14)
+
+
+def test_active_bounds_rule():
+    prm = Rf.RefineParams()
+    xi = np.array([prm.b_t, -prm.b_t, 0.1, prm.b_r, -prm.b_r, prm.b_r])
+    g = np.array([-1.0, 1.0, -1.0, 1.0, -1.0, 0.0])
+    # at +b with descent pushing up (g < 0), at -b pushing down (g > 0): held;
+    # interior, or gradient pointing back inside, or zero: free
+    assert Rf.active_bounds(xi, g, prm).tolist() == [True, True, False, False, False, False]
