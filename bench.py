@@ -123,6 +123,7 @@ def main():
         info["starts"] = starts.cpu().numpy()
         info["iters"] = res[2].cpu().numpy()
         info["J"] = res[1].cpu().numpy()
+        info.update(rd.register_refine_stats(h))
         rd.register_free(h)
         return sc, top
 
@@ -174,12 +175,12 @@ def main():
         "score_phase": {"ms_per_step": score_s * 1e3, "rotations_per_s": M / score_s,
                         "model_GBps": model_bytes / score_s / 1e9},
         "kernels": kern,
-        "refine": {"ms_per_step": float(np.mean(refine_s)) * 1e3, "starts": K_TOP,
-                   "accepted_steps": [int(x) for x in info["iters"]], "best_J": float(np.min(info["J"]))},
+        "refine": {"ms_per_step": float(np.mean(refine_s)) * 1e3, "starts": K_TOP, "rounds": info["rounds"],
+                   "evaluations": info["evaluations"], "accepted_steps": [int(x) for x in info["iters"]],
+                   "best_J": float(np.min(info["J"]))},
     }
     if args.cpu_sample > 0:
-        evals = int(sum(1 + 2 * int(x) for x in info["iters"]))
-        out["cpu_baseline"] = cpu_baseline(p, args.cpu_sample, info["starts"], evals)
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_sample, info["starts"], int(info["evaluations"]))
     print(json.dumps(out), flush=True)
 
 
