@@ -226,6 +226,85 @@ int register_refine_stats(reg_handle* h, int64_t* rounds, int64_t* evaluations);
  * change s, s' or s''.  Synchronous. */
 int register_debug_distance(reg_handle* h, const double* R, const double* p, float* out);
 
+/* ------------------------------------------------------------------ serving
+ *
+ * A server runs whole registrations -- object grid and spectrum, swept
+ * occupancy, the global search over every SO(3) sample (Sec. IV), the top-K
+ * peaks and their SE(3) refinement (Sec. V) -- for requests submitted from
+ * any thread.  Requests are admitted in arrival order when a worker slot is
+ * free and their device footprint fits beside the registrations in flight;
+ * each slot has its own HIP stream, so admitted registrations overlap on the
+ * device and a request arriving while others run starts as soon as a slot and
+ * memory free up.  Objects (mesh + canvas + object-grid thresholds) stay
+ * resident in a cache keyed by the request's object_id: a later request with
+ * the same key skips the object grid and its spectrum.  A registration's
+ * results do not depend on what else runs beside it.
+ */
+typedef struct reg_server reg_server;
+typedef uint64_t reg_ticket;
+
+typedef struct {
+    int64_t hbm_budget_bytes;   /* device bytes for registrations in flight; 0: 3/4 of free memory minus the cache */
+    int32_t max_inflight;       /* worker slots (concurrent registrations); 0: 4 */
+    int32_t mode;               /* 0: continuous, 1: serial (one registration at a time) */
+    int64_t cache_bytes;        /* object cache budget (least recently used objects evicted); 0: 4 GiB */
+    int32_t fake;               /* test hook: 1 = no device work, a registration takes fake_us_per_rotation per rotation */
+    double fake_us_per_rotation;
+} reg_server_cfg;
+
+/* All arrays in HOST memory; they are copied before register_submit returns. */
+typedef struct {
+    reg_mesh mesh;
+    int64_t object_id;          /* cache key of the object (>= 0), or -1 not to cache it */
+    reg_probe probe;
+    const float* poses;         /* n_poses x 7 */
+    int32_t n_poses;
+    const float* so3;           /* n_rot x 4 */
+    int32_t n_rot;
+    reg_grid_spec grid;
+    reg_params params;          /* zero fields take the defaults */
+    int32_t top_k;              /* peaks kept, 1..16 (0: 16) */
+    int32_t refine;             /* 1: refine the top_k peaks */
+} reg_request;
+
+typedef struct {
+    int32_t status;             /* REG_OK or the error of the registration */
+    int32_t n_top;
+    float best_score;           /* the largest search score */
+    double best_pose[7];        /* refined pose of lowest J (refine = 1), else the best search pose */
+    double best_J;
+    int32_t top_rot[16];        /* rotation indices of the peaks, score descending */
+    float top_score[16];
+    double top_pose[16 * 7];    /* search poses of the peaks */
+    double refined_pose[16 * 7];
+    double refined_J[16];
+    int64_t t_submit_ns, t_admit_ns, t_start_ns, t_end_ns;  /* steady clock */
+    int64_t footprint_bytes;    /* device bytes reserved for the registration */
+    char error[128];
+} reg_result;
+
+typedef struct {
+    int64_t queued, running, done;
+    int64_t in_use_bytes, budget_bytes;
+    int64_t cache_hits, cache_misses, cache_bytes, cached_objects;
+} reg_server_stats;
+
+/* Errors: REG_EINVAL, REG_EDEVICE (stream creation), REG_ENOMEM. */
+int register_server_create(const reg_server_cfg* cfg, reg_server** out);
+/* Cancels queued requests (REG_ECANCELED), waits for running ones, frees all. */
+void register_server_destroy(reg_server* s);
+/* Queues a registration.  Errors: REG_EINVAL, REG_EBUSY (needs more than the
+ * whole budget), REG_ECANCELED (server stopping). */
+int register_submit(reg_server* s, const reg_request* request, reg_ticket* out);
+/* The result if the registration has finished (the ticket is then released),
+ * else REG_EAGAIN.  Returns the registration's own status when it failed. */
+int register_poll(reg_server* s, reg_ticket t, reg_result* out);
+/* As register_poll, waiting up to timeout_ms (< 0: without limit). */
+int register_wait(reg_server* s, reg_ticket t, int64_t timeout_ms, reg_result* out);
+int register_server_stats(reg_server* s, reg_server_stats* out);
+/* message of the calling thread's last failing server call */
+const char* register_server_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,9 @@ _NAMES = {-1: "REG_EINVAL", -2: "REG_ENOMEM", -3: "REG_EDEVICE", -4: "REG_EBUSY"
 EXPORTS = ["register_init", "score_rotations", "register_top_k", "register_free", "register_last_error",
            "register_info", "register_debug_object_grid", "register_debug_swept", "register_debug_correlation",
            "register_set_grids", "register_set_timing", "register_get_timing", "register_search_stats",
-           "refine_se3", "register_debug_distance", "register_refine_stats"]
+           "refine_se3", "register_debug_distance", "register_refine_stats", "register_server_create",
+           "register_server_destroy", "register_submit", "register_poll", "register_wait", "register_server_stats",
+           "register_server_last_error"]
 
 
 class RegError(RuntimeError):
@@ -53,6 +55,32 @@ class reg_params(ctypes.Structure):
                 ("lambda_", ctypes.c_double), ("b_t", ctypes.c_double), ("b_r", ctypes.c_double),
                 ("eps", ctypes.c_double), ("max_iters", ctypes.c_int32), ("batch", ctypes.c_int32),
                 ("rescore", ctypes.c_int32)]
+
+
+class reg_server_cfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("cache_bytes", ctypes.c_int64), ("fake", ctypes.c_int32), ("fake_us_per_rotation", ctypes.c_double)]
+
+
+class reg_request(ctypes.Structure):
+    _fields_ = [("mesh", reg_mesh), ("object_id", ctypes.c_int64), ("probe", reg_probe), ("poses", ctypes.c_void_p),
+                ("n_poses", ctypes.c_int32), ("so3", ctypes.c_void_p), ("n_rot", ctypes.c_int32),
+                ("grid", reg_grid_spec), ("params", reg_params), ("top_k", ctypes.c_int32), ("refine", ctypes.c_int32)]
+
+
+class reg_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_top", ctypes.c_int32), ("best_score", ctypes.c_float),
+                ("best_pose", ctypes.c_double * 7), ("best_J", ctypes.c_double), ("top_rot", ctypes.c_int32 * 16),
+                ("top_score", ctypes.c_float * 16), ("top_pose", ctypes.c_double * 112),
+                ("refined_pose", ctypes.c_double * 112), ("refined_J", ctypes.c_double * 16),
+                ("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64), ("t_start_ns", ctypes.c_int64),
+                ("t_end_ns", ctypes.c_int64), ("footprint_bytes", ctypes.c_int64), ("error", ctypes.c_char * 128)]
+
+
+class reg_server_stats(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int64), ("running", ctypes.c_int64), ("done", ctypes.c_int64),
+                ("in_use_bytes", ctypes.c_int64), ("budget_bytes", ctypes.c_int64), ("cache_hits", ctypes.c_int64),
+                ("cache_misses", ctypes.c_int64), ("cache_bytes", ctypes.c_int64), ("cached_objects", ctypes.c_int64)]
 
 
 _lib = None
@@ -105,6 +133,20 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.register_debug_distance.argtypes = [p, p, p, p]
     L.register_refine_stats.restype = ctypes.c_int
     L.register_refine_stats.argtypes = [p, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.register_server_create.restype = ctypes.c_int
+    L.register_server_create.argtypes = [ctypes.POINTER(reg_server_cfg), ctypes.POINTER(p)]
+    L.register_server_destroy.restype = None
+    L.register_server_destroy.argtypes = [p]
+    L.register_submit.restype = ctypes.c_int
+    L.register_submit.argtypes = [p, ctypes.POINTER(reg_request), ctypes.POINTER(ctypes.c_uint64)]
+    L.register_poll.restype = ctypes.c_int
+    L.register_poll.argtypes = [p, ctypes.c_uint64, ctypes.POINTER(reg_result)]
+    L.register_wait.restype = ctypes.c_int
+    L.register_wait.argtypes = [p, ctypes.c_uint64, i64, ctypes.POINTER(reg_result)]
+    L.register_server_stats.restype = ctypes.c_int
+    L.register_server_stats.argtypes = [p, ctypes.POINTER(reg_server_stats)]
+    L.register_server_last_error.restype = ctypes.c_char_p
+    L.register_server_last_error.argtypes = []
     _lib = L
     return L
 
@@ -294,3 +336,85 @@ def register_refine_stats(h: Handle) -> dict:
     r, e = ctypes.c_int64(), ctypes.c_int64()
     _check(load_library().register_refine_stats(h.ptr, ctypes.byref(r), ctypes.byref(e)))
     return dict(rounds=r.value, evaluations=e.value)
+
+
+# ------------------------------------------------------------------ serving
+
+def _server_check(rc: int):
+    if rc != REG_OK:
+        raise RegError(rc, load_library().register_server_last_error().decode())
+
+
+def _result_dict(r: reg_result) -> dict:
+    k = r.n_top
+    return dict(status=r.status, n_top=k, best_score=r.best_score, best_pose=np.array(r.best_pose[:]),
+                best_J=r.best_J, top_rot=np.array(r.top_rot[:k]), top_score=np.array(r.top_score[:k]),
+                top_pose=np.array(r.top_pose[:7 * k]).reshape(k, 7),
+                refined_pose=np.array(r.refined_pose[:7 * k]).reshape(k, 7), refined_J=np.array(r.refined_J[:k]),
+                t_submit_ns=r.t_submit_ns, t_admit_ns=r.t_admit_ns, t_start_ns=r.t_start_ns, t_end_ns=r.t_end_ns,
+                footprint_bytes=r.footprint_bytes, error=r.error.decode())
+
+
+class Server:
+    """A registration server (see the serving section of the header)."""
+
+    def __init__(self, max_inflight: int = 4, mode: str = "continuous", hbm_budget_bytes: int = 0,
+                 cache_bytes: int = 0, fake_us_per_rotation: float | None = None):
+        L = load_library()
+        cfg = reg_server_cfg(hbm_budget_bytes, max_inflight, 1 if mode == "serial" else 0, cache_bytes,
+                             1 if fake_us_per_rotation is not None else 0, fake_us_per_rotation or 0.0)
+        self.ptr = ctypes.c_void_p()
+        _server_check(L.register_server_create(ctypes.byref(cfg), ctypes.byref(self.ptr)))
+
+    def submit(self, vertices, faces, touchable, poses, so3, n: int, h_mm: float, center=(0.0, 0.0, 0.0),
+               radius_mm: float = 0.5, length_mm: float = 8.0, object_id: int = -1, top_k: int = 16,
+               refine: bool = True, params: dict | None = None) -> int:
+        V = np.ascontiguousarray(vertices, dtype=np.float32)
+        F = np.ascontiguousarray(faces, dtype=np.int32)
+        T = None if touchable is None else np.ascontiguousarray(touchable, dtype=np.uint8)
+        P = np.ascontiguousarray(poses, dtype=np.float32)
+        Q = np.ascontiguousarray(so3, dtype=np.float32)
+        hp = lambda a: a.ctypes.data_as(ctypes.c_void_p).value if a is not None else None
+        prm = reg_params()
+        for k, v in (params or {}).items():
+            setattr(prm, "lambda_" if k == "lambda" else k, v)
+        rq = reg_request(reg_mesh(hp(V), V.shape[0], hp(F), F.shape[0], hp(T)), object_id,
+                         reg_probe(radius_mm, length_mm), hp(P), P.shape[0], hp(Q), Q.shape[0],
+                         reg_grid_spec(n, h_mm, (ctypes.c_double * 3)(*[float(c) for c in center])), prm, top_k,
+                         1 if refine else 0)
+        t = ctypes.c_uint64()
+        _server_check(load_library().register_submit(self.ptr, ctypes.byref(rq), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        """The result dict, or None while the registration runs."""
+        r = reg_result()
+        rc = load_library().register_poll(self.ptr, ticket, ctypes.byref(r))
+        if rc == REG_EAGAIN:
+            return None
+        _server_check(rc)
+        return _result_dict(r)
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        r = reg_result()
+        rc = load_library().register_wait(self.ptr, ticket, timeout_ms, ctypes.byref(r))
+        if rc == REG_EAGAIN:
+            return None
+        _server_check(rc)
+        return _result_dict(r)
+
+    def stats(self) -> dict:
+        st = reg_server_stats()
+        _server_check(load_library().register_server_stats(self.ptr, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in reg_server_stats._fields_}
+
+    def close(self):
+        if self.ptr:
+            load_library().register_server_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -7,11 +7,15 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "refine_kernels.h"
 #include "regdock.h"
+#include "runtime.h"
 #include "search_kernels.h"
 
 using namespace regdock;
@@ -34,7 +38,55 @@ int lattice_edge(int n) { return 2 * (int)std::ceil((std::sqrt(3.0) * n + 2.0) /
 
 }  // namespace
 
+// Everything derived from the object alone (mesh, canvas edge and spacing,
+// and the object-grid thresholds): the mesh, its anchor, the object grid O,
+// its spectrum conj(F(O))/n^3 with the exact low-frequency block, the nonzero
+// list of O, the twiddles and the refinement's bounding-sphere hierarchy.
+// Handles share it, so a serving cache keeps object spectra resident.
+struct ObjectData {
+    int n = 0, nv = 0, nf = 0;
+    double h = 0, tau_out1 = 0, tau_in1 = 0, rho = 0;
+    float* V = nullptr;
+    int32_t* F = nullptr;
+    uint8_t* touch = nullptr;
+    double* anchor = nullptr;
+    float* O = nullptr;
+    float* fo = nullptr;
+    float2* W = nullptr;
+    double2* Wlow = nullptr;
+    uint32_t* nz_idx = nullptr;
+    float* nz_val = nullptr;
+    int* nz_count = nullptr;
+    int* nz_bcount = nullptr;
+    int* nz_boff = nullptr;
+    float2* tw = nullptr;
+    double2* tw64 = nullptr;
+    bool geo_ready = false;
+    RefineGeometry geo{};
+    size_t bytes = 0;
+    std::vector<void*> owned;
+    template <class T>
+    hipError_t alloc(T** p, size_t count) {
+        void* q = nullptr;
+        const size_t b = count * sizeof(T) > 0 ? count * sizeof(T) : 1;
+        hipError_t e = hipMalloc(&q, b);
+        if (e == hipSuccess) {
+            owned.push_back(q);
+            bytes += b;
+            *p = (T*)q;
+        }
+        return e;
+    }
+    bool matches(int n_, double h_, const reg_params& p) const {
+        return n == n_ && h == h_ && tau_out1 == p.tau_out1 && tau_in1 == p.tau_in1 && rho == p.rho;
+    }
+    ~ObjectData() {
+        for (void* q : owned) (void)hipFree(q);
+    }
+};
+
 struct reg_handle {
+    std::shared_ptr<ObjectData> obj;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     bool poisoned = false;
@@ -84,10 +136,7 @@ struct reg_handle {
     double2* Wlow = nullptr;
     double2* Plow = nullptr;
     int* err = nullptr;
-    // refinement: bounding-sphere hierarchy of the mesh (built on first use)
-    // and per-start solver state
-    bool geo_ready = false;
-    RefineGeometry geo{};
+    // refinement solver state (the mesh hierarchy lives in the object)
     RefineState* rst = nullptr;
     RefineTrial* rtr = nullptr;
     RefineEval* rev = nullptr;
@@ -154,6 +203,16 @@ struct reg_handle {
         }                                                                                        \
     } while (0)
 
+#define OBJ_ALLOC_TRY(ob, ptr, count)                                                            \
+    do {                                                                                         \
+        hipError_t e_ = (ob)->alloc(&(ptr), (count));                                            \
+        if (e_ != hipSuccess) {                                                                  \
+            (void)hipGetLastError();                                                             \
+            return fail(REG_ENOMEM, "device allocation of %zu elements for %s failed: %s",       \
+                        (size_t)(count), #ptr, hipGetErrorString(e_));                           \
+        }                                                                                        \
+    } while (0)
+
 static void fill_defaults(reg_params& p) {
     if (p.tau_out1 <= 0) p.tau_out1 = 0.5;
     if (p.tau_in1 <= 0) p.tau_in1 = 0.2;
@@ -168,7 +227,19 @@ static void fill_defaults(reg_params& p) {
     if (p.max_iters <= 0) p.max_iters = 200;
 }
 
+// rotation batch per canvas edge recorded by the autotuner
+static std::mutex g_tune_mu;
+static std::map<int, int> g_tuned;
+
 static int default_batch(int n, size_t H, int n_rot) {
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(n);
+        if (it != g_tuned.end()) {
+            size_t need = ((size_t)n_rot + 7) / 8 * 8;
+            return (int)std::min<size_t>((size_t)it->second, need);
+        }
+    }
     // about 256 MB of spectrum work buffer, a multiple of 8 for the XCD mapping
     size_t b = (256u << 20) / (H * sizeof(float2));
     if (b < 8) b = 8;
@@ -195,6 +266,7 @@ static int build_object_derived(reg_handle* h) {
 // conservative.  Face centroid and radius follow the body-frame definition of
 // the bounding-sphere test (mean of the three vertices, largest vertex distance).
 static int build_refine_geometry(reg_handle* h) {
+    ObjectData* o = h->obj.get();
     const int nf = h->nf, nv = h->nv;
     std::vector<float> V(3 * (size_t)nv);
     std::vector<int32_t> F(3 * (size_t)nf);
@@ -298,12 +370,12 @@ static int build_refine_geometry(reg_handle* h) {
     float4 *d_face, *d_cl, *d_top;
     int2 *d_clr, *d_topr;
     int* d_slot;
-    ALLOC_TRY(h, d_slot, slot_of.size());
-    ALLOC_TRY(h, d_face, face.size());
-    ALLOC_TRY(h, d_cl, cl.size());
-    ALLOC_TRY(h, d_top, top.size());
-    ALLOC_TRY(h, d_clr, cl_range.size());
-    ALLOC_TRY(h, d_topr, top_range.size());
+    OBJ_ALLOC_TRY(o, d_slot, slot_of.size());
+    OBJ_ALLOC_TRY(o, d_face, face.size());
+    OBJ_ALLOC_TRY(o, d_cl, cl.size());
+    OBJ_ALLOC_TRY(o, d_top, top.size());
+    OBJ_ALLOC_TRY(o, d_clr, cl_range.size());
+    OBJ_ALLOC_TRY(o, d_topr, top_range.size());
     hipStream_t s = h->stream;
     DEV_TRY(h, hipMemcpyAsync(d_face, face.data(), face.size() * sizeof(float4), hipMemcpyHostToDevice, s));
     DEV_TRY(h, hipMemcpyAsync(d_cl, cl.data(), cl.size() * sizeof(float4), hipMemcpyHostToDevice, s));
@@ -312,8 +384,8 @@ static int build_refine_geometry(reg_handle* h) {
     DEV_TRY(h, hipMemcpyAsync(d_topr, top_range.data(), top_range.size() * sizeof(int2), hipMemcpyHostToDevice, s));
     DEV_TRY(h, hipMemcpyAsync(d_slot, slot_of.data(), slot_of.size() * sizeof(int), hipMemcpyHostToDevice, s));
     DEV_TRY(h, hipStreamSynchronize(s));
-    h->geo = RefineGeometry{d_top, d_topr, d_cl, d_clr, d_face, d_slot, n_top, n_cl};
-    h->geo_ready = true;
+    o->geo = RefineGeometry{d_top, d_topr, d_cl, d_clr, d_face, d_slot, n_top, n_cl};
+    o->geo_ready = true;
     return REG_OK;
 }
 
@@ -340,7 +412,7 @@ static RefineConst refine_const(const reg_handle* h) {
 }
 
 static int ensure_refine_buffers(reg_handle* h, int K) {
-    if (!h->geo_ready) {
+    if (!h->obj->geo_ready) {
         int rc = build_refine_geometry(h);
         if (rc) return rc;
     }
@@ -374,12 +446,12 @@ static int ensure_refine_buffers(reg_handle* h, int K) {
     return REG_OK;
 }
 
-extern "C" {
-
-const char* register_last_error(void) { return g_err.c_str(); }
-
-int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* poses, int32_t n_poses, const float* so3,
-                  int32_t n_rot, const reg_grid_spec* grid, const reg_params* params, void* hip_stream, reg_handle** out) {
+// register_init with an optional object already built for the same mesh,
+// canvas and object-grid thresholds (the serving cache): then the mesh copy,
+// the object grid, its spectrum and nonzero list are taken from it.
+static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* poses, int32_t n_poses,
+                     const float* so3, int32_t n_rot, const reg_grid_spec* grid, const reg_params* params,
+                     void* hip_stream, std::shared_ptr<ObjectData> cached, reg_handle** out) {
     g_err.clear();
     if (!out) return fail(REG_EINVAL, "out is NULL");
     *out = nullptr;
@@ -415,25 +487,69 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
     h->nf = mesh->n_faces;
     h->H = spectrum_elems(h->n);
     h->batch = h->prm.batch > 0 ? (h->prm.batch + 7) / 8 * 8 : default_batch(h->n, h->H, n_rot);
-
     h->stream = (hipStream_t)hip_stream;  // NULL: the null stream
     const size_t n3 = (size_t)h->n * h->n * h->n;
     const size_t m3 = (size_t)h->m * h->m * h->m;
     const size_t mp3 = (size_t)h->mp * h->mp * h->mp;
-    ALLOC_TRY(h, h->V, 3 * (size_t)h->nv);
-    ALLOC_TRY(h, h->F, 3 * (size_t)h->nf);
-    ALLOC_TRY(h, h->touch, (size_t)h->nf);
+    hipStream_t s = h->stream;
+
+    const bool build = !cached;
+    if (cached) {
+        if (!cached->matches(h->n, h->h, h->prm) || cached->nv != h->nv || cached->nf != h->nf)
+            return fail(REG_EINVAL, "cached object does not match the mesh, canvas or thresholds");
+        h->obj = cached;
+    } else {
+        auto o = std::make_shared<ObjectData>();
+        o->n = h->n;
+        o->h = h->h;
+        o->nv = h->nv;
+        o->nf = h->nf;
+        o->tau_out1 = h->prm.tau_out1;
+        o->tau_in1 = h->prm.tau_in1;
+        o->rho = h->prm.rho;
+        OBJ_ALLOC_TRY(o, o->V, 3 * (size_t)h->nv);
+        OBJ_ALLOC_TRY(o, o->F, 3 * (size_t)h->nf);
+        OBJ_ALLOC_TRY(o, o->touch, (size_t)h->nf);
+        OBJ_ALLOC_TRY(o, o->anchor, 3);
+        OBJ_ALLOC_TRY(o, o->O, n3);
+        OBJ_ALLOC_TRY(o, o->fo, n3);
+        OBJ_ALLOC_TRY(o, o->W, h->H);
+        OBJ_ALLOC_TRY(o, o->Wlow, (size_t)NLOW3);
+        OBJ_ALLOC_TRY(o, o->nz_idx, n3);
+        OBJ_ALLOC_TRY(o, o->nz_val, n3);
+        OBJ_ALLOC_TRY(o, o->nz_count, 1);
+        OBJ_ALLOC_TRY(o, o->nz_bcount, (n3 + 255) / 256);
+        OBJ_ALLOC_TRY(o, o->nz_boff, (n3 + 255) / 256);
+        OBJ_ALLOC_TRY(o, o->tw, (size_t)h->n);
+        OBJ_ALLOC_TRY(o, o->tw64, (size_t)h->n);
+        h->obj = o;
+    }
+    ObjectData* o = h->obj.get();
+    h->V = o->V;
+    h->F = o->F;
+    h->touch = o->touch;
+    h->anchor = o->anchor;
+    h->O = o->O;
+    h->fo = o->fo;
+    h->W = o->W;
+    h->Wlow = o->Wlow;
+    h->nz_idx = o->nz_idx;
+    h->nz_val = o->nz_val;
+    h->nz_count = o->nz_count;
+    h->nz_bcount = o->nz_bcount;
+    h->nz_boff = o->nz_boff;
+    h->tw = o->tw;
+    h->tw64 = o->tw64;
+
     ALLOC_TRY(h, h->poses, 7 * (size_t)n_poses);
     ALLOC_TRY(h, h->so3, 4 * (size_t)n_rot);
     ALLOC_TRY(h, h->rots, 9 * (size_t)n_rot);
     ALLOC_TRY(h, h->pose_prep, 12 * (size_t)n_poses);
-    ALLOC_TRY(h, h->anchor, 3);
-    ALLOC_TRY(h, h->O, n3);
-    ALLOC_TRY(h, h->fo, n3);
-    ALLOC_TRY(h, h->od2, n3);
-    ALLOC_TRY(h, h->odt2, n3);
-    ALLOC_TRY(h, h->opar, (size_t)h->n * h->n * ((h->n + 31) / 32));
-    ALLOC_TRY(h, h->W, h->H);
+    if (build) {
+        ALLOC_TRY(h, h->od2, n3);
+        ALLOC_TRY(h, h->odt2, n3);
+        ALLOC_TRY(h, h->opar, (size_t)h->n * h->n * ((h->n + 31) / 32));
+    }
     ALLOC_TRY(h, h->spec, h->H * (size_t)h->batch);
     ALLOC_TRY(h, h->ptop, (size_t)h->batch * h->n * KTOP);
     ALLOC_TRY(h, h->pssq, (size_t)h->batch * h->n);
@@ -447,40 +563,32 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
     ALLOC_TRY(h, h->best_flat, (size_t)n_rot);
     ALLOC_TRY(h, h->need_list, (size_t)n_rot);
     ALLOC_TRY(h, h->need_count, 1);
-    ALLOC_TRY(h, h->nz_idx, n3);
-    ALLOC_TRY(h, h->nz_val, n3);
-    ALLOC_TRY(h, h->nz_count, 1);
-    ALLOC_TRY(h, h->nz_bcount, (n3 + 255) / 256);
-    ALLOC_TRY(h, h->nz_boff, (n3 + 255) / 256);
     ALLOC_TRY(h, h->Sw, m3);
     ALLOC_TRY(h, h->cm, mp3);
-    ALLOC_TRY(h, h->tw, (size_t)h->n);
-    ALLOC_TRY(h, h->tw64, (size_t)h->n);
     ALLOC_TRY(h, h->lowT, (size_t)h->batch * h->n * NLOW2);
-    ALLOC_TRY(h, h->Wlow, (size_t)NLOW3);
     ALLOC_TRY(h, h->Plow, (size_t)h->batch * NLOW3);
     ALLOC_TRY(h, h->err, 1);
 
-    hipStream_t s = h->stream;
-    DEV_TRY(h, hipMemcpyAsync(h->V, mesh->vertices, 12 * (size_t)h->nv, hipMemcpyDeviceToDevice, s));
-    DEV_TRY(h, hipMemcpyAsync(h->F, mesh->faces, 12 * (size_t)h->nf, hipMemcpyDeviceToDevice, s));
-    if (mesh->touchable)
-        DEV_TRY(h, hipMemcpyAsync(h->touch, mesh->touchable, (size_t)h->nf, hipMemcpyDeviceToDevice, s));
-    else
-        DEV_TRY(h, hipMemsetAsync(h->touch, 1, (size_t)h->nf, s));
+    if (build) {
+        DEV_TRY(h, hipMemcpyAsync(h->V, mesh->vertices, 12 * (size_t)h->nv, hipMemcpyDeviceToDevice, s));
+        DEV_TRY(h, hipMemcpyAsync(h->F, mesh->faces, 12 * (size_t)h->nf, hipMemcpyDeviceToDevice, s));
+        if (mesh->touchable)
+            DEV_TRY(h, hipMemcpyAsync(h->touch, mesh->touchable, (size_t)h->nf, hipMemcpyDeviceToDevice, s));
+        else
+            DEV_TRY(h, hipMemsetAsync(h->touch, 1, (size_t)h->nf, s));
+        // twiddles exp(-2 pi i t / n) in double, rounded to float
+        std::vector<float2> tw(h->n);
+        std::vector<double2> tw64(h->n);
+        for (int t = 0; t < h->n; ++t) {
+            const double ang = -2.0 * M_PI * (double)t / (double)h->n;
+            tw64[t] = make_double2(std::cos(ang), std::sin(ang));
+            tw[t] = make_float2((float)tw64[t].x, (float)tw64[t].y);
+        }
+        DEV_TRY(h, hipMemcpyAsync(h->tw, tw.data(), sizeof(float2) * h->n, hipMemcpyHostToDevice, s));
+        DEV_TRY(h, hipMemcpyAsync(h->tw64, tw64.data(), sizeof(double2) * h->n, hipMemcpyHostToDevice, s));
+    }
     DEV_TRY(h, hipMemcpyAsync(h->poses, poses, 28 * (size_t)n_poses, hipMemcpyDeviceToDevice, s));
     DEV_TRY(h, hipMemcpyAsync(h->so3, so3, 16 * (size_t)n_rot, hipMemcpyDeviceToDevice, s));
-
-    // twiddles exp(-2 pi i t / n) in double, rounded to float
-    std::vector<float2> tw(h->n);
-    std::vector<double2> tw64(h->n);
-    for (int t = 0; t < h->n; ++t) {
-        const double ang = -2.0 * M_PI * (double)t / (double)h->n;
-        tw64[t] = make_double2(std::cos(ang), std::sin(ang));
-        tw[t] = make_float2((float)tw64[t].x, (float)tw64[t].y);
-    }
-    DEV_TRY(h, hipMemcpyAsync(h->tw, tw.data(), sizeof(float2) * h->n, hipMemcpyHostToDevice, s));
-    DEV_TRY(h, hipMemcpyAsync(h->tw64, tw64.data(), sizeof(double2) * h->n, hipMemcpyHostToDevice, s));
 
     // input checks on the device, then wait for them
     DEV_TRY(h, hipMemsetAsync(h->err, 0, sizeof(int), s));
@@ -495,17 +603,28 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
     if (herr & REGK_ERR_QUAT) return fail(REG_EINVAL, "quaternion norm outside 1 +- 1e-3 (or not finite)");
 
     // object grid and spectrum (per object), swept occupancy (per request)
-    DEV_TRY(h, setup_anchor(h->V, h->nv, h->anchor, s));
-    DEV_TRY(h, setup_object_grid(h->V, h->F, h->touch, h->nf, h->n, h->h, h->anchor, (float)h->prm.tau_out1,
-                                 (float)h->prm.tau_in1, (float)h->prm.rho, h->O, h->fo,
-                                 ObjectScratch{h->od2, h->odt2, h->opar}, s));
-    int rc = build_object_derived(h);
-    if (rc) return rc;
+    if (build) {
+        DEV_TRY(h, setup_anchor(h->V, h->nv, h->anchor, s));
+        DEV_TRY(h, setup_object_grid(h->V, h->F, h->touch, h->nf, h->n, h->h, h->anchor, (float)h->prm.tau_out1,
+                                     (float)h->prm.tau_in1, (float)h->prm.rho, h->O, h->fo,
+                                     ObjectScratch{h->od2, h->odt2, h->opar}, s));
+        int rc = build_object_derived(h);
+        if (rc) return rc;
+    }
     DEV_TRY(h, setup_swept(h->poses, n_poses, (float)probe->radius_mm, (float)probe->length_mm, h->m, h->mp, h->h, h->wc,
                            h->pose_prep, h->Sw, h->cm, s));
     *out = h;
     h = nullptr;  // release the guard
     return REG_OK;
+}
+
+extern "C" {
+
+const char* register_last_error(void) { return g_err.c_str(); }
+
+int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* poses, int32_t n_poses, const float* so3,
+                  int32_t n_rot, const reg_grid_spec* grid, const reg_params* params, void* hip_stream, reg_handle** out) {
+    return init_impl(mesh, probe, poses, n_poses, so3, n_rot, grid, params, hip_stream, nullptr, out);
 }
 
 void register_free(reg_handle* h) {
@@ -701,7 +820,7 @@ int refine_se3(reg_handle* h, const double* init_poses, int32_t K, double* out_p
     const long max_rounds = 1 + (long)(c.max_iters + 1) * 52;
     long round = 0;
     while (round < max_rounds) {
-        DEV_TRY(h, refine_round(h->rst, h->rtr, K, h->geo, h->poses, h->n_poses, c, h->rw, h->rhits, h->rev,
+        DEV_TRY(h, refine_round(h->rst, h->rtr, K, h->obj->geo, h->poses, h->n_poses, c, h->rw, h->rhits, h->rev,
                                 h->r_active, s));
         ++round;
         if (round % 4 == 0 || round == max_rounds) {
@@ -737,10 +856,55 @@ int register_debug_distance(reg_handle* h, const double* R, const double* p, flo
     tr.valid = 1;
     const RefineConst c = refine_const(h);
     DEV_TRY(h, hipMemcpyAsync(h->rtr, &tr, sizeof tr, hipMemcpyHostToDevice, h->stream));
-    DEV_TRY(h, refine_query_only(h->rtr, h->geo, h->poses, h->n_poses, c, h->rw, h->rhits, h->r_active, h->stream));
+    DEV_TRY(h, refine_query_only(h->rtr, h->obj->geo, h->poses, h->n_poses, c, h->rw, h->rhits, h->r_active, h->stream));
     DEV_TRY(h, hipMemcpyAsync(out, h->rhits, sizeof(RefineHit) * h->n_poses, hipMemcpyDeviceToDevice, h->stream));
     DEV_TRY(h, hipStreamSynchronize(h->stream));
     return REG_OK;
 }
 
 }  // extern "C"
+
+namespace regdock_rt {
+
+int init_shared(const reg_mesh* mesh, const reg_probe* probe, const float* poses, int32_t n_poses, const float* so3,
+                int32_t n_rot, const reg_grid_spec* grid, const reg_params* params, void* hip_stream,
+                std::shared_ptr<ObjectData> cached, reg_handle** out) {
+    return init_impl(mesh, probe, poses, n_poses, so3, n_rot, grid, params, hip_stream, std::move(cached), out);
+}
+
+std::shared_ptr<ObjectData> object_of(reg_handle* h) { return h ? h->obj : nullptr; }
+
+size_t object_bytes(const ObjectData* o) { return o ? o->bytes : 0; }
+
+Footprint footprint(int n, int n_rot, int n_poses, int nv, int nf, int batch, int refine_starts) {
+    const size_t n3 = (size_t)n * n * n, H = spectrum_elems(n);
+    const size_t m = (size_t)lattice_edge(n), mp = (m + 3) / 4 * 4;
+    const size_t B = (size_t)batch, M = (size_t)n_rot, N = (size_t)n_poses;
+    Footprint f;
+    f.object = 16 * n3 + 8 * H + 16 * (size_t)NLOW3 + 12 * (size_t)nv + 13 * (size_t)nf + 24 * (size_t)n +
+               8 * ((n3 + 255) / 256) + 68 * (size_t)nf + 2048;
+    const size_t per_rot = 4 * 4 + 4 + 12 + 8 + 4 + 8 + 1 + 8 + 4 + 4 + CMAX * 4 + CMAX * 8 * (size_t)rescore_slices(n);
+    const size_t K = (size_t)std::max(refine_starts, 1), nq = K * REF_TMAX * N;
+    f.request = H * B * 8 + B * n * KTOP * 8 + B * n * 8 + B * n * NLOW2 * 16 + B * NLOW3 * 16 + M * per_rot +
+                M * (4 + 56) + 28 * N + 48 * N + m * m * m + mp * mp * mp + 8 * n3 + n * n * ((n + 31) / 32) * 4 +
+                K * (sizeof(RefineState) + REF_TMAX * (sizeof(RefineTrial) + sizeof(RefineEval))) +
+                nq * (sizeof(RefineHit) + 48 + 8 + 4 + 8 + 16 * (8 + 16)) + 4096;
+    return f;
+}
+
+int default_batch_for(int n, int n_rot) { return default_batch(n, spectrum_elems(n), n_rot); }
+
+std::string last_error() { return g_err; }
+
+int tuned_batch(int n) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(n);
+    return it == g_tuned.end() ? 0 : it->second;
+}
+
+void set_tuned_batch(int n, int batch) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[n] = batch;
+}
+
+}  // namespace regdock_rt

@@ -1,0 +1,41 @@
+// Internal interface between the handle layer (api.cpp) and the serving and
+// batching runtime: registrations that share one device-resident object
+// (mesh, object grid, spectrum), and the device footprint used for admission.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <memory>
+#include <string>
+
+#include "regdock.h"
+
+struct ObjectData;
+
+namespace regdock_rt {
+
+// register_init, reusing `cached` (built for the same mesh, canvas and
+// object-grid thresholds) when it is not null.
+int init_shared(const reg_mesh* mesh, const reg_probe* probe, const float* poses, int32_t n_poses, const float* so3,
+                int32_t n_rot, const reg_grid_spec* grid, const reg_params* params, void* hip_stream,
+                std::shared_ptr<ObjectData> cached, reg_handle** out);
+
+std::shared_ptr<ObjectData> object_of(reg_handle* h);
+size_t object_bytes(const ObjectData* o);
+
+// Device bytes of one registration: the object part (grid, spectrum, lists,
+// mesh and its hierarchy) and the request part (swept lattice, spectrum work
+// buffer of one batch, per-rotation arrays, refinement buffers).
+struct Footprint {
+    size_t object = 0, request = 0;
+};
+Footprint footprint(int n, int n_rot, int n_poses, int n_vertices, int n_faces, int batch, int refine_starts);
+int default_batch_for(int n, int n_rot);
+
+// the calling thread's last error message
+std::string last_error();
+
+// Rotation batch per canvas edge chosen by the autotuner (0: none recorded).
+int tuned_batch(int n);
+void set_tuned_batch(int n, int batch);
+
+}  // namespace regdock_rt

@@ -11,5 +11,6 @@ from .gen import (  # noqa: F401
     SEED, rng, icosphere, perturbed_sphere, touchable_mask, quat_to_mat,
     mat_to_quat, quat_mul, haar_quaternion, sobol_hopf_so3, hemisphere_directions,
     min_rotation_to, footprint_top, make_trajectory, Problem, make_problem,
-    CONFIGS, config_problem, grid_edge_m,
+    CONFIGS, config_problem, grid_edge_m, BATCH_N, BATCH_M, SERVE_MESHES, SERVE_RATE, batch_spec,
+    batch_problem, serve_mesh, serve_spec, serve_problem, serve_arrivals,
 )

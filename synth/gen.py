@@ -34,7 +34,7 @@ from scipy.stats import qmc
 SEED = 260521398
 
 # stream ids of the seeded generators
-S_MESH, S_GT, S_TRAJ, S_CONTACT, S_SOBOL, S_ARRIVAL = 0, 1, 2, 3, 4, 5
+S_MESH, S_GT, S_TRAJ, S_CONTACT, S_SOBOL, S_ARRIVAL, S_SIZE = 0, 1, 2, 3, 4, 5, 6
 
 
 def rng(cfg: int, item: int, stream: int) -> np.random.Generator:
@@ -347,8 +347,10 @@ CONFIGS = {
 
 def make_problem(cfg: int, item: int, level: int, lmax: int, N: int, n: int, h: float, M: int,
                  hop: float = 0.0, noise_t: float = 0.0, noise_r: float = 0.0,
-                 radius: float = 0.5, length: float = 8.0) -> Problem:
-    V, F = perturbed_sphere(level, lmax, rng(cfg, item, S_MESH))
+                 radius: float = 0.5, length: float = 8.0, mesh=None) -> Problem:
+    """A registration problem; `mesh` = (V, F) reuses a given object mesh (the
+    serving workload draws its objects from a fixed pool)."""
+    V, F = mesh if mesh is not None else perturbed_sphere(level, lmax, rng(cfg, item, S_MESH))
     touch = touchable_mask(V, F)
     gg = rng(cfg, item, S_GT)
     q_gt = haar_quaternion(gg)
@@ -368,3 +370,73 @@ def config_problem(cfg: int, item: int = 0, **over) -> Problem:
     p.update(over)
     return make_problem(cfg, item, p["level"], p["lmax"], p["N"], p["n"], p["h"], p["M"],
                         hop=p["hop"], noise_t=p["noise_t"], noise_r=p["noise_r"])
+
+
+# ----------------------------------------------------------------------------
+# uneven batches and serving
+# ----------------------------------------------------------------------------
+
+# canvas edges and SO(3) set sizes of the uneven batch (h = 15.36 mm / n keeps
+# the 15.36 mm canvas of the 128^3 workload)
+BATCH_N = (48, 60, 64, 80, 96, 120, 128)
+BATCH_M = (512, 1024, 2048, 4096)
+SERVE_MESHES = 20
+SERVE_RATE = 200.0   # requests per second (Poisson)
+
+
+def batch_spec(i: int, cfg: int = 4) -> dict:
+    """Sizes of registration i of the uneven batch: n, h = 15.36/n, M, N in
+    [300, 2000], SH degree in [6, 12], level-5 mesh, the pose noise of the
+    128^3 workload."""
+    g = rng(cfg, i, S_SIZE)
+    n = int(g.choice(BATCH_N))
+    return dict(level=5, lmax=int(g.integers(6, 13)), N=int(g.integers(300, 2001)), n=n, h=15.36 / n,
+                M=int(g.choice(BATCH_M)), hop=0.0, noise_t=0.05, noise_r=0.2)
+
+
+def batch_problem(i: int, cfg: int = 4, **over) -> Problem:
+    spec = batch_spec(i, cfg)
+    spec.update(over)
+    return make_problem(cfg, i, **spec)
+
+
+def serve_mesh(mesh_id: int, cfg: int = 5):
+    """Object `mesh_id` of the serving pool: a level-5 perturbed sphere."""
+    g = rng(cfg, 10_000 + mesh_id, S_MESH)
+    lmax = int(g.integers(6, 13))
+    return perturbed_sphere(5, lmax, rng(cfg, 10_000 + mesh_id, S_TRAJ))
+
+
+def serve_spec(req: int, cfg: int = 5) -> dict:
+    """Request `req` of the serving stream: one of SERVE_MESHES objects drawn
+    uniformly; 10 % at n = 160 (h = 0.096 mm, 8192 rotations), the rest sized
+    as the uneven batch."""
+    g = rng(cfg, req, S_SIZE)
+    mesh_id = int(g.integers(0, SERVE_MESHES))
+    if g.uniform() < 0.1:
+        spec = dict(level=5, lmax=0, N=int(g.integers(300, 2001)), n=160, h=0.096, M=8192)
+    else:
+        n = int(g.choice(BATCH_N))
+        spec = dict(level=5, lmax=0, N=int(g.integers(300, 2001)), n=n, h=15.36 / n, M=int(g.choice(BATCH_M)))
+    spec.update(hop=0.0, noise_t=0.05, noise_r=0.2)
+    return dict(mesh_id=mesh_id, **spec)
+
+
+def serve_problem(req: int, cfg: int = 5, mesh_cache: dict | None = None, **over) -> tuple[int, Problem]:
+    """(mesh id, problem) of request `req`; trajectory, ground truth and SO(3)
+    set are drawn fresh from the request id."""
+    spec = serve_spec(req, cfg)
+    spec.update(over)
+    mid = spec.pop("mesh_id")
+    if mesh_cache is not None and mid in mesh_cache:
+        mesh = mesh_cache[mid]
+    else:
+        mesh = serve_mesh(mid, cfg)
+        if mesh_cache is not None:
+            mesh_cache[mid] = mesh
+    return mid, make_problem(cfg, req, mesh=mesh, **spec)
+
+
+def serve_arrivals(count: int, rate: float = SERVE_RATE, cfg: int = 5) -> np.ndarray:
+    """Arrival times (s) of a Poisson stream of `count` requests."""
+    return np.cumsum(rng(cfg, 0, S_ARRIVAL).exponential(1.0 / rate, size=count))
