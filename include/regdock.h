@@ -226,6 +226,43 @@ int register_refine_stats(reg_handle* h, int64_t* rounds, int64_t* evaluations);
  * change s, s' or s''.  Synchronous. */
 int register_debug_distance(reg_handle* h, const double* R, const double* p, float* out);
 
+/* ----------------------------------------------------------------- batching
+ *
+ * Many registrations of uneven canvases as one captured hipGraph: for each
+ * handle, the global search over all its rotations (Sec. IV), its top_k peaks
+ * and graph_rounds rounds of their SE(3) refinement (Sec. V), on a few
+ * parallel branches balanced by model HBM bytes.  A replay recomputes
+ * everything from the handles' inputs; refinements still running after the
+ * captured rounds are continued by register_batch_run, so the results equal
+ * those of score_rotations / register_top_k / refine_se3 on each handle.
+ * The handles must stay alive and must not be used elsewhere while the batch
+ * runs; their event timing must be off.
+ */
+typedef struct reg_batch reg_batch;
+
+/* handles: count handle pointers (host array).  top_k in [1, 16]; refine 0/1;
+ * graph_rounds: refinement rounds captured (0: 64); branches: parallel
+ * streams (0: 4).  Errors: REG_EINVAL, REG_ENOMEM, REG_EDEVICE. */
+int register_batch_create(reg_handle* const* handles, int32_t count, int32_t top_k, int32_t refine,
+                          int32_t graph_rounds, int32_t branches, reg_batch** out);
+/* Replays the graph and waits for it (and any continued refinement). */
+int register_batch_run(reg_batch* b);
+/* Copies handle i's outputs of the last run into the given device buffers:
+ * scores (n_rot float), search poses (n_rot x 7 double), top (K int32), refined
+ * poses (K x 7 double) and J (K double), K = min(top_k, n_rot).  Any pointer
+ * may be NULL.  Synchronous. */
+int register_batch_outputs(reg_batch* b, int32_t i, float* scores, double* poses, int32_t* top, double* refined,
+                           double* J);
+void register_batch_free(reg_batch* b);
+
+/* Autotuner: times score_rotations on the handle's own problem (its first
+ * max_rotations rotations, 0: 512) for rotation batches of 8..256 that fit in
+ * device memory and records the fastest for the handle's canvas edge; later
+ * register_init calls with params.batch = 0 use it.  Synchronous. */
+int register_autotune(reg_handle* h, int32_t max_rotations, int32_t* out_batch);
+/* the recorded batch for canvas edge n, 0 if none */
+int register_tuned_batch(int32_t n);
+
 /* ------------------------------------------------------------------ serving
  *
  * A server runs whole registrations -- object grid and spectrum, swept

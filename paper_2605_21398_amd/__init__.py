@@ -27,7 +27,8 @@ EXPORTS = ["register_init", "score_rotations", "register_top_k", "register_free"
            "register_set_grids", "register_set_timing", "register_get_timing", "register_search_stats",
            "refine_se3", "register_debug_distance", "register_refine_stats", "register_server_create",
            "register_server_destroy", "register_submit", "register_poll", "register_wait", "register_server_stats",
-           "register_server_last_error"]
+           "register_server_last_error", "register_batch_create", "register_batch_run", "register_batch_outputs",
+           "register_batch_free", "register_autotune", "register_tuned_batch"]
 
 
 class RegError(RuntimeError):
@@ -147,6 +148,18 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.register_server_stats.argtypes = [p, ctypes.POINTER(reg_server_stats)]
     L.register_server_last_error.restype = ctypes.c_char_p
     L.register_server_last_error.argtypes = []
+    L.register_batch_create.restype = ctypes.c_int
+    L.register_batch_create.argtypes = [p, i32, i32, i32, i32, i32, ctypes.POINTER(p)]
+    L.register_batch_run.restype = ctypes.c_int
+    L.register_batch_run.argtypes = [p]
+    L.register_batch_outputs.restype = ctypes.c_int
+    L.register_batch_outputs.argtypes = [p, i32, p, p, p, p, p]
+    L.register_batch_free.restype = None
+    L.register_batch_free.argtypes = [p]
+    L.register_autotune.restype = ctypes.c_int
+    L.register_autotune.argtypes = [p, i32, ctypes.POINTER(i32)]
+    L.register_tuned_batch.restype = ctypes.c_int
+    L.register_tuned_batch.argtypes = [i32]
     _lib = L
     return L
 
@@ -418,3 +431,58 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------- batching
+
+class Batch:
+    """Registrations of several handles captured as one hipGraph (see the
+    batching section of the header)."""
+
+    def __init__(self, handles, top_k: int = 16, refine: bool = True, graph_rounds: int = 0, branches: int = 0):
+        L = load_library()
+        self.handles = list(handles)
+        arr = (ctypes.c_void_p * len(self.handles))(*[h.ptr.value for h in self.handles])
+        self.ptr = ctypes.c_void_p()
+        _check(L.register_batch_create(arr, len(self.handles), top_k, 1 if refine else 0, graph_rounds, branches,
+                                       ctypes.byref(self.ptr)))
+        self.top_k = top_k
+
+    def run(self):
+        _check(load_library().register_batch_run(self.ptr))
+
+    def outputs(self, i: int) -> dict:
+        """Host copies of handle i's outputs of the last run."""
+        torch = _torch()
+        h = self.handles[i]
+        K = min(self.top_k, h.n_rot)
+        sc = torch.empty(h.n_rot, dtype=torch.float32, device="cuda")
+        po = torch.empty((h.n_rot, 7), dtype=torch.float64, device="cuda")
+        tp = torch.empty(K, dtype=torch.int32, device="cuda")
+        rf = torch.empty((K, 7), dtype=torch.float64, device="cuda")
+        J = torch.empty(K, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        _check(load_library().register_batch_outputs(self.ptr, i, _ptr(sc), _ptr(po), _ptr(tp), _ptr(rf), _ptr(J)))
+        return dict(scores=sc.cpu().numpy(), poses=po.cpu().numpy(), top=tp.cpu().numpy(), refined=rf.cpu().numpy(),
+                    J=J.cpu().numpy())
+
+    def close(self):
+        if self.ptr:
+            load_library().register_batch_free(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def register_autotune(h: Handle, max_rotations: int = 512) -> int:
+    b = ctypes.c_int32()
+    _check(load_library().register_autotune(h.ptr, max_rotations, ctypes.byref(b)))
+    return b.value
+
+
+def register_tuned_batch(n: int) -> int:
+    return load_library().register_tuned_batch(n)

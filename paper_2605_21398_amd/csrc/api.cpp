@@ -618,6 +618,172 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
     return REG_OK;
 }
 
+// Refinement rounds on the handle's stream until no start is left (checked
+// every 4 rounds), then the results.  Every round evaluates the next trials
+// of each unfinished start and settles at least one of its trial steps; a
+// start takes at most max_iters accepted steps and the damping can grow 3x at
+// most 51 times in a row, which bounds the rounds.
+static int refine_continue(reg_handle* h, int K, double* out_poses, double* out_J, int32_t* out_iters) {
+    const RefineConst c = refine_const(h);
+    hipStream_t s = h->stream;
+    const long max_rounds = 1 + (long)(c.max_iters + 1) * 52;
+    DEV_TRY(h, hipMemcpyAsync(h->r_active_host, h->r_active, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    DEV_TRY(h, hipStreamSynchronize(s));
+    long round = h->r_rounds;
+    while (h->r_active_host[0] > 0 && round < max_rounds) {
+        DEV_TRY(h, refine_round(h->rst, h->rtr, K, h->obj->geo, h->poses, h->n_poses, c, h->rw, h->rhits, h->rev,
+                                h->r_active, s));
+        ++round;
+        if (round % 4 == 0 || round == max_rounds) {
+            DEV_TRY(h, hipMemcpyAsync(h->r_active_host, h->r_active, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+            DEV_TRY(h, hipStreamSynchronize(s));
+        }
+    }
+    DEV_TRY(h, refine_finish(h->rst, K, out_poses, out_J, out_iters, s));
+    DEV_TRY(h, hipMemcpyAsync(h->r_active_host, h->r_active, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    DEV_TRY(h, hipStreamSynchronize(s));
+    h->r_rounds = round;
+    h->r_evals = h->r_active_host[1];
+    return REG_OK;
+}
+
+// ------------------------------------------------------------- batching
+//
+// Many registrations of uneven canvases in one captured hipGraph: the search
+// over every rotation, the top K and a fixed budget of refinement rounds of
+// each handle go onto one of a few parallel branches (streams forked from and
+// joined to the launch stream), balanced by their model HBM bytes.  Rounds
+// after a start has finished are no-ops, so the captured budget gives the
+// same result as the host-driven loop; a start still running afterwards is
+// continued on its handle's stream.
+struct reg_batch {
+    struct Out {
+        float* score = nullptr;
+        double* pose = nullptr;
+        int32_t* top = nullptr;
+        double* init = nullptr;
+        double* refined = nullptr;
+        double* J = nullptr;
+        int32_t* iters = nullptr;
+    };
+    std::vector<reg_handle*> hs;
+    std::vector<int> K, branch_of;
+    std::vector<Out> out;
+    int rounds = 0, refine = 1;
+    hipStream_t main = nullptr;
+    std::vector<hipStream_t> br;
+    std::vector<hipEvent_t> ev;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<void*> owned;
+    ~reg_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (auto e : ev) (void)hipEventDestroy(e);
+        for (auto s : br) (void)hipStreamDestroy(s);
+        if (main) (void)hipStreamDestroy(main);
+        for (void* p : owned) (void)hipFree(p);
+    }
+    template <class T>
+    bool alloc(T** p, size_t count) {
+        void* q = nullptr;
+        if (hipMalloc(&q, count * sizeof(T) > 0 ? count * sizeof(T) : 1) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        owned.push_back(q);
+        *p = (T*)q;
+        return true;
+    }
+};
+
+static int run_batches(reg_handle* h, int first, int count, float* out_score, int32_t* out_shift, double* out_pose,
+                       float* corr_out);
+
+// enqueue one handle's registration on stream s (captured)
+static int batch_enqueue(reg_batch* b, int i, hipStream_t s) {
+    reg_handle* h = b->hs[i];
+    const reg_batch::Out& o = b->out[i];
+    hipStream_t saved = h->stream;
+    h->stream = s;
+    struct Restore {
+        reg_handle* h;
+        hipStream_t s;
+        ~Restore() { h->stream = s; }
+    } rs{h, saved};
+    int rc = run_batches(h, 0, h->n_rot, o.score, nullptr, o.pose, nullptr);
+    if (rc) return rc;
+    const int K = b->K[i];
+    DEV_TRY(h, top_k(o.score, h->n_rot, K, o.top, s));
+    if (!b->refine) return REG_OK;
+    DEV_TRY(h, gather_poses(o.top, o.pose, K, o.init, s));
+    const RefineConst c = refine_const(h);
+    DEV_TRY(h, refine_start(o.init, K, h->anchor, c, h->rst, h->rtr, h->r_active, h->rw, s));
+    for (int r = 0; r < b->rounds; ++r)
+        DEV_TRY(h, refine_round(h->rst, h->rtr, K, h->obj->geo, h->poses, h->n_poses, c, h->rw, h->rhits, h->rev,
+                                h->r_active, s));
+    DEV_TRY(h, refine_finish(h->rst, K, o.refined, o.J, o.iters, s));
+    return REG_OK;
+}
+
+// rotation batches timed on the handle's own problem; the fastest is recorded
+// for its canvas edge and used by later handles that leave params.batch at 0
+static int autotune_impl(reg_handle* h, int max_rotations, int* out_batch) {
+    const int M = std::max(8, std::min(h->n_rot, max_rotations > 0 ? max_rotations : 512));
+    float* score = nullptr;
+    if (hipMalloc((void**)&score, (size_t)M * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(REG_ENOMEM, "autotune score buffer");
+    }
+    struct FreeS {
+        float* p;
+        ~FreeS() { (void)hipFree(p); }
+    } fs{score};
+    hipEvent_t e0, e1;
+    DEV_TRY(h, hipEventCreate(&e0));
+    DEV_TRY(h, hipEventCreate(&e1));
+    struct FreeE {
+        hipEvent_t a, b;
+        ~FreeE() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } fe{e0, e1};
+    double best_t = INFINITY;
+    int best = 0;
+    for (int B : {8, 16, 32, 64, 128, 256}) {
+        if ((size_t)B * h->H * sizeof(float2) > ((size_t)2 << 30) || B > ((M + 7) / 8) * 8) continue;
+        reg_params prm = h->prm;
+        prm.batch = B;
+        reg_mesh mesh{h->V, h->nv, h->F, h->nf, h->touch};
+        reg_grid_spec grid{h->n, h->h, {h->wc[0], h->wc[1], h->wc[2]}};
+        reg_handle* t = nullptr;
+        int rc = init_impl(&mesh, &h->probe, h->poses, h->n_poses, h->so3, M, &grid, &prm, (void*)h->stream, h->obj,
+                           &t);
+        if (rc == REG_ENOMEM) continue;
+        if (rc) return rc;
+        rc = run_batches(t, 0, M, score, nullptr, nullptr, nullptr);  // warm-up
+        if (!rc) {
+            DEV_TRY(h, hipEventRecord(e0, h->stream));
+            for (int rep = 0; rep < 2 && !rc; ++rep) rc = run_batches(t, 0, M, score, nullptr, nullptr, nullptr);
+            DEV_TRY(h, hipEventRecord(e1, h->stream));
+            DEV_TRY(h, hipEventSynchronize(e1));
+        }
+        register_free(t);
+        if (rc) return rc;
+        float ms = 0;
+        DEV_TRY(h, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_t) {
+            best_t = ms;
+            best = B;
+        }
+    }
+    if (!best) return fail(REG_ENOMEM, "no rotation batch fits in device memory");
+    regdock_rt::set_tuned_batch(h->n, best);
+    *out_batch = best;
+    return REG_OK;
+}
+
 extern "C" {
 
 const char* register_last_error(void) { return g_err.c_str(); }
@@ -810,31 +976,9 @@ int refine_se3(reg_handle* h, const double* init_poses, int32_t K, double* out_p
     }
     int rc = ensure_refine_buffers(h, K);
     if (rc) return rc;
-    const RefineConst c = refine_const(h);
-    hipStream_t s = h->stream;
-    DEV_TRY(h, refine_start(init_poses, K, h->anchor, c, h->rst, h->rtr, h->r_active, h->rw, s));
-    // every round evaluates the next trials of each unfinished start and
-    // settles at least one of its trial steps; a start takes at most
-    // max_iters accepted steps and the damping can grow 3x at most 51 times
-    // in a row
-    const long max_rounds = 1 + (long)(c.max_iters + 1) * 52;
-    long round = 0;
-    while (round < max_rounds) {
-        DEV_TRY(h, refine_round(h->rst, h->rtr, K, h->obj->geo, h->poses, h->n_poses, c, h->rw, h->rhits, h->rev,
-                                h->r_active, s));
-        ++round;
-        if (round % 4 == 0 || round == max_rounds) {
-            DEV_TRY(h, hipMemcpyAsync(h->r_active_host, h->r_active, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-            DEV_TRY(h, hipStreamSynchronize(s));
-            if (h->r_active_host[0] == 0) break;
-        }
-    }
-    DEV_TRY(h, refine_finish(h->rst, K, out_poses, out_J, out_iters, s));
-    DEV_TRY(h, hipMemcpyAsync(h->r_active_host, h->r_active, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-    DEV_TRY(h, hipStreamSynchronize(s));
-    h->r_rounds = round;
-    h->r_evals = h->r_active_host[1];
-    return REG_OK;
+    DEV_TRY(h, refine_start(init_poses, K, h->anchor, refine_const(h), h->rst, h->rtr, h->r_active, h->rw, h->stream));
+    h->r_rounds = 0;
+    return refine_continue(h, K, out_poses, out_J, out_iters);
 }
 
 int register_refine_stats(reg_handle* h, int64_t* rounds, int64_t* evaluations) {
@@ -843,6 +987,133 @@ int register_refine_stats(reg_handle* h, int64_t* rounds, int64_t* evaluations) 
     *evaluations = h->r_evals;
     return REG_OK;
 }
+
+int register_batch_create(reg_handle* const* handles, int32_t count, int32_t top_k, int32_t refine,
+                          int32_t graph_rounds, int32_t branches, reg_batch** out) {
+    g_err.clear();
+    if (!handles || !out || count < 1) return fail(REG_EINVAL, "register_batch_create needs >= 1 handle");
+    *out = nullptr;
+    if (top_k < 1 || top_k > 16) return fail(REG_EINVAL, "top_k must be in [1, 16]");
+    auto b = std::make_unique<reg_batch>();
+    b->refine = refine != 0;
+    b->rounds = graph_rounds > 0 ? graph_rounds : 64;
+    const int nb = std::max(1, std::min<int>(branches > 0 ? branches : 4, count));
+    for (int i = 0; i < count; ++i) {
+        reg_handle* h = handles[i];
+        if (!h) return fail(REG_EINVAL, "handle %d is NULL", i);
+        if (h->poisoned) return fail(REG_EDEVICE, "handle %d is poisoned", i);
+        if (h->timing) return fail(REG_EINVAL, "handle %d has event timing on (not capturable)", i);
+        for (int j = 0; j < i; ++j)
+            if (handles[j] == h) return fail(REG_EINVAL, "handle %d appears twice", i);
+        b->hs.push_back(h);
+        const int K = std::min<int>(top_k, h->n_rot);
+        b->K.push_back(K);
+        if (b->refine) {
+            int rc = ensure_refine_buffers(h, K);
+            if (rc) return rc;
+        }
+        reg_batch::Out o;
+        if (!b->alloc(&o.score, h->n_rot) || !b->alloc(&o.pose, 7 * (size_t)h->n_rot) || !b->alloc(&o.top, K) ||
+            !b->alloc(&o.init, 7 * (size_t)K) || !b->alloc(&o.refined, 7 * (size_t)K) || !b->alloc(&o.J, K) ||
+            !b->alloc(&o.iters, K))
+            return fail(REG_ENOMEM, "batch output allocation failed");
+        b->out.push_back(o);
+        DEV_TRY(h, hipStreamSynchronize(h->stream));
+    }
+    // longest-processing-time assignment of the handles to the branches by
+    // their model bytes (4 half-spectra per rotation)
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    auto cost = [&](int i) { return (double)b->hs[i]->H * b->hs[i]->n_rot; };
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
+    std::vector<double> load(nb, 0.0);
+    b->branch_of.assign(count, 0);
+    for (int i : order) {
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        b->branch_of[i] = k;
+        load[k] += cost(i);
+    }
+    reg_handle* h0 = b->hs[0];
+    DEV_TRY(h0, hipStreamCreateWithFlags(&b->main, hipStreamNonBlocking));
+    b->br.assign(nb, nullptr);
+    for (auto& s : b->br) DEV_TRY(h0, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    b->ev.assign(nb + 1, nullptr);
+    for (auto& e : b->ev) DEV_TRY(h0, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+
+    DEV_TRY(h0, hipStreamBeginCapture(b->main, hipStreamCaptureModeRelaxed));
+    int rc = REG_OK;
+    if (hipEventRecord(b->ev[0], b->main) != hipSuccess) rc = fail(REG_EDEVICE, "fork event");
+    for (int k = 0; k < nb && !rc; ++k)
+        if (hipStreamWaitEvent(b->br[k], b->ev[0], 0) != hipSuccess) rc = fail(REG_EDEVICE, "fork wait");
+    for (int i : order) {
+        if (rc) break;
+        rc = batch_enqueue(b.get(), i, b->br[b->branch_of[i]]);
+    }
+    for (int k = 0; k < nb && !rc; ++k)
+        if (hipEventRecord(b->ev[1 + k], b->br[k]) != hipSuccess || hipStreamWaitEvent(b->main, b->ev[1 + k], 0) != hipSuccess)
+            rc = fail(REG_EDEVICE, "join");
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(b->main, &g);
+    b->graph = g;
+    if (rc) return rc;
+    if (ec != hipSuccess) return fail(REG_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(ec));
+    DEV_TRY(h0, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    *out = b.release();
+    return REG_OK;
+}
+
+int register_batch_run(reg_batch* b) {
+    g_err.clear();
+    if (!b) return fail(REG_EINVAL, "NULL batch");
+    reg_handle* h0 = b->hs[0];
+    DEV_TRY(h0, hipGraphLaunch(b->exec, b->main));
+    DEV_TRY(h0, hipStreamSynchronize(b->main));
+    if (!b->refine) return REG_OK;
+    for (size_t i = 0; i < b->hs.size(); ++i) {
+        reg_handle* h = b->hs[i];
+        h->r_rounds = b->rounds;
+        const reg_batch::Out& o = b->out[i];
+        int rc = refine_continue(h, b->K[i], o.refined, o.J, o.iters);
+        if (rc) return rc;
+    }
+    return REG_OK;
+}
+
+int register_batch_outputs(reg_batch* b, int32_t i, float* scores, double* poses, int32_t* top, double* refined,
+                           double* J) {
+    g_err.clear();
+    if (!b || i < 0 || i >= (int32_t)b->hs.size()) return fail(REG_EINVAL, "bad batch index");
+    const reg_batch::Out& o = b->out[i];
+    reg_handle* h = b->hs[i];
+    const size_t M = (size_t)h->n_rot, K = (size_t)b->K[i];
+    const hipMemcpyKind d2d = hipMemcpyDeviceToDevice;
+    if (scores) DEV_TRY(h, hipMemcpyAsync(scores, o.score, M * 4, d2d, b->main));
+    if (poses) DEV_TRY(h, hipMemcpyAsync(poses, o.pose, M * 56, d2d, b->main));
+    if (top) DEV_TRY(h, hipMemcpyAsync(top, o.top, K * 4, d2d, b->main));
+    if (refined) DEV_TRY(h, hipMemcpyAsync(refined, o.refined, K * 56, d2d, b->main));
+    if (J) DEV_TRY(h, hipMemcpyAsync(J, o.J, K * 8, d2d, b->main));
+    DEV_TRY(h, hipStreamSynchronize(b->main));
+    return REG_OK;
+}
+
+void register_batch_free(reg_batch* b) {
+    if (!b) return;
+    if (b->main) (void)hipStreamSynchronize(b->main);
+    delete b;
+}
+
+int register_autotune(reg_handle* h, int32_t max_rotations, int32_t* out_batch) {
+    g_err.clear();
+    if (!h || !out_batch) return fail(REG_EINVAL, "NULL argument");
+    if (h->poisoned) return fail(REG_EDEVICE, "handle poisoned by an earlier device error");
+    int b = 0;
+    int rc = autotune_impl(h, max_rotations, &b);
+    if (rc) return rc;
+    *out_batch = b;
+    return REG_OK;
+}
+
+int register_tuned_batch(int32_t n) { return regdock_rt::tuned_batch(n); }
 
 int register_debug_distance(reg_handle* h, const double* R, const double* p, float* out) {
     g_err.clear();

@@ -92,3 +92,5 @@ hipError_t refine_finish(const RefineState* st, int K, double* out_poses, double
 hipError_t refine_query_only(const RefineTrial* tr, const RefineGeometry& geo, const float* poses, int n_poses,
                              const RefineConst& c, const RefineScratch& w, RefineHit* hits, int* counters,
                              hipStream_t s);
+// dst[k] = src[idx[k]] for K rows of 7 doubles (search poses -> starts)
+hipError_t gather_poses(const int32_t* idx, const double* src, int K, double* dst, hipStream_t s);

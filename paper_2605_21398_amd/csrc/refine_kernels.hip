@@ -408,6 +408,15 @@ __device__ void probe_frame(const float* __restrict__ poses, int i, double* Ri, 
 
 __global__ void k_ref_reset(int* __restrict__ pair_count) { *pair_count = 0; }
 
+// refinement starts from search results: rows idx[k] of a count x 7 pose array
+__global__ void k_gather_poses(const int32_t* __restrict__ idx, const double* __restrict__ src, int K,
+                               double* __restrict__ dst) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 7 * K) return;
+    const int k = t / 7, c = t - 7 * k;
+    dst[t] = src[7 * (size_t)idx[k] + c];
+}
+
 __device__ __forceinline__ float wave_min_f(float v) {
     for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
     return v;
@@ -949,5 +958,10 @@ hipError_t refine_query_only(const RefineTrial* tr, const RefineGeometry& geo, c
                              hipStream_t s) {
     k_ref_reset<<<1, 1, 0, s>>>(w.pair_count);
     launch_queries(tr, 1, geo, poses, n_poses, c, w, hits, counters, s);
+    return hipGetLastError();
+}
+
+hipError_t gather_poses(const int32_t* idx, const double* src, int K, double* dst, hipStream_t s) {
+    k_gather_poses<<<(7 * K + 63) / 64, 64, 0, s>>>(idx, src, K, dst);
     return hipGetLastError();
 }

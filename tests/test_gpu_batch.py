@@ -1,0 +1,96 @@
+"""Uneven batches as one captured hipGraph, and the rotation-batch autotuner.
+
+Every replay of the graph (with eager work and synchronisations between the
+replays) must reproduce, bitwise, what score_rotations, register_top_k and
+refine_se3 give on each handle eagerly; the captured refinement budget is kept
+small so that continuing refinements are covered too.  The rotation batch
+does not change a rotation's arithmetic, so scores are bitwise equal under any
+batch the autotuner picks.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    import paper_2605_21398_amd as rd
+    rd.load_library()
+    return rd
+
+
+def _handle(rd, p, **kw):
+    return rd.register_init(p.vertices, p.faces, p.touchable, p.poses, p.so3, p.n, p.h, p.center, p.radius,
+                            p.length, **kw)
+
+
+def _eager(rd, h):
+    sc, _, po = rd.score_rotations(h, shift=False)
+    top = rd.register_top_k(h, sc, 16)
+    starts = po[top.long()]
+    out, J, _ = rd.refine_se3(h, starts)
+    return dict(scores=sc.cpu().numpy(), poses=po.cpu().numpy(), top=top.cpu().numpy(), refined=out.cpu().numpy(),
+                J=J.cpu().numpy())
+
+
+def test_batch_graph_replays_equal_eager_results():
+    rd = _lib()
+    ps = [synth.batch_problem(i, level=4, lmax=6, N=400, M=256) for i in range(4)]
+    print("\ncanvases", [p.n for p in ps])
+    hs = [_handle(rd, p) for p in ps]
+    try:
+        ref = [_eager(rd, h) for h in hs]
+        b = rd.Batch(hs, top_k=16, graph_rounds=8, branches=3)
+        try:
+            for rep in range(3):
+                b.run()
+                for i in range(len(hs)):
+                    got = b.outputs(i)
+                    for k in ("scores", "poses", "top", "refined", "J"):
+                        assert np.array_equal(got[k], ref[i][k]), (rep, i, k)
+                # eager work between the replays
+                rd.score_rotations(hs[rep % len(hs)], 0, 32)
+                import torch
+                torch.cuda.synchronize()
+        finally:
+            b.close()
+    finally:
+        for h in hs:
+            rd.register_free(h)
+
+
+def test_batch_abi_errors():
+    rd = _lib()
+    p = synth.batch_problem(0, level=4, lmax=6, N=300, M=64)
+    h = _handle(rd, p)
+    try:
+        with pytest.raises(rd.RegError):
+            rd.Batch([h], top_k=17)
+        with pytest.raises(rd.RegError):
+            rd.Batch([h, h])
+    finally:
+        rd.register_free(h)
+
+
+def test_autotune_records_a_batch_and_scores_do_not_depend_on_it():
+    rd = _lib()
+    p = synth.config_problem(2, 0, M=256)
+    h = _handle(rd, p)
+    try:
+        B = rd.register_autotune(h, 256)
+        assert B in (8, 16, 32, 64, 128, 256)
+        assert rd.register_tuned_batch(p.n) == B
+        h2 = _handle(rd, p)
+        h8 = _handle(rd, p, params={"batch": 8})
+        try:
+            assert h2.batch == min(B, 256)
+            s2 = rd.score_rotations(h2, shift=False)[0].cpu().numpy()
+            s8 = rd.score_rotations(h8, shift=False)[0].cpu().numpy()
+            assert np.array_equal(s2, s8)
+        finally:
+            rd.register_free(h2)
+            rd.register_free(h8)
+    finally:
+        rd.register_free(h)
