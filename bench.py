@@ -69,6 +69,123 @@ def cpu_baseline(p, n_sample: int, starts, evals: int):
                        f"threads) times the {evals} evaluations of the {len(starts)} starts")}
 
 
+def _gen_batch(i):
+    import synth
+    return synth.batch_problem(i)
+
+
+def _gen_serve(req):
+    import synth
+    return synth.serve_problem(req)
+
+
+def generate(args):
+    """All synthetic workloads, made in a process pool before the GPU is touched."""
+    import multiprocessing as mp
+
+    import synth
+    jobs = {}
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with mp.get_context("fork").Pool(workers) as pool:
+        if args.batch > 0:
+            jobs["batch"] = pool.map_async(_gen_batch, range(args.batch))
+        if args.serve > 0:
+            jobs["serve"] = pool.map_async(_gen_serve, range(args.serve))
+        main_p = synth.config_problem(args.config)
+        out = {k: v.get() for k, v in jobs.items()}
+    out["main"] = main_p
+    return out
+
+
+def batch_bench(rd, torch, probs, args):
+    """The uneven batch: autotune the rotation batch per canvas edge, capture all
+    registrations (search + top-16 + refinement) in one graph, replay it, and
+    time the same work issued eagerly handle after handle."""
+    import numpy as np
+    mk = lambda p, **kw: rd.register_init(p.vertices, p.faces, p.touchable, p.poses, p.so3, p.n, p.h, p.center,
+                                          p.radius, p.length, **kw)
+    tuned = {}
+    for p in probs:
+        if p.n not in tuned:
+            h = mk(p)
+            tuned[p.n] = rd.register_autotune(h, 256)
+            rd.register_free(h)
+    hs = [mk(p) for p in probs]
+    try:
+        t0 = time.perf_counter()
+        for h in hs:
+            sc, _, po = rd.score_rotations(h, shift=False)
+            top = rd.register_top_k(h, sc, 16)
+            rd.refine_se3(h, po[top.long()])
+        torch.cuda.synchronize()
+        eager = time.perf_counter() - t0
+        b = rd.Batch(hs, top_k=16, graph_rounds=64)
+        try:
+            b.run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.batch_reps):
+                b.run()
+            torch.cuda.synchronize()
+            graph = (time.perf_counter() - t0) / args.batch_reps
+        finally:
+            b.close()
+    finally:
+        for h in hs:
+            rd.register_free(h)
+    rot = sum(len(p.so3) for p in probs)
+    return {"registrations": len(probs), "rotations": rot, "canvases": sorted({p.n for p in probs}),
+            "tuned_batch": {str(k): v for k, v in sorted(tuned.items())},
+            "graph_ms": graph * 1e3, "graph_rotations_per_s": rot / graph,
+            "eager_ms": eager * 1e3, "eager_rotations_per_s": rot / eager,
+            "work": "per registration: every rotation scored, top-16, refinement of the 16 starts"}
+
+
+def serve_bench(rd, reqs, args):
+    """A Poisson stream of registrations through the server, serial (one at a
+    time, the plain path) and continuous (several in flight on their own
+    streams); latency = completion - arrival."""
+    import threading
+
+    import numpy as np
+
+    import synth
+    arr = synth.serve_arrivals(len(reqs), args.serve_rate)
+    out = {}
+    for mode, slots in (("serial", 1), ("continuous", args.serve_slots)):
+        srv = rd.Server(max_inflight=slots, mode=mode)
+        tickets = [None] * len(reqs)
+        t0 = time.perf_counter()
+
+        def feed():
+            for i, (mid, p) in enumerate(reqs):
+                d = arr[i] - (time.perf_counter() - t0)
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = srv.submit(p.vertices, p.faces, p.touchable, p.poses, p.so3, p.n, p.h, p.center,
+                                        p.radius, p.length, object_id=mid)
+
+        th = threading.Thread(target=feed)
+        th.start()
+        th.join()
+        res = [srv.wait(t) for t in tickets]
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        lat = np.array([(r["t_end_ns"] - r["t_submit_ns"]) / 1e6 for r in res])
+        run = np.array([(r["t_end_ns"] - r["t_start_ns"]) / 1e6 for r in res])
+        out[mode] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                     "mean_run_ms": float(run.mean()), "served_per_s": len(res) / wall, "slots": slots,
+                     "cache_hits": st["cache_hits"], "cache_misses": st["cache_misses"]}
+    rot = sum(len(p.so3) for _, p in reqs)
+    out["requests"] = len(reqs)
+    out["offered_per_s"] = args.serve_rate
+    out["rotations"] = rot
+    out["workload"] = ("Poisson arrivals; 20 objects; 90 % canvases 48..128 with 512..4096 rotations, 10 % 160^3 "
+                       "with 8192; 300..2000 probe poses; search + top-16 + refinement per request")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +193,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=8, help="oracle rotations in the CPU baseline (0: skip)")
+    ap.add_argument("--batch", type=int, default=32, help="registrations of the uneven batch (0: skip)")
+    ap.add_argument("--batch-reps", type=int, default=2)
+    ap.add_argument("--serve", type=int, default=48, help="requests of the serving run (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate (requests/s)")
+    ap.add_argument("--serve-slots", type=int, default=4)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -83,15 +205,17 @@ def main():
               "range across GPUs, which this build does not launch.", file=sys.stderr)
         sys.exit(2)
 
+    work = generate(args)
+    print("bench: workloads generated", file=sys.stderr, flush=True)
+
     import numpy as np
     import torch
 
     import paper_2605_21398_amd as rd
-    import synth
 
     rd.load_library()
     torch.cuda.set_device(0)
-    p = synth.config_problem(args.config)
+    p = work["main"]
     dev = lambda x, dt: torch.from_numpy(np.ascontiguousarray(x)).to("cuda", dt)
     V, F, T = dev(p.vertices, torch.float32), dev(p.faces, torch.int32), dev(p.touchable, torch.uint8)
     P, Q = dev(p.poses, torch.float32), dev(p.so3, torch.float32)
@@ -179,6 +303,13 @@ def main():
                    "evaluations": info["evaluations"], "accepted_steps": [int(x) for x in info["iters"]],
                    "best_J": float(np.min(info["J"]))},
     }
+    print("bench: timed steps done", file=sys.stderr, flush=True)
+    if args.batch > 0:
+        out["batch"] = batch_bench(rd, torch, work["batch"], args)
+        print("bench: uneven batch done", file=sys.stderr, flush=True)
+    if args.serve > 0:
+        out["serving"] = serve_bench(rd, work["serve"], args)
+        print("bench: serving done", file=sys.stderr, flush=True)
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_sample, info["starts"], int(info["evaluations"]))
     print(json.dumps(out), flush=True)
