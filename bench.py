@@ -69,6 +69,26 @@ def cpu_baseline(p, n_sample: int, starts, evals: int):
                        f"threads) times the {evals} evaluations of the {len(starts)} starts")}
 
 
+def counter_traffic(kernel: str, n: int):
+    """HBM bytes per launch of `kernel` at edge n from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's counters), or
+    None when there is none or the kernel source has changed since."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "traffic_search_128.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    data = json.loads(m.group(1))
+    src = os.path.join(ROOT, "paper_2605_21398_amd", "csrc", "search_kernels.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != data.get("search_kernels_sha256"):
+        return None
+    k = data["kernels"].get(f"{kernel}<{n}>")
+    return None if k is None else k["traffic_bytes"]
+
+
 def _gen_batch(i):
     import synth
     return synth.batch_problem(i)
@@ -198,6 +218,8 @@ def main():
     ap.add_argument("--serve", type=int, default=48, help="requests of the serving run (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate (requests/s)")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="issue one plain 512 MiB device copy first (the counter calibration of the traffic figure)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -216,6 +238,12 @@ def main():
     rd.load_library()
     torch.cuda.set_device(0)
     p = work["main"]
+    if args.traffic_probe:
+        src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     dev = lambda x, dt: torch.from_numpy(np.ascontiguousarray(x)).to("cuda", dt)
     V, F, T = dev(p.vertices, torch.float32), dev(p.faces, torch.int32), dev(p.touchable, torch.uint8)
     P, Q = dev(p.poses, torch.float32), dev(p.so3, torch.float32)
@@ -293,7 +321,9 @@ def main():
         "config": {"workload": workload_name(p, args.config), "n": p.n, "h_mm": p.h, "rotations": M,
                    "poses": len(p.poses), "faces": len(p.faces), "batch": B, "top_k": K_TOP},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["achieved_GBps"], "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": d["achieved_GBps"] / HBM_PEAK_GBPS, "traffic": None},
+                     "unit": "GB/s", "frac": d["achieved_GBps"] / HBM_PEAK_GBPS,
+                     "traffic": counter_traffic(dom, p.n) if d["rotations_per_launch"] == 32 else None,
+                     "algorithmic_bytes_per_launch": d["algorithmic_bytes_per_launch"]},
         "latency_ms": {"p50": float(np.percentile(lat, 50)) * 1e3, "p99": float(np.percentile(lat, 99)) * 1e3,
                        "mode": "serial, one request at a time"},
         "score_phase": {"ms_per_step": score_s * 1e3, "rotations_per_s": M / score_s,
