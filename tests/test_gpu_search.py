@@ -101,7 +101,8 @@ def test_object_grid_and_swept_match_oracle(cfg, over):
 
 @pytest.mark.parametrize("n,h,M,batch,rescore", [(32, 0.4, 64, 0, 0), (32, 0.4, 64, 0, 1), (48, 0.3, 13, 8, 1),
                                                  (60, 0.25, 11, 0, 0), (64, 0.25, 16, 8, 1), (80, 0.2, 9, 0, 0),
-                                                 (16, 0.8, 10, 8, 1)])
+                                                 (16, 0.8, 10, 8, 1), (96, 0.16, 5, 0, 0), (120, 0.128, 3, 8, 1),
+                                                 (160, 0.096, 2, 0, 0)])
 def test_correlation_field_matches_oracle(n, h, M, batch, rescore):
     """Element-wise correlation field and peak of every rotation, with the
     oracle's O and S_w injected (several tiles, ragged batches); rescore=1
@@ -167,6 +168,17 @@ def test_top_k_ties_and_ragged():
     import torch
     out = rd.register_top_k(handle, torch.from_numpy(s).cuda(), 12).cpu().numpy()
     assert list(out[:9]) == list(S.top_k(s, 9)) and list(out[9:]) == [-1, -1, -1]
+    # an empty call enqueues nothing and leaves the outputs untouched
+    sc = torch.full((4,), 7.0, device="cuda")
+    rd.score_rotations(handle, 3, 0, out=(sc, None, None))
+    assert (sc.cpu().numpy() == 7.0).all()
+    # a single-rotation call at the end of the set (a ragged last batch of one):
+    # each call certifies against its own tolerance (1e-4 of its largest score),
+    # so the value may come from the float32 field or an exact re-score, both
+    # within the tolerance of the full call's
+    one = rd.score_rotations(handle, 15, 1)[0].cpu().numpy()
+    full = rd.score_rotations(handle)[0].cpu().numpy()
+    assert abs(float(one[0]) - float(full[15])) <= TOL_REL * np.abs(full).max()
 
 
 def test_abi_rejects_bad_inputs():
