@@ -164,46 +164,49 @@ def batch_bench(rd, torch, probs, args):
 def serve_bench(rd, reqs, args):
     """A Poisson stream of registrations through the server, serial (one at a
     time, the plain path) and continuous (several in flight on their own
-    streams); latency = completion - arrival."""
+    streams), at the workload's overloaded rate and at a rate the serial path
+    sustains; latency = completion - submission."""
     import threading
 
     import numpy as np
 
     import synth
-    arr = synth.serve_arrivals(len(reqs), args.serve_rate)
-    out = {}
-    for mode, slots in (("serial", 1), ("continuous", args.serve_slots)):
-        srv = rd.Server(max_inflight=slots, mode=mode)
-        tickets = [None] * len(reqs)
-        t0 = time.perf_counter()
+    runs = []
+    for rate in (args.serve_rate, args.serve_sustained):
+        if rate <= 0:
+            continue
+        arr = synth.serve_arrivals(len(reqs), rate)
+        run = {"offered_per_s": rate}
+        for mode, slots in (("serial", 1), ("continuous", args.serve_slots)):
+            srv = rd.Server(max_inflight=slots, mode=mode)
+            tickets = [None] * len(reqs)
+            t0 = time.perf_counter()
 
-        def feed():
-            for i, (mid, p) in enumerate(reqs):
-                d = arr[i] - (time.perf_counter() - t0)
-                if d > 0:
-                    time.sleep(d)
-                tickets[i] = srv.submit(p.vertices, p.faces, p.touchable, p.poses, p.so3, p.n, p.h, p.center,
-                                        p.radius, p.length, object_id=mid)
+            def feed():
+                for i, (mid, p) in enumerate(reqs):
+                    d = arr[i] - (time.perf_counter() - t0)
+                    if d > 0:
+                        time.sleep(d)
+                    tickets[i] = srv.submit(p.vertices, p.faces, p.touchable, p.poses, p.so3, p.n, p.h, p.center,
+                                            p.radius, p.length, object_id=mid)
 
-        th = threading.Thread(target=feed)
-        th.start()
-        th.join()
-        res = [srv.wait(t) for t in tickets]
-        wall = time.perf_counter() - t0
-        st = srv.stats()
-        srv.close()
-        lat = np.array([(r["t_end_ns"] - r["t_submit_ns"]) / 1e6 for r in res])
-        run = np.array([(r["t_end_ns"] - r["t_start_ns"]) / 1e6 for r in res])
-        out[mode] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                     "mean_run_ms": float(run.mean()), "served_per_s": len(res) / wall, "slots": slots,
-                     "cache_hits": st["cache_hits"], "cache_misses": st["cache_misses"]}
-    rot = sum(len(p.so3) for _, p in reqs)
-    out["requests"] = len(reqs)
-    out["offered_per_s"] = args.serve_rate
-    out["rotations"] = rot
-    out["workload"] = ("Poisson arrivals; 20 objects; 90 % canvases 48..128 with 512..4096 rotations, 10 % 160^3 "
-                       "with 8192; 300..2000 probe poses; search + top-16 + refinement per request")
-    return out
+            th = threading.Thread(target=feed)
+            th.start()
+            th.join()
+            res = [srv.wait(t) for t in tickets]
+            wall = time.perf_counter() - t0
+            st = srv.stats()
+            srv.close()
+            lat = np.array([(r["t_end_ns"] - r["t_submit_ns"]) / 1e6 for r in res])
+            busy = np.array([(r["t_end_ns"] - r["t_start_ns"]) / 1e6 for r in res])
+            run[mode] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                         "mean_run_ms": float(busy.mean()), "served_per_s": len(res) / wall, "slots": slots,
+                         "cache_hits": st["cache_hits"], "cache_misses": st["cache_misses"]}
+        runs.append(run)
+        print(f"bench: serving at {rate}/s done", file=sys.stderr, flush=True)
+    return {"requests": len(reqs), "rotations": sum(len(p.so3) for _, p in reqs), "runs": runs,
+            "workload": ("Poisson arrivals; 20 objects; 90 % canvases 48..128 with 512..4096 rotations, 10 % 160^3 "
+                         "with 8192; 300..2000 probe poses; search + top-16 + refinement per request")}
 
 
 def main():
@@ -217,6 +220,8 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=2)
     ap.add_argument("--serve", type=int, default=48, help="requests of the serving run (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate (requests/s)")
+    ap.add_argument("--serve-sustained", type=float, default=6.0,
+                    help="a second arrival rate below the serial path's capacity (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="issue one plain 512 MiB device copy first (the counter calibration of the traffic figure)")
