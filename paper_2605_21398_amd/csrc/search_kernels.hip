@@ -58,7 +58,12 @@ template <int N> struct Canvas {
     static constexpr int NT2 = N2 / T;                    // main tiles per ky row
     static constexpr int TILES = N * NT2 + N / T;         // tiles per rotation
     static constexpr size_t H = (size_t)N * P * N;        // complex per rotation
-    static constexpr int NT = 256;                        // threads per workgroup
+    // threads of a plane workgroup: the plane fills most of the LDS, so only
+    // one or two workgroups fit per CU; from 128^3 up a workgroup of 8 waves
+    // gives each SIMD more waves to hide LDS and barrier latency
+    static constexpr int NT = N >= 128 ? 512 : 256;
+    static constexpr int WPE = N == 128 ? 4 : 1;          // waves per SIMD asked of the compiler
+    static constexpr int ZT = 256;                        // threads of a z-pencil workgroup
     static_assert(N % 2 == 0, "canvas edge must be even");
     static_assert(fft_supported(N) && fft_supported(N2), "edge must be 2^a 3^b 5^c");
     static_assert((size_t)N * P * 8 <= 160 * 1024, "plane must fit in LDS");
@@ -440,7 +445,7 @@ __device__ __forceinline__ void generate_plane(float2* plane, const RotSampler& 
 // ------------------------------------------------------------------ pass 1
 
 template <int N>
-__global__ __launch_bounds__(256) void k_rotvox_fwd_xy(const uint8_t* __restrict__ cmask, int m, int mb,
+__global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_rotvox_fwd_xy(const uint8_t* __restrict__ cmask, int m, int mb,
                                                        const double* __restrict__ rots, int count,
                                                        const float2* __restrict__ twg, const double2* __restrict__ tw64,
                                                        float2* __restrict__ spec, double2* __restrict__ lowT) {
@@ -465,7 +470,7 @@ __global__ __launch_bounds__(256) void k_rotvox_fwd_xy(const uint8_t* __restrict
 
 // pass 1 on a real grid (the object grid O): same transform, no rotation
 template <int N>
-__global__ __launch_bounds__(256) void k_grid_fwd_xy(const float* __restrict__ grid, const float2* __restrict__ twg,
+__global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_grid_fwd_xy(const float* __restrict__ grid, const float2* __restrict__ twg,
                                                      const double2* __restrict__ tw64, float2* __restrict__ spec,
                                                      double2* __restrict__ lowT) {
     using C = Canvas<N>;
@@ -500,26 +505,26 @@ __global__ __launch_bounds__(256) void k_zpass(float2* __restrict__ spec, const 
     __shared__ float2 tw[N];
     const int tile = blockIdx.x % C::TILES, rot = blockIdx.x / C::TILES;
     float2* src = spec + (size_t)rot * C::H + (size_t)tile * E;
-    for (int i = threadIdx.x; i < N; i += C::NT) tw[i] = twg[i];
-    for (int i = threadIdx.x; i < E; i += C::NT) buf[i] = src[i];
+    for (int i = threadIdx.x; i < N; i += C::ZT) tw[i] = twg[i];
+    for (int i = threadIdx.x; i < E; i += C::ZT) buf[i] = src[i];
     __syncthreads();
-    fft_lds<N, false, C::T, C::NT, true, N>(buf, C::T, 1, tw);
+    fft_lds<N, false, C::T, C::ZT, true, N>(buf, C::T, 1, tw);
     if (MODE == 0) {
         const float2* w = W + (size_t)tile * E;
         // the low block (max(|kx|,|ky|,|kz|) <= KLOW) is carried exactly elsewhere
         const int ky = tile / C::NT2;
         const bool low_tile = tile < N * C::NT2 && (tile % C::NT2) == 0 && (ky <= KLOW || ky >= N - KLOW);
-        for (int i = threadIdx.x; i < E; i += C::NT) {
+        for (int i = threadIdx.x; i < E; i += C::ZT) {
             const int kz = i / C::T, kx = i % C::T;
             const bool low = low_tile && kx <= KLOW && (kz <= KLOW || kz >= N - KLOW);
             buf[i] = low ? make_float2(0.0f, 0.0f) : cmul(buf[i], w[i]);
         }
         __syncthreads();
-        fft_lds<N, true, C::T, C::NT, true, N>(buf, C::T, 1, tw);
-        for (int i = threadIdx.x; i < E; i += C::NT) src[i] = buf[i];
+        fft_lds<N, true, C::T, C::ZT, true, N>(buf, C::T, 1, tw);
+        for (int i = threadIdx.x; i < E; i += C::ZT) src[i] = buf[i];
     } else {
         float2* dst = wout + (size_t)tile * E;
-        for (int i = threadIdx.x; i < E; i += C::NT) dst[i] = cscale(cconj(buf[i]), scale);
+        for (int i = threadIdx.x; i < E; i += C::ZT) dst[i] = cscale(cconj(buf[i]), scale);
     }
 }
 
@@ -559,7 +564,7 @@ __device__ __forceinline__ double key_value(unsigned long long k) {
 __device__ __forceinline__ uint32_t key_flat(unsigned long long k) { return 0x3fffffu - (uint32_t)(k & 0x3fffffull); }
 
 template <int N>
-__global__ __launch_bounds__(256) void k_inv_xy_argmax(const float2* __restrict__ spec, int count, const float2* __restrict__ twg,
+__global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_inv_xy_argmax(const float2* __restrict__ spec, int count, const float2* __restrict__ twg,
                                                        const double2* __restrict__ tw64, const double2* __restrict__ Plow,
                                                        unsigned long long* __restrict__ ptop, double* __restrict__ pssq,
                                                        float* __restrict__ corr_out) {
@@ -1416,7 +1421,7 @@ static hipError_t launch_search_pass(int pass, const SearchBatchArgs& a) {
     else if (pass == 1) {
         hipLaunchKernelGGL((k_low_combine<0>), dim3(a.count * NLOW2), dim3(256), 0, a.stream, a.lowT, N, a.tw64, a.Wlow, 1.0,
                            a.Plow);
-        hipLaunchKernelGGL((k_zpass<N, 0>), dim3(a.count * C::TILES), dim3(C::NT), 0, a.stream, a.spec, a.W, nullptr, a.tw,
+        hipLaunchKernelGGL((k_zpass<N, 0>), dim3(a.count * C::TILES), dim3(C::ZT), 0, a.stream, a.spec, a.W, nullptr, a.tw,
                            1.0f);
     } else {
         hipLaunchKernelGGL(k_inv_xy_argmax<N>, dim3(a.count * N), dim3(C::NT), 0, a.stream, a.spec, a.count, a.tw, a.tw64,
@@ -1431,7 +1436,7 @@ static hipError_t launch_object_spectrum(const float* O, float2* spec_tmp, float
     using C = Canvas<N>;
     const double scale = 1.0 / ((double)N * N * N);
     hipLaunchKernelGGL(k_grid_fwd_xy<N>, dim3(N), dim3(C::NT), 0, s, O, tw, tw64, spec_tmp, lowT_tmp);
-    hipLaunchKernelGGL((k_zpass<N, 1>), dim3(C::TILES), dim3(C::NT), 0, s, spec_tmp, nullptr, W, tw, (float)scale);
+    hipLaunchKernelGGL((k_zpass<N, 1>), dim3(C::TILES), dim3(C::ZT), 0, s, spec_tmp, nullptr, W, tw, (float)scale);
     hipLaunchKernelGGL((k_low_combine<1>), dim3(NLOW2), dim3(256), 0, s, lowT_tmp, N, tw64, nullptr, scale, Wlow);
     return hipGetLastError();
 }
