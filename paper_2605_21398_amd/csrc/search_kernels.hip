@@ -58,11 +58,12 @@ template <int N> struct Canvas {
     static constexpr int NT2 = N2 / T;                    // main tiles per ky row
     static constexpr int TILES = N * NT2 + N / T;         // tiles per rotation
     static constexpr size_t H = (size_t)N * P * N;        // complex per rotation
-    // threads of a plane workgroup: the plane fills most of the LDS, so only
-    // one or two workgroups fit per CU; from 128^3 up a workgroup of 8 waves
-    // gives each SIMD more waves to hide LDS and barrier latency
-    static constexpr int NT = N >= 128 ? 512 : 256;
-    static constexpr int WPE = N == 128 ? 4 : 1;          // waves per SIMD asked of the compiler
+    // threads of a plane workgroup: from 96^3 up the plane fills enough LDS
+    // that only one to three workgroups fit per CU, and workgroups of 8 (16
+    // above 128^3, where one fits) waves give each SIMD more waves to hide LDS
+    // and barrier latency
+    static constexpr int NT = N > 128 ? 1024 : N >= 96 ? 512 : 256;
+    static constexpr int WPE = N >= 96 ? 4 : 1;  // waves per SIMD asked of the compiler
     static constexpr int ZT = 256;                        // threads of a z-pencil workgroup
     static_assert(N % 2 == 0, "canvas edge must be even");
     static_assert(fft_supported(N) && fft_supported(N2), "edge must be 2^a 3^b 5^c");
