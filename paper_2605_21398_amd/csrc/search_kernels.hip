@@ -116,6 +116,26 @@ __device__ __forceinline__ float trilinear_mask(uint32_t mk, float fx, float fy,
     return c0 * gz + c1 * fz;
 }
 
+// Global -> LDS copy of COUNT elements by NTH threads with every thread's
+// loads issued before the first is waited for (a loop that stores each load
+// to LDS before issuing the next pays one memory latency per element):
+// dst(e, src(e)) for e in [0, COUNT).
+template <int COUNT, int NTH, class Src, class Dst>
+__device__ __forceinline__ void batched_copy(Src src, Dst dst) {
+    constexpr int PER = (COUNT + NTH - 1) / NTH;
+    float2 v[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = threadIdx.x + i * NTH;
+        if (COUNT % NTH == 0 || e < COUNT) v[i] = src(e);
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = threadIdx.x + i * NTH;
+        if (COUNT % NTH == 0 || e < COUNT) dst(e, v[i]);
+    }
+}
+
 // ------------------------------------------------------------- plane FFTs
 // The plane lives in LDS as [y][kx] with pitch P = N/2 + 1 complex.
 
@@ -507,7 +527,7 @@ __global__ __launch_bounds__(256) void k_zpass(float2* __restrict__ spec, const 
     const int tile = blockIdx.x % C::TILES, rot = blockIdx.x / C::TILES;
     float2* src = spec + (size_t)rot * C::H + (size_t)tile * E;
     for (int i = threadIdx.x; i < N; i += C::ZT) tw[i] = twg[i];
-    for (int i = threadIdx.x; i < E; i += C::ZT) buf[i] = src[i];
+    batched_copy<E, C::ZT>([&](int i) { return src[i]; }, [&](int i, float2 v) { buf[i] = v; });
     __syncthreads();
     fft_lds<N, false, C::T, C::ZT, true, N>(buf, C::T, 1, tw);
     if (MODE == 0) {
@@ -585,13 +605,15 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_inv_xy_argmax
         tws[i] = tw64[i];
     }
     const float2* spec_rot = spec + (size_t)rot * C::H;
-    for (int e = threadIdx.x; e < N * C::N2; e += C::NT) {
-        const int ky = e / C::N2, kx = e % C::N2;
-        plane[ky * C::P + kx] = spec_rot[((size_t)(ky * C::NT2 + kx / C::T) * N + z) * C::T + (kx % C::T)];
-    }
+    batched_copy<N * C::N2, C::NT>(
+        [&](int e) {
+            const int ky = e / C::N2, kx = e % C::N2;
+            return spec_rot[((size_t)(ky * C::NT2 + kx / C::T) * N + z) * C::T + (kx % C::T)];
+        },
+        [&](int e, float2 v) { plane[(e / C::N2) * C::P + e % C::N2] = v; });
     const float2* nyq = spec_rot + (size_t)N * C::N2 * N;
-    for (int ky = threadIdx.x; ky < N; ky += C::NT)
-        plane[ky * C::P + C::N2] = nyq[((size_t)(ky / C::T) * N + z) * C::T + (ky % C::T)];
+    batched_copy<N, C::NT>([&](int ky) { return nyq[((size_t)(ky / C::T) * N + z) * C::T + (ky % C::T)]; },
+                           [&](int ky, float2 v) { plane[ky * C::P + C::N2] = v; });
     __syncthreads();
     // low block of this plane: az[kx][ky] = sum_kz P[kx][ky][kz] e^{+2 pi i kz z / N}
     {
