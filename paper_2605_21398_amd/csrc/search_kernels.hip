@@ -205,10 +205,12 @@ __device__ __forceinline__ void plane_forward_and_store(float2* plane, const flo
     fft_lds<C::N2, false, N, C::NT, true, N>(plane, 1, C::P, tw);
     r2c_post<N>(plane, tw);
     fft_lds<N, false, C::P, C::NT, true, N>(plane, C::P, 1, tw);
-    for (int e = threadIdx.x; e < N * C::N2; e += C::NT) {
-        const int ky = e / C::N2, kx = e % C::N2;
-        spec_rot[((size_t)(ky * C::NT2 + kx / C::T) * N + z) * C::T + (kx % C::T)] = plane[ky * C::P + kx];
-    }
+    // LDS reads first, then the global stores
+    batched_copy<N * C::N2, C::NT>([&](int e) { return plane[(e / C::N2) * C::P + e % C::N2]; },
+                                   [&](int e, float2 v) {
+                                       const int ky = e / C::N2, kx = e % C::N2;
+                                       spec_rot[((size_t)(ky * C::NT2 + kx / C::T) * N + z) * C::T + (kx % C::T)] = v;
+                                   });
     float2* nyq = spec_rot + (size_t)N * C::N2 * N;
     for (int ky = threadIdx.x; ky < N; ky += C::NT)
         nyq[((size_t)(ky / C::T) * N + z) * C::T + (ky % C::T)] = plane[ky * C::P + C::N2];
@@ -657,6 +659,9 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_inv_xy_argmax
             w0[k] = tws[(k * 2 * j) % N];
             w1[k] = tws[(k * (2 * j + 1)) % N];
         }
+        // value of the fourth key so far: a voxel below it cannot enter the
+        // list, so its key is formed only at or above it
+        double thr = -INFINITY;
         for (int y = threadIdx.x / C::N2; y < N; y += C::NT / C::N2) {
             const float2 v = plane[y * C::P + j];
             const uint32_t flat0 = (uint32_t)(((z * N) + y) * N + 2 * j);
@@ -669,9 +674,12 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_inv_xy_argmax
                 c1 = fma(2.0 * bk.x, w1[k].x, fma(2.0 * bk.y, w1[k].y, c1));
             }
             const double v0 = (double)v.x + c0, v1 = (double)v.y + c1;
-            const unsigned long long k0 = key64(v0, flat0), k1 = key64(v1, flat0 + 1);
-            if (k0 > t3) top4_insert(k0, t0, t1, t2, t3);
-            if (k1 > t3) top4_insert(k1, t0, t1, t2, t3);
+            if (v0 >= thr || v1 >= thr) {
+                const unsigned long long k0 = key64(v0, flat0), k1 = key64(v1, flat0 + 1);
+                if (k0 > t3) top4_insert(k0, t0, t1, t2, t3);
+                if (k1 > t3) top4_insert(k1, t0, t1, t2, t3);
+                thr = t3 ? key_value(t3) : -INFINITY;
+            }
             ss = fmaf(v.x, v.x, fmaf(v.y, v.y, ss));
             if (corr_out) {
                 corr_out[flat0] = (float)v0;
@@ -679,6 +687,7 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_inv_xy_argmax
             }
         }
     } else {
+        double thr = -INFINITY;  // as in the path above
         for (int e = threadIdx.x; e < N * C::N2; e += C::NT) {
             const int y = e / C::N2, j = e % C::N2;
             const float2 v = plane[y * C::P + j];
@@ -694,9 +703,12 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_inv_xy_argmax
                 c1 = fma(2.0 * bk.x, w1.x, fma(2.0 * bk.y, w1.y, c1));
             }
             const double v0 = (double)v.x + c0, v1 = (double)v.y + c1;
-            const unsigned long long k0 = key64(v0, flat0), k1 = key64(v1, flat0 + 1);
-            if (k0 > t3) top4_insert(k0, t0, t1, t2, t3);
-            if (k1 > t3) top4_insert(k1, t0, t1, t2, t3);
+            if (v0 >= thr || v1 >= thr) {
+                const unsigned long long k0 = key64(v0, flat0), k1 = key64(v1, flat0 + 1);
+                if (k0 > t3) top4_insert(k0, t0, t1, t2, t3);
+                if (k1 > t3) top4_insert(k1, t0, t1, t2, t3);
+                thr = t3 ? key_value(t3) : -INFINITY;
+            }
             ss = fmaf(v.x, v.x, fmaf(v.y, v.y, ss));
             if (corr_out) {
                 corr_out[flat0] = (float)v0;
