@@ -439,7 +439,8 @@ static int ensure_refine_buffers(reg_handle* h, int K) {
         ALLOC_TRY(h, h->rw.qst, nq);
         ALLOC_TRY(h, h->rw.pairs, 16 * nq);
         ALLOC_TRY(h, h->rw.pres, 16 * nq);
-        if (!h->rw.pair_count) ALLOC_TRY(h, h->rw.pair_count, 1);
+        ALLOC_TRY(h, h->rw.nest, 16 * nq);
+        if (!h->rw.pair_count) ALLOC_TRY(h, h->rw.pair_count, 2);
         h->rw.pair_cap = (int)std::min<size_t>(16 * nq, 1u << 30);
         h->r_cap = cap;
     }
@@ -1159,7 +1160,7 @@ Footprint footprint(int n, int n_rot, int n_poses, int nv, int nf, int batch, in
     f.request = H * B * 8 + B * n * KTOP * 8 + B * n * 8 + B * n * NLOW2 * 16 + B * NLOW3 * 16 + M * per_rot +
                 M * (4 + 56) + 28 * N + 48 * N + m * m * m + mp * mp * mp + 8 * n3 + n * n * ((n + 31) / 32) * 4 +
                 K * (sizeof(RefineState) + REF_TMAX * (sizeof(RefineTrial) + sizeof(RefineEval))) +
-                nq * (sizeof(RefineHit) + 48 + 8 + 4 + 8 + 16 * (8 + 16)) + 4096;
+                nq * (sizeof(RefineHit) + 48 + 8 + 4 + 8 + 16 * (8 + 16 + 4)) + 4096;
     return f;
 }
 

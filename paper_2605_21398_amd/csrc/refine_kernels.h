@@ -30,10 +30,11 @@ struct RefineScratch {
     unsigned long long* qkey;   // best (value, face index) key
     int* qflag;                 // 0: no face kept, 1: key valid, 2: pair list overflowed
     float2* qst;                // barycentric witness of the winning search (-1: a vertex won)
-    int2* pairs;                // (query, face slot) pairs for a golden-section search
+    int2* pairs;                // (query, face slot) pairs for a face search
     float4* pres;               // per pair: minimum, s, t
-    int* pair_count;
-    int pair_cap;
+    int* nest;                  // pairs left to the nested golden-section search (indices into pairs)
+    int* pair_count;            // [pairs, nested pairs]
+    int pair_cap;               // capacity of pairs, pres and nest
 };
 
 struct RefineConst {

@@ -30,6 +30,7 @@ constexpr float EDGE_TOL = 1e-4f;         // barycentric distance below which a 
 constexpr float INVPHI_F = 0.618033988749894848f;
 constexpr float BOUND_SLACK = 1e-5f;      // float32 rounding allowance of the face bounds (mm)
 constexpr float VERTEX_GAP = 2e-6f;       // bounds this close: the best vertex is the face minimum (mm)
+constexpr float CERT_TOL = 4e-6f;         // a boundary point this close to a lower bound is the face minimum (mm)
 
 // ------------------------------------------------------------ FP64 rotations
 
@@ -153,7 +154,7 @@ __device__ float inner_min(const Tri& T, float s, float tmax, float& t_out) {
 
 // min of the probe SDF over the triangle p0 + s e1 + t e2 (s, t >= 0, s + t <= 1).
 // f is convex, so is its partial minimum over t; nested golden sections.
-__device__ float face_min(const Tri& T, float& s_out, float& t_out) {
+__device__ float face_min_nested(const Tri& T, float& s_out, float& t_out) {
     float a = 0.0f, b = 1.0f, tt;
     float c = b - INVPHI_F * (b - a), d = a + INVPHI_F * (b - a);
     float fc = inner_min(T, c, 1.0f - c, tt), fd = inner_min(T, d, 1.0f - d, tt);
@@ -176,6 +177,170 @@ __device__ float face_min(const Tri& T, float& s_out, float& t_out) {
 }
 
 __device__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+__device__ __forceinline__ float3 f3sub(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ float3 f3add(float3 a, float3 b) { return make_float3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ float3 f3scale(float3 a, float k) { return make_float3(k * a.x, k * a.y, k * a.z); }
+
+// the probe's point farthest along m (its support point): the rim in the
+// direction of m's xy part, on the cap m.z points to
+__device__ __forceinline__ float3 probe_support(float3 m, float r, float L) {
+    const float h = hw_sqrt(m.x * m.x + m.y * m.y);
+    const float k = h > 0.0f ? r / h : 0.0f;
+    return make_float3(k * m.x, k * m.y, m.z > 0.0f ? L : 0.0f);
+}
+
+// min of f_p over the segment P + l D, l in [0, 1], given the values and
+// subgradients at its ends.  f_p is convex: an end whose subgradient does not
+// descend into the segment holds the minimum; otherwise golden section over
+// l, then the ends.
+__device__ float seg_min(float3 P, float3 D, float f0, float3 g0, float f1, float3 g1, float r, float L,
+                         float& l_out) {
+    if (dot3(g0, D) >= 0.0f) {
+        l_out = 0.0f;
+        return f0;
+    }
+    if (dot3(g1, D) <= 0.0f) {
+        l_out = 1.0f;
+        return f1;
+    }
+    auto at = [&](float l) { return sdf_f(P.x + l * D.x, P.y + l * D.y, P.z + l * D.z, r, L); };
+    float a = 0.0f, b = 1.0f;
+    float c = b - INVPHI_F * (b - a), d = a + INVPHI_F * (b - a);
+    float fc = at(c), fd = at(d);
+    while (b - a > GOLD_TOL) {
+        if (fc <= fd) {
+            b = d; d = c; fd = fc; c = b - INVPHI_F * (b - a); fc = at(c);
+        } else {
+            a = c; c = d; fc = fd; d = a + INVPHI_F * (b - a); fd = at(d);
+        }
+    }
+    float lm = 0.5f * (a + b), fm = at(lm);
+    if (f0 < fm) { fm = f0; lm = 0.0f; }
+    if (f1 < fm) { fm = f1; lm = 1.0f; }
+    l_out = lm;
+    return fm;
+}
+
+// Lower bound of f_p over the triangle with vertices xb + w_j from the
+// supporting half-space of the probe with unit normal m: f_p(y) >= m . y -
+// max_C m . x for every y (inside the probe too), minimised over the vertices.
+__device__ __forceinline__ float plane_lb(float3 m, float3 xb, float3 w0, float3 w1, float3 w2, float r, float L) {
+    const float3 sp = probe_support(m, r, L);
+    return fminf(dot3(m, w0), fminf(dot3(m, w1), dot3(m, w2))) + dot3(m, f3sub(xb, sp));
+}
+
+// Lower bound of f_p over the triangle from the two branches at xb:
+// f_p >= max(q1, q2) >= a q1 + (1 - a) q2 for a in [0, 1], with q1 = rho - r
+// and q2 = |z - L/2| - L/2 convex and bounded below by their tangent planes at
+// xb.  Over the triangle this is min_j (c_j + a d_j), maximised over a at 0,
+// 1 and the crossings of the three lines.
+__device__ float ridge_lb(float3 xb, float3 w0, float3 w1, float3 w2, float r, float L) {
+    const float rho = hw_sqrt(xb.x * xb.x + xb.y * xb.y);
+    if (!(rho > 0.0f)) return -INFINITY;
+    const float q1 = rho - r, q2 = fabsf(xb.z - 0.5f * L) - 0.5f * L;
+    const float sz = xb.z >= 0.5f * L ? 1.0f : -1.0f;
+    const float ex = xb.x / rho, ey = xb.y / rho;
+    // c_j = q2 + g2 . w_j, d_j = (q1 - q2) + (g1 - g2) . w_j
+    const float c0 = q2 + sz * w0.z, c1 = q2 + sz * w1.z, c2 = q2 + sz * w2.z;
+    const float d0 = (q1 - q2) + ex * w0.x + ey * w0.y - sz * w0.z;
+    const float d1 = (q1 - q2) + ex * w1.x + ey * w1.y - sz * w1.z;
+    const float d2 = (q1 - q2) + ex * w2.x + ey * w2.y - sz * w2.z;
+    auto env = [&](float a) { return fminf(c0 + a * d0, fminf(c1 + a * d1, c2 + a * d2)); };
+    float best = fmaxf(env(0.0f), env(1.0f));
+    auto cross_at = [&](float ci, float di, float cj, float dj) {
+        if (di != dj) {
+            const float a = (cj - ci) / (di - dj);
+            if (a > 0.0f && a < 1.0f) best = fmaxf(best, env(a));
+        }
+    };
+    cross_at(c0, d0, c1, d1);
+    cross_at(c0, d0, c2, d2);
+    cross_at(c1, d1, c2, d2);
+    return best;
+}
+
+// Minimum of the probe SDF over the triangle p0 + s e1 + t e2 (s, t >= 0,
+// s + t <= 1), exact up to the golden-section bracket:
+//  * the least of the three edge minima is the boundary minimum;
+//  * if the probe lies strictly on one side of the face plane, f_p on the
+//    plane is the distance to the probe and its minimum is the projection of
+//    the probe's nearest (support) point: the face minimum if inside the
+//    face, else the minimum lies on the boundary;
+//  * otherwise the boundary minimum is the face minimum when a lower bound of
+//    f_p over the face (supporting half-spaces of the probe at the witness'
+//    normal, and the branch bound) comes within CERT_TOL of it;
+//  * else (a minimum inside the face on the side/cap ridge of a penetrating
+//    face) nested golden sections.
+// face_min_bounded stops before the last step and clears `done` instead.
+__device__ float face_min_bounded(const Tri& T, float& s_out, float& t_out, bool& done) {
+    done = true;
+    const float r = T.r, L = T.L;
+    const float3 p0 = T.p0, p1 = f3add(T.p0, T.e1), p2 = f3add(T.p0, T.e2), e12 = f3sub(T.e2, T.e1);
+    float3 g0, g1, g2;
+    const float f0 = sdf_grad_f(p0, r, L, g0), f1 = sdf_grad_f(p1, r, L, g1), f2 = sdf_grad_f(p2, r, L, g2);
+    float l, best, bs, bt;
+    float3 edge = T.e1;
+    best = seg_min(p0, T.e1, f0, g0, f1, g1, r, L, l);
+    bs = l;
+    bt = 0.0f;
+    bool inner = l > 0.0f && l < 1.0f;
+    float m = seg_min(p0, T.e2, f0, g0, f2, g2, r, L, l);
+    if (m < best) {
+        best = m; bs = 0.0f; bt = l; edge = T.e2; inner = l > 0.0f && l < 1.0f;
+    }
+    m = seg_min(p1, e12, f1, g1, f2, g2, r, L, l);
+    if (m < best) {
+        best = m; bs = 1.0f - l; bt = l; edge = e12; inner = l > 0.0f && l < 1.0f;
+    }
+    s_out = bs;
+    t_out = bt;
+    const float3 N = make_float3(T.e1.y * T.e2.z - T.e1.z * T.e2.y, T.e1.z * T.e2.x - T.e1.x * T.e2.z,
+                                 T.e1.x * T.e2.y - T.e1.y * T.e2.x);
+    const float nn = dot3(N, N);
+    if (!(nn > 0.0f)) return best;  // a degenerate face is the union of its edges
+    const float3 n = f3scale(N, 1.0f / hw_sqrt(nn));
+    const float3 sh = probe_support(n, r, L), sl = probe_support(make_float3(-n.x, -n.y, -n.z), r, L);
+    const float top = dot3(n, f3sub(sh, p0)), bot = dot3(n, f3sub(sl, p0));
+    if (bot > 0.0f || top < 0.0f) {
+        const float h = bot > 0.0f ? bot : top;
+        const float3 x = f3sub(f3sub(bot > 0.0f ? sl : sh, f3scale(n, h)), p0);
+        const float a11 = dot3(T.e1, T.e1), a12 = dot3(T.e1, T.e2), a22 = dot3(T.e2, T.e2);
+        const float b1 = dot3(x, T.e1), b2 = dot3(x, T.e2), det = a11 * a22 - a12 * a12;
+        const float s = (b1 * a22 - b2 * a12) / det, t = (b2 * a11 - b1 * a12) / det;
+        if (s >= 0.0f && t >= 0.0f && s + t <= 1.0f) {
+            const float v = T.at(s, t);
+            if (v < best) {
+                s_out = s;
+                t_out = t;
+                return v;
+            }
+        }
+        return best;
+    }
+    const float3 xb = make_float3(p0.x + bs * T.e1.x + bt * T.e2.x, p0.y + bs * T.e1.y + bt * T.e2.y,
+                                  p0.z + bs * T.e1.z + bt * T.e2.z);
+    const float3 w0 = f3sub(p0, xb), w1 = f3sub(p1, xb), w2 = f3sub(p2, xb);
+    float3 gm;
+    (void)sdf_grad_f(xb, r, L, gm);
+    float lb = fmaxf(plane_lb(gm, xb, w0, w1, w2, r, L), ridge_lb(xb, w0, w1, w2, r, L));
+    if (inner && lb < best - CERT_TOL) {
+        // at a minimum inside an edge the normal is orthogonal to the edge:
+        // drop the component the bracket error leaves along it
+        const float3 pm = f3sub(gm, f3scale(edge, dot3(gm, edge) / dot3(edge, edge)));
+        const float pn = dot3(pm, pm);
+        if (pn > 0.0f) lb = fmaxf(lb, plane_lb(f3scale(pm, 1.0f / hw_sqrt(pn)), xb, w0, w1, w2, r, L));
+    }
+    done = lb >= best - CERT_TOL;
+    return best;
+}
+
+__device__ float face_min(const Tri& T, float& s_out, float& t_out) {
+    bool done;
+    const float m = face_min_bounded(T, s_out, t_out, done);
+    return done ? m : face_min_nested(T, s_out, t_out);
+}
+
 
 // Gradient of the face minimum with respect to a motion of the face, at the
 // witness u = p0 + s e1 + t e2: grad f_p where it is differentiable; on the
@@ -266,7 +431,7 @@ __global__ void k_ref_start(const double* __restrict__ init, int K, const double
     if (k == 0) {
         counters[0] = K;
         counters[1] = 0;
-        *pair_count = 0;
+        pair_count[0] = pair_count[1] = 0;
     }
     if (k >= K) return;
     RefineState& S = st[k];
@@ -406,7 +571,7 @@ __device__ void probe_frame(const float* __restrict__ poses, int i, double* Ri, 
     pi[2] = P[6];
 }
 
-__global__ void k_ref_reset(int* __restrict__ pair_count) { *pair_count = 0; }
+__global__ void k_ref_reset(int* __restrict__ pair_count) { pair_count[0] = pair_count[1] = 0; }
 
 // refinement starts from search results: rows idx[k] of a count x 7 pose array
 __global__ void k_gather_poses(const int32_t* __restrict__ idx, const double* __restrict__ src, int K,
@@ -432,56 +597,101 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
     return v;
 }
 
-constexpr int CULL_WAVES = 4;  // queries per 256-thread block, one wavefront each
+constexpr int CULL_WAVES = 4;   // queries per 256-thread block, one wavefront each
+constexpr int CULL_LIST = 256;  // kept faces a wavefront holds in LDS between its two passes
 
-// Kept faces of one query, spread over the lanes of its wavefront: the
-// cluster spheres are tested 64 at a time, then each kept cluster's faces
-// (at most REF_FANOUT = 32) take half a wavefront.  fn(lane_has_face, slot, a0..a3)
-// is called by every lane at the same points (uniform control flow).
+// Kept faces of one query, spread over the lanes of its wavefront: the top
+// spheres are tested 64 at a time, the clusters of two kept top nodes (at most
+// REF_FANOUT = 32 each) take half a wavefront each, and so do the faces of two
+// kept clusters.  fn(lane_has_face, slot, a0..a3) is called by every lane at
+// the same points (uniform control flow).
 template <class Fn>
-__device__ void wave_kept_faces(const Xf& X, const RefineGeometry& geo, int n_cluster, float r, float L, float cull,
-                                int lane, Fn&& fn) {
-    for (int c0 = 0; c0 < n_cluster; c0 += 64) {
-        const int cl = c0 + lane;
-        const bool keep = cl < n_cluster && sphere_kept(X, geo.cluster[cl], r, L, cull);
-        unsigned long long mask = __ballot(keep);
-        while (mask) {
-            const int a = __ffsll((long long)mask) - 1;
-            mask &= mask - 1;
-            int b = -1;
-            if (mask) {
-                b = __ffsll((long long)mask) - 1;
-                mask &= mask - 1;
+__device__ void wave_kept_faces(const Xf& X, const RefineGeometry& geo, float r, float L, float cull, int lane,
+                                Fn&& fn) {
+    const int half = lane & 31;
+    for (int t0 = 0; t0 < geo.n_top; t0 += 64) {
+        const int tn = t0 + lane;
+        unsigned long long tmask = __ballot(tn < geo.n_top && sphere_kept(X, geo.top[tn], r, L, cull));
+        while (tmask) {
+            const int ta = __ffsll((long long)tmask) - 1;
+            tmask &= tmask - 1;
+            int tb = -1;
+            if (tmask) {
+                tb = __ffsll((long long)tmask) - 1;
+                tmask &= tmask - 1;
             }
-            const int mine = lane < 32 ? a : b;
-            bool has = false;
-            int f = 0;
-            float4 a0 = make_float4(0, 0, 0, 0), a1 = a0, a2 = a0, a3 = a0;
-            if (mine >= 0) {
-                const int2 fr = geo.cluster_range[c0 + mine];
-                if ((lane & 31) < fr.y) {
-                    f = fr.x + (lane & 31);
-                    a2 = geo.face[4 * f + 2];
-                    a3 = geo.face[4 * f + 3];
-                    const float3 u = X.apply(a2.y, a2.z, a2.w);
-                    has = sdf_f(u.x, u.y, u.z, r, L) < a3.x + cull;
-                    if (has) {
-                        a0 = geo.face[4 * f];
-                        a1 = geo.face[4 * f + 1];
+            const int mt = lane < 32 ? ta : tb;
+            int cl = -1;
+            if (mt >= 0) {
+                const int2 cr = geo.top_range[t0 + mt];
+                if (half < cr.y && sphere_kept(X, geo.cluster[cr.x + half], r, L, cull)) cl = cr.x + half;
+            }
+            unsigned long long cmask = __ballot(cl >= 0);
+            while (cmask) {
+                const int la = __ffsll((long long)cmask) - 1;
+                cmask &= cmask - 1;
+                int lb = -1;
+                if (cmask) {
+                    lb = __ffsll((long long)cmask) - 1;
+                    cmask &= cmask - 1;
+                }
+                const int ca = __shfl(cl, la, 64);
+                const int cb = lb >= 0 ? __shfl(cl, lb, 64) : -1;
+                const int mine = lane < 32 ? ca : cb;
+                bool has = false;
+                int f = 0;
+                float4 a0 = make_float4(0, 0, 0, 0), a1 = a0, a2 = a0, a3 = a0;
+                if (mine >= 0) {
+                    const int2 fr = geo.cluster_range[mine];
+                    if (half < fr.y) {
+                        f = fr.x + half;
+                        a2 = geo.face[4 * f + 2];
+                        a3 = geo.face[4 * f + 3];
+                        const float3 u = X.apply(a2.y, a2.z, a2.w);
+                        has = sdf_f(u.x, u.y, u.z, r, L) < a3.x + cull;
+                        if (has) {
+                            a0 = geo.face[4 * f];
+                            a1 = geo.face[4 * f + 1];
+                        }
                     }
                 }
+                fn(has, f, a0, a1, a2, a3);
             }
-            fn(has, f, a0, a1, a2, a3);
         }
     }
 }
 
+// wavefront-wide list append: lanes with `keep` take consecutive positions
+__device__ __forceinline__ int wave_append(bool keep, int lane, int& count) {
+    const unsigned long long m = __ballot(keep);
+    const int pos = count + __popcll(m & ((1ull << lane) - 1));
+    count += __popcll(m);
+    return pos;
+}
+
+// queue pair (q, f) for lanes with `need` (one atomic per wavefront)
+__device__ __forceinline__ void push_pairs(bool need, int lane, int q, int f, const RefineScratch& w, bool& overflow) {
+    const unsigned long long nm = __ballot(need);
+    if (!nm) return;
+    const int leader = __ffsll((long long)nm) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(w.pair_count, __popcll(nm));
+    base = __shfl(base, leader, 64);
+    if (need) {
+        const int slot = base + __popcll(nm & ((1ull << lane) - 1));
+        if (slot < w.pair_cap) w.pairs[slot] = make_int2(q, f);
+        else overflow = true;
+    }
+}
+
 __global__ __launch_bounds__(64 * CULL_WAVES) void k_ref_cull(const RefineTrial* __restrict__ tr, int K,
-                                                              RefineGeometry geo, int n_cluster,
-                                                              const float* __restrict__ poses, int N, RefineConst c,
-                                                              RefineScratch w, int* __restrict__ active) {
-    const int lane = threadIdx.x & 63;
-    const int q = blockIdx.x * CULL_WAVES + (threadIdx.x >> 6);
+                                                              RefineGeometry geo, const float* __restrict__ poses,
+                                                              int N, RefineConst c, RefineScratch w,
+                                                              int* __restrict__ active) {
+    __shared__ int l_slot[CULL_WAVES][CULL_LIST], l_idx[CULL_WAVES][CULL_LIST];
+    __shared__ float l_lb[CULL_WAVES][CULL_LIST], l_ub[CULL_WAVES][CULL_LIST];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int q = blockIdx.x * CULL_WAVES + wv;
     if (blockIdx.x == 0 && threadIdx.x == 0) active[0] = 0;  // counted again by k_ref_decide
     if (q >= K * N) return;  // whole wavefronts
     const int k = q / N, i = q - k * N;
@@ -495,18 +705,36 @@ __global__ __launch_bounds__(64 * CULL_WAVES) void k_ref_cull(const RefineTrial*
             X.a[3 * a + b] = (float)(Ri[a] * S.R[b] + Ri[3 + a] * S.R[3 + b] + Ri[6 + a] * S.R[6 + b]);
         X.c[a] = (float)(Ri[a] * (S.p[0] - pi[0]) + Ri[3 + a] * (S.p[1] - pi[1]) + Ri[6 + a] * (S.p[2] - pi[2]));
     }
-    if (lane < 12) w.xf[12 * q + lane] = lane < 9 ? X.a[lane] : X.c[lane - 9];
+    float xv = 0.0f;  // constant indices keep X in registers
+#pragma unroll
+    for (int j = 0; j < 12; ++j)
+        if (lane == j) xv = j < 9 ? X.a[j] : X.c[j - 9];
+    if (lane < 12) w.xf[12 * q + lane] = xv;
     if (lane == 0) w.qst[q] = make_float2(-1.0f, -1.0f);
     const float r = c.r, L = c.L;
 
-    // pass 1: the best vertex value over the kept faces
-    float best_ub = INFINITY;
+    // pass 1: the bounds of every kept face; the best vertex value.  A face
+    // whose lb exceeds its lane's best ub so far (never below the final best)
+    // cannot hold the minimum; the others are listed for pass 2.
+    float run_ub = INFINITY;
     bool any = false;
-    wave_kept_faces(X, geo, n_cluster, r, L, c.cull, lane,
-                    [&](bool has, int, const float4& a0, const float4& a1, const float4& a2, const float4&) {
+    int n_list = 0;
+    wave_kept_faces(X, geo, r, L, c.cull, lane,
+                    [&](bool has, int f, const float4& a0, const float4& a1, const float4& a2, const float4& a3) {
+                        FaceBounds B{};
+                        bool keep = false;
                         if (has) {
                             any = true;
-                            best_ub = fminf(best_ub, face_bounds(X, a0, a1, a2, r, L).ub);
+                            B = face_bounds(X, a0, a1, a2, r, L);
+                            run_ub = fminf(run_ub, B.ub);
+                            keep = B.lb <= run_ub + BOUND_SLACK;
+                        }
+                        const int pos = wave_append(keep, lane, n_list);
+                        if (keep && pos < CULL_LIST) {
+                            l_slot[wv][pos] = f;
+                            l_idx[wv][pos] = __float_as_int(a3.y);
+                            l_lb[wv][pos] = B.lb;
+                            l_ub[wv][pos] = B.ub;
                         }
                     });
     if (!__ballot(any)) {
@@ -516,38 +744,52 @@ __global__ __launch_bounds__(64 * CULL_WAVES) void k_ref_cull(const RefineTrial*
         }
         return;
     }
-    best_ub = wave_min_f(best_ub);
+    const float best_ub = wave_min_f(run_ub);
 
     // pass 2: settle faces whose bounds meet; queue the others for a search
     unsigned long long best = ~0ull;
     bool overflow = false;
-    wave_kept_faces(X, geo, n_cluster, r, L, c.cull, lane,
-                    [&](bool has, int f, const float4& a0, const float4& a1, const float4& a2, const float4& a3) {
-                        bool need = false;
-                        if (has) {
-                            const FaceBounds B = face_bounds(X, a0, a1, a2, r, L);
-                            if (B.lb <= best_ub + BOUND_SLACK) {
-                                if (B.ub - B.lb <= VERTEX_GAP) {
-                                    const unsigned long long key = face_key(B.ub, __float_as_int(a3.y));
-                                    best = key < best ? key : best;
-                                } else {
-                                    need = true;
+    if (n_list <= CULL_LIST) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int j0 = 0; j0 < n_list; j0 += 64) {
+            const int j = j0 + lane;
+            bool need = false;
+            int f = 0;
+            if (j < n_list) {
+                const float lb = l_lb[wv][j], ub = l_ub[wv][j];
+                f = l_slot[wv][j];
+                if (lb <= best_ub + BOUND_SLACK) {
+                    if (ub - lb <= VERTEX_GAP) {
+                        const unsigned long long key = face_key(ub, l_idx[wv][j]);
+                        best = key < best ? key : best;
+                    } else {
+                        need = true;
+                    }
+                }
+            }
+            push_pairs(need, lane, q, f, w, overflow);
+        }
+    } else {
+        // the list overflowed: walk the kept faces again
+        wave_kept_faces(X, geo, r, L, c.cull, lane,
+                        [&](bool has, int f, const float4& a0, const float4& a1, const float4& a2, const float4& a3) {
+                            bool need = false;
+                            if (has) {
+                                const FaceBounds B = face_bounds(X, a0, a1, a2, r, L);
+                                if (B.lb <= best_ub + BOUND_SLACK) {
+                                    if (B.ub - B.lb <= VERTEX_GAP) {
+                                        const unsigned long long key = face_key(B.ub, __float_as_int(a3.y));
+                                        best = key < best ? key : best;
+                                    } else {
+                                        need = true;
+                                    }
                                 }
                             }
-                        }
-                        const unsigned long long nm = __ballot(need);
-                        if (nm) {
-                            const int leader = __ffsll((long long)nm) - 1;
-                            int base = 0;
-                            if (lane == leader) base = atomicAdd(w.pair_count, __popcll(nm));
-                            base = __shfl(base, leader, 64);
-                            if (need) {
-                                const int slot = base + __popcll(nm & ((1ull << lane) - 1));
-                                if (slot < w.pair_cap) w.pairs[slot] = make_int2(q, f);
-                                else overflow = true;
-                            }
-                        }
-                    });
+                            push_pairs(need, lane, q, f, w, overflow);
+                        });
+    }
     best = wave_min_u64(best);
     const bool ovf = __ballot(overflow) != 0;
     if (lane == 0) {
@@ -557,22 +799,98 @@ __global__ __launch_bounds__(64 * CULL_WAVES) void k_ref_cull(const RefineTrial*
 }
 
 __global__ __launch_bounds__(256) void k_ref_pairs(RefineGeometry geo, RefineConst c, RefineScratch w) {
-    const int n = min(*w.pair_count, w.pair_cap);
+    const int n = min(w.pair_count[0], w.pair_cap);
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
         const int2 pr = w.pairs[j];
         const Xf X = load_xf(w.xf, pr.x);
         const int f = pr.y;
         const FaceBounds B = face_bounds(X, geo.face[4 * f], geo.face[4 * f + 1], geo.face[4 * f + 2], c.r, c.L);
         float s, t;
-        const float m = face_min(make_tri(B, c.r, c.L), s, t);
+        bool done;
+        const float m = face_min_bounded(make_tri(B, c.r, c.L), s, t, done);
         w.pres[j] = make_float4(m, s, t, 0.0f);
-        atomicMin(&w.qkey[pr.x], face_key(m, __float_as_int(geo.face[4 * f + 3].y)));
+        if (done) {
+            atomicMin(&w.qkey[pr.x], face_key(m, __float_as_int(geo.face[4 * f + 3].y)));
+        } else {
+            // a few percent of the pairs, left to k_ref_nested with the
+            // boundary minimum in pres
+            w.nest[atomicAdd(&w.pair_count[1], 1)] = j;
+        }
+    }
+}
+
+// (v, i) of the least v over aligned groups of `width` lanes, the lowest i on ties
+__device__ __forceinline__ void group_argmin(float& v, int& i, int first_mask, int width) {
+    for (int m = first_mask; m < first_mask * width; m <<= 1) {
+        const float ov = __shfl_xor(v, m, 64);
+        const int oi = __shfl_xor(i, m, 64);
+        if (ov < v || (ov == v && oi < i)) {
+            v = ov;
+            i = oi;
+        }
+    }
+}
+
+constexpr int NSEC = 8;     // points per bracket of the parallel searches
+constexpr int NSEC_IT = 8;  // (2 / (NSEC + 1))^NSEC_IT = 6e-6 of the bracket is left
+
+// The face minimum of a deferred pair inside the face, one wavefront per
+// pair: f is convex, so is its partial minimum over t.  Eight groups of eight
+// lanes evaluate the partial minimum at NSEC points of the s bracket, each by
+// NSEC-section over t; the bracket then shrinks to the neighbours of the best
+// point (for a unimodal function the minimum lies between them).  The best
+// point evaluated is folded with the boundary minimum k_ref_pairs left in
+// pres.
+__global__ __launch_bounds__(64) void k_ref_nested(RefineGeometry geo, RefineConst c, RefineScratch w) {
+    const int n = w.pair_count[1];
+    const int lane = threadIdx.x, grp = lane >> 3, sub = lane & 7;
+    for (int e = blockIdx.x; e < n; e += gridDim.x) {
+        const int j = w.nest[e];
+        const int2 pr = w.pairs[j];
+        const Xf X = load_xf(w.xf, pr.x);
+        const int f = pr.y;
+        const FaceBounds B = face_bounds(X, geo.face[4 * f], geo.face[4 * f + 1], geo.face[4 * f + 2], c.r, c.L);
+        const Tri T = make_tri(B, c.r, c.L);
+        float bv = INFINITY, bs = 0.0f, bt = 0.0f;  // this lane's best evaluation
+        float sa = 0.0f, sb = 1.0f;
+        for (int io = 0; io < NSEC_IT; ++io) {
+            const float hs = (sb - sa) * (1.0f / (NSEC + 1));
+            const float sv = sa + hs * (float)(grp + 1);
+            float ta = 0.0f, tb = 1.0f - sv, phi = INFINITY;
+            for (int ii = 0; ii < NSEC_IT; ++ii) {
+                const float ht = (tb - ta) * (1.0f / (NSEC + 1));
+                const float tv = ta + ht * (float)(sub + 1);
+                float v = T.at(sv, tv);
+                if (v < bv) {
+                    bv = v; bs = sv; bt = tv;
+                }
+                int im = sub;
+                group_argmin(v, im, 1, NSEC);
+                phi = fminf(phi, v);
+                ta = ta + ht * (float)im;
+                tb = ta + 2.0f * ht;
+            }
+            int ig = grp;
+            group_argmin(phi, ig, NSEC, 64 / NSEC);
+            sa = sa + hs * (float)ig;
+            sb = sa + 2.0f * hs;
+        }
+        int il = lane;
+        float v = bv;
+        group_argmin(v, il, 1, 64);
+        const float ws = __shfl(bs, il, 64), wt = __shfl(bt, il, 64);
+        if (lane == 0) {
+            float4 cur = w.pres[j];  // the boundary minimum
+            if (v < cur.x) cur = make_float4(v, ws, wt, 0.0f);
+            w.pres[j] = cur;
+            atomicMin(&w.qkey[pr.x], face_key(cur.x, __float_as_int(geo.face[4 * f + 3].y)));
+        }
     }
 }
 
 // the pair that holds its query's minimum hands over its barycentric witness
 __global__ __launch_bounds__(256) void k_ref_winner(RefineGeometry geo, RefineScratch w) {
-    const int n = min(*w.pair_count, w.pair_cap);
+    const int n = min(w.pair_count[0], w.pair_cap);
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
         const int2 pr = w.pairs[j];
         const float4 res = w.pres[j];
@@ -807,7 +1125,7 @@ __global__ void k_ref_decide(RefineState* __restrict__ st, RefineTrial* __restri
                              const RefineEval* __restrict__ ev, RefineConst c, int* __restrict__ pair_count,
                              int* __restrict__ counters) {
     const int k = blockIdx.x;
-    if (k == 0 && threadIdx.x == 0) *pair_count = 0;  // for the next round's queries
+    if (k == 0 && threadIdx.x == 0) pair_count[0] = pair_count[1] = 0;  // for the next round's queries
     RefineState& S = st[k];
     if (S.status == 2) return;
     __shared__ int ntrial;
@@ -928,11 +1246,12 @@ static void launch_queries(const RefineTrial* tr, int slots, const RefineGeometr
                            const RefineConst& c, const RefineScratch& w, RefineHit* hits, int* counters,
                            hipStream_t s) {
     const long long q = (long long)slots * N;
-    k_ref_cull<<<(unsigned)((q + CULL_WAVES - 1) / CULL_WAVES), 64 * CULL_WAVES, 0, s>>>(tr, slots, geo, geo.n_cluster,
-                                                                                      poses, N, c, w, counters);
+    k_ref_cull<<<(unsigned)((q + CULL_WAVES - 1) / CULL_WAVES), 64 * CULL_WAVES, 0, s>>>(tr, slots, geo, poses, N, c,
+                                                                                      w, counters);
     // about 3 searches per query are needed; the kernels stride over the rest
     const unsigned pb = (unsigned)std::min<long long>(2048, std::max<long long>(1, (4 * q + 255) / 256));
     k_ref_pairs<<<pb, 256, 0, s>>>(geo, c, w);
+    k_ref_nested<<<4096, 64, 0, s>>>(geo, c, w);
     k_ref_winner<<<pb, 256, 0, s>>>(geo, w);
     k_ref_resolve<<<(unsigned)((q + 63) / 64), 64, 0, s>>>(tr, slots, geo, poses, N, c, w, hits);
 }
