@@ -440,8 +440,8 @@ static int ensure_refine_buffers(reg_handle* h, int K) {
         ALLOC_TRY(h, h->rw.pairs, 16 * nq);
         ALLOC_TRY(h, h->rw.pres, 16 * nq);
         ALLOC_TRY(h, h->rw.nest, 16 * nq);
-        if (!h->rw.pair_count) ALLOC_TRY(h, h->rw.pair_count, 2);
-        h->rw.pair_cap = (int)std::min<size_t>(16 * nq, 1u << 30);
+        if (!h->rw.pair_count) ALLOC_TRY(h, h->rw.pair_count, REF_COUNTERS);
+        h->rw.pair_cap = (int)(std::min<size_t>(16 * nq, 1u << 30) / REF_SEGS * REF_SEGS);
         h->r_cap = cap;
     }
     return REG_OK;

@@ -13,6 +13,14 @@
 // (faces in Morton order of their centroids).
 constexpr int REF_FANOUT = 32;
 
+// The pair queue is cut into REF_SEGS segments of pair_cap / REF_SEGS slots,
+// each with its own counter on a cache line of its own, so that the queries'
+// appends do not all serialise on one atomic.
+constexpr int REF_SEGS = 64;
+constexpr int REF_SEG_STRIDE = 16;                              // ints between counters
+constexpr int REF_NESTED_AT = REF_SEGS * REF_SEG_STRIDE;        // the nested pairs count
+constexpr int REF_COUNTERS = REF_NESTED_AT + REF_SEG_STRIDE;
+
 struct RefineGeometry {
     const float4* top;        // n_top spheres (centre, radius)
     const int2* top_range;    // first cluster, cluster count
@@ -32,9 +40,9 @@ struct RefineScratch {
     float2* qst;                // barycentric witness of the winning search (-1: a vertex won)
     int2* pairs;                // (query, face slot) pairs for a face search
     float4* pres;               // per pair: minimum, s, t
-    int* nest;                  // pairs left to the nested golden-section search (indices into pairs)
-    int* pair_count;            // [pairs, nested pairs]
-    int pair_cap;               // capacity of pairs, pres and nest
+    int* nest;                  // pairs left to the nested search (indices into pairs)
+    int* pair_count;            // REF_COUNTERS ints: the segment counters, then the nested count
+    int pair_cap;               // capacity of pairs, pres and nest (a multiple of REF_SEGS)
 };
 
 struct RefineConst {

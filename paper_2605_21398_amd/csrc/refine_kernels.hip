@@ -95,13 +95,19 @@ __device__ __forceinline__ float sdf_f(float x, float y, float z, float r, float
     return in + hw_sqrt(a * a + b * b);
 }
 
+// hardware reciprocal (v_rcp_f32, about 1 ulp): the gradients feed bounds
+// and slope tests whose allowances are far above float32 rounding
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // f_p and a subgradient (the gradient where f_p is differentiable; on the
 // inner ridge the gradient of the larger branch)
 __device__ __forceinline__ float sdf_grad_f(float3 u, float r, float L, float3& g) {
     const float rho = hw_sqrt(u.x * u.x + u.y * u.y);
     const float q1 = rho - r, q2 = fabsf(u.z - 0.5f * L) - 0.5f * L;
     const float sz = u.z >= 0.5f * L ? 1.0f : -1.0f;
-    const float ex = rho > 0 ? u.x / rho : 1.0f, ey = rho > 0 ? u.y / rho : 0.0f;
+    const bool off_axis = rho > 1e-30f;
+    const float ir = off_axis ? hw_rcp(rho) : 0.0f;
+    const float ex = off_axis ? u.x * ir : 1.0f, ey = off_axis ? u.y * ir : 0.0f;
     if (q1 <= 0 && q2 <= 0) {
         if (q1 >= q2) {
             g = make_float3(ex, ey, 0.0f);
@@ -112,7 +118,8 @@ __device__ __forceinline__ float sdf_grad_f(float3 u, float r, float L, float3& 
     }
     const float a = fmaxf(q1, 0.0f), b = fmaxf(q2, 0.0f);
     const float n = hw_sqrt(a * a + b * b);
-    g = make_float3(a * ex / n, a * ey / n, b * sz / n);
+    const float in = n > 0.0f ? hw_rcp(n) : 0.0f;
+    g = make_float3(a * in * ex, a * in * ey, b * in * sz);
     return n;
 }
 
@@ -392,6 +399,12 @@ __device__ float3 witness_gradient(float3 u, const Tri& T, float s, float t) {
 
 // ------------------------------------------------------------------ kernels
 
+// zero the pair-queue counters; called by threads t = 0..63 of one block
+__device__ __forceinline__ void clear_pair_counters(int* __restrict__ pair_count, int t) {
+    if (t < REF_SEGS) pair_count[t * REF_SEG_STRIDE] = 0;
+    if (t == 0) pair_count[REF_NESTED_AT] = 0;
+}
+
 // pose of the twist x about the start's anchor and the Jacobians the
 // sensitivities need, into the trial T
 __device__ void pose_at(const RefineState& S, const double* x, RefineTrial& T) {
@@ -431,8 +444,8 @@ __global__ void k_ref_start(const double* __restrict__ init, int K, const double
     if (k == 0) {
         counters[0] = K;
         counters[1] = 0;
-        pair_count[0] = pair_count[1] = 0;
     }
+    if (blockIdx.x == 0) clear_pair_counters(pair_count, threadIdx.x);
     if (k >= K) return;
     RefineState& S = st[k];
     const double* P = init + 7 * k;
@@ -571,7 +584,36 @@ __device__ void probe_frame(const float* __restrict__ poses, int i, double* Ri, 
     pi[2] = P[6];
 }
 
-__global__ void k_ref_reset(int* __restrict__ pair_count) { pair_count[0] = pair_count[1] = 0; }
+__global__ void k_ref_reset(int* __restrict__ pair_count) { clear_pair_counters(pair_count, threadIdx.x); }
+
+// Flat view of the segmented pair queue: pre[s] = pairs in segments below s
+// (each count clamped to the segment's capacity).  Every thread of the block
+// must call it; the first wavefront scans.
+__device__ int pair_prefix(const RefineScratch& w, int* pre) {
+    if (threadIdx.x < 64) {
+        const int t = threadIdx.x;
+        int x = min(w.pair_count[t * REF_SEG_STRIDE], w.pair_cap / REF_SEGS);
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (t >= o) x += y;
+        }
+        pre[t + 1] = x;
+        if (t == 0) pre[0] = 0;
+    }
+    __syncthreads();
+    return pre[REF_SEGS];
+}
+
+// queue slot of flat index e < pre[REF_SEGS]: the segment s with pre[s] <= e < pre[s + 1]
+__device__ __forceinline__ int pair_slot(const int* pre, int e, int seg_cap) {
+    int lo = 0, hi = REF_SEGS;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= e) lo = mid;
+        else hi = mid;
+    }
+    return lo * seg_cap + (e - pre[lo]);
+}
 
 // refinement starts from search results: rows idx[k] of a count x 7 pose array
 __global__ void k_gather_poses(const int32_t* __restrict__ idx, const double* __restrict__ src, int K,
@@ -600,65 +642,11 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
 constexpr int CULL_WAVES = 4;   // queries per 256-thread block, one wavefront each
 constexpr int CULL_LIST = 256;  // kept faces a wavefront holds in LDS between its two passes
 
-// Kept faces of one query, spread over the lanes of its wavefront: the top
-// spheres are tested 64 at a time, the clusters of two kept top nodes (at most
-// REF_FANOUT = 32 each) take half a wavefront each, and so do the faces of two
-// kept clusters.  fn(lane_has_face, slot, a0..a3) is called by every lane at
-// the same points (uniform control flow).
-template <class Fn>
-__device__ void wave_kept_faces(const Xf& X, const RefineGeometry& geo, float r, float L, float cull, int lane,
-                                Fn&& fn) {
-    const int half = lane & 31;
-    for (int t0 = 0; t0 < geo.n_top; t0 += 64) {
-        const int tn = t0 + lane;
-        unsigned long long tmask = __ballot(tn < geo.n_top && sphere_kept(X, geo.top[tn], r, L, cull));
-        while (tmask) {
-            const int ta = __ffsll((long long)tmask) - 1;
-            tmask &= tmask - 1;
-            int tb = -1;
-            if (tmask) {
-                tb = __ffsll((long long)tmask) - 1;
-                tmask &= tmask - 1;
-            }
-            const int mt = lane < 32 ? ta : tb;
-            int cl = -1;
-            if (mt >= 0) {
-                const int2 cr = geo.top_range[t0 + mt];
-                if (half < cr.y && sphere_kept(X, geo.cluster[cr.x + half], r, L, cull)) cl = cr.x + half;
-            }
-            unsigned long long cmask = __ballot(cl >= 0);
-            while (cmask) {
-                const int la = __ffsll((long long)cmask) - 1;
-                cmask &= cmask - 1;
-                int lb = -1;
-                if (cmask) {
-                    lb = __ffsll((long long)cmask) - 1;
-                    cmask &= cmask - 1;
-                }
-                const int ca = __shfl(cl, la, 64);
-                const int cb = lb >= 0 ? __shfl(cl, lb, 64) : -1;
-                const int mine = lane < 32 ? ca : cb;
-                bool has = false;
-                int f = 0;
-                float4 a0 = make_float4(0, 0, 0, 0), a1 = a0, a2 = a0, a3 = a0;
-                if (mine >= 0) {
-                    const int2 fr = geo.cluster_range[mine];
-                    if (half < fr.y) {
-                        f = fr.x + half;
-                        a2 = geo.face[4 * f + 2];
-                        a3 = geo.face[4 * f + 3];
-                        const float3 u = X.apply(a2.y, a2.z, a2.w);
-                        has = sdf_f(u.x, u.y, u.z, r, L) < a3.x + cull;
-                        if (has) {
-                            a0 = geo.face[4 * f];
-                            a1 = geo.face[4 * f + 1];
-                        }
-                    }
-                }
-                fn(has, f, a0, a1, a2, a3);
-            }
-        }
-    }
+// LDS written by one lane of a wavefront and read by another afterwards
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // wavefront-wide list append: lanes with `keep` take consecutive positions
@@ -669,17 +657,72 @@ __device__ __forceinline__ int wave_append(bool keep, int lane, int& count) {
     return pos;
 }
 
-// queue pair (q, f) for lanes with `need` (one atomic per wavefront)
-__device__ __forceinline__ void push_pairs(bool need, int lane, int q, int f, const RefineScratch& w, bool& overflow) {
+// Kept faces of one query, spread over the lanes of its wavefront, one level
+// of the hierarchy at a time: the top spheres are tested 64 at a time, the
+// kept ones listed in LDS (ktop); their clusters are enumerated flat, one per
+// lane, and the kept ones listed (kcl, at most 64 per step); their faces are
+// enumerated flat and tested.  Each level costs one round of independent loads
+// instead of one per node.  fn(lane_has_face, slot) is called by every lane at
+// the same points (uniform control flow).
+template <class Fn>
+__device__ void wave_kept_faces(const Xf& X, const RefineGeometry& geo, float r, float L, float cull, int lane,
+                                int* ktop, int* kcl, Fn&& fn) {
+    for (int t0 = 0; t0 < geo.n_top; t0 += 64) {
+        const int tn = t0 + lane;
+        const bool tk = tn < geo.n_top && sphere_kept(X, geo.top[tn], r, L, cull);
+        int nt = 0;
+        const int tp = wave_append(tk, lane, nt);
+        if (tk) ktop[tp] = tn;
+        if (nt == 0) continue;
+        wave_lds_sync();
+        for (int e0 = 0; e0 < REF_FANOUT * nt; e0 += 64) {
+            const int e = e0 + lane;
+            int cl = -1;
+            if (e < REF_FANOUT * nt) {
+                const int2 cr = geo.top_range[ktop[e / REF_FANOUT]];
+                const int j = e % REF_FANOUT;
+                if (j < cr.y && sphere_kept(X, geo.cluster[cr.x + j], r, L, cull)) cl = cr.x + j;
+            }
+            int nc = 0;
+            const int cp = wave_append(cl >= 0, lane, nc);
+            if (cl >= 0) kcl[cp] = cl;
+            if (nc == 0) continue;
+            wave_lds_sync();
+            for (int f0 = 0; f0 < REF_FANOUT * nc; f0 += 64) {
+                const int fe = f0 + lane;
+                bool has = false;
+                int f = 0;
+                if (fe < REF_FANOUT * nc) {
+                    const int2 fr = geo.cluster_range[kcl[fe / REF_FANOUT]];
+                    const int j = fe % REF_FANOUT;
+                    if (j < fr.y) {
+                        f = fr.x + j;
+                        const float4 a2 = geo.face[4 * f + 2], a3 = geo.face[4 * f + 3];
+                        const float3 u = X.apply(a2.y, a2.z, a2.w);
+                        has = sdf_f(u.x, u.y, u.z, r, L) < a3.x + cull;
+                    }
+                }
+                fn(has, f);
+            }
+            wave_lds_sync();  // kcl is rewritten by the next step
+        }
+        wave_lds_sync();      // and ktop by the next chunk of top nodes
+    }
+}
+
+// queue pair (q, f) for lanes with `need` in segment seg (one atomic per wavefront)
+__device__ __forceinline__ void push_pairs(bool need, int lane, int q, int f, int seg, const RefineScratch& w,
+                                           bool& overflow) {
     const unsigned long long nm = __ballot(need);
     if (!nm) return;
     const int leader = __ffsll((long long)nm) - 1;
     int base = 0;
-    if (lane == leader) base = atomicAdd(w.pair_count, __popcll(nm));
+    if (lane == leader) base = atomicAdd(&w.pair_count[seg * REF_SEG_STRIDE], __popcll(nm));
     base = __shfl(base, leader, 64);
     if (need) {
-        const int slot = base + __popcll(nm & ((1ull << lane) - 1));
-        if (slot < w.pair_cap) w.pairs[slot] = make_int2(q, f);
+        const int seg_cap = w.pair_cap / REF_SEGS;
+        const int off = base + __popcll(nm & ((1ull << lane) - 1));
+        if (off < seg_cap) w.pairs[seg * seg_cap + off] = make_int2(q, f);
         else overflow = true;
     }
 }
@@ -690,6 +733,8 @@ __global__ __launch_bounds__(64 * CULL_WAVES) void k_ref_cull(const RefineTrial*
                                                               int* __restrict__ active) {
     __shared__ int l_slot[CULL_WAVES][CULL_LIST], l_idx[CULL_WAVES][CULL_LIST];
     __shared__ float l_lb[CULL_WAVES][CULL_LIST], l_ub[CULL_WAVES][CULL_LIST];
+    __shared__ int l_queue[CULL_WAVES][128];
+    __shared__ int l_ktop[CULL_WAVES][64], l_kcl[CULL_WAVES][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int q = blockIdx.x * CULL_WAVES + wv;
     if (blockIdx.x == 0 && threadIdx.x == 0) active[0] = 0;  // counted again by k_ref_decide
@@ -697,6 +742,7 @@ __global__ __launch_bounds__(64 * CULL_WAVES) void k_ref_cull(const RefineTrial*
     const int k = q / N, i = q - k * N;
     const RefineTrial& S = tr[k];
     if (!S.valid) return;
+    const int seg = blockIdx.x % REF_SEGS;
     double Ri[9], pi[3];
     probe_frame(poses, i, Ri, pi);
     Xf X;
@@ -713,30 +759,52 @@ __global__ __launch_bounds__(64 * CULL_WAVES) void k_ref_cull(const RefineTrial*
     if (lane == 0) w.qst[q] = make_float2(-1.0f, -1.0f);
     const float r = c.r, L = c.L;
 
-    // pass 1: the bounds of every kept face; the best vertex value.  A face
-    // whose lb exceeds its lane's best ub so far (never below the final best)
-    // cannot hold the minimum; the others are listed for pass 2.
+    // pass 1: the bounds of every kept face; the best vertex value.  Kept
+    // faces queue up in LDS and their bounds are taken 64 at a time, one per
+    // lane.  A face whose lb exceeds its lane's best ub so far (never below
+    // the final best) cannot hold the minimum; the others are listed for
+    // pass 2.
     float run_ub = INFINITY;
     bool any = false;
-    int n_list = 0;
-    wave_kept_faces(X, geo, r, L, c.cull, lane,
-                    [&](bool has, int f, const float4& a0, const float4& a1, const float4& a2, const float4& a3) {
-                        FaceBounds B{};
-                        bool keep = false;
-                        if (has) {
-                            any = true;
-                            B = face_bounds(X, a0, a1, a2, r, L);
-                            run_ub = fminf(run_ub, B.ub);
-                            keep = B.lb <= run_ub + BOUND_SLACK;
-                        }
-                        const int pos = wave_append(keep, lane, n_list);
-                        if (keep && pos < CULL_LIST) {
-                            l_slot[wv][pos] = f;
-                            l_idx[wv][pos] = __float_as_int(a3.y);
-                            l_lb[wv][pos] = B.lb;
-                            l_ub[wv][pos] = B.ub;
-                        }
-                    });
+    int n_list = 0, n_q = 0;
+    auto bounds_of_queue = [&](int count) {
+        FaceBounds B{};
+        bool keep = false;
+        int f = 0, idx = 0;
+        if (lane < count) {
+            f = l_queue[wv][lane];
+            const float4 a0 = geo.face[4 * f], a1 = geo.face[4 * f + 1], a2 = geo.face[4 * f + 2];
+            idx = __float_as_int(geo.face[4 * f + 3].y);
+            B = face_bounds(X, a0, a1, a2, r, L);
+            run_ub = fminf(run_ub, B.ub);
+            keep = B.lb <= run_ub + BOUND_SLACK;
+        }
+        const int pos = wave_append(keep, lane, n_list);
+        if (keep && pos < CULL_LIST) {
+            l_slot[wv][pos] = f;
+            l_idx[wv][pos] = idx;
+            l_lb[wv][pos] = B.lb;
+            l_ub[wv][pos] = B.ub;
+        }
+    };
+    wave_kept_faces(X, geo, r, L, c.cull, lane, l_ktop[wv], l_kcl[wv], [&](bool has, int f) {
+        any |= has;
+        const int pos = wave_append(has, lane, n_q);  // n_q < 128 after the append
+        if (has) l_queue[wv][pos] = f;
+        if (n_q >= 64) {
+            wave_lds_sync();
+            bounds_of_queue(64);
+            const int rest = n_q - 64;
+            const int mv = lane < rest ? l_queue[wv][64 + lane] : 0;
+            wave_lds_sync();
+            if (lane < rest) l_queue[wv][lane] = mv;
+            n_q = rest;
+        }
+    });
+    if (n_q > 0) {
+        wave_lds_sync();
+        bounds_of_queue(n_q);
+    }
     if (!__ballot(any)) {
         if (lane == 0) {
             w.qkey[q] = ~0ull;
@@ -750,9 +818,7 @@ __global__ __launch_bounds__(64 * CULL_WAVES) void k_ref_cull(const RefineTrial*
     unsigned long long best = ~0ull;
     bool overflow = false;
     if (n_list <= CULL_LIST) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_lds_sync();
         for (int j0 = 0; j0 < n_list; j0 += 64) {
             const int j = j0 + lane;
             bool need = false;
@@ -769,25 +835,26 @@ __global__ __launch_bounds__(64 * CULL_WAVES) void k_ref_cull(const RefineTrial*
                     }
                 }
             }
-            push_pairs(need, lane, q, f, w, overflow);
+            push_pairs(need, lane, q, f, seg, w, overflow);
         }
     } else {
         // the list overflowed: walk the kept faces again
-        wave_kept_faces(X, geo, r, L, c.cull, lane,
-                        [&](bool has, int f, const float4& a0, const float4& a1, const float4& a2, const float4& a3) {
+        wave_kept_faces(X, geo, r, L, c.cull, lane, l_ktop[wv], l_kcl[wv], [&](bool has, int f) {
                             bool need = false;
                             if (has) {
-                                const FaceBounds B = face_bounds(X, a0, a1, a2, r, L);
+                                const FaceBounds B = face_bounds(X, geo.face[4 * f], geo.face[4 * f + 1],
+                                                                 geo.face[4 * f + 2], r, L);
                                 if (B.lb <= best_ub + BOUND_SLACK) {
                                     if (B.ub - B.lb <= VERTEX_GAP) {
-                                        const unsigned long long key = face_key(B.ub, __float_as_int(a3.y));
+                                        const unsigned long long key =
+                                            face_key(B.ub, __float_as_int(geo.face[4 * f + 3].y));
                                         best = key < best ? key : best;
                                     } else {
                                         need = true;
                                     }
                                 }
                             }
-                            push_pairs(need, lane, q, f, w, overflow);
+                            push_pairs(need, lane, q, f, seg, w, overflow);
                         });
     }
     best = wave_min_u64(best);
@@ -799,8 +866,10 @@ __global__ __launch_bounds__(64 * CULL_WAVES) void k_ref_cull(const RefineTrial*
 }
 
 __global__ __launch_bounds__(256) void k_ref_pairs(RefineGeometry geo, RefineConst c, RefineScratch w) {
-    const int n = min(w.pair_count[0], w.pair_cap);
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    __shared__ int pre[REF_SEGS + 1];
+    const int n = pair_prefix(w, pre), seg_cap = w.pair_cap / REF_SEGS;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int j = pair_slot(pre, e, seg_cap);
         const int2 pr = w.pairs[j];
         const Xf X = load_xf(w.xf, pr.x);
         const int f = pr.y;
@@ -814,7 +883,7 @@ __global__ __launch_bounds__(256) void k_ref_pairs(RefineGeometry geo, RefineCon
         } else {
             // a few percent of the pairs, left to k_ref_nested with the
             // boundary minimum in pres
-            w.nest[atomicAdd(&w.pair_count[1], 1)] = j;
+            w.nest[atomicAdd(&w.pair_count[REF_NESTED_AT], 1)] = j;
         }
     }
 }
@@ -842,7 +911,7 @@ constexpr int NSEC_IT = 8;  // (2 / (NSEC + 1))^NSEC_IT = 6e-6 of the bracket is
 // point evaluated is folded with the boundary minimum k_ref_pairs left in
 // pres.
 __global__ __launch_bounds__(64) void k_ref_nested(RefineGeometry geo, RefineConst c, RefineScratch w) {
-    const int n = w.pair_count[1];
+    const int n = w.pair_count[REF_NESTED_AT];
     const int lane = threadIdx.x, grp = lane >> 3, sub = lane & 7;
     for (int e = blockIdx.x; e < n; e += gridDim.x) {
         const int j = w.nest[e];
@@ -890,8 +959,10 @@ __global__ __launch_bounds__(64) void k_ref_nested(RefineGeometry geo, RefineCon
 
 // the pair that holds its query's minimum hands over its barycentric witness
 __global__ __launch_bounds__(256) void k_ref_winner(RefineGeometry geo, RefineScratch w) {
-    const int n = min(w.pair_count[0], w.pair_cap);
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    __shared__ int pre[REF_SEGS + 1];
+    const int n = pair_prefix(w, pre), seg_cap = w.pair_cap / REF_SEGS;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int j = pair_slot(pre, e, seg_cap);
         const int2 pr = w.pairs[j];
         const float4 res = w.pres[j];
         if (face_key(res.x, __float_as_int(geo.face[4 * pr.y + 3].y)) == w.qkey[pr.x])
@@ -1125,7 +1196,7 @@ __global__ void k_ref_decide(RefineState* __restrict__ st, RefineTrial* __restri
                              const RefineEval* __restrict__ ev, RefineConst c, int* __restrict__ pair_count,
                              int* __restrict__ counters) {
     const int k = blockIdx.x;
-    if (k == 0 && threadIdx.x == 0) pair_count[0] = pair_count[1] = 0;  // for the next round's queries
+    if (k == 0) clear_pair_counters(pair_count, threadIdx.x);  // for the next round's queries
     RefineState& S = st[k];
     if (S.status == 2) return;
     __shared__ int ntrial;
@@ -1275,7 +1346,7 @@ hipError_t refine_finish(const RefineState* st, int K, double* out_poses, double
 hipError_t refine_query_only(const RefineTrial* tr, const RefineGeometry& geo, const float* poses, int n_poses,
                              const RefineConst& c, const RefineScratch& w, RefineHit* hits, int* counters,
                              hipStream_t s) {
-    k_ref_reset<<<1, 1, 0, s>>>(w.pair_count);
+    k_ref_reset<<<1, 64, 0, s>>>(w.pair_count);
     launch_queries(tr, 1, geo, poses, n_poses, c, w, hits, counters, s);
     return hipGetLastError();
 }
