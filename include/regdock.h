@@ -144,8 +144,17 @@ int register_search_stats(reg_handle* h, int64_t* rotations, int64_t* candidates
  * Errors: REG_EINVAL, REG_EDEVICE. */
 int register_top_k(reg_handle* h, const float* scores, int32_t count, int32_t K, int32_t* out_idx);
 
-/* Release a handle and every device buffer it owns (NULL is a no-op). */
+/* Release a handle and every device buffer it owns (NULL is a no-op).  Waits
+ * for the handle's stream; the buffers go to the library's device memory
+ * cache, where the next handles, batches and server requests of the same sizes
+ * take them without hipMalloc (the cache holds at most 32 GiB per process, and
+ * an allocation that fails first returns the device's cached blocks to HIP). */
 void register_free(reg_handle* h);
+
+/* Memory management (not an operation of the method): bytes held by the
+ * device memory cache, and the release of every cached block back to HIP. */
+int64_t register_cached_bytes(void);
+void register_release_cached(void);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* register_last_error(void);

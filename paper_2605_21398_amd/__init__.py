@@ -28,7 +28,8 @@ EXPORTS = ["register_init", "score_rotations", "register_top_k", "register_free"
            "refine_se3", "register_debug_distance", "register_refine_stats", "register_server_create",
            "register_server_destroy", "register_submit", "register_poll", "register_wait", "register_server_stats",
            "register_server_last_error", "register_batch_create", "register_batch_run", "register_batch_outputs",
-           "register_batch_free", "register_autotune", "register_tuned_batch"]
+           "register_batch_free", "register_autotune", "register_tuned_batch", "register_cached_bytes",
+           "register_release_cached"]
 
 
 class RegError(RuntimeError):
@@ -109,6 +110,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.register_top_k.argtypes = [p, p, i32, i32, p]
     L.register_free.restype = None
     L.register_free.argtypes = [p]
+    L.register_cached_bytes.restype = i64
+    L.register_cached_bytes.argtypes = []
+    L.register_release_cached.restype = None
+    L.register_release_cached.argtypes = []
     L.register_last_error.restype = ctypes.c_char_p
     L.register_last_error.argtypes = []
     L.register_info.restype = ctypes.c_int
@@ -486,3 +491,13 @@ def register_autotune(h: Handle, max_rotations: int = 512) -> int:
 
 def register_tuned_batch(n: int) -> int:
     return load_library().register_tuned_batch(n)
+
+
+def register_cached_bytes() -> int:
+    """Device bytes held by the library's memory cache (blocks of freed handles)."""
+    return load_library().register_cached_bytes()
+
+
+def register_release_cached() -> None:
+    """Return every cached device block to HIP."""
+    load_library().register_release_cached()

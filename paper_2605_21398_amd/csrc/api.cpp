@@ -10,6 +10,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -43,6 +44,98 @@ int lattice_edge(int n) { return 2 * (int)std::ceil((std::sqrt(3.0) * n + 2.0) /
 // its spectrum conj(F(O))/n^3 with the exact low-frequency block, the nonzero
 // list of O, the twiddles and the refinement's bounding-sphere hierarchy.
 // Handles share it, so a serving cache keeps object spectra resident.
+// ------------------------------------------------------ device memory cache
+
+namespace {
+struct DevCache {
+    std::mutex mu;
+    std::map<std::pair<int, size_t>, std::vector<void*>> free_blocks;  // (device, size) -> blocks
+    std::unordered_map<void*, std::pair<int, size_t>> live;             // block -> (device, size)
+    size_t cached = 0;
+    size_t cap = (size_t)32 << 30;  // cached bytes beyond this go back to HIP
+};
+// never destroyed: blocks still cached at exit go with the process
+DevCache& dev_cache() {
+    static DevCache* c = new DevCache;
+    return *c;
+}
+size_t round_block(size_t b) {
+    const size_t small = 512, big = (size_t)2 << 20;
+    return b <= ((size_t)1 << 20) ? (b + small - 1) / small * small : (b + big - 1) / big * big;
+}
+void trim_device(int dev) {
+    std::vector<void*> out;
+    {
+        DevCache& c = dev_cache();
+        std::lock_guard<std::mutex> g(c.mu);
+        for (auto it = c.free_blocks.begin(); it != c.free_blocks.end();) {
+            if (dev < 0 || it->first.first == dev) {
+                for (void* q : it->second) out.push_back(q);
+                c.cached -= it->first.second * it->second.size();
+                it = c.free_blocks.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
+    for (void* q : out) (void)hipFree(q);
+}
+}  // namespace
+
+namespace regdock_rt {
+hipError_t dev_alloc(void** p, size_t bytes) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const size_t rb = round_block(bytes ? bytes : 1);
+    DevCache& c = dev_cache();
+    {
+        std::lock_guard<std::mutex> g(c.mu);
+        auto it = c.free_blocks.find({dev, rb});
+        if (it != c.free_blocks.end() && !it->second.empty()) {
+            *p = it->second.back();
+            it->second.pop_back();
+            c.cached -= rb;
+            c.live[*p] = {dev, rb};
+            return hipSuccess;
+        }
+    }
+    hipError_t e = hipMalloc(p, rb);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        trim_device(dev);
+        e = hipMalloc(p, rb);
+        if (e != hipSuccess) return e;
+    }
+    std::lock_guard<std::mutex> g(c.mu);
+    c.live[*p] = {dev, rb};
+    return hipSuccess;
+}
+void dev_release(void* p) {
+    if (!p) return;
+    DevCache& c = dev_cache();
+    {
+        std::lock_guard<std::mutex> g(c.mu);
+        auto it = c.live.find(p);
+        if (it != c.live.end()) {
+            const auto key = it->second;
+            c.live.erase(it);
+            if (c.cached + key.second <= c.cap) {
+                c.free_blocks[key].push_back(p);
+                c.cached += key.second;
+                return;
+            }
+        }
+    }
+    (void)hipFree(p);
+}
+size_t dev_cached_bytes() {
+    DevCache& c = dev_cache();
+    std::lock_guard<std::mutex> g(c.mu);
+    return c.cached;
+}
+void dev_trim() { trim_device(-1); }
+}  // namespace regdock_rt
+
 struct ObjectData {
     int n = 0, nv = 0, nf = 0;
     double h = 0, tau_out1 = 0, tau_in1 = 0, rho = 0;
@@ -69,7 +162,7 @@ struct ObjectData {
     hipError_t alloc(T** p, size_t count) {
         void* q = nullptr;
         const size_t b = count * sizeof(T) > 0 ? count * sizeof(T) : 1;
-        hipError_t e = hipMalloc(&q, b);
+        hipError_t e = regdock_rt::dev_alloc(&q, b);
         if (e == hipSuccess) {
             owned.push_back(q);
             bytes += b;
@@ -80,8 +173,9 @@ struct ObjectData {
     bool matches(int n_, double h_, const reg_params& p) const {
         return n == n_ && h == h_ && tau_out1 == p.tau_out1 && tau_in1 == p.tau_in1 && rho == p.rho;
     }
+    // the last handle using the object has synchronised its stream
     ~ObjectData() {
-        for (void* q : owned) (void)hipFree(q);
+        for (void* q : owned) regdock_rt::dev_release(q);
     }
 };
 
@@ -169,7 +263,7 @@ struct reg_handle {
     template <class T>
     hipError_t alloc(T** p, size_t count) {
         void* q = nullptr;
-        hipError_t e = hipMalloc(&q, count * sizeof(T) > 0 ? count * sizeof(T) : 1);
+        hipError_t e = regdock_rt::dev_alloc(&q, count * sizeof(T) > 0 ? count * sizeof(T) : 1);
         if (e == hipSuccess) {
             owned.push_back(q);
             *p = (T*)q;
@@ -177,8 +271,11 @@ struct reg_handle {
         return e;
     }
     ~reg_handle() {
+        // queued work must finish before the blocks (and the object, released
+        // after this body) can serve anyone else
+        if (stream) (void)hipStreamSynchronize(stream);
         for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
-        for (void* p : owned) (void)hipFree(p);
+        for (void* p : owned) regdock_rt::dev_release(p);
         if (r_active_host) (void)hipHostFree(r_active_host);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
@@ -678,17 +775,20 @@ struct reg_batch {
     hipGraphExec_t exec = nullptr;
     std::vector<void*> owned;
     ~reg_batch() {
+        // replays still queued must finish before the blocks are reused
+        if (main) (void)hipStreamSynchronize(main);
+        for (auto s : br) (void)hipStreamSynchronize(s);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         for (auto e : ev) (void)hipEventDestroy(e);
         for (auto s : br) (void)hipStreamDestroy(s);
         if (main) (void)hipStreamDestroy(main);
-        for (void* p : owned) (void)hipFree(p);
+        for (void* p : owned) regdock_rt::dev_release(p);
     }
     template <class T>
     bool alloc(T** p, size_t count) {
         void* q = nullptr;
-        if (hipMalloc(&q, count * sizeof(T) > 0 ? count * sizeof(T) : 1) != hipSuccess) {
+        if (regdock_rt::dev_alloc(&q, count * sizeof(T) > 0 ? count * sizeof(T) : 1) != hipSuccess) {
             (void)hipGetLastError();
             return false;
         }
@@ -799,6 +899,10 @@ void register_free(reg_handle* h) {
     (void)hipStreamSynchronize(h->stream);
     delete h;
 }
+
+int64_t register_cached_bytes(void) { return (int64_t)regdock_rt::dev_cached_bytes(); }
+
+void register_release_cached(void) { regdock_rt::dev_trim(); }
 
 int register_info(const reg_handle* h, int32_t* n, int32_t* m, int64_t* spectrum_elems_out, int32_t* batch, int32_t* n_rot) {
     if (!h) return fail(REG_EINVAL, "NULL handle");

@@ -2,6 +2,8 @@
 // batching runtime: registrations that share one device-resident object
 // (mesh, object grid, spectrum), and the device footprint used for admission.
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include <cstddef>
 #include <cstdint>
 #include <memory>
@@ -33,6 +35,17 @@ int default_batch_for(int n, int n_rot);
 
 // the calling thread's last error message
 std::string last_error();
+
+// Device memory cache: blocks released by handles, objects, batches and
+// server requests are kept per device and rounded size for the next ones
+// (hipMalloc and hipFree cost milliseconds, and hipFree waits for the whole
+// device).  A block may be released only once no queued work uses it (the
+// releasing side synchronises its stream first).  A failed allocation returns
+// every cached block of the device to HIP and tries once more.
+hipError_t dev_alloc(void** p, size_t bytes);
+void dev_release(void* p);
+size_t dev_cached_bytes();
+void dev_trim();
 
 // Rotation batch per canvas edge chosen by the autotuner (0: none recorded).
 int tuned_batch(int n);

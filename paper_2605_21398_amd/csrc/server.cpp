@@ -127,13 +127,15 @@ int reg_server::run_gpu(Job& j, hipStream_t s) {
     std::vector<void*> dev;
     struct Free {
         std::vector<void*>& d;
+        hipStream_t s;
         ~Free() {
-            for (void* p : d) (void)hipFree(p);
+            (void)hipStreamSynchronize(s);
+            for (void* p : d) regdock_rt::dev_release(p);
         }
-    } fr{dev};
+    } fr{dev, s};
     auto dalloc = [&](size_t bytes) -> void* {
         void* p = nullptr;
-        if (hipMalloc(&p, bytes ? bytes : 1) != hipSuccess) {
+        if (regdock_rt::dev_alloc(&p, bytes ? bytes : 1) != hipSuccess) {
             (void)hipGetLastError();
             return nullptr;
         }

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     txt = open(os.path.join(ROOT, "include", "regdock.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    names = re.findall(r"^\s*(?:int|void|const char\*)\s+\**(\w+)\s*\(", txt, flags=re.M)
+    names = re.findall(r"^\s*(?:int|int64_t|void|const char\*)\s+\**(\w+)\s*\(", txt, flags=re.M)
     return sorted(set(names))
 
 
