@@ -104,6 +104,13 @@ __device__ __forceinline__ size_t brick_index(int ix, int iy, int iz, int mb) {
     return ((((size_t)(iz >> 2) * mb + (iy >> 2)) * mb + (ix >> 2)) << 6) + ((iz & 3) << 4) + ((iy & 3) << 2) + (ix & 3);
 }
 
+// brick_index in 32-bit arithmetic with 24-bit multiplies (mp^3 < 2^31 for
+// every supported canvas)
+__device__ __forceinline__ uint32_t brick_index32(uint32_t ix, uint32_t iy, uint32_t iz, uint32_t mb) {
+    const uint32_t b = __umul24(__umul24(iz >> 2, mb) + (iy >> 2), mb) + (ix >> 2);
+    return (b << 6) | ((iz & 3u) << 4) | ((iy & 3u) << 2) | (ix & 3u);
+}
+
 // Trilinear value of a binary lattice from the corner mask of the cell
 // (bit cx + 2 cy + 4 cz is the lattice value at (i + cx, j + cy, k + cz)).
 __device__ __forceinline__ float trilinear_mask(uint32_t mk, float fx, float fy, float fz) {
@@ -372,6 +379,10 @@ struct RotSampler {
 // word, the trilinear fraction the low word), so a sample costs three integer
 // additions instead of a double-precision matrix product.  The start and the
 // step are rounded from double once: after n rows the drift is below 1e-8 voxel.
+// That path needs no bounds test: rotations are orthonormal (checked and
+// normalised in double at set-up) and |k - n/2| <= n sqrt(3) / 2, so with
+// m = 2 ceil((sqrt(3) n + 2) / 2) every sample lies in [1, m - 1] on each axis
+// (the launcher checks m).  Eight rows per batch keep 16 gathers in flight.
 template <int N>
 __device__ __forceinline__ void generate_plane(float2* plane, const RotSampler& rs, const uint8_t* __restrict__ cmask, int m,
                                                int mb, int z) {
@@ -379,7 +390,7 @@ __device__ __forceinline__ void generate_plane(float2* plane, const RotSampler& 
     constexpr int TOT = N * C::N2;
     if constexpr (C::NT % C::N2 == 0) {
         constexpr int YS = C::NT / C::N2;  // row step of a lane
-        constexpr int G = 4;               // rows per batch of loads
+        constexpr int G = 8;               // rows per batch of loads
         const int j = threadIdx.x % C::N2, y0 = threadIdx.x / C::N2;
         if (y0 >= N) return;
         const double two32 = 4294967296.0;
@@ -409,9 +420,7 @@ __device__ __forceinline__ void generate_plane(float2* plane, const RotSampler& 
                     fx[q] = (float)(uint32_t)U[s2][0] * inv32;
                     fy[q] = (float)(uint32_t)U[s2][1] * inv32;
                     fz[q] = (float)(uint32_t)U[s2][2] * inv32;
-                    const bool in = (unsigned)ix < (unsigned)m && (unsigned)iy < (unsigned)m && (unsigned)iz < (unsigned)m &&
-                                    y + g * YS < N;
-                    addr[q] = in ? (int)brick_index(ix, iy, iz, mb) : -1;
+                    addr[q] = y + g * YS < N ? (int)brick_index32(ix, iy, iz, mb) : -1;
                     U[s2][0] += D[0];
                     U[s2][1] += D[1];
                     U[s2][2] += D[2];
@@ -524,23 +533,48 @@ __global__ __launch_bounds__(256) void k_zpass(float2* __restrict__ spec, const 
                                                const float2* __restrict__ twg, float scale) {
     using C = Canvas<N>;
     constexpr int E = N * C::T;
+    constexpr int PER = (E + C::ZT - 1) / C::ZT;
     __shared__ float2 buf[E];
     __shared__ float2 tw[N];
-    const int tile = blockIdx.x % C::TILES, rot = blockIdx.x / C::TILES;
+    // Block -> (tile, rotation).  Blocks are dealt round-robin to the 8 XCDs;
+    // with a batch that is a multiple of 8, each XCD takes rotations xcd,
+    // xcd + 8, ... of one tile in a row, so its L2 reads the tile of W once.
+    const int count = gridDim.x / C::TILES;
+    int tile, rot;
+    if (MODE == 0 && (count & 7) == 0) {
+        const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, per = count >> 3;
+        tile = local / per;
+        rot = (local % per) * 8 + xcd;
+    } else {
+        tile = blockIdx.x % C::TILES;
+        rot = blockIdx.x / C::TILES;
+    }
     float2* src = spec + (size_t)rot * C::H + (size_t)tile * E;
     for (int i = threadIdx.x; i < N; i += C::ZT) tw[i] = twg[i];
     batched_copy<E, C::ZT>([&](int i) { return src[i]; }, [&](int i, float2 v) { buf[i] = v; });
+    // the tile of W is loaded into registers while the forward FFT runs
+    float2 wv[PER];
+    if (MODE == 0) {
+        const float2* w = W + (size_t)tile * E;
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int i = threadIdx.x + r * C::ZT;
+            wv[r] = (E % C::ZT == 0 || i < E) ? w[i] : make_float2(0.0f, 0.0f);
+        }
+    }
     __syncthreads();
     fft_lds<N, false, C::T, C::ZT, true, N>(buf, C::T, 1, tw);
     if (MODE == 0) {
-        const float2* w = W + (size_t)tile * E;
         // the low block (max(|kx|,|ky|,|kz|) <= KLOW) is carried exactly elsewhere
         const int ky = tile / C::NT2;
         const bool low_tile = tile < N * C::NT2 && (tile % C::NT2) == 0 && (ky <= KLOW || ky >= N - KLOW);
-        for (int i = threadIdx.x; i < E; i += C::ZT) {
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int i = threadIdx.x + r * C::ZT;
+            if (E % C::ZT != 0 && i >= E) break;
             const int kz = i / C::T, kx = i % C::T;
             const bool low = low_tile && kx <= KLOW && (kz <= KLOW || kz >= N - KLOW);
-            buf[i] = low ? make_float2(0.0f, 0.0f) : cmul(buf[i], w[i]);
+            buf[i] = low ? make_float2(0.0f, 0.0f) : cmul(buf[i], wv[r]);
         }
         __syncthreads();
         fft_lds<N, true, C::T, C::ZT, true, N>(buf, C::T, 1, tw);
@@ -1450,6 +1484,9 @@ __global__ void k_validate(const float* __restrict__ V, int nv, const int32_t* _
 template <int N>
 static hipError_t launch_search_pass(int pass, const SearchBatchArgs& a) {
     using C = Canvas<N>;
+    // the sample generator relies on every rotated canvas point lying inside
+    // the lattice with a one-cell margin
+    if (a.m < 2 * (int)std::ceil((std::sqrt(3.0) * N + 2.0) / 2.0) || a.mp < a.m || a.mp % 4) return hipErrorInvalidValue;
     if (pass == 0)
         hipLaunchKernelGGL(k_rotvox_fwd_xy<N>, dim3(a.count * N), dim3(C::NT), 0, a.stream, a.cmask, a.m, a.mp / 4, a.rots,
                            a.count, a.tw, a.tw64, a.spec, a.lowT);
