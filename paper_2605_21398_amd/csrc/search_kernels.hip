@@ -373,13 +373,14 @@ struct RotSampler {
 // corner-mask loads of several elements are issued together before any is
 // used, so each lane keeps many gathers in flight.
 //
-// When every lane owns fixed columns x = 2j, 2j+1 (n/2 divides the workgroup)
-// its lattice coordinates advance by a constant step per row: they are kept in
-// 64-bit fixed point with 32 fractional bits (the integer cell is the high
-// word, the trilinear fraction the low word), so a sample costs three integer
-// additions instead of a double-precision matrix product.  The start and the
-// step are rounded from double once: after n rows the drift is below 1e-8 voxel.
-// That path needs no bounds test: rotations are orthonormal (checked and
+// Every working lane owns fixed columns x = 2j, 2j+1 (the first YS n/2 lanes,
+// YS = workgroup / (n/2); the other few are idle), so its lattice coordinates
+// advance by a constant step per row: they are kept in 64-bit fixed point with
+// 32 fractional bits (the integer cell is the high word, the trilinear
+// fraction the low word), so a sample costs three integer additions instead of
+// a double-precision matrix product.  The start and the step are rounded from
+// double once: after n rows the drift is below 1e-8 voxel.  No bounds test is
+// needed: rotations are orthonormal (checked and
 // normalised in double at set-up) and |k - n/2| <= n sqrt(3) / 2, so with
 // m = 2 ceil((sqrt(3) n + 2) / 2) every sample lies in [1, m - 1] on each axis
 // (the launcher checks m).  Eight rows per batch keep 16 gathers in flight.
@@ -388,11 +389,11 @@ __device__ __forceinline__ void generate_plane(float2* plane, const RotSampler& 
                                                int mb, int z) {
     using C = Canvas<N>;
     constexpr int TOT = N * C::N2;
-    if constexpr (C::NT % C::N2 == 0) {
-        constexpr int YS = C::NT / C::N2;  // row step of a lane
+    if constexpr (C::N2 <= C::NT) {
+        constexpr int YS = C::NT / C::N2;  // row step of a lane (YS * N2 lanes work, the rest idle)
         constexpr int G = 8;               // rows per batch of loads
         const int j = threadIdx.x % C::N2, y0 = threadIdx.x / C::N2;
-        if (y0 >= N) return;
+        if (threadIdx.x >= YS * C::N2 || y0 >= N) return;
         const double two32 = 4294967296.0;
         long long U[2][3], D[3];
         {
@@ -684,8 +685,10 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_inv_xy_argmax
     fft_lds<C::N2, true, N, C::NT, true, N>(plane, 1, C::P, tw);
     unsigned long long t0 = 0, t1 = 0, t2 = 0, t3 = 0;
     float ss = 0.0f;
-    if constexpr (C::NT % C::N2 == 0) {
-        // every lane keeps the same x = 2j, 2j+1: its low-block phases live in registers
+    if constexpr (C::N2 <= C::NT) {
+        // every working lane keeps the same x = 2j, 2j+1, so its low-block
+        // phases live in registers (YS n/2 lanes work, the rest are idle)
+        constexpr int YS = C::NT / C::N2;
         const int j = threadIdx.x % C::N2;
         double2 w0[NLX], w1[NLX];
 #pragma unroll
@@ -696,7 +699,7 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_inv_xy_argmax
         // value of the fourth key so far: a voxel below it cannot enter the
         // list, so its key is formed only at or above it
         double thr = -INFINITY;
-        for (int y = threadIdx.x / C::N2; y < N; y += C::NT / C::N2) {
+        for (int y = threadIdx.x < YS * C::N2 ? threadIdx.x / C::N2 : N; y < N; y += YS) {
             const float2 v = plane[y * C::P + j];
             const uint32_t flat0 = (uint32_t)(((z * N) + y) * N + 2 * j);
             const double2* b = btab + y * NLX;
