@@ -525,7 +525,7 @@ static int ensure_refine_buffers(reg_handle* h, int K) {
         const int cap = std::max(K, 16);
         ALLOC_TRY(h, h->rst, (size_t)cap);
         ALLOC_TRY(h, h->rtr, (size_t)cap * REF_TMAX);
-        ALLOC_TRY(h, h->rev, (size_t)cap * REF_TMAX);
+        ALLOC_TRY(h, h->rev, (size_t)cap * REF_TMAX * REF_EVAL_PARTS);
         ALLOC_TRY(h, h->rhits, (size_t)cap * REF_TMAX * h->n_poses);
         // pairs: 16 per query on average (about 3 are needed); a query whose
         // pairs do not fit is searched by itself
@@ -1263,7 +1263,7 @@ Footprint footprint(int n, int n_rot, int n_poses, int nv, int nf, int batch, in
     const size_t K = (size_t)std::max(refine_starts, 1), nq = K * REF_TMAX * N;
     f.request = H * B * 8 + B * n * KTOP * 8 + B * n * 8 + B * n * NLOW2 * 16 + B * NLOW3 * 16 + M * per_rot +
                 M * (4 + 56) + 28 * N + 48 * N + m * m * m + mp * mp * mp + 8 * n3 + n * n * ((n + 31) / 32) * 4 +
-                K * (sizeof(RefineState) + REF_TMAX * (sizeof(RefineTrial) + sizeof(RefineEval))) +
+                K * (sizeof(RefineState) + REF_TMAX * (sizeof(RefineTrial) + REF_EVAL_PARTS * sizeof(RefineEval))) +
                 nq * (sizeof(RefineHit) + 48 + 8 + 4 + 8 + 16 * (8 + 16 + 4)) + 4096;
     return f;
 }

@@ -80,6 +80,10 @@ struct RefineTrial {
 struct RefineEval {
     double J, g[6], H[21];
 };
+// the evaluation of a trial is summed by REF_EVAL_PARTS blocks over fixed
+// ranges of probe poses; the partial sums (ev holds REF_EVAL_PARTS per trial
+// slot) are added in part order by k_ref_decide
+constexpr int REF_EVAL_PARTS = 16;
 
 // One distance-query result: {d, x*} and {n, face index bits}.
 struct RefineHit {

@@ -1063,7 +1063,7 @@ __device__ void proximity(double d, const RefineConst& c, double& s, double& ds,
     d2 /= tau * tau;
 }
 
-constexpr int RED_T = 128;
+constexpr int RED_T = 64;
 constexpr int NACC = 28;  // J, grad (6), H upper triangle (21)
 
 // Cholesky solve of the SPD 6x6 system A x = b; false if A is not positive definite
@@ -1100,12 +1100,13 @@ __device__ double maxabs6(const double* v) {
     return m;
 }
 
-// One block per valid trial slot: J, grad J and the curvature in FP64 over
-// the probe poses in a fixed order.  counters[1] counts the evaluations.
+// REF_EVAL_PARTS blocks per valid trial slot, each a fixed range of probe
+// poses: -sum s, -sum s' g and the curvature sum max(0, -s'') g g^T in FP64,
+// lane sums added in lane order.  counters[1] counts the evaluations.
 __global__ __launch_bounds__(RED_T) void k_ref_eval(const RefineTrial* __restrict__ tr, const RefineHit* __restrict__ hits,
                                                    int N, RefineConst c, RefineEval* __restrict__ ev,
                                                    int* __restrict__ counters) {
-    const int k = blockIdx.x;
+    const int k = blockIdx.x / REF_EVAL_PARTS, part = blockIdx.x % REF_EVAL_PARTS;
     const RefineTrial& S = tr[k];
     if (!S.valid) return;
     __shared__ double red[NACC][RED_T];
@@ -1117,7 +1118,9 @@ __global__ __launch_bounds__(RED_T) void k_ref_eval(const RefineTrial* __restric
     for (int j = 0; j < 3; ++j) cc[j] = S.c[j];
     double acc[NACC];
     for (int j = 0; j < NACC; ++j) acc[j] = 0.0;
-    for (int i = threadIdx.x; i < N; i += RED_T) {
+    const int chunk = (N + REF_EVAL_PARTS - 1) / REF_EVAL_PARTS;
+    const int i1 = min(N, (part + 1) * chunk);
+    for (int i = part * chunk + threadIdx.x; i < i1; i += RED_T) {
         const RefineHit hv = hits[(size_t)k * N + i];
         double s, ds, d2;
         proximity((double)hv.dx.x, c, s, ds, d2);
@@ -1140,22 +1143,12 @@ __global__ __launch_bounds__(RED_T) void k_ref_eval(const RefineTrial* __restric
     }
     for (int j = 0; j < NACC; ++j) red[j][threadIdx.x] = acc[j];
     __syncthreads();
-    for (int stride = RED_T / 2; stride > 0; stride >>= 1) {
-        if (threadIdx.x < stride)
-            for (int j = 0; j < NACC; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + stride];
-        __syncthreads();
+    if (threadIdx.x < NACC) {
+        double t = 0.0;
+        for (int l = 0; l < RED_T; ++l) t += red[threadIdx.x][l];
+        reinterpret_cast<double*>(&ev[blockIdx.x])[threadIdx.x] = t;
     }
-    if (threadIdx.x == 0) {
-        RefineEval& E = ev[k];
-        double xx = 0;
-        for (int j = 0; j < 6; ++j) xx += S.xe[j] * S.xe[j];
-        E.J = red[0][0] + c.lambda * xx;
-        for (int j = 0; j < 6; ++j) E.g[j] = red[1 + j][0] + 2 * c.lambda * S.xe[j];
-        int o = 0;
-        for (int a = 0; a < 6; ++a)
-            for (int b = a; b < 6; ++b, ++o) E.H[o] = red[7 + o][0] + (a == b ? 2 * c.lambda : 0.0);
-        atomicAdd(&counters[1], 1);
-    }
+    if (part == 0 && threadIdx.x == 0) atomicAdd(&counters[1], 1);
 }
 
 // Trial step with damping mu from (xi, g, H): a coordinate at its bound whose
@@ -1200,6 +1193,33 @@ __global__ void k_ref_decide(RefineState* __restrict__ st, RefineTrial* __restri
     RefineState& S = st[k];
     if (S.status == 2) return;
     __shared__ int ntrial;
+    // the trials' evaluations: partial sums in part order, plus lambda |xi|^2
+    // and its derivatives
+    __shared__ RefineEval Es[REF_TMAX];
+    for (int t = threadIdx.x; t < REF_TMAX * NACC; t += blockDim.x) {
+        const int j = t / NACC, a = t % NACC;
+        const RefineTrial& T = tr[k * REF_TMAX + j];
+        if (!T.valid) continue;
+        double v = 0.0;
+        for (int p = 0; p < REF_EVAL_PARTS; ++p)
+            v += reinterpret_cast<const double*>(&ev[(k * REF_TMAX + j) * REF_EVAL_PARTS + p])[a];
+        if (a == 0) {
+            double xx = 0.0;
+            for (int q = 0; q < 6; ++q) xx += T.xe[q] * T.xe[q];
+            v += c.lambda * xx;
+        } else if (a < 7) {
+            v += 2 * c.lambda * T.xe[a - 1];
+        } else {
+            int o = a - 7, r = 0;  // upper-triangle index o -> row r, diagonal when o hits its start
+            while (o >= 6 - r) {
+                o -= 6 - r;
+                ++r;
+            }
+            if (o == 0) v += 2 * c.lambda;
+        }
+        reinterpret_cast<double*>(&Es[j])[a] = v;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         int next = 0;
         int taken = -1;
@@ -1208,7 +1228,7 @@ __global__ void k_ref_decide(RefineState* __restrict__ st, RefineTrial* __restri
         for (int j = 0; j < REF_TMAX; ++j) {
             const RefineTrial& T = tr[k * REF_TMAX + j];
             if (!T.valid) break;
-            const RefineEval& E = ev[k * REF_TMAX + j];
+            const RefineEval& E = Es[j];
             if (S.status == 0 || E.J < S.J) {
                 taken = j;
                 break;
@@ -1221,7 +1241,7 @@ __global__ void k_ref_decide(RefineState* __restrict__ st, RefineTrial* __restri
         }
         if (taken >= 0) {
             const RefineTrial& T = tr[k * REF_TMAX + taken];
-            const RefineEval& E = ev[k * REF_TMAX + taken];
+            const RefineEval& E = Es[taken];
             const bool first = S.status == 0;
             for (int j = 0; j < 6; ++j) {
                 S.xi[j] = T.xe[j];
@@ -1332,7 +1352,7 @@ hipError_t refine_round(RefineState* st, RefineTrial* tr, int K, const RefineGeo
                         int* counters, hipStream_t s) {
     const int slots = K * REF_TMAX;
     launch_queries(tr, slots, geo, poses, n_poses, c, w, hits, counters, s);
-    k_ref_eval<<<slots, RED_T, 0, s>>>(tr, hits, n_poses, c, ev, counters);
+    k_ref_eval<<<slots * REF_EVAL_PARTS, RED_T, 0, s>>>(tr, hits, n_poses, c, ev, counters);
     k_ref_decide<<<K, 64, 0, s>>>(st, tr, ev, c, w.pair_count, counters);
     return hipGetLastError();
 }
