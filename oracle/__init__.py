@@ -9,7 +9,9 @@ the two share no code (the seeded input generators in `synth` feed both).
              circular correlation, peak and pose, top-K
   refine  -- Sec. V: SE(3) refinement (pose update, proximity score,
              distance queries, sensitivities, damped Gauss-Newton)
+  sampling -- Sec. IV-C: Super-Fibonacci and GeoBall-SF orientation samplers
 """
 from . import search  # noqa: F401
 from .search import GridParams  # noqa: F401
 from . import refine  # noqa: F401
+from . import sampling  # noqa: F401
