@@ -209,6 +209,49 @@ def serve_bench(rd, reqs, args):
                          "with 8192; 300..2000 probe poses; search + top-16 + refinement per request")}
 
 
+def local_search_bench(rd, torch, p, args):
+    """Local search in the orientation subspace (Sec. IV-C, IV-D): GeoBall-SF
+    samples in the geodesic ball of radius theta around the global maximum,
+    scored on the same handle (same object grid and swept lattice)."""
+    import numpy as np
+
+    def sync():
+        torch.cuda.synchronize()
+        return time.perf_counter()
+
+    def angle_deg(q):
+        q = np.asarray(q, dtype=np.float64)
+        q = q / np.linalg.norm(q)
+        return float(np.degrees(2.0 * np.arccos(min(1.0, abs(float(np.dot(q, p.q_gt)))))))
+
+    h = rd.register_init(p.vertices, p.faces, p.touchable, p.poses, p.so3, p.n, p.h, p.center, p.radius, p.length)
+    try:
+        sc, _, po = rd.score_rotations(h)
+        sc, po = sc.cpu().numpy(), po.cpu().numpy()
+        g = int(np.argmax(sc))
+        q_star = po[g, :4]
+        theta = np.radians(args.local_theta)
+        t0 = sync()
+        local = rd.so3_geoball_sf(args.local, q_star, theta)
+        t1 = sync()
+        rd.register_set_rotations(h, local)
+        rd.score_rotations(h)  # warm
+        times = []
+        for _ in range(2):
+            t2 = sync()
+            sc2, _, po2 = rd.score_rotations(h)
+            times.append(sync() - t2)
+        sc2, po2 = sc2.cpu().numpy(), po2.cpu().numpy()
+        b = int(np.argmax(sc2))
+        score_s = min(times)
+        return {"samples": args.local, "theta_deg": args.local_theta, "sampler": "GeoBall-SF (gamma = n)",
+                "sampler_ms": (t1 - t0) * 1e3, "score_ms": score_s * 1e3, "rotations_per_s": args.local / score_s,
+                "best_score_global": float(sc[g]), "best_score_local": float(sc2[b]),
+                "rotation_error_deg": {"global": angle_deg(q_star), "local": angle_deg(po2[b, :4])}}
+    finally:
+        rd.register_free(h)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +266,8 @@ def main():
     ap.add_argument("--serve-sustained", type=float, default=6.0,
                     help="a second arrival rate below the serial path's capacity (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--local", type=int, default=5000, help="GeoBall-SF samples of the local search (0: skip)")
+    ap.add_argument("--local-theta", type=float, default=5.0, help="geodesic ball radius (deg)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="issue one plain 512 MiB device copy first (the counter calibration of the traffic figure)")
     args = ap.parse_args()
@@ -339,6 +384,9 @@ def main():
                    "best_J": float(np.min(info["J"]))},
     }
     print("bench: timed steps done", file=sys.stderr, flush=True)
+    if args.local > 0:
+        out["local_search"] = local_search_bench(rd, torch, p, args)
+        print("bench: local search done", file=sys.stderr, flush=True)
     if args.batch > 0:
         out["batch"] = batch_bench(rd, torch, work["batch"], args)
         print("bench: uneven batch done", file=sys.stderr, flush=True)

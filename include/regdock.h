@@ -151,6 +151,33 @@ int register_top_k(reg_handle* h, const float* scores, int32_t count, int32_t K,
  * an allocation that fails first returns the device's cached blocks to HIP). */
 void register_free(reg_handle* h);
 
+/* ------------------------------------------------ orientation samplers
+ * (Sec. IV-C).  Unit quaternions, scalar first, written as n x 4 float32 to
+ * the device buffer `out` on hip_stream (NULL: the null stream); the call
+ * returns when they are written.  Errors: REG_EINVAL, REG_EDEVICE. */
+
+/* Super-Fibonacci sequence (the global sampler the paper adopts): for
+ * s = i + 1/2, r = sqrt(s/n), R = sqrt(1 - s/n), a = 2 pi s / sqrt 2,
+ * b = 2 pi s / psi (psi^4 = psi + 4): q = (r sin a, r cos a, R sin b, R cos b). */
+int so3_super_fibonacci(int32_t n, float* out, void* hip_stream);
+
+/* GeoBall-SF (Alg. geoball-sf): n low-discrepancy samples uniform in the
+ * geodesic ball {q : arccos |<q, q0>| <= theta} (rotations within 2 theta of
+ * q0).  q0: 4 host doubles (normalised here); theta in (0, pi/2]; gamma: the
+ * divisor of the radial coordinate u1 = (i + 1/2) / gamma mod 1, 0 meaning
+ * gamma = n (the paper leaves it undefined).  The radial law r L(r),
+ * L(r) = 2 arccos(cos theta / sqrt(1 - r^2)), is tabulated at 4096 points and
+ * inverted by linear interpolation. */
+int so3_geoball_sf(int32_t n, const double* q0, double theta, double gamma, float* out, void* hip_stream);
+
+/* Replace the handle's SO(3) sample set (M x 4 float32 on the device, copied)
+ * so that score_rotations scores it against the same object grid and swept
+ * lattice, e.g. the local GeoBall-SF set around the global maximum (Sec.
+ * IV-D).  Synchronises the handle's stream.  Errors: REG_EINVAL (NULL, M < 1,
+ * a quaternion norm outside 1 +- 1e-3: the handle then has no rotations until
+ * a valid set is given), REG_ENOMEM, REG_EDEVICE. */
+int register_set_rotations(reg_handle* h, const float* so3, int32_t n_rot);
+
 /* Memory management (not an operation of the method): bytes held by the
  * device memory cache, and the release of every cached block back to HIP. */
 int64_t register_cached_bytes(void);

@@ -29,7 +29,7 @@ EXPORTS = ["register_init", "score_rotations", "register_top_k", "register_free"
            "register_server_destroy", "register_submit", "register_poll", "register_wait", "register_server_stats",
            "register_server_last_error", "register_batch_create", "register_batch_run", "register_batch_outputs",
            "register_batch_free", "register_autotune", "register_tuned_batch", "register_cached_bytes",
-           "register_release_cached"]
+           "register_release_cached", "so3_super_fibonacci", "so3_geoball_sf", "register_set_rotations"]
 
 
 class RegError(RuntimeError):
@@ -112,6 +112,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.register_free.argtypes = [p]
     L.register_cached_bytes.restype = i64
     L.register_cached_bytes.argtypes = []
+    L.so3_super_fibonacci.restype = ctypes.c_int
+    L.so3_super_fibonacci.argtypes = [i32, p, p]
+    L.so3_geoball_sf.restype = ctypes.c_int
+    L.so3_geoball_sf.argtypes = [i32, p, ctypes.c_double, ctypes.c_double, p, p]
+    L.register_set_rotations.restype = ctypes.c_int
+    L.register_set_rotations.argtypes = [p, p, i32]
     L.register_release_cached.restype = None
     L.register_release_cached.argtypes = []
     L.register_last_error.restype = ctypes.c_char_p
@@ -491,6 +497,38 @@ def register_autotune(h: Handle, max_rotations: int = 512) -> int:
 
 def register_tuned_batch(n: int) -> int:
     return load_library().register_tuned_batch(n)
+
+
+# -------------------------------------------------------- orientation samplers
+
+def so3_super_fibonacci(n: int, stream=None):
+    """n Super-Fibonacci unit quaternions (scalar first), float32 [n, 4] on the device."""
+    torch = _torch()
+    out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(load_library().so3_super_fibonacci(n, _ptr(out), ctypes.c_void_p(st.cuda_stream)))
+    return out
+
+
+def so3_geoball_sf(n: int, q0, theta: float, gamma: float = 0.0, stream=None):
+    """n GeoBall-SF unit quaternions in the geodesic ball of radius theta (rad)
+    around q0 (scalar first), float32 [n, 4] on the device; gamma 0 means n."""
+    torch = _torch()
+    out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    q = np.ascontiguousarray(q0, dtype=np.float64).reshape(4)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(load_library().so3_geoball_sf(n, q.ctypes.data_as(ctypes.c_void_p), float(theta), float(gamma), _ptr(out),
+                                          ctypes.c_void_p(st.cuda_stream)))
+    return out
+
+
+def register_set_rotations(h: Handle, so3) -> None:
+    """Replace the handle's SO(3) sample set (M x 4 unit quaternions)."""
+    torch = _torch()
+    Q = _dev(so3, torch.float32)
+    h.n_rot = 0
+    _check(load_library().register_set_rotations(h.ptr, _ptr(Q), Q.shape[0]))
+    h.n_rot = int(Q.shape[0])
 
 
 def register_cached_bytes() -> int:

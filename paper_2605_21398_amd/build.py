@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libregdock.so")
-SOURCES = ["search_kernels.hip", "refine_kernels.hip", "api.cpp", "server.cpp"]
+SOURCES = ["search_kernels.hip", "refine_kernels.hip", "so3_sampling.hip", "api.cpp", "server.cpp"]
 ARCH = os.environ.get("REGDOCK_ARCH", "gfx950")
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU ops.

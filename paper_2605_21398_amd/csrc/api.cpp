@@ -18,6 +18,7 @@
 #include "regdock.h"
 #include "runtime.h"
 #include "search_kernels.h"
+#include "so3_sampling.h"
 
 using namespace regdock;
 
@@ -185,6 +186,7 @@ struct reg_handle {
     bool own_stream = false;
     bool poisoned = false;
     int n = 0, m = 0, mp = 0, n_rot = 0, n_poses = 0, nv = 0, nf = 0, batch = 0;
+    int rot_cap = 0;  // rotations the per-rotation buffers hold
     size_t H = 0;
     double h = 0, wc[3] = {0, 0, 0};
     reg_probe probe{};
@@ -269,6 +271,15 @@ struct reg_handle {
             *p = (T*)q;
         }
         return e;
+    }
+    // give one owned block back (the stream has no queued work using it)
+    void release(void* p) {
+        for (size_t i = 0; i < owned.size(); ++i)
+            if (owned[i] == p) {
+                owned.erase(owned.begin() + i);
+                regdock_rt::dev_release(p);
+                return;
+            }
     }
     ~reg_handle() {
         // queued work must finish before the blocks (and the object, released
@@ -547,6 +558,28 @@ static int ensure_refine_buffers(reg_handle* h, int K) {
 // register_init with an optional object already built for the same mesh,
 // canvas and object-grid thresholds (the serving cache): then the mesh copy,
 // the object grid, its spectrum and nonzero list are taken from it.
+// Per-rotation buffers for `count` rotations (the old ones, if any, are
+// released first; the handle's stream has no queued work using them).
+static int alloc_rotation_buffers(reg_handle* h, int count) {
+    for (void* p : {(void*)h->so3, (void*)h->rots, (void*)h->cand_idx, (void*)h->cand_n, (void*)h->cand_part,
+                    (void*)h->window, (void*)h->ovf, (void*)h->best_val, (void*)h->best_flat, (void*)h->need_list})
+        if (p) h->release(p);
+    h->rot_cap = 0;
+    const size_t M = (size_t)count;
+    ALLOC_TRY(h, h->so3, 4 * M);
+    ALLOC_TRY(h, h->rots, 9 * M);
+    ALLOC_TRY(h, h->cand_idx, M * CMAX);
+    ALLOC_TRY(h, h->cand_n, M);
+    ALLOC_TRY(h, h->cand_part, M * CMAX * rescore_slices(h->n));
+    ALLOC_TRY(h, h->window, M);
+    ALLOC_TRY(h, h->ovf, M);
+    ALLOC_TRY(h, h->best_val, M);
+    ALLOC_TRY(h, h->best_flat, M);
+    ALLOC_TRY(h, h->need_list, M);
+    h->rot_cap = count;
+    return REG_OK;
+}
+
 static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* poses, int32_t n_poses,
                      const float* so3, int32_t n_rot, const reg_grid_spec* grid, const reg_params* params,
                      void* hip_stream, std::shared_ptr<ObjectData> cached, reg_handle** out) {
@@ -640,8 +673,10 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
     h->tw64 = o->tw64;
 
     ALLOC_TRY(h, h->poses, 7 * (size_t)n_poses);
-    ALLOC_TRY(h, h->so3, 4 * (size_t)n_rot);
-    ALLOC_TRY(h, h->rots, 9 * (size_t)n_rot);
+    {
+        const int rc = alloc_rotation_buffers(h, n_rot);
+        if (rc) return rc;
+    }
     ALLOC_TRY(h, h->pose_prep, 12 * (size_t)n_poses);
     if (build) {
         ALLOC_TRY(h, h->od2, n3);
@@ -651,15 +686,7 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
     ALLOC_TRY(h, h->spec, h->H * (size_t)h->batch);
     ALLOC_TRY(h, h->ptop, (size_t)h->batch * h->n * KTOP);
     ALLOC_TRY(h, h->pssq, (size_t)h->batch * h->n);
-    ALLOC_TRY(h, h->cand_idx, (size_t)n_rot * CMAX);
-    ALLOC_TRY(h, h->cand_n, (size_t)n_rot);
-    ALLOC_TRY(h, h->cand_part, (size_t)n_rot * CMAX * rescore_slices(h->n));
     ALLOC_TRY(h, h->stats, 5);
-    ALLOC_TRY(h, h->window, (size_t)n_rot);
-    ALLOC_TRY(h, h->ovf, (size_t)n_rot);
-    ALLOC_TRY(h, h->best_val, (size_t)n_rot);
-    ALLOC_TRY(h, h->best_flat, (size_t)n_rot);
-    ALLOC_TRY(h, h->need_list, (size_t)n_rot);
     ALLOC_TRY(h, h->need_count, 1);
     ALLOC_TRY(h, h->Sw, m3);
     ALLOC_TRY(h, h->cm, mp3);
@@ -898,6 +925,54 @@ void register_free(reg_handle* h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
     delete h;
+}
+
+// ------------------------------------------------------ orientation samplers
+
+int so3_super_fibonacci(int32_t n, float* out, void* hip_stream) {
+    if (n < 1 || !out) return fail(REG_EINVAL, "n >= 1 and an output buffer are required");
+    hipStream_t s = (hipStream_t)hip_stream;
+    reg_handle* none = nullptr;
+    DEV_TRY(none, super_fibonacci(n, out, s));
+    DEV_TRY(none, hipStreamSynchronize(s));
+    return REG_OK;
+}
+
+int so3_geoball_sf(int32_t n, const double* q0, double theta, double gamma, float* out, void* hip_stream) {
+    if (n < 1 || !out || !q0) return fail(REG_EINVAL, "n >= 1, q0 and an output buffer are required");
+    double qn = 0.0;
+    for (int j = 0; j < 4; ++j) {
+        if (!std::isfinite(q0[j])) return fail(REG_EINVAL, "non-finite q0");
+        qn += q0[j] * q0[j];
+    }
+    if (!(qn > 1e-12)) return fail(REG_EINVAL, "q0 has zero norm");
+    if (!(theta > 0.0 && theta <= 0.5 * M_PI)) return fail(REG_EINVAL, "theta must lie in (0, pi/2]");
+    if (!(gamma >= 0.0) || !std::isfinite(gamma)) return fail(REG_EINVAL, "gamma must be >= 0 (0: gamma = n)");
+    reg_handle* none = nullptr;
+    DEV_TRY(none, geoball_sf(n, q0, theta, gamma, out, (hipStream_t)hip_stream));
+    return REG_OK;
+}
+
+int register_set_rotations(reg_handle* h, const float* so3, int32_t n_rot) {
+    if (!h || !so3) return fail(REG_EINVAL, "NULL argument");
+    if (h->poisoned) return fail(REG_EDEVICE, "handle unusable after a device error");
+    if (n_rot < 1) return fail(REG_EINVAL, "n_rot must be >= 1");
+    hipStream_t s = h->stream;
+    DEV_TRY(h, hipStreamSynchronize(s));
+    if (n_rot > h->rot_cap) {
+        const int rc = alloc_rotation_buffers(h, n_rot);
+        if (rc) return rc;
+    }
+    DEV_TRY(h, hipMemcpyAsync(h->so3, so3, 16 * (size_t)n_rot, hipMemcpyDeviceToDevice, s));
+    DEV_TRY(h, hipMemsetAsync(h->err, 0, sizeof(int), s));
+    DEV_TRY(h, setup_rotations(h->so3, n_rot, h->rots, h->err, s));
+    int herr = 0;
+    DEV_TRY(h, hipMemcpyAsync(&herr, h->err, sizeof(int), hipMemcpyDeviceToHost, s));
+    DEV_TRY(h, hipStreamSynchronize(s));
+    h->n_rot = 0;  // unusable until the new set is known to be valid
+    if (herr & REGK_ERR_QUAT) return fail(REG_EINVAL, "quaternion norm outside 1 +- 1e-3 (or not finite)");
+    h->n_rot = n_rot;
+    return REG_OK;
 }
 
 int64_t register_cached_bytes(void) { return (int64_t)regdock_rt::dev_cached_bytes(); }
