@@ -175,7 +175,8 @@ int so3_geoball_sf(int32_t n, const double* q0, double theta, double gamma, floa
  * lattice, e.g. the local GeoBall-SF set around the global maximum (Sec.
  * IV-D).  Synchronises the handle's stream.  Errors: REG_EINVAL (NULL, M < 1,
  * a quaternion norm outside 1 +- 1e-3: the handle then has no rotations until
- * a valid set is given), REG_ENOMEM, REG_EDEVICE. */
+ * a valid set is given), REG_EBUSY (the handle is in a live batch, whose graph
+ * captured its rotation set), REG_ENOMEM, REG_EDEVICE. */
 int register_set_rotations(reg_handle* h, const float* so3, int32_t n_rot);
 
 /* Memory management (not an operation of the method): bytes held by the

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <future>
 #include <mutex>
 #include <unordered_map>
 #include <string>
@@ -137,6 +138,13 @@ size_t dev_cached_bytes() {
 void dev_trim() { trim_device(-1); }
 }  // namespace regdock_rt
 
+// Refinement hierarchy on the host (built off the device path, uploaded once).
+struct HostGeometry {
+    std::vector<float4> face, cl, top;
+    std::vector<int2> cl_range, top_range;
+    std::vector<int> slot_of;
+};
+
 struct ObjectData {
     int n = 0, nv = 0, nf = 0;
     double h = 0, tau_out1 = 0, tau_in1 = 0, rho = 0;
@@ -157,6 +165,8 @@ struct ObjectData {
     double2* tw64 = nullptr;
     bool geo_ready = false;
     RefineGeometry geo{};
+    std::mutex geo_mu;                        // the first refinement of the object builds geo
+    std::future<HostGeometry> geo_job;  // host part of geo, started when the object is built
     size_t bytes = 0;
     std::vector<void*> owned;
     template <class T>
@@ -176,6 +186,7 @@ struct ObjectData {
     }
     // the last handle using the object has synchronised its stream
     ~ObjectData() {
+        if (geo_job.valid()) geo_job.wait();
         for (void* q : owned) regdock_rt::dev_release(q);
     }
 };
@@ -186,7 +197,8 @@ struct reg_handle {
     bool own_stream = false;
     bool poisoned = false;
     int n = 0, m = 0, mp = 0, n_rot = 0, n_poses = 0, nv = 0, nf = 0, batch = 0;
-    int rot_cap = 0;  // rotations the per-rotation buffers hold
+    int rot_cap = 0;     // rotations the per-rotation buffers hold
+    int in_batches = 0;  // live batches whose captured graph holds this handle's buffers
     size_t H = 0;
     double h = 0, wc[3] = {0, 0, 0};
     reg_probe probe{};
@@ -373,14 +385,10 @@ static int build_object_derived(reg_handle* h) {
 // own radius), widened by 1e-5 mm so that float32 evaluation stays
 // conservative.  Face centroid and radius follow the body-frame definition of
 // the bounding-sphere test (mean of the three vertices, largest vertex distance).
-static int build_refine_geometry(reg_handle* h) {
-    ObjectData* o = h->obj.get();
-    const int nf = h->nf, nv = h->nv;
-    std::vector<float> V(3 * (size_t)nv);
-    std::vector<int32_t> F(3 * (size_t)nf);
-    DEV_TRY(h, hipMemcpyAsync(V.data(), h->V, V.size() * 4, hipMemcpyDeviceToHost, h->stream));
-    DEV_TRY(h, hipMemcpyAsync(F.data(), h->F, F.size() * 4, hipMemcpyDeviceToHost, h->stream));
-    DEV_TRY(h, hipStreamSynchronize(h->stream));
+// Faces in Morton order of their centroids with clusters of REF_FANOUT faces
+// and top nodes of REF_FANOUT clusters (pure host work on copies of the mesh).
+static HostGeometry host_refine_geometry(std::vector<float> V, std::vector<int32_t> F, int nv, int nf) {
+    (void)nv;
     std::vector<double> fc(3 * (size_t)nf), fr(nf);
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int f = 0; f < nf; ++f) {
@@ -475,22 +483,58 @@ static int build_refine_geometry(reg_handle* h) {
         top[t] = make_float4((float)tc[0], (float)tc[1], (float)tc[2], (float)(r * (1 + 1e-6) + slack));
         top_range[t] = make_int2(c0, c1 - c0);
     }
+    HostGeometry g;
+    g.face = std::move(face);
+    g.cl = std::move(cl);
+    g.top = std::move(top);
+    g.cl_range = std::move(cl_range);
+    g.top_range = std::move(top_range);
+    g.slot_of = std::move(slot_of);
+    return g;
+}
+
+// Starts the host part of the hierarchy on a thread of its own (the mesh is
+// on the device and the stream idle); the first refinement uploads it.
+static int start_refine_geometry(reg_handle* h) {
+    std::vector<float> V(3 * (size_t)h->nv);
+    std::vector<int32_t> F(3 * (size_t)h->nf);
+    DEV_TRY(h, hipMemcpyAsync(V.data(), h->V, V.size() * 4, hipMemcpyDeviceToHost, h->stream));
+    DEV_TRY(h, hipMemcpyAsync(F.data(), h->F, F.size() * 4, hipMemcpyDeviceToHost, h->stream));
+    DEV_TRY(h, hipStreamSynchronize(h->stream));
+    h->obj->geo_job = std::async(std::launch::async, host_refine_geometry, std::move(V), std::move(F), h->nv, h->nf);
+    return REG_OK;
+}
+
+// The hierarchy on the device (called with the object's geo_mu held).
+static int build_refine_geometry(reg_handle* h) {
+    ObjectData* o = h->obj.get();
+    if (!o->geo_job.valid()) {
+        const int rc = start_refine_geometry(h);
+        if (rc) return rc;
+    }
+    HostGeometry g;
+    try {
+        g = o->geo_job.get();
+    } catch (const std::exception& e) {
+        return fail(REG_ENOMEM, "refinement hierarchy: %s", e.what());
+    }
+    const int n_cl = (int)g.cl.size(), n_top = (int)g.top.size();
     float4 *d_face, *d_cl, *d_top;
     int2 *d_clr, *d_topr;
     int* d_slot;
-    OBJ_ALLOC_TRY(o, d_slot, slot_of.size());
-    OBJ_ALLOC_TRY(o, d_face, face.size());
-    OBJ_ALLOC_TRY(o, d_cl, cl.size());
-    OBJ_ALLOC_TRY(o, d_top, top.size());
-    OBJ_ALLOC_TRY(o, d_clr, cl_range.size());
-    OBJ_ALLOC_TRY(o, d_topr, top_range.size());
+    OBJ_ALLOC_TRY(o, d_slot, g.slot_of.size());
+    OBJ_ALLOC_TRY(o, d_face, g.face.size());
+    OBJ_ALLOC_TRY(o, d_cl, g.cl.size());
+    OBJ_ALLOC_TRY(o, d_top, g.top.size());
+    OBJ_ALLOC_TRY(o, d_clr, g.cl_range.size());
+    OBJ_ALLOC_TRY(o, d_topr, g.top_range.size());
     hipStream_t s = h->stream;
-    DEV_TRY(h, hipMemcpyAsync(d_face, face.data(), face.size() * sizeof(float4), hipMemcpyHostToDevice, s));
-    DEV_TRY(h, hipMemcpyAsync(d_cl, cl.data(), cl.size() * sizeof(float4), hipMemcpyHostToDevice, s));
-    DEV_TRY(h, hipMemcpyAsync(d_top, top.data(), top.size() * sizeof(float4), hipMemcpyHostToDevice, s));
-    DEV_TRY(h, hipMemcpyAsync(d_clr, cl_range.data(), cl_range.size() * sizeof(int2), hipMemcpyHostToDevice, s));
-    DEV_TRY(h, hipMemcpyAsync(d_topr, top_range.data(), top_range.size() * sizeof(int2), hipMemcpyHostToDevice, s));
-    DEV_TRY(h, hipMemcpyAsync(d_slot, slot_of.data(), slot_of.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    DEV_TRY(h, hipMemcpyAsync(d_face, g.face.data(), g.face.size() * sizeof(float4), hipMemcpyHostToDevice, s));
+    DEV_TRY(h, hipMemcpyAsync(d_cl, g.cl.data(), g.cl.size() * sizeof(float4), hipMemcpyHostToDevice, s));
+    DEV_TRY(h, hipMemcpyAsync(d_top, g.top.data(), g.top.size() * sizeof(float4), hipMemcpyHostToDevice, s));
+    DEV_TRY(h, hipMemcpyAsync(d_clr, g.cl_range.data(), g.cl_range.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    DEV_TRY(h, hipMemcpyAsync(d_topr, g.top_range.data(), g.top_range.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    DEV_TRY(h, hipMemcpyAsync(d_slot, g.slot_of.data(), g.slot_of.size() * sizeof(int), hipMemcpyHostToDevice, s));
     DEV_TRY(h, hipStreamSynchronize(s));
     o->geo = RefineGeometry{d_top, d_topr, d_cl, d_clr, d_face, d_slot, n_top, n_cl};
     o->geo_ready = true;
@@ -520,9 +564,12 @@ static RefineConst refine_const(const reg_handle* h) {
 }
 
 static int ensure_refine_buffers(reg_handle* h, int K) {
-    if (!h->obj->geo_ready) {
-        int rc = build_refine_geometry(h);
-        if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> g(h->obj->geo_mu);
+        if (!h->obj->geo_ready) {
+            int rc = build_refine_geometry(h);
+            if (rc) return rc;
+        }
     }
     if (!h->r_active_host) {
         if (hipHostMalloc((void**)&h->r_active_host, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
@@ -727,8 +774,11 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
     if (herr & REGK_ERR_FACE) return fail(REG_EINVAL, "face vertex index out of range");
     if (herr & REGK_ERR_QUAT) return fail(REG_EINVAL, "quaternion norm outside 1 +- 1e-3 (or not finite)");
 
-    // object grid and spectrum (per object), swept occupancy (per request)
+    // object grid and spectrum (per object), swept occupancy (per request);
+    // the refinement hierarchy is built on the host meanwhile
     if (build) {
+        const int grc = start_refine_geometry(h);
+        if (grc) return grc;
         DEV_TRY(h, setup_anchor(h->V, h->nv, h->anchor, s));
         DEV_TRY(h, setup_object_grid(h->V, h->F, h->touch, h->nf, h->n, h->h, h->anchor, (float)h->prm.tau_out1,
                                      (float)h->prm.tau_in1, (float)h->prm.rho, h->O, h->fo,
@@ -811,6 +861,7 @@ struct reg_batch {
         for (auto s : br) (void)hipStreamDestroy(s);
         if (main) (void)hipStreamDestroy(main);
         for (void* p : owned) regdock_rt::dev_release(p);
+        for (reg_handle* h : hs) --h->in_batches;
     }
     template <class T>
     bool alloc(T** p, size_t count) {
@@ -957,6 +1008,8 @@ int register_set_rotations(reg_handle* h, const float* so3, int32_t n_rot) {
     if (!h || !so3) return fail(REG_EINVAL, "NULL argument");
     if (h->poisoned) return fail(REG_EDEVICE, "handle unusable after a device error");
     if (n_rot < 1) return fail(REG_EINVAL, "n_rot must be >= 1");
+    if (h->in_batches > 0)
+        return fail(REG_EBUSY, "a live batch captured this handle's rotation set; free the batch first");
     hipStream_t s = h->stream;
     DEV_TRY(h, hipStreamSynchronize(s));
     if (n_rot > h->rot_cap) {
@@ -1186,6 +1239,7 @@ int register_batch_create(reg_handle* const* handles, int32_t count, int32_t top
         for (int j = 0; j < i; ++j)
             if (handles[j] == h) return fail(REG_EINVAL, "handle %d appears twice", i);
         b->hs.push_back(h);
+        ++h->in_batches;  // released by ~reg_batch
         const int K = std::min<int>(top_k, h->n_rot);
         b->K.push_back(K);
         if (b->refine) {

@@ -669,7 +669,8 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_inv_xy_argmax
     // az is complete before the first barrier inside the y inverse FFT and is
     // read only after it
     fft_lds<N, true, C::P, C::NT, true, N>(plane, C::P, 1, tw);
-    // btab[y][kx] = sum_ky az[kx][ky] e^{+2 pi i ky y / N}
+    // btab[y][kx] = sum_ky az[kx][ky] e^{+2 pi i ky y / N}, doubled for kx > 0
+    // (the field sums Re b_0 + 2 sum_kx Re(b_kx e^{+2 pi i kx x / N}))
     for (int t = threadIdx.x; t < N * NLX; t += C::NT) {
         const int y = t / NLX, kx = t % NLX;
         double2 acc = make_double2(0.0, 0.0);
@@ -679,7 +680,7 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_inv_xy_argmax
             acc.x += v.x;
             acc.y += v.y;
         }
-        btab[t] = acc;
+        btab[t] = kx > 0 ? make_double2(2.0 * acc.x, 2.0 * acc.y) : acc;
     }
     c2r_pre<N>(plane, tw);
     fft_lds<C::N2, true, N, C::NT, true, N>(plane, 1, C::P, tw);
@@ -707,8 +708,8 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_inv_xy_argmax
 #pragma unroll
             for (int k = 1; k < NLX; ++k) {
                 const double2 bk = b[k];
-                c0 = fma(2.0 * bk.x, w0[k].x, fma(2.0 * bk.y, w0[k].y, c0));
-                c1 = fma(2.0 * bk.x, w1[k].x, fma(2.0 * bk.y, w1[k].y, c1));
+                c0 = fma(bk.x, w0[k].x, fma(bk.y, w0[k].y, c0));
+                c1 = fma(bk.x, w1[k].x, fma(bk.y, w1[k].y, c1));
             }
             const double v0 = (double)v.x + c0, v1 = (double)v.y + c1;
             if (v0 >= thr || v1 >= thr) {
@@ -736,8 +737,8 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_inv_xy_argmax
             for (int k = 1; k < NLX; ++k) {
                 const double2 bk = b[k];
                 const double2 w0 = tws[(k * 2 * j) % N], w1 = tws[(k * (2 * j + 1)) % N];
-                c0 = fma(2.0 * bk.x, w0.x, fma(2.0 * bk.y, w0.y, c0));
-                c1 = fma(2.0 * bk.x, w1.x, fma(2.0 * bk.y, w1.y, c1));
+                c0 = fma(bk.x, w0.x, fma(bk.y, w0.y, c0));
+                c1 = fma(bk.x, w1.x, fma(bk.y, w1.y, c1));
             }
             const double v0 = (double)v.x + c0, v1 = (double)v.y + c1;
             if (v0 >= thr || v1 >= thr) {

@@ -70,6 +70,16 @@ def test_batch_abi_errors():
             rd.Batch([h], top_k=17)
         with pytest.raises(rd.RegError):
             rd.Batch([h, h])
+        # a live batch captured the handle's rotation set: it cannot change
+        b = rd.Batch([h], top_k=4, graph_rounds=2)
+        try:
+            with pytest.raises(rd.RegError) as e:
+                rd.register_set_rotations(h, p.so3[:8])
+            assert e.value.code == rd.REG_EBUSY
+        finally:
+            b.close()
+        rd.register_set_rotations(h, p.so3[:8])
+        assert h.n_rot == 8
     finally:
         rd.register_free(h)
 
