@@ -25,7 +25,10 @@ Readings taken (listed in the design notes):
     FP64 6x6 solve in place of L-BFGS-B; curvature sum_i max(0, -s'') g g^T.
     Like L-BFGS-B it keeps an active set: a coordinate at its bound whose
     gradient points out of the box is held there and the step solves for the
-    others (a clamped full step stalls along the box faces).
+    others (a clamped full step stalls along the box faces);
+  * refine_lbfgsb is the paper's L-BFGS-B on the same J and gradient (SciPy's
+    implementation as the optimiser primitive), the reference of the device's
+    L-BFGS-B solver.
 """
 from __future__ import annotations
 
@@ -283,3 +286,26 @@ def refine(pb: Problem, prm: RefineParams = RefineParams()) -> RefineResult:
         J, g, H = evaluate(xi, pb, prm)
     R, p = pose_of(xi, pb.R0, pb.p0, pb.a)
     return RefineResult(R=R, p=p, J=J, iters=it, xi=xi)
+
+
+def refine_lbfgsb(pb: Problem, prm: RefineParams = RefineParams(), memory: int = 10, gtol: float = 1e-9,
+                  ftol: float = 1e-15) -> RefineResult:
+    """The paper's solver (Sec. V-C): L-BFGS-B on J(xi) over the box from
+    xi = 0 with the analytic gradient, stopped when the projected gradient
+    (gtol) or the relative reduction of J (ftol) falls below its threshold.
+    SciPy's L-BFGS-B is the optimiser primitive; J and grad J are this
+    module's."""
+    from scipy.optimize import minimize
+
+    bounds = [(-prm.b_t, prm.b_t)] * 3 + [(-prm.b_r, prm.b_r)] * 3
+
+    def fun(xi):
+        J, g, _ = evaluate(np.asarray(xi, dtype=np.float64), pb, prm)
+        return J, g
+
+    res = minimize(fun, np.zeros(6), jac=True, method="L-BFGS-B", bounds=bounds,
+                   options=dict(maxcor=memory, gtol=gtol, ftol=ftol, maxiter=prm.max_iters, maxfun=20 * prm.max_iters))
+    xi = np.asarray(res.x, dtype=np.float64)
+    R, p = pose_of(xi, pb.R0, pb.p0, pb.a)
+    return RefineResult(R=R, p=p, J=float(res.fun), iters=int(res.nit), xi=xi)
+

@@ -266,3 +266,22 @@ def test_active_bounds_rule():
     # at +b with descent pushing up (g < 0), at -b pushing down (g > 0): held;
     # interior, or gradient pointing back inside, or zero: free
     assert Rf.active_bounds(xi, g, prm).tolist() == [True, True, False, False, False, False]
+
+
+def test_lbfgsb_reaches_the_known_pose_and_the_gauss_newton_minimum(small_problem):
+    """The paper's L-BFGS-B on the same objective: the noise-free truth is
+    recovered (as by the Gauss-Newton iteration), the two solvers end at the
+    same minimum, and the solution satisfies the box KKT conditions."""
+    p, pb, Rg = small_problem
+    lb = Rf.refine_lbfgsb(pb)
+    gn = Rf.refine(pb)
+    a = pb.a
+    ce = np.linalg.norm((lb.R @ a + lb.p) - (Rg @ a + p.t_gt))
+    re = np.degrees(Rotation.from_matrix(lb.R.T @ Rg).magnitude())
+    assert ce < 1e-4 and re < 1e-3
+    assert np.linalg.norm((lb.R @ a + lb.p) - (gn.R @ a + gn.p)) < 1e-4
+    assert lb.J == pytest.approx(gn.J, abs=1e-6)
+    prm = Rf.RefineParams()
+    _, g, _ = Rf.evaluate(lb.xi, pb, prm)
+    pg = lb.xi - Rf.project_box(lb.xi - g, prm)
+    assert np.abs(pg).max() < 1e-5
