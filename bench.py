@@ -252,6 +252,44 @@ def local_search_bench(rd, torch, p, args):
         rd.register_free(h)
 
 
+def solver_bench(rd, torch, p, dev_args, starts, reps: int = 3):
+    """The refinement of the step's 16 starts by both solvers on one handle:
+    time per call (after one untimed call each) and how far apart the refined
+    poses are (anchor displacement, rotation angle)."""
+    import numpy as np
+    from scipy.spatial.transform import Rotation
+
+    h = rd.register_init(*dev_args, p.n, p.h, p.center, p.radius, p.length)
+    try:
+        res, ms, stats = {}, {}, {}
+        for solver in ("gn", "lbfgsb"):
+            rd.refine_se3(h, starts, solver=solver)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                r = rd.refine_se3(h, starts, solver=solver)
+            torch.cuda.synchronize()
+            ms[solver] = (time.perf_counter() - t0) / reps * 1e3
+            res[solver] = [x.cpu().numpy() for x in r]
+            stats[solver] = rd.register_refine_stats(h)
+    finally:
+        rd.register_free(h)
+    a = p.vertices.astype(np.float64).mean(axis=0)
+    dpos, dang = [], []
+    for k in range(len(starts)):
+        Ra = Rotation.from_quat(res["gn"][0][k, [1, 2, 3, 0]]).as_matrix()
+        Rb = Rotation.from_quat(res["lbfgsb"][0][k, [1, 2, 3, 0]]).as_matrix()
+        dpos.append(float(np.linalg.norm(Ra @ a + res["gn"][0][k, 4:] - Rb @ a - res["lbfgsb"][0][k, 4:])))
+        dang.append(float(np.degrees(Rotation.from_matrix(Ra.T @ Rb).magnitude())))
+    same = [i for i in range(len(starts)) if dpos[i] <= 1e-3 and dang[i] <= 1e-3]
+    return {"starts": len(starts), "ms_per_call": ms,
+            "rounds": {k: v["rounds"] for k, v in stats.items()},
+            "accepted_steps": {k: [int(x) for x in v[2]] for k, v in res.items()},
+            "best_J": {k: float(np.min(v[1])) for k, v in res.items()},
+            "same_minimum_within_1e-3": len(same),
+            "pose_gap_max": {"mm": max(dpos), "deg": max(dang)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,6 +304,7 @@ def main():
     ap.add_argument("--serve-sustained", type=float, default=6.0,
                     help="a second arrival rate below the serial path's capacity (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--solvers", type=int, default=1, help="compare Gauss-Newton and L-BFGS-B refinement (0: skip)")
     ap.add_argument("--local", type=int, default=5000, help="GeoBall-SF samples of the local search (0: skip)")
     ap.add_argument("--local-theta", type=float, default=5.0, help="geodesic ball radius (deg)")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -387,6 +426,10 @@ def main():
     if args.local > 0:
         out["local_search"] = local_search_bench(rd, torch, p, args)
         print("bench: local search done", file=sys.stderr, flush=True)
+    if args.solvers:
+        out["refine_solvers"] = solver_bench(rd, torch, p, (V, F, T, P, Q),
+                                             torch.from_numpy(info["starts"]).to("cuda"))
+        print("bench: solver comparison done", file=sys.stderr, flush=True)
     if args.batch > 0:
         out["batch"] = batch_bench(rd, torch, work["batch"], args)
         print("bench: uneven batch done", file=sys.stderr, flush=True)

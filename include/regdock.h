@@ -248,6 +248,16 @@ int register_set_grids(reg_handle* h, const float* O, const uint8_t* Sw);
 int refine_se3(reg_handle* h, const double* init_poses, int32_t K, double* out_poses, double* out_J,
                int32_t* out_iters);
 
+/* The same refinement with the paper's solver, L-BFGS-B (Sec. V-C), on the
+ * same objective, gradient and box: generalised Cauchy point and subspace step
+ * on the limited-memory matrix of the last 10 correction pairs, backtracking
+ * line search with sufficient decrease.  Stops on a projected gradient below
+ * 1e-6, a relative decrease of J below 1e-10, max_iters steps, or no decrease
+ * found even along the projected steepest descent.  out_iters: accepted steps.
+ * Arguments, ownership and errors as refine_se3. */
+int refine_se3_lbfgsb(reg_handle* h, const double* init_poses, int32_t K, double* out_poses, double* out_J,
+                      int32_t* out_iters);
+
 /* Work of the last refine_se3 call on the handle: evaluation rounds launched
  * (all unfinished starts are evaluated together in a round) and evaluations
  * made (one per unfinished start per round: a trial step, or the start

@@ -29,7 +29,8 @@ EXPORTS = ["register_init", "score_rotations", "register_top_k", "register_free"
            "register_server_destroy", "register_submit", "register_poll", "register_wait", "register_server_stats",
            "register_server_last_error", "register_batch_create", "register_batch_run", "register_batch_outputs",
            "register_batch_free", "register_autotune", "register_tuned_batch", "register_cached_bytes",
-           "register_release_cached", "so3_super_fibonacci", "so3_geoball_sf", "register_set_rotations"]
+           "register_release_cached", "so3_super_fibonacci", "so3_geoball_sf", "register_set_rotations",
+           "refine_se3_lbfgsb"]
 
 
 class RegError(RuntimeError):
@@ -141,6 +142,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.register_get_timing.argtypes = [p, p, p, p]
     L.refine_se3.restype = ctypes.c_int
     L.refine_se3.argtypes = [p, p, i32, p, p, p]
+    L.refine_se3_lbfgsb.restype = ctypes.c_int
+    L.refine_se3_lbfgsb.argtypes = [p, p, i32, p, p, p]
     L.register_debug_distance.restype = ctypes.c_int
     L.register_debug_distance.argtypes = [p, p, p, p]
     L.register_refine_stats.restype = ctypes.c_int
@@ -331,15 +334,20 @@ def register_search_stats(h: Handle) -> dict:
                 rescored=v[4].value)
 
 
-def refine_se3(h: Handle, init_poses):
-    """(poses f64 [K,7], J f64 [K], iters i32 [K]) on the device from K x 7 starts."""
+def refine_se3(h: Handle, init_poses, solver: str = "gn"):
+    """(poses f64 [K,7], J f64 [K], iters i32 [K]) on the device from K x 7 starts.
+    solver: "gn" (damped Gauss-Newton) or "lbfgsb" (L-BFGS-B)."""
     torch = _torch()
+    if solver not in ("gn", "lbfgsb"):
+        raise ValueError(f"unknown solver {solver!r}")
     ip = _dev(init_poses, torch.float64)
     K = ip.shape[0]
     out = torch.empty((K, 7), dtype=torch.float64, device="cuda")
     J = torch.empty(K, dtype=torch.float64, device="cuda")
     it = torch.empty(K, dtype=torch.int32, device="cuda")
-    _check(load_library().refine_se3(h.ptr, _ptr(ip), K, _ptr(out), _ptr(J), _ptr(it)))
+    L = load_library()
+    fn = L.refine_se3 if solver == "gn" else L.refine_se3_lbfgsb
+    _check(fn(h.ptr, _ptr(ip), K, _ptr(out), _ptr(J), _ptr(it)))
     return out, J, it
 
 

@@ -248,6 +248,8 @@ struct reg_handle {
     RefineState* rst = nullptr;
     RefineTrial* rtr = nullptr;
     RefineEval* rev = nullptr;
+    LbfgsState* rlb = nullptr;  // L-BFGS-B state per start
+    bool r_lbfgsb = false;      // the solver of the refinement in progress
     RefineHit* rhits = nullptr;
     RefineScratch rw{};
     int r_cap = 0;
@@ -584,6 +586,7 @@ static int ensure_refine_buffers(reg_handle* h, int K) {
         ALLOC_TRY(h, h->rst, (size_t)cap);
         ALLOC_TRY(h, h->rtr, (size_t)cap * REF_TMAX);
         ALLOC_TRY(h, h->rev, (size_t)cap * REF_TMAX * REF_EVAL_PARTS);
+        ALLOC_TRY(h, h->rlb, (size_t)cap);
         ALLOC_TRY(h, h->rhits, (size_t)cap * REF_TMAX * h->n_poses);
         // pairs: 16 per query on average (about 3 are needed); a query whose
         // pairs do not fit is searched by itself
@@ -801,13 +804,19 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
 static int refine_continue(reg_handle* h, int K, double* out_poses, double* out_J, int32_t* out_iters) {
     const RefineConst c = refine_const(h);
     hipStream_t s = h->stream;
-    const long max_rounds = 1 + (long)(c.max_iters + 1) * 52;
+    // Gauss-Newton: at most 51 rejections in a row; L-BFGS-B: at most 9
+    // backtracking rounds per iteration and one restart from steepest descent
+    const long max_rounds = 1 + (long)(c.max_iters + 1) * (h->r_lbfgsb ? 20 : 52);
     DEV_TRY(h, hipMemcpyAsync(h->r_active_host, h->r_active, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     DEV_TRY(h, hipStreamSynchronize(s));
     long round = h->r_rounds;
     while (h->r_active_host[0] > 0 && round < max_rounds) {
-        DEV_TRY(h, refine_round(h->rst, h->rtr, K, h->obj->geo, h->poses, h->n_poses, c, h->rw, h->rhits, h->rev,
-                                h->r_active, s));
+        if (h->r_lbfgsb)
+            DEV_TRY(h, refine_round_lbfgsb(h->rst, h->rlb, h->rtr, K, h->obj->geo, h->poses, h->n_poses, c, h->rw,
+                                           h->rhits, h->rev, h->r_active, s));
+        else
+            DEV_TRY(h, refine_round(h->rst, h->rtr, K, h->obj->geo, h->poses, h->n_poses, c, h->rw, h->rhits, h->rev,
+                                    h->r_active, s));
         ++round;
         if (round % 4 == 0 || round == max_rounds) {
             DEV_TRY(h, hipMemcpyAsync(h->r_active_host, h->r_active, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1191,8 +1200,8 @@ int register_set_grids(reg_handle* h, const float* O, const uint8_t* Sw) {
     return REG_OK;
 }
 
-int refine_se3(reg_handle* h, const double* init_poses, int32_t K, double* out_poses, double* out_J,
-               int32_t* out_iters) {
+static int refine_impl(reg_handle* h, const double* init_poses, int32_t K, double* out_poses, double* out_J,
+                       int32_t* out_iters, bool lbfgsb) {
     g_err.clear();
     if (!h) return fail(REG_EINVAL, "NULL handle");
     if (h->poisoned) return fail(REG_EDEVICE, "handle poisoned by an earlier device error");
@@ -1211,7 +1220,20 @@ int refine_se3(reg_handle* h, const double* init_poses, int32_t K, double* out_p
     if (rc) return rc;
     DEV_TRY(h, refine_start(init_poses, K, h->anchor, refine_const(h), h->rst, h->rtr, h->r_active, h->rw, h->stream));
     h->r_rounds = 0;
-    return refine_continue(h, K, out_poses, out_J, out_iters);
+    h->r_lbfgsb = lbfgsb;
+    const int rc2 = refine_continue(h, K, out_poses, out_J, out_iters);
+    h->r_lbfgsb = false;
+    return rc2;
+}
+
+int refine_se3(reg_handle* h, const double* init_poses, int32_t K, double* out_poses, double* out_J,
+               int32_t* out_iters) {
+    return refine_impl(h, init_poses, K, out_poses, out_J, out_iters, false);
+}
+
+int refine_se3_lbfgsb(reg_handle* h, const double* init_poses, int32_t K, double* out_poses, double* out_J,
+                      int32_t* out_iters) {
+    return refine_impl(h, init_poses, K, out_poses, out_J, out_iters, true);
 }
 
 int register_refine_stats(reg_handle* h, int64_t* rounds, int64_t* evaluations) {
@@ -1392,7 +1414,8 @@ Footprint footprint(int n, int n_rot, int n_poses, int nv, int nf, int batch, in
     const size_t K = (size_t)std::max(refine_starts, 1), nq = K * REF_TMAX * N;
     f.request = H * B * 8 + B * n * KTOP * 8 + B * n * 8 + B * n * NLOW2 * 16 + B * NLOW3 * 16 + M * per_rot +
                 M * (4 + 56) + 28 * N + 48 * N + m * m * m + mp * mp * mp + 8 * n3 + n * n * ((n + 31) / 32) * 4 +
-                K * (sizeof(RefineState) + REF_TMAX * (sizeof(RefineTrial) + REF_EVAL_PARTS * sizeof(RefineEval))) +
+                K * (sizeof(RefineState) + sizeof(LbfgsState) +
+                     REF_TMAX * (sizeof(RefineTrial) + REF_EVAL_PARTS * sizeof(RefineEval))) +
                 nq * (sizeof(RefineHit) + 48 + 8 + 4 + 8 + 16 * (8 + 16 + 4)) + 4096;
     return f;
 }

@@ -69,6 +69,18 @@ struct RefineState {
 // rejected step does not cost a round of its own.
 constexpr int REF_TMAX = 4;
 
+// L-BFGS-B per start (the paper's solver, Sec. V-C): the last LBFGS_M
+// correction pairs, the search direction of the current iteration and the
+// step lengths of its line-search trials.
+constexpr int LBFGS_M = 10;
+struct LbfgsState {
+    double S[LBFGS_M][6], Y[LBFGS_M][6];
+    double p[6];    // direction x_bar - x (x_bar from the Cauchy point and the subspace step)
+    double gp;      // g . p
+    double lam0;    // largest step length of the trials in flight (trial j: lam0 / 2^j)
+    double fprev;   // J before the last accepted step
+    int npairs, head, nback, pad;
+};
 // One trial point of a start, FP64: twist, step, damping, pose and Jacobians.
 struct RefineTrial {
     double xe[6], step[6], mu;
@@ -99,6 +111,11 @@ hipError_t refine_start(const double* init_poses, int K, const double* anchor, c
 hipError_t refine_round(RefineState* st, RefineTrial* tr, int K, const RefineGeometry& geo, const float* poses,
                         int n_poses, const RefineConst& c, const RefineScratch& w, RefineHit* hits, RefineEval* ev,
                         int* counters, hipStream_t s);
+// one round of the L-BFGS-B iteration: the queries and evaluations of the
+// trials in flight, then the line-search decision and the next direction
+hipError_t refine_round_lbfgsb(RefineState* st, LbfgsState* lb, RefineTrial* tr, int K, const RefineGeometry& geo,
+                               const float* poses, int n_poses, const RefineConst& c, const RefineScratch& w,
+                               RefineHit* hits, RefineEval* ev, int* counters, hipStream_t s);
 hipError_t refine_finish(const RefineState* st, int K, double* out_poses, double* out_J, int32_t* out_iters,
                          hipStream_t s);
 // Distance queries of all poses at the object pose of trial slot 0 (R, p set, valid).

@@ -1151,6 +1151,35 @@ __global__ __launch_bounds__(RED_T) void k_ref_eval(const RefineTrial* __restric
     if (part == 0 && threadIdx.x == 0) atomicAdd(&counters[1], 1);
 }
 
+// The evaluations of start k's trials: their partial sums in part order, plus
+// lambda |xi|^2 and its derivatives (all threads of the block take part).
+__device__ void gather_trial_evals(const RefineTrial* __restrict__ tr, const RefineEval* __restrict__ ev, int k,
+                                   const RefineConst& c, RefineEval* Es) {
+    for (int t = threadIdx.x; t < REF_TMAX * NACC; t += blockDim.x) {
+        const int j = t / NACC, a = t % NACC;
+        const RefineTrial& T = tr[k * REF_TMAX + j];
+        if (!T.valid) continue;
+        double v = 0.0;
+        for (int p = 0; p < REF_EVAL_PARTS; ++p)
+            v += reinterpret_cast<const double*>(&ev[(k * REF_TMAX + j) * REF_EVAL_PARTS + p])[a];
+        if (a == 0) {
+            double xx = 0.0;
+            for (int q = 0; q < 6; ++q) xx += T.xe[q] * T.xe[q];
+            v += c.lambda * xx;
+        } else if (a < 7) {
+            v += 2 * c.lambda * T.xe[a - 1];
+        } else {
+            int o = a - 7, r = 0;  // upper-triangle index o -> row r, diagonal when o hits its start
+            while (o >= 6 - r) {
+                o -= 6 - r;
+                ++r;
+            }
+            if (o == 0) v += 2 * c.lambda;
+        }
+        reinterpret_cast<double*>(&Es[j])[a] = v;
+    }
+}
+
 // Trial step with damping mu from (xi, g, H): a coordinate at its bound whose
 // gradient points out of the box is held there (its row and column replaced
 // by the identity, its right-hand side zero); false if the system is not
@@ -1193,32 +1222,8 @@ __global__ void k_ref_decide(RefineState* __restrict__ st, RefineTrial* __restri
     RefineState& S = st[k];
     if (S.status == 2) return;
     __shared__ int ntrial;
-    // the trials' evaluations: partial sums in part order, plus lambda |xi|^2
-    // and its derivatives
     __shared__ RefineEval Es[REF_TMAX];
-    for (int t = threadIdx.x; t < REF_TMAX * NACC; t += blockDim.x) {
-        const int j = t / NACC, a = t % NACC;
-        const RefineTrial& T = tr[k * REF_TMAX + j];
-        if (!T.valid) continue;
-        double v = 0.0;
-        for (int p = 0; p < REF_EVAL_PARTS; ++p)
-            v += reinterpret_cast<const double*>(&ev[(k * REF_TMAX + j) * REF_EVAL_PARTS + p])[a];
-        if (a == 0) {
-            double xx = 0.0;
-            for (int q = 0; q < 6; ++q) xx += T.xe[q] * T.xe[q];
-            v += c.lambda * xx;
-        } else if (a < 7) {
-            v += 2 * c.lambda * T.xe[a - 1];
-        } else {
-            int o = a - 7, r = 0;  // upper-triangle index o -> row r, diagonal when o hits its start
-            while (o >= 6 - r) {
-                o -= 6 - r;
-                ++r;
-            }
-            if (o == 0) v += 2 * c.lambda;
-        }
-        reinterpret_cast<double*>(&Es[j])[a] = v;
-    }
+    gather_trial_evals(tr, ev, k, c, Es);
     __syncthreads();
     if (threadIdx.x == 0) {
         int next = 0;
@@ -1292,6 +1297,248 @@ __global__ void k_ref_decide(RefineState* __restrict__ st, RefineTrial* __restri
     }
 }
 
+// ------------------------------------------------- L-BFGS-B (Sec. V-C)
+//
+// The paper's solver on the same objective and gradient.  With six variables
+// the limited-memory matrix is formed explicitly: B = theta I updated by the
+// BFGS formula with the stored pairs, oldest first (theta = y'y / s'y of the
+// newest pair).  An iteration takes the generalised Cauchy point of the
+// quadratic model along the projected-gradient path x(t) = P(x - t g), then
+// minimises the model over the variables still free there (Cholesky of their
+// block of B) and truncates that step to the box; the direction is
+// p = x_bar - x.  The line search backtracks from step 1 (1/|p| at the first
+// iteration) by halving, four step lengths per round, and takes the first
+// that meets the sufficient decrease J <= J0 + 1e-4 lam g.p; a pair enters the
+// memory when s'y > eps y'y.  The iteration stops on a projected gradient
+// below tol_pg, a relative decrease of J below 1e-10, max_iters steps, or a
+// line search that finds no decrease even from steepest descent.
+
+__device__ __forceinline__ double dot6(const double* a, const double* b) {
+    double t = 0.0;
+    for (int j = 0; j < 6; ++j) t += a[j] * b[j];
+    return t;
+}
+
+__device__ __forceinline__ void matvec6(const double* A, const double* v, double* o) {
+    for (int i = 0; i < 6; ++i) o[i] = dot6(A + 6 * i, v);
+}
+
+__device__ double projected_gradient(const RefineState& S, const RefineConst& c) {
+    double pg = 0;
+    for (int j = 0; j < 6; ++j) {
+        const double b = j < 3 ? c.b_t : c.b_r;
+        pg = fmax(pg, fabs(S.xi[j] - clampd(S.xi[j] - S.g[j], b)));
+    }
+    return pg;
+}
+
+__device__ void lbfgsb_direction(const RefineState& S, LbfgsState& L, const RefineConst& c) {
+    const double* x = S.xi;
+    const double* g = S.g;
+    double lo[6], hi[6];
+    for (int j = 0; j < 6; ++j) {
+        hi[j] = j < 3 ? c.b_t : c.b_r;
+        lo[j] = -hi[j];
+    }
+    // the limited-memory matrix
+    double B[36];
+    double theta = 1.0;
+    if (L.npairs > 0) {
+        const int nw = (L.head + LBFGS_M - 1) % LBFGS_M;
+        theta = dot6(L.Y[nw], L.Y[nw]) / dot6(L.S[nw], L.Y[nw]);
+    }
+    for (int i = 0; i < 36; ++i) B[i] = (i % 7 == 0) ? theta : 0.0;
+    for (int q = 0; q < L.npairs; ++q) {
+        const int idx = (L.head - L.npairs + q + 2 * LBFGS_M) % LBFGS_M;
+        const double* sv = L.S[idx];
+        const double* yv = L.Y[idx];
+        double Bs[6];
+        matvec6(B, sv, Bs);
+        const double sBs = dot6(sv, Bs), ys = dot6(yv, sv);
+        if (!(sBs > 0.0 && ys > 0.0)) continue;
+        for (int i = 0; i < 6; ++i)
+            for (int j = 0; j < 6; ++j) B[6 * i + j] += yv[i] * yv[j] / ys - Bs[i] * Bs[j] / sBs;
+    }
+    // generalised Cauchy point: breakpoints of the projected path in order
+    double tb[6], d[6], z[6];
+    int ord[6];
+    for (int i = 0; i < 6; ++i) {
+        tb[i] = g[i] < 0.0 ? (x[i] - hi[i]) / g[i] : g[i] > 0.0 ? (x[i] - lo[i]) / g[i] : INFINITY;
+        d[i] = tb[i] > 0.0 ? -g[i] : 0.0;
+        z[i] = 0.0;
+        ord[i] = i;
+    }
+    for (int i = 1; i < 6; ++i)
+        for (int j = i; j > 0 && tb[ord[j]] < tb[ord[j - 1]]; --j) {
+            const int t = ord[j];
+            ord[j] = ord[j - 1];
+            ord[j - 1] = t;
+        }
+    double tprev = 0.0;
+    for (int q = 0; q <= 6; ++q) {
+        if (q < 6 && d[ord[q]] == 0.0) continue;  // at its bound from the start (or g = 0)
+        double Bz[6], Bd[6];
+        matvec6(B, z, Bz);
+        matvec6(B, d, Bd);
+        const double fp = dot6(g, d) + dot6(d, Bz), fpp = dot6(d, Bd);
+        if (!(fp < 0.0)) break;  // the model no longer decreases along the path
+        const double tnext = q < 6 ? tb[ord[q]] : INFINITY;
+        const double dtmin = fpp > 0.0 ? -fp / fpp : INFINITY;
+        if (dtmin < tnext - tprev) {
+            for (int i = 0; i < 6; ++i) z[i] += dtmin * d[i];
+            break;
+        }
+        if (!(tnext < INFINITY)) break;
+        for (int i = 0; i < 6; ++i) z[i] += (tnext - tprev) * d[i];
+        const int b = ord[q];
+        z[b] = (d[b] > 0.0 ? hi[b] : lo[b]) - x[b];
+        d[b] = 0.0;
+        tprev = tnext;
+    }
+    // subspace step on the variables free at the Cauchy point
+    double xc[6], r[6], A[36], rhs[6], du[6];
+    bool fr[6];
+    for (int i = 0; i < 6; ++i) {
+        xc[i] = fmin(hi[i], fmax(lo[i], x[i] + z[i]));
+        fr[i] = xc[i] > lo[i] && xc[i] < hi[i];
+        z[i] = xc[i] - x[i];
+    }
+    matvec6(B, z, r);
+    for (int i = 0; i < 6; ++i) {
+        r[i] += g[i];
+        rhs[i] = fr[i] ? -r[i] : 0.0;
+        for (int j = 0; j < 6; ++j) A[6 * i + j] = (fr[i] && fr[j]) ? B[6 * i + j] : (i == j ? 1.0 : 0.0);
+    }
+    double xbar[6];
+    for (int i = 0; i < 6; ++i) xbar[i] = xc[i];
+    if (chol6(A, rhs, du)) {
+        double alpha = 1.0;
+        for (int i = 0; i < 6; ++i) {
+            if (!fr[i]) continue;
+            if (du[i] > 0.0) alpha = fmin(alpha, (hi[i] - xc[i]) / du[i]);
+            else if (du[i] < 0.0) alpha = fmin(alpha, (lo[i] - xc[i]) / du[i]);
+        }
+        for (int i = 0; i < 6; ++i)
+            if (fr[i]) xbar[i] = xc[i] + alpha * du[i];
+    }
+    for (int i = 0; i < 6; ++i) L.p[i] = xbar[i] - x[i];
+    L.gp = dot6(g, L.p);
+    if (!(L.gp < 0.0)) {
+        // not a descent direction: drop the memory, projected steepest descent
+        L.npairs = 0;
+        for (int i = 0; i < 6; ++i) L.p[i] = fmin(hi[i], fmax(lo[i], x[i] - g[i])) - x[i];
+        L.gp = dot6(g, L.p);
+    }
+}
+
+__global__ void k_ref_decide_lbfgsb(RefineState* __restrict__ st, LbfgsState* __restrict__ lb,
+                                    RefineTrial* __restrict__ tr, const RefineEval* __restrict__ ev, RefineConst c,
+                                    int* __restrict__ pair_count, int* __restrict__ counters) {
+    const int k = blockIdx.x;
+    if (k == 0) clear_pair_counters(pair_count, threadIdx.x);  // for the next round's queries
+    RefineState& S = st[k];
+    if (S.status == 2) return;
+    __shared__ RefineEval Es[REF_TMAX];
+    __shared__ int ntrial;
+    gather_trial_evals(tr, ev, k, c, Es);
+    __syncthreads();
+    LbfgsState& L = lb[k];
+    if (threadIdx.x == 0) {
+        constexpr double C1 = 1e-4, FTOL = 1e-10;
+        bool stop = false;
+        if (S.status == 0) {
+            // the start's evaluation at xi = 0
+            S.J = Es[0].J;
+            for (int j = 0; j < 6; ++j) S.g[j] = Es[0].g[j];
+            S.it = 0;
+            L.npairs = 0;
+            L.head = 0;
+            L.nback = 0;
+            L.fprev = INFINITY;
+            if (projected_gradient(S, c) <= c.tol_pg) {
+                stop = true;
+            } else {
+                lbfgsb_direction(S, L, c);
+                L.lam0 = fmin(1.0, 1.0 / sqrt(dot6(L.p, L.p)));
+            }
+        } else {
+            int taken = -1;
+            for (int j = 0; j < REF_TMAX; ++j) {
+                const RefineTrial& T = tr[k * REF_TMAX + j];
+                if (!T.valid) break;
+                if (Es[j].J <= S.J + C1 * T.mu * L.gp) {
+                    taken = j;
+                    break;
+                }
+            }
+            if (taken >= 0) {
+                const RefineTrial& T = tr[k * REF_TMAX + taken];
+                double sv[6], yv[6];
+                for (int j = 0; j < 6; ++j) {
+                    sv[j] = T.xe[j] - S.xi[j];
+                    yv[j] = Es[taken].g[j] - S.g[j];
+                }
+                if (dot6(sv, yv) > 2.220446049250313e-16 * dot6(yv, yv)) {
+                    for (int j = 0; j < 6; ++j) {
+                        L.S[L.head][j] = sv[j];
+                        L.Y[L.head][j] = yv[j];
+                    }
+                    L.head = (L.head + 1) % LBFGS_M;
+                    L.npairs = min(L.npairs + 1, LBFGS_M);
+                }
+                L.fprev = S.J;
+                S.J = Es[taken].J;
+                for (int j = 0; j < 6; ++j) {
+                    S.xi[j] = T.xe[j];
+                    S.g[j] = Es[taken].g[j];
+                }
+                S.it += 1;
+                L.nback = 0;
+                if (projected_gradient(S, c) <= c.tol_pg ||
+                    L.fprev - S.J <= FTOL * fmax(fmax(fabs(L.fprev), fabs(S.J)), 1.0) || S.it >= c.max_iters) {
+                    stop = true;
+                } else {
+                    lbfgsb_direction(S, L, c);
+                    L.lam0 = 1.0;
+                }
+            } else {
+                L.lam0 *= 1.0 / 16.0;  // the four trials of the next round continue the halving
+                L.nback += 1;
+                if (L.nback > 8) {
+                    if (L.npairs > 0) {
+                        L.npairs = 0;
+                        lbfgsb_direction(S, L, c);
+                        L.lam0 = fmin(1.0, 1.0 / sqrt(dot6(L.p, L.p)));
+                        L.nback = 0;
+                    } else {
+                        stop = true;
+                    }
+                }
+            }
+        }
+        S.status = stop ? 2 : 1;
+        ntrial = stop ? 0 : REF_TMAX;
+        if (!stop) atomicAdd(&counters[0], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < REF_TMAX) {
+        RefineTrial& T = tr[k * REF_TMAX + threadIdx.x];
+        T.valid = 0;
+        if ((int)threadIdx.x < ntrial) {
+            double lam = L.lam0;
+            for (unsigned j = 0; j < threadIdx.x; ++j) lam *= 0.5;
+            for (int j = 0; j < 6; ++j) {
+                const double b = j < 3 ? c.b_t : c.b_r;
+                T.xe[j] = clampd(S.xi[j] + lam * L.p[j], b);
+                T.step[j] = T.xe[j] - S.xi[j];
+            }
+            T.mu = lam;
+            pose_at(S, T.xe, T);
+            T.valid = 1;
+        }
+    }
+}
+
 __global__ void k_ref_finish(const RefineState* __restrict__ st, int K, double* __restrict__ out_poses,
                              double* __restrict__ out_J, int32_t* __restrict__ out_iters) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1354,6 +1601,16 @@ hipError_t refine_round(RefineState* st, RefineTrial* tr, int K, const RefineGeo
     launch_queries(tr, slots, geo, poses, n_poses, c, w, hits, counters, s);
     k_ref_eval<<<slots * REF_EVAL_PARTS, RED_T, 0, s>>>(tr, hits, n_poses, c, ev, counters);
     k_ref_decide<<<K, 64, 0, s>>>(st, tr, ev, c, w.pair_count, counters);
+    return hipGetLastError();
+}
+
+hipError_t refine_round_lbfgsb(RefineState* st, LbfgsState* lb, RefineTrial* tr, int K, const RefineGeometry& geo,
+                               const float* poses, int n_poses, const RefineConst& c, const RefineScratch& w,
+                               RefineHit* hits, RefineEval* ev, int* counters, hipStream_t s) {
+    const int slots = K * REF_TMAX;
+    launch_queries(tr, slots, geo, poses, n_poses, c, w, hits, counters, s);
+    k_ref_eval<<<slots * REF_EVAL_PARTS, RED_T, 0, s>>>(tr, hits, n_poses, c, ev, counters);
+    k_ref_decide_lbfgsb<<<K, 64, 0, s>>>(st, lb, tr, ev, c, w.pair_count, counters);
     return hipGetLastError();
 }
 
