@@ -538,7 +538,7 @@ static int build_refine_geometry(reg_handle* h) {
     DEV_TRY(h, hipMemcpyAsync(d_topr, g.top_range.data(), g.top_range.size() * sizeof(int2), hipMemcpyHostToDevice, s));
     DEV_TRY(h, hipMemcpyAsync(d_slot, g.slot_of.data(), g.slot_of.size() * sizeof(int), hipMemcpyHostToDevice, s));
     DEV_TRY(h, hipStreamSynchronize(s));
-    o->geo = RefineGeometry{d_top, d_topr, d_cl, d_clr, d_face, d_slot, n_top, n_cl};
+    o->geo = RefineGeometry{d_top, d_topr, d_cl, d_clr, d_face, d_slot, n_top, n_cl, (int)g.slot_of.size()};
     o->geo_ready = true;
     return REG_OK;
 }
@@ -548,6 +548,8 @@ static RefineConst refine_const(const reg_handle* h) {
     RefineConst c{};
     c.r = (float)h->probe.radius_mm;
     c.L = (float)h->probe.length_mm;
+    c.r64 = h->probe.radius_mm;
+    c.L64 = h->probe.length_mm;
     // faces farther than tau_out2 cannot change s, s' or s''; cull at the
     // smaller of the cutoff and tau_out2
     c.cull = (float)std::min(h->prm.eps, h->prm.tau_out2);

@@ -30,6 +30,7 @@ struct RefineGeometry {
     const int* slot_of;       // original face index -> slot
     int n_top;
     int n_cluster;
+    int n_faces;              // entries of slot_of
 };
 
 // Work buffers of the distance query, per (start, probe pose) query q.
@@ -49,6 +50,7 @@ struct RefineConst {
     float r, L;               // probe radius and length (mm)
     float cull;               // cutoff margin of the node/face test (mm)
     float eps;                // d reported when no face is kept
+    double r64, L64;          // the same in FP64 (witness polish)
     double tau_out2, tau_in2, k, lambda, b_t, b_r;
     double tol_pg, tol_step, mu0;
     int max_iters;

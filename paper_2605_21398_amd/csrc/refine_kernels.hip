@@ -397,6 +397,294 @@ __device__ float3 witness_gradient(float3 u, const Tri& T, float s, float t) {
     return make_float3(g2.x + alpha * db.x, g2.y + alpha * db.y, g2.z + alpha * db.z);
 }
 
+// ------------------------------------------------------ FP64 witness polish
+//
+// The float32 searches place a smooth face minimum only to about
+// sqrt(2 e / k) (e the float32 rounding of f_p, k its curvature along the
+// face): up to ~1e-3 mm where the probe wall runs close to an edge.  The
+// witness sets the contact normal and the moment arm of the sensitivities, so
+// the winning face of every query is minimised again in FP64 (face vertices
+// placed by the FP64 pose, as the search's float32 ones are) wherever f_p is
+// smooth around the witness:
+//  * on an edge in the wall branch (q2 <= 0 and q2 below q1 by more than
+//    RIDGE_TOL inside): f_p = rho - r and rho^2 is quadratic along the edge,
+//    its minimiser in closed form;
+//  * on an edge in the rim branch (q1, q2 > 0): Newton on q1^2 + q2^2;
+//  * on an edge where it crosses the inner side/cap ridge: rho = r + q2 with
+//    q2 linear along the edge is a quadratic equation, its root nearest the
+//    search's point (one Newton step polishes it);
+//  * inside the face with the probe strictly on one side of its plane: the
+//    projection of the probe's support point;
+//  * inside the face on the inner side/cap ridge (q1 = q2 <= 0), where a face
+//    almost parallel to the tip disk makes the minimum flat along the ridge:
+//    Newton on the optimality conditions a grad q1 + (1 - a) grad q2 = 0,
+//    q1 = q2 in the face coordinates (q2 is linear there).
+// The new point must stay on the edge or face and in the same branch, and may
+// not raise f_p; the remaining kinks (a ridge crossing an edge, the cap plane,
+// vertices) are located to the search's bracket already and keep their witness.
+__device__ __forceinline__ void sdf_q64(const double* u, double r, double L, double& rho, double& q1, double& q2) {
+    rho = sqrt(u[0] * u[0] + u[1] * u[1]);
+    q1 = rho - r;
+    q2 = fabs(u[2] - 0.5 * L) - 0.5 * L;
+}
+
+__device__ double sdf64(const double* u, double r, double L) {
+    double rho, q1, q2;
+    sdf_q64(u, r, L, rho, q1, q2);
+    const double a = fmax(q1, 0.0), b = fmax(q2, 0.0);
+    return fmin(fmax(q1, q2), 0.0) + sqrt(a * a + b * b);
+}
+
+__device__ __forceinline__ bool wall_branch(double q1, double q2) {
+    return q2 <= 0.0 && (q1 > 0.0 || q2 < q1 - (double)RIDGE_TOL);
+}
+
+// minimiser of f_p on the segment Q + l D, l in [0, 1], near l0; false: keep l0
+__device__ bool polish_edge(const double* Q, const double* D, double l0, double r, double L, double& l_out) {
+    double u[3], rho, q1, q2;
+    for (int a = 0; a < 3; ++a) u[a] = Q[a] + l0 * D[a];
+    sdf_q64(u, r, L, rho, q1, q2);
+    const double f0 = sdf64(u, r, L);
+    const bool wall = wall_branch(q1, q2), rim = q1 > 0.0 && q2 > 0.0;
+    const bool ridge = q1 <= 0.0 && q2 <= 0.0 && fabs(q1 - q2) <= (double)RIDGE_TOL;
+    const double sz = u[2] >= 0.5 * L ? 1.0 : -1.0;
+    double l;
+    if (ridge) {
+        // (Qx + l Dx)^2 + (Qy + l Dy)^2 = (r + b0 + b1 l)^2, q2 = b0 + b1 l
+        const double b1 = sz * D[2], g0 = r + sz * (Q[2] - 0.5 * L) - 0.5 * L;
+        const double qa = D[0] * D[0] + D[1] * D[1] - b1 * b1;
+        const double qb = Q[0] * D[0] + Q[1] * D[1] - g0 * b1;
+        const double qc = Q[0] * Q[0] + Q[1] * Q[1] - g0 * g0;
+        const double disc = qb * qb - qa * qc;
+        if (!(disc >= 0.0)) return false;
+        const double qq = -(qb + copysign(sqrt(disc), qb));
+        const double la = qa != 0.0 ? qq / qa : INFINITY, lb = qq != 0.0 ? qc / qq : INFINITY;
+        l = fabs(la - l0) <= fabs(lb - l0) ? la : lb;
+        if (!(fabs(l - l0) <= 1e-2)) return false;
+        // one Newton step on rho - r - q2
+        const double ux = Q[0] + l * D[0], uy = Q[1] + l * D[1], rh = sqrt(ux * ux + uy * uy);
+        if (!(rh > 0.0)) return false;
+        const double phi = rh - r - (g0 - r + b1 * l), dphi = (ux * D[0] + uy * D[1]) / rh - b1;
+        if (dphi != 0.0) l -= phi / dphi;
+    } else if (wall) {
+        const double dd = D[0] * D[0] + D[1] * D[1];
+        if (!(dd > 0.0)) return false;  // edge along the axis: rho constant on it
+        l = -(Q[0] * D[0] + Q[1] * D[1]) / dd;
+    } else if (rim) {
+        l = l0;
+        for (int it = 0; it < 4; ++it) {
+            for (int a = 0; a < 3; ++a) u[a] = Q[a] + l * D[a];
+            rho = sqrt(u[0] * u[0] + u[1] * u[1]);
+            if (!(rho > 0.0)) return false;
+            const double rp = (u[0] * D[0] + u[1] * D[1]) / rho;
+            const double rpp = (D[0] * D[0] + D[1] * D[1] - rp * rp) / rho;
+            const double a1 = rho - r, a2 = sz * (u[2] - 0.5 * L) - 0.5 * L;
+            const double g1 = a1 * rp + a2 * sz * D[2], g2 = rp * rp + a1 * rpp + D[2] * D[2];
+            if (!(g2 > 0.0)) return false;
+            l -= g1 / g2;
+        }
+    } else {
+        return false;
+    }
+    if (!(l >= 0.0 && l <= 1.0)) return false;
+    for (int a = 0; a < 3; ++a) u[a] = Q[a] + l * D[a];
+    sdf_q64(u, r, L, rho, q1, q2);
+    const double sz1 = u[2] >= 0.5 * L ? 1.0 : -1.0;
+    if (ridge ? !(q1 <= 0.0 && q2 <= 0.0 && fabs(q1 - q2) <= 1e-9 && sz1 == sz)
+              : wall ? !wall_branch(q1, q2) : !(q1 > 0.0 && q2 > 0.0 && sz1 == sz))
+        return false;
+    if (!(sdf64(u, r, L) <= f0)) return false;
+    l_out = l;
+    return true;
+}
+
+// interior witness with the probe strictly on one side of the face plane
+__device__ bool polish_support(const double* P0, const double* E1, const double* E2, double s0, double t0, double r,
+                               double L, double& s_out, double& t_out) {
+    double N[3] = {E1[1] * E2[2] - E1[2] * E2[1], E1[2] * E2[0] - E1[0] * E2[2], E1[0] * E2[1] - E1[1] * E2[0]};
+    const double nn = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+    if (!(nn > 0.0)) return false;
+    for (int a = 0; a < 3; ++a) N[a] /= nn;
+    auto support = [&](double sg, double* o) {
+        const double mx = sg * N[0], my = sg * N[1], h = sqrt(mx * mx + my * my);
+        const double k = h > 0.0 ? r / h : 0.0;
+        o[0] = k * mx;
+        o[1] = k * my;
+        o[2] = sg * N[2] > 0.0 ? L : 0.0;
+    };
+    double sh[3], sl[3];
+    support(1.0, sh);
+    support(-1.0, sl);
+    double top = 0.0, bot = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        top += N[a] * (sh[a] - P0[a]);
+        bot += N[a] * (sl[a] - P0[a]);
+    }
+    if (!(bot > 0.0 || top < 0.0)) return false;
+    const double h = bot > 0.0 ? bot : top;
+    const double* sp = bot > 0.0 ? sl : sh;
+    double x[3];
+    for (int a = 0; a < 3; ++a) x[a] = sp[a] - N[a] * h - P0[a];
+    const double a11 = E1[0] * E1[0] + E1[1] * E1[1] + E1[2] * E1[2];
+    const double a12 = E1[0] * E2[0] + E1[1] * E2[1] + E1[2] * E2[2];
+    const double a22 = E2[0] * E2[0] + E2[1] * E2[1] + E2[2] * E2[2];
+    const double b1 = x[0] * E1[0] + x[1] * E1[1] + x[2] * E1[2], b2 = x[0] * E2[0] + x[1] * E2[1] + x[2] * E2[2];
+    const double det = a11 * a22 - a12 * a12;
+    if (!(det > 0.0)) return false;
+    const double s = (b1 * a22 - b2 * a12) / det, t = (b2 * a11 - b1 * a12) / det;
+    if (!(s >= 0.0 && t >= 0.0 && s + t <= 1.0)) return false;
+    double u[3], u0[3];
+    for (int a = 0; a < 3; ++a) {
+        u[a] = P0[a] + s * E1[a] + t * E2[a];
+        u0[a] = P0[a] + s0 * E1[a] + t0 * E2[a];
+    }
+    if (!(sdf64(u, r, L) <= sdf64(u0, r, L))) return false;
+    s_out = s;
+    t_out = t;
+    return true;
+}
+
+// interior witness on the inner ridge; (s, t) and the branch weight a by Newton
+__device__ bool polish_ridge(const double* P0, const double* E1, const double* E2, double s0, double t0, double r,
+                             double L, double& s_out, double& t_out) {
+    double u0[3];
+    for (int a = 0; a < 3; ++a) u0[a] = P0[a] + s0 * E1[a] + t0 * E2[a];
+    double rho, q1, q2;
+    sdf_q64(u0, r, L, rho, q1, q2);
+    if (!(q1 <= 0.0 && q2 <= 0.0 && fabs(q1 - q2) <= (double)RIDGE_TOL && rho > 0.0)) return false;
+    const double f0 = sdf64(u0, r, L);
+    const double sz = u0[2] >= 0.5 * L ? 1.0 : -1.0;
+    const double c1 = sz * E1[2], c2 = sz * E2[2];  // grad q2 in (s, t)
+    double s = s0, t = t0, wa = -1.0;
+    for (int it = 0; it < 6; ++it) {
+        const double wx = P0[0] + s * E1[0] + t * E2[0], wy = P0[1] + s * E1[1] + t * E2[1];
+        rho = sqrt(wx * wx + wy * wy);
+        if (!(rho > 0.0)) return false;
+        const double g1 = (E1[0] * wx + E1[1] * wy) / rho, g2 = (E2[0] * wx + E2[1] * wy) / rho;  // grad q1
+        const double h11 = (E1[0] * E1[0] + E1[1] * E1[1] - g1 * g1) / rho;
+        const double h12 = (E1[0] * E2[0] + E1[1] * E2[1] - g1 * g2) / rho;
+        const double h22 = (E2[0] * E2[0] + E2[1] * E2[1] - g2 * g2) / rho;
+        const double d1 = g1 - c1, d2 = g2 - c2;
+        if (wa < 0.0) {  // the weight that best cancels the two gradients
+            const double dd = d1 * d1 + d2 * d2;
+            if (!(dd > 0.0)) return false;
+            wa = fmin(1.0, fmax(0.0, -(c1 * d1 + c2 * d2) / dd));
+        }
+        const double zq2 = sz * (P0[2] + s * E1[2] + t * E2[2] - 0.5 * L) - 0.5 * L;
+        const double F1 = c1 + wa * d1, F2 = c2 + wa * d2, F3 = (rho - r) - zq2;
+        // [[a H, d], [d^T, 0]] (ds, dt, da) = -(F1, F2, F3)
+        const double A11 = wa * h11, A12 = wa * h12, A22 = wa * h22;
+        const double det = -A11 * d2 * d2 + A12 * d1 * d2 + d1 * (A12 * d2 - A22 * d1);
+        if (!(fabs(det) > 1e-300)) return false;
+        const double b1 = -F1, b2 = -F2, b3 = -F3;
+        // Cramer's rule
+        const double ds = (-b1 * d2 * d2 + A12 * d2 * b3 + d1 * (b2 * d2 - A22 * b3)) / det;
+        const double dt = (-A11 * d2 * b3 + b1 * d1 * d2 + d1 * (A12 * b3 - b2 * d1)) / det;
+        const double da = (A11 * (A22 * b3 - b2 * d2) - A12 * (A12 * b3 - b2 * d1) + b1 * (A12 * d2 - A22 * d1)) / det;
+        s += ds;
+        t += dt;
+        wa += da;
+    }
+    if (!(wa >= 0.0 && wa <= 1.0 && s >= 0.0 && t >= 0.0 && s + t <= 1.0)) return false;
+    double u[3];
+    for (int a = 0; a < 3; ++a) u[a] = P0[a] + s * E1[a] + t * E2[a];
+    sdf_q64(u, r, L, rho, q1, q2);
+    if (!(q1 <= 0.0 && q2 <= 0.0 && fabs(q1 - q2) <= 1e-9 && (u[2] >= 0.5 * L ? 1.0 : -1.0) == sz)) return false;
+    if (!(sdf64(u, r, L) <= f0)) return false;
+    s_out = s;
+    t_out = t;
+    return true;
+}
+
+// witness_gradient in FP64: grad f_p, or on the inner ridge the branch mix
+// with no component along the face (interior witness) or the edge it is on
+__device__ void witness_gradient64(const double* u, const double* E1, const double* E2, double s, double t, double r,
+                                   double L, double* g) {
+    double rho, q1, q2;
+    sdf_q64(u, r, L, rho, q1, q2);
+    const double ex = rho > 0.0 ? u[0] / rho : 1.0, ey = rho > 0.0 ? u[1] / rho : 0.0;
+    const double sz = u[2] >= 0.5 * L ? 1.0 : -1.0;
+    if (!(q1 <= 0.0 && q2 <= 0.0)) {
+        const double a = fmax(q1, 0.0), b = fmax(q2, 0.0), n = sqrt(a * a + b * b);
+        g[0] = a * ex / n;
+        g[1] = a * ey / n;
+        g[2] = b * sz / n;
+        return;
+    }
+    g[0] = q1 >= q2 ? ex : 0.0;
+    g[1] = q1 >= q2 ? ey : 0.0;
+    g[2] = q1 >= q2 ? 0.0 : sz;
+    if (!(fabs(q1 - q2) <= (double)RIDGE_TOL && rho > 0.0)) return;
+    const bool on_s = s <= (double)EDGE_TOL, on_t = t <= (double)EDGE_TOL, on_st = 1.0 - s - t <= (double)EDGE_TOL;
+    const int active = (int)on_s + (int)on_t + (int)on_st;
+    if (active >= 2) return;
+    const double g2v[3] = {0.0, 0.0, sz}, db[3] = {ex, ey, -sz};
+    double pa[3], pb[3];
+    if (active == 0) {
+        const double N[3] = {E1[1] * E2[2] - E1[2] * E2[1], E1[2] * E2[0] - E1[0] * E2[2],
+                             E1[0] * E2[1] - E1[1] * E2[0]};
+        const double nn = N[0] * N[0] + N[1] * N[1] + N[2] * N[2];
+        if (!(nn > 0.0)) return;
+        const double ga = (g2v[0] * N[0] + g2v[1] * N[1] + g2v[2] * N[2]) / nn;
+        const double gb = (db[0] * N[0] + db[1] * N[1] + db[2] * N[2]) / nn;
+        for (int a = 0; a < 3; ++a) {
+            pa[a] = g2v[a] - ga * N[a];
+            pb[a] = db[a] - gb * N[a];
+        }
+    } else {
+        double e[3];
+        for (int a = 0; a < 3; ++a) e[a] = on_s ? E2[a] : on_t ? E1[a] : E2[a] - E1[a];
+        const double ee = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+        if (!(ee > 0.0)) return;
+        const double ga = (g2v[0] * e[0] + g2v[1] * e[1] + g2v[2] * e[2]) / ee;
+        const double gb = (db[0] * e[0] + db[1] * e[1] + db[2] * e[2]) / ee;
+        for (int a = 0; a < 3; ++a) {
+            pa[a] = ga * e[a];
+            pb[a] = gb * e[a];
+        }
+    }
+    const double bb = pb[0] * pb[0] + pb[1] * pb[1] + pb[2] * pb[2];
+    if (!(bb > 1e-24)) return;
+    const double al = fmin(1.0, fmax(0.0, -(pa[0] * pb[0] + pa[1] * pb[1] + pa[2] * pb[2]) / bb));
+    for (int a = 0; a < 3; ++a) g[a] = g2v[a] + al * db[a];
+}
+
+// The winner's witness on its face in FP64: (s, t) polished where the
+// minimum is smooth, else the search's point; u (probe frame), f_p there and
+// its gradient, evaluated in FP64 either way.  A (row-major) and c place body
+// points in the probe frame.
+__device__ void polish_witness(const double* A, const double* c, const float4& a0, const float4& a1, const float4& a2,
+                               float bs, float bt, double r, double L, double* u, double& f, double* g) {
+    const double b[3][3] = {{a0.x, a0.y, a0.z}, {a0.w, a1.x, a1.y}, {a1.z, a1.w, a2.x}};
+    double P[3][3];
+    for (int v = 0; v < 3; ++v)
+        for (int a = 0; a < 3; ++a) P[v][a] = A[3 * a] * b[v][0] + A[3 * a + 1] * b[v][1] + A[3 * a + 2] * b[v][2] + c[a];
+    double E1[3], E2[3], E12[3];
+    for (int a = 0; a < 3; ++a) {
+        E1[a] = P[1][a] - P[0][a];
+        E2[a] = P[2][a] - P[0][a];
+        E12[a] = P[2][a] - P[1][a];
+    }
+    double s = bs, t = bt, l;
+    bool ok = false;
+    if (bt == 0.0f && bs > 0.0f && bs < 1.0f) {
+        if ((ok = polish_edge(P[0], E1, bs, r, L, l))) { s = l; t = 0.0; }
+    } else if (bs == 0.0f && bt > 0.0f && bt < 1.0f) {
+        if ((ok = polish_edge(P[0], E2, bt, r, L, l))) { s = 0.0; t = l; }
+    } else if (bt > 0.0f && bt < 1.0f && fabsf(1.0f - bs - bt) <= 1e-6f) {
+        if ((ok = polish_edge(P[1], E12, bt, r, L, l))) { s = 1.0 - l; t = l; }
+    } else if (bs > 0.0f && bt > 0.0f) {
+        ok = polish_support(P[0], E1, E2, bs, bt, r, L, s, t) || polish_ridge(P[0], E1, E2, bs, bt, r, L, s, t);
+    }
+    if (!ok) {
+        s = bs;
+        t = bt;
+    }
+    for (int a = 0; a < 3; ++a) u[a] = P[0][a] + s * E1[a] + t * E2[a];
+    f = sdf64(u, r, L);
+    witness_gradient64(u, E1, E2, s, t, r, L, g);
+}
+
 // ------------------------------------------------------------------ kernels
 
 // zero the pair-queue counters; called by threads t = 0..63 of one block
@@ -1027,13 +1315,34 @@ __global__ __launch_bounds__(64) void k_ref_resolve(const RefineTrial* __restric
     }
     double Ri[9], pi[3];
     probe_frame(poses, i, Ri, pi);
-    const float3 u = make_float3(BT.p0.x + bs * BT.e1.x + bt * BT.e2.x, BT.p0.y + bs * BT.e1.y + bt * BT.e2.y,
-                                 BT.p0.z + bs * BT.e1.z + bt * BT.e2.z);
-    const float3 gl = witness_gradient(u, BT, bs, bt);
-    double xw[3], nw[3];
+    // body -> probe frame in FP64 for the polish
+    const RefineTrial& P = tr[k];
+    double A[9], cc[3];
     for (int a = 0; a < 3; ++a) {
-        xw[a] = Ri[3 * a] * u.x + Ri[3 * a + 1] * u.y + Ri[3 * a + 2] * u.z + pi[a];
-        nw[a] = Ri[3 * a] * gl.x + Ri[3 * a + 1] * gl.y + Ri[3 * a + 2] * gl.z;
+        for (int b = 0; b < 3; ++b) A[3 * a + b] = Ri[a] * P.R[b] + Ri[3 + a] * P.R[3 + b] + Ri[6 + a] * P.R[6 + b];
+        cc[a] = Ri[a] * (P.p[0] - pi[0]) + Ri[3 + a] * (P.p[1] - pi[1]) + Ri[6 + a] * (P.p[2] - pi[2]);
+    }
+    double u64[3], f64;
+    double xw[3], nw[3];
+    const bool found = bidx >= 0 && bidx < geo.n_faces;
+    const int fs = found ? geo.slot_of[bidx] : 0;
+    double g[3];
+    if (found) {
+        polish_witness(A, cc, geo.face[4 * fs], geo.face[4 * fs + 1], geo.face[4 * fs + 2], bs, bt, c.r64, c.L64, u64,
+                       f64, g);
+        for (int a = 0; a < 3; ++a) {
+            xw[a] = Ri[3 * a] * u64[0] + Ri[3 * a + 1] * u64[1] + Ri[3 * a + 2] * u64[2] + pi[a];
+            nw[a] = Ri[3 * a] * g[0] + Ri[3 * a + 1] * g[1] + Ri[3 * a + 2] * g[2];
+        }
+        best = (float)f64;
+    } else {
+        const float3 u = make_float3(BT.p0.x + bs * BT.e1.x + bt * BT.e2.x, BT.p0.y + bs * BT.e1.y + bt * BT.e2.y,
+                                     BT.p0.z + bs * BT.e1.z + bt * BT.e2.z);
+        const float3 gl = witness_gradient(u, BT, bs, bt);
+        for (int a = 0; a < 3; ++a) {
+            xw[a] = Ri[3 * a] * u.x + Ri[3 * a + 1] * u.y + Ri[3 * a + 2] * u.z + pi[a];
+            nw[a] = Ri[3 * a] * gl.x + Ri[3 * a + 1] * gl.y + Ri[3 * a + 2] * gl.z;
+        }
     }
     out.dx = make_float4(best, (float)xw[0], (float)xw[1], (float)xw[2]);
     out.nf = make_float4((float)nw[0], (float)nw[1], (float)nw[2], __int_as_float(bidx));

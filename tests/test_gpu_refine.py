@@ -279,12 +279,15 @@ def test_lbfgsb_matches_oracle_near_truth(cfg1):
         assert abs(Jg - o.J) <= 1e-3 * max(1.0, abs(o.J))
 
 
-@pytest.mark.skip(reason="the float32 witness of a smooth face minimum is located to ~1e-3 mm only, which moves "
-                         "this ill-conditioned box minimum by ~7e-3 deg; the FP64 witness polish fixes it")
 def test_lbfgsb_minimum_on_the_box(cfg1):
     """Starts 0.55 mm off the truth along x and y: the minimum of J lies on the
     translation bound b_t = 0.5 mm (the oracle's xi has a component at -b_t),
-    where the projected gradient, not the gradient, vanishes."""
+    where the projected gradient, not the gradient, vanishes.  It is
+    ill-conditioned (54 of 200 probes penetrate): the FP64 witnesses keep the
+    device's pose on the oracle's.  On the y start SciPy's L-BFGS-B halts at a
+    kink of J 6.6e-5 above the minimum the oracle's Gauss-Newton reaches; the
+    device's line search passes it, so there the pose is held to that minimum
+    and its J (the oracle's, at the device's pose) may not exceed SciPy's."""
     rd = _lib()
     p = cfg1
     R0 = synth.quat_to_mat(p.q_gt)
@@ -294,10 +297,25 @@ def test_lbfgsb_minimum_on_the_box(cfg1):
         t[ax] += 0.55
         starts.append((R0, t))
     prm = Rf.RefineParams()
-    for ax, (ce, ang, _, _, Jg, o, _, _) in enumerate(_refine_lbfgsb_pair(rd, p, starts)):
+    a = S.anchor(p.vertices)
+    res = _refine_lbfgsb_pair(rd, p, starts)
+    for ax, (ce, ang, ce2, ang2, Jg, o, Rg, pg) in enumerate(res):
         assert o.xi[ax] == pytest.approx(-prm.b_t, abs=1e-12)
-        assert ce <= POS_TOL and ang <= ANG_TOL
+        if ax == 0:
+            assert ce <= POS_TOL and ang <= ANG_TOL
+        else:
+            assert ce2 <= POS_TOL and ang2 <= ANG_TOL
+            pb = Rf.Problem(p.vertices, p.faces, p.poses, p.radius, p.length, R0, starts[ax][1], a)
+            Jat = Rf.evaluate(_xi_of(Rg, pg, pb), pb, prm, want_grad=False)[0]
+            assert Jat <= o.J + 1e-9, (Jat, o.J)
         assert abs(Jg - o.J) <= 1e-3 * max(1.0, abs(o.J))
+
+
+def _xi_of(R, p, pb):
+    """The twist about the start's anchor that gives the pose (R, p)."""
+    w = Rotation.from_matrix(R @ pb.R0.T).as_rotvec()
+    v = np.linalg.solve(Rf.left_jacobian(w), p - pb.p0 - (np.eye(3) - Rf.so3_exp(w)) @ pb.R0 @ pb.a)
+    return np.concatenate([v, w])
 
 
 def test_lbfgsb_config3_from_search_peak_matches_oracle():
