@@ -31,6 +31,8 @@ constexpr float INVPHI_F = 0.618033988749894848f;
 constexpr float BOUND_SLACK = 1e-5f;      // float32 rounding allowance of the face bounds (mm)
 constexpr float VERTEX_GAP = 2e-6f;       // bounds this close: the best vertex is the face minimum (mm)
 constexpr float CERT_TOL = 4e-6f;         // a boundary point this close to a lower bound is the face minimum (mm)
+constexpr int RIM_NEWTON = 3;             // Newton steps of the FP64 witness polish (rim edge)
+constexpr int RIDGE_NEWTON = 4;           // and (inner ridge inside a face)
 
 // ------------------------------------------------------------ FP64 rotations
 
@@ -401,27 +403,27 @@ __device__ float3 witness_gradient(float3 u, const Tri& T, float s, float t) {
 //
 // The float32 searches place a smooth face minimum only to about
 // sqrt(2 e / k) (e the float32 rounding of f_p, k its curvature along the
-// face): up to ~1e-3 mm where the probe wall runs close to an edge.  The
-// witness sets the contact normal and the moment arm of the sensitivities, so
-// the winning face of every query is minimised again in FP64 (face vertices
-// placed by the FP64 pose, as the search's float32 ones are) wherever f_p is
-// smooth around the witness:
-//  * on an edge in the wall branch (q2 <= 0 and q2 below q1 by more than
-//    RIDGE_TOL inside): f_p = rho - r and rho^2 is quadratic along the edge,
-//    its minimiser in closed form;
-//  * on an edge in the rim branch (q1, q2 > 0): Newton on q1^2 + q2^2;
-//  * on an edge where it crosses the inner side/cap ridge: rho = r + q2 with
-//    q2 linear along the edge is a quadratic equation, its root nearest the
-//    search's point (one Newton step polishes it);
-//  * inside the face with the probe strictly on one side of its plane: the
-//    projection of the probe's support point;
-//  * inside the face on the inner side/cap ridge (q1 = q2 <= 0), where a face
-//    almost parallel to the tip disk makes the minimum flat along the ridge:
-//    Newton on the optimality conditions a grad q1 + (1 - a) grad q2 = 0,
-//    q1 = q2 in the face coordinates (q2 is linear there).
-// The new point must stay on the edge or face and in the same branch, and may
-// not raise f_p; the remaining kinks (a ridge crossing an edge, the cap plane,
-// vertices) are located to the search's bracket already and keep their witness.
+// face): up to ~1e-3 mm where the probe wall runs close to an edge, and a
+// minimum where f_p is nearly constant (a face almost parallel to the tip
+// disk) anywhere in that flat part.  The witness sets d, the contact normal and
+// the moment arm of the sensitivities, so the winning face of every live query
+// is placed by the FP64 pose and minimised again in FP64 over a few candidate
+// points that hold the exact minimiser: f_p of the capped cylinder along a line
+// or over a plane is made of pieces (wall: rho - r, cap: a linear q2, rim:
+// sqrt(q1^2 + q2^2), inside: max(q1, q2)), so its minimum is at a stationary
+// point of a smooth piece, on the inner side/cap ridge where max(q1, q2)
+// kinks, or at an end.  The candidate with the least f_p wins; the search's own
+// point is one of them, so the polish never raises f_p.
+//  * On an edge: both ends; the wall's stationary point (rho^2 is quadratic
+//    along the edge, closed form); the rim's (Newton on q1^2 + q2^2 from the
+//    search's point); the two crossings of the ridge rho = r + q2 (a quadratic
+//    equation, q2 being linear along the edge; one Newton step polishes each).
+//  * Inside the face: the projection of the probe's support point (exact when
+//    the probe lies strictly on one side of the plane); the minimiser on the
+//    inner ridge (Newton on a grad q1 + (1 - a) grad q2 = 0, q1 = q2 in the
+//    face coordinates, from the better of the search's point and that
+//    projection: a face grazing the rim circle cuts the probe by a hair); the
+//    crossing of the axis (rho = 0).
 __device__ __forceinline__ void sdf_q64(const double* u, double r, double L, double& rho, double& q1, double& q2) {
     rho = sqrt(u[0] * u[0] + u[1] * u[1]);
     q1 = rho - r;
@@ -435,72 +437,71 @@ __device__ double sdf64(const double* u, double r, double L) {
     return fmin(fmax(q1, q2), 0.0) + sqrt(a * a + b * b);
 }
 
-__device__ __forceinline__ bool wall_branch(double q1, double q2) {
-    return q2 <= 0.0 && (q1 > 0.0 || q2 < q1 - (double)RIDGE_TOL);
+__device__ __forceinline__ double seg_f64(const double* Q, const double* D, double l, double r, double L) {
+    const double u[3] = {Q[0] + l * D[0], Q[1] + l * D[1], Q[2] + l * D[2]};
+    return sdf64(u, r, L);
 }
 
-// minimiser of f_p on the segment Q + l D, l in [0, 1], near l0; false: keep l0
-__device__ bool polish_edge(const double* Q, const double* D, double l0, double r, double L, double& l_out) {
-    double u[3], rho, q1, q2;
-    for (int a = 0; a < 3; ++a) u[a] = Q[a] + l0 * D[a];
-    sdf_q64(u, r, L, rho, q1, q2);
-    const double f0 = sdf64(u, r, L);
-    const bool wall = wall_branch(q1, q2), rim = q1 > 0.0 && q2 > 0.0;
-    const bool ridge = q1 <= 0.0 && q2 <= 0.0 && fabs(q1 - q2) <= (double)RIDGE_TOL;
-    const double sz = u[2] >= 0.5 * L ? 1.0 : -1.0;
-    double l;
-    if (ridge) {
-        // (Qx + l Dx)^2 + (Qy + l Dy)^2 = (r + b0 + b1 l)^2, q2 = b0 + b1 l
+// minimiser of f_p on the segment Q + l D, l in [0, 1]: l_best / f_best hold
+// the search's point on entry and the best candidate on return
+__device__ void polish_edge(const double* Q, const double* D, double r, double L, double& l_best, double& f_best) {
+    const double l0 = l_best;
+    auto consider = [&](double l) {
+        if (!(l >= 0.0 && l <= 1.0)) return;
+        const double f = seg_f64(Q, D, l, r, L);
+        if (f < f_best) {
+            f_best = f;
+            l_best = l;
+        }
+    };
+    consider(0.0);
+    consider(1.0);
+    const double dd = D[0] * D[0] + D[1] * D[1];
+    if (dd > 0.0) consider(-(Q[0] * D[0] + Q[1] * D[1]) / dd);  // wall
+    const double sz = Q[2] + l0 * D[2] >= 0.5 * L ? 1.0 : -1.0;
+    {   // rim
+        double l = l0;
+        bool ok = true;
+        for (int it = 0; it < RIM_NEWTON && ok; ++it) {
+            const double ux = Q[0] + l * D[0], uy = Q[1] + l * D[1], uz = Q[2] + l * D[2];
+            const double rho = sqrt(ux * ux + uy * uy);
+            ok = rho > 0.0;
+            if (!ok) break;
+            const double ir = 1.0 / rho;
+            const double rp = (ux * D[0] + uy * D[1]) * ir, rpp = (dd - rp * rp) * ir;
+            const double a1 = rho - r, a2 = sz * (uz - 0.5 * L) - 0.5 * L;
+            const double g2 = rp * rp + a1 * rpp + D[2] * D[2];
+            ok = g2 > 0.0;
+            if (ok) l -= (a1 * rp + a2 * sz * D[2]) / g2;
+        }
+        if (ok) consider(l);
+    }
+    {   // ridge crossings: (Qx + l Dx)^2 + (Qy + l Dy)^2 = (r + q2)^2, q2 = b0 + b1 l
         const double b1 = sz * D[2], g0 = r + sz * (Q[2] - 0.5 * L) - 0.5 * L;
-        const double qa = D[0] * D[0] + D[1] * D[1] - b1 * b1;
-        const double qb = Q[0] * D[0] + Q[1] * D[1] - g0 * b1;
+        const double qa = dd - b1 * b1, qb = Q[0] * D[0] + Q[1] * D[1] - g0 * b1;
         const double qc = Q[0] * Q[0] + Q[1] * Q[1] - g0 * g0;
         const double disc = qb * qb - qa * qc;
-        if (!(disc >= 0.0)) return false;
-        const double qq = -(qb + copysign(sqrt(disc), qb));
-        const double la = qa != 0.0 ? qq / qa : INFINITY, lb = qq != 0.0 ? qc / qq : INFINITY;
-        l = fabs(la - l0) <= fabs(lb - l0) ? la : lb;
-        if (!(fabs(l - l0) <= 1e-2)) return false;
-        // one Newton step on rho - r - q2
-        const double ux = Q[0] + l * D[0], uy = Q[1] + l * D[1], rh = sqrt(ux * ux + uy * uy);
-        if (!(rh > 0.0)) return false;
-        const double phi = rh - r - (g0 - r + b1 * l), dphi = (ux * D[0] + uy * D[1]) / rh - b1;
-        if (dphi != 0.0) l -= phi / dphi;
-    } else if (wall) {
-        const double dd = D[0] * D[0] + D[1] * D[1];
-        if (!(dd > 0.0)) return false;  // edge along the axis: rho constant on it
-        l = -(Q[0] * D[0] + Q[1] * D[1]) / dd;
-    } else if (rim) {
-        l = l0;
-        for (int it = 0; it < 4; ++it) {
-            for (int a = 0; a < 3; ++a) u[a] = Q[a] + l * D[a];
-            rho = sqrt(u[0] * u[0] + u[1] * u[1]);
-            if (!(rho > 0.0)) return false;
-            const double rp = (u[0] * D[0] + u[1] * D[1]) / rho;
-            const double rpp = (D[0] * D[0] + D[1] * D[1] - rp * rp) / rho;
-            const double a1 = rho - r, a2 = sz * (u[2] - 0.5 * L) - 0.5 * L;
-            const double g1 = a1 * rp + a2 * sz * D[2], g2 = rp * rp + a1 * rpp + D[2] * D[2];
-            if (!(g2 > 0.0)) return false;
-            l -= g1 / g2;
+        if (disc >= 0.0) {
+            const double qq = -(qb + copysign(sqrt(disc), qb));
+            const double roots[2] = {qa != 0.0 ? qq / qa : INFINITY, qq != 0.0 ? qc / qq : INFINITY};
+            for (int j = 0; j < 2; ++j) {
+                double l = roots[j];
+                if (!(l >= -1e-3 && l <= 1.0 + 1e-3)) continue;
+                const double ux = Q[0] + l * D[0], uy = Q[1] + l * D[1], rh = sqrt(ux * ux + uy * uy);
+                if (rh > 0.0) {  // one Newton step on rho - r - q2
+                    const double dphi = (ux * D[0] + uy * D[1]) / rh - b1;
+                    if (dphi != 0.0) l -= (rh - g0 - b1 * l) / dphi;
+                }
+                consider(l);
+            }
         }
-    } else {
-        return false;
     }
-    if (!(l >= 0.0 && l <= 1.0)) return false;
-    for (int a = 0; a < 3; ++a) u[a] = Q[a] + l * D[a];
-    sdf_q64(u, r, L, rho, q1, q2);
-    const double sz1 = u[2] >= 0.5 * L ? 1.0 : -1.0;
-    if (ridge ? !(q1 <= 0.0 && q2 <= 0.0 && fabs(q1 - q2) <= 1e-9 && sz1 == sz)
-              : wall ? !wall_branch(q1, q2) : !(q1 > 0.0 && q2 > 0.0 && sz1 == sz))
-        return false;
-    if (!(sdf64(u, r, L) <= f0)) return false;
-    l_out = l;
-    return true;
 }
 
-// interior witness with the probe strictly on one side of the face plane
-__device__ bool polish_support(const double* P0, const double* E1, const double* E2, double s0, double t0, double r,
-                               double L, double& s_out, double& t_out) {
+// interior candidate: the projection of the probe's support point onto the
+// face plane (the minimiser when the probe lies strictly on one side)
+__device__ bool polish_support(const double* P0, const double* E1, const double* E2, double r, double L, double& s_out,
+                               double& t_out) {
     double N[3] = {E1[1] * E2[2] - E1[2] * E2[1], E1[2] * E2[0] - E1[0] * E2[2], E1[0] * E2[1] - E1[1] * E2[0]};
     const double nn = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
     if (!(nn > 0.0)) return false;
@@ -520,9 +521,11 @@ __device__ bool polish_support(const double* P0, const double* E1, const double*
         top += N[a] * (sh[a] - P0[a]);
         bot += N[a] * (sl[a] - P0[a]);
     }
-    if (!(bot > 0.0 || top < 0.0)) return false;
-    const double h = bot > 0.0 ? bot : top;
-    const double* sp = bot > 0.0 ? sl : sh;
+    // the probe's nearest point to the plane, or where it cuts the plane the
+    // support point of the shallower side (a face grazing the rim circle)
+    const bool low = bot > 0.0 || (!(top < 0.0) && fabs(bot) <= fabs(top));
+    const double h = low ? bot : top;
+    const double* sp = low ? sl : sh;
     double x[3];
     for (int a = 0; a < 3; ++a) x[a] = sp[a] - N[a] * h - P0[a];
     const double a11 = E1[0] * E1[0] + E1[1] * E1[1] + E1[2] * E1[2];
@@ -533,12 +536,6 @@ __device__ bool polish_support(const double* P0, const double* E1, const double*
     if (!(det > 0.0)) return false;
     const double s = (b1 * a22 - b2 * a12) / det, t = (b2 * a11 - b1 * a12) / det;
     if (!(s >= 0.0 && t >= 0.0 && s + t <= 1.0)) return false;
-    double u[3], u0[3];
-    for (int a = 0; a < 3; ++a) {
-        u[a] = P0[a] + s * E1[a] + t * E2[a];
-        u0[a] = P0[a] + s0 * E1[a] + t0 * E2[a];
-    }
-    if (!(sdf64(u, r, L) <= sdf64(u0, r, L))) return false;
     s_out = s;
     t_out = t;
     return true;
@@ -552,18 +549,19 @@ __device__ bool polish_ridge(const double* P0, const double* E1, const double* E
     double rho, q1, q2;
     sdf_q64(u0, r, L, rho, q1, q2);
     if (!(q1 <= 0.0 && q2 <= 0.0 && fabs(q1 - q2) <= (double)RIDGE_TOL && rho > 0.0)) return false;
-    const double f0 = sdf64(u0, r, L);
     const double sz = u0[2] >= 0.5 * L ? 1.0 : -1.0;
     const double c1 = sz * E1[2], c2 = sz * E2[2];  // grad q2 in (s, t)
     double s = s0, t = t0, wa = -1.0;
-    for (int it = 0; it < 6; ++it) {
+    const double m11 = E1[0] * E1[0] + E1[1] * E1[1], m12 = E1[0] * E2[0] + E1[1] * E2[1];
+    const double m22 = E2[0] * E2[0] + E2[1] * E2[1];
+    // quadratic convergence from the search's point (~1e-3 of the face off)
+    for (int it = 0; it < RIDGE_NEWTON; ++it) {
         const double wx = P0[0] + s * E1[0] + t * E2[0], wy = P0[1] + s * E1[1] + t * E2[1];
         rho = sqrt(wx * wx + wy * wy);
         if (!(rho > 0.0)) return false;
-        const double g1 = (E1[0] * wx + E1[1] * wy) / rho, g2 = (E2[0] * wx + E2[1] * wy) / rho;  // grad q1
-        const double h11 = (E1[0] * E1[0] + E1[1] * E1[1] - g1 * g1) / rho;
-        const double h12 = (E1[0] * E2[0] + E1[1] * E2[1] - g1 * g2) / rho;
-        const double h22 = (E2[0] * E2[0] + E2[1] * E2[1] - g2 * g2) / rho;
+        const double ir = 1.0 / rho;
+        const double g1 = (E1[0] * wx + E1[1] * wy) * ir, g2 = (E2[0] * wx + E2[1] * wy) * ir;  // grad q1
+        const double h11 = (m11 - g1 * g1) * ir, h12 = (m12 - g1 * g2) * ir, h22 = (m22 - g2 * g2) * ir;
         const double d1 = g1 - c1, d2 = g2 - c2;
         if (wa < 0.0) {  // the weight that best cancels the two gradients
             const double dd = d1 * d1 + d2 * d2;
@@ -576,21 +574,17 @@ __device__ bool polish_ridge(const double* P0, const double* E1, const double* E
         const double A11 = wa * h11, A12 = wa * h12, A22 = wa * h22;
         const double det = -A11 * d2 * d2 + A12 * d1 * d2 + d1 * (A12 * d2 - A22 * d1);
         if (!(fabs(det) > 1e-300)) return false;
+        const double idet = 1.0 / det;
         const double b1 = -F1, b2 = -F2, b3 = -F3;
         // Cramer's rule
-        const double ds = (-b1 * d2 * d2 + A12 * d2 * b3 + d1 * (b2 * d2 - A22 * b3)) / det;
-        const double dt = (-A11 * d2 * b3 + b1 * d1 * d2 + d1 * (A12 * b3 - b2 * d1)) / det;
-        const double da = (A11 * (A22 * b3 - b2 * d2) - A12 * (A12 * b3 - b2 * d1) + b1 * (A12 * d2 - A22 * d1)) / det;
+        const double ds = (-b1 * d2 * d2 + A12 * d2 * b3 + d1 * (b2 * d2 - A22 * b3)) * idet;
+        const double dt = (-A11 * d2 * b3 + b1 * d1 * d2 + d1 * (A12 * b3 - b2 * d1)) * idet;
+        const double da = (A11 * (A22 * b3 - b2 * d2) - A12 * (A12 * b3 - b2 * d1) + b1 * (A12 * d2 - A22 * d1)) * idet;
         s += ds;
         t += dt;
         wa += da;
     }
-    if (!(wa >= 0.0 && wa <= 1.0 && s >= 0.0 && t >= 0.0 && s + t <= 1.0)) return false;
-    double u[3];
-    for (int a = 0; a < 3; ++a) u[a] = P0[a] + s * E1[a] + t * E2[a];
-    sdf_q64(u, r, L, rho, q1, q2);
-    if (!(q1 <= 0.0 && q2 <= 0.0 && fabs(q1 - q2) <= 1e-9 && (u[2] >= 0.5 * L ? 1.0 : -1.0) == sz)) return false;
-    if (!(sdf64(u, r, L) <= f0)) return false;
+    if (!(wa >= 0.0 && wa <= 1.0)) return false;
     s_out = s;
     t_out = t;
     return true;
@@ -649,9 +643,8 @@ __device__ void witness_gradient64(const double* u, const double* E1, const doub
     for (int a = 0; a < 3; ++a) g[a] = g2v[a] + al * db[a];
 }
 
-// The winner's witness on its face in FP64: (s, t) polished where the
-// minimum is smooth, else the search's point; u (probe frame), f_p there and
-// its gradient, evaluated in FP64 either way.  A (row-major) and c place body
+// The winner's witness on its face in FP64 from the search's point (bs, bt):
+// u (probe frame), f_p there and its gradient.  A (row-major) and c place body
 // points in the probe frame.
 __device__ void polish_witness(const double* A, const double* c, const float4& a0, const float4& a1, const float4& a2,
                                float bs, float bt, double r, double L, double* u, double& f, double* g) {
@@ -665,20 +658,39 @@ __device__ void polish_witness(const double* A, const double* c, const float4& a
         E2[a] = P[2][a] - P[0][a];
         E12[a] = P[2][a] - P[1][a];
     }
-    double s = bs, t = bt, l;
-    bool ok = false;
+    double s = bs, t = bt;
+    for (int a = 0; a < 3; ++a) u[a] = P[0][a] + s * E1[a] + t * E2[a];
+    double fb = sdf64(u, r, L);
+    auto take = [&](double sc, double tc) {
+        if (!(sc >= 0.0 && tc >= 0.0 && sc + tc <= 1.0)) return;
+        double uc[3];
+        for (int a = 0; a < 3; ++a) uc[a] = P[0][a] + sc * E1[a] + tc * E2[a];
+        const double fc = sdf64(uc, r, L);
+        if (fc < fb) {
+            fb = fc;
+            s = sc;
+            t = tc;
+        }
+    };
     if (bt == 0.0f && bs > 0.0f && bs < 1.0f) {
-        if ((ok = polish_edge(P[0], E1, bs, r, L, l))) { s = l; t = 0.0; }
+        double l = bs, fl = fb;
+        polish_edge(P[0], E1, r, L, l, fl);
+        if (fl < fb) { fb = fl; s = l; t = 0.0; }
     } else if (bs == 0.0f && bt > 0.0f && bt < 1.0f) {
-        if ((ok = polish_edge(P[0], E2, bt, r, L, l))) { s = 0.0; t = l; }
+        double l = bt, fl = fb;
+        polish_edge(P[0], E2, r, L, l, fl);
+        if (fl < fb) { fb = fl; s = 0.0; t = l; }
     } else if (bt > 0.0f && bt < 1.0f && fabsf(1.0f - bs - bt) <= 1e-6f) {
-        if ((ok = polish_edge(P[1], E12, bt, r, L, l))) { s = 1.0 - l; t = l; }
+        double l = bt, fl = fb;
+        polish_edge(P[1], E12, r, L, l, fl);
+        if (fl < fb) { fb = fl; s = 1.0 - l; t = l; }
     } else if (bs > 0.0f && bt > 0.0f) {
-        ok = polish_support(P[0], E1, E2, bs, bt, r, L, s, t) || polish_ridge(P[0], E1, E2, bs, bt, r, L, s, t);
-    }
-    if (!ok) {
-        s = bs;
-        t = bt;
+        double sc, tc;
+        if (polish_support(P[0], E1, E2, r, L, sc, tc)) take(sc, tc);
+        // Newton on the ridge from the better of the two
+        if (polish_ridge(P[0], E1, E2, s, t, r, L, sc, tc)) take(sc, tc);
+        const double det = E1[0] * E2[1] - E2[0] * E1[1];  // the axis crossing the face
+        if (det != 0.0) take((E2[0] * P[0][1] - P[0][0] * E2[1]) / det, (P[0][0] * E1[1] - E1[0] * P[0][1]) / det);
     }
     for (int a = 0; a < 3; ++a) u[a] = P[0][a] + s * E1[a] + t * E2[a];
     f = sdf64(u, r, L);
@@ -1315,19 +1327,20 @@ __global__ __launch_bounds__(64) void k_ref_resolve(const RefineTrial* __restric
     }
     double Ri[9], pi[3];
     probe_frame(poses, i, Ri, pi);
-    // body -> probe frame in FP64 for the polish
-    const RefineTrial& P = tr[k];
-    double A[9], cc[3];
-    for (int a = 0; a < 3; ++a) {
-        for (int b = 0; b < 3; ++b) A[3 * a + b] = Ri[a] * P.R[b] + Ri[3 + a] * P.R[3 + b] + Ri[6 + a] * P.R[6 + b];
-        cc[a] = Ri[a] * (P.p[0] - pi[0]) + Ri[3 + a] * (P.p[1] - pi[1]) + Ri[6 + a] * (P.p[2] - pi[2]);
-    }
     double u64[3], f64;
     double xw[3], nw[3];
-    const bool found = bidx >= 0 && bidx < geo.n_faces;
+    // beyond tau_out2 s, s' and s'' vanish: the float32 witness serves
+    const bool found = bidx >= 0 && bidx < geo.n_faces && best < (float)c.tau_out2 + 1e-4f;
     const int fs = found ? geo.slot_of[bidx] : 0;
     double g[3];
     if (found) {
+        // body -> probe frame in FP64
+        const RefineTrial& P = tr[k];
+        double A[9], cc[3];
+        for (int a = 0; a < 3; ++a) {
+            for (int b = 0; b < 3; ++b) A[3 * a + b] = Ri[a] * P.R[b] + Ri[3 + a] * P.R[3 + b] + Ri[6 + a] * P.R[6 + b];
+            cc[a] = Ri[a] * (P.p[0] - pi[0]) + Ri[3 + a] * (P.p[1] - pi[1]) + Ri[6 + a] * (P.p[2] - pi[2]);
+        }
         polish_witness(A, cc, geo.face[4 * fs], geo.face[4 * fs + 1], geo.face[4 * fs + 2], bs, bt, c.r64, c.L64, u64,
                        f64, g);
         for (int a = 0; a < 3; ++a) {
