@@ -252,6 +252,82 @@ def local_search_bench(rd, torch, p, args):
         rd.register_free(h)
 
 
+def _pose_errors(p, po):
+    """Rotation angle (deg) and anchor displacement (mm) of FP64 poses
+    (quaternion, translation) against the problem's ground truth."""
+    import numpy as np
+    from scipy.spatial.transform import Rotation
+
+    a = p.vertices.astype(np.float64).mean(axis=0)
+    Rg = Rotation.from_quat(np.roll(p.q_gt, -1)).as_matrix()
+    R = Rotation.from_quat(np.roll(po[:4], -1)).as_matrix()
+    ang = float(np.degrees(Rotation.from_matrix(R.T @ Rg).magnitude()))
+    return ang, float(np.linalg.norm(R @ a + po[4:] - (Rg @ a + p.t_gt)))
+
+
+def sampler_bench(rd, torch, p, M: int):
+    """Global search with the workload's Sobol->Hopf set against a
+    Super-Fibonacci set of the same size (Sec. IV-C) on one handle: the best
+    peak's pose error and the best of the top-16."""
+    import numpy as np
+
+    h = rd.register_init(p.vertices, p.faces, p.touchable, p.poses, p.so3[:M], p.n, p.h, p.center, p.radius,
+                         p.length)
+    try:
+        out = {}
+        for name, so3 in (("sobol_hopf", None), ("super_fibonacci", rd.so3_super_fibonacci(M))):
+            if so3 is not None:
+                rd.register_set_rotations(h, so3)
+            sc, _, po = rd.score_rotations(h)
+            top = rd.register_top_k(h, sc, 16).cpu().numpy()
+            po = po.cpu().numpy()
+            errs = [_pose_errors(p, po[t]) for t in top]
+            q = (p.so3[:M] if so3 is None else so3.cpu().numpy()).astype(np.float64)
+            q /= np.linalg.norm(q, axis=1, keepdims=True)
+            nearest = float(np.degrees(2.0 * np.arccos(min(1.0, np.abs(q @ p.q_gt).max()))))
+            out[name] = {"best": {"deg": errs[0][0], "mm": errs[0][1]}, "nearest_sample_deg": nearest,
+                         "top16_min_deg": min(e[0] for e in errs), "best_score": float(sc.max())}
+        out["rotations"] = M
+        return out
+    finally:
+        rd.register_free(h)
+
+
+def linear_bench(rd, torch, M: int = 4096):
+    """The padded variant of the search (Sec. IV-B) on the smallest workload
+    (h 0.4 mm): the circular search on its 32^3 canvas against the same search
+    on the edge register_linear_edge gives (n_o + n_s - 1 = 107 -> 120), where
+    the correlation is linear.  Same Super-Fibonacci set; rotations/s of the
+    scoring, model HBM bytes per rotation and the best peak's pose error."""
+    import numpy as np
+    import synth
+
+    p = synth.config_problem(1, 0)
+    need, edge = rd.register_linear_edge(p.vertices, p.radius, p.length, p.poses, p.center, p.h)
+    so3 = rd.so3_super_fibonacci(M)
+    res = {"needed_edge": need, "rotations": M}
+    for name, n in (("circular", p.n), ("linear", edge)):
+        h = rd.register_init(p.vertices, p.faces, p.touchable, p.poses, so3, n, p.h, p.center, p.radius, p.length)
+        try:
+            rd.score_rotations(h)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sc, _, po = rd.score_rotations(h)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            info = rd.register_info(h)
+            sc, po = sc.cpu().numpy(), po.cpu().numpy()
+            b = int(np.argmax(sc))
+            ang, mm = _pose_errors(p, po[b])
+            H8 = info["spectrum_elems"] * 8
+            res[name] = {"n": n, "rotations_per_s": M / dt, "model_bytes_per_rotation": 4 * H8 + H8 / info["batch"],
+                         "best": {"deg": ang, "mm": mm, "score": float(sc[b])}}
+        finally:
+            rd.register_free(h)
+    res["cost_ratio"] = res["circular"]["rotations_per_s"] / res["linear"]["rotations_per_s"]
+    return res
+
+
 def solver_bench(rd, torch, p, dev_args, starts, reps: int = 3):
     """The refinement of the step's 16 starts by both solvers on one handle:
     time per call (after one untimed call each) and how far apart the refined
@@ -304,6 +380,8 @@ def main():
     ap.add_argument("--serve-sustained", type=float, default=6.0,
                     help="a second arrival rate below the serial path's capacity (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--variants", type=int, default=1,
+                    help="Super-Fibonacci vs Sobol->Hopf and padded linear correlation (0: skip)")
     ap.add_argument("--solvers", type=int, default=1, help="compare Gauss-Newton and L-BFGS-B refinement (0: skip)")
     ap.add_argument("--local", type=int, default=5000, help="GeoBall-SF samples of the local search (0: skip)")
     ap.add_argument("--local-theta", type=float, default=5.0, help="geodesic ball radius (deg)")
@@ -430,6 +508,10 @@ def main():
         out["refine_solvers"] = solver_bench(rd, torch, p, (V, F, T, P, Q),
                                              torch.from_numpy(info["starts"]).to("cuda"))
         print("bench: solver comparison done", file=sys.stderr, flush=True)
+    if args.variants:
+        out["samplers"] = sampler_bench(rd, torch, p, len(p.so3))
+        out["linear_correlation"] = linear_bench(rd, torch)
+        print("bench: sampler and linear-correlation variants done", file=sys.stderr, flush=True)
     if args.batch > 0:
         out["batch"] = batch_bench(rd, torch, work["batch"], args)
         print("bench: uneven batch done", file=sys.stderr, flush=True)

@@ -110,6 +110,25 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
                   const float* so3, int32_t n_rot, const reg_grid_spec* grid, const reg_params* params,
                   void* hip_stream, reg_handle** out);
 
+/* Canvas edge for the padded, linear correlation of Sec. IV-B: the search's
+ * correlation is circular on the n^3 canvas, and it equals the linear
+ * (zero-padded) correlation once n >= n_o + n_s - 1, where n_o and n_s are the
+ * grid extents of the object and of the rotated swept occupancy.  Both are
+ * bounded by spheres about the canvas centre: the vertex radius about the
+ * vertex mean plus tau_out1 (the object grid vanishes farther from the mesh;
+ * <= 0 selects 0.5 mm), and the farthest probe point of the trajectory from
+ * center_world (grid spec) plus sqrt(3) h (the reach of the trilinear
+ * resampling); a radius R covers 2 floor(R/h) + 1 grid points.
+ *   vertices: n_vertices x 3 float, poses: n_poses x 7 float, both HOST
+ *   memory (this is a planning call, before register_init).
+ *   *needed = n_o + n_s - 1; *edge = the smallest supported edge >= *needed.
+ * Passing *edge as grid.n (same h and centre) gives a wrap-free search.
+ * Errors: REG_EINVAL (NULL or non-finite input, h or probe size <= 0),
+ * REG_ENOTSUP (*needed above 160; *needed is still set, *edge = 0). */
+int register_linear_edge(const float* vertices, int32_t n_vertices, const reg_probe* probe, const float* poses,
+                         int32_t n_poses, const double* center_world, double h_mm, double tau_out1, int32_t* needed,
+                         int32_t* edge);
+
 /* Score SO(3) samples [first, first + count) (Sec. IV-B and IV-D).  For each
  * rotation R: S_r[k] = trilinear S_w at R (x_k - a) + center_world; C = circular
  * correlation of O with S_r; score = max C; d* = the lowest flat index among

@@ -8,7 +8,9 @@ Readings of the paper taken here (each listed in the design notes):
   * S(y) = 1 iff min_i f_p(T_i^{-1} y) <= 0 (inside-inclusive);
   * the score is the correlation C[d] = sum_k O[k] S[k + d] of Eq. (xcorr),
     whose FFT form is F^{-1}(conj(F(O)) * F(S));
-  * the correlation is circular on the n^3 canvas (no anti-wrap padding);
+  * the correlation is circular on the n^3 canvas; the padded (linear)
+    variant of Sec. IV-B is the same search on an edge n >= n_o + n_s - 1
+    (linear_edge), where no shift wraps (linear_correlate is its definition);
   * the swept grid is the one rotated: S_w is built once on a world lattice and
     trilinearly resampled per rotation, while O and its spectrum stay fixed;
   * anchor a = mean of the mesh vertices; canvas x_k = a + h (k - n/2);
@@ -187,6 +189,73 @@ def correlate_direct(O: np.ndarray, S: np.ndarray) -> np.ndarray:
             for dx in range(n):
                 C[dz, dy, dx] = np.sum(O * np.roll(S, shift=(-dz, -dy, -dx), axis=(0, 1, 2)))
     return C
+
+
+def linear_correlate(O: np.ndarray, S: np.ndarray) -> np.ndarray:
+    """C_lin[d] = sum_k O[k] S[k + d] for every d in [-(n-1), n-1]^3 with S = 0
+    off the grid: the correlation of the zero-padded grids (Sec. IV-B pads
+    each axis to at least n_o + n_s - 1).  Axis order (dz, dy, dx), indexed by
+    d + n - 1; computed as the circular correlation of the grids padded to 2n,
+    where no shift in that range wraps onto the data."""
+    n = O.shape[0]
+    Op = np.zeros((2 * n,) * 3)
+    Sp = np.zeros((2 * n,) * 3)
+    Op[:n, :n, :n] = O
+    Sp[:n, :n, :n] = S
+    C = correlate(Op, Sp)
+    idx = np.arange(-(n - 1), n) % (2 * n)
+    return C[np.ix_(idx, idx, idx)]
+
+
+def linear_peak(C_lin: np.ndarray):
+    """(max, signed shift (dx, dy, dz)) of a linear correlation; the first
+    maximum in (dz, dy, dx) order from the most negative shifts."""
+    n = (C_lin.shape[0] + 1) // 2
+    flat = int(np.argmax(C_lin.ravel()))
+    kz, ky, kx = np.unravel_index(flat, C_lin.shape)
+    return float(C_lin.ravel()[flat]), np.array([kx, ky, kz], dtype=np.int64) - (n - 1)
+
+
+def probe_reach(poses, r: float, L: float, wc) -> float:
+    """Largest distance from wc to a point of the probe (capped cylinder of
+    radius r, tip disk at the pose origin, axis +z of length L) over the
+    trajectory.  The farthest point of a disk with centre e, unit axis z and
+    radius r from c lies on its rim: sqrt(((e-c).z)^2 + (|(e-c) x z| + r)^2)."""
+    P = np.asarray(poses, dtype=np.float32).astype(np.float64)
+    reach = 0.0
+    for Pi in P:
+        R = quat_to_mat(Pi[:4])
+        z = R[:, 2]
+        for end in (0.0, L):
+            v = Pi[4:] + end * z - np.asarray(wc, dtype=np.float64)
+            along = float(v @ z)
+            across = float(np.linalg.norm(np.cross(v, z)))
+            reach = max(reach, math.hypot(along, across + r))
+    return reach
+
+
+def linear_edge(vertices, poses, r: float, L: float, wc, h: float, tau_out1: float = 0.5):
+    """(n_o, n_s, n_o + n_s - 1): grid extents of the object grid and of the
+    rotated swept occupancy, and the edge from which the circular correlation
+    is the linear one.  O vanishes beyond tau_out1 outside the mesh, so its
+    support lies within the vertex radius about the anchor plus tau_out1; S_r
+    lies within the probe reach about wc plus sqrt(3) h, the reach of the
+    trilinear taps.  A ball of radius R about the canvas centre (a grid point)
+    holds 2 floor(R/h) + 1 points along an axis."""
+    V = np.asarray(vertices, dtype=np.float32).astype(np.float64)
+    ro = float(np.max(np.linalg.norm(V - anchor(V), axis=1)))
+    rs = probe_reach(poses, r, L, wc)
+    n_o = 2 * math.floor((ro + tau_out1) / h) + 1
+    n_s = 2 * math.floor(rs / h + math.sqrt(3.0)) + 1
+    return n_o, n_s, n_o + n_s - 1
+
+
+def support_extent(G: np.ndarray) -> int:
+    """Largest per-axis extent (in grid points) of the nonzero entries of G."""
+    nz = np.argwhere(G != 0)
+    if len(nz) == 0:
+        return 0
+    return int((nz.max(axis=0) - nz.min(axis=0) + 1).max())
 
 
 def peak(C: np.ndarray):

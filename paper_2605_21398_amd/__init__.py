@@ -30,7 +30,7 @@ EXPORTS = ["register_init", "score_rotations", "register_top_k", "register_free"
            "register_server_last_error", "register_batch_create", "register_batch_run", "register_batch_outputs",
            "register_batch_free", "register_autotune", "register_tuned_batch", "register_cached_bytes",
            "register_release_cached", "so3_super_fibonacci", "so3_geoball_sf", "register_set_rotations",
-           "refine_se3_lbfgsb"]
+           "refine_se3_lbfgsb", "register_linear_edge"]
 
 
 class RegError(RuntimeError):
@@ -117,6 +117,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.so3_super_fibonacci.argtypes = [i32, p, p]
     L.so3_geoball_sf.restype = ctypes.c_int
     L.so3_geoball_sf.argtypes = [i32, p, ctypes.c_double, ctypes.c_double, p, p]
+    L.register_linear_edge.restype = ctypes.c_int
+    L.register_linear_edge.argtypes = [p, i32, ctypes.POINTER(reg_probe), p, i32, p, ctypes.c_double, ctypes.c_double,
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     L.register_set_rotations.restype = ctypes.c_int
     L.register_set_rotations.argtypes = [p, p, i32]
     L.register_release_cached.restype = None
@@ -528,6 +531,25 @@ def so3_geoball_sf(n: int, q0, theta: float, gamma: float = 0.0, stream=None):
     _check(load_library().so3_geoball_sf(n, q.ctypes.data_as(ctypes.c_void_p), float(theta), float(gamma), _ptr(out),
                                           ctypes.c_void_p(st.cuda_stream)))
     return out
+
+
+def register_linear_edge(vertices, radius: float, length: float, poses, center, h: float,
+                         tau_out1: float = 0.0):
+    """(needed, edge): the canvas edge n_o + n_s - 1 at which the circular
+    correlation equals the linear one, and the smallest supported edge at least
+    that large (0 when none is).  Host arrays."""
+    V = np.ascontiguousarray(vertices, dtype=np.float32).reshape(-1, 3)
+    P = np.ascontiguousarray(poses, dtype=np.float32).reshape(-1, 7)
+    c = np.ascontiguousarray(center, dtype=np.float64).reshape(3)
+    probe = reg_probe(float(radius), float(length))
+    need, edge = ctypes.c_int32(), ctypes.c_int32()
+    rc = load_library().register_linear_edge(V.ctypes.data_as(ctypes.c_void_p), len(V), ctypes.byref(probe),
+                                              P.ctypes.data_as(ctypes.c_void_p), len(P),
+                                              c.ctypes.data_as(ctypes.c_void_p), float(h), float(tau_out1),
+                                              ctypes.byref(need), ctypes.byref(edge))
+    if rc != REG_ENOTSUP:
+        _check(rc)
+    return need.value, edge.value
 
 
 def register_set_rotations(h: Handle, so3) -> None:

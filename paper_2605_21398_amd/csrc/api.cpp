@@ -989,6 +989,74 @@ void register_free(reg_handle* h) {
     delete h;
 }
 
+// ------------------------------------------------------ linear correlation
+
+// Both supports are bounded by spheres about the canvas centre: the object's
+// by the vertex radius about the anchor plus tau_out1 (O vanishes farther out
+// of the mesh), the rotated swept occupancy's by the trajectory's farthest
+// probe point from center_world plus sqrt(3) h, the reach of its trilinear
+// resampling.  A sphere of radius R holds 2 floor(R / h) + 1 grid points along
+// an axis, and the circular correlation of the canvas equals the linear one
+// once n >= n_o + n_s - 1 (Sec. IV-B).
+int register_linear_edge(const float* vertices, int32_t n_vertices, const reg_probe* probe, const float* poses,
+                         int32_t n_poses, const double* center_world, double h_mm, double tau_out1, int32_t* needed,
+                         int32_t* edge) {
+    g_err.clear();
+    if (!vertices || n_vertices < 1 || !probe || !poses || n_poses < 1 || !center_world || !needed || !edge)
+        return fail(REG_EINVAL, "register_linear_edge: NULL argument or empty mesh/trajectory");
+    if (!(h_mm > 0) || !std::isfinite(h_mm) || !(probe->radius_mm > 0) || !(probe->length_mm > 0) ||
+        !std::isfinite(probe->radius_mm) || !std::isfinite(probe->length_mm))
+        return fail(REG_EINVAL, "register_linear_edge: h and the probe dimensions must be finite and > 0");
+    if (!(tau_out1 > 0)) tau_out1 = 0.5;
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < n_vertices; ++i)
+        for (int k = 0; k < 3; ++k) {
+            if (!std::isfinite(vertices[3 * i + k])) return fail(REG_EINVAL, "vertex %d is not finite", i);
+            a[k] += vertices[3 * i + k];
+        }
+    for (int k = 0; k < 3; ++k) a[k] /= n_vertices;
+    double ro = 0.0;
+    for (int i = 0; i < n_vertices; ++i) {
+        const double dx = vertices[3 * i] - a[0], dy = vertices[3 * i + 1] - a[1], dz = vertices[3 * i + 2] - a[2];
+        ro = std::max(ro, std::sqrt(dx * dx + dy * dy + dz * dz));
+    }
+    const double r = probe->radius_mm, L = probe->length_mm;
+    double rs = 0.0;
+    for (int i = 0; i < n_poses; ++i) {
+        const float* P = poses + 7 * i;
+        for (int k = 0; k < 7; ++k)
+            if (!std::isfinite(P[k])) return fail(REG_EINVAL, "pose %d is not finite", i);
+        const double qn = std::sqrt((double)P[0] * P[0] + (double)P[1] * P[1] + (double)P[2] * P[2] + (double)P[3] * P[3]);
+        if (!(qn > 0)) return fail(REG_EINVAL, "pose %d has a zero quaternion", i);
+        const double w = P[0] / qn, x = P[1] / qn, y = P[2] / qn, z = P[3] / qn;
+        const double ax[3] = {2 * (x * z + w * y), 2 * (y * z - w * x), 1 - 2 * (x * x + y * y)};  // probe axis
+        for (int e = 0; e < 2; ++e) {  // tip disk and far disk: the farthest point is on a rim
+            double v[3];
+            for (int k = 0; k < 3; ++k) v[k] = P[4 + k] + e * L * ax[k] - center_world[k];
+            const double al = v[0] * ax[0] + v[1] * ax[1] + v[2] * ax[2];
+            double pr2 = 0.0;
+            for (int k = 0; k < 3; ++k) pr2 += (v[k] - al * ax[k]) * (v[k] - al * ax[k]);
+            const double b = std::sqrt(pr2) + r;
+            rs = std::max(rs, std::sqrt(al * al + b * b));
+        }
+    }
+    const double no = 2.0 * std::floor((ro + tau_out1) / h_mm) + 1.0;
+    const double ns = 2.0 * std::floor(rs / h_mm + std::sqrt(3.0)) + 1.0;
+    const double need = no + ns - 1.0;
+    *needed = need > 2147483647.0 ? 2147483647 : (int32_t)need;
+    *edge = 0;
+    static const int edges[] = {16, 32, 48, 60, 64, 80, 96, 120, 128, 160};
+    for (int n : edges)
+        if (canvas_supported(n) && n >= need) {
+            *edge = n;
+            break;
+        }
+    if (*edge == 0)
+        return fail(REG_ENOTSUP, "the linear correlation needs a canvas edge >= %d; the largest supported is 160",
+                    (int)*needed);
+    return REG_OK;
+}
+
 // ------------------------------------------------------ orientation samplers
 
 int so3_super_fibonacci(int32_t n, float* out, void* hip_stream) {
