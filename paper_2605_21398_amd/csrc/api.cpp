@@ -243,6 +243,16 @@ struct reg_handle {
     double2* lowT = nullptr;
     double2* Wlow = nullptr;
     double2* Plow = nullptr;
+    // the second lane of the search pipeline: the odd batches of a call run on
+    // stream2 with pass buffers of their own, so that one batch's HBM-bound z
+    // pass overlaps the VALU-bound plane passes of the next
+    hipStream_t stream2 = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    float2* spec2 = nullptr;
+    unsigned long long* ptop2 = nullptr;
+    double* pssq2 = nullptr;
+    double2* lowT2 = nullptr;
+    double2* Plow2 = nullptr;
     int* err = nullptr;
     // refinement solver state (the mesh hierarchy lives in the object)
     RefineState* rst = nullptr;
@@ -299,6 +309,10 @@ struct reg_handle {
         // queued work must finish before the blocks (and the object, released
         // after this body) can serve anyone else
         if (stream) (void)hipStreamSynchronize(stream);
+        if (stream2) (void)hipStreamSynchronize(stream2);
+        if (stream2) (void)hipStreamDestroy(stream2);
+        if (fork_ev) (void)hipEventDestroy(fork_ev);
+        if (join_ev) (void)hipEventDestroy(join_ev);
         for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
         for (void* p : owned) regdock_rt::dev_release(p);
         if (r_active_host) (void)hipHostFree(r_active_host);
@@ -744,6 +758,16 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
     ALLOC_TRY(h, h->cm, mp3);
     ALLOC_TRY(h, h->lowT, (size_t)h->batch * h->n * NLOW2);
     ALLOC_TRY(h, h->Plow, (size_t)h->batch * NLOW3);
+    if (n_rot > h->batch) {  // a call can span two batches: the second lane
+        ALLOC_TRY(h, h->spec2, h->H * (size_t)h->batch);
+        ALLOC_TRY(h, h->ptop2, (size_t)h->batch * h->n * KTOP);
+        ALLOC_TRY(h, h->pssq2, (size_t)h->batch * h->n);
+        ALLOC_TRY(h, h->lowT2, (size_t)h->batch * h->n * NLOW2);
+        ALLOC_TRY(h, h->Plow2, (size_t)h->batch * NLOW3);
+        DEV_TRY(h, hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking));
+        DEV_TRY(h, hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
+        DEV_TRY(h, hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming));
+    }
     ALLOC_TRY(h, h->err, 1);
 
     if (build) {
@@ -1125,8 +1149,18 @@ static int run_batches(reg_handle* h, int first, int count, float* out_score, in
                        float* corr_out) {
     const PeakArrays pk{h->cand_idx, h->cand_n, h->window, h->ovf, h->best_val, h->best_flat,
                         h->need_list, h->need_count, h->cand_part, h->stats};
-    for (int b0 = 0; b0 < count; b0 += h->batch) {
+    // two lanes when the call spans more than one batch: even batches on the
+    // handle's stream, odd ones on stream2 (forked from it here and joined back
+    // before the call's last step); each lane keeps its own pass buffers.  Not
+    // under graph capture, whose batches already run on parallel branches (a
+    // fork of stream2 inside the capture crashed register_batch_create).
+    hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+    DEV_TRY(h, hipStreamIsCapturing(h->stream, &capture));
+    const bool two = h->stream2 && count > h->batch && capture == hipStreamCaptureStatusNone;
+    for (int b0 = 0, j = 0; b0 < count; b0 += h->batch, ++j) {
         const int cnt = count - b0 < h->batch ? count - b0 : h->batch;
+        const bool odd = two && (j & 1);
+        hipStream_t ls = odd ? h->stream2 : h->stream;
         SearchBatchArgs a{};
         a.cmask = h->cm;
         a.m = h->m;
@@ -1134,31 +1168,42 @@ static int run_batches(reg_handle* h, int first, int count, float* out_score, in
         a.rots = h->rots + 9 * (size_t)(first + b0);
         a.count = cnt;
         a.tw = h->tw;
-        a.spec = h->spec;
+        a.spec = odd ? h->spec2 : h->spec;
         a.W = h->W;
         a.tw64 = h->tw64;
-        a.lowT = h->lowT;
+        a.lowT = odd ? h->lowT2 : h->lowT;
         a.Wlow = h->Wlow;
-        a.Plow = h->Plow;
-        a.ptop = h->ptop;
-        a.pssq = h->pssq;
+        a.Plow = odd ? h->Plow2 : h->Plow;
+        a.ptop = odd ? h->ptop2 : h->ptop;
+        a.pssq = odd ? h->pssq2 : h->pssq;
         a.corr_out = corr_out;
-        a.stream = h->stream;
+        a.stream = ls;
         for (int pass = 0; pass < 3; ++pass) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (h->timing) {
                 e0 = h->next_event();
                 e1 = h->next_event();
                 if (!e0 || !e1) return fail(REG_EDEVICE, "hipEventCreate failed");
-                DEV_TRY(h, hipEventRecord(e0, h->stream));
+                DEV_TRY(h, hipEventRecord(e0, ls));
             }
             DEV_TRY(h, search_pass(h->n, pass, a));
             if (h->timing) {
-                DEV_TRY(h, hipEventRecord(e1, h->stream));
+                DEV_TRY(h, hipEventRecord(e1, ls));
                 h->timed.push_back({e0, e1, pass, cnt});
+            }
+            if (two && j == 0 && pass == 0) {
+                // the second lane starts once the first batch's plane pass is
+                // done, half a batch out of phase: its plane passes then meet
+                // the first lane's z pass more often than its plane passes
+                DEV_TRY(h, hipEventRecord(h->fork_ev, h->stream));
+                DEV_TRY(h, hipStreamWaitEvent(h->stream2, h->fork_ev, 0));
             }
         }
         DEV_TRY(h, select_batch(h->n, a, first + b0, pk));
+    }
+    if (two) {
+        DEV_TRY(h, hipEventRecord(h->join_ev, h->stream2));
+        DEV_TRY(h, hipStreamWaitEvent(h->stream, h->join_ev, 0));
     }
     const RescoreInputs ri{h->nz_idx, h->nz_val, h->nz_count, h->cm, h->m, h->mp, h->rots};
     DEV_TRY(h, finish_call(h->n, first, count, h->prm.rescore != 0, pk, ri, h->so3 + 4 * (size_t)first, h->h, h->anchor,
@@ -1482,7 +1527,8 @@ Footprint footprint(int n, int n_rot, int n_poses, int nv, int nf, int batch, in
                8 * ((n3 + 255) / 256) + 68 * (size_t)nf + 2048;
     const size_t per_rot = 4 * 4 + 4 + 12 + 8 + 4 + 8 + 1 + 8 + 4 + 4 + CMAX * 4 + CMAX * 8 * (size_t)rescore_slices(n);
     const size_t K = (size_t)std::max(refine_starts, 1), nq = K * REF_TMAX * N;
-    f.request = H * B * 8 + B * n * KTOP * 8 + B * n * 8 + B * n * NLOW2 * 16 + B * NLOW3 * 16 + M * per_rot +
+    const size_t lanes = M > B ? 2 : 1;  // the second lane's pass buffers
+    f.request = lanes * (H * B * 8 + B * n * KTOP * 8 + B * n * 8 + B * n * NLOW2 * 16 + B * NLOW3 * 16) + M * per_rot +
                 M * (4 + 56) + 28 * N + 48 * N + m * m * m + mp * mp * mp + 8 * n3 + n * n * ((n + 31) / 32) * 4 +
                 K * (sizeof(RefineState) + sizeof(LbfgsState) +
                      REF_TMAX * (sizeof(RefineTrial) + REF_EVAL_PARTS * sizeof(RefineEval))) +
