@@ -82,8 +82,11 @@ def counter_traffic(kernel: str, n: int):
     if not m:
         return None
     data = json.loads(m.group(1))
-    src = os.path.join(ROOT, "paper_2605_21398_amd", "csrc", "search_kernels.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != data.get("search_kernels_sha256"):
+    csrc = os.path.join(ROOT, "paper_2605_21398_amd", "csrc")
+    sha = hashlib.sha256()
+    for f in ("search_kernels.hip", "search_kernels.h"):
+        sha.update(open(os.path.join(csrc, f), "rb").read())
+    if sha.hexdigest() != data.get("search_kernels_sha256"):
         return None
     k = data["kernels"].get(f"{kernel}<{n}>")
     return None if k is None else k["traffic_bytes"]

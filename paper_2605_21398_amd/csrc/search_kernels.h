@@ -12,7 +12,7 @@ constexpr int CMAX = 16;
 // Exact low-frequency block: frequencies with max(|kx|, |ky|, |kz|) <= KLOW are
 // taken out of the float32 FFT path and carried in double (they hold nearly all
 // of the correlation's energy, which the -50 penalty makes huge).
-constexpr int KLOW = 4;
+constexpr int KLOW = 3;
 constexpr int NLX = KLOW + 1;        // kx in [0, KLOW]
 constexpr int NLY = 2 * KLOW + 1;    // ky, kz in [-KLOW, KLOW]
 constexpr int NLOW2 = NLX * NLY;     // (kx, ky) pairs of a plane

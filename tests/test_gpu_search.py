@@ -22,7 +22,7 @@ pytestmark = pytest.mark.gpu
 TOL_REL = 1e-4
 
 
-KLOW = 4  # frequencies with max(|kx|,|ky|,|kz|) <= KLOW are carried in double
+KLOW = 3  # the library's KLOW: frequencies with max(|kx|,|ky|,|kz|) <= KLOW are carried in double
 
 
 def eps_bound(C_ref, n):
@@ -261,3 +261,28 @@ def test_config2_full_size_sampled_exact_rescore():
 def test_config3_full_size_sampled():
     p, sc, sh = _sampled_full_size(3, 6)
     assert np.isfinite(sc).all()
+
+
+def test_two_lanes_equal_one_lane():
+    """A call over many batches alternates them between the handle's two
+    streams (each with its own pass buffers); calls of one batch each stay on
+    one lane.  With every rotation re-scored exactly (rescore = 1; otherwise the
+    certification tolerance, 1e-4 of the call's largest score, depends on how
+    the rotations are split into calls) scores, shifts and poses must be
+    bit-identical."""
+    rd = _lib()
+    p = _problem(2, 0)
+    h = _handle(rd, p, params=dict(rescore=1))
+    try:
+        B = rd.register_info(h)["batch"]
+        M = len(p.so3)
+        assert M > 2 * B
+        full = [t.cpu().numpy() for t in rd.score_rotations(h)]
+        parts = [[], [], []]
+        for b0 in range(0, M, B):
+            for k, t in enumerate(rd.score_rotations(h, b0, min(B, M - b0))):
+                parts[k].append(t.cpu().numpy())
+    finally:
+        rd.register_free(h)
+    for k in range(3):
+        assert np.array_equal(full[k], np.concatenate(parts[k]))
