@@ -81,7 +81,8 @@ struct LbfgsState {
     double gp;      // g . p
     double lam0;    // largest step length of the trials in flight (trial j: lam0 / 2^j)
     double fprev;   // J before the last accepted step
-    int npairs, head, nback, pad;
+    int npairs, head, nback;  // nback: halvings of the current line search
+    int ntr;                  // step lengths evaluated in the last round
 };
 // One trial point of a start, FP64: twist, step, damping, pose and Jacobians.
 struct RefineTrial {

@@ -1629,11 +1629,14 @@ __global__ void k_ref_decide(RefineState* __restrict__ st, RefineTrial* __restri
 // minimises the model over the variables still free there (Cholesky of their
 // block of B) and truncates that step to the box; the direction is
 // p = x_bar - x.  The line search backtracks from step 1 (1/|p| at the first
-// iteration) by halving, four step lengths per round, and takes the first
-// that meets the sufficient decrease J <= J0 + 1e-4 lam g.p; a pair enters the
-// memory when s'y > eps y'y.  The iteration stops on a projected gradient
-// below tol_pg, a relative decrease of J below 1e-10, max_iters steps, or a
-// line search that finds no decrease even from steepest descent.
+// iteration) by halving and takes the first step length that meets the
+// sufficient decrease J <= J0 + 1e-4 lam g.p.  After an accepted step the
+// next round evaluates the unit step alone (taken most of the time); once a
+// round finds no decrease, the following ones evaluate four halvings each.
+// A pair enters the memory when s'y > eps y'y.  The iteration stops on a
+// projected gradient below tol_pg, a relative decrease of J below 1e-10,
+// max_iters steps, or a line search that finds no decrease (32 halvings) even
+// from steepest descent.
 
 __device__ __forceinline__ double dot6(const double* a, const double* b) {
     double t = 0.0;
@@ -1767,7 +1770,9 @@ __global__ void k_ref_decide_lbfgsb(RefineState* __restrict__ st, LbfgsState* __
     LbfgsState& L = lb[k];
     if (threadIdx.x == 0) {
         constexpr double C1 = 1e-4, FTOL = 1e-10;
+        constexpr int MAX_HALVINGS = 32;
         bool stop = false;
+        int next = REF_TMAX;  // step lengths for the next round
         if (S.status == 0) {
             // the start's evaluation at xi = 0
             S.J = Es[0].J;
@@ -1822,11 +1827,14 @@ __global__ void k_ref_decide_lbfgsb(RefineState* __restrict__ st, LbfgsState* __
                 } else {
                     lbfgsb_direction(S, L, c);
                     L.lam0 = 1.0;
+                    // the unit step is taken most of the time: try it alone,
+                    // and four halvings only once it fails
+                    next = 1;
                 }
             } else {
-                L.lam0 *= 1.0 / 16.0;  // the four trials of the next round continue the halving
-                L.nback += 1;
-                if (L.nback > 8) {
+                for (int j = 0; j < L.ntr; ++j) L.lam0 *= 0.5;  // continue the halving
+                L.nback += L.ntr;
+                if (L.nback > MAX_HALVINGS) {
                     if (L.npairs > 0) {
                         L.npairs = 0;
                         lbfgsb_direction(S, L, c);
@@ -1839,7 +1847,8 @@ __global__ void k_ref_decide_lbfgsb(RefineState* __restrict__ st, LbfgsState* __
             }
         }
         S.status = stop ? 2 : 1;
-        ntrial = stop ? 0 : REF_TMAX;
+        ntrial = stop ? 0 : next;
+        L.ntr = stop ? 0 : next;
         if (!stop) atomicAdd(&counters[0], 1);
     }
     __syncthreads();
