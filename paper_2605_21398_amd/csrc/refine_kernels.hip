@@ -3,10 +3,12 @@
 // Every start (an initial object pose from the global search) is refined by a
 // damped Gauss-Newton iteration on the twist xi = (v, w), one evaluation round
 // per trial step for all unfinished starts at once:
-//   k_ref_cull, k_ref_pairs, k_ref_winner, k_ref_resolve
-//                 FP32: per (start, probe pose) the smallest signed distance d,
-//                 its witness x* and the probe normal n (Sec. V-B);
-//   k_ref_eval    FP64, one block per trial: J = -sum s(d) + lambda |xi|^2,
+//   k_ref_cull, k_ref_pairs, k_ref_nested, k_ref_winner, k_ref_resolve
+//                 per (start, probe pose) the smallest signed distance d, its
+//                 witness x* and the probe normal n (Sec. V-B): the face
+//                 searches in FP32, the winning face's minimiser polished and
+//                 evaluated in FP64;
+//   k_ref_eval    FP64, REF_EVAL_PARTS blocks per trial: J = -sum s(d) + lambda |xi|^2,
 //                 grad J and the curvature sum max(0, -s'') g g^T + 2 lambda I
 //                 with g the contact sensitivities (Sec. V-C), in a fixed
 //                 summation order;
@@ -17,6 +19,8 @@
 //                 R = exp(w^) R0, p = p0 + V(w) v + (I - exp(w^)) R0 a
 //                 (Eq. se3-exp and the left updates) with V(w), the coupling
 //                 D = d(V v)/dw and the pivot c = p0 + V v + R0 a.
+// The L-BFGS-B variant (the paper's solver) replaces k_ref_decide by
+// k_ref_decide_lbfgsb on the same queries and evaluations.
 #include "refine_kernels.h"
 
 #include <algorithm>
