@@ -331,6 +331,21 @@ def linear_bench(rd, torch, M: int = 4096):
     return res
 
 
+def isolated_launches(rd, torch, p, dev_args, reps: int = 8):
+    """Mean event-timed launch of each search pass when it runs alone: calls of
+    one batch each stay on one lane, so no other pass shares the GPU."""
+    h = rd.register_init(*dev_args, p.n, p.h, p.center, p.radius, p.length)
+    try:
+        B = rd.register_info(h)["batch"]
+        rd.score_rotations(h, 0, B)
+        rd.register_set_timing(h, True)
+        for r in range(reps):
+            rd.score_rotations(h, (r * B) % max(1, len(p.so3) - B + 1), B)
+        return {KERNELS[k]: ms / la for k, (ms, la, ro) in rd.register_get_timing(h).items() if la}
+    finally:
+        rd.register_free(h)
+
+
 def solver_bench(rd, torch, p, dev_args, starts, reps: int = 3):
     """The refinement of the step's 16 starts by both solvers on one handle:
     time per call (after one untimed call each) and how far apart the refined
@@ -501,7 +516,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["achieved_GBps"], "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": d["achieved_GBps"] / HBM_PEAK_GBPS,
                      "traffic": counter_traffic(dom, p.n) if d["rotations_per_launch"] == 32 else None,
-                     "algorithmic_bytes_per_launch": d["algorithmic_bytes_per_launch"]},
+                     "algorithmic_bytes_per_launch": d["algorithmic_bytes_per_launch"],
+                     "note": "per-launch time in the timed region, where the two lanes' passes share the GPU; "
+                             "'isolated' times the same launch alone"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)) * 1e3, "p99": float(np.percentile(lat, 99)) * 1e3,
                        "mode": "serial, one request at a time"},
         "score_phase": {"ms_per_step": score_s * 1e3, "rotations_per_s": M / score_s,
@@ -515,6 +532,11 @@ def main():
                    "best_J": float(np.min(info["J"]))},
     }
     print("bench: timed steps done", file=sys.stderr, flush=True)
+    iso = isolated_launches(rd, torch, p, (V, F, T, P, Q))
+    if dom in iso:
+        a_iso = d["algorithmic_bytes_per_launch"] / (iso[dom] / 1e3) / 1e9
+        out["roofline"]["isolated"] = {"avg_launch_ms": iso[dom], "achieved": a_iso, "frac": a_iso / HBM_PEAK_GBPS,
+                                       "all_passes_ms": iso}
     if args.local > 0:
         out["local_search"] = local_search_bench(rd, torch, p, args)
         print("bench: local search done", file=sys.stderr, flush=True)
