@@ -1069,14 +1069,14 @@ int register_linear_edge(const float* vertices, int32_t n_vertices, const reg_pr
     const double need = no + ns - 1.0;
     *needed = need > 2147483647.0 ? 2147483647 : (int32_t)need;
     *edge = 0;
-    static const int edges[] = {16, 32, 48, 60, 64, 80, 96, 120, 128, 160};
-    for (int n : edges)
-        if (canvas_supported(n) && n >= need) {
+    constexpr int kMaxEdge = 1024;  // above every supported edge
+    for (int n = (int)std::min(need, (double)kMaxEdge + 1); n <= kMaxEdge; ++n)
+        if (canvas_supported(n)) {
             *edge = n;
             break;
         }
     if (*edge == 0)
-        return fail(REG_ENOTSUP, "the linear correlation needs a canvas edge >= %d; the largest supported is 160",
+        return fail(REG_ENOTSUP, "the linear correlation needs a canvas edge >= %d, above every supported edge",
                     (int)*needed);
     return REG_OK;
 }
