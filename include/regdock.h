@@ -367,7 +367,8 @@ typedef struct {
     reg_grid_spec grid;
     reg_params params;          /* zero fields take the defaults */
     int32_t top_k;              /* peaks kept, 1..16 (0: 16) */
-    int32_t refine;             /* 1: refine the top_k peaks */
+    int32_t refine;             /* 0: no refinement; 1: the top_k peaks by Gauss-Newton (refine_se3);
+                                   2: by L-BFGS-B (refine_se3_lbfgsb); other values: REG_EINVAL */
 } reg_request;
 
 typedef struct {

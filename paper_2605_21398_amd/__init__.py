@@ -403,7 +403,11 @@ class Server:
 
     def submit(self, vertices, faces, touchable, poses, so3, n: int, h_mm: float, center=(0.0, 0.0, 0.0),
                radius_mm: float = 0.5, length_mm: float = 8.0, object_id: int = -1, top_k: int = 16,
-               refine: bool = True, params: dict | None = None) -> int:
+               refine=True, params: dict | None = None) -> int:
+        """refine: False (none), True or "gn" (Gauss-Newton), "lbfgsb" (L-BFGS-B)."""
+        mode = {False: 0, True: 1, "gn": 1, "lbfgsb": 2}.get(refine)
+        if mode is None:
+            raise ValueError(f"unknown refine mode {refine!r}")
         V = np.ascontiguousarray(vertices, dtype=np.float32)
         F = np.ascontiguousarray(faces, dtype=np.int32)
         T = None if touchable is None else np.ascontiguousarray(touchable, dtype=np.uint8)
@@ -416,7 +420,7 @@ class Server:
         rq = reg_request(reg_mesh(hp(V), V.shape[0], hp(F), F.shape[0], hp(T)), object_id,
                          reg_probe(radius_mm, length_mm), hp(P), P.shape[0], hp(Q), Q.shape[0],
                          reg_grid_spec(n, h_mm, (ctypes.c_double * 3)(*[float(c) for c in center])), prm, top_k,
-                         1 if refine else 0)
+                         mode)
         t = ctypes.c_uint64()
         _server_check(load_library().register_submit(self.ptr, ctypes.byref(rq), ctypes.byref(t)))
         return t.value

@@ -201,7 +201,7 @@ int reg_server::run_gpu(Job& j, hipStream_t s) {
     if (j.refine) {
         if (hipMemcpyAsync(dInit, r.top_pose, (size_t)K * 56, hipMemcpyHostToDevice, s) != hipSuccess)
             return sfail(REG_EDEVICE, "start copy failed");
-        rc = refine_se3(h, dInit, K, dOut, dJ, nullptr);
+        rc = j.refine == 2 ? refine_se3_lbfgsb(h, dInit, K, dOut, dJ, nullptr) : refine_se3(h, dInit, K, dOut, dJ, nullptr);
         if (rc) return sfail(rc, regdock_rt::last_error());
         if (hipMemcpyAsync(r.refined_pose, dOut, (size_t)K * 56, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipMemcpyAsync(r.refined_J, dJ, (size_t)K * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -339,6 +339,7 @@ int register_submit(reg_server* s, const reg_request* rq, reg_ticket* out) {
         rq->n_rot < 1)
         return sfail(REG_EINVAL, "request needs a mesh, >= 1 pose and >= 1 rotation");
     if (rq->top_k < 0 || rq->top_k > 16) return sfail(REG_EINVAL, "top_k must be in [0, 16]");
+    if (rq->refine < 0 || rq->refine > 2) return sfail(REG_EINVAL, "refine must be 0, 1 or 2");
     auto j = std::make_shared<Job>();
     j->vertices.assign(m.vertices, m.vertices + 3 * (size_t)m.n_vertices);
     j->faces.assign(m.faces, m.faces + 3 * (size_t)m.n_faces);

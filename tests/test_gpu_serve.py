@@ -81,6 +81,30 @@ def test_server_matches_the_direct_path():
     assert np.array_equal(r["refined_J"], J.cpu().numpy())
 
 
+def test_server_lbfgsb_refinement_matches_the_direct_path():
+    """A request may ask for the paper's solver (refine = 2): the served
+    result equals refine_se3_lbfgsb on a handle of its own, bit for bit."""
+    rd = _lib()
+    p = _problems(1)[0]
+    srv = rd.Server(max_inflight=2)
+    try:
+        r = srv.wait(_submit(srv, p, refine="lbfgsb"))
+        with pytest.raises(ValueError):
+            _submit(srv, p, refine="newton")
+    finally:
+        srv.close()
+    h = rd.register_init(p.vertices, p.faces, p.touchable, p.poses, p.so3, p.n, p.h, p.center, p.radius, p.length)
+    try:
+        sc, _, po = rd.score_rotations(h, shift=False)
+        top = rd.register_top_k(h, sc, 16).cpu().numpy()
+        starts = po.cpu().numpy()[top]
+        out, J, _ = rd.refine_se3(h, starts, solver="lbfgsb")
+    finally:
+        rd.register_free(h)
+    assert np.array_equal(r["refined_pose"], out.cpu().numpy())
+    assert np.array_equal(r["refined_J"], J.cpu().numpy())
+
+
 def test_object_cache_hit_gives_the_same_result():
     rd = _lib()
     p = _problems(1)[0]
