@@ -409,7 +409,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}); the search shards by rotation "
-              "range across GPUs, which this build does not launch.", file=sys.stderr)
+              "range across GPUs, which this benchmark does not launch.", file=sys.stderr)
         sys.exit(2)
 
     work = generate(args)
