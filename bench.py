@@ -466,6 +466,7 @@ def main():
         info["starts"] = starts.cpu().numpy()
         info["iters"] = res[2].cpu().numpy()
         info["J"] = res[1].cpu().numpy()
+        info["refined"] = res[0].cpu().numpy()
         info.update(rd.register_refine_stats(h))
         rd.register_free(h)
         return sc, top
@@ -531,6 +532,13 @@ def main():
                    "evaluations": info["evaluations"], "accepted_steps": [int(x) for x in info["iters"]],
                    "best_J": float(np.min(info["J"]))},
     }
+    # pose error against the synthetic ground truth: the best search peak and
+    # the refined start of least J (the paper's Table II stages)
+    g_ang, g_mm = _pose_errors(p, info["starts"][0])
+    r_ang, r_mm = _pose_errors(p, info["refined"][int(np.argmin(info["J"]))])
+    out["accuracy"] = {"search_best": {"deg": g_ang, "mm": g_mm}, "refined_best_J": {"deg": r_ang, "mm": r_mm},
+                       "note": "anchor displacement (mm) and rotation angle (deg) from the ground-truth pose; "
+                               "the probe poses carry 0.05 mm / 0.2 deg noise"}
     print("bench: timed steps done", file=sys.stderr, flush=True)
     iso = isolated_launches(rd, torch, p, (V, F, T, P, Q))
     if dom in iso:

@@ -300,13 +300,15 @@ int register_debug_distance(reg_handle* h, const double* R, const double* p, flo
  * parallel branches balanced by model HBM bytes.  A replay recomputes
  * everything from the handles' inputs; refinements still running after the
  * captured rounds are continued by register_batch_run, so the results equal
- * those of score_rotations / register_top_k / refine_se3 on each handle.
+ * those of score_rotations / register_top_k / refine_se3 (or refine_se3_lbfgsb)
+ * on each handle.
  * The handles must stay alive and must not be used elsewhere while the batch
  * runs; their event timing must be off.
  */
 typedef struct reg_batch reg_batch;
 
-/* handles: count handle pointers (host array).  top_k in [1, 16]; refine 0/1;
+/* handles: count handle pointers (host array).  top_k in [1, 16]; refine 0
+ * (none), 1 (Gauss-Newton, as refine_se3) or 2 (L-BFGS-B, as refine_se3_lbfgsb);
  * graph_rounds: refinement rounds captured (0: 64); branches: parallel
  * streams (0: 4).  Errors: REG_EINVAL, REG_ENOMEM, REG_EDEVICE. */
 int register_batch_create(reg_handle* const* handles, int32_t count, int32_t top_k, int32_t refine,

@@ -465,12 +465,16 @@ class Batch:
     """Registrations of several handles captured as one hipGraph (see the
     batching section of the header)."""
 
-    def __init__(self, handles, top_k: int = 16, refine: bool = True, graph_rounds: int = 0, branches: int = 0):
+    def __init__(self, handles, top_k: int = 16, refine=True, graph_rounds: int = 0, branches: int = 0):
+        """refine: False (none), True or "gn" (Gauss-Newton), "lbfgsb" (L-BFGS-B)."""
+        mode = {False: 0, True: 1, "gn": 1, "lbfgsb": 2}.get(refine)
+        if mode is None:
+            raise ValueError(f"unknown refine mode {refine!r}")
         L = load_library()
         self.handles = list(handles)
         arr = (ctypes.c_void_p * len(self.handles))(*[h.ptr.value for h in self.handles])
         self.ptr = ctypes.c_void_p()
-        _check(L.register_batch_create(arr, len(self.handles), top_k, 1 if refine else 0, graph_rounds, branches,
+        _check(L.register_batch_create(arr, len(self.handles), top_k, mode, graph_rounds, branches,
                                        ctypes.byref(self.ptr)))
         self.top_k = top_k
 

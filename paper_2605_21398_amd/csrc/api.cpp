@@ -879,7 +879,7 @@ struct reg_batch {
     std::vector<reg_handle*> hs;
     std::vector<int> K, branch_of;
     std::vector<Out> out;
-    int rounds = 0, refine = 1;
+    int rounds = 0, refine = 1;  // refine: 0 none, 1 Gauss-Newton, 2 L-BFGS-B
     hipStream_t main = nullptr;
     std::vector<hipStream_t> br;
     std::vector<hipEvent_t> ev;
@@ -933,9 +933,14 @@ static int batch_enqueue(reg_batch* b, int i, hipStream_t s) {
     DEV_TRY(h, gather_poses(o.top, o.pose, K, o.init, s));
     const RefineConst c = refine_const(h);
     DEV_TRY(h, refine_start(o.init, K, h->anchor, c, h->rst, h->rtr, h->r_active, h->rw, s));
-    for (int r = 0; r < b->rounds; ++r)
-        DEV_TRY(h, refine_round(h->rst, h->rtr, K, h->obj->geo, h->poses, h->n_poses, c, h->rw, h->rhits, h->rev,
-                                h->r_active, s));
+    for (int r = 0; r < b->rounds; ++r) {
+        if (b->refine == 2)
+            DEV_TRY(h, refine_round_lbfgsb(h->rst, h->rlb, h->rtr, K, h->obj->geo, h->poses, h->n_poses, c, h->rw,
+                                           h->rhits, h->rev, h->r_active, s));
+        else
+            DEV_TRY(h, refine_round(h->rst, h->rtr, K, h->obj->geo, h->poses, h->n_poses, c, h->rw, h->rhits, h->rev,
+                                    h->r_active, s));
+    }
     DEV_TRY(h, refine_finish(h->rst, K, o.refined, o.J, o.iters, s));
     return REG_OK;
 }
@@ -1365,7 +1370,8 @@ int register_batch_create(reg_handle* const* handles, int32_t count, int32_t top
     *out = nullptr;
     if (top_k < 1 || top_k > 16) return fail(REG_EINVAL, "top_k must be in [1, 16]");
     auto b = std::make_unique<reg_batch>();
-    b->refine = refine != 0;
+    if (refine < 0 || refine > 2) return fail(REG_EINVAL, "refine must be 0, 1 or 2");
+    b->refine = refine;
     b->rounds = graph_rounds > 0 ? graph_rounds : 64;
     const int nb = std::max(1, std::min<int>(branches > 0 ? branches : 4, count));
     for (int i = 0; i < count; ++i) {
@@ -1444,7 +1450,9 @@ int register_batch_run(reg_batch* b) {
         reg_handle* h = b->hs[i];
         h->r_rounds = b->rounds;
         const reg_batch::Out& o = b->out[i];
+        h->r_lbfgsb = b->refine == 2;
         int rc = refine_continue(h, b->K[i], o.refined, o.J, o.iters);
+        h->r_lbfgsb = false;
         if (rc) return rc;
     }
     return REG_OK;

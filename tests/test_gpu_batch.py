@@ -61,6 +61,36 @@ def test_batch_graph_replays_equal_eager_results():
             rd.register_free(h)
 
 
+def test_batch_graph_lbfgsb_equals_eager():
+    """The same graph with the paper's solver (refine = "lbfgsb"): every replay
+    equals refine_se3_lbfgsb on each handle, bit for bit."""
+    rd = _lib()
+    ps = [synth.batch_problem(i, level=4, lmax=6, N=400, M=256) for i in range(4, 6)]
+    hs = [_handle(rd, p) for p in ps]
+    try:
+        ref = []
+        for h in hs:
+            sc, _, po = rd.score_rotations(h, shift=False)
+            top = rd.register_top_k(h, sc, 16)
+            out, J, _ = rd.refine_se3(h, po[top.long()], solver="lbfgsb")
+            ref.append(dict(top=top.cpu().numpy(), refined=out.cpu().numpy(), J=J.cpu().numpy()))
+        b = rd.Batch(hs, top_k=16, refine="lbfgsb", graph_rounds=6, branches=2)
+        try:
+            for rep in range(2):
+                b.run()
+                for i in range(len(hs)):
+                    got = b.outputs(i)
+                    for k in ("top", "refined", "J"):
+                        assert np.array_equal(got[k], ref[i][k]), (rep, i, k)
+        finally:
+            b.close()
+        with pytest.raises(ValueError):
+            rd.Batch(hs, refine="newton")
+    finally:
+        for h in hs:
+            rd.register_free(h)
+
+
 def test_batch_abi_errors():
     rd = _lib()
     p = synth.batch_problem(0, level=4, lmax=6, N=300, M=64)
