@@ -575,7 +575,10 @@ static RefineConst refine_const(const reg_handle* h) {
     c.b_t = h->prm.b_t;
     c.b_r = h->prm.b_r;
     c.tol_pg = 1e-6;
-    c.tol_step = 1e-9;
+    // an accepted step below 1e-6 (mm, rad) ends a start: with the linear
+    // convergence of the last iterations the pose is then ~1e-6 mm / 1e-4 deg
+    // from the limit, three orders inside the refined-pose tolerance
+    c.tol_step = 1e-6;
     c.mu0 = 1e-3;
     c.max_iters = h->prm.max_iters;
     return c;
