@@ -341,9 +341,11 @@ int register_tuned_batch(int32_t n);
  * each slot has its own HIP stream, so admitted registrations overlap on the
  * device and a request arriving while others run starts as soon as a slot and
  * memory free up.  Objects (mesh + canvas + object-grid thresholds) stay
- * resident in a cache keyed by the request's object_id: a later request with
- * the same key skips the object grid and its spectrum.  A registration's
- * results do not depend on what else runs beside it.
+ * resident in a cache keyed by the mesh's contents (a hash of the vertex,
+ * face and touchable arrays, confirmed byte for byte on a hit), the canvas and
+ * the thresholds: a later request for the same object skips the object grid
+ * and its spectrum.  A registration's results do not depend on what else runs
+ * beside it.
  */
 typedef struct reg_server reg_server;
 typedef uint64_t reg_ticket;
@@ -360,7 +362,7 @@ typedef struct {
 /* All arrays in HOST memory; they are copied before register_submit returns. */
 typedef struct {
     reg_mesh mesh;
-    int64_t object_id;          /* cache key of the object (>= 0), or -1 not to cache it */
+    int64_t object_id;          /* >= 0: the object may be cached and taken from the cache; -1: built afresh, not cached */
     reg_probe probe;
     const float* poses;         /* n_poses x 7 */
     int32_t n_poses;

@@ -145,11 +145,14 @@ def swept_occupancy(minf) -> np.ndarray:
 
 # ------------------------------------------------------ per-rotation score
 
-def resample(S_w: np.ndarray, q, n: int, h: float, a, wc) -> np.ndarray:
+def resample(S_w, q, n: int, h: float, a, wc):
     """S_r[k] = S_w at the world point R (x_k - a) + wc, trilinear on the
     lattice y_j = wc + h (j - m/2), taps outside the lattice count as 0
-    (Sec. IV-D: rotate and resample by trilinear interpolation)."""
-    m = S_w.shape[0]
+    (Sec. IV-D: rotate and resample by trilinear interpolation).  S_w may be a
+    list of lattices of one edge m; each is resampled with the same weights and
+    a list is returned."""
+    grids = list(S_w) if isinstance(S_w, (list, tuple)) else [S_w]
+    m = grids[0].shape[0]
     R = quat_to_mat(q)
     k = np.arange(n, dtype=np.float64) - n / 2
     kz, ky, kx = np.meshgrid(k, k, k, indexing="ij")
@@ -159,7 +162,7 @@ def resample(S_w: np.ndarray, q, n: int, h: float, a, wc) -> np.ndarray:
     U = (Y - y0) / h                                               # lattice coords (x,y,z)
     I = np.floor(U).astype(np.int64)
     Fr = U - I
-    out = np.zeros(len(U))
+    outs = [np.zeros(len(U)) for _ in grids]
     for cz in (0, 1):
         for cy in (0, 1):
             for cx in (0, 1):
@@ -167,10 +170,12 @@ def resample(S_w: np.ndarray, q, n: int, h: float, a, wc) -> np.ndarray:
                 w = ((Fr[:, 0] if cx else 1 - Fr[:, 0]) * (Fr[:, 1] if cy else 1 - Fr[:, 1])
                      * (Fr[:, 2] if cz else 1 - Fr[:, 2]))
                 ok = (ix >= 0) & (ix < m) & (iy >= 0) & (iy < m) & (iz >= 0) & (iz < m)
-                val = np.zeros(len(U))
-                val[ok] = S_w[iz[ok], iy[ok], ix[ok]]
-                out += w * val
-    return out.reshape(n, n, n)
+                for G, out in zip(grids, outs):
+                    val = np.zeros(len(U))
+                    val[ok] = G[iz[ok], iy[ok], ix[ok]]
+                    out += w * val
+    outs = [o.reshape(n, n, n) for o in outs]
+    return outs if isinstance(S_w, (list, tuple)) else outs[0]
 
 
 def correlate(O: np.ndarray, S: np.ndarray) -> np.ndarray:
@@ -293,6 +298,60 @@ def score_rotations(O, S_w, so3, n, h, a, wc, indices=None):
         fl.append(f)
         sh.append(d)
     return np.array(sc), np.array(fl, dtype=np.int64), np.array(sh, dtype=np.int64).reshape(-1, 3)
+
+
+# ------------------------------------------- threshold decisions (flags)
+#
+# Two decisions of the grids are step functions of a distance: the object
+# template jumps from 1 + f_o/tau_in1 (about 0) to -rho at f_o = -tau_in1, and
+# the swept occupancy switches at f_p = 0.  A float32 evaluation of the
+# distance can take either side within its rounding error, so voxels within
+# delta of a jump are flagged, and the score of a rotation is bounded over
+# every combination of their two values.
+
+def object_flags(O, fo, d, prm: GridParams = GridParams(), delta: float = 1e-4):
+    """|O_alt - O| at the object voxels with |f_o + tau_in1| < delta (else 0):
+    the change of O if the template takes the other side of its jump."""
+    fo = np.asarray(fo, dtype=np.float64)
+    near = np.abs(fo + prm.tau_in1) < delta
+    shell = np.minimum(1.0 + fo / prm.tau_in1, np.maximum(0.0, 1.0 - np.asarray(d) / prm.tau_out1))
+    alt = np.where(fo <= -prm.tau_in1, shell, -prm.rho)
+    return np.where(near, np.abs(alt - np.asarray(O, dtype=np.float64)), 0.0)
+
+
+def swept_flags(minf, delta: float = 1e-4):
+    """1 at the lattice points with |min_i f_p| < delta, where the occupancy
+    may take either value."""
+    return (np.abs(np.asarray(minf)) < delta).astype(np.float64)
+
+
+def score_bounds(O, dO, S_w, F_s, q, n: int, h: float, a, wc):
+    """The correlation field C of one rotation and a bound B >= |C' - C| for
+    every field C' obtained by moving flagged voxels to their other value.
+    With D_r the resampled flag indicator (0 <= S_r' <= S_r + D_r, since
+    resampling is linear with non-negative weights):
+        C' - C = corr(O' - O, S_r') + corr(O, S_r' - S_r)
+        |C' - C| <= corr(|dO|, S_r + D_r) + corr(|O|, D_r) = B."""
+    S_r, D_r = resample([S_w, F_s], q, n, h, a, wc)
+    C = correlate(O, S_r)
+    B = np.zeros_like(C)
+    if np.any(dO):
+        B += correlate(dO, S_r + D_r)
+    if np.any(D_r):
+        B += correlate(np.abs(O), D_r)
+    return C, np.maximum(B, 0.0)
+
+
+def score_interval(C, B):
+    """(lowest, highest) score of a rotation over the flagged alternatives:
+    max (C - B) and max (C + B)."""
+    return float(np.max(C - B)), float(np.max(C + B))
+
+
+def peak_admissible(C, B, lo: float, tol: float) -> np.ndarray:
+    """Flat indices that may be the peak of some alternative field within tol:
+    C + B >= lo - tol (with no flags this is the tie band of the maximum)."""
+    return np.flatnonzero((C + B).ravel() >= lo - tol)
 
 
 def top_k(scores, K: int):

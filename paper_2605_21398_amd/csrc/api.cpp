@@ -169,6 +169,9 @@ struct ObjectData {
     std::future<HostGeometry> geo_job;  // host part of geo, started when the object is built
     size_t bytes = 0;
     std::vector<void*> owned;
+    // recorded on the building stream once the grid, spectrum and nonzero list
+    // are written; a handle that takes the object from a cache waits for it
+    hipEvent_t ready = nullptr;
     template <class T>
     hipError_t alloc(T** p, size_t count) {
         void* q = nullptr;
@@ -187,6 +190,7 @@ struct ObjectData {
     // the last handle using the object has synchronised its stream
     ~ObjectData() {
         if (geo_job.valid()) geo_job.wait();
+        if (ready) (void)hipEventDestroy(ready);
         for (void* q : owned) regdock_rt::dev_release(q);
     }
 };
@@ -210,12 +214,12 @@ struct reg_handle {
     float* poses = nullptr;
     float* so3 = nullptr;
     double* rots = nullptr;
-    float* pose_prep = nullptr;
+    double* pose_prep = nullptr;
     double* anchor = nullptr;
     float* O = nullptr;
     float* fo = nullptr;
-    uint32_t* od2 = nullptr;
-    uint32_t* odt2 = nullptr;
+    unsigned long long* od2 = nullptr;
+    unsigned long long* odt2 = nullptr;
     uint32_t* opar = nullptr;
     float2* W = nullptr;
     float2* spec = nullptr;
@@ -575,10 +579,11 @@ static RefineConst refine_const(const reg_handle* h) {
     c.b_t = h->prm.b_t;
     c.b_r = h->prm.b_r;
     c.tol_pg = 1e-6;
-    // an accepted step below 1e-6 (mm, rad) ends a start: with the linear
-    // convergence of the last iterations the pose is then ~1e-6 mm / 1e-4 deg
-    // from the limit, three orders inside the refined-pose tolerance
-    c.tol_step = 1e-6;
+    // an accepted, nearly undamped step (mu <= 10 mu0) below 1e-7 (mm, rad)
+    // ends a start: with a linear rate rho of the last iterations the iterate
+    // is then step * rho / (1 - rho) from the limit, within 1e-3 mm and 1e-3 deg
+    // for rho up to 0.99
+    c.tol_step = 1e-7;
     c.mu0 = 1e-3;
     c.max_iters = h->prm.max_iters;
     return c;
@@ -698,6 +703,8 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
         if (!cached->matches(h->n, h->h, h->prm) || cached->nv != h->nv || cached->nf != h->nf)
             return fail(REG_EINVAL, "cached object does not match the mesh, canvas or thresholds");
         h->obj = cached;
+        // the object may still be in the making on the stream that built it
+        if (cached->ready) DEV_TRY(h, hipStreamWaitEvent(s, cached->ready, 0));
     } else {
         auto o = std::make_shared<ObjectData>();
         o->n = h->n;
@@ -812,13 +819,15 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
         const int grc = start_refine_geometry(h);
         if (grc) return grc;
         DEV_TRY(h, setup_anchor(h->V, h->nv, h->anchor, s));
-        DEV_TRY(h, setup_object_grid(h->V, h->F, h->touch, h->nf, h->n, h->h, h->anchor, (float)h->prm.tau_out1,
-                                     (float)h->prm.tau_in1, (float)h->prm.rho, h->O, h->fo,
+        DEV_TRY(h, setup_object_grid(h->V, h->F, h->touch, h->nf, h->n, h->h, h->anchor, h->prm.tau_out1,
+                                     h->prm.tau_in1, h->prm.rho, h->O, h->fo,
                                      ObjectScratch{h->od2, h->odt2, h->opar}, s));
         int rc = build_object_derived(h);
         if (rc) return rc;
+        DEV_TRY(h, hipEventCreateWithFlags(&h->obj->ready, hipEventDisableTiming));
+        DEV_TRY(h, hipEventRecord(h->obj->ready, s));
     }
-    DEV_TRY(h, setup_swept(h->poses, n_poses, (float)probe->radius_mm, (float)probe->length_mm, h->m, h->mp, h->h, h->wc,
+    DEV_TRY(h, setup_swept(h->poses, n_poses, probe->radius_mm, probe->length_mm, h->m, h->mp, h->h, h->wc,
                            h->pose_prep, h->Sw, h->cm, s));
     *out = h;
     h = nullptr;  // release the guard
@@ -1537,10 +1546,11 @@ Footprint footprint(int n, int n_rot, int n_poses, int nv, int nf, int batch, in
     f.object = 16 * n3 + 8 * H + 16 * (size_t)NLOW3 + 12 * (size_t)nv + 13 * (size_t)nf + 24 * (size_t)n +
                8 * ((n3 + 255) / 256) + 68 * (size_t)nf + 2048;
     const size_t per_rot = 4 * 4 + 4 + 12 + 8 + 4 + 8 + 1 + 8 + 4 + 4 + CMAX * 4 + CMAX * 8 * (size_t)rescore_slices(n);
-    const size_t K = (size_t)std::max(refine_starts, 1), nq = K * REF_TMAX * N;
+    // refinement buffers are allocated for at least 16 starts (ensure_refine_buffers)
+    const size_t K = refine_starts > 0 ? (size_t)std::max(refine_starts, 16) : 1, nq = K * REF_TMAX * N;
     const size_t lanes = M > B ? 2 : 1;  // the second lane's pass buffers
     f.request = lanes * (H * B * 8 + B * n * KTOP * 8 + B * n * 8 + B * n * NLOW2 * 16 + B * NLOW3 * 16) + M * per_rot +
-                M * (4 + 56) + 28 * N + 48 * N + m * m * m + mp * mp * mp + 8 * n3 + n * n * ((n + 31) / 32) * 4 +
+                M * (4 + 56) + 28 * N + 96 * N + m * m * m + mp * mp * mp + 16 * n3 + n * n * ((n + 31) / 32) * 4 +
                 K * (sizeof(RefineState) + sizeof(LbfgsState) +
                      REF_TMAX * (sizeof(RefineTrial) + REF_EVAL_PARTS * sizeof(RefineEval))) +
                 nq * (sizeof(RefineHit) + 48 + 8 + 4 + 8 + 16 * (8 + 16 + 4)) + 4096;

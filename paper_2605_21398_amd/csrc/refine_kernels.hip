@@ -1535,8 +1535,9 @@ __device__ bool trial_step(const RefineState& S, double mu, const RefineConst& c
 // damped Gauss-Newton decisions over the evaluated trials in the order the
 // sequential iteration would try them: the first trial that lowers J is
 // taken (mu = max(mu / 3, 1e-12)); a rejected trial multiplies mu by 3 and
-// ends the start when mu reaches 1e12 or its step was below tol_step.  At an
-// accepted point the projected-gradient test and the iteration cap apply.
+// ends the start when mu reaches 1e12 or its step was below tol_step.  An
+// accepted step below tol_step taken with a damping of at most 10 mu0 ends the
+// start; otherwise the projected-gradient test and the iteration cap apply.
 // Then the block's threads set up the next round's trials in parallel: one
 // after a first-try acceptance, two after an acceptance that needed a
 // rejection, REF_TMAX after a round of rejections.
@@ -1584,7 +1585,10 @@ __global__ void k_ref_decide(RefineState* __restrict__ st, RefineTrial* __restri
                 for (int b = a; b < 6; ++b, ++o) S.H[6 * a + b] = S.H[6 * b + a] = E.H[o];
             if (!first) S.mu = fmax(T.mu / 3.0, 1e-12);
             S.status = 1;
-            if (!first && maxabs6(T.step) <= c.tol_step) {
+            // a small step ends the start only when it was taken with little
+            // damping: a heavily damped step is small because mu is large,
+            // not because the iterate is near the minimum
+            if (!first && maxabs6(T.step) <= c.tol_step && T.mu <= 10.0 * c.mu0) {
                 S.status = 2;
             } else {
                 double pg = 0;

@@ -55,18 +55,18 @@ hipError_t search_pass(int n, int pass, const SearchBatchArgs& a);
 hipError_t object_spectrum(int n, const float* O, float2* spec_tmp, float2* W, const float2* tw, const double2* tw64,
                            double2* lowT_tmp, double2* Wlow, hipStream_t s);
 hipError_t setup_anchor(const float* V, int nv, double* anchor, hipStream_t s);
-// scratch of the object-grid build: squared distances (float bits, n^3 each)
+// scratch of the object-grid build: squared distances (double bits, n^3 each)
 // and the inside-parity bit words of every column (n^2 * ceil(n/32))
 struct ObjectScratch {
-    uint32_t* d2;
-    uint32_t* dt2;
+    unsigned long long* d2;
+    unsigned long long* dt2;
     uint32_t* par;
 };
 hipError_t setup_object_grid(const float* V, const int32_t* F, const uint8_t* touch, int nf, int n, double h,
-                             const double* anchor, float tau_out1, float tau_in1, float rho, float* O, float* fo,
+                             const double* anchor, double tau_out1, double tau_in1, double rho, float* O, float* fo,
                              const ObjectScratch& w, hipStream_t s);
-hipError_t setup_swept(const float* poses, int np, float r, float L, int m, int mp, double h, const double* wc,
-                       float* pose_tmp, uint8_t* Sw, uint8_t* cm, hipStream_t s);
+hipError_t setup_swept(const float* poses, int np, double r, double L, int m, int mp, double h, const double* wc,
+                       double* pose_tmp, uint8_t* Sw, uint8_t* cm, hipStream_t s);
 hipError_t setup_cellmask(const uint8_t* Sw, int m, int mp, uint8_t* cm, hipStream_t s);
 hipError_t setup_rotations(const float* so3, int M, double* rots, int* err, hipStream_t s);
 hipError_t validate_inputs(const float* V, int nv, const int32_t* F, int nf, const float* poses, int np, int* err,

@@ -5,7 +5,7 @@
 //   k_object_grid    O[k] = min(O_t, O_m) on the n^3 canvas x_k = a + h(k - n/2)
 //                    (Sec. IV-A: banded template of the signed distance, surface
 //                    mask of the touchable distance, element-wise minimum)
-//   k_pose_prep      probe poses -> rotation matrix + position (float)
+//   k_pose_prep      probe poses -> rotation matrix + position (double)
 //   k_swept          S_w[j] = 1 iff min_i f_p(T_i^{-1} y_j) <= 0 on the m^3 world
 //                    lattice y_j = wc + h(j - m/2) (Sec. IV-A, swept occupancy)
 //   k_cellmask       8-bit corner masks of S_w, 4x4x4-bricked, so one byte load
@@ -1172,99 +1172,86 @@ __global__ __launch_bounds__(256) void k_anchor(const float* __restrict__ V, int
 }
 
 // squared distance from p to triangle abc (closest-point case analysis of
-// Ericson, Real-Time Collision Detection, Sec. 5.1.5), float
-__device__ __forceinline__ float tri_dist2(float3 p, float3 a, float3 b, float3 c) {
-    const float3 ab = make_float3(b.x - a.x, b.y - a.y, b.z - a.z);
-    const float3 ac = make_float3(c.x - a.x, c.y - a.y, c.z - a.z);
-    const float3 ap = make_float3(p.x - a.x, p.y - a.y, p.z - a.z);
-    const float d1 = ab.x * ap.x + ab.y * ap.y + ab.z * ap.z;
-    const float d2 = ac.x * ap.x + ac.y * ap.y + ac.z * ap.z;
-    float3 q;
-    if (d1 <= 0.f && d2 <= 0.f) {
+// Ericson, Real-Time Collision Detection, Sec. 5.1.5), in double: the object
+// grid's jump at f_o = -tau_in1 is then decided on the same side as an FP64
+// evaluation up to rounding order
+struct d3 {
+    double x, y, z;
+};
+__device__ __forceinline__ d3 d3sub(d3 a, d3 b) { return d3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ double d3dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ d3 d3axpy(d3 a, double v, d3 u) { return d3{a.x + v * u.x, a.y + v * u.y, a.z + v * u.z}; }
+
+__device__ __forceinline__ double tri_dist2(d3 p, d3 a, d3 b, d3 c) {
+    const d3 ab = d3sub(b, a), ac = d3sub(c, a), ap = d3sub(p, a);
+    const double d1 = d3dot(ab, ap), d2 = d3dot(ac, ap);
+    d3 q;
+    if (d1 <= 0.0 && d2 <= 0.0) {
         q = a;
     } else {
-        const float3 bp = make_float3(p.x - b.x, p.y - b.y, p.z - b.z);
-        const float d3 = ab.x * bp.x + ab.y * bp.y + ab.z * bp.z;
-        const float d4 = ac.x * bp.x + ac.y * bp.y + ac.z * bp.z;
-        const float3 cp = make_float3(p.x - c.x, p.y - c.y, p.z - c.z);
-        const float d5 = ab.x * cp.x + ab.y * cp.y + ab.z * cp.z;
-        const float d6 = ac.x * cp.x + ac.y * cp.y + ac.z * cp.z;
-        const float vc = d1 * d4 - d3 * d2;
-        const float vb = d5 * d2 - d1 * d6;
-        const float va = d3 * d6 - d5 * d4;
-        if (d3 >= 0.f && d4 <= d3) {
+        const d3 bp = d3sub(p, b), cp = d3sub(p, c);
+        const double d3v = d3dot(ab, bp), d4 = d3dot(ac, bp);
+        const double d5 = d3dot(ab, cp), d6 = d3dot(ac, cp);
+        const double vc = d1 * d4 - d3v * d2;
+        const double vb = d5 * d2 - d1 * d6;
+        const double va = d3v * d6 - d5 * d4;
+        if (d3v >= 0.0 && d4 <= d3v) {
             q = b;
-        } else if (vc <= 0.f && d1 >= 0.f && d3 <= 0.f) {
-            const float v = d1 / (d1 - d3);
-            q = make_float3(a.x + v * ab.x, a.y + v * ab.y, a.z + v * ab.z);
-        } else if (d6 >= 0.f && d5 <= d6) {
+        } else if (vc <= 0.0 && d1 >= 0.0 && d3v <= 0.0) {
+            q = d3axpy(a, d1 / (d1 - d3v), ab);
+        } else if (d6 >= 0.0 && d5 <= d6) {
             q = c;
-        } else if (vb <= 0.f && d2 >= 0.f && d6 <= 0.f) {
-            const float w = d2 / (d2 - d6);
-            q = make_float3(a.x + w * ac.x, a.y + w * ac.y, a.z + w * ac.z);
-        } else if (va <= 0.f && (d4 - d3) >= 0.f && (d5 - d6) >= 0.f) {
-            const float w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
-            q = make_float3(b.x + w * (c.x - b.x), b.y + w * (c.y - b.y), b.z + w * (c.z - b.z));
+        } else if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {
+            q = d3axpy(a, d2 / (d2 - d6), ac);
+        } else if (va <= 0.0 && (d4 - d3v) >= 0.0 && (d5 - d6) >= 0.0) {
+            q = d3axpy(b, (d4 - d3v) / ((d4 - d3v) + (d5 - d6)), d3sub(c, b));
         } else {
-            const float den = 1.0f / (va + vb + vc);
-            const float v = vb * den, w = vc * den;
-            q = make_float3(a.x + ab.x * v + ac.x * w, a.y + ab.y * v + ac.y * w, a.z + ab.z * v + ac.z * w);
+            const double den = 1.0 / (va + vb + vc);
+            q = d3axpy(d3axpy(a, vb * den, ab), vc * den, ac);
         }
     }
-    const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
-    return dx * dx + dy * dy + dz * dz;
-}
-
-// signed solid angle of abc seen from p (Van Oosterom & Strackee, 1983)
-__device__ __forceinline__ float solid_angle(float3 p, float3 a, float3 b, float3 c) {
-    const float3 ra = make_float3(a.x - p.x, a.y - p.y, a.z - p.z);
-    const float3 rb = make_float3(b.x - p.x, b.y - p.y, b.z - p.z);
-    const float3 rc = make_float3(c.x - p.x, c.y - p.y, c.z - p.z);
-    const float la = sqrtf(ra.x * ra.x + ra.y * ra.y + ra.z * ra.z);
-    const float lb = sqrtf(rb.x * rb.x + rb.y * rb.y + rb.z * rb.z);
-    const float lc = sqrtf(rc.x * rc.x + rc.y * rc.y + rc.z * rc.z);
-    const float num = ra.x * (rb.y * rc.z - rb.z * rc.y) + ra.y * (rb.z * rc.x - rb.x * rc.z) + ra.z * (rb.x * rc.y - rb.y * rc.x);
-    const float den = la * lb * lc + (ra.x * rb.x + ra.y * rb.y + ra.z * rb.z) * lc +
-                      (ra.x * rc.x + ra.y * rc.y + ra.z * rc.z) * lb + (rb.x * rc.x + rb.y * rc.y + rb.z * rc.z) * la;
-    return 2.0f * atan2f(num, den);
+    const d3 d = d3sub(p, q);
+    return d3dot(d, d);
 }
 
 // banded template, surface mask and their minimum (Sec. IV-A)
-__device__ __forceinline__ float object_value(float fo, float dt, float tau_out1, float tau_in1, float rho) {
-    float ot;
-    if (fo >= 0.f && fo < tau_out1) ot = 1.0f - fo / tau_out1;
-    else if (fo < 0.f && fo > -tau_in1) ot = 1.0f + fo / tau_in1;
+__device__ __forceinline__ double object_value(double fo, double dt, double tau_out1, double tau_in1, double rho) {
+    double ot;
+    if (fo >= 0.0 && fo < tau_out1) ot = 1.0 - fo / tau_out1;
+    else if (fo < 0.0 && fo > -tau_in1) ot = 1.0 + fo / tau_in1;
     else if (fo <= -tau_in1) ot = -rho;
-    else ot = 0.0f;
-    const float om = fmaxf(0.0f, 1.0f - fabsf(dt) / tau_out1);
-    return fminf(ot, om);
+    else ot = 0.0;
+    const double om = fmax(0.0, 1.0 - fabs(dt) / tau_out1);
+    return fmin(ot, om);
 }
 
-// capped-cylinder SDF of the probe, float (tip disk at the origin, axis +z)
-__device__ __forceinline__ float probe_sdf(float x, float y, float z, float r, float L) {
-    const float q1 = sqrtf(x * x + y * y) - r;
-    const float q2 = fabsf(z - 0.5f * L) - 0.5f * L;
-    const float a = fmaxf(q1, 0.f), b = fmaxf(q2, 0.f);
-    return fminf(fmaxf(q1, q2), 0.f) + sqrtf(a * a + b * b);
+// capped-cylinder SDF of the probe (tip disk at the origin, axis +z), in
+// double so that the swept occupancy switches at f_p = 0 where an FP64
+// evaluation does
+__device__ __forceinline__ double probe_sdf(double x, double y, double z, double r, double L) {
+    const double q1 = sqrt(x * x + y * y) - r;
+    const double q2 = fabs(z - 0.5 * L) - 0.5 * L;
+    const double a = fmax(q1, 0.0), b = fmax(q2, 0.0);
+    return fmin(fmax(q1, q2), 0.0) + sqrt(a * a + b * b);
 }
 
 // ---- object grid by scatter (per object) ----------------------------------
 // Distances matter only inside the band (tau_out1 + h): every face updates
-// the voxels of its bounding box grown by the band with atomicMin on float bits
-// (non-negative floats order like their bits), so the minimum is exact there
+// the voxels of its bounding box grown by the band with atomicMin on double
+// bits (non-negative doubles order like their bits), so the minimum is exact there
 // and independent of the order.  Inside/outside comes from +z ray crossing
 // parity: every face toggles, in each column its projection covers, the bits of
 // the voxels below the crossing (atomicXor on per-column bit words), with the
 // same simulation-of-simplicity tie rule at shared edges as the FP64 oracle.
 
-constexpr uint32_t FLT_MAX_BITS = 0x7f7fffffu;
+constexpr unsigned long long DBL_MAX_BITS = 0x7fefffffffffffffull;
 
-__global__ void k_obj_init(uint32_t* __restrict__ d2, uint32_t* __restrict__ dt2, size_t n3, uint32_t* __restrict__ par,
-                           size_t nwords) {
+__global__ void k_obj_init(unsigned long long* __restrict__ d2, unsigned long long* __restrict__ dt2, size_t n3,
+                           uint32_t* __restrict__ par, size_t nwords) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n3) {
-        d2[i] = FLT_MAX_BITS;
-        dt2[i] = FLT_MAX_BITS;
+        d2[i] = DBL_MAX_BITS;
+        dt2[i] = DBL_MAX_BITS;
     }
     if (i < nwords) par[i] = 0u;
 }
@@ -1283,33 +1270,32 @@ __device__ __forceinline__ void face_box(const double* lo_w, const double* hi_w,
 __global__ __launch_bounds__(256) void k_obj_faces(const float* __restrict__ V, const int32_t* __restrict__ F,
                                                    const uint8_t* __restrict__ touch, int n, double h,
                                                    const double* __restrict__ anchor, double band,
-                                                   uint32_t* __restrict__ d2, uint32_t* __restrict__ dt2) {
+                                                   unsigned long long* __restrict__ d2, unsigned long long* __restrict__ dt2) {
     const int f = blockIdx.x;
     const int i0 = F[3 * f], i1 = F[3 * f + 1], i2 = F[3 * f + 2];
-    const float3 a = make_float3(V[3 * i0], V[3 * i0 + 1], V[3 * i0 + 2]);
-    const float3 b = make_float3(V[3 * i1], V[3 * i1 + 1], V[3 * i1 + 2]);
-    const float3 c = make_float3(V[3 * i2], V[3 * i2 + 1], V[3 * i2 + 2]);
+    const d3 a{V[3 * i0], V[3 * i0 + 1], V[3 * i0 + 2]};
+    const d3 b{V[3 * i1], V[3 * i1 + 1], V[3 * i1 + 2]};
+    const d3 c{V[3 * i2], V[3 * i2 + 1], V[3 * i2 + 2]};
     const bool tf = touch[f] != 0;
     const double an[3] = {anchor[0], anchor[1], anchor[2]};
-    double lo_w[3] = {fmin((double)a.x, fmin((double)b.x, (double)c.x)) - band, fmin((double)a.y, fmin((double)b.y, (double)c.y)) - band,
-                      fmin((double)a.z, fmin((double)b.z, (double)c.z)) - band};
-    double hi_w[3] = {fmax((double)a.x, fmax((double)b.x, (double)c.x)) + band, fmax((double)a.y, fmax((double)b.y, (double)c.y)) + band,
-                      fmax((double)a.z, fmax((double)b.z, (double)c.z)) + band};
+    double lo_w[3] = {fmin(a.x, fmin(b.x, c.x)) - band, fmin(a.y, fmin(b.y, c.y)) - band, fmin(a.z, fmin(b.z, c.z)) - band};
+    double hi_w[3] = {fmax(a.x, fmax(b.x, c.x)) + band, fmax(a.y, fmax(b.y, c.y)) + band, fmax(a.z, fmax(b.z, c.z)) + band};
     int lo[3], hi[3];
     face_box(lo_w, hi_w, an, h, n, lo, hi);
     const int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
     if (ex <= 0 || ey <= 0 || ez <= 0) return;
     const int cnt = ex * ey * ez;
-    const float band2 = (float)(band * band);
+    const double band2 = band * band;
     const double hn = 0.5 * n;
     for (int q = threadIdx.x; q < cnt; q += 256) {
         const int kx = lo[0] + q % ex, ky = lo[1] + (q / ex) % ey, kz = lo[2] + q / (ex * ey);
-        const float3 p = make_float3((float)(an[0] + h * (kx - hn)), (float)(an[1] + h * (ky - hn)), (float)(an[2] + h * (kz - hn)));
-        const float dd = tri_dist2(p, a, b, c);
+        const d3 p{an[0] + h * (kx - hn), an[1] + h * (ky - hn), an[2] + h * (kz - hn)};
+        const double dd = tri_dist2(p, a, b, c);
         if (dd < band2) {
             const size_t id = ((size_t)kz * n + ky) * n + kx;
-            atomicMin(d2 + id, __float_as_uint(dd));
-            if (tf) atomicMin(dt2 + id, __float_as_uint(dd));
+            const unsigned long long bits = (unsigned long long)__double_as_longlong(dd);
+            atomicMin(d2 + id, bits);
+            if (tf) atomicMin(dt2 + id, bits);
         }
     }
 }
@@ -1363,19 +1349,19 @@ __global__ __launch_bounds__(64) void k_obj_parity(const float* __restrict__ V, 
     }
 }
 
-__global__ void k_obj_finalize(const uint32_t* __restrict__ d2, const uint32_t* __restrict__ dt2,
-                               const uint32_t* __restrict__ par, int W, int n, float tau_out1, float tau_in1, float rho,
+__global__ void k_obj_finalize(const unsigned long long* __restrict__ d2, const unsigned long long* __restrict__ dt2,
+                               const uint32_t* __restrict__ par, int W, int n, double tau_out1, double tau_in1, double rho,
                                float* __restrict__ O, float* __restrict__ fo_out) {
     const size_t n3 = (size_t)n * n * n;
     const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= n3) return;
     const int kx = (int)(id % n), ky = (int)((id / n) % n), kz = (int)(id / ((size_t)n * n));
     const bool inside = (par[((size_t)ky * n + kx) * W + (kz >> 5)] >> (kz & 31)) & 1u;
-    const float dm = d2[id] == FLT_MAX_BITS ? INFINITY : sqrtf(__uint_as_float(d2[id]));
-    const float dt = dt2[id] == FLT_MAX_BITS ? INFINITY : sqrtf(__uint_as_float(dt2[id]));
-    const float fo = inside ? -dm : dm;
-    O[id] = object_value(fo, dt, tau_out1, tau_in1, rho);
-    if (fo_out) fo_out[id] = fo;
+    const double dm = d2[id] == DBL_MAX_BITS ? INFINITY : sqrt(__longlong_as_double((long long)d2[id]));
+    const double dt = dt2[id] == DBL_MAX_BITS ? INFINITY : sqrt(__longlong_as_double((long long)dt2[id]));
+    const double fo = inside ? -dm : dm;
+    O[id] = (float)object_value(fo, dt, tau_out1, tau_in1, rho);
+    if (fo_out) fo_out[id] = (float)fo;
 }
 
 // ---- swept occupancy by scatter (per request) -----------------------------
@@ -1388,16 +1374,16 @@ __global__ void k_fill_u8(uint8_t* __restrict__ p, size_t cnt, uint8_t v) {
     if (i < cnt) p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void k_swept_pose(const float* __restrict__ pz, float r, float L, int m, double h,
+__global__ __launch_bounds__(256) void k_swept_pose(const double* __restrict__ pz, double r, double L, int m, double h,
                                                     double wc0, double wc1, double wc2, uint8_t* __restrict__ Sw) {
-    const float* P = pz + 12 * blockIdx.x;
+    const double* P = pz + 12 * blockIdx.x;
     const double wc[3] = {wc0, wc1, wc2};
     const double ax[3] = {P[2], P[5], P[8]};  // probe axis in world
     const double hm = 0.5 * m;
     int lo[3], hi[3];
     for (int j = 0; j < 3; ++j) {
-        const double e = (double)r * sqrt(fmax(0.0, 1.0 - ax[j] * ax[j])) + 1e-3;
-        const double c0 = P[9 + j], c1 = P[9 + j] + (double)L * ax[j];
+        const double e = r * sqrt(fmax(0.0, 1.0 - ax[j] * ax[j])) + 1e-3;
+        const double c0 = P[9 + j], c1 = P[9 + j] + L * ax[j];
         lo[j] = (int)ceil((fmin(c0, c1) - e - wc[j]) / h + hm);
         hi[j] = (int)floor((fmax(c0, c1) + e - wc[j]) / h + hm);
         lo[j] = lo[j] < 0 ? 0 : lo[j];
@@ -1408,30 +1394,28 @@ __global__ __launch_bounds__(256) void k_swept_pose(const float* __restrict__ pz
     const int cnt = ex * ey * ez;
     for (int q = threadIdx.x; q < cnt; q += 256) {
         const int jx = lo[0] + q % ex, jy = lo[1] + (q / ex) % ey, jz = lo[2] + q / (ex * ey);
-        const float yx = (float)(wc0 + h * (jx - hm)), yy = (float)(wc1 + h * (jy - hm)), yz = (float)(wc2 + h * (jz - hm));
-        const float dx = yx - P[9], dy = yy - P[10], dz = yz - P[11];
-        const float lx = P[0] * dx + P[3] * dy + P[6] * dz;
-        const float ly = P[1] * dx + P[4] * dy + P[7] * dz;
-        const float lz = P[2] * dx + P[5] * dy + P[8] * dz;
-        if (probe_sdf(lx, ly, lz, r, L) <= 0.f) Sw[((size_t)jz * m + jy) * m + jx] = 1;
+        const double dx = wc0 + h * (jx - hm) - P[9], dy = wc1 + h * (jy - hm) - P[10], dz = wc2 + h * (jz - hm) - P[11];
+        const double lx = P[0] * dx + P[3] * dy + P[6] * dz;
+        const double ly = P[1] * dx + P[4] * dy + P[7] * dz;
+        const double lz = P[2] * dx + P[5] * dy + P[8] * dz;
+        if (probe_sdf(lx, ly, lz, r, L) <= 0.0) Sw[((size_t)jz * m + jy) * m + jx] = 1;
     }
 }
 
-// poses (qw qx qy qz tx ty tz) -> R (row-major, from the normalised quaternion
-// in double) and p, 12 floats per pose
-__global__ void k_pose_prep(const float* __restrict__ poses, int np, float* __restrict__ out) {
+// poses (qw qx qy qz tx ty tz) -> R (row-major, from the normalised quaternion)
+// and p, 12 doubles per pose
+__global__ void k_pose_prep(const float* __restrict__ poses, int np, double* __restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= np) return;
     double q[4] = {poses[7 * i], poses[7 * i + 1], poses[7 * i + 2], poses[7 * i + 3]};
     const double nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     const double w = q[0] / nq, x = q[1] / nq, y = q[2] / nq, z = q[3] / nq;
-    float* o = out + 12 * i;
-    o[0] = (float)(1 - 2 * (y * y + z * z)); o[1] = (float)(2 * (x * y - w * z)); o[2] = (float)(2 * (x * z + w * y));
-    o[3] = (float)(2 * (x * y + w * z)); o[4] = (float)(1 - 2 * (x * x + z * z)); o[5] = (float)(2 * (y * z - w * x));
-    o[6] = (float)(2 * (x * z - w * y)); o[7] = (float)(2 * (y * z + w * x)); o[8] = (float)(1 - 2 * (x * x + y * y));
+    double* o = out + 12 * i;
+    o[0] = 1 - 2 * (y * y + z * z); o[1] = 2 * (x * y - w * z); o[2] = 2 * (x * z + w * y);
+    o[3] = 2 * (x * y + w * z); o[4] = 1 - 2 * (x * x + z * z); o[5] = 2 * (y * z - w * x);
+    o[6] = 2 * (x * z - w * y); o[7] = 2 * (y * z + w * x); o[8] = 1 - 2 * (x * x + y * y);
     o[9] = poses[7 * i + 4]; o[10] = poses[7 * i + 5]; o[11] = poses[7 * i + 6];
 }
-
 
 // corner masks over the padded, bricked lattice; taps beyond the lattice are 0
 __global__ void k_cellmask(const uint8_t* __restrict__ Sw, int m, int mp, uint8_t* __restrict__ cm) {
@@ -1566,7 +1550,7 @@ hipError_t object_spectrum(int n, const float* O, float2* spec_tmp, float2* W, c
 }
 
 hipError_t setup_object_grid(const float* V, const int32_t* F, const uint8_t* touch, int nf, int n, double h,
-                             const double* anchor, float tau_out1, float tau_in1, float rho, float* O, float* fo,
+                             const double* anchor, double tau_out1, double tau_in1, double rho, float* O, float* fo,
                              const ObjectScratch& w, hipStream_t s) {
     const size_t n3 = (size_t)n * n * n;
     const int W = (n + 31) / 32;
@@ -1585,8 +1569,8 @@ hipError_t setup_anchor(const float* V, int nv, double* anchor, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t setup_swept(const float* poses, int np, float r, float L, int m, int mp, double h, const double* wc,
-                       float* pose_tmp, uint8_t* Sw, uint8_t* cm, hipStream_t s) {
+hipError_t setup_swept(const float* poses, int np, double r, double L, int m, int mp, double h, const double* wc,
+                       double* pose_tmp, uint8_t* Sw, uint8_t* cm, hipStream_t s) {
     hipLaunchKernelGGL(k_pose_prep, dim3((np + 255) / 256), dim3(256), 0, s, poses, np, pose_tmp);
     const size_t m3 = (size_t)m * m * m;
     hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)((m3 + 255) / 256)), dim3(256), 0, s, Sw, m3, (uint8_t)0);

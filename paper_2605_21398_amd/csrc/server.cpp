@@ -2,9 +2,10 @@
 // arrival order as device memory and worker slots free up, and run
 // concurrently on one HIP stream per slot, so the work of requests that
 // arrive while others are on the GPU overlaps on the device (continuous
-// batching).  Object spectra stay resident in a cache keyed by the caller's
-// object id, the canvas and the object-grid thresholds.  In serial mode a
-// single slot gives the plain one-request-at-a-time path.
+// batching).  Object spectra stay resident in a cache keyed by the mesh's
+// contents (a 64-bit hash, confirmed byte for byte on a hit), the canvas and
+// the object-grid thresholds.  In serial mode a single slot gives the plain
+// one-request-at-a-time path.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,12 +39,32 @@ int sfail(int code, const std::string& msg) {
     return code;
 }
 
+// FNV-1a over a byte range, continuing from h
+uint64_t fnv1a(const void* p, size_t n, uint64_t h) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+// the mesh of a request, kept by the cache to confirm a hash hit exactly
+struct MeshBytes {
+    std::vector<float> vertices;
+    std::vector<int32_t> faces;
+    std::vector<uint8_t> touchable;
+    uint64_t hash = 0;
+    bool same(const MeshBytes& o) const {
+        return hash == o.hash && vertices == o.vertices && faces == o.faces && touchable == o.touchable;
+    }
+};
+
 // a request's inputs, copied at submission
 struct Job {
     reg_ticket ticket = 0;
-    std::vector<float> vertices, poses, so3;
-    std::vector<int32_t> faces;
-    std::vector<uint8_t> touchable;
+    std::shared_ptr<MeshBytes> mesh;
+    std::vector<float> poses, so3;
     int64_t object_id = -1;
     reg_probe probe{};
     reg_grid_spec grid{};
@@ -54,7 +75,14 @@ struct Job {
     reg_result result{};
 };
 
-using ObjKey = std::tuple<int64_t, int, double, double, double, double>;
+// mesh hash, canvas edge, voxel size and the object-grid thresholds
+using ObjKey = std::tuple<uint64_t, int, double, double, double, double>;
+
+struct CacheEntry {
+    ObjKey key;
+    std::shared_ptr<const MeshBytes> mesh;
+    std::shared_ptr<ObjectData> obj;
+};
 
 }  // namespace
 
@@ -74,30 +102,32 @@ struct reg_server {
     int64_t n_done = 0, hits = 0, misses = 0;
     // object cache, least recently used first
     std::mutex cache_mu;
-    std::list<std::pair<ObjKey, std::shared_ptr<ObjectData>>> cache;
+    std::list<CacheEntry> cache;
     size_t cache_bytes = 0;
 
-    std::shared_ptr<ObjectData> cache_get(const ObjKey& k) {
+    std::shared_ptr<ObjectData> cache_get(const ObjKey& k, const MeshBytes& mesh) {
         std::lock_guard<std::mutex> lk(cache_mu);
         for (auto it = cache.begin(); it != cache.end(); ++it)
-            if (it->first == k) {
+            if (it->key == k && it->mesh->same(mesh)) {
                 cache.splice(cache.end(), cache, it);
                 ++hits;
-                return it->second;
+                return it->obj;
             }
         ++misses;
         return nullptr;
     }
-    void cache_put(const ObjKey& k, std::shared_ptr<ObjectData> o) {
+    // An object is published once its build is queued: its ready event orders
+    // every later user's stream after the build.
+    void cache_put(const ObjKey& k, std::shared_ptr<const MeshBytes> mesh, std::shared_ptr<ObjectData> o) {
         std::lock_guard<std::mutex> lk(cache_mu);
         for (auto& e : cache)
-            if (e.first == k) return;
+            if (e.key == k && e.mesh->same(*mesh)) return;
         cache_bytes += regdock_rt::object_bytes(o.get());
-        cache.emplace_back(k, std::move(o));
+        cache.push_back(CacheEntry{k, std::move(mesh), std::move(o)});
         // evict least recently used objects no registration holds any more
         for (auto it = cache.begin(); it != cache.end() && cache_bytes > (size_t)cfg.cache_bytes;) {
-            if (it->second.use_count() == 1) {
-                cache_bytes -= regdock_rt::object_bytes(it->second.get());
+            if (it->obj.use_count() == 1) {
+                cache_bytes -= regdock_rt::object_bytes(it->obj.get());
                 it = cache.erase(it);
             } else {
                 ++it;
@@ -122,7 +152,8 @@ struct reg_server {
 // One registration on the worker's stream: stage the inputs, build (or take
 // from the cache) the object, score every rotation, take the top K and refine.
 int reg_server::run_gpu(Job& j, hipStream_t s) {
-    const int32_t nv = (int32_t)(j.vertices.size() / 3), nf = (int32_t)(j.faces.size() / 3);
+    const MeshBytes& mb = *j.mesh;
+    const int32_t nv = (int32_t)(mb.vertices.size() / 3), nf = (int32_t)(mb.faces.size() / 3);
     const int32_t N = (int32_t)(j.poses.size() / 7), M = (int32_t)(j.so3.size() / 4);
     std::vector<void*> dev;
     struct Free {
@@ -142,9 +173,9 @@ int reg_server::run_gpu(Job& j, hipStream_t s) {
         dev.push_back(p);
         return p;
     };
-    float* dV = (float*)dalloc(j.vertices.size() * 4);
-    int32_t* dF = (int32_t*)dalloc(j.faces.size() * 4);
-    uint8_t* dT = j.touchable.empty() ? nullptr : (uint8_t*)dalloc(j.touchable.size());
+    float* dV = (float*)dalloc(mb.vertices.size() * 4);
+    int32_t* dF = (int32_t*)dalloc(mb.faces.size() * 4);
+    uint8_t* dT = mb.touchable.empty() ? nullptr : (uint8_t*)dalloc(mb.touchable.size());
     float* dP = (float*)dalloc(j.poses.size() * 4);
     float* dQ = (float*)dalloc(j.so3.size() * 4);
     float* dS = (float*)dalloc((size_t)M * 4);
@@ -154,18 +185,18 @@ int reg_server::run_gpu(Job& j, hipStream_t s) {
     double* dInit = (double*)dalloc((size_t)K * 56);
     double* dOut = (double*)dalloc((size_t)K * 56);
     double* dJ = (double*)dalloc((size_t)K * 8);
-    if (!dV || !dF || (!dT && !j.touchable.empty()) || !dP || !dQ || !dS || !dPose || !dTop || !dInit || !dOut || !dJ)
+    if (!dV || !dF || (!dT && !mb.touchable.empty()) || !dP || !dQ || !dS || !dPose || !dTop || !dInit || !dOut || !dJ)
         return sfail(REG_ENOMEM, "device staging allocation failed");
     auto up = [&](void* d, const void* hsrc, size_t bytes) {
         return hipMemcpyAsync(d, hsrc, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
     };
-    if (!up(dV, j.vertices.data(), j.vertices.size() * 4) || !up(dF, j.faces.data(), j.faces.size() * 4) ||
-        (dT && !up(dT, j.touchable.data(), j.touchable.size())) || !up(dP, j.poses.data(), j.poses.size() * 4) ||
+    if (!up(dV, mb.vertices.data(), mb.vertices.size() * 4) || !up(dF, mb.faces.data(), mb.faces.size() * 4) ||
+        (dT && !up(dT, mb.touchable.data(), mb.touchable.size())) || !up(dP, j.poses.data(), j.poses.size() * 4) ||
         !up(dQ, j.so3.data(), j.so3.size() * 4))
         return sfail(REG_EDEVICE, "staging copy failed");
 
-    const ObjKey key{j.object_id, j.grid.n, j.grid.h_mm, j.params.tau_out1, j.params.tau_in1, j.params.rho};
-    std::shared_ptr<ObjectData> cached = j.object_id >= 0 ? cache_get(key) : nullptr;
+    const ObjKey key{mb.hash, j.grid.n, j.grid.h_mm, j.params.tau_out1, j.params.tau_in1, j.params.rho};
+    std::shared_ptr<ObjectData> cached = j.object_id >= 0 ? cache_get(key, mb) : nullptr;
     reg_mesh mesh{dV, nv, dF, nf, dT};
     reg_handle* h = nullptr;
     int rc = regdock_rt::init_shared(&mesh, &j.probe, dP, N, dQ, M, &j.grid, &j.params, (void*)s, cached, &h);
@@ -174,7 +205,7 @@ int reg_server::run_gpu(Job& j, hipStream_t s) {
         reg_handle* h;
         ~HFree() { register_free(h); }
     } hf{h};
-    if (!cached && j.object_id >= 0) cache_put(key, regdock_rt::object_of(h));
+    if (!cached && j.object_id >= 0) cache_put(key, j.mesh, regdock_rt::object_of(h));
 
     rc = score_rotations(h, 0, M, dS, nullptr, dPose);
     if (rc) return sfail(rc, regdock_rt::last_error());
@@ -341,9 +372,20 @@ int register_submit(reg_server* s, const reg_request* rq, reg_ticket* out) {
     if (rq->top_k < 0 || rq->top_k > 16) return sfail(REG_EINVAL, "top_k must be in [0, 16]");
     if (rq->refine < 0 || rq->refine > 2) return sfail(REG_EINVAL, "refine must be 0, 1 or 2");
     auto j = std::make_shared<Job>();
-    j->vertices.assign(m.vertices, m.vertices + 3 * (size_t)m.n_vertices);
-    j->faces.assign(m.faces, m.faces + 3 * (size_t)m.n_faces);
-    if (m.touchable) j->touchable.assign(m.touchable, m.touchable + (size_t)m.n_faces);
+    auto mesh = std::make_shared<MeshBytes>();
+    mesh->vertices.assign(m.vertices, m.vertices + 3 * (size_t)m.n_vertices);
+    mesh->faces.assign(m.faces, m.faces + 3 * (size_t)m.n_faces);
+    if (m.touchable) mesh->touchable.assign(m.touchable, m.touchable + (size_t)m.n_faces);
+    {
+        uint64_t hh = 0xcbf29ce484222325ull;
+        const int64_t sizes[3] = {m.n_vertices, m.n_faces, m.touchable ? 1 : 0};
+        hh = fnv1a(sizes, sizeof sizes, hh);
+        hh = fnv1a(mesh->vertices.data(), mesh->vertices.size() * 4, hh);
+        hh = fnv1a(mesh->faces.data(), mesh->faces.size() * 4, hh);
+        hh = fnv1a(mesh->touchable.data(), mesh->touchable.size(), hh);
+        mesh->hash = hh;
+    }
+    j->mesh = std::move(mesh);
     j->poses.assign(rq->poses, rq->poses + 7 * (size_t)rq->n_poses);
     j->so3.assign(rq->so3, rq->so3 + 4 * (size_t)rq->n_rot);
     j->object_id = rq->object_id;
@@ -360,7 +402,7 @@ int register_submit(reg_server* s, const reg_request* rq, reg_ticket* out) {
                                           : regdock_rt::default_batch_for(rq->grid.n, rq->n_rot);
     const auto fp = regdock_rt::footprint(rq->grid.n, rq->n_rot, rq->n_poses, m.n_vertices, m.n_faces, batch,
                                           rq->refine ? j->top_k : 0);
-    const size_t staging = j->vertices.size() * 4 + j->faces.size() * 4 + j->touchable.size() + j->poses.size() * 4 +
+    const size_t staging = j->mesh->vertices.size() * 4 + j->mesh->faces.size() * 4 + j->mesh->touchable.size() + j->poses.size() * 4 +
                            j->so3.size() * 4 + (size_t)rq->n_rot * 60 + 16 * 200;
     j->object_part = fp.object;
     j->footprint = fp.request + fp.object + staging;

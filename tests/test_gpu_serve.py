@@ -120,3 +120,53 @@ def test_object_cache_hit_gives_the_same_result():
     assert first["status"] == 0
     assert st["cache_hits"] >= 1 and st["cached_objects"] == 1
     _same(hit, cold)
+
+
+def test_concurrent_requests_for_one_object_equal_cold_runs():
+    """Two requests for the same object submitted back to back into a 2-slot
+    server: the second may take the object from the cache while the first's
+    build is still queued on the device.  Both must equal cold runs (object
+    built afresh) bit for bit."""
+    rd = _lib()
+    p = synth.batch_problem(1, level=5, lmax=8, N=600, M=512)
+    q = synth.batch_problem(1, level=5, lmax=8, N=300, M=256)
+    assert np.array_equal(p.vertices, q.vertices) and p.n == q.n
+    import time
+    srv = rd.Server(max_inflight=2)
+    try:
+        # the second and third requests arrive while the first registration
+        # (which builds the object) is still running
+        t1 = _submit(srv, p, object_id=3)
+        time.sleep(0.02)
+        t2 = _submit(srv, q, object_id=3)
+        t3 = _submit(srv, q, object_id=3)
+        r1, r2, r3 = srv.wait(t1), srv.wait(t2), srv.wait(t3)
+        st = srv.stats()
+        c1 = srv.wait(_submit(srv, p, object_id=-1))
+        c2 = srv.wait(_submit(srv, q, object_id=-1))
+    finally:
+        srv.close()
+    print("cache hits", st["cache_hits"], "misses", st["cache_misses"])
+    assert st["cache_hits"] + st["cache_misses"] == 3 and st["cache_hits"] >= 1
+    for a, b in ((r1, c1), (r2, c2), (r3, c2)):
+        assert a["status"] == 0 and b["status"] == 0
+        _same(a, b)
+
+
+def test_object_cache_is_keyed_by_the_mesh_contents():
+    """The same caller id for two different meshes does not share an object:
+    the second request builds its own and equals its cold run."""
+    rd = _lib()
+    p = synth.batch_problem(0, level=4, lmax=6, N=300, M=128)
+    q = synth.batch_problem(0, level=4, lmax=6, N=300, M=128)
+    q.vertices = (q.vertices * np.float32(1.01)).astype(np.float32)
+    srv = rd.Server(max_inflight=1)
+    try:
+        srv.wait(_submit(srv, p, object_id=9))
+        r = srv.wait(_submit(srv, q, object_id=9))
+        st = srv.stats()
+        cold = srv.wait(_submit(srv, q, object_id=-1))
+    finally:
+        srv.close()
+    assert st["cache_hits"] == 0 and st["cached_objects"] == 2
+    _same(r, cold)
