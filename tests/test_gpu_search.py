@@ -317,3 +317,60 @@ def test_two_lanes_equal_one_lane():
         rd.register_free(h)
     for k in range(3):
         assert np.array_equal(full[k], np.concatenate(parts[k]))
+
+
+# ------------------------------------- full size, every rotation, from the mesh
+
+GOLD = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
+
+
+def _golden_search(cfg, p):
+    """The oracle's results of every rotation (tests/golden/make_search_golden.py)."""
+    import importlib.util
+    import os
+    spec = importlib.util.spec_from_file_location("make_search_golden", os.path.join(GOLD, "make_search_golden.py"))
+    mg = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mg)
+    g = np.load(os.path.join(GOLD, f"search_cfg{cfg}.npz"))
+    assert str(g["digest"]) == mg.input_digest(p), "golden file written for other inputs: rerun make_search_golden.py"
+    return g
+
+
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_full_size_every_rotation_matches_oracle(cfg):
+    """The 64^3 (1024 rotations) and 128^3 (4096 rotations) workloads from the
+    mesh, in the default launch configuration: device-built grids against the
+    oracle's, then every rotation's score and peak against the oracle's field
+    (interval over flagged voxels), and the top-16 against the oracle's."""
+    rd = _lib()
+    p = _problem(cfg, 0)
+    gold = _golden_search(cfg, p)
+    handle = _handle(rd, p)
+    try:
+        sc, sh, _ = [t.cpu().numpy() for t in rd.score_rotations(handle)]
+        top = rd.register_top_k(handle, rd._dev(sc, __import__("torch").float32), 16).cpu().numpy()
+        st = rd.register_search_stats(handle)
+        O, fo, d = S.object_grid(p.vertices, p.faces, p.touchable, p.n, p.h)
+        mf = S.swept_lattice(p.poses, p.radius, p.length, S.lattice_edge(p.n), p.h, p.center)
+        _grid_agreement(rd, handle, p, O, fo, d, mf)
+    finally:
+        rd.register_free(handle)
+    print(f"config {cfg}: search stats {st}")
+    assert st["uncertain"] == 0
+    lo, hi, cmax = gold["lo"], gold["hi"], gold["cmax"]
+    tol = TOL_REL * np.abs(cmax).max()
+    assert tol <= float(gold["window"])
+    off, idx, val = gold["adm_off"], gold["adm_idx"], gold["adm_val"]
+    adm = [set(idx[off[r]:off[r + 1]][val[off[r]:off[r + 1]] >= lo[r] - tol].tolist()) for r in range(len(sc))]
+    wide = _check_intervals(sc, _flat_from_shift(sh, p.n), lo, hi, adm, tol, f"config {cfg} end to end")
+    assert wide <= 0.01 * len(sc)
+    # top-16: every device pick could be in the oracle's top-16, and every
+    # rotation certainly in it is picked
+    order = np.sort(lo)[::-1]
+    lo16 = order[15]
+    hi17 = np.sort(hi)[::-1][16]
+    for r in top:
+        assert hi[r] + 2 * tol >= lo16, r
+    must = np.flatnonzero(lo - 2 * tol > hi17)
+    assert set(must.tolist()) <= set(top.tolist())
+    print(f"config {cfg}: top-16 {list(top)}; oracle top-16 {list(S.top_k(cmax, 16))}")

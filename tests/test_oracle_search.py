@@ -193,6 +193,108 @@ def test_object_grid_banded_equals_brute_force(cfg1):
     assert (np.sign(fo.ravel()[sel]) == np.sign(fo2)).all()
 
 
+# ------------------------------------------- threshold flags and bounds
+
+def test_object_flags_box_closed_form():
+    """Box whose top face lies 0.2 mm above a plane of canvas points: those
+    voxels sit on the -tau_in1 jump.  The flagged set is the band of the
+    textbook SDF, and the alternative value of each is the other branch of
+    the template (closed form)."""
+    b = (1.53125, 1.171875, 1.0)   # exact in float32; z = 0.8 is a canvas plane
+    V, F = box_mesh(b)
+    n, h = 40, 0.1
+    O, fo, d = S.object_grid(V, F, None, n, h)
+    P = S.canvas_points(n, h, S.anchor(V))
+    sdf = box_sdf(P, b)
+    delta = 1e-6
+    dO = S.object_flags(O, fo, d, delta=delta).ravel()
+    near = np.abs(sdf + 0.2) < delta
+    assert near.sum() > 100 and (dO > 0).sum() == near.sum()
+    assert ((dO > 0) == near).all()
+    # other branch: deep voxels could take the shell value 1 + f/tau_in1 (about
+    # 0, capped by the mask), shell voxels the penalty -50
+    deep = sdf <= -0.2
+    alt = np.where(deep, np.minimum(1 + sdf / 0.2, np.maximum(0, 1 - np.abs(sdf) / 0.5)), -50.0)
+    ref = np.abs(alt - template(sdf, np.abs(sdf)))
+    assert np.abs(dO[near] - ref[near]).max() < 1e-9
+    assert np.all(dO[near] > 49.0)
+
+
+def test_swept_flags_band():
+    mf = np.array([-1.0, -1e-7, 0.0, 2e-7, 5e-5, np.inf])
+    assert list(S.swept_flags(mf, 1e-6)) == [0, 1, 1, 1, 0, 0]
+
+
+def test_score_bounds_cover_every_flag_combination():
+    """Brute force: every combination of moving three flagged object voxels
+    (by any amount up to |dO|, either sign) and flipping three flagged lattice
+    points gives a field within the bound of its unperturbed one, computed
+    by the direct O(n^6) definition of the correlation."""
+    n, h = 6, 0.3
+    m = S.lattice_edge(n)
+    g = np.random.default_rng(41)
+    O = g.normal(size=(n, n, n))
+    O[g.random((n, n, n)) < 0.2] = -50.0
+    Sw = (g.random((m, m, m)) < 0.5).astype(float)
+    a, wc = np.array([0.1, -0.2, 0.05]), np.array([0.02, 0.0, -0.03])
+    q = np.array([0.9, 0.2, -0.3, 0.25])
+    q /= np.linalg.norm(q)
+    flagO = [tuple(g.integers(0, n, 3)) for _ in range(3)]
+    dO = np.zeros_like(O)
+    for k in flagO:
+        dO[k] = 50.0 * g.random() + 1.0
+    # lattice points that are taps of canvas points (so the flips matter)
+    R = S.quat_to_mat(q)
+    ks = np.array([[1, 2, 3], [4, 4, 1], [2, 5, 5]], dtype=float)
+    U = ((h * (ks - n / 2)) @ R.T + wc - (wc - h * m / 2)) / h
+    flagS = [tuple(np.floor(u).astype(int)[::-1]) for u in U]
+    Fs = np.zeros_like(Sw)
+    for j in flagS:
+        Fs[j] = 1.0
+    C, B = S.score_bounds(O, dO, Sw, Fs, q, n, h, a, wc)
+    assert np.allclose(C, S.correlate_direct(O, S.resample(Sw, q, n, h, a, wc)), atol=1e-9)
+    assert B.max() > 0
+    worst = 0.0
+    for bits in range(1 << 6):
+        O2 = O.copy()
+        for i, k in enumerate(flagO):
+            if bits >> i & 1:
+                O2[k] += (1 if (bits + i) % 2 else -1) * dO[k]
+        S2 = Sw.copy()
+        for i, j in enumerate(flagS):
+            if bits >> (3 + i) & 1:
+                S2[j] = 1.0 - S2[j]
+        C2 = S.correlate_direct(O2, S.resample(S2, q, n, h, a, wc))
+        assert np.all(np.abs(C2 - C) <= B + 1e-9)
+        worst = max(worst, float(np.max(np.abs(C2 - C) / np.maximum(B, 1e-300) * (B > 0))))
+        lo, hi = S.score_interval(C, B)
+        assert lo - 1e-9 <= C2.max() <= hi + 1e-9
+        # the peak of every alternative is admissible
+        assert int(np.argmax(C2.ravel())) in set(S.peak_admissible(C, B, lo, 1e-9).tolist())
+    assert worst > 0.3   # the bound is not vacuous: some combination comes close
+
+
+def test_peak_admissible_without_flags_is_the_tie_band():
+    C = np.zeros((4, 4, 4))
+    C.ravel()[[5, 17, 40]] = [3.0, 3.0 - 1e-6, 2.0]
+    B = np.zeros_like(C)
+    lo, hi = S.score_interval(C, B)
+    assert lo == hi == 3.0
+    assert list(S.peak_admissible(C, B, lo, 1e-5)) == [5, 17]
+    assert list(S.peak_admissible(C, B, lo, 1e-7)) == [5]
+
+
+def test_resample_of_a_list_equals_single_calls():
+    n, h = 8, 0.25
+    m = S.lattice_edge(n)
+    g = np.random.default_rng(42)
+    A, Bm = g.random((m, m, m)), g.random((m, m, m))
+    q = np.array([0.3, -0.5, 0.7, 0.4])
+    ra, rb = S.resample([A, Bm], q, n, h, np.zeros(3), np.zeros(3))
+    assert np.array_equal(ra, S.resample(A, q, n, h, np.zeros(3), np.zeros(3)))
+    assert np.array_equal(rb, S.resample(Bm, q, n, h, np.zeros(3), np.zeros(3)))
+
+
 # ---------------------------------------------------- swept occupancy
 
 def test_swept_single_axis_aligned_pose_count():
