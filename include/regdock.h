@@ -189,6 +189,26 @@ int so3_super_fibonacci(int32_t n, float* out, void* hip_stream);
  * inverted by linear interpolation. */
 int so3_geoball_sf(int32_t n, const double* q0, double theta, double gamma, float* out, void* hip_stream);
 
+/* Largest n of the samplers: (n + 255) / 256 blocks of 256 threads must be
+ * indexable in int32. */
+#define SO3_SAMPLER_MAX_N 2147483392
+
+/* so3_geoball_sf for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same samples, with no allocation, no host copy and no synchronisation.
+ * Its only scratch is the radial table (radii and distribution function,
+ * 2 x 4096 doubles = 64 KiB), built on the device by a kernel into a static
+ * device array that each GPU holds for the life of the process; its size does
+ * not depend on n.  Arguments as so3_geoball_sf; out: n x 4 float32 on the
+ * device, written asynchronously on hip_stream (NULL: the null stream).  The
+ * table keeps the last call's contents and is rebuilt by every call: calls
+ * that overlap on one GPU (different streams, or threads) race on it and must
+ * be serialised by the caller.  The samples agree with so3_geoball_sf's to
+ * float32 rounding (both tabulate the same function in the same order).
+ * Errors: REG_EINVAL (as so3_geoball_sf, or n > SO3_SAMPLER_MAX_N),
+ * REG_EDEVICE. */
+int so3_geoball_sf_noalloc(int32_t n, const double* q0, double theta, double gamma, float* out, void* hip_stream);
+
 /* Replace the handle's SO(3) sample set (M x 4 float32 on the device, copied)
  * so that score_rotations scores it against the same object grid and swept
  * lattice, e.g. the local GeoBall-SF set around the global maximum (Sec.

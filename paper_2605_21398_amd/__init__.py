@@ -29,7 +29,8 @@ EXPORTS = ["register_init", "score_rotations", "register_top_k", "register_free"
            "register_server_destroy", "register_submit", "register_poll", "register_wait", "register_server_stats",
            "register_server_last_error", "register_batch_create", "register_batch_run", "register_batch_outputs",
            "register_batch_free", "register_autotune", "register_tuned_batch", "register_cached_bytes",
-           "register_release_cached", "so3_super_fibonacci", "so3_geoball_sf", "register_set_rotations",
+           "register_release_cached", "so3_super_fibonacci", "so3_geoball_sf", "so3_geoball_sf_noalloc",
+           "register_set_rotations",
            "refine_se3_lbfgsb", "register_linear_edge"]
 
 
@@ -117,6 +118,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.so3_super_fibonacci.argtypes = [i32, p, p]
     L.so3_geoball_sf.restype = ctypes.c_int
     L.so3_geoball_sf.argtypes = [i32, p, ctypes.c_double, ctypes.c_double, p, p]
+    L.so3_geoball_sf_noalloc.restype = ctypes.c_int
+    L.so3_geoball_sf_noalloc.argtypes = [i32, p, ctypes.c_double, ctypes.c_double, p, p]
     L.register_linear_edge.restype = ctypes.c_int
     L.register_linear_edge.argtypes = [p, i32, ctypes.POINTER(reg_probe), p, i32, p, ctypes.c_double, ctypes.c_double,
                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
@@ -538,6 +541,22 @@ def so3_geoball_sf(n: int, q0, theta: float, gamma: float = 0.0, stream=None):
     st = stream if stream is not None else torch.cuda.current_stream()
     _check(load_library().so3_geoball_sf(n, q.ctypes.data_as(ctypes.c_void_p), float(theta), float(gamma), _ptr(out),
                                           ctypes.c_void_p(st.cuda_stream)))
+    return out
+
+
+def so3_geoball_sf_noalloc(n: int, q0, theta: float, gamma: float = 0.0, out=None, stream=None):
+    """so3_geoball_sf without device allocation in the library: the samples are
+    written to `out` (float32 [>= n, 4] on the device; allocated here by torch
+    if None) asynchronously on the stream."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    if out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous() or out.numel() < 4 * n:
+        raise ValueError("out must be a contiguous float32 device tensor of at least n x 4 values")
+    q = np.ascontiguousarray(q0, dtype=np.float64).reshape(4)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(load_library().so3_geoball_sf_noalloc(n, q.ctypes.data_as(ctypes.c_void_p), float(theta), float(gamma),
+                                                 _ptr(out), ctypes.c_void_p(st.cuda_stream)))
     return out
 
 

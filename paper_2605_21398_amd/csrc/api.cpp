@@ -1102,6 +1102,7 @@ int register_linear_edge(const float* vertices, int32_t n_vertices, const reg_pr
 
 int so3_super_fibonacci(int32_t n, float* out, void* hip_stream) {
     if (n < 1 || !out) return fail(REG_EINVAL, "n >= 1 and an output buffer are required");
+    if (n > SO3_SAMPLER_MAX_N) return fail(REG_EINVAL, "n = %d exceeds SO3_SAMPLER_MAX_N", n);
     hipStream_t s = (hipStream_t)hip_stream;
     reg_handle* none = nullptr;
     DEV_TRY(none, super_fibonacci(n, out, s));
@@ -1111,6 +1112,7 @@ int so3_super_fibonacci(int32_t n, float* out, void* hip_stream) {
 
 int so3_geoball_sf(int32_t n, const double* q0, double theta, double gamma, float* out, void* hip_stream) {
     if (n < 1 || !out || !q0) return fail(REG_EINVAL, "n >= 1, q0 and an output buffer are required");
+    if (n > SO3_SAMPLER_MAX_N) return fail(REG_EINVAL, "n = %d exceeds SO3_SAMPLER_MAX_N", n);
     double qn = 0.0;
     for (int j = 0; j < 4; ++j) {
         if (!std::isfinite(q0[j])) return fail(REG_EINVAL, "non-finite q0");
@@ -1121,6 +1123,22 @@ int so3_geoball_sf(int32_t n, const double* q0, double theta, double gamma, floa
     if (!(gamma >= 0.0) || !std::isfinite(gamma)) return fail(REG_EINVAL, "gamma must be >= 0 (0: gamma = n)");
     reg_handle* none = nullptr;
     DEV_TRY(none, geoball_sf(n, q0, theta, gamma, out, (hipStream_t)hip_stream));
+    return REG_OK;
+}
+
+int so3_geoball_sf_noalloc(int32_t n, const double* q0, double theta, double gamma, float* out, void* hip_stream) {
+    if (n < 1 || !out || !q0) return fail(REG_EINVAL, "n >= 1, q0 and an output buffer are required");
+    double qn = 0.0;
+    for (int j = 0; j < 4; ++j) {
+        if (!std::isfinite(q0[j])) return fail(REG_EINVAL, "non-finite q0");
+        qn += q0[j] * q0[j];
+    }
+    if (!(qn > 1e-12)) return fail(REG_EINVAL, "q0 has zero norm");
+    if (!(theta > 0.0 && theta <= 0.5 * M_PI)) return fail(REG_EINVAL, "theta must lie in (0, pi/2]");
+    if (!(gamma >= 0.0) || !std::isfinite(gamma)) return fail(REG_EINVAL, "gamma must be >= 0 (0: gamma = n)");
+    if (n > SO3_SAMPLER_MAX_N) return fail(REG_EINVAL, "n = %d exceeds SO3_SAMPLER_MAX_N", n);
+    reg_handle* none = nullptr;
+    DEV_TRY(none, geoball_sf_noalloc(n, q0, theta, gamma, out, (hipStream_t)hip_stream));
     return REG_OK;
 }
 

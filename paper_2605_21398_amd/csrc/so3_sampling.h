@@ -18,4 +18,9 @@ hipError_t super_fibonacci(int n, float* out, hipStream_t s);
 // built on the host and released after the kernel).
 hipError_t geoball_sf(int n, const double* q0, double theta, double gamma, float* out, hipStream_t s);
 
+// The same samples with the radial table built on the device in a static
+// device array (no allocation, no host copy); asynchronous on s.  Calls that
+// overlap on one device share the table and race.
+hipError_t geoball_sf_noalloc(int n, const double* q0, double theta, double gamma, float* out, hipStream_t s);
+
 }  // namespace regdock

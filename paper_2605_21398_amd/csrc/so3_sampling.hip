@@ -16,11 +16,19 @@
 #include "so3_sampling.h"
 
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "runtime.h"
 
 namespace regdock {
+
+// Radial table of the allocation-free GeoBall-SF entry point: radii, then the
+// normalised distribution function, GEOBALL_TABLE doubles each (64 KiB).  Each
+// device holds its own copy for the life of the process; host code reaches it
+// only through the address hipGetSymbolAddress gives on that device.
+static __device__ __align__(256) double scratch[2 * GEOBALL_TABLE];
 
 namespace {
 
@@ -74,7 +82,72 @@ __global__ __launch_bounds__(256) void k_geoball_sf(int n, double q0w, double q0
                                                     (float)(q0w * z + q0x * y - q0y * x + q0z * w));
 }
 
+// Radial distribution function of GeoBall-SF on the device, the same
+// quantity the host tabulates for geoball_sf: radii on a uniform grid of
+// [0, sin theta], the density r L(r) at each, its cumulative trapezoid sum in
+// grid order (one thread, so the sum is in a fixed order), normalised to 1.
+__global__ __launch_bounds__(256) void k_geoball_table(double* __restrict__ tab, int points, double theta) {
+    double* tr = tab;
+    double* tF = tab + points;
+    __shared__ double total;
+    const double rmax = sin(theta), ct = cos(theta);
+    for (int j = threadIdx.x; j < points; j += blockDim.x) {
+        const double r = rmax * (double)j / (double)(points - 1);
+        const double c = ct / sqrt(1.0 - r * r);
+        tr[j] = r;
+        tF[j] = r * 2.0 * acos(c < 1.0 ? c : 1.0);  // density, summed below
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double prev = tF[0], acc = 0.0;
+        tF[0] = 0.0;
+        for (int j = 1; j < points; ++j) {
+            const double d = tF[j];
+            acc += 0.5 * (d + prev) * (tr[j] - tr[j - 1]);
+            tF[j] = acc;
+            prev = d;
+        }
+        total = acc;
+    }
+    __syncthreads();
+    const double inv = total;
+    for (int j = threadIdx.x; j < points; j += blockDim.x) tF[j] /= inv;
+}
+
+// device address of `scratch` on the current device, looked up once per device
+hipError_t scratch_address(double** out) {
+    static std::mutex mu;
+    static std::map<int, double*> addr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        it = addr.emplace(dev, static_cast<double*>(ptr)).first;
+    }
+    *out = it->second;
+    return hipSuccess;
+}
+
 }  // namespace
+
+hipError_t geoball_sf_noalloc(int n, const double* q0, double theta, double gamma, float* out, hipStream_t s) {
+    double* tab = nullptr;
+    hipError_t e = scratch_address(&tab);
+    if (e != hipSuccess) return e;
+    const double qn = std::sqrt(q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2] + q0[3] * q0[3]);
+    k_geoball_table<<<1, 256, 0, s>>>(tab, GEOBALL_TABLE, theta);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_geoball_sf<<<(n + 255) / 256, 256, 0, s>>>(n, q0[0] / qn, q0[1] / qn, q0[2] / qn, q0[3] / qn, std::cos(theta),
+                                                 gamma > 0.0 ? gamma : (double)n, 1.0 / std::sqrt(2.0),
+                                                 1.0 / psi_constant(), tab, tab + GEOBALL_TABLE, GEOBALL_TABLE, out);
+    return hipGetLastError();
+}
 
 hipError_t super_fibonacci(int n, float* out, hipStream_t s) {
     k_super_fibonacci<<<(n + 255) / 256, 256, 0, s>>>(n, 1.0 / std::sqrt(2.0), 1.0 / psi_constant(), out);
