@@ -760,7 +760,7 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
         ALLOC_TRY(h, h->opar, (size_t)h->n * h->n * ((h->n + 31) / 32));
     }
     ALLOC_TRY(h, h->spec, h->H * (size_t)h->batch);
-    ALLOC_TRY(h, h->ptop, (size_t)h->batch * h->n * KTOP);
+    ALLOC_TRY(h, h->ptop, (size_t)h->batch * h->n * KREC);
     ALLOC_TRY(h, h->pssq, (size_t)h->batch * h->n);
     ALLOC_TRY(h, h->stats, 5);
     ALLOC_TRY(h, h->need_count, 1);
@@ -770,7 +770,7 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
     ALLOC_TRY(h, h->Plow, (size_t)h->batch * NLOW3);
     if (n_rot > h->batch) {  // a call can span two batches: the second lane
         ALLOC_TRY(h, h->spec2, h->H * (size_t)h->batch);
-        ALLOC_TRY(h, h->ptop2, (size_t)h->batch * h->n * KTOP);
+        ALLOC_TRY(h, h->ptop2, (size_t)h->batch * h->n * KREC);
         ALLOC_TRY(h, h->pssq2, (size_t)h->batch * h->n);
         ALLOC_TRY(h, h->lowT2, (size_t)h->batch * h->n * NLOW2);
         ALLOC_TRY(h, h->Plow2, (size_t)h->batch * NLOW3);
@@ -1567,7 +1567,7 @@ Footprint footprint(int n, int n_rot, int n_poses, int nv, int nf, int batch, in
     // refinement buffers are allocated for at least 16 starts (ensure_refine_buffers)
     const size_t K = refine_starts > 0 ? (size_t)std::max(refine_starts, 16) : 1, nq = K * REF_TMAX * N;
     const size_t lanes = M > B ? 2 : 1;  // the second lane's pass buffers
-    f.request = lanes * (H * B * 8 + B * n * KTOP * 8 + B * n * 8 + B * n * NLOW2 * 16 + B * NLOW3 * 16) + M * per_rot +
+    f.request = lanes * (H * B * 8 + B * n * KREC * 8 + B * n * 8 + B * n * NLOW2 * 16 + B * NLOW3 * 16) + M * per_rot +
                 M * (4 + 56) + 28 * N + 96 * N + m * m * m + mp * mp * mp + 16 * n3 + n * n * ((n + 31) / 32) * 4 +
                 K * (sizeof(RefineState) + sizeof(LbfgsState) +
                      REF_TMAX * (sizeof(RefineTrial) + REF_EVAL_PARTS * sizeof(RefineEval))) +

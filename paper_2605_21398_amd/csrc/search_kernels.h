@@ -6,8 +6,10 @@
 
 namespace regdock {
 
-// per-plane candidates kept by pass 3, candidates re-scored per rotation
+// per-plane candidates kept by pass 3 (plus one bound per plane), candidates
+// re-scored per rotation
 constexpr int KTOP = 4;
+constexpr int KREC = KTOP + 1;
 constexpr int CMAX = 16;
 // Exact low-frequency block: frequencies with max(|kx|, |ky|, |kz|) <= KLOW are
 // taken out of the float32 FFT path and carried in double (they hold nearly all
@@ -39,7 +41,7 @@ struct SearchBatchArgs {
     double2* lowT;             // [count][n][NLOW2] per-plane low 2D DFT of S_r (double)
     const double2* Wlow;       // [NLOW3] conj(F(O)) / n^3 on the low block (double)
     double2* Plow;             // [count][NLOW3] exact product on the low block
-    unsigned long long* ptop;  // [count][n][KTOP] per-plane best keys (score bits, ~flat)
+    unsigned long long* ptop;  // [count][n][KREC] per plane: best keys (score bits, ~flat), then the bound (double bits)
     double* pssq;              // [count][n] per-plane sums of squares of the field
     float* corr_out;           // optional: full float32 field of a 1-rotation batch
     hipStream_t stream;

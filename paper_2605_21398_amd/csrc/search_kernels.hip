@@ -22,10 +22,13 @@
 //   pass2  k_zpass           per (rotation, tile of T z-pencils): FFT along z,
 //                            multiply by W, inverse FFT along z, in LDS
 //   pass3  k_inv_xy_argmax   per (rotation, z-plane): inverse FFT along y,
-//                            complex-to-real along x, plane max with the lowest
-//                            flat index; one 64-bit atomicMax per workgroup into
-//                            the rotation's key (orderable score bits, ~index)
-//   k_finalize               key -> score, shift, pose (FP64)
+//                            complex-to-real along x, the exact low block added
+//                            in double; the plane's four best column maxima
+//                            as keys (orderable score bits, ~index) and a bound
+//                            on every other voxel of the plane
+//   k_select, k_certify,     candidates within the float32 error of each
+//   k_rescore, k_finalize    rotation's maximum, exact re-scoring where that
+//                            error exceeds the tolerance; score, shift, pose
 //
 // Spectrum layout of one rotation (complex64, H = n (n/2 + 1) n elements):
 //   tile t in [0, n * (n/2)/T): ky = t / (n/2/T), kx in [(t % (n/2/T)) T, +T)
@@ -369,6 +372,45 @@ struct RotSampler {
     }
 };
 
+// Trilinear value of a binary lattice cell as a polynomial in the fractions:
+// with bit c = cx + 2 cy + 4 cz of the corner mask holding the lattice value
+// b_c, sum_c b_c prod_axes (c ? f : 1 - f) expands to
+//   c0 + c1 fx + c2 fy + c3 fz + c4 fx fy + c5 fx fz + c6 fy fz + c7 fx fy fz
+// with c0 = b0, c1 = b1 - b0, c2 = b2 - b0, c3 = b4 - b0,
+// c4 = b3 - b1 - b2 + b0, c5 = b5 - b1 - b4 + b0, c6 = b6 - b2 - b4 + b0,
+// c7 = b7 - b3 - b5 - b6 + b1 + b2 + b4 - b0 (small integers).  The table
+// holds them per mask, each scaled by 2^(-32 per fraction factor), so the
+// fractions enter as their raw 32-bit fixed-point words converted to float
+// (powers of two scale exactly).  Entry e: lut[2e] = (c0, c1, c2, c3),
+// lut[2e + 1] = (c4, c5, c6, c7).
+constexpr int TRI_LUT = 2 * 256;  // float4 entries
+
+template <int NT>
+__device__ __forceinline__ void build_trilinear_lut(float4* lut) {
+    const float s1 = 2.3283064365386963e-10f;  // 2^-32
+    const float s2 = s1 * s1, s3 = s2 * s1;
+    for (int e = threadIdx.x; e < 256; e += NT) {
+        int b[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) b[c] = (e >> c) & 1;
+        lut[2 * e] = make_float4((float)b[0], (float)(b[1] - b[0]) * s1, (float)(b[2] - b[0]) * s1,
+                                 (float)(b[4] - b[0]) * s1);
+        lut[2 * e + 1] = make_float4((float)(b[3] - b[1] - b[2] + b[0]) * s2, (float)(b[5] - b[1] - b[4] + b[0]) * s2,
+                                     (float)(b[6] - b[2] - b[4] + b[0]) * s2,
+                                     (float)(b[7] - b[3] - b[5] - b[6] + b[1] + b[2] + b[4] - b[0]) * s3);
+    }
+}
+
+// the polynomial at raw fraction words X, Y, Z (floats of the 32-bit words)
+__device__ __forceinline__ float trilinear_poly(const float4* lut, uint32_t mk, float X, float Y, float Z) {
+    const float4 a = lut[2 * mk], b = lut[2 * mk + 1];
+    const float yz = fmaf(b.w, X, b.z);
+    const float zc = fmaf(b.y, X, a.w);
+    const float yc = fmaf(b.x, X, a.z);
+    const float c0 = fmaf(a.y, X, a.x);
+    return fmaf(fmaf(yz, Y, zc), Z, fmaf(yc, Y, c0));
+}
+
 // Fill the LDS plane with z[j] = S_r[2j] + i S_r[2j+1] for plane z.  The
 // corner-mask loads of several elements are issued together before any is
 // used, so each lane keeps many gathers in flight.
@@ -384,93 +426,63 @@ struct RotSampler {
 // normalised in double at set-up) and |k - n/2| <= n sqrt(3) / 2, so with
 // m = 2 ceil((sqrt(3) n + 2) / 2) every sample lies in [1, m - 1] on each axis
 // (the launcher checks m).  Eight rows per batch keep 16 gathers in flight.
+// Each value is the trilinear polynomial of its cell (table in LDS), with no
+// branch on the mask.
 template <int N>
-__device__ __forceinline__ void generate_plane(float2* plane, const RotSampler& rs, const uint8_t* __restrict__ cmask, int m,
-                                               int mb, int z) {
+__device__ __forceinline__ void generate_plane(float2* plane, const float4* lut, const RotSampler& rs,
+                                               const uint8_t* __restrict__ cmask, int mb, int z) {
     using C = Canvas<N>;
-    constexpr int TOT = N * C::N2;
-    if constexpr (C::N2 <= C::NT) {
-        constexpr int YS = C::NT / C::N2;  // row step of a lane (YS * N2 lanes work, the rest idle)
-        constexpr int G = 8;               // rows per batch of loads
-        const int j = threadIdx.x % C::N2, y0 = threadIdx.x / C::N2;
-        if (threadIdx.x >= YS * C::N2 || y0 >= N) return;
-        const double two32 = 4294967296.0;
-        long long U[2][3], D[3];
-        {
-            const double yc = (double)y0 - rs.hn, zc = (double)z - rs.hn;
+    static_assert(C::N2 <= C::NT, "a plane workgroup covers every column pair");
+    constexpr int YS = C::NT / C::N2;  // row step of a lane (YS * N2 lanes work, the rest idle)
+    constexpr int G = 8;               // rows per batch of loads
+    const int j = threadIdx.x % C::N2, y0 = threadIdx.x / C::N2;
+    if (threadIdx.x >= YS * C::N2 || y0 >= N) return;
+    const double two32 = 4294967296.0;
+    long long U[2][3], D[3];
+    {
+        const double yc = (double)y0 - rs.hn, zc = (double)z - rs.hn;
+        for (int s2 = 0; s2 < 2; ++s2) {
+            const double xc = (double)(2 * j + s2) - rs.hn;
+            U[s2][0] = __double2ll_rn(fma(rs.r00, xc, fma(rs.r01, yc, fma(rs.r02, zc, rs.hm))) * two32);
+            U[s2][1] = __double2ll_rn(fma(rs.r10, xc, fma(rs.r11, yc, fma(rs.r12, zc, rs.hm))) * two32);
+            U[s2][2] = __double2ll_rn(fma(rs.r20, xc, fma(rs.r21, yc, fma(rs.r22, zc, rs.hm))) * two32);
+        }
+        D[0] = __double2ll_rn((double)YS * rs.r01 * two32);
+        D[1] = __double2ll_rn((double)YS * rs.r11 * two32);
+        D[2] = __double2ll_rn((double)YS * rs.r21 * two32);
+    }
+    for (int y = y0; y < N; y += YS * G) {
+        uint32_t addr[2 * G];
+        float fx[2 * G], fy[2 * G], fz[2 * G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+#pragma unroll
             for (int s2 = 0; s2 < 2; ++s2) {
-                const double xc = (double)(2 * j + s2) - rs.hn;
-                U[s2][0] = __double2ll_rn(fma(rs.r00, xc, fma(rs.r01, yc, fma(rs.r02, zc, rs.hm))) * two32);
-                U[s2][1] = __double2ll_rn(fma(rs.r10, xc, fma(rs.r11, yc, fma(rs.r12, zc, rs.hm))) * two32);
-                U[s2][2] = __double2ll_rn(fma(rs.r20, xc, fma(rs.r21, yc, fma(rs.r22, zc, rs.hm))) * two32);
-            }
-            D[0] = __double2ll_rn((double)YS * rs.r01 * two32);
-            D[1] = __double2ll_rn((double)YS * rs.r11 * two32);
-            D[2] = __double2ll_rn((double)YS * rs.r21 * two32);
-        }
-        const float inv32 = 2.3283064365386963e-10f;  // 2^-32
-        for (int y = y0; y < N; y += YS * G) {
-            int addr[2 * G];
-            float fx[2 * G], fy[2 * G], fz[2 * G];
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-#pragma unroll
-                for (int s2 = 0; s2 < 2; ++s2) {
-                    const int q = 2 * g + s2;
-                    const int ix = (int)(U[s2][0] >> 32), iy = (int)(U[s2][1] >> 32), iz = (int)(U[s2][2] >> 32);
-                    fx[q] = (float)(uint32_t)U[s2][0] * inv32;
-                    fy[q] = (float)(uint32_t)U[s2][1] * inv32;
-                    fz[q] = (float)(uint32_t)U[s2][2] * inv32;
-                    addr[q] = y + g * YS < N ? (int)brick_index32(ix, iy, iz, mb) : -1;
-                    U[s2][0] += D[0];
-                    U[s2][1] += D[1];
-                    U[s2][2] += D[2];
-                }
-            }
-            uint32_t mk[2 * G];
-#pragma unroll
-            for (int q = 0; q < 2 * G; ++q) mk[q] = addr[q] >= 0 ? (uint32_t)cmask[addr[q]] : 0u;
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int yy = y + g * YS;
-                if (yy < N) {
-                    const float a = mk[2 * g] ? trilinear_mask(mk[2 * g], fx[2 * g], fy[2 * g], fz[2 * g]) : 0.0f;
-                    const float b =
-                        mk[2 * g + 1] ? trilinear_mask(mk[2 * g + 1], fx[2 * g + 1], fy[2 * g + 1], fz[2 * g + 1]) : 0.0f;
-                    plane[yy * C::P + j] = make_float2(a, b);
-                }
+                const int q = 2 * g + s2;
+                const uint32_t ix = (uint32_t)(U[s2][0] >> 32), iy = (uint32_t)(U[s2][1] >> 32),
+                               iz = (uint32_t)(U[s2][2] >> 32);
+                fx[q] = (float)(uint32_t)U[s2][0];
+                fy[q] = (float)(uint32_t)U[s2][1];
+                fz[q] = (float)(uint32_t)U[s2][2];
+                addr[q] = brick_index32(ix, iy, iz, (uint32_t)mb);
+                U[s2][0] += D[0];
+                U[s2][1] += D[1];
+                U[s2][2] += D[2];
             }
         }
-    } else {
-        constexpr int G = 4;
-        for (int e0 = threadIdx.x; e0 < TOT; e0 += C::NT * G) {
-            long addr[2 * G];
-            float fx[2 * G], fy[2 * G], fz[2 * G];
+        uint32_t mk[2 * G];
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int e = e0 + g * C::NT;
-                const int y = e / C::N2, j = e % C::N2;
-                if (e < TOT) {
-                    addr[2 * g] = rs.locate(m, mb, 2 * j, y, z, fx[2 * g], fy[2 * g], fz[2 * g]);
-                    addr[2 * g + 1] = rs.locate(m, mb, 2 * j + 1, y, z, fx[2 * g + 1], fy[2 * g + 1], fz[2 * g + 1]);
-                } else {
-                    addr[2 * g] = addr[2 * g + 1] = -1;
-                }
-            }
-            uint32_t mk[2 * G];
+        for (int q = 0; q < 2 * G; ++q) {
+            const bool live = (N % (YS * G) == 0) || y + (q / 2) * YS < N;
+            mk[q] = live ? (uint32_t)cmask[addr[q]] : 0u;
+        }
 #pragma unroll
-            for (int q = 0; q < 2 * G; ++q) mk[q] = addr[q] >= 0 ? (uint32_t)cmask[addr[q]] : 0u;
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int e = e0 + g * C::NT;
-                if (e < TOT) {
-                    const int y = e / C::N2, j = e % C::N2;
-                    const float a = mk[2 * g] ? trilinear_mask(mk[2 * g], fx[2 * g], fy[2 * g], fz[2 * g]) : 0.0f;
-                    const float b =
-                        mk[2 * g + 1] ? trilinear_mask(mk[2 * g + 1], fx[2 * g + 1], fy[2 * g + 1], fz[2 * g + 1]) : 0.0f;
-                    plane[y * C::P + j] = make_float2(a, b);
-                }
-            }
+        for (int g = 0; g < G; ++g) {
+            const int yy = y + g * YS;
+            if ((N % (YS * G) == 0) || yy < N)
+                plane[yy * C::P + j] = make_float2(trilinear_poly(lut, mk[2 * g], fx[2 * g], fy[2 * g], fz[2 * g]),
+                                                   trilinear_poly(lut, mk[2 * g + 1], fx[2 * g + 1], fy[2 * g + 1],
+                                                                  fz[2 * g + 1]));
         }
     }
 }
@@ -486,16 +498,23 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_rotvox_fwd_xy
     __shared__ float2 plane[N * C::P];
     __shared__ float2 tw[N];
     __shared__ double2 tws[N];
-    __shared__ double2 rbuf[N * NLX];
+    // the trilinear table is used only while the plane is generated, the
+    // low-block row sums only afterwards: they share one buffer
+    constexpr int RB = N * NLX * (int)sizeof(double2), LB = TRI_LUT * (int)sizeof(float4);
+    __shared__ __align__(16) unsigned char scratch_lds[RB > LB ? RB : LB];
+    double2* rbuf = reinterpret_cast<double2*>(scratch_lds);
+    float4* lut = reinterpret_cast<float4*>(scratch_lds);
     int rot, z;
     map_plane_block(blockIdx.x, count, N, rot, z);
     for (int i = threadIdx.x; i < N; i += C::NT) {
         tw[i] = twg[i];
         tws[i] = tw64[i];
     }
+    build_trilinear_lut<C::NT>(lut);
     RotSampler rs;
     rs.load(rots + rot * 9, m, N);
-    generate_plane<N>(plane, rs, cmask, m, mb, z);
+    __syncthreads();
+    generate_plane<N>(plane, lut, rs, cmask, mb, z);
     __syncthreads();
     plane_low_dft<N>(plane, tws, rbuf, lowT + ((size_t)rot * N + z) * NLOW2);
     plane_forward_and_store<N>(plane, tw, spec + (size_t)rot * C::H, z);
@@ -588,25 +607,10 @@ __global__ __launch_bounds__(256) void k_zpass(float2* __restrict__ spec, const 
 
 // ------------------------------------------------------------------ pass 3
 // Per (rotation, plane): inverse FFT along y, complex-to-real along x, then the
-// plane's four largest keys (orderable score bits, ~flat index) and its sum of
-// squares.  The float32 field only locates candidates; their scores are
-// recomputed exactly by k_rescore.
-
-// branch-free insertion of k into the descending list t0 >= t1 >= t2 >= t3
-__device__ __forceinline__ void top4_insert(unsigned long long k, unsigned long long& t0, unsigned long long& t1,
-                                            unsigned long long& t2, unsigned long long& t3) {
-    unsigned long long a;
-    a = t0 > k ? t0 : k;
-    k = t0 > k ? k : t0;
-    t0 = a;
-    a = t1 > k ? t1 : k;
-    k = t1 > k ? k : t1;
-    t1 = a;
-    a = t2 > k ? t2 : k;
-    k = t2 > k ? k : t2;
-    t2 = a;
-    t3 = t3 > k ? t3 : k;
-}
+// plane's four best column maxima as keys (orderable score bits, ~flat index),
+// a bound on its other voxels and its sum of squares.  The float32 field only
+// locates candidates; their scores are recomputed exactly by k_rescore where
+// its error could exceed the tolerance.
 
 // key = orderable bits of a double, low 22 bits replaced by ~flat (flat < 2^22)
 __device__ __forceinline__ unsigned long long key64(double v, uint32_t flat) {
@@ -633,8 +637,9 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_inv_xy_argmax
     __shared__ double2 btab[N * NLX];
     __shared__ double2 az[NLOW2];
     __shared__ double2 tws[N];
-    __shared__ unsigned long long wtop[NW][KTOP];
+    __shared__ unsigned long long wtop[NW][KTOP + 1];
     __shared__ double wss[NW];
+    __shared__ double wsec[NW];
     int rot, z;
     map_plane_block(blockIdx.x, count, N, rot, z);
     for (int i = threadIdx.x; i < N; i += C::NT) {
@@ -684,81 +689,65 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_inv_xy_argmax
     }
     c2r_pre<N>(plane, tw);
     fft_lds<C::N2, true, N, C::NT, true, N>(plane, 1, C::P, tw);
-    unsigned long long t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+    // Every working lane keeps the same columns x = 2j, 2j+1 (YS n/2 lanes
+    // work, the rest idle), so its low-block phases live in registers.  Each
+    // column of a lane ("virtual lane": x fixed, rows y0, y0 + YS, ...) keeps
+    // its largest value with the lowest row holding it, and the largest value
+    // below that (or equal to it at another row).  The plane then reports the
+    // four best virtual-lane maxima as keys and a bound: the larger of the
+    // fifth-best virtual-lane maximum and every virtual lane's second value.
+    // No voxel outside the four keys exceeds the bound, so a candidate window
+    // that the bound does not reach holds only those keys.
+    static_assert(C::N2 <= C::NT, "a plane workgroup covers every column pair");
+    constexpr int YS = C::NT / C::N2;
+    const int j = threadIdx.x % C::N2;
+    double2 w0[NLX], w1[NLX];
+#pragma unroll
+    for (int k = 1; k < NLX; ++k) {
+        w0[k] = tws[(k * 2 * j) % N];
+        w1[k] = tws[(k * (2 * j + 1)) % N];
+    }
+    double m1a = -INFINITY, m2a = -INFINITY, m1b = -INFINITY, m2b = -INFINITY;
+    int ya = -1, yb = -1;
     float ss = 0.0f;
-    if constexpr (C::N2 <= C::NT) {
-        // every working lane keeps the same x = 2j, 2j+1, so its low-block
-        // phases live in registers (YS n/2 lanes work, the rest are idle)
-        constexpr int YS = C::NT / C::N2;
-        const int j = threadIdx.x % C::N2;
-        double2 w0[NLX], w1[NLX];
+    const int ystart = threadIdx.x < YS * C::N2 ? threadIdx.x / C::N2 : N;
+    for (int y = ystart; y < N; y += YS) {
+        const float2 v = plane[y * C::P + j];
+        const double2* b = btab + y * NLX;
+        double c0 = b[0].x, c1 = b[0].x;
 #pragma unroll
         for (int k = 1; k < NLX; ++k) {
-            w0[k] = tws[(k * 2 * j) % N];
-            w1[k] = tws[(k * (2 * j + 1)) % N];
+            const double2 bk = b[k];
+            c0 = fma(bk.x, w0[k].x, fma(bk.y, w0[k].y, c0));
+            c1 = fma(bk.x, w1[k].x, fma(bk.y, w1[k].y, c1));
         }
-        // value of the fourth key so far: a voxel below it cannot enter the
-        // list, so its key is formed only at or above it
-        double thr = -INFINITY;
-        for (int y = threadIdx.x < YS * C::N2 ? threadIdx.x / C::N2 : N; y < N; y += YS) {
-            const float2 v = plane[y * C::P + j];
+        const double v0 = (double)v.x + c0, v1 = (double)v.y + c1;
+        // rows ascend, so a strict test keeps the lowest row of a tie, and a
+        // tie becomes the second value
+        ya = v0 > m1a ? y : ya;
+        m2a = fmax(m2a, fmin(v0, m1a));
+        m1a = fmax(m1a, v0);
+        yb = v1 > m1b ? y : yb;
+        m2b = fmax(m2b, fmin(v1, m1b));
+        m1b = fmax(m1b, v1);
+        ss = fmaf(v.x, v.x, fmaf(v.y, v.y, ss));
+        if (corr_out) {
             const uint32_t flat0 = (uint32_t)(((z * N) + y) * N + 2 * j);
-            const double2* b = btab + y * NLX;
-            double c0 = b[0].x, c1 = b[0].x;
-#pragma unroll
-            for (int k = 1; k < NLX; ++k) {
-                const double2 bk = b[k];
-                c0 = fma(bk.x, w0[k].x, fma(bk.y, w0[k].y, c0));
-                c1 = fma(bk.x, w1[k].x, fma(bk.y, w1[k].y, c1));
-            }
-            const double v0 = (double)v.x + c0, v1 = (double)v.y + c1;
-            if (v0 >= thr || v1 >= thr) {
-                const unsigned long long k0 = key64(v0, flat0), k1 = key64(v1, flat0 + 1);
-                if (k0 > t3) top4_insert(k0, t0, t1, t2, t3);
-                if (k1 > t3) top4_insert(k1, t0, t1, t2, t3);
-                thr = t3 ? key_value(t3) : -INFINITY;
-            }
-            ss = fmaf(v.x, v.x, fmaf(v.y, v.y, ss));
-            if (corr_out) {
-                corr_out[flat0] = (float)v0;
-                corr_out[flat0 + 1] = (float)v1;
-            }
-        }
-    } else {
-        double thr = -INFINITY;  // as in the path above
-        for (int e = threadIdx.x; e < N * C::N2; e += C::NT) {
-            const int y = e / C::N2, j = e % C::N2;
-            const float2 v = plane[y * C::P + j];
-            const uint32_t flat0 = (uint32_t)(((z * N) + y) * N + 2 * j);
-            // field of the low block at x = 2j, 2j+1: Re b0 + 2 sum_kx Re(b_kx e^{+2 pi i kx x / N})
-            const double2* b = btab + y * NLX;
-            double c0 = b[0].x, c1 = b[0].x;
-#pragma unroll
-            for (int k = 1; k < NLX; ++k) {
-                const double2 bk = b[k];
-                const double2 w0 = tws[(k * 2 * j) % N], w1 = tws[(k * (2 * j + 1)) % N];
-                c0 = fma(bk.x, w0.x, fma(bk.y, w0.y, c0));
-                c1 = fma(bk.x, w1.x, fma(bk.y, w1.y, c1));
-            }
-            const double v0 = (double)v.x + c0, v1 = (double)v.y + c1;
-            if (v0 >= thr || v1 >= thr) {
-                const unsigned long long k0 = key64(v0, flat0), k1 = key64(v1, flat0 + 1);
-                if (k0 > t3) top4_insert(k0, t0, t1, t2, t3);
-                if (k1 > t3) top4_insert(k1, t0, t1, t2, t3);
-                thr = t3 ? key_value(t3) : -INFINITY;
-            }
-            ss = fmaf(v.x, v.x, fmaf(v.y, v.y, ss));
-            if (corr_out) {
-                corr_out[flat0] = (float)v0;
-                corr_out[flat0 + 1] = (float)v1;
-            }
+            corr_out[flat0] = (float)v0;
+            corr_out[flat0 + 1] = (float)v1;
         }
     }
-    // wave: merge the 64 sorted lists by four rounds of a wave maximum; the
-    // lane holding the maximum (keys are unique) shifts its list up
-    unsigned long long wt[KTOP];
+    // each lane: its two virtual-lane maxima as keys, sorted
+    const uint32_t rowbase = (uint32_t)(z * N) * N;
+    unsigned long long ka = ya >= 0 ? key64(m1a, rowbase + (uint32_t)(ya * N + 2 * j)) : 0ull;
+    unsigned long long kb = yb >= 0 ? key64(m1b, rowbase + (uint32_t)(yb * N + 2 * j + 1)) : 0ull;
+    unsigned long long t0 = ka > kb ? ka : kb, t1 = ka > kb ? kb : ka;
+    double sec = fmax(m2a, m2b);
+    // wave: five rounds of a wave maximum over the lanes' list heads; the lane
+    // holding the maximum (keys are unique) shifts its list up
+    unsigned long long wt[KTOP + 1];
 #pragma unroll
-    for (int r = 0; r < KTOP; ++r) {
+    for (int r = 0; r < KTOP + 1; ++r) {
         unsigned long long mx = t0;
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
@@ -767,33 +756,46 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_inv_xy_argmax
         }
         const bool mine = t0 == mx && mx != 0ull;
         t0 = mine ? t1 : t0;
-        t1 = mine ? t2 : t1;
-        t2 = mine ? t3 : t2;
-        t3 = mine ? 0ull : t3;
+        t1 = mine ? 0ull : t1;
         wt[r] = mx;
     }
     double ds = (double)ss;
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) ds += __shfl_xor(ds, off, 64);
+    for (int off = 32; off >= 1; off >>= 1) {
+        ds += __shfl_xor(ds, off, 64);
+        sec = fmax(sec, __shfl_xor(sec, off, 64));
+    }
     const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-        for (int r = 0; r < KTOP; ++r) wtop[wave][r] = wt[r];
+        for (int r = 0; r < KTOP + 1; ++r) wtop[wave][r] = wt[r];
         wss[wave] = ds;
+        wsec[wave] = sec;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long b0 = 0, b1 = 0, b2 = 0, b3 = 0;
-        double tot = 0.0;
+        unsigned long long b0 = 0, b1 = 0, b2 = 0, b3 = 0, b4 = 0;
+        double tot = 0.0, bound = -INFINITY;
         for (int w = 0; w < NW; ++w) {
-            for (int r = 0; r < KTOP; ++r) top4_insert(wtop[w][r], b0, b1, b2, b3);
+            for (int r = 0; r < KTOP + 1; ++r) {
+                // insertion into the descending five b0..b4
+                unsigned long long k = wtop[w][r], x;
+                x = b0 > k ? b0 : k; k = b0 > k ? k : b0; b0 = x;
+                x = b1 > k ? b1 : k; k = b1 > k ? k : b1; b1 = x;
+                x = b2 > k ? b2 : k; k = b2 > k ? k : b2; b2 = x;
+                x = b3 > k ? b3 : k; k = b3 > k ? k : b3; b3 = x;
+                b4 = b4 > k ? b4 : k;
+            }
             tot += wss[w];
+            bound = fmax(bound, wsec[w]);
         }
-        unsigned long long* o = ptop + ((size_t)rot * N + z) * KTOP;
+        if (b4) bound = fmax(bound, key_value(b4));
+        unsigned long long* o = ptop + ((size_t)rot * N + z) * KREC;
         o[0] = b0;
         o[1] = b1;
         o[2] = b2;
         o[3] = b3;
+        o[KTOP] = (unsigned long long)__double_as_longlong(bound);
         pssq[(size_t)rot * N + z] = tot;
     }
 }
@@ -802,8 +804,9 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_inv_xy_argmax
 // from the keys), the RMS of the float32 part (from the plane sums of squares),
 // the window 2 eps with eps = REGK_EPS_SCALE * 2^-24 * rms * log2(n^3) bounding
 // the float32 error, and every key inside [v - 2 eps, v] as a candidate (at
-// most CMAX, in descending key order).  If a plane's fourth key is still inside
-// the window the plane may hold more: the rotation is marked as overflowed.
+// most CMAX, in descending key order).  If a plane's bound (no voxel of the
+// plane besides its keys exceeds it) reaches the window, the plane may hold
+// more: the rotation is marked as overflowed.
 __global__ __launch_bounds__(256) void k_select(const unsigned long long* __restrict__ ptop, const double* __restrict__ pssq,
                                                 int n, double eps_per_rms, int base, int32_t* __restrict__ cand_idx,
                                                 int32_t* __restrict__ cand_n, double* __restrict__ window,
@@ -815,9 +818,9 @@ __global__ __launch_bounds__(256) void k_select(const unsigned long long* __rest
     __shared__ unsigned long long list[CMAX];
     __shared__ int overflow;
     const int rot = blockIdx.x, r = base + blockIdx.x;
-    const unsigned long long* T = ptop + (size_t)rot * n * KTOP;
+    const unsigned long long* T = ptop + (size_t)rot * n * KREC;
     unsigned long long mx = 0;
-    for (int zz = threadIdx.x; zz < n; zz += 256) mx = T[zz * KTOP] > mx ? T[zz * KTOP] : mx;
+    for (int zz = threadIdx.x; zz < n; zz += 256) mx = T[zz * KREC] > mx ? T[zz * KREC] : mx;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         const unsigned long long o = __shfl_xor(mx, off, 64);
@@ -843,12 +846,13 @@ __global__ __launch_bounds__(256) void k_select(const unsigned long long* __rest
     }
     __syncthreads();
     const double thr = thr_s;
-    for (int i = threadIdx.x; i < n * KTOP; i += 256) {
+    for (int i = threadIdx.x; i < n * KREC; i += 256) {
         const unsigned long long k = T[i];
-        if (k != 0ull && key_value(k) >= thr) {
+        if (i % KREC == KTOP) {
+            if (__longlong_as_double((long long)k) >= thr) overflow = 1;
+        } else if (k != 0ull && key_value(k) >= thr) {
             const int slot = atomicAdd(&cnt, 1);
             if (slot < CMAX) list[slot] = k;
-            if ((i % KTOP) == KTOP - 1) overflow = 1;
         }
     }
     __syncthreads();
