@@ -24,6 +24,8 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# the oracle's processes run one BLAS thread each (set before numpy loads)
+os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
 
 HBM_PEAK_GBPS = 8000.0
 METRIC = "SO(3) rotations scored/sec at 128^3 (GB/s vs HBM peak); p50/p99 request latency"
@@ -35,38 +37,86 @@ def workload_name(p, cfg):
             f"{len(p.vertices)}-vertex mesh")
 
 
-def cpu_baseline(p, n_sample: int, starts, evals: int):
-    """The FP64 oracle on its own: setup grids + n_sample strided rotations,
-    extrapolated linearly to the full rotation set, plus one objective
-    evaluation of the refinement at the first start, scaled by the number of
-    evaluations the refinement of all starts made."""
-    import numpy as np
+_ORC = {}
 
-    from oracle import refine as Rf
+
+def _oracle_rotation(r):
+    """One rotation of the oracle's search (grids from the pool's parent)."""
+    from oracle import search as S
+    g = _ORC
+    t = time.perf_counter()
+    S.score_rotation(g["O"], g["Sw"], g["so3"][r], g["n"], g["h"], g["a"], g["wc"])
+    return time.perf_counter() - t
+
+
+def host_cores() -> int:
+    """Host cores the oracle's process pool uses: the CPU share of the process
+    (at most 16, the share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def oracle_search_rate(p, n_sample: int, cores: int):
+    """The oracle's search on `n_sample` strided rotations of p: (setup s,
+    rotations/s on `cores` processes (numpy FFTs, one thread each), rotations)."""
+    import multiprocessing as mp
+
     from oracle import search as S
     t0 = time.perf_counter()
     O, _, _ = S.object_grid(p.vertices, p.faces, p.touchable, p.n, p.h)
     Sw = S.swept_occupancy(S.swept_lattice(p.poses, p.radius, p.length, S.lattice_edge(p.n), p.h, p.center))
-    t1 = time.perf_counter()
-    a = S.anchor(p.vertices)
+    setup = time.perf_counter() - t0
+    _ORC.update(O=O, Sw=Sw, so3=p.so3, n=p.n, h=p.h, a=S.anchor(p.vertices), wc=p.center)
     M = len(p.so3)
     idx = list(range(0, M, max(1, M // n_sample)))[:n_sample]
-    for r in idx:
-        S.score_rotation(O, Sw, p.so3[r], p.n, p.h, a, p.center)
-    t2 = time.perf_counter()
-    per_rot = (t2 - t1) / len(idx)
+    t1 = time.perf_counter()
+    if cores == 1:
+        for r in idx:
+            _oracle_rotation(r)
+    else:
+        with mp.get_context("fork").Pool(cores) as pool:
+            pool.map(_oracle_rotation, idx, chunksize=1)
+    return setup, len(idx) / (time.perf_counter() - t1), len(idx)
+
+
+def cpu_baseline(p, args, starts, evals: int, small):
+    """The FP64 oracle as it stands, on the host cores.  The headline workload:
+    setup grids, a strided sample of rotations on a pool over all cores
+    (extrapolated linearly to the full set) and one refinement objective
+    evaluation times the number the refinement of all starts made; the same
+    search on one core; the two smaller workloads' searches."""
+    import numpy as np
+
+    from oracle import refine as Rf
+    from oracle import search as S
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    cores = host_cores()
+    setup, rate, n_all = oracle_search_rate(p, args.cpu_sample, cores)
+    _, rate1, n_one = oracle_search_rate(p, max(2, args.cpu_sample // 32), 1)
+    M = len(p.so3)
+    a = S.anchor(p.vertices)
     q = starts[0]
     pb = Rf.Problem(p.vertices, p.faces, p.poses, p.radius, p.length, S.quat_to_mat(q[:4]), q[4:], a)
     t3 = time.perf_counter()
     Rf.evaluate(np.zeros(6), pb)
     per_eval = time.perf_counter() - t3
-    full = (t1 - t0) + M * per_rot + evals * per_eval
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": M / full, "unit": "rotations/s", "cores": threads, "kind": "oracle",
-            "sample": (f"object grid + swept lattice ({t1 - t0:.2f} s), {len(idx)} of {M} rotations "
-                       f"({per_rot:.3f} s each, one thread, numpy FFT in FP64) extrapolated to all {M}, and one "
-                       f"refinement objective evaluation ({per_eval:.2f} s, distance queries on {threads} OpenMP "
-                       f"threads) times the {evals} evaluations of the {len(starts)} starts")}
+    full = setup + M / rate + evals * per_eval
+    omp = int(os.environ.get("OMP_NUM_THREADS", "1"))
+    out = {"value": M / full, "unit": "rotations/s", "cores": cores, "kind": "oracle",
+           "sample": (f"object grid + swept lattice ({setup:.2f} s), {n_all} strided rotations of {M} on a pool of "
+                      f"{cores} processes (numpy FFTs in FP64, one thread each: {rate:.2f} rotations/s) extrapolated "
+                      f"to all {M}, and one refinement objective evaluation ({per_eval:.2f} s, distance queries on "
+                      f"{omp} OpenMP thread(s)) times the {evals} evaluations of the {len(starts)} starts"),
+           "search_rotations_per_s": {"all_cores": rate, "one_core": rate1, "cores": cores,
+                                      "rotations_timed": {"all_cores": n_all, "one_core": n_one}}}
+    for cfg, q_small in small.items():
+        _, r, n = oracle_search_rate(q_small, len(q_small.so3) if cfg == 1 else 128, cores)
+        out[f"config{cfg}_search_rotations_per_s"] = {"value": r, "rotations_timed": n, "cores": cores,
+                                                      "n": q_small.n}
+    return out
 
 
 def counter_traffic(kernel: str, n: int):
@@ -113,9 +163,11 @@ def generate(args):
         if args.batch > 0:
             jobs["batch"] = pool.map_async(_gen_batch, range(args.batch))
         if args.serve > 0:
-            jobs["serve"] = pool.map_async(_gen_serve, range(args.serve))
+            jobs["serve"] = pool.map_async(_gen_serve, range(args.serve_pool))
+        small = {c: pool.apply_async(synth.config_problem, (c,)) for c in (1, 2) if c != args.config}
         main_p = synth.config_problem(args.config)
         out = {k: v.get() for k, v in jobs.items()}
+        out["small"] = {c: v.get() for c, v in small.items()}
     out["main"] = main_p
     return out
 
@@ -164,52 +216,118 @@ def batch_bench(rd, torch, probs, args):
             "work": "per registration: every rotation scored, top-16, refinement of the 16 starts"}
 
 
-def serve_bench(rd, reqs, args):
-    """A Poisson stream of registrations through the server, serial (one at a
-    time, the plain path) and continuous (several in flight on their own
-    streams), at the workload's overloaded rate and at a rate the serial path
-    sustains; latency = completion - submission."""
+def _serve_run(rd, pool, arrivals, pick, mode, slots, window=None):
+    """Feed Poisson arrivals (times in s; request i takes pool[pick[i]]) to a
+    server and collect the results.  With a window (s), submission stops at
+    its end, the server is closed once the requests running then finish (the
+    queue is cancelled), and only requests completed inside the window count.
+    Returns (results, wall s, queue-depth samples (t, queued, running),
+    offered rotations)."""
     import threading
 
+    srv = rd.Server(max_inflight=slots, mode=mode)
+    tickets, depth = [], []
+    t0 = time.perf_counter()
+    stop = threading.Event()
+
+    def feed():
+        for i, t in enumerate(arrivals):
+            if window is not None and t > window:
+                break
+            d = t - (time.perf_counter() - t0)
+            if d > 0:
+                time.sleep(d)
+            mid, p = pool[pick[i]]
+            tickets.append((pick[i], srv.submit(p.vertices, p.faces, p.touchable, p.poses, p.so3, p.n, p.h, p.center,
+                                                p.radius, p.length, object_id=mid)))
+
+    def watch():
+        while not stop.is_set():
+            st = srv.stats()
+            depth.append((time.perf_counter() - t0, st["queued"], st["running"]))
+            stop.wait(0.25)
+
+    th, tw = threading.Thread(target=feed), threading.Thread(target=watch)
+    th.start()
+    tw.start()
+    th.join()
+    res = []
+    if window is None:
+        res = [(k, srv.wait(t)) for k, t in tickets]
+        wall = time.perf_counter() - t0
+    else:
+        end_ns = None
+        while time.perf_counter() - t0 < window:
+            time.sleep(0.01)
+        for k, t in tickets:
+            r = srv.poll(t)
+            if r is not None:
+                res.append((k, r))
+        wall = window
+    stop.set()
+    tw.join()
+    st = srv.stats()
+    srv.close()
+    offered = sum(len(pool[pick[i]][1].so3) for i in range(len(tickets)))
+    return res, wall, depth, offered, st
+
+
+def serve_bench(rd, pool, args):
+    """Poisson streams of registrations (config 5's size mix: requests drawn
+    from a pool of pre-generated ones, 20 objects) through the server, serial
+    (one at a time, the plain path) against continuous (shared search streams,
+    least remaining work first): at a rate the serial path sustains, every
+    request timed from submission to completion; and at the workload's 200/s
+    over a fixed window, offered against served rotations/s and the queue
+    depth."""
     import numpy as np
 
     import synth
-    runs = []
-    for rate in (args.serve_rate, args.serve_sustained):
-        if rate <= 0:
-            continue
-        arr = synth.serve_arrivals(len(reqs), rate)
-        run = {"offered_per_s": rate}
+    # serial service time of the pool (each request once, after a warm pass)
+    srv = rd.Server(mode="serial")
+    try:
+        for mid, p in pool[:4]:
+            srv.wait(srv.submit(p.vertices, p.faces, p.touchable, p.poses, p.so3, p.n, p.h, p.center, p.radius,
+                                p.length, object_id=mid))
+        svc = []
+        for mid, p in pool:
+            r = srv.wait(srv.submit(p.vertices, p.faces, p.touchable, p.poses, p.so3, p.n, p.h, p.center, p.radius,
+                                    p.length, object_id=mid))
+            svc.append((r["t_end_ns"] - r["t_start_ns"]) / 1e9)
+    finally:
+        srv.close()
+    mean_svc = float(np.mean(svc))
+    capacity = 1.0 / mean_svc
+    out = {"pool": len(pool), "pool_rotations": sum(len(p.so3) for _, p in pool),
+           "serial_service_ms": {"mean": mean_svc * 1e3, "p50": float(np.percentile(svc, 50)) * 1e3,
+                                 "max": float(np.max(svc)) * 1e3},
+           "serial_capacity_per_s": capacity, "runs": []}
+    rate = args.serve_load * capacity
+    for label, r, count, window in (("sustained", rate, args.serve, None),
+                                    ("overloaded", args.serve_rate, int(args.serve_rate * args.serve_window) + 1,
+                                     args.serve_window)):
+        arr = synth.serve_arrivals(count, r)
+        pick = synth.serve_picks(count, len(pool))
+        run = {"label": label, "offered_per_s": r, "arrivals": int(np.sum(arr <= window)) if window else count}
+        if window:
+            run["window_s"] = window
         for mode, slots in (("serial", 1), ("continuous", args.serve_slots)):
-            srv = rd.Server(max_inflight=slots, mode=mode)
-            tickets = [None] * len(reqs)
-            t0 = time.perf_counter()
-
-            def feed():
-                for i, (mid, p) in enumerate(reqs):
-                    d = arr[i] - (time.perf_counter() - t0)
-                    if d > 0:
-                        time.sleep(d)
-                    tickets[i] = srv.submit(p.vertices, p.faces, p.touchable, p.poses, p.so3, p.n, p.h, p.center,
-                                            p.radius, p.length, object_id=mid)
-
-            th = threading.Thread(target=feed)
-            th.start()
-            th.join()
-            res = [srv.wait(t) for t in tickets]
-            wall = time.perf_counter() - t0
-            st = srv.stats()
-            srv.close()
-            lat = np.array([(r["t_end_ns"] - r["t_submit_ns"]) / 1e6 for r in res])
-            busy = np.array([(r["t_end_ns"] - r["t_start_ns"]) / 1e6 for r in res])
-            run[mode] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                         "mean_run_ms": float(busy.mean()), "served_per_s": len(res) / wall, "slots": slots,
-                         "cache_hits": st["cache_hits"], "cache_misses": st["cache_misses"]}
-        runs.append(run)
-        print(f"bench: serving at {rate}/s done", file=sys.stderr, flush=True)
-    return {"requests": len(reqs), "rotations": sum(len(p.so3) for _, p in reqs), "runs": runs,
-            "workload": ("Poisson arrivals; 20 objects; 90 % canvases 48..128 with 512..4096 rotations, 10 % 160^3 "
-                         "with 8192; 300..2000 probe poses; search + top-16 + refinement per request")}
+            res, wall, depth, offered, st = _serve_run(rd, pool, arr, pick, mode, slots, window)
+            lat = np.array([(x["t_end_ns"] - x["t_submit_ns"]) / 1e6 for _, x in res]) if res else np.zeros(1)
+            served_rot = sum(len(pool[k][1].so3) for k, _ in res)
+            d = np.array([q for _, q, _ in depth]) if depth else np.zeros(1)
+            run[mode] = {"completed": len(res), "p50_ms": float(np.percentile(lat, 50)),
+                         "p99_ms": float(np.percentile(lat, 99)), "served_per_s": len(res) / wall,
+                         "offered_rotations_per_s": offered / wall, "served_rotations_per_s": served_rot / wall,
+                         "queue_depth": {"mean": float(d.mean()), "max": int(d.max()), "last": int(d[-1])},
+                         "slots": slots, "cache_hits": st["cache_hits"], "cache_misses": st["cache_misses"]}
+            print(f"bench: serving {label} {mode} done", file=sys.stderr, flush=True)
+        out["runs"].append(run)
+    out["workload"] = ("Poisson arrivals; requests drawn from a pool of pre-generated ones with config 5's mix: "
+                       "20 objects; 90 % canvases 48..128 with 512..4096 rotations, 10 % 160^3 with 8192; "
+                       "300..2000 probe poses; search + top-16 + refinement per request; the sustained rate is "
+                       f"{args.serve_load:.2f} x the serial capacity measured on the pool")
+    return out
 
 
 def local_search_bench(rd, torch, p, args):
@@ -253,6 +371,44 @@ def local_search_bench(rd, torch, p, args):
                 "rotation_error_deg": {"global": angle_deg(q_star), "local": angle_deg(po2[b, :4])}}
     finally:
         rd.register_free(h)
+
+
+def small_config_bench(rd, torch, probs, reps: int = 5):
+    """The smaller workloads' searches (32^3 with 64 rotations, 64^3 with 1024):
+    rotations/s of score_rotations over all rotations with the tuned schedule,
+    and the model HBM traffic rate (4 half-spectra per rotation plus the object
+    spectrum once per batch); at these sizes the intermediates stay in the
+    L2/MALL caches, so the HBM roofline does not bind."""
+    out = {}
+    for cfg, p in sorted(probs.items()):
+        h = rd.register_init(p.vertices, p.faces, p.touchable, p.poses, p.so3, p.n, p.h, p.center, p.radius,
+                             p.length)
+        try:
+            rd.register_autotune(h, len(p.so3))
+        finally:
+            rd.register_free(h)
+        h = rd.register_init(p.vertices, p.faces, p.touchable, p.poses, p.so3, p.n, p.h, p.center, p.radius,
+                             p.length)
+        try:
+            rd.score_rotations(h, shift=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                rd.score_rotations(h, shift=False)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            info = rd.register_info(h)
+            st = rd.register_search_stats(h)
+        finally:
+            rd.register_free(h)
+        M = len(p.so3)
+        H8 = info["spectrum_elems"] * 8
+        model = (4 * H8 + H8 / info["batch"]) * M
+        out[f"config{cfg}"] = {"workload": workload_name(p, cfg), "rotations_per_s": M / dt, "ms_per_call": dt * 1e3,
+                               "model_GBps": model / dt / 1e9, "model_frac": model / dt / 1e9 / HBM_PEAK_GBPS,
+                               "schedule": rd.register_tuned_schedule(p.n),
+                               "search_stats_per_call": {k: v / (reps + 1) for k, v in st.items()}}
+    return out
 
 
 def _pose_errors(p, po):
@@ -390,14 +546,18 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=8, help="oracle rotations in the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=256,
+                    help="strided oracle rotations of the headline workload in the CPU baseline (0: skip)")
+    ap.add_argument("--tune", type=int, default=1, help="autotune the search schedule before timing (0: defaults)")
+    ap.add_argument("--small", type=int, default=1, help="time the 32^3 and 64^3 workloads too (0: skip)")
     ap.add_argument("--batch", type=int, default=32, help="registrations of the uneven batch (0: skip)")
     ap.add_argument("--batch-reps", type=int, default=2)
-    ap.add_argument("--serve", type=int, default=48, help="requests of the serving run (0: skip)")
-    ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate (requests/s)")
-    ap.add_argument("--serve-sustained", type=float, default=6.0,
-                    help="a second arrival rate below the serial path's capacity (0: skip)")
-    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve", type=int, default=600, help="requests of the sustained serving run (0: skip serving)")
+    ap.add_argument("--serve-pool", type=int, default=64, help="pre-generated requests the arrivals draw from")
+    ap.add_argument("--serve-load", type=float, default=0.7, help="sustained rate as a share of the serial capacity")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="overloaded Poisson arrival rate (requests/s)")
+    ap.add_argument("--serve-window", type=float, default=8.0, help="seconds of arrivals at the overloaded rate")
+    ap.add_argument("--serve-slots", type=int, default=6)
     ap.add_argument("--variants", type=int, default=1,
                     help="Super-Fibonacci vs Sobol->Hopf and padded linear correlation (0: skip)")
     ap.add_argument("--solvers", type=int, default=1, help="compare Gauss-Newton and L-BFGS-B refinement (0: skip)")
@@ -436,6 +596,13 @@ def main():
     K_TOP = 16
     stats = {k: [0.0, 0, 0] for k in KERNELS}
     info = {}
+    if args.tune:
+        h = rd.register_init(V, F, T, P, Q, p.n, p.h, p.center, p.radius, p.length)
+        try:
+            rd.register_autotune(h, 512)
+        finally:
+            rd.register_free(h)
+        print("bench: schedule tuned", file=sys.stderr, flush=True)
 
     refine_s = []
     score_wall = []
@@ -468,6 +635,7 @@ def main():
         info["J"] = res[1].cpu().numpy()
         info["refined"] = res[0].cpu().numpy()
         info.update(rd.register_refine_stats(h))
+        info["search_stats"] = rd.register_search_stats(h)
         rd.register_free(h)
         return sc, top
 
@@ -507,6 +675,7 @@ def main():
     # the two lanes of the search overlap batches, so the kernels' event times
     # add up to more than the phase's wall time
     score_s = float(np.mean(score_wall))
+    sched = rd.register_tuned_schedule(p.n)
     model_bytes = (4 * H8 + H8 / B) * M
     out = {
         "metric": METRIC, "value": value, "unit": "rotations/s", "n_gpus": 1, "steps": args.steps,
@@ -518,15 +687,17 @@ def main():
                      "unit": "GB/s", "frac": d["achieved_GBps"] / HBM_PEAK_GBPS,
                      "traffic": counter_traffic(dom, p.n) if d["rotations_per_launch"] == 32 else None,
                      "algorithmic_bytes_per_launch": d["algorithmic_bytes_per_launch"],
-                     "note": "per-launch time in the timed region, where the two lanes' passes share the GPU; "
-                             "'isolated' times the same launch alone"},
+                     "note": ("per-launch time in the timed region" +
+                              (", where the two lanes' passes share the GPU; 'isolated' times the same launch alone"
+                               if sched["lanes"] > 1 else "; one lane, so each launch has the GPU to itself"))},
         "latency_ms": {"p50": float(np.percentile(lat, 50)) * 1e3, "p99": float(np.percentile(lat, 99)) * 1e3,
                        "mode": "serial, one request at a time"},
         "score_phase": {"ms_per_step": score_s * 1e3, "rotations_per_s": M / score_s,
                         "model_GBps": model_bytes / score_s / 1e9, "model_frac": model_bytes / score_s / 1e9 / HBM_PEAK_GBPS,
                         "kernel_ms_per_step": tot / args.steps,
-                        "lanes": "two streams; batches alternate, so a launch's duration includes the time it "
-                                 "shares the GPU with the other lane's passes"},
+                        "lanes": sched["lanes"]},
+        "schedule": sched,
+        "search_stats": info["search_stats"],
         "kernels": kern,
         "refine": {"ms_per_step": float(np.mean(refine_s)) * 1e3, "starts": K_TOP, "rounds": info["rounds"],
                    "evaluations": info["evaluations"], "accepted_steps": [int(x) for x in info["iters"]],
@@ -562,8 +733,12 @@ def main():
     if args.serve > 0:
         out["serving"] = serve_bench(rd, work["serve"], args)
         print("bench: serving done", file=sys.stderr, flush=True)
+    if args.small and work.get("small"):
+        out["configs"] = small_config_bench(rd, torch, work["small"])
+        print("bench: smaller workloads done", file=sys.stderr, flush=True)
     if args.cpu_sample > 0:
-        out["cpu_baseline"] = cpu_baseline(p, args.cpu_sample, info["starts"], int(info["evaluations"]))
+        out["cpu_baseline"] = cpu_baseline(p, args, info["starts"], int(info["evaluations"]), work.get("small", {}))
+        print("bench: cpu baseline done", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 

@@ -83,10 +83,16 @@ typedef struct {
  * tau_out1 0.5 mm, tau_in1 0.2 mm, deep-penetration penalty rho 50 (a deep voxel
  * gets -rho), tau_out2 0.2 mm, tau_in2 0.03 mm, k 15, lambda 1e-3; bounds
  * b_t 0.5 mm and b_r 0.2 rad and the query cutoff eps 0.25 mm are not given by
- * the paper.  batch = rotations per batched launch (0: chosen from n).
- * rescore = 1 re-scores the candidates of every rotation exactly; 0 only those
- * whose float32 error window exceeds the score tolerance (see
- * register_search_stats). */
+ * the paper.  batch = rotations per batched launch (0: the autotuner's choice
+ * for n, else chosen from n).  rescore = 1 re-scores the candidates of every
+ * rotation exactly; 0 only those whose float32 error window exceeds the score
+ * tolerance (see register_search_stats).  The launch schedule (0: the
+ * autotuner's choice for n, else the default): lanes = streams a call's
+ * batches alternate over (1 or 2); plane_variant = workgroup of the two plane
+ * passes, k selecting variant k - 1 of (threads, waves per SIMD) = (256, 1),
+ * (256, 2), (512, 4), (1024, 4) (edges up to 80 take the first three, edges
+ * up to 128 the last three, larger edges the last); z_variant = threads of the z-pencil workgroup, k
+ * selecting 128, 256 or 512. */
 typedef struct {
     double tau_out1, tau_in1, rho;
     double tau_out2, tau_in2, k, lambda;
@@ -94,6 +100,9 @@ typedef struct {
     int32_t max_iters;
     int32_t batch;
     int32_t rescore;
+    int32_t lanes;
+    int32_t plane_variant;
+    int32_t z_variant;
 } reg_params;
 
 /* Build a registration problem (Sec. IV-A): the object grid O and its spectrum
@@ -343,13 +352,30 @@ int register_batch_outputs(reg_batch* b, int32_t i, float* scores, double* poses
                            double* J);
 void register_batch_free(reg_batch* b);
 
-/* Autotuner: times score_rotations on the handle's own problem (its first
- * max_rotations rotations, 0: 512) for rotation batches of 8..256 that fit in
- * device memory and records the fastest for the handle's canvas edge; later
- * register_init calls with params.batch = 0 use it.  Synchronous. */
+/* Autotuner of the search schedule for the handle's canvas edge, timed on
+ * the handle's own problem (its first max_rotations rotations, 0: 512) with
+ * HIP events: every valid plane-workgroup variant for pass 1 and for pass 3
+ * and every z-workgroup variant (each pass timed alone), then rotation
+ * batches of 8..512 (up to the rotations timed, within 4 GB of work buffers)
+ * on one and on two lanes with the chosen kernels, the whole search timed.
+ * The fastest schedule is recorded for the edge; later register_init calls
+ * whose params leave a field at 0 take it.  *out_batch receives the batch.
+ * Synchronous.  Errors: REG_EINVAL, REG_ENOMEM, REG_EDEVICE. */
 int register_autotune(reg_handle* h, int32_t max_rotations, int32_t* out_batch);
 /* the recorded batch for canvas edge n, 0 if none */
 int register_tuned_batch(int32_t n);
+/* The recorded schedule for edge n: out[0] batch, out[1] lanes, out[2] pass-1
+ * plane variant, out[3] pass-3 plane variant, out[4] z variant (variants
+ * numbered from 0 as in reg_params, less one); out[5..7] the best times (us
+ * per rotation) of pass 1, the z pass and pass 3; out[8] the whole search (ns
+ * per rotation).  Returns 1 if a schedule is recorded, 0 if not (out is then
+ * filled with the defaults), or REG_EINVAL. */
+int register_tuned_schedule(int32_t n, double* out);
+/* Save every recorded schedule to a JSON file (one object per edge), or load
+ * such a file (entries for unsupported edges or invalid variants are
+ * skipped).  Errors: REG_EINVAL (NULL path, unreadable or malformed file). */
+int register_tune_save(const char* path);
+int register_tune_load(const char* path);
 
 /* ------------------------------------------------------------------ serving
  *

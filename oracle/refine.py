@@ -253,6 +253,7 @@ class RefineResult:
     J: float
     iters: int
     xi: np.ndarray
+    mu: float = 0.0   # damping when the iteration stopped (Gauss-Newton)
 
 
 def refine(pb: Problem, prm: RefineParams = RefineParams()) -> RefineResult:
@@ -285,7 +286,7 @@ def refine(pb: Problem, prm: RefineParams = RefineParams()) -> RefineResult:
             break
         J, g, H = evaluate(xi, pb, prm)
     R, p = pose_of(xi, pb.R0, pb.p0, pb.a)
-    return RefineResult(R=R, p=p, J=J, iters=it, xi=xi)
+    return RefineResult(R=R, p=p, J=J, iters=it, xi=xi, mu=mu)
 
 
 def refine_lbfgsb(pb: Problem, prm: RefineParams = RefineParams(), memory: int = 10, gtol: float = 1e-9,

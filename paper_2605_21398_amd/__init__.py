@@ -28,7 +28,8 @@ EXPORTS = ["register_init", "score_rotations", "register_top_k", "register_free"
            "refine_se3", "register_debug_distance", "register_refine_stats", "register_server_create",
            "register_server_destroy", "register_submit", "register_poll", "register_wait", "register_server_stats",
            "register_server_last_error", "register_batch_create", "register_batch_run", "register_batch_outputs",
-           "register_batch_free", "register_autotune", "register_tuned_batch", "register_cached_bytes",
+           "register_batch_free", "register_autotune", "register_tuned_batch", "register_tuned_schedule",
+           "register_tune_save", "register_tune_load", "register_cached_bytes",
            "register_release_cached", "so3_super_fibonacci", "so3_geoball_sf", "so3_geoball_sf_noalloc",
            "register_set_rotations",
            "refine_se3_lbfgsb", "register_linear_edge"]
@@ -58,7 +59,8 @@ class reg_params(ctypes.Structure):
                 ("tau_out2", ctypes.c_double), ("tau_in2", ctypes.c_double), ("k", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("b_t", ctypes.c_double), ("b_r", ctypes.c_double),
                 ("eps", ctypes.c_double), ("max_iters", ctypes.c_int32), ("batch", ctypes.c_int32),
-                ("rescore", ctypes.c_int32)]
+                ("rescore", ctypes.c_int32), ("lanes", ctypes.c_int32), ("plane_variant", ctypes.c_int32),
+                ("z_variant", ctypes.c_int32)]
 
 
 class reg_server_cfg(ctypes.Structure):
@@ -180,6 +182,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.register_autotune.argtypes = [p, i32, ctypes.POINTER(i32)]
     L.register_tuned_batch.restype = ctypes.c_int
     L.register_tuned_batch.argtypes = [i32]
+    L.register_tuned_schedule.restype = ctypes.c_int
+    L.register_tuned_schedule.argtypes = [i32, p]
+    L.register_tune_save.restype = ctypes.c_int
+    L.register_tune_save.argtypes = [ctypes.c_char_p]
+    L.register_tune_load.restype = ctypes.c_int
+    L.register_tune_load.argtypes = [ctypes.c_char_p]
     _lib = L
     return L
 
@@ -519,6 +527,33 @@ def register_autotune(h: Handle, max_rotations: int = 512) -> int:
 
 def register_tuned_batch(n: int) -> int:
     return load_library().register_tuned_batch(n)
+
+
+PLANE_VARIANTS = ((256, 1), (256, 2), (512, 4), (1024, 4))  # (threads, waves per SIMD) of the plane passes
+Z_THREADS = (128, 256, 512)
+
+
+def register_tuned_schedule(n: int) -> dict:
+    """The schedule recorded for canvas edge n (the defaults if none): batch,
+    lanes, the plane variants of passes 1 and 3, the z variant, and the tuned
+    timings."""
+    out = (ctypes.c_double * 9)()
+    rc = load_library().register_tuned_schedule(n, out)
+    if rc < 0:
+        _check(rc)
+    v = list(out)
+    return {"tuned": rc == 1, "batch": int(v[0]), "lanes": int(v[1]),
+            "pass1_workgroup": PLANE_VARIANTS[int(v[2])], "pass3_workgroup": PLANE_VARIANTS[int(v[3])],
+            "z_threads": Z_THREADS[int(v[4])], "us_per_rotation": {"pass1": v[5], "z": v[6], "pass3": v[7]},
+            "search_ns_per_rotation": v[8]}
+
+
+def register_tune_save(path: str):
+    _check(load_library().register_tune_save(os.fsencode(path)))
+
+
+def register_tune_load(path: str):
+    _check(load_library().register_tune_load(os.fsencode(path)))
 
 
 # -------------------------------------------------------- orientation samplers

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -145,6 +146,13 @@ struct HostGeometry {
     std::vector<int> slot_of;
 };
 
+// Launch schedule of a handle's search: rotations per batch, streams the
+// batches alternate over, and the workgroup variants of the three passes.
+struct Schedule {
+    int batch = 0, lanes = 2, pv1 = -1, pv3 = -1, zv = -1;
+    double us1 = 0, usz = 0, us3 = 0, ns_rot = 0;  // tuned timings (us per rotation per pass, ns per rotation)
+};
+
 struct ObjectData {
     int n = 0, nv = 0, nf = 0;
     double h = 0, tau_out1 = 0, tau_in1 = 0, rho = 0;
@@ -201,6 +209,7 @@ struct reg_handle {
     bool own_stream = false;
     bool poisoned = false;
     int n = 0, m = 0, mp = 0, n_rot = 0, n_poses = 0, nv = 0, nf = 0, batch = 0;
+    Schedule sched;  // lanes and kernel variants (batch is the field above)
     int rot_cap = 0;     // rotations the per-rotation buffers hold
     int in_batches = 0;  // live batches whose captured graph holds this handle's buffers
     size_t H = 0;
@@ -367,28 +376,45 @@ static void fill_defaults(reg_params& p) {
     if (p.max_iters <= 0) p.max_iters = 200;
 }
 
-// rotation batch per canvas edge recorded by the autotuner
+// schedules per canvas edge recorded by the autotuner
 static std::mutex g_tune_mu;
-static std::map<int, int> g_tuned;
+static std::map<int, Schedule> g_tuned;
 
 static int default_batch(int n, size_t H, int n_rot) {
+    size_t need = ((size_t)n_rot + 7) / 8 * 8;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find(n);
-        if (it != g_tuned.end()) {
-            size_t need = ((size_t)n_rot + 7) / 8 * 8;
-            return (int)std::min<size_t>((size_t)it->second, need);
-        }
+        if (it != g_tuned.end() && it->second.batch > 0) return (int)std::min<size_t>((size_t)it->second.batch, need);
     }
     // about 256 MB of spectrum work buffer, a multiple of 8 for the XCD mapping
     size_t b = (256u << 20) / (H * sizeof(float2));
     if (b < 8) b = 8;
     if (b > 4096) b = 4096;
-    size_t need = ((size_t)n_rot + 7) / 8 * 8;
     if (b > need) b = need;
     b = (b + 7) / 8 * 8;
-    (void)n;
     return (int)b;
+}
+
+// the handle's lanes and kernel variants: the params where set, else the
+// recorded schedule for the edge, else the defaults
+static int resolve_schedule(int n, const reg_params& p, Schedule& s) {
+    Schedule t;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(n);
+        if (it != g_tuned.end()) t = it->second;
+    }
+    s.lanes = p.lanes > 0 ? p.lanes : t.lanes > 0 ? t.lanes : 2;
+    if (s.lanes > 2) return fail(REG_EINVAL, "lanes must be 1 or 2");
+    const int dpv = default_plane_variant(n), dzv = default_z_variant(n);
+    s.pv1 = p.plane_variant > 0 ? p.plane_variant - 1 : t.pv1 >= 0 ? t.pv1 : dpv;
+    s.pv3 = p.plane_variant > 0 ? p.plane_variant - 1 : t.pv3 >= 0 ? t.pv3 : dpv;
+    s.zv = p.z_variant > 0 ? p.z_variant - 1 : t.zv >= 0 ? t.zv : dzv;
+    if (!plane_variant_ok(n, s.pv1) || !plane_variant_ok(n, s.pv3))
+        return fail(REG_EINVAL, "plane_variant %d is not valid for edge %d", p.plane_variant, n);
+    if (!z_variant_ok(n, s.zv)) return fail(REG_EINVAL, "z_variant %d is not valid for edge %d", p.z_variant, n);
+    return REG_OK;
 }
 
 // spectrum conj(F(O))/n^3 and the nonzero list of O, both derived from h->O
@@ -692,6 +718,10 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
     h->nf = mesh->n_faces;
     h->H = spectrum_elems(h->n);
     h->batch = h->prm.batch > 0 ? (h->prm.batch + 7) / 8 * 8 : default_batch(h->n, h->H, n_rot);
+    {
+        const int rc = resolve_schedule(h->n, h->prm, h->sched);
+        if (rc) return rc;
+    }
     h->stream = (hipStream_t)hip_stream;  // NULL: the null stream
     const size_t n3 = (size_t)h->n * h->n * h->n;
     const size_t m3 = (size_t)h->m * h->m * h->m;
@@ -768,7 +798,7 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
     ALLOC_TRY(h, h->cm, mp3);
     ALLOC_TRY(h, h->lowT, (size_t)h->batch * h->n * NLOW2);
     ALLOC_TRY(h, h->Plow, (size_t)h->batch * NLOW3);
-    if (n_rot > h->batch) {  // a call can span two batches: the second lane
+    if (n_rot > h->batch && h->sched.lanes > 1) {  // a call can span two batches: the second lane
         ALLOC_TRY(h, h->spec2, h->H * (size_t)h->batch);
         ALLOC_TRY(h, h->ptop2, (size_t)h->batch * h->n * KREC);
         ALLOC_TRY(h, h->pssq2, (size_t)h->batch * h->n);
@@ -957,8 +987,11 @@ static int batch_enqueue(reg_batch* b, int i, hipStream_t s) {
     return REG_OK;
 }
 
-// rotation batches timed on the handle's own problem; the fastest is recorded
-// for its canvas edge and used by later handles that leave params.batch at 0
+// The schedule timed on the handle's own problem (its first M rotations):
+// each pass's workgroup variants alone (event-timed launches, one lane), then
+// rotation batches on one and two lanes with the chosen kernels (the whole
+// search, event-timed on the handle's stream).  The fastest is recorded for
+// the handle's canvas edge.
 static int autotune_impl(reg_handle* h, int max_rotations, int* out_batch) {
     const int M = std::max(8, std::min(h->n_rot, max_rotations > 0 ? max_rotations : 512));
     float* score = nullptr;
@@ -980,38 +1013,135 @@ static int autotune_impl(reg_handle* h, int max_rotations, int* out_batch) {
             (void)hipEventDestroy(b);
         }
     } fe{e0, e1};
-    double best_t = INFINITY;
-    int best = 0;
-    for (int B : {8, 16, 32, 64, 128, 256}) {
-        if ((size_t)B * h->H * sizeof(float2) > ((size_t)2 << 30) || B > ((M + 7) / 8) * 8) continue;
+    reg_mesh mesh{h->V, h->nv, h->F, h->nf, h->touch};
+    reg_grid_spec grid{h->n, h->h, {h->wc[0], h->wc[1], h->wc[2]}};
+    struct FreeH {
+        reg_handle* t = nullptr;
+        ~FreeH() {
+            if (t) register_free(t);
+        }
+    };
+    auto make = [&](int B, int lanes, FreeH& fh) -> int {
         reg_params prm = h->prm;
         prm.batch = B;
-        reg_mesh mesh{h->V, h->nv, h->F, h->nf, h->touch};
-        reg_grid_spec grid{h->n, h->h, {h->wc[0], h->wc[1], h->wc[2]}};
-        reg_handle* t = nullptr;
-        int rc = init_impl(&mesh, &h->probe, h->poses, h->n_poses, h->so3, M, &grid, &prm, (void*)h->stream, h->obj,
-                           &t);
-        if (rc == REG_ENOMEM) continue;
-        if (rc) return rc;
-        rc = run_batches(t, 0, M, score, nullptr, nullptr, nullptr);  // warm-up
-        if (!rc) {
-            DEV_TRY(h, hipEventRecord(e0, h->stream));
-            for (int rep = 0; rep < 2 && !rc; ++rep) rc = run_batches(t, 0, M, score, nullptr, nullptr, nullptr);
-            DEV_TRY(h, hipEventRecord(e1, h->stream));
-            DEV_TRY(h, hipEventSynchronize(e1));
+        prm.lanes = lanes;
+        prm.plane_variant = 0;
+        prm.z_variant = 0;
+        return init_impl(&mesh, &h->probe, h->poses, h->n_poses, h->so3, M, &grid, &prm, (void*)h->stream, h->obj,
+                         &fh.t);
+    };
+    // per-pass time (us per rotation) of the timed launches of t
+    auto pass_us = [&](reg_handle* t, double* us) -> int {
+        double ms[3] = {0, 0, 0};
+        long rot[3] = {0, 0, 0};
+        DEV_TRY(t, hipStreamSynchronize(t->stream));
+        for (const auto& x : t->timed) {
+            float e = 0;
+            DEV_TRY(t, hipEventElapsedTime(&e, x.a, x.b));
+            ms[x.kernel] += e;
+            rot[x.kernel] += x.rotations;
         }
-        register_free(t);
+        for (int k = 0; k < 3; ++k) us[k] = rot[k] ? 1e3 * ms[k] / (double)rot[k] : INFINITY;
+        return REG_OK;
+    };
+    Schedule best;
+    best.us1 = best.usz = best.us3 = INFINITY;
+    {
+        // kernel variants on a batch of the default size, one lane
+        const int B0 = std::min(default_batch(h->n, h->H, M), ((M + 7) / 8) * 8);
+        FreeH fh;
+        int rc = make(B0, 1, fh);
         if (rc) return rc;
-        float ms = 0;
-        DEV_TRY(h, hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best_t) {
-            best_t = ms;
-            best = B;
+        reg_handle* t = fh.t;
+        const int cnt = std::min(M, 2 * t->batch);
+        best.pv1 = best.pv3 = t->sched.pv1;
+        best.zv = t->sched.zv;
+        for (int v = 0; v < PLANE_VARIANTS; ++v) {
+            if (!plane_variant_ok(h->n, v)) continue;
+            t->sched.pv1 = t->sched.pv3 = v;
+            t->timing = false;
+            rc = run_batches(t, 0, cnt, score, nullptr, nullptr, nullptr);  // warm-up
+            if (rc) return rc;
+            DEV_TRY(t, hipStreamSynchronize(t->stream));
+            t->timing = true;
+            t->timed.clear();
+            t->pool_used = 0;
+            for (int rep = 0; rep < 2 && !rc; ++rep) rc = run_batches(t, 0, cnt, score, nullptr, nullptr, nullptr);
+            if (rc) return rc;
+            double us[3];
+            rc = pass_us(t, us);
+            if (rc) return rc;
+            if (us[0] < best.us1) {
+                best.us1 = us[0];
+                best.pv1 = v;
+            }
+            if (us[2] < best.us3) {
+                best.us3 = us[2];
+                best.pv3 = v;
+            }
+        }
+        t->sched.pv1 = best.pv1;
+        t->sched.pv3 = best.pv3;
+        for (int v = 0; v < Z_VARIANTS; ++v) {
+            if (!z_variant_ok(h->n, v)) continue;
+            t->sched.zv = v;
+            t->timing = false;
+            rc = run_batches(t, 0, cnt, score, nullptr, nullptr, nullptr);
+            if (rc) return rc;
+            DEV_TRY(t, hipStreamSynchronize(t->stream));
+            t->timing = true;
+            t->timed.clear();
+            t->pool_used = 0;
+            for (int rep = 0; rep < 2 && !rc; ++rep) rc = run_batches(t, 0, cnt, score, nullptr, nullptr, nullptr);
+            if (rc) return rc;
+            double us[3];
+            rc = pass_us(t, us);
+            if (rc) return rc;
+            if (us[1] < best.usz) {
+                best.usz = us[1];
+                best.zv = v;
+            }
+        }
+        t->timing = false;
+    }
+    // rotation batch and lanes with the chosen kernels
+    double best_t = INFINITY;
+    for (int B : {8, 16, 32, 64, 128, 256, 512}) {
+        if ((size_t)B * h->H * sizeof(float2) > ((size_t)2 << 30) || B > ((M + 7) / 8) * 8) continue;
+        for (int lanes = 1; lanes <= 2; ++lanes) {
+            if (lanes == 2 && B >= M) continue;
+            FreeH fh;
+            int rc = make(B, lanes, fh);
+            if (rc == REG_ENOMEM) continue;
+            if (rc) return rc;
+            reg_handle* t = fh.t;
+            t->sched.pv1 = best.pv1;
+            t->sched.pv3 = best.pv3;
+            t->sched.zv = best.zv;
+            rc = run_batches(t, 0, M, score, nullptr, nullptr, nullptr);  // warm-up
+            if (!rc) {
+                DEV_TRY(h, hipEventRecord(e0, h->stream));
+                for (int rep = 0; rep < 2 && !rc; ++rep) rc = run_batches(t, 0, M, score, nullptr, nullptr, nullptr);
+                DEV_TRY(h, hipEventRecord(e1, h->stream));
+                DEV_TRY(h, hipEventSynchronize(e1));
+            }
+            if (rc) return rc;
+            float ms = 0;
+            DEV_TRY(h, hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_t) {
+                best_t = ms;
+                best.batch = B;
+                best.lanes = lanes;
+            }
         }
     }
-    if (!best) return fail(REG_ENOMEM, "no rotation batch fits in device memory");
-    regdock_rt::set_tuned_batch(h->n, best);
-    *out_batch = best;
+    if (!best.batch) return fail(REG_ENOMEM, "no rotation batch fits in device memory");
+    best.ns_rot = 1e6 * best_t / (2.0 * M);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[h->n] = best;
+    }
+    *out_batch = best.batch;
     return REG_OK;
 }
 
@@ -1180,70 +1310,94 @@ int register_info(const reg_handle* h, int32_t* n, int32_t* m, int64_t* spectrum
     return REG_OK;
 }
 
+static PeakArrays peak_arrays(reg_handle* h) {
+    return PeakArrays{h->cand_idx, h->cand_n, h->window, h->ovf, h->best_val, h->best_flat,
+                      h->need_list, h->need_count, h->cand_part, h->stats};
+}
+
+// One rotation batch [b0, b0 + cnt) of the handle's set through the three
+// search passes and the per-rotation candidate selection, on stream ls with
+// pass-buffer set `lane` (1: the second set, which exists when the set spans
+// more than one batch).  after_plane_pass, when given, is recorded on ls once
+// the batch's first pass is enqueued.
+static int enqueue_batch(reg_handle* h, int b0, int cnt, int lane, hipStream_t ls, float* corr_out,
+                         hipEvent_t after_plane_pass = nullptr) {
+    const bool odd = lane == 1;
+    SearchBatchArgs a{};
+    a.cmask = h->cm;
+    a.m = h->m;
+    a.mp = h->mp;
+    a.rots = h->rots + 9 * (size_t)b0;
+    a.count = cnt;
+    a.tw = h->tw;
+    a.spec = odd ? h->spec2 : h->spec;
+    a.W = h->W;
+    a.tw64 = h->tw64;
+    a.lowT = odd ? h->lowT2 : h->lowT;
+    a.Wlow = h->Wlow;
+    a.Plow = odd ? h->Plow2 : h->Plow;
+    a.ptop = odd ? h->ptop2 : h->ptop;
+    a.pssq = odd ? h->pssq2 : h->pssq;
+    a.corr_out = corr_out;
+    a.pv1 = h->sched.pv1;
+    a.pv3 = h->sched.pv3;
+    a.zv = h->sched.zv;
+    a.stream = ls;
+    for (int pass = 0; pass < 3; ++pass) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (h->timing) {
+            e0 = h->next_event();
+            e1 = h->next_event();
+            if (!e0 || !e1) return fail(REG_EDEVICE, "hipEventCreate failed");
+            DEV_TRY(h, hipEventRecord(e0, ls));
+        }
+        DEV_TRY(h, search_pass(h->n, pass, a));
+        if (h->timing) {
+            DEV_TRY(h, hipEventRecord(e1, ls));
+            h->timed.push_back({e0, e1, pass, cnt});
+        }
+        if (pass == 0 && after_plane_pass) DEV_TRY(h, hipEventRecord(after_plane_pass, ls));
+    }
+    DEV_TRY(h, select_batch(h->n, a, b0, peak_arrays(h)));
+    return REG_OK;
+}
+
+// certification, exact re-scoring and the outputs of rotations [first, first + count)
+static int enqueue_finish(reg_handle* h, int first, int count, float* out_score, int32_t* out_shift, double* out_pose,
+                          hipStream_t s) {
+    const RescoreInputs ri{h->nz_idx, h->nz_val, h->nz_count, h->cm, h->m, h->mp, h->rots};
+    DEV_TRY(h, finish_call(h->n, first, count, h->prm.rescore != 0, peak_arrays(h), ri, h->so3 + 4 * (size_t)first,
+                           h->h, h->anchor, h->wc, out_score, out_shift, out_pose, s));
+    return REG_OK;
+}
+
 static int run_batches(reg_handle* h, int first, int count, float* out_score, int32_t* out_shift, double* out_pose,
                        float* corr_out) {
-    const PeakArrays pk{h->cand_idx, h->cand_n, h->window, h->ovf, h->best_val, h->best_flat,
-                        h->need_list, h->need_count, h->cand_part, h->stats};
-    // two lanes when the call spans more than one batch: even batches on the
-    // handle's stream, odd ones on stream2 (forked from it here and joined back
-    // before the call's last step); each lane keeps its own pass buffers.  Not
-    // under graph capture, whose batches already run on parallel branches (a
-    // fork of stream2 inside the capture crashed register_batch_create).
+    // two lanes when the schedule asks for them and the call spans more than
+    // one batch: even batches on the handle's stream, odd ones on stream2
+    // (forked from it here and joined back before the call's last step); each
+    // lane keeps its own pass buffers.  Not under graph capture, whose batches
+    // already run on parallel branches (a fork of stream2 inside the capture
+    // crashed register_batch_create).
     hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
     DEV_TRY(h, hipStreamIsCapturing(h->stream, &capture));
-    const bool two = h->stream2 && count > h->batch && capture == hipStreamCaptureStatusNone;
+    const bool two = h->stream2 && h->sched.lanes > 1 && count > h->batch && capture == hipStreamCaptureStatusNone;
     for (int b0 = 0, j = 0; b0 < count; b0 += h->batch, ++j) {
         const int cnt = count - b0 < h->batch ? count - b0 : h->batch;
         const bool odd = two && (j & 1);
-        hipStream_t ls = odd ? h->stream2 : h->stream;
-        SearchBatchArgs a{};
-        a.cmask = h->cm;
-        a.m = h->m;
-        a.mp = h->mp;
-        a.rots = h->rots + 9 * (size_t)(first + b0);
-        a.count = cnt;
-        a.tw = h->tw;
-        a.spec = odd ? h->spec2 : h->spec;
-        a.W = h->W;
-        a.tw64 = h->tw64;
-        a.lowT = odd ? h->lowT2 : h->lowT;
-        a.Wlow = h->Wlow;
-        a.Plow = odd ? h->Plow2 : h->Plow;
-        a.ptop = odd ? h->ptop2 : h->ptop;
-        a.pssq = odd ? h->pssq2 : h->pssq;
-        a.corr_out = corr_out;
-        a.stream = ls;
-        for (int pass = 0; pass < 3; ++pass) {
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (h->timing) {
-                e0 = h->next_event();
-                e1 = h->next_event();
-                if (!e0 || !e1) return fail(REG_EDEVICE, "hipEventCreate failed");
-                DEV_TRY(h, hipEventRecord(e0, ls));
-            }
-            DEV_TRY(h, search_pass(h->n, pass, a));
-            if (h->timing) {
-                DEV_TRY(h, hipEventRecord(e1, ls));
-                h->timed.push_back({e0, e1, pass, cnt});
-            }
-            if (two && j == 0 && pass == 0) {
-                // the second lane starts once the first batch's plane pass is
-                // done, half a batch out of phase: its plane passes then meet
-                // the first lane's z pass more often than its plane passes
-                DEV_TRY(h, hipEventRecord(h->fork_ev, h->stream));
-                DEV_TRY(h, hipStreamWaitEvent(h->stream2, h->fork_ev, 0));
-            }
-        }
-        DEV_TRY(h, select_batch(h->n, a, first + b0, pk));
+        // the second lane starts once the first batch's plane pass is done,
+        // half a batch out of phase: its plane passes then meet the first
+        // lane's z pass more often than its plane passes
+        const int rc = enqueue_batch(h, first + b0, cnt, odd ? 1 : 0, odd ? h->stream2 : h->stream, corr_out,
+                                     two && j == 0 ? h->fork_ev : nullptr);
+        if (rc) return rc;
+        if (two && j == 0) DEV_TRY(h, hipStreamWaitEvent(h->stream2, h->fork_ev, 0));
     }
     if (two) {
         DEV_TRY(h, hipEventRecord(h->join_ev, h->stream2));
         DEV_TRY(h, hipStreamWaitEvent(h->stream, h->join_ev, 0));
     }
-    const RescoreInputs ri{h->nz_idx, h->nz_val, h->nz_count, h->cm, h->m, h->mp, h->rots};
-    DEV_TRY(h, finish_call(h->n, first, count, h->prm.rescore != 0, pk, ri, h->so3 + 4 * (size_t)first, h->h, h->anchor,
-                           h->wc, out_score, out_shift, out_pose, h->stream));
-    return REG_OK;
+    return enqueue_finish(h, first, count, out_score, out_shift, out_pose, h->stream);
 }
 
 int score_rotations(reg_handle* h, int32_t first, int32_t count, float* out_score, int32_t* out_shift, double* out_pose) {
@@ -1524,6 +1678,109 @@ int register_autotune(reg_handle* h, int32_t max_rotations, int32_t* out_batch) 
 
 int register_tuned_batch(int32_t n) { return regdock_rt::tuned_batch(n); }
 
+int register_tuned_schedule(int32_t n, double* out) {
+    g_err.clear();
+    if (!out || !canvas_supported(n)) return fail(REG_EINVAL, "NULL output or unsupported edge %d", n);
+    Schedule s;
+    bool have = false;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(n);
+        if (it != g_tuned.end()) {
+            s = it->second;
+            have = true;
+        }
+    }
+    if (s.pv1 < 0) s.pv1 = default_plane_variant(n);
+    if (s.pv3 < 0) s.pv3 = default_plane_variant(n);
+    if (s.zv < 0) s.zv = default_z_variant(n);
+    if (s.batch <= 0) s.batch = default_batch(n, spectrum_elems(n), 1 << 30);
+    const double v[9] = {(double)s.batch, (double)s.lanes, (double)s.pv1, (double)s.pv3, (double)s.zv,
+                         s.us1, s.usz, s.us3, s.ns_rot};
+    for (int k = 0; k < 9; ++k) out[k] = v[k];
+    return have ? 1 : 0;
+}
+
+int register_tune_save(const char* path) {
+    g_err.clear();
+    if (!path) return fail(REG_EINVAL, "NULL path");
+    std::map<int, Schedule> snap;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        snap = g_tuned;
+    }
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(REG_EINVAL, "cannot write %s", path);
+    std::fprintf(f, "[\n");
+    size_t k = 0;
+    for (const auto& e : snap) {
+        const Schedule& s = e.second;
+        std::fprintf(f,
+                     "  {\"n\": %d, \"batch\": %d, \"lanes\": %d, \"pv1\": %d, \"pv3\": %d, \"zv\": %d, "
+                     "\"us1\": %.4f, \"usz\": %.4f, \"us3\": %.4f, \"ns_rot\": %.2f}%s\n",
+                     e.first, s.batch, s.lanes, s.pv1, s.pv3, s.zv, std::isfinite(s.us1) ? s.us1 : 0.0,
+                     std::isfinite(s.usz) ? s.usz : 0.0, std::isfinite(s.us3) ? s.us3 : 0.0, s.ns_rot,
+                     ++k < snap.size() ? "," : "");
+    }
+    std::fprintf(f, "]\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok ? REG_OK : fail(REG_EINVAL, "write of %s failed", path);
+}
+
+int register_tune_load(const char* path) {
+    g_err.clear();
+    if (!path) return fail(REG_EINVAL, "NULL path");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(REG_EINVAL, "cannot read %s", path);
+    std::string txt;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, got);
+    std::fclose(f);
+    // one object per edge: {"n": .., "batch": .., "lanes": .., "pv1": .., "pv3": .., "zv": .., ...}
+    auto field = [](const std::string& obj, const char* key, double& v) {
+        const std::string k = std::string("\"") + key + "\"";
+        const size_t p = obj.find(k);
+        if (p == std::string::npos) return false;
+        const size_t c = obj.find(':', p + k.size());
+        if (c == std::string::npos) return false;
+        char* end = nullptr;
+        v = std::strtod(obj.c_str() + c + 1, &end);
+        return end != obj.c_str() + c + 1;
+    };
+    std::map<int, Schedule> add;
+    size_t pos = 0;
+    while ((pos = txt.find('{', pos)) != std::string::npos) {
+        const size_t e = txt.find('}', pos);
+        if (e == std::string::npos) return fail(REG_EINVAL, "malformed schedule file %s", path);
+        const std::string obj = txt.substr(pos, e - pos + 1);
+        pos = e + 1;
+        double n, b, l, p1, p3, z;
+        if (!field(obj, "n", n) || !field(obj, "batch", b) || !field(obj, "lanes", l) || !field(obj, "pv1", p1) ||
+            !field(obj, "pv3", p3) || !field(obj, "zv", z))
+            return fail(REG_EINVAL, "malformed schedule entry in %s", path);
+        const int ni = (int)n;
+        if (!canvas_supported(ni) || !plane_variant_ok(ni, (int)p1) || !plane_variant_ok(ni, (int)p3) ||
+            !z_variant_ok(ni, (int)z) || b < 8 || (l != 1 && l != 2))
+            continue;
+        Schedule s;
+        s.batch = ((int)b + 7) / 8 * 8;
+        s.lanes = (int)l;
+        s.pv1 = (int)p1;
+        s.pv3 = (int)p3;
+        s.zv = (int)z;
+        double x;
+        if (field(obj, "us1", x)) s.us1 = x;
+        if (field(obj, "usz", x)) s.usz = x;
+        if (field(obj, "us3", x)) s.us3 = x;
+        if (field(obj, "ns_rot", x)) s.ns_rot = x;
+        add[ni] = s;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& e : add) g_tuned[e.first] = e.second;
+    return REG_OK;
+}
+
 int register_debug_distance(reg_handle* h, const double* R, const double* p, float* out) {
     g_err.clear();
     if (!h || !R || !p || !out) return fail(REG_EINVAL, "NULL argument");
@@ -1554,6 +1811,19 @@ int init_shared(const reg_mesh* mesh, const reg_probe* probe, const float* poses
 
 std::shared_ptr<ObjectData> object_of(reg_handle* h) { return h ? h->obj : nullptr; }
 
+int handle_batch(const reg_handle* h) { return h->batch; }
+
+int handle_buffer_sets(const reg_handle* h) { return h->spec2 ? 2 : 1; }
+
+int enqueue_search_batch(reg_handle* h, int b0, int cnt, int set, hipStream_t s) {
+    if (set == 1 && !h->spec2) return fail(REG_EINVAL, "the handle has one pass-buffer set");
+    return enqueue_batch(h, b0, cnt, set, s, nullptr);
+}
+
+int enqueue_search_finish(reg_handle* h, float* out_score, int32_t* out_shift, double* out_pose, hipStream_t s) {
+    return enqueue_finish(h, 0, h->n_rot, out_score, out_shift, out_pose, s);
+}
+
 size_t object_bytes(const ObjectData* o) { return o ? o->bytes : 0; }
 
 Footprint footprint(int n, int n_rot, int n_poses, int nv, int nf, int batch, int refine_starts) {
@@ -1582,12 +1852,12 @@ std::string last_error() { return g_err; }
 int tuned_batch(int n) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(n);
-    return it == g_tuned.end() ? 0 : it->second;
+    return it == g_tuned.end() ? 0 : it->second.batch;
 }
 
 void set_tuned_batch(int n, int batch) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[n] = batch;
+    g_tuned[n].batch = batch;
 }
 
 }  // namespace regdock_rt

@@ -22,6 +22,18 @@ int init_shared(const reg_mesh* mesh, const reg_probe* probe, const float* poses
                 std::shared_ptr<ObjectData> cached, reg_handle** out);
 
 std::shared_ptr<ObjectData> object_of(reg_handle* h);
+
+// The search of a handle as separate work items, for a scheduler that
+// interleaves items of several handles on its own streams: the rotation batch
+// [b0, b0 + cnt) through the three passes and the candidate selection with
+// pass-buffer set `set` (0, or 1 when handle_buffer_sets is 2) on stream s;
+// then, once every batch is done, the certification, re-scoring and outputs
+// of all rotations (as score_rotations over the whole set).  The caller
+// orders items that share a buffer set and the finish after every batch.
+int handle_batch(const reg_handle* h);
+int handle_buffer_sets(const reg_handle* h);
+int enqueue_search_batch(reg_handle* h, int b0, int cnt, int set, hipStream_t s);
+int enqueue_search_finish(reg_handle* h, float* out_score, int32_t* out_shift, double* out_pose, hipStream_t s);
 size_t object_bytes(const ObjectData* o);
 
 // Device bytes of one registration: the object part (grid, spectrum, lists,

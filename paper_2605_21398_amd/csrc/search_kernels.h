@@ -44,8 +44,20 @@ struct SearchBatchArgs {
     unsigned long long* ptop;  // [count][n][KREC] per plane: best keys (score bits, ~flat), then the bound (double bits)
     double* pssq;              // [count][n] per-plane sums of squares of the field
     float* corr_out;           // optional: full float32 field of a 1-rotation batch
+    int pv1, pv3, zv;          // schedule variants of pass 1, pass 3 and the z pass
     hipStream_t stream;
 };
+
+// Schedule variants (threads and waves per SIMD of the plane workgroups;
+// threads of the z-pencil workgroups), valid per canvas edge.
+constexpr int PLANE_VARIANTS = 4;
+constexpr int Z_VARIANTS = 3;
+bool plane_variant_ok(int n, int v);
+bool z_variant_ok(int n, int v);
+int default_plane_variant(int n);
+int default_z_variant(int n);
+int plane_variant_threads(int v);
+int z_variant_threads(int v);
 
 bool canvas_supported(int n);
 int rescore_slices(int n);

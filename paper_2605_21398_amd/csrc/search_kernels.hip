@@ -67,7 +67,6 @@ template <int N> struct Canvas {
     // and barrier latency
     static constexpr int NT = N > 128 ? 1024 : N >= 96 ? 512 : 256;
     static constexpr int WPE = N >= 96 ? 4 : 1;  // waves per SIMD asked of the compiler
-    static constexpr int ZT = 256;                        // threads of a z-pencil workgroup
     static_assert(N % 2 == 0, "canvas edge must be even");
     static_assert(fft_supported(N) && fft_supported(N2), "edge must be 2^a 3^b 5^c");
     static_assert((size_t)N * P * 8 <= 160 * 1024, "plane must fit in LDS");
@@ -152,11 +151,11 @@ __device__ __forceinline__ void batched_copy(Src src, Dst dst) {
 // Rows hold z[j] = s[2j] + i s[2j+1]; after the length-N/2 FFT, turn each row
 // into X[k], k in [0, N/2], of the length-N real FFT:
 //   X[k] = ((Z[k] + conj Z[N/2-k]) - i w^k (Z[k] - conj Z[N/2-k])) / 2.
-template <int N>
+template <int N, int NT>
 __device__ __forceinline__ void r2c_post(float2* plane, const float2* tw) {
     using C = Canvas<N>;
     constexpr int Q = C::N2 / 2 + 1;
-    for (int e = threadIdx.x; e < N * Q; e += C::NT) {
+    for (int e = threadIdx.x; e < N * Q; e += NT) {
         const int y = e / Q, k = e % Q;
         float2* row = plane + y * C::P;
         if (k == 0) {
@@ -184,11 +183,11 @@ __device__ __forceinline__ void r2c_post(float2* plane, const float2* tw) {
 // Inverse of r2c_post (up to the factor 2 that makes the length-N/2 inverse
 // FFT below equal the unnormalised length-N inverse real FFT):
 //   Z[k] = (X[k] + conj X[N/2-k]) + i conj(w^k) (X[k] - conj X[N/2-k]).
-template <int N>
+template <int N, int NT>
 __device__ __forceinline__ void c2r_pre(float2* plane, const float2* tw) {
     using C = Canvas<N>;
     constexpr int Q = C::N2 / 2 + 1;
-    for (int e = threadIdx.x; e < N * Q; e += C::NT) {
+    for (int e = threadIdx.x; e < N * Q; e += NT) {
         const int y = e / Q, k = e % Q;
         float2* row = plane + y * C::P;
         const int kk = C::N2 - k;
@@ -209,20 +208,20 @@ __device__ __forceinline__ void c2r_pre(float2* plane, const float2* tw) {
 }
 
 // forward 2D real FFT of the packed plane (x then y) and write to the tiled spectrum
-template <int N>
+template <int N, int NT>
 __device__ __forceinline__ void plane_forward_and_store(float2* plane, const float2* tw, float2* __restrict__ spec_rot, int z) {
     using C = Canvas<N>;
-    fft_lds<C::N2, false, N, C::NT, true, N>(plane, 1, C::P, tw);
-    r2c_post<N>(plane, tw);
-    fft_lds<N, false, C::P, C::NT, true, N>(plane, C::P, 1, tw);
+    fft_lds<C::N2, false, N, NT, true, N>(plane, 1, C::P, tw);
+    r2c_post<N, NT>(plane, tw);
+    fft_lds<N, false, C::P, NT, true, N>(plane, C::P, 1, tw);
     // LDS reads first, then the global stores
-    batched_copy<N * C::N2, C::NT>([&](int e) { return plane[(e / C::N2) * C::P + e % C::N2]; },
+    batched_copy<N * C::N2, NT>([&](int e) { return plane[(e / C::N2) * C::P + e % C::N2]; },
                                    [&](int e, float2 v) {
                                        const int ky = e / C::N2, kx = e % C::N2;
                                        spec_rot[((size_t)(ky * C::NT2 + kx / C::T) * N + z) * C::T + (kx % C::T)] = v;
                                    });
     float2* nyq = spec_rot + (size_t)N * C::N2 * N;
-    for (int ky = threadIdx.x; ky < N; ky += C::NT)
+    for (int ky = threadIdx.x; ky < N; ky += NT)
         nyq[((size_t)(ky / C::T) * N + z) * C::T + (ky % C::T)] = plane[ky * C::P + C::N2];
 }
 
@@ -258,12 +257,12 @@ __device__ __forceinline__ int mod_n(int v, int n) {
 // double twiddle table in LDS.  Row sums over x run as second-order Goertzel
 // recurrences per kx (one FMA and one subtraction per sample and frequency, no
 // table reads); each row is split into CH contiguous chunks on CH lanes.
-template <int N>
+template <int N, int NT>
 __device__ __forceinline__ void plane_low_dft(const float2* plane, const double2* tw64, double2* rbuf,
                                               double2* __restrict__ out) {
     using C = Canvas<N>;
-    static_assert(N <= C::NT, "one row task set per pass");
-    constexpr int CH = pow2floor(C::NT / N);  // lanes per row, a power of two
+    static_assert(N <= NT, "one row task set per pass");
+    constexpr int CH = pow2floor(NT / N);  // lanes per row, a power of two
     constexpr int JC = (C::N2 + CH - 1) / CH;
     const int t = threadIdx.x;
     if (t < N * CH) {
@@ -314,7 +313,7 @@ __device__ __forceinline__ void plane_low_dft(const float2* plane, const double2
     __syncthreads();
     // y direction: four lanes per (kx, ky), each a quarter of the rows
     constexpr int CB = 4;
-    static_assert(N % CB == 0 && NLOW2 * CB <= C::NT, "low-block y pass layout");
+    static_assert(N % CB == 0 && NLOW2 * CB <= NT, "low-block y pass layout");
     double2 part = make_double2(0.0, 0.0);
     if (t < NLOW2 * CB) {
         const int o = t / CB, c = t % CB;
@@ -428,12 +427,12 @@ __device__ __forceinline__ float trilinear_poly(const float4* lut, uint32_t mk, 
 // (the launcher checks m).  Eight rows per batch keep 16 gathers in flight.
 // Each value is the trilinear polynomial of its cell (table in LDS), with no
 // branch on the mask.
-template <int N>
+template <int N, int NT>
 __device__ __forceinline__ void generate_plane(float2* plane, const float4* lut, const RotSampler& rs,
                                                const uint8_t* __restrict__ cmask, int mb, int z) {
     using C = Canvas<N>;
-    static_assert(C::N2 <= C::NT, "a plane workgroup covers every column pair");
-    constexpr int YS = C::NT / C::N2;  // row step of a lane (YS * N2 lanes work, the rest idle)
+    static_assert(C::N2 <= NT, "a plane workgroup covers every column pair");
+    constexpr int YS = NT / C::N2;  // row step of a lane (YS * N2 lanes work, the rest idle)
     constexpr int G = 8;               // rows per batch of loads
     const int j = threadIdx.x % C::N2, y0 = threadIdx.x / C::N2;
     if (threadIdx.x >= YS * C::N2 || y0 >= N) return;
@@ -489,8 +488,8 @@ __device__ __forceinline__ void generate_plane(float2* plane, const float4* lut,
 
 // ------------------------------------------------------------------ pass 1
 
-template <int N>
-__global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_rotvox_fwd_xy(const uint8_t* __restrict__ cmask, int m, int mb,
+template <int N, int NT, int WPE>
+__global__ __launch_bounds__(NT, WPE) void k_rotvox_fwd_xy(const uint8_t* __restrict__ cmask, int m, int mb,
                                                        const double* __restrict__ rots, int count,
                                                        const float2* __restrict__ twg, const double2* __restrict__ tw64,
                                                        float2* __restrict__ spec, double2* __restrict__ lowT) {
@@ -506,18 +505,18 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_rotvox_fwd_xy
     float4* lut = reinterpret_cast<float4*>(scratch_lds);
     int rot, z;
     map_plane_block(blockIdx.x, count, N, rot, z);
-    for (int i = threadIdx.x; i < N; i += C::NT) {
+    for (int i = threadIdx.x; i < N; i += NT) {
         tw[i] = twg[i];
         tws[i] = tw64[i];
     }
-    build_trilinear_lut<C::NT>(lut);
+    build_trilinear_lut<NT>(lut);
     RotSampler rs;
     rs.load(rots + rot * 9, m, N);
     __syncthreads();
-    generate_plane<N>(plane, lut, rs, cmask, mb, z);
+    generate_plane<N, NT>(plane, lut, rs, cmask, mb, z);
     __syncthreads();
-    plane_low_dft<N>(plane, tws, rbuf, lowT + ((size_t)rot * N + z) * NLOW2);
-    plane_forward_and_store<N>(plane, tw, spec + (size_t)rot * C::H, z);
+    plane_low_dft<N, NT>(plane, tws, rbuf, lowT + ((size_t)rot * N + z) * NLOW2);
+    plane_forward_and_store<N, NT>(plane, tw, spec + (size_t)rot * C::H, z);
 }
 
 // pass 1 on a real grid (the object grid O): same transform, no rotation
@@ -541,19 +540,19 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_grid_fwd_xy(c
         plane[y * C::P + j] = make_float2(row[2 * j], row[2 * j + 1]);
     }
     __syncthreads();
-    plane_low_dft<N>(plane, tws, rbuf, lowT + (size_t)z * NLOW2);
-    plane_forward_and_store<N>(plane, tw, spec, z);
+    plane_low_dft<N, Canvas<N>::NT>(plane, tws, rbuf, lowT + (size_t)z * NLOW2);
+    plane_forward_and_store<N, Canvas<N>::NT>(plane, tw, spec, z);
 }
 
 // ------------------------------------------------------------------ pass 2
 // MODE 0: x <- IFFT_z(FFT_z(x) * W);  MODE 1: W <- conj(FFT_z(x)) * scale
 
-template <int N, int MODE>
-__global__ __launch_bounds__(256) void k_zpass(float2* __restrict__ spec, const float2* __restrict__ W, float2* __restrict__ wout,
+template <int N, int MODE, int ZT>
+__global__ __launch_bounds__(ZT) void k_zpass(float2* __restrict__ spec, const float2* __restrict__ W, float2* __restrict__ wout,
                                                const float2* __restrict__ twg, float scale) {
     using C = Canvas<N>;
     constexpr int E = N * C::T;
-    constexpr int PER = (E + C::ZT - 1) / C::ZT;
+    constexpr int PER = (E + ZT - 1) / ZT;
     __shared__ float2 buf[E];
     __shared__ float2 tw[N];
     // Block -> (tile, rotation).  Blocks are dealt round-robin to the 8 XCDs;
@@ -570,38 +569,38 @@ __global__ __launch_bounds__(256) void k_zpass(float2* __restrict__ spec, const 
         rot = blockIdx.x / C::TILES;
     }
     float2* src = spec + (size_t)rot * C::H + (size_t)tile * E;
-    for (int i = threadIdx.x; i < N; i += C::ZT) tw[i] = twg[i];
-    batched_copy<E, C::ZT>([&](int i) { return src[i]; }, [&](int i, float2 v) { buf[i] = v; });
+    for (int i = threadIdx.x; i < N; i += ZT) tw[i] = twg[i];
+    batched_copy<E, ZT>([&](int i) { return src[i]; }, [&](int i, float2 v) { buf[i] = v; });
     // the tile of W is loaded into registers while the forward FFT runs
     float2 wv[PER];
     if (MODE == 0) {
         const float2* w = W + (size_t)tile * E;
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
-            const int i = threadIdx.x + r * C::ZT;
-            wv[r] = (E % C::ZT == 0 || i < E) ? w[i] : make_float2(0.0f, 0.0f);
+            const int i = threadIdx.x + r * ZT;
+            wv[r] = (E % ZT == 0 || i < E) ? w[i] : make_float2(0.0f, 0.0f);
         }
     }
     __syncthreads();
-    fft_lds<N, false, C::T, C::ZT, true, N>(buf, C::T, 1, tw);
+    fft_lds<N, false, C::T, ZT, true, N>(buf, C::T, 1, tw);
     if (MODE == 0) {
         // the low block (max(|kx|,|ky|,|kz|) <= KLOW) is carried exactly elsewhere
         const int ky = tile / C::NT2;
         const bool low_tile = tile < N * C::NT2 && (tile % C::NT2) == 0 && (ky <= KLOW || ky >= N - KLOW);
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
-            const int i = threadIdx.x + r * C::ZT;
-            if (E % C::ZT != 0 && i >= E) break;
+            const int i = threadIdx.x + r * ZT;
+            if (E % ZT != 0 && i >= E) break;
             const int kz = i / C::T, kx = i % C::T;
             const bool low = low_tile && kx <= KLOW && (kz <= KLOW || kz >= N - KLOW);
             buf[i] = low ? make_float2(0.0f, 0.0f) : cmul(buf[i], wv[r]);
         }
         __syncthreads();
-        fft_lds<N, true, C::T, C::ZT, true, N>(buf, C::T, 1, tw);
-        for (int i = threadIdx.x; i < E; i += C::ZT) src[i] = buf[i];
+        fft_lds<N, true, C::T, ZT, true, N>(buf, C::T, 1, tw);
+        for (int i = threadIdx.x; i < E; i += ZT) src[i] = buf[i];
     } else {
         float2* dst = wout + (size_t)tile * E;
-        for (int i = threadIdx.x; i < E; i += C::ZT) dst[i] = cscale(cconj(buf[i]), scale);
+        for (int i = threadIdx.x; i < E; i += ZT) dst[i] = cscale(cconj(buf[i]), scale);
     }
 }
 
@@ -625,13 +624,13 @@ __device__ __forceinline__ double key_value(unsigned long long k) {
 }
 __device__ __forceinline__ uint32_t key_flat(unsigned long long k) { return 0x3fffffu - (uint32_t)(k & 0x3fffffull); }
 
-template <int N>
-__global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_inv_xy_argmax(const float2* __restrict__ spec, int count, const float2* __restrict__ twg,
+template <int N, int NT, int WPE>
+__global__ __launch_bounds__(NT, WPE) void k_inv_xy_argmax(const float2* __restrict__ spec, int count, const float2* __restrict__ twg,
                                                        const double2* __restrict__ tw64, const double2* __restrict__ Plow,
                                                        unsigned long long* __restrict__ ptop, double* __restrict__ pssq,
                                                        float* __restrict__ corr_out) {
     using C = Canvas<N>;
-    constexpr int NW = C::NT / 64;
+    constexpr int NW = NT / 64;
     __shared__ float2 plane[N * C::P];
     __shared__ float2 tw[N];
     __shared__ double2 btab[N * NLX];
@@ -642,25 +641,25 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_inv_xy_argmax
     __shared__ double wsec[NW];
     int rot, z;
     map_plane_block(blockIdx.x, count, N, rot, z);
-    for (int i = threadIdx.x; i < N; i += C::NT) {
+    for (int i = threadIdx.x; i < N; i += NT) {
         tw[i] = twg[i];
         tws[i] = tw64[i];
     }
     const float2* spec_rot = spec + (size_t)rot * C::H;
-    batched_copy<N * C::N2, C::NT>(
+    batched_copy<N * C::N2, NT>(
         [&](int e) {
             const int ky = e / C::N2, kx = e % C::N2;
             return spec_rot[((size_t)(ky * C::NT2 + kx / C::T) * N + z) * C::T + (kx % C::T)];
         },
         [&](int e, float2 v) { plane[(e / C::N2) * C::P + e % C::N2] = v; });
     const float2* nyq = spec_rot + (size_t)N * C::N2 * N;
-    batched_copy<N, C::NT>([&](int ky) { return nyq[((size_t)(ky / C::T) * N + z) * C::T + (ky % C::T)]; },
+    batched_copy<N, NT>([&](int ky) { return nyq[((size_t)(ky / C::T) * N + z) * C::T + (ky % C::T)]; },
                            [&](int ky, float2 v) { plane[ky * C::P + C::N2] = v; });
     __syncthreads();
     // low block of this plane: az[kx][ky] = sum_kz P[kx][ky][kz] e^{+2 pi i kz z / N}
     {
         const double2* P = Plow + (size_t)rot * NLOW3;
-        for (int o = threadIdx.x; o < NLOW2; o += C::NT) {
+        for (int o = threadIdx.x; o < NLOW2; o += NT) {
             double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
             for (int kzi = 0; kzi < NLY; ++kzi) {
@@ -673,10 +672,10 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_inv_xy_argmax
     }
     // az is complete before the first barrier inside the y inverse FFT and is
     // read only after it
-    fft_lds<N, true, C::P, C::NT, true, N>(plane, C::P, 1, tw);
+    fft_lds<N, true, C::P, NT, true, N>(plane, C::P, 1, tw);
     // btab[y][kx] = sum_ky az[kx][ky] e^{+2 pi i ky y / N}, doubled for kx > 0
     // (the field sums Re b_0 + 2 sum_kx Re(b_kx e^{+2 pi i kx x / N}))
-    for (int t = threadIdx.x; t < N * NLX; t += C::NT) {
+    for (int t = threadIdx.x; t < N * NLX; t += NT) {
         const int y = t / NLX, kx = t % NLX;
         double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
@@ -687,8 +686,8 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_inv_xy_argmax
         }
         btab[t] = kx > 0 ? make_double2(2.0 * acc.x, 2.0 * acc.y) : acc;
     }
-    c2r_pre<N>(plane, tw);
-    fft_lds<C::N2, true, N, C::NT, true, N>(plane, 1, C::P, tw);
+    c2r_pre<N, NT>(plane, tw);
+    fft_lds<C::N2, true, N, NT, true, N>(plane, 1, C::P, tw);
     // Every working lane keeps the same columns x = 2j, 2j+1 (YS n/2 lanes
     // work, the rest idle), so its low-block phases live in registers.  Each
     // column of a lane ("virtual lane": x fixed, rows y0, y0 + YS, ...) keeps
@@ -698,8 +697,8 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_inv_xy_argmax
     // fifth-best virtual-lane maximum and every virtual lane's second value.
     // No voxel outside the four keys exceeds the bound, so a candidate window
     // that the bound does not reach holds only those keys.
-    static_assert(C::N2 <= C::NT, "a plane workgroup covers every column pair");
-    constexpr int YS = C::NT / C::N2;
+    static_assert(C::N2 <= NT, "a plane workgroup covers every column pair");
+    constexpr int YS = NT / C::N2;
     const int j = threadIdx.x % C::N2;
     double2 w0[NLX], w1[NLX];
 #pragma unroll
@@ -1473,23 +1472,73 @@ __global__ void k_validate(const float* __restrict__ V, int nv, const int32_t* _
 
 // ------------------------------------------------------------- launchers
 
+// Schedule variants of the search kernels, chosen per canvas edge by the
+// autotuner.  Plane workgroups (passes 1 and 3): (threads, waves per SIMD asked
+// of the compiler) = (256, 1), (256, 2), (512, 4), (1024, 4); edges up to 80
+// take the first three, edges up to 128 the last three, larger edges the last.
+// z-pencil workgroups: 128, 256 or 512 threads per tile of T pencils.
+template <int V> struct PlaneVariant;
+template <> struct PlaneVariant<0> { static constexpr int NT = 256, WPE = 1; };
+template <> struct PlaneVariant<1> { static constexpr int NT = 256, WPE = 2; };
+template <> struct PlaneVariant<2> { static constexpr int NT = 512, WPE = 4; };
+template <> struct PlaneVariant<3> { static constexpr int NT = 1024, WPE = 4; };
+__host__ __device__ constexpr int z_threads_of(int v) { return v == 0 ? 128 : v == 1 ? 256 : 512; }
+
+__host__ __device__ constexpr bool plane_variant_valid(int N, int v) {
+    // above 128 a plane fills more than half of the LDS, so one workgroup per
+    // CU holds the whole plane: only the widest workgroup is offered
+    return v >= 0 && v < PLANE_VARIANTS && (N <= 80 ? v <= 2 : N <= 128 ? v >= 1 : v == 3);
+}
+template <int N>
+constexpr bool z_variant_valid(int v) {
+    return v >= 0 && v < Z_VARIANTS && (v == 1 || z_threads_of(v) <= N * Canvas<N>::T);
+}
+
+template <int N, int V>
+static void launch_plane(int pass, const SearchBatchArgs& a) {
+    if constexpr (plane_variant_valid(N, V)) {
+        constexpr int NT = PlaneVariant<V>::NT, WPE = PlaneVariant<V>::WPE;
+        if (pass == 0)
+            hipLaunchKernelGGL((k_rotvox_fwd_xy<N, NT, WPE>), dim3(a.count * N), dim3(NT), 0, a.stream, a.cmask, a.m,
+                               a.mp / 4, a.rots, a.count, a.tw, a.tw64, a.spec, a.lowT);
+        else
+            hipLaunchKernelGGL((k_inv_xy_argmax<N, NT, WPE>), dim3(a.count * N), dim3(NT), 0, a.stream, a.spec, a.count,
+                               a.tw, a.tw64, a.Plow, a.ptop, a.pssq, a.corr_out);
+    }
+}
+
+template <int N, int V>
+static void launch_z(const SearchBatchArgs& a) {
+    if constexpr (z_variant_valid<N>(V)) {
+        constexpr int ZT = z_threads_of(V);
+        hipLaunchKernelGGL((k_zpass<N, 0, ZT>), dim3(a.count * Canvas<N>::TILES), dim3(ZT), 0, a.stream, a.spec, a.W,
+                           nullptr, a.tw, 1.0f);
+    }
+}
+
 template <int N>
 static hipError_t launch_search_pass(int pass, const SearchBatchArgs& a) {
-    using C = Canvas<N>;
     // the sample generator relies on every rotated canvas point lying inside
     // the lattice with a one-cell margin
     if (a.m < 2 * (int)std::ceil((std::sqrt(3.0) * N + 2.0) / 2.0) || a.mp < a.m || a.mp % 4) return hipErrorInvalidValue;
-    if (pass == 0)
-        hipLaunchKernelGGL(k_rotvox_fwd_xy<N>, dim3(a.count * N), dim3(C::NT), 0, a.stream, a.cmask, a.m, a.mp / 4, a.rots,
-                           a.count, a.tw, a.tw64, a.spec, a.lowT);
-    else if (pass == 1) {
+    if (pass == 1) {
+        if (!z_variant_valid<N>(a.zv)) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_low_combine<0>), dim3(a.count * NLOW2), dim3(256), 0, a.stream, a.lowT, N, a.tw64, a.Wlow, 1.0,
                            a.Plow);
-        hipLaunchKernelGGL((k_zpass<N, 0>), dim3(a.count * C::TILES), dim3(C::ZT), 0, a.stream, a.spec, a.W, nullptr, a.tw,
-                           1.0f);
-    } else {
-        hipLaunchKernelGGL(k_inv_xy_argmax<N>, dim3(a.count * N), dim3(C::NT), 0, a.stream, a.spec, a.count, a.tw, a.tw64,
-                           a.Plow, a.ptop, a.pssq, a.corr_out);
+        switch (a.zv) {
+            case 0: launch_z<N, 0>(a); break;
+            case 1: launch_z<N, 1>(a); break;
+            default: launch_z<N, 2>(a); break;
+        }
+        return hipGetLastError();
+    }
+    const int v = pass == 0 ? a.pv1 : a.pv3;
+    if (!plane_variant_valid(N, v)) return hipErrorInvalidValue;
+    switch (v) {
+        case 0: launch_plane<N, 0>(pass, a); break;
+        case 1: launch_plane<N, 1>(pass, a); break;
+        case 2: launch_plane<N, 2>(pass, a); break;
+        default: launch_plane<N, 3>(pass, a); break;
     }
     return hipGetLastError();
 }
@@ -1500,7 +1549,7 @@ static hipError_t launch_object_spectrum(const float* O, float2* spec_tmp, float
     using C = Canvas<N>;
     const double scale = 1.0 / ((double)N * N * N);
     hipLaunchKernelGGL(k_grid_fwd_xy<N>, dim3(N), dim3(C::NT), 0, s, O, tw, tw64, spec_tmp, lowT_tmp);
-    hipLaunchKernelGGL((k_zpass<N, 1>), dim3(C::TILES), dim3(C::ZT), 0, s, spec_tmp, nullptr, W, tw, (float)scale);
+    hipLaunchKernelGGL((k_zpass<N, 1, 256>), dim3(C::TILES), dim3(256), 0, s, spec_tmp, nullptr, W, tw, (float)scale);
     hipLaunchKernelGGL((k_low_combine<1>), dim3(NLOW2), dim3(256), 0, s, lowT_tmp, N, tw64, nullptr, scale, Wlow);
     return hipGetLastError();
 }
@@ -1533,6 +1582,29 @@ int tile_width(int n) {
         default: return 0;
     }
 }
+
+bool plane_variant_ok(int n, int v) {
+    switch (n) {
+#define CASE(N) case N: return plane_variant_valid(N, v);
+        REGDOCK_FOR_EACH_N(CASE)
+#undef CASE
+        default: return false;
+    }
+}
+
+bool z_variant_ok(int n, int v) {
+    switch (n) {
+#define CASE(N) case N: return z_variant_valid<N>(v);
+        REGDOCK_FOR_EACH_N(CASE)
+#undef CASE
+        default: return false;
+    }
+}
+
+int default_plane_variant(int n) { return n > 128 ? 3 : n >= 96 ? 2 : 0; }
+int default_z_variant(int) { return 1; }
+int plane_variant_threads(int v) { return v == 0 || v == 1 ? 256 : v == 2 ? 512 : 1024; }
+int z_variant_threads(int v) { return z_threads_of(v); }
 
 hipError_t search_pass(int n, int pass, const SearchBatchArgs& a) {
     switch (n) {

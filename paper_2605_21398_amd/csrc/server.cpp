@@ -1,14 +1,28 @@
-// Serving loop: registrations are submitted from any thread, admitted in
-// arrival order as device memory and worker slots free up, and run
-// concurrently on one HIP stream per slot, so the work of requests that
-// arrive while others are on the GPU overlaps on the device (continuous
-// batching).  Object spectra stay resident in a cache keyed by the mesh's
-// contents (a 64-bit hash, confirmed byte for byte on a hit), the canvas and
-// the object-grid thresholds.  In serial mode a single slot gives the plain
-// one-request-at-a-time path.
+// Serving loop: registrations are submitted from any thread and admitted in
+// arrival order as device memory and worker slots free up.
+//
+// Serial mode (one slot) is the plain path: each registration runs whole on
+// one stream, one after the other.
+//
+// Continuous mode splits each admitted registration into work items.  Its
+// worker thread stages the inputs and builds the handle (object grid and
+// spectrum, or the cached object; swept lattice) on the worker's stream; a
+// scheduler thread then issues the registration's rotation batches (three
+// search passes and candidate selection each) onto two shared search
+// streams, always taking the next batch of the admitted registration with the
+// least search work left, so a small request is not stuck behind a large one;
+// once its last batch is issued, the worker certifies the scores, takes the
+// top K and refines them on its own stream while the search streams serve
+// other registrations.  Results equal the serial path's bit for bit: every
+// item runs the same kernels on the same data.
+//
+// Object spectra stay resident in a cache keyed by the mesh's contents (a
+// 64-bit hash, confirmed byte for byte on a hit), the canvas and the
+// object-grid thresholds.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -84,18 +98,39 @@ struct CacheEntry {
     std::shared_ptr<ObjectData> obj;
 };
 
+// a registration's search in continuous mode, shared by its worker and the
+// scheduler (guarded by reg_server::mu)
+struct SearchTask {
+    reg_handle* h = nullptr;
+    int M = 0, B = 0, nb = 0, sets = 1;
+    int next = 0;                 // next batch to issue
+    double cost = 0;              // model bytes of one batch (4 half-spectra per rotation)
+    hipEvent_t ready = nullptr;   // the handle is built (recorded on the worker's stream)
+    hipEvent_t set_ev[2] = {nullptr, nullptr};  // last batch issued on each pass-buffer set
+    bool issued_all = false;
+    int error = 0;
+};
+
 }  // namespace
 
 struct reg_server {
     reg_server_cfg cfg{};
     std::mutex mu;
-    std::condition_variable cv_dispatch, cv_done, cv_work;
+    std::condition_variable cv_dispatch, cv_done, cv_work, cv_sched, cv_issued;
     std::deque<std::shared_ptr<Job>> queue;
     std::map<reg_ticket, std::shared_ptr<Job>> jobs;
     std::vector<std::shared_ptr<Job>> slot_job;  // per worker: assigned job or null
     std::vector<std::thread> workers;
     std::thread dispatcher;
     std::vector<hipStream_t> streams;
+    // continuous mode: registrations searching, the shared search streams and
+    // the batches in flight on them (completion events, oldest first)
+    std::vector<std::shared_ptr<SearchTask>> tasks;
+    std::thread scheduler;
+    hipStream_t sstream[2] = {nullptr, nullptr};
+    std::deque<hipEvent_t> inflight[2];
+    std::vector<hipEvent_t> ev_pool;
+    int64_t batches_issued = 0;
     bool stopping = false;
     reg_ticket next_ticket = 1;
     size_t in_use = 0;
@@ -147,6 +182,7 @@ struct reg_server {
     int run_gpu(Job& j, hipStream_t s);
     void worker_loop(int w);
     void dispatch_loop();
+    void schedule_loop();
 };
 
 // One registration on the worker's stream: stage the inputs, build (or take
@@ -207,8 +243,43 @@ int reg_server::run_gpu(Job& j, hipStream_t s) {
     } hf{h};
     if (!cached && j.object_id >= 0) cache_put(key, j.mesh, regdock_rt::object_of(h));
 
-    rc = score_rotations(h, 0, M, dS, nullptr, dPose);
-    if (rc) return sfail(rc, regdock_rt::last_error());
+    if (cfg.mode == 1) {
+        rc = score_rotations(h, 0, M, dS, nullptr, dPose);
+        if (rc) return sfail(rc, regdock_rt::last_error());
+    } else {
+        // hand the search to the scheduler, then certify on this stream
+        auto t = std::make_shared<SearchTask>();
+        t->h = h;
+        t->M = M;
+        t->B = regdock_rt::handle_batch(h);
+        t->nb = (M + t->B - 1) / t->B;
+        t->sets = regdock_rt::handle_buffer_sets(h);
+        t->cost = 4.0 * (double)t->B * (double)j.grid.n * j.grid.n * (j.grid.n / 2 + 1) * 8.0;
+        struct FreeEv {
+            SearchTask* t;
+            hipStream_t s;
+            ~FreeEv() {
+                (void)hipStreamSynchronize(s);  // every batch is done once the stream's later work is
+                for (hipEvent_t e : {t->ready, t->set_ev[0], t->set_ev[1]})
+                    if (e) (void)hipEventDestroy(e);
+            }
+        } fe{t.get(), s};
+        for (hipEvent_t* e : {&t->ready, &t->set_ev[0], &t->set_ev[1]})
+            if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return sfail(REG_EDEVICE, "event");
+        if (hipEventRecord(t->ready, s) != hipSuccess) return sfail(REG_EDEVICE, "event record");
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            tasks.push_back(t);
+            cv_sched.notify_all();
+            cv_issued.wait(lk, [&] { return t->issued_all; });
+            tasks.erase(std::find(tasks.begin(), tasks.end(), t));
+        }
+        if (t->error) return sfail(t->error, "search batch failed");
+        for (int k = 0; k < t->sets; ++k)
+            if (hipStreamWaitEvent(s, t->set_ev[k], 0) != hipSuccess) return sfail(REG_EDEVICE, "wait");
+        rc = regdock_rt::enqueue_search_finish(h, dS, nullptr, dPose, s);
+        if (rc) return sfail(rc, regdock_rt::last_error());
+    }
     rc = register_top_k(h, dS, M, K, dTop);
     if (rc) return sfail(rc, regdock_rt::last_error());
     std::vector<int32_t> top(K);
@@ -278,6 +349,83 @@ void reg_server::worker_loop(int w) {
     }
 }
 
+// Continuous mode: issue rotation batches of the registrations whose handle is
+// built, the one with the least search work left first, onto the two search
+// streams, keeping at most two batches in flight per stream.  A batch waits
+// on the device for its handle's build and for the previous batch that used
+// its pass-buffer set.
+void reg_server::schedule_loop() {
+    constexpr int PER_STREAM = 2;
+    int rr = 0;
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+        for (int k = 0; k < 2; ++k)
+            while (!inflight[k].empty() && hipEventQuery(inflight[k].front()) == hipSuccess) {
+                ev_pool.push_back(inflight[k].front());
+                inflight[k].pop_front();
+            }
+        SearchTask* pick = nullptr;
+        double least = INFINITY;
+        for (auto& t : tasks) {
+            if (t->issued_all) continue;
+            const double left = (double)(t->nb - t->next) * t->cost;
+            if (left < least) {
+                least = left;
+                pick = t.get();
+            }
+        }
+        const int slot = inflight[rr].size() < PER_STREAM ? rr : inflight[1 - rr].size() < PER_STREAM ? 1 - rr : -1;
+        if (pick && slot >= 0) {
+            hipStream_t ss = sstream[slot];
+            const int b = pick->next++;
+            const int set = pick->sets == 2 ? (b & 1) : 0;
+            const int b0 = b * pick->B, cnt = std::min(pick->B, pick->M - b0);
+            hipEvent_t done = nullptr;
+            if (!ev_pool.empty()) {
+                done = ev_pool.back();
+                ev_pool.pop_back();
+            } else if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) {
+                done = nullptr;
+            }
+            int rc = REG_OK;
+            if (!done || hipStreamWaitEvent(ss, pick->ready, 0) != hipSuccess ||
+                (b >= pick->sets && hipStreamWaitEvent(ss, pick->set_ev[set], 0) != hipSuccess))
+                rc = REG_EDEVICE;
+            if (!rc) rc = regdock_rt::enqueue_search_batch(pick->h, b0, cnt, set, ss);
+            if (!rc && (hipEventRecord(pick->set_ev[set], ss) != hipSuccess || hipEventRecord(done, ss) != hipSuccess))
+                rc = REG_EDEVICE;
+            if (rc) {
+                pick->error = rc;
+                pick->issued_all = true;
+                if (done) ev_pool.push_back(done);
+                cv_issued.notify_all();
+                continue;
+            }
+            inflight[slot].push_back(done);
+            ++batches_issued;
+            rr = 1 - slot;
+            if (pick->next == pick->nb) {
+                pick->issued_all = true;
+                cv_issued.notify_all();
+            }
+            continue;
+        }
+        if (stopping && tasks.empty()) break;
+        // wait for a new registration, or poll the batches in flight
+        cv_sched.wait_for(lk, std::chrono::microseconds(100));
+    }
+    lk.unlock();
+    for (int k = 0; k < 2; ++k) {
+        for (hipEvent_t e : inflight[k]) {
+            (void)hipEventSynchronize(e);
+            (void)hipEventDestroy(e);
+        }
+        inflight[k].clear();
+    }
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    ev_pool.clear();
+}
+
 // Admission in arrival order: the head of the queue starts when a slot is free
 // and its footprint fits beside the registrations in flight.
 void reg_server::dispatch_loop() {
@@ -333,10 +481,19 @@ int register_server_create(const reg_server_cfg* cfg, reg_server** out) {
                 return sfail(REG_EDEVICE, "hipStreamCreate failed");
             }
     }
+    if (!c.fake && c.mode != 1)
+        for (auto& st : srv->sstream)
+            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+                for (auto& t : srv->streams) (void)hipStreamDestroy(t);
+                for (auto& t : srv->sstream)
+                    if (t) (void)hipStreamDestroy(t);
+                return sfail(REG_EDEVICE, "hipStreamCreate failed");
+            }
     srv->slot_job.resize(c.max_inflight);
     reg_server* s = srv.get();
     for (int w = 0; w < c.max_inflight; ++w) s->workers.emplace_back([s, w] { s->worker_loop(w); });
     s->dispatcher = std::thread([s] { s->dispatch_loop(); });
+    if (!c.fake && c.mode != 1) s->scheduler = std::thread([s] { s->schedule_loop(); });
     *out = srv.release();
     return REG_OK;
 }
@@ -357,8 +514,17 @@ void register_server_destroy(reg_server* s) {
     s->dispatcher.join();
     s->cv_work.notify_all();
     for (auto& t : s->workers) t.join();  // running registrations finish first
+    if (s->scheduler.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->cv_sched.notify_all();
+        }
+        s->scheduler.join();
+    }
     s->cv_done.notify_all();
     for (auto& st : s->streams) (void)hipStreamDestroy(st);
+    for (auto& st : s->sstream)
+        if (st) (void)hipStreamDestroy(st);
     s->cache.clear();
     delete s;
 }

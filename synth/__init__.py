@@ -12,5 +12,5 @@ from .gen import (  # noqa: F401
     mat_to_quat, quat_mul, haar_quaternion, sobol_hopf_so3, hemisphere_directions,
     min_rotation_to, footprint_top, make_trajectory, Problem, make_problem,
     CONFIGS, config_problem, grid_edge_m, BATCH_N, BATCH_M, SERVE_MESHES, SERVE_RATE, batch_spec,
-    batch_problem, serve_mesh, serve_spec, serve_problem, serve_arrivals,
+    batch_problem, serve_mesh, serve_spec, serve_problem, serve_arrivals, serve_picks,
 )

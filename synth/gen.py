@@ -34,7 +34,7 @@ from scipy.stats import qmc
 SEED = 260521398
 
 # stream ids of the seeded generators
-S_MESH, S_GT, S_TRAJ, S_CONTACT, S_SOBOL, S_ARRIVAL, S_SIZE = 0, 1, 2, 3, 4, 5, 6
+S_MESH, S_GT, S_TRAJ, S_CONTACT, S_SOBOL, S_ARRIVAL, S_SIZE, S_PICK = 0, 1, 2, 3, 4, 5, 6, 7
 
 
 def rng(cfg: int, item: int, stream: int) -> np.random.Generator:
@@ -435,6 +435,11 @@ def serve_problem(req: int, cfg: int = 5, mesh_cache: dict | None = None, **over
         if mesh_cache is not None:
             mesh_cache[mid] = mesh
     return mid, make_problem(cfg, req, mesh=mesh, **spec)
+
+
+def serve_picks(count: int, pool: int, cfg: int = 5) -> np.ndarray:
+    """Which of `pool` pre-generated requests each of `count` arrivals carries."""
+    return rng(cfg, 0, S_PICK).integers(0, pool, size=count)
 
 
 def serve_arrivals(count: int, rate: float = SERVE_RATE, cfg: int = 5) -> np.ndarray:

@@ -5,7 +5,10 @@ Only the FP64 oracle (oracle/) and the seeded input generators (synth/) are
 called.  The starts are the oracle's own top-16 (score descending, rotation
 index ascending) from tests/golden/search_cfg3.npz, which
 make_search_golden.py writes: each start is the pose of its rotation's peak
-(oracle.search.pose_from_shift).  Each is refined by oracle.refine.refine.
+(oracle.search.pose_from_shift).  Each is refined by oracle.refine.refine; the
+file also holds the final twist, the projected gradient there and the damping
+mu when the iteration stopped (small where it converged, large where the
+Gauss-Newton model kept failing, as at a kink of the objective).
 
     python tests/golden/make_refine_golden.py --workers 4
 """
@@ -62,8 +65,12 @@ def _one(k: int):
                     S.quat_to_mat(st[:4]), st[4:], g["a"], g["table"])
     t0 = time.time()
     o = Rf.refine(pb)
-    print(f"start {k}: J {o.J:.8f} iters {o.iters} in {time.time() - t0:.0f} s", flush=True)
-    return k, o.R, o.p, o.J, o.iters
+    # projected gradient where the iteration stopped: small at a stationary
+    # point, not at a kink of J where the damped steps stall
+    _, gr, _ = Rf.evaluate(o.xi, pb)
+    pg = float(np.abs(o.xi - Rf.project_box(o.xi - gr, Rf.RefineParams())).max())
+    print(f"start {k}: J {o.J:.8f} iters {o.iters} pg {pg:.3e} mu {o.mu:.1e} in {time.time() - t0:.0f} s", flush=True)
+    return k, o.R, o.p, o.J, o.iters, o.xi, pg, o.mu
 
 
 def main():
@@ -81,7 +88,9 @@ def main():
     out = os.path.join(HERE, "refine_cfg3.npz")
     np.savez_compressed(out, digest=np.array(input_digest(p)), rotations=top, starts=starts,
                         R=np.stack([x[1] for x in res]), p=np.stack([x[2] for x in res]),
-                        J=np.array([x[3] for x in res]), iters=np.array([x[4] for x in res]))
+                        J=np.array([x[3] for x in res]), iters=np.array([x[4] for x in res]),
+                        xi=np.stack([x[5] for x in res]), pg=np.array([x[6] for x in res]),
+                        mu=np.array([x[7] for x in res]))
     print(f"{len(res)} starts refined in {time.time() - t0:.0f} s -> {out}")
 
 
