@@ -1,4 +1,4 @@
-// Mixed-radix (2, 3, 4, 5, 8) complex FFTs on LDS-resident batches, for gfx950.
+// Mixed-radix (2, 3, 4, 5, 8, 16) complex FFTs on LDS-resident batches, for gfx950.
 //
 // The docking score of Sec. IV-B is a circular cross-correlation evaluated
 // through 3D FFTs (Eq. xcorr and the FFT identity that follows it).  This
@@ -125,14 +125,70 @@ template <bool INV> struct Dft<8, INV> {
     }
 };
 
+template <bool INV> struct Dft<16, INV> {
+    // 4 x 4: radix-4 DFTs over the residues n2 = j mod 4 (inputs j = 4 n1 + n2),
+    // twiddles W16^(n2 k1), radix-4 DFTs over n2; output k = k1 + 4 k2
+    __device__ __forceinline__ static void run(float2* v) {
+        const float h = 0.707106781186547524f;   // cos(pi/4)
+        const float c1 = 0.923879532511286756f;  // cos(pi/8)
+        const float s1 = 0.382683432365089772f;  // sin(pi/8)
+        float2 a[4][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < 4; ++n1) a[n2][n1] = v[4 * n1 + n2];
+            Dft<4, INV>::run(a[n2]);
+        }
+        // forward W16^m = exp(-2 pi i m / 16); the inverse conjugates
+        auto tw = [](float2 x, float wr, float wi) {
+            const float si = INV ? -wi : wi;
+            return make_float2(x.x * wr - x.y * si, x.x * si + x.y * wr);
+        };
+        a[1][1] = tw(a[1][1], c1, -s1);   // m = 1
+        a[1][2] = INV ? make_float2(h * (a[1][2].x - a[1][2].y), h * (a[1][2].x + a[1][2].y))
+                      : make_float2(h * (a[1][2].x + a[1][2].y), h * (a[1][2].y - a[1][2].x));  // m = 2
+        a[1][3] = tw(a[1][3], s1, -c1);   // m = 3
+        a[2][1] = INV ? make_float2(h * (a[2][1].x - a[2][1].y), h * (a[2][1].x + a[2][1].y))
+                      : make_float2(h * (a[2][1].x + a[2][1].y), h * (a[2][1].y - a[2][1].x));  // m = 2
+        a[2][2] = mul_mi<INV>(a[2][2]);    // m = 4
+        a[2][3] = INV ? make_float2(-h * (a[2][3].x + a[2][3].y), h * (a[2][3].x - a[2][3].y))
+                      : make_float2(h * (a[2][3].y - a[2][3].x), -h * (a[2][3].x + a[2][3].y));  // m = 6
+        a[3][1] = tw(a[3][1], s1, -c1);   // m = 3
+        a[3][2] = INV ? make_float2(-h * (a[3][2].x + a[3][2].y), h * (a[3][2].x - a[3][2].y))
+                      : make_float2(h * (a[3][2].y - a[3][2].x), -h * (a[3][2].x + a[3][2].y));  // m = 6
+        a[3][3] = tw(a[3][3], -c1, s1);   // m = 9
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            float2 b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+            Dft<4, INV>::run(b);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = b[k2];
+        }
+    }
+};
+
 // ------------------------------------------------------- factorisation plan
 
+__host__ __device__ constexpr int pow2_exponent(int L) {
+    int e = 0;
+    while (L > 1 && L % 2 == 0) {
+        L /= 2;
+        ++e;
+    }
+    return e;
+}
+
 __host__ __device__ constexpr int fft_radix(int L, int p) {
-    // greedy: 8s, then a 4, then a 2, then 5s, then 3s
+    // greedy: 8s, then a 4, then a 2, then 5s, then 3s; when the power of two
+    // in L is 2^(3k + 1) (k >= 1) one radix-16 stage replaces an 8 and a 2,
+    // saving a pass
+    bool use16 = pow2_exponent(L) >= 4 && pow2_exponent(L) % 3 == 1;
     int i = 0;
     while (L > 1) {
-        int r = (L % 8 == 0) ? 8 : (L % 4 == 0) ? 4 : (L % 2 == 0) ? 2 : (L % 5 == 0) ? 5 : (L % 3 == 0) ? 3 : 0;
+        int r = (use16 && L % 16 == 0) ? 16
+              : (L % 8 == 0) ? 8 : (L % 4 == 0) ? 4 : (L % 2 == 0) ? 2 : (L % 5 == 0) ? 5 : (L % 3 == 0) ? 3 : 0;
         if (r == 0) return 0;
+        if (r == 16) use16 = false;
         if (i == p) return r;
         L /= r;
         ++i;

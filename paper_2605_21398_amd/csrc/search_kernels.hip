@@ -154,27 +154,32 @@ __device__ __forceinline__ void batched_copy(Src src, Dst dst) {
 template <int N, int NT>
 __device__ __forceinline__ void r2c_post(float2* plane, const float2* tw) {
     using C = Canvas<N>;
-    constexpr int Q = C::N2 / 2 + 1;
-    for (int e = threadIdx.x; e < N * Q; e += NT) {
-        const int y = e / Q, k = e % Q;
-        float2* row = plane + y * C::P;
-        if (k == 0) {
-            const float2 z0 = row[0];
-            row[0] = make_float2(z0.x + z0.y, 0.0f);
-            row[C::N2] = make_float2(z0.x - z0.y, 0.0f);
-        } else {
-            const int kk = C::N2 - k;
-            const float2 a = row[k], b = row[kk];
-            // pair k
-            float2 s = cadd(a, cconj(b)), d = csub(a, cconj(b));
-            float2 wd = cmul(tw[k], d);
-            float2 xk = make_float2(0.5f * (s.x + wd.y), 0.5f * (s.y - wd.x));
-            // pair N/2 - k
-            float2 s2 = cadd(b, cconj(a)), d2 = csub(b, cconj(a));
-            float2 wd2 = cmul(tw[kk], d2);
-            float2 xkk = make_float2(0.5f * (s2.x + wd2.y), 0.5f * (s2.y - wd2.x));
-            row[k] = xk;
-            row[kk] = xkk;
+    constexpr int Q = C::N2 / 2 + 1;  // pairs (k, N/2 - k), k in [0, N/4]
+    constexpr int R = NT / Q;         // rows per step: thread t keeps k = t % Q and its twiddles
+    static_assert(R >= 1, "a plane workgroup covers the pairs of a row");
+    const int t = threadIdx.x;
+    if (t < R * Q) {
+        const int k = t % Q, kk = C::N2 - k;
+        const float2 wk = tw[k], wkk = tw[kk];
+        for (int y = t / Q; y < N; y += R) {
+            float2* row = plane + y * C::P;
+            if (k == 0) {
+                const float2 z0 = row[0];
+                row[0] = make_float2(z0.x + z0.y, 0.0f);
+                row[C::N2] = make_float2(z0.x - z0.y, 0.0f);
+            } else {
+                const float2 a = row[k], b = row[kk];
+                // pair k
+                float2 s = cadd(a, cconj(b)), d = csub(a, cconj(b));
+                float2 wd = cmul(wk, d);
+                float2 xk = make_float2(0.5f * (s.x + wd.y), 0.5f * (s.y - wd.x));
+                // pair N/2 - k
+                float2 s2 = cadd(b, cconj(a)), d2 = csub(b, cconj(a));
+                float2 wd2 = cmul(wkk, d2);
+                float2 xkk = make_float2(0.5f * (s2.x + wd2.y), 0.5f * (s2.y - wd2.x));
+                row[k] = xk;
+                row[kk] = xkk;
+            }
         }
     }
     __syncthreads();
@@ -187,21 +192,26 @@ template <int N, int NT>
 __device__ __forceinline__ void c2r_pre(float2* plane, const float2* tw) {
     using C = Canvas<N>;
     constexpr int Q = C::N2 / 2 + 1;
-    for (int e = threadIdx.x; e < N * Q; e += NT) {
-        const int y = e / Q, k = e % Q;
-        float2* row = plane + y * C::P;
-        const int kk = C::N2 - k;
-        const float2 a = row[k], b = row[kk];
-        float2 s = cadd(a, cconj(b)), d = csub(a, cconj(b));
-        float2 wd = cmulc(d, tw[k]);
-        float2 zk = make_float2(s.x - wd.y, s.y + wd.x);
-        if (k == 0) {
-            row[0] = zk;
-        } else {
-            float2 s2 = cadd(b, cconj(a)), d2 = csub(b, cconj(a));
-            float2 wd2 = cmulc(d2, tw[kk]);
-            row[kk] = make_float2(s2.x - wd2.y, s2.y + wd2.x);
-            row[k] = zk;
+    constexpr int R = NT / Q;
+    static_assert(R >= 1, "a plane workgroup covers the pairs of a row");
+    const int t = threadIdx.x;
+    if (t < R * Q) {
+        const int k = t % Q, kk = C::N2 - k;
+        const float2 wk = tw[k], wkk = tw[kk];
+        for (int y = t / Q; y < N; y += R) {
+            float2* row = plane + y * C::P;
+            const float2 a = row[k], b = row[kk];
+            float2 s = cadd(a, cconj(b)), d = csub(a, cconj(b));
+            float2 wd = cmulc(d, wk);
+            float2 zk = make_float2(s.x - wd.y, s.y + wd.x);
+            if (k == 0) {
+                row[0] = zk;
+            } else {
+                float2 s2 = cadd(b, cconj(a)), d2 = csub(b, cconj(a));
+                float2 wd2 = cmulc(d2, wkk);
+                row[kk] = make_float2(s2.x - wd2.y, s2.y + wd2.x);
+                row[k] = zk;
+            }
         }
     }
     __syncthreads();
