@@ -453,15 +453,23 @@ def sampler_bench(rd, torch, p, M: int):
 
 
 def linear_bench(rd, torch, M: int = 4096):
-    """The padded variant of the search (Sec. IV-B) on the smallest workload
-    (h 0.4 mm): the circular search on its 32^3 canvas against the same search
-    on the edge register_linear_edge gives (n_o + n_s - 1 = 107 -> 120), where
-    the correlation is linear.  Same Super-Fibonacci set; rotations/s of the
-    scoring, model HBM bytes per rotation and the best peak's pose error."""
+    """The padded variant of the search (Sec. IV-B) on the 32^3 (h 0.4 mm) and
+    64^3 (h 0.25 mm) workloads: the circular search on the workload's canvas
+    against the same search on the edge register_linear_edge gives
+    (n_o + n_s - 1 = 107 -> 120 and 173 -> 180), where the correlation is
+    linear.  Same Super-Fibonacci set; rotations/s of the scoring, model HBM
+    bytes per rotation and the best peak's pose error."""
+    out = {}
+    for cfg in (1, 2):
+        out[f"config{cfg}"] = _linear_one(rd, torch, cfg, M)
+    return out
+
+
+def _linear_one(rd, torch, cfg: int, M: int):
     import numpy as np
     import synth
 
-    p = synth.config_problem(1, 0)
+    p = synth.config_problem(cfg, 0)
     need, edge = rd.register_linear_edge(p.vertices, p.radius, p.length, p.poses, p.center, p.h)
     so3 = rd.so3_super_fibonacci(M)
     res = {"needed_edge": need, "rotations": M}

@@ -72,7 +72,7 @@ typedef struct {
 /* Common canvas of edge n at spacing h (Sec. IV-A/B).  The object canvas is
  * x_k = a + h (k - n/2) with a the mean of the mesh vertices; the swept
  * lattice is y_j = center_world + h (j - m/2), m = 2 ceil((sqrt(3) n + 2)/2).
- * n must be one of 16, 32, 48, 60, 64, 80, 96, 120, 128, 160. */
+ * n must be one of 16, 32, 48, 60, 64, 80, 96, 120, 128, 160, 180. */
 typedef struct {
     int32_t n;
     double h_mm;
@@ -133,7 +133,7 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
  *   *needed = n_o + n_s - 1; *edge = the smallest supported edge >= *needed.
  * Passing *edge as grid.n (same h and centre) gives a wrap-free search.
  * Errors: REG_EINVAL (NULL or non-finite input, h or probe size <= 0),
- * REG_ENOTSUP (*needed above 160; *needed is still set, *edge = 0). */
+ * REG_ENOTSUP (*needed above 180; *needed is still set, *edge = 0). */
 int register_linear_edge(const float* vertices, int32_t n_vertices, const reg_probe* probe, const float* poses,
                          int32_t n_poses, const double* center_world, double h_mm, double tau_out1, int32_t* needed,
                          int32_t* edge);

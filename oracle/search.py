@@ -304,10 +304,10 @@ def score_rotations(O, S_w, so3, n, h, a, wc, indices=None):
 #
 # Two decisions of the grids are step functions of a distance: the object
 # template jumps from 1 + f_o/tau_in1 (about 0) to -rho at f_o = -tau_in1, and
-# the swept occupancy switches at f_p = 0.  A float32 evaluation of the
-# distance can take either side within its rounding error, so voxels within
-# delta of a jump are flagged, and the score of a rotation is bounded over
-# every combination of their two values.
+# the swept occupancy switches at f_p = 0.  An evaluation of the distance in
+# another operation order (or precision) can take either side within its
+# rounding error, so voxels within delta of a jump are flagged, and the score
+# of a rotation is bounded over every combination of their two values.
 
 def object_flags(O, fo, d, prm: GridParams = GridParams(), delta: float = 1e-4):
     """|O_alt - O| at the object voxels with |f_o + tau_in1| < delta (else 0):

@@ -54,8 +54,17 @@ __host__ __device__ constexpr int largest_divisor_le(int v, int cap) {
     return 1;
 }
 
+// lattice edge m = 2 ceil((sqrt(3) n + 2) / 2): the smallest even m with
+// m - 2 >= sqrt(3) n, i.e. (m - 2)^2 >= 3 n^2 (exact in integers)
+__host__ __device__ constexpr int lattice_edge_of(int n) {
+    int m = 2;
+    while ((long long)(m - 2) * (m - 2) < 3ll * n * n) m += 2;
+    return m;
+}
+
 template <int N> struct Canvas {
     static constexpr int N2 = N / 2;
+    static constexpr int M = lattice_edge_of(N);          // swept lattice edge
     static constexpr int P = N2 + 1;                      // LDS row pitch (complex)
     static constexpr int T = largest_divisor_le(N2, 16);  // tile width (complex)
     static constexpr int NT2 = N2 / T;                    // main tiles per ky row
@@ -70,6 +79,7 @@ template <int N> struct Canvas {
     static_assert(N % 2 == 0, "canvas edge must be even");
     static_assert(fft_supported(N) && fft_supported(N2), "edge must be 2^a 3^b 5^c");
     static_assert((size_t)N * P * 8 <= 160 * 1024, "plane must fit in LDS");
+    static_assert((size_t)N * N * N <= (1u << 23), "flat indices must fit the 23-bit field of the peak keys");
 };
 
 // Workgroup -> (rotation, plane).  Workgroups are dealt round-robin to the 8
@@ -106,12 +116,6 @@ __device__ __forceinline__ size_t brick_index(int ix, int iy, int iz, int mb) {
     return ((((size_t)(iz >> 2) * mb + (iy >> 2)) * mb + (ix >> 2)) << 6) + ((iz & 3) << 4) + ((iy & 3) << 2) + (ix & 3);
 }
 
-// brick_index in 32-bit arithmetic with 24-bit multiplies (mp^3 < 2^31 for
-// every supported canvas)
-__device__ __forceinline__ uint32_t brick_index32(uint32_t ix, uint32_t iy, uint32_t iz, uint32_t mb) {
-    const uint32_t b = __umul24(__umul24(iz >> 2, mb) + (iy >> 2), mb) + (ix >> 2);
-    return (b << 6) | ((iz & 3u) << 4) | ((iy & 3u) << 2) | (ix & 3u);
-}
 
 // Trilinear value of a binary lattice from the corner mask of the cell
 // (bit cx + 2 cy + 4 cz is the lattice value at (i + cx, j + cy, k + cz)).
@@ -266,7 +270,14 @@ __device__ __forceinline__ int mod_n(int v, int n) {
 // sum_{x,y} s[x,y] exp(-2 pi i (kx x + ky y) / N) in double.  tw64 is the
 // double twiddle table in LDS.  Row sums over x run as second-order Goertzel
 // recurrences per kx (one FMA and one subtraction per sample and frequency, no
-// table reads); each row is split into CH contiguous chunks on CH lanes.
+// table reads); each row is split into CH contiguous chunks on CH lanes.  The
+// row sums go to rbuf[y][kx] with kx rotated by y / 4 inside the row
+// (low_slot), so that the 16 consecutive rows that the lanes of a wave read
+// together in the y pass fall in distinct banks.
+__device__ __forceinline__ int low_slot(int y, int kx) {
+    static_assert(NLX == 4, "the rotation assumes four kx entries per row");
+    return y * NLX + ((kx + (y >> 2)) & 3);
+}
 template <int N, int NT>
 __device__ __forceinline__ void plane_low_dft(const float2* plane, const double2* tw64, double2* rbuf,
                                               double2* __restrict__ out) {
@@ -318,30 +329,33 @@ __device__ __forceinline__ void plane_low_dft(const float2* plane, const double2
             }
         if (c == 0)
 #pragma unroll
-            for (int k = 0; k < NLX; ++k) rbuf[y * NLX + k] = acc[k];
+            for (int k = 0; k < NLX; ++k) rbuf[low_slot(y, k)] = acc[k];
     }
     __syncthreads();
-    // y direction: four lanes per (kx, ky), each a quarter of the rows
-    constexpr int CB = 4;
-    static_assert(N % CB == 0 && NLOW2 * CB <= NT, "low-block y pass layout");
+    // y direction: CB lanes per (kx, ky) (CB a power of two, at most 16, with
+    // NLOW2 CB <= NT), lane c taking rows c, c + CB, ...; a shuffle tree adds
+    // the CB parts
+    constexpr int CB = pow2floor(NT / NLOW2) < 16 ? pow2floor(NT / NLOW2) : 16;
+    static_assert(CB >= 1 && NLOW2 * CB <= NT && 64 % CB == 0, "low-block y pass layout");
     double2 part = make_double2(0.0, 0.0);
     if (t < NLOW2 * CB) {
         const int o = t / CB, c = t % CB;
         const int kx = o / NLY, ky = o % NLY - KLOW;
-        int idx = mod_n(ky * c * (N / CB), N);
-        const int step = mod_n(ky, N);
-        for (int y = c * (N / CB); y < (c + 1) * (N / CB); ++y) {
-            const double2 r = rbuf[y * NLX + kx], w = tw64[idx];
+        int idx = mod_n(ky * c, N);
+        const int step = mod_n(ky * CB, N);
+        for (int y = c; y < N; y += CB) {
+            const double2 r = rbuf[low_slot(y, kx)], w = tw64[idx];
             part.x = fma(r.x, w.x, fma(-r.y, w.y, part.x));
             part.y = fma(r.x, w.y, fma(r.y, w.x, part.y));
             idx += step;
             idx -= idx >= N ? N : 0;
         }
     }
-    part.x += __shfl_xor(part.x, 1, 64);
-    part.y += __shfl_xor(part.y, 1, 64);
-    part.x += __shfl_xor(part.x, 2, 64);
-    part.y += __shfl_xor(part.y, 2, 64);
+#pragma unroll
+    for (int off = CB / 2; off >= 1; off >>= 1) {
+        part.x += __shfl_xor(part.x, off, 64);
+        part.y += __shfl_xor(part.y, off, 64);
+    }
     if (t < NLOW2 * CB && (t % CB) == 0) out[t / CB] = part;
 }
 
@@ -410,6 +424,21 @@ __device__ __forceinline__ void build_trilinear_lut(float4* lut) {
     }
 }
 
+// Per-axis parts of brick_index on a lattice of edge m (padded to mb bricks of
+// 4 per axis): the brick coordinate times its stride in bytes, plus the
+// position inside the brick.  The three parts of a cell occupy disjoint bits
+// inside the brick and add up across bricks, so their sum is the address
+// (below 2^31: mp^3 < 2^31 for every supported canvas).
+template <int NT>
+__device__ __forceinline__ void build_brick_tables(uint32_t* bax, uint32_t* bay, uint32_t* baz, int m, int mb) {
+    for (int i = threadIdx.x; i < m; i += NT) {
+        const uint32_t b = (uint32_t)i >> 2, r = (uint32_t)i & 3u;
+        bax[i] = (b << 6) | r;
+        bay[i] = ((b * (uint32_t)mb) << 6) | (r << 2);
+        baz[i] = ((b * (uint32_t)mb * (uint32_t)mb) << 6) | (r << 4);
+    }
+}
+
 // the polynomial at raw fraction words X, Y, Z (floats of the 32-bit words)
 __device__ __forceinline__ float trilinear_poly(const float4* lut, uint32_t mk, float X, float Y, float Z) {
     const float4 a = lut[2 * mk], b = lut[2 * mk + 1];
@@ -436,10 +465,14 @@ __device__ __forceinline__ float trilinear_poly(const float4* lut, uint32_t mk, 
 // m = 2 ceil((sqrt(3) n + 2) / 2) every sample lies in [1, m - 1] on each axis
 // (the launcher checks m).  Eight rows per batch keep 16 gathers in flight.
 // Each value is the trilinear polynomial of its cell (table in LDS), with no
-// branch on the mask.
+// branch on the mask.  The brick address of cell (ix, iy, iz) is the sum of
+// three per-axis table entries (bax[ix] + bay[iy] + baz[iz], see
+// build_brick_tables), three LDS reads in place of the shifts, masks and
+// multiplies of brick_index.
 template <int N, int NT>
-__device__ __forceinline__ void generate_plane(float2* plane, const float4* lut, const RotSampler& rs,
-                                               const uint8_t* __restrict__ cmask, int mb, int z) {
+__device__ __forceinline__ void generate_plane(float2* plane, const float4* lut, const uint32_t* bax,
+                                               const uint32_t* bay, const uint32_t* baz, const RotSampler& rs,
+                                               const uint8_t* __restrict__ cmask, int z) {
     using C = Canvas<N>;
     static_assert(C::N2 <= NT, "a plane workgroup covers every column pair");
     constexpr int YS = NT / C::N2;  // row step of a lane (YS * N2 lanes work, the rest idle)
@@ -473,7 +506,7 @@ __device__ __forceinline__ void generate_plane(float2* plane, const float4* lut,
                 fx[q] = (float)(uint32_t)U[s2][0];
                 fy[q] = (float)(uint32_t)U[s2][1];
                 fz[q] = (float)(uint32_t)U[s2][2];
-                addr[q] = brick_index32(ix, iy, iz, (uint32_t)mb);
+                addr[q] = bax[ix] + bay[iy] + baz[iz];
                 U[s2][0] += D[0];
                 U[s2][1] += D[1];
                 U[s2][2] += D[2];
@@ -511,6 +544,7 @@ __global__ __launch_bounds__(NT, WPE) void k_rotvox_fwd_xy(const uint8_t* __rest
     // low-block row sums only afterwards: they share one buffer
     constexpr int RB = N * NLX * (int)sizeof(double2), LB = TRI_LUT * (int)sizeof(float4);
     __shared__ __align__(16) unsigned char scratch_lds[RB > LB ? RB : LB];
+    __shared__ uint32_t bax[C::M], bay[C::M], baz[C::M];
     double2* rbuf = reinterpret_cast<double2*>(scratch_lds);
     float4* lut = reinterpret_cast<float4*>(scratch_lds);
     int rot, z;
@@ -520,10 +554,11 @@ __global__ __launch_bounds__(NT, WPE) void k_rotvox_fwd_xy(const uint8_t* __rest
         tws[i] = tw64[i];
     }
     build_trilinear_lut<NT>(lut);
+    build_brick_tables<NT>(bax, bay, baz, C::M, mb);
     RotSampler rs;
     rs.load(rots + rot * 9, m, N);
     __syncthreads();
-    generate_plane<N, NT>(plane, lut, rs, cmask, mb, z);
+    generate_plane<N, NT>(plane, lut, bax, bay, baz, rs, cmask, z);
     __syncthreads();
     plane_low_dft<N, NT>(plane, tws, rbuf, lowT + ((size_t)rot * N + z) * NLOW2);
     plane_forward_and_store<N, NT>(plane, tw, spec + (size_t)rot * C::H, z);
@@ -621,18 +656,22 @@ __global__ __launch_bounds__(ZT) void k_zpass(float2* __restrict__ spec, const f
 // locates candidates; their scores are recomputed exactly by k_rescore where
 // its error could exceed the tolerance.
 
-// key = orderable bits of a double, low 22 bits replaced by ~flat (flat < 2^22)
+// key = orderable bits of a double, low FLAT_BITS bits replaced by ~flat
+// (flat < 2^FLAT_BITS = 8,388,608 > 180^3); the value keeps 52 - FLAT_BITS
+// mantissa bits (relative truncation below 2^-29, under float32's rounding)
+constexpr int FLAT_BITS = 23;
+constexpr unsigned long long FLAT_MASK = (1ull << FLAT_BITS) - 1;
 __device__ __forceinline__ unsigned long long key64(double v, uint32_t flat) {
     unsigned long long b = (unsigned long long)__double_as_longlong(v);
     b = (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
-    return (b & ~0x3fffffull) | (unsigned long long)(0x3fffffu - flat);
+    return (b & ~FLAT_MASK) | (FLAT_MASK - flat);
 }
 __device__ __forceinline__ double key_value(unsigned long long k) {
-    unsigned long long b = k & ~0x3fffffull;
+    unsigned long long b = k & ~FLAT_MASK;
     b = (b & 0x8000000000000000ull) ? (b & 0x7fffffffffffffffull) : ~b;
     return __longlong_as_double((long long)b);
 }
-__device__ __forceinline__ uint32_t key_flat(unsigned long long k) { return 0x3fffffu - (uint32_t)(k & 0x3fffffull); }
+__device__ __forceinline__ uint32_t key_flat(unsigned long long k) { return (uint32_t)(FLAT_MASK - (k & FLAT_MASK)); }
 
 template <int N, int NT, int WPE>
 __global__ __launch_bounds__(NT, WPE) void k_inv_xy_argmax(const float2* __restrict__ spec, int count, const float2* __restrict__ twg,
@@ -1529,8 +1568,9 @@ static void launch_z(const SearchBatchArgs& a) {
 template <int N>
 static hipError_t launch_search_pass(int pass, const SearchBatchArgs& a) {
     // the sample generator relies on every rotated canvas point lying inside
-    // the lattice with a one-cell margin
-    if (a.m < 2 * (int)std::ceil((std::sqrt(3.0) * N + 2.0) / 2.0) || a.mp < a.m || a.mp % 4) return hipErrorInvalidValue;
+    // the lattice (edge m = 2 ceil((sqrt(3) n + 2) / 2)),
+    // with a one-cell margin, and its brick-address tables hold m entries
+    if (a.m != Canvas<N>::M || a.mp < a.m || a.mp % 4) return hipErrorInvalidValue;
     if (pass == 1) {
         if (!z_variant_valid<N>(a.zv)) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_low_combine<0>), dim3(a.count * NLOW2), dim3(256), 0, a.stream, a.lowT, N, a.tw64, a.Wlow, 1.0,
@@ -1564,7 +1604,7 @@ static hipError_t launch_object_spectrum(const float* O, float2* spec_tmp, float
     return hipGetLastError();
 }
 
-#define REGDOCK_FOR_EACH_N(X) X(16) X(32) X(48) X(60) X(64) X(80) X(96) X(120) X(128) X(160)
+#define REGDOCK_FOR_EACH_N(X) X(16) X(32) X(48) X(60) X(64) X(80) X(96) X(120) X(128) X(160) X(180)
 
 bool canvas_supported(int n) {
     switch (n) {

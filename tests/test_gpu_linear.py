@@ -2,13 +2,15 @@
 the C ABI:
 
 * register_linear_edge gives the oracle's n_o + n_s - 1, bit for bit, and the
-  smallest supported edge above it (none for the 64^3 and 128^3 workloads,
-  whose probe shafts need 173 and 359 points);
+  smallest supported edge above it (120 for the 32^3 workload, 180 for the
+  64^3 one, whose probe shafts need 173 points, none for the 128^3 one, which
+  needs 359);
 * on that edge the device's circular search is the linear correlation: for
-  the smallest workload at 120^3 (h 0.4 mm), with the oracle's grids injected,
-  scores meet the search's bar (1e-4 of the largest |score|) against the
-  oracle's zero-padded correlation of the same grids, and the peak shifts
-  agree modulo n or are tied within that bar.
+  the 32^3 workload at 120^3 (h 0.4 mm) and the 64^3 workload at 180^3
+  (h 0.25 mm), with the oracle's grids injected, scores meet the search's bar
+  (1e-4 of the largest |score|) against the oracle's zero-padded correlation
+  of the same grids, and the peak shifts agree modulo n or are tied within
+  that bar.
 """
 import math
 
@@ -37,7 +39,7 @@ def test_linear_edge_matches_oracle(cfg):
     n_o, n_s, ref = S.linear_edge(p.vertices, p.poses, p.radius, p.length, p.center, p.h)
     print(f"\nconfig {cfg}: n_o {n_o}, n_s {n_s}, needed {need}, edge {edge}")
     assert need == ref
-    supported = [16, 32, 48, 60, 64, 80, 96, 120, 128, 160]
+    supported = [16, 32, 48, 60, 64, 80, 96, 120, 128, 160, 180]
     assert edge == next((n for n in supported if n >= ref), 0)
 
 
@@ -54,11 +56,12 @@ def test_linear_edge_rejects_bad_input():
         rd.register_linear_edge(V, p.radius, p.length, p.poses, p.center, p.h)
 
 
-def test_padded_search_is_the_linear_correlation():
+@pytest.mark.parametrize("cfg,edge", [(1, 120), (2, 180)])
+def test_padded_search_is_the_linear_correlation(cfg, edge):
     rd = _lib()
-    p = synth.config_problem(1, 0, M=16)
+    p = synth.config_problem(cfg, 0, M=16)
     _, n = rd.register_linear_edge(p.vertices, p.radius, p.length, p.poses, p.center, p.h)
-    assert n == 120
+    assert n == edge
     O, _, _ = S.object_grid(p.vertices, p.faces, p.touchable, n, p.h)
     m = S.lattice_edge(n)
     Sw = S.swept_occupancy(S.swept_lattice(p.poses, p.radius, p.length, m, p.h, p.center))
