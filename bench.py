@@ -30,6 +30,8 @@ os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
 HBM_PEAK_GBPS = 8000.0
 METRIC = "SO(3) rotations scored/sec at 128^3 (GB/s vs HBM peak); p50/p99 request latency"
 KERNELS = {0: "k_rotvox_fwd_xy", 1: "k_zpass", 2: "k_inv_xy_argmax"}
+# search schedules tuned on an MI355X (paper_2605_21398_amd/schedules/make_schedule.py)
+SCHEDULE_FILE = os.path.join(ROOT, "paper_2605_21398_amd", "schedules", "mi355x.json")
 
 
 def workload_name(p, cfg):
@@ -119,10 +121,11 @@ def cpu_baseline(p, args, starts, evals: int, small):
     return out
 
 
-def counter_traffic(kernel: str, n: int):
+def counter_traffic(kernel: str, n: int, rotations_per_launch: float):
     """HBM bytes per launch of `kernel` at edge n from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's counters), or
-    None when there is none or the kernel source has changed since."""
+    None when there is none, its launches held another number of rotations, or
+    the kernel source has changed since."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "traffic_search_128.md")
@@ -139,7 +142,9 @@ def counter_traffic(kernel: str, n: int):
     if sha.hexdigest() != data.get("search_kernels_sha256"):
         return None
     k = data["kernels"].get(f"{kernel}<{n}>")
-    return None if k is None else k["traffic_bytes"]
+    if k is None or k.get("rotations_per_launch") != rotations_per_launch:
+        return None
+    return k["traffic_bytes"]
 
 
 def _gen_batch(i):
@@ -173,15 +178,20 @@ def generate(args):
 
 
 def batch_bench(rd, torch, probs, args):
-    """The uneven batch: autotune the rotation batch per canvas edge, capture all
-    registrations (search + top-16 + refinement) in one graph, replay it, and
-    time the same work issued eagerly handle after handle."""
+    """The uneven batch: the recorded schedule per canvas edge (autotuned here
+    where none is recorded), all registrations (search + top-16 + refinement)
+    captured in one graph and replayed, against the same work issued eagerly
+    handle after handle."""
     import numpy as np
     mk = lambda p, **kw: rd.register_init(p.vertices, p.faces, p.touchable, p.poses, p.so3, p.n, p.h, p.center,
                                           p.radius, p.length, **kw)
     tuned = {}
     for p in probs:
         if p.n not in tuned:
+            rec = rd.register_tuned_schedule(p.n)
+            if rec["tuned"]:
+                tuned[p.n] = rec["batch"]
+                continue
             h = mk(p)
             tuned[p.n] = rd.register_autotune(h, 256)
             rd.register_free(h)
@@ -384,7 +394,8 @@ def small_config_bench(rd, torch, probs, reps: int = 5):
         h = rd.register_init(p.vertices, p.faces, p.touchable, p.poses, p.so3, p.n, p.h, p.center, p.radius,
                              p.length)
         try:
-            rd.register_autotune(h, len(p.so3))
+            if not rd.register_tuned_schedule(p.n)["tuned"]:
+                rd.register_autotune(h, len(p.so3))
         finally:
             rd.register_free(h)
         h = rd.register_init(p.vertices, p.faces, p.touchable, p.poses, p.so3, p.n, p.h, p.center, p.radius,
@@ -556,7 +567,10 @@ def main():
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=256,
                     help="strided oracle rotations of the headline workload in the CPU baseline (0: skip)")
-    ap.add_argument("--tune", type=int, default=1, help="autotune the search schedule before timing (0: defaults)")
+    ap.add_argument("--tune", type=int, default=0,
+                    help="1: autotune the search schedule of the workload's edge before timing (else the --schedule file)")
+    ap.add_argument("--schedule", default=SCHEDULE_FILE,
+                    help="tuned schedules to load (register_tune_load; '' for the library defaults)")
     ap.add_argument("--small", type=int, default=1, help="time the 32^3 and 64^3 workloads too (0: skip)")
     ap.add_argument("--batch", type=int, default=32, help="registrations of the uneven batch (0: skip)")
     ap.add_argument("--batch-reps", type=int, default=2)
@@ -604,6 +618,10 @@ def main():
     K_TOP = 16
     stats = {k: [0.0, 0, 0] for k in KERNELS}
     info = {}
+    sched_source = "library defaults"
+    if args.schedule and not args.tune and (args.schedule != SCHEDULE_FILE or os.path.exists(args.schedule)):
+        rd.register_tune_load(args.schedule)
+        sched_source = os.path.relpath(args.schedule, ROOT)
     if args.tune:
         h = rd.register_init(V, F, T, P, Q, p.n, p.h, p.center, p.radius, p.length)
         try:
@@ -611,6 +629,7 @@ def main():
         finally:
             rd.register_free(h)
         print("bench: schedule tuned", file=sys.stderr, flush=True)
+        sched_source = "autotuned in this run"
 
     refine_s = []
     score_wall = []
@@ -693,7 +712,7 @@ def main():
                    "poses": len(p.poses), "faces": len(p.faces), "batch": B, "top_k": K_TOP},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["achieved_GBps"], "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": d["achieved_GBps"] / HBM_PEAK_GBPS,
-                     "traffic": counter_traffic(dom, p.n) if d["rotations_per_launch"] == 32 else None,
+                     "traffic": counter_traffic(dom, p.n, d["rotations_per_launch"]),
                      "algorithmic_bytes_per_launch": d["algorithmic_bytes_per_launch"],
                      "note": ("per-launch time in the timed region" +
                               (", where the two lanes' passes share the GPU; 'isolated' times the same launch alone"
@@ -704,7 +723,7 @@ def main():
                         "model_GBps": model_bytes / score_s / 1e9, "model_frac": model_bytes / score_s / 1e9 / HBM_PEAK_GBPS,
                         "kernel_ms_per_step": tot / args.steps,
                         "lanes": sched["lanes"]},
-        "schedule": sched,
+        "schedule": dict(sched, source=sched_source),
         "search_stats": info["search_stats"],
         "kernels": kern,
         "refine": {"ms_per_step": float(np.mean(refine_s)) * 1e3, "starts": K_TOP, "rounds": info["rounds"],
