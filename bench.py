@@ -89,7 +89,8 @@ def cpu_baseline(p, args, starts, evals: int, small):
     setup grids, a strided sample of rotations on a pool over all cores
     (extrapolated linearly to the full set) and one refinement objective
     evaluation times the number the refinement of all starts made; the same
-    search on one core; the two smaller workloads' searches."""
+    search on one core; the two smaller workloads' searches over all their
+    rotations."""
     import numpy as np
 
     from oracle import refine as Rf
@@ -115,7 +116,7 @@ def cpu_baseline(p, args, starts, evals: int, small):
            "search_rotations_per_s": {"all_cores": rate, "one_core": rate1, "cores": cores,
                                       "rotations_timed": {"all_cores": n_all, "one_core": n_one}}}
     for cfg, q_small in small.items():
-        _, r, n = oracle_search_rate(q_small, len(q_small.so3) if cfg == 1 else 128, cores)
+        _, r, n = oracle_search_rate(q_small, len(q_small.so3), cores)   # every rotation
         out[f"config{cfg}_search_rotations_per_s"] = {"value": r, "rotations_timed": n, "cores": cores,
                                                       "n": q_small.n}
     return out
