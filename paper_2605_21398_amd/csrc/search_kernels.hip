@@ -155,6 +155,8 @@ __device__ __forceinline__ void batched_copy(Src src, Dst dst) {
 // Rows hold z[j] = s[2j] + i s[2j+1]; after the length-N/2 FFT, turn each row
 // into X[k], k in [0, N/2], of the length-N real FFT:
 //   X[k] = ((Z[k] + conj Z[N/2-k]) - i w^k (Z[k] - conj Z[N/2-k])) / 2.
+// X[0] and X[N/2] are real; both go to slot 0 as X[0] + i X[N/2], so that the
+// y transform runs over n/2 columns (unpack_nyquist splits the result).
 template <int N, int NT>
 __device__ __forceinline__ void r2c_post(float2* plane, const float2* tw) {
     using C = Canvas<N>;
@@ -169,8 +171,7 @@ __device__ __forceinline__ void r2c_post(float2* plane, const float2* tw) {
             float2* row = plane + y * C::P;
             if (k == 0) {
                 const float2 z0 = row[0];
-                row[0] = make_float2(z0.x + z0.y, 0.0f);
-                row[C::N2] = make_float2(z0.x - z0.y, 0.0f);
+                row[0] = make_float2(z0.x + z0.y, z0.x - z0.y);
             } else {
                 const float2 a = row[k], b = row[kk];
                 // pair k
@@ -192,6 +193,8 @@ __device__ __forceinline__ void r2c_post(float2* plane, const float2* tw) {
 // Inverse of r2c_post (up to the factor 2 that makes the length-N/2 inverse
 // FFT below equal the unnormalised length-N inverse real FFT):
 //   Z[k] = (X[k] + conj X[N/2-k]) + i conj(w^k) (X[k] - conj X[N/2-k]).
+// Slot 0 holds x[0] + i x[N/2] (pack_nyquist before the y transform), both
+// real after it.
 template <int N, int NT>
 __device__ __forceinline__ void c2r_pre(float2* plane, const float2* tw) {
     using C = Canvas<N>;
@@ -204,7 +207,8 @@ __device__ __forceinline__ void c2r_pre(float2* plane, const float2* tw) {
         const float2 wk = tw[k], wkk = tw[kk];
         for (int y = t / Q; y < N; y += R) {
             float2* row = plane + y * C::P;
-            const float2 a = row[k], b = row[kk];
+            const float2 a = k == 0 ? make_float2(row[0].x, 0.0f) : row[k];
+            const float2 b = k == 0 ? make_float2(row[0].y, 0.0f) : row[kk];
             float2 s = cadd(a, cconj(b)), d = csub(a, cconj(b));
             float2 wd = cmulc(d, wk);
             float2 zk = make_float2(s.x - wd.y, s.y + wd.x);
@@ -221,13 +225,49 @@ __device__ __forceinline__ void c2r_pre(float2* plane, const float2* tw) {
     __syncthreads();
 }
 
+// After the y transform of slot 0 (holding X0 + i XN, both real along y):
+// Z[k] -> A[k] = (Z[k] + conj Z[-k]) / 2 in column 0 and B[k] = (Z[k] - conj
+// Z[-k]) / 2i in column n/2, the transforms of X0 and XN.  One thread per pair
+// (k, n - k), k in [0, n/2].
+template <int N, int NT>
+__device__ __forceinline__ void unpack_nyquist(float2* plane) {
+    using C = Canvas<N>;
+    for (int k = threadIdx.x; k <= N / 2; k += NT) {
+        const int kk = (N - k) % N;
+        const float2 z = plane[k * C::P], zz = plane[kk * C::P];
+        const float2 a = make_float2(0.5f * (z.x + zz.x), 0.5f * (z.y - zz.y));
+        const float2 b = make_float2(0.5f * (z.y + zz.y), 0.5f * (zz.x - z.x));
+        plane[k * C::P] = a;
+        plane[k * C::P + C::N2] = b;
+        if (kk != k) {
+            plane[kk * C::P] = cconj(a);
+            plane[kk * C::P + C::N2] = cconj(b);
+        }
+    }
+    __syncthreads();
+}
+
+// Before the inverse y transform: column 0 (A) and column n/2 (B) of each row
+// become A + i B in column 0; after the transform its real and imaginary parts
+// are the two real columns.
+template <int N, int NT>
+__device__ __forceinline__ void pack_nyquist(float2* plane) {
+    using C = Canvas<N>;
+    for (int k = threadIdx.x; k < N; k += NT) {
+        const float2 a = plane[k * C::P], b = plane[k * C::P + C::N2];
+        plane[k * C::P] = make_float2(a.x - b.y, a.y + b.x);
+    }
+    __syncthreads();
+}
+
 // forward 2D real FFT of the packed plane (x then y) and write to the tiled spectrum
 template <int N, int NT>
 __device__ __forceinline__ void plane_forward_and_store(float2* plane, const float2* tw, float2* __restrict__ spec_rot, int z) {
     using C = Canvas<N>;
     fft_lds<C::N2, false, N, NT, true, N>(plane, 1, C::P, tw);
     r2c_post<N, NT>(plane, tw);
-    fft_lds<N, false, C::P, NT, true, N>(plane, C::P, 1, tw);
+    fft_lds<N, false, C::N2, NT, true, N>(plane, C::P, 1, tw);
+    unpack_nyquist<N, NT>(plane);
     // LDS reads first, then the global stores
     batched_copy<N * C::N2, NT>([&](int e) { return plane[(e / C::N2) * C::P + e % C::N2]; },
                                    [&](int e, float2 v) {
@@ -719,9 +759,10 @@ __global__ __launch_bounds__(NT, WPE) void k_inv_xy_argmax(const float2* __restr
             az[o] = acc;
         }
     }
-    // az is complete before the first barrier inside the y inverse FFT and is
-    // read only after it
-    fft_lds<N, true, C::P, NT, true, N>(plane, C::P, 1, tw);
+    // az is complete before the barrier that ends pack_nyquist and is read
+    // only after it
+    pack_nyquist<N, NT>(plane);
+    fft_lds<N, true, C::N2, NT, true, N>(plane, C::P, 1, tw);
     // btab[y][kx] = sum_ky az[kx][ky] e^{+2 pi i ky y / N}, doubled for kx > 0
     // (the field sums Re b_0 + 2 sum_kx Re(b_kx e^{+2 pi i kx x / N}))
     for (int t = threadIdx.x; t < N * NLX; t += NT) {
