@@ -325,9 +325,16 @@ __device__ __forceinline__ void plane_low_dft(const float2* plane, const double2
     static_assert(N <= NT, "one row task set per pass");
     constexpr int CH = pow2floor(NT / N);  // lanes per row, a power of two
     constexpr int JC = (C::N2 + CH - 1) / CH;
+    // A wave takes RPW consecutive rows: lane l reads row l % RPW, chunk
+    // l / RPW.  The lanes that read together (a half wave) then take distinct
+    // rows, whose offsets 2 P y fall in distinct banks, rather than the chunks
+    // of one row, which at n = 128 start 16 elements (32 banks of 4 bytes)
+    // apart and hit the same banks.
+    constexpr int RPW = 64 / CH;
+    static_assert(CH <= 64 && ((N + RPW - 1) / RPW) * 64 <= NT, "low-block x pass layout");
     const int t = threadIdx.x;
-    if (t < N * CH) {
-        const int y = t / CH, c = t % CH;
+    const int y = (t >> 6) * RPW + (t & 63) % RPW, c = (t & 63) / RPW;
+    if (y < N) {
         const int j0 = c * JC, j1 = min(C::N2, j0 + JC);
         double coef[NLX], s1[NLX], s2[NLX];
         double sum0 = 0.0;
@@ -360,8 +367,9 @@ __device__ __forceinline__ void plane_low_dft(const float2* plane, const double2
             acc[k] = dcmul(yk, tw64[(k * xl) % N]);
             if (j1 <= j0) acc[k] = make_double2(0.0, 0.0);
         }
+        // the CH chunks of a row sit RPW lanes apart
 #pragma unroll
-        for (int off = CH / 2; off >= 1; off >>= 1)
+        for (int off = 32; off >= RPW; off >>= 1)
 #pragma unroll
             for (int k = 0; k < NLX; ++k) {
                 acc[k].x += __shfl_xor(acc[k].x, off, 64);
