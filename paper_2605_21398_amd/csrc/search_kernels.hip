@@ -870,30 +870,44 @@ __global__ __launch_bounds__(NT, WPE) void k_inv_xy_argmax(const float2* __restr
         wsec[wave] = sec;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long b0 = 0, b1 = 0, b2 = 0, b3 = 0, b4 = 0;
-        double tot = 0.0, bound = -INFINITY;
-        for (int w = 0; w < NW; ++w) {
-            for (int r = 0; r < KTOP + 1; ++r) {
-                // insertion into the descending five b0..b4
-                unsigned long long k = wtop[w][r], x;
-                x = b0 > k ? b0 : k; k = b0 > k ? k : b0; b0 = x;
-                x = b1 > k ? b1 : k; k = b1 > k ? k : b1; b1 = x;
-                x = b2 > k ? b2 : k; k = b2 > k ? k : b2; b2 = x;
-                x = b3 > k ? b3 : k; k = b3 > k ? k : b3; b3 = x;
-                b4 = b4 > k ? b4 : k;
+    if (threadIdx.x < 64) {
+        // the plane, in wave 0: five rounds of a maximum over the waves' sorted
+        // lists (lane w < NW holds wave w's list and pops its head when it
+        // wins), then the sums of squares and the bounds of the waves
+        static_assert(NW <= 64, "one lane per wave of the workgroup");
+        constexpr int SPAN = pow2floor(2 * NW - 1);  // lanes holding lists, rounded up to a power of two
+        const int l = threadIdx.x;
+        unsigned long long L[KTOP + 1], b[KTOP + 1];
+#pragma unroll
+        for (int r = 0; r < KTOP + 1; ++r) L[r] = l < NW ? wtop[l][r] : 0ull;
+#pragma unroll
+        for (int r = 0; r < KTOP + 1; ++r) {
+            unsigned long long mx = L[0];
+#pragma unroll
+            for (int off = SPAN / 2; off >= 1; off >>= 1) {
+                const unsigned long long o = __shfl_xor(mx, off, 64);
+                mx = o > mx ? o : mx;
             }
-            tot += wss[w];
-            bound = fmax(bound, wsec[w]);
+            const bool mine = L[0] == mx && mx != 0ull;
+#pragma unroll
+            for (int q = 0; q < KTOP; ++q) L[q] = mine ? L[q + 1] : L[q];
+            L[KTOP] = mine ? 0ull : L[KTOP];
+            b[r] = mx;
         }
-        if (b4) bound = fmax(bound, key_value(b4));
-        unsigned long long* o = ptop + ((size_t)rot * N + z) * KREC;
-        o[0] = b0;
-        o[1] = b1;
-        o[2] = b2;
-        o[3] = b3;
-        o[KTOP] = (unsigned long long)__double_as_longlong(bound);
-        pssq[(size_t)rot * N + z] = tot;
+        double tot = l < NW ? wss[l] : 0.0, bound = l < NW ? wsec[l] : -INFINITY;
+#pragma unroll
+        for (int off = SPAN / 2; off >= 1; off >>= 1) {
+            tot += __shfl_xor(tot, off, 64);
+            bound = fmax(bound, __shfl_xor(bound, off, 64));
+        }
+        if (l == 0) {
+            if (b[KTOP]) bound = fmax(bound, key_value(b[KTOP]));
+            unsigned long long* o = ptop + ((size_t)rot * N + z) * KREC;
+#pragma unroll
+            for (int r = 0; r < KTOP; ++r) o[r] = b[r];
+            o[KTOP] = (unsigned long long)__double_as_longlong(bound);
+            pssq[(size_t)rot * N + z] = tot;
+        }
     }
 }
 
