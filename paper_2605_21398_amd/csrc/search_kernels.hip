@@ -149,6 +149,30 @@ __device__ __forceinline__ void batched_copy(Src src, Dst dst) {
     }
 }
 
+// The same copy split in two: load() issues the global loads into registers
+// and store() writes them to LDS later, so other loads can go out in between.
+template <int COUNT, int NTH>
+struct RegStage {
+    static constexpr int PER = (COUNT + NTH - 1) / NTH;
+    float2 v[PER];
+    template <class Src>
+    __device__ __forceinline__ void load(Src src) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = threadIdx.x + i * NTH;
+            if (COUNT % NTH == 0 || e < COUNT) v[i] = src(e);
+        }
+    }
+    template <class Dst>
+    __device__ __forceinline__ void store(Dst dst) const {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = threadIdx.x + i * NTH;
+            if (COUNT % NTH == 0 || e < COUNT) dst(e, v[i]);
+        }
+    }
+};
+
 // ------------------------------------------------------------- plane FFTs
 // The plane lives in LDS as [y][kx] with pitch P = N/2 + 1 complex.
 
@@ -595,16 +619,26 @@ __global__ __launch_bounds__(NT, WPE) void k_rotvox_fwd_xy(const uint8_t* __rest
     __shared__ uint32_t bax[C::M], bay[C::M], baz[C::M];
     double2* rbuf = reinterpret_cast<double2*>(scratch_lds);
     float4* lut = reinterpret_cast<float4*>(scratch_lds);
+    static_assert(N <= NT, "one twiddle per thread at most");
     int rot, z;
     map_plane_block(blockIdx.x, count, N, rot, z);
-    for (int i = threadIdx.x; i < N; i += NT) {
-        tw[i] = twg[i];
-        tws[i] = tw64[i];
+    // the global loads (twiddles, rotation) go out first; the tables are built
+    // while they are in flight
+    const int tid = threadIdx.x;
+    float2 twv;
+    double2 tw64v;
+    if (tid < N) {
+        twv = twg[tid];
+        tw64v = tw64[tid];
     }
-    build_trilinear_lut<NT>(lut);
-    build_brick_tables<NT>(bax, bay, baz, C::M, mb);
     RotSampler rs;
     rs.load(rots + rot * 9, m, N);
+    build_trilinear_lut<NT>(lut);
+    build_brick_tables<NT>(bax, bay, baz, C::M, mb);
+    if (tid < N) {
+        tw[tid] = twv;
+        tws[tid] = tw64v;
+    }
     __syncthreads();
     generate_plane<N, NT>(plane, lut, bax, bay, baz, rs, cmask, z);
     __syncthreads();
@@ -662,9 +696,14 @@ __global__ __launch_bounds__(ZT) void k_zpass(float2* __restrict__ spec, const f
         rot = blockIdx.x / C::TILES;
     }
     float2* src = spec + (size_t)rot * C::H + (size_t)tile * E;
-    for (int i = threadIdx.x; i < N; i += ZT) tw[i] = twg[i];
-    batched_copy<E, ZT>([&](int i) { return src[i]; }, [&](int i, float2 v) { buf[i] = v; });
-    // the tile of W is loaded into registers while the forward FFT runs
+    // the twiddles and the tile go out together; the tile of W is loaded into
+    // registers after them and arrives while the forward FFT runs
+    RegStage<N, ZT> st_tw;
+    RegStage<E, ZT> st_tile;
+    st_tw.load([&](int i) { return twg[i]; });
+    st_tile.load([&](int i) { return src[i]; });
+    st_tw.store([&](int i, float2 v) { tw[i] = v; });
+    st_tile.store([&](int i, float2 v) { buf[i] = v; });
     float2 wv[PER];
     if (MODE == 0) {
         const float2* w = W + (size_t)tile * E;
@@ -736,36 +775,50 @@ __global__ __launch_bounds__(NT, WPE) void k_inv_xy_argmax(const float2* __restr
     __shared__ unsigned long long wtop[NW][KTOP + 1];
     __shared__ double wss[NW];
     __shared__ double wsec[NW];
+    static_assert(N <= NT && NLOW2 <= NT, "one twiddle and one low-block row per thread at most");
     int rot, z;
     map_plane_block(blockIdx.x, count, N, rot, z);
-    for (int i = threadIdx.x; i < N; i += NT) {
-        tw[i] = twg[i];
-        tws[i] = tw64[i];
+    // every global load of the plane is issued before the first is waited for:
+    // the twiddles, this thread's row of the low-block product, the spectrum
+    const int tid = threadIdx.x;
+    float2 twv;
+    double2 tw64v;
+    if (tid < N) {
+        twv = twg[tid];
+        tw64v = tw64[tid];
+    }
+    double2 pz[NLY];
+    if (tid < NLOW2) {
+        const double2* P = Plow + (size_t)rot * NLOW3 + tid * NLY;
+#pragma unroll
+        for (int kzi = 0; kzi < NLY; ++kzi) pz[kzi] = P[kzi];
     }
     const float2* spec_rot = spec + (size_t)rot * C::H;
-    batched_copy<N * C::N2, NT>(
-        [&](int e) {
-            const int ky = e / C::N2, kx = e % C::N2;
-            return spec_rot[((size_t)(ky * C::NT2 + kx / C::T) * N + z) * C::T + (kx % C::T)];
-        },
-        [&](int e, float2 v) { plane[(e / C::N2) * C::P + e % C::N2] = v; });
+    RegStage<N * C::N2, NT> st_main;
+    RegStage<N, NT> st_nyq;
+    st_main.load([&](int e) {
+        const int ky = e / C::N2, kx = e % C::N2;
+        return spec_rot[((size_t)(ky * C::NT2 + kx / C::T) * N + z) * C::T + (kx % C::T)];
+    });
     const float2* nyq = spec_rot + (size_t)N * C::N2 * N;
-    batched_copy<N, NT>([&](int ky) { return nyq[((size_t)(ky / C::T) * N + z) * C::T + (ky % C::T)]; },
-                           [&](int ky, float2 v) { plane[ky * C::P + C::N2] = v; });
+    st_nyq.load([&](int ky) { return nyq[((size_t)(ky / C::T) * N + z) * C::T + (ky % C::T)]; });
+    if (tid < N) {
+        tw[tid] = twv;
+        tws[tid] = tw64v;
+    }
+    st_main.store([&](int e, float2 v) { plane[(e / C::N2) * C::P + e % C::N2] = v; });
+    st_nyq.store([&](int ky, float2 v) { plane[ky * C::P + C::N2] = v; });
     __syncthreads();
     // low block of this plane: az[kx][ky] = sum_kz P[kx][ky][kz] e^{+2 pi i kz z / N}
-    {
-        const double2* P = Plow + (size_t)rot * NLOW3;
-        for (int o = threadIdx.x; o < NLOW2; o += NT) {
-            double2 acc = make_double2(0.0, 0.0);
+    if (tid < NLOW2) {
+        double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
-            for (int kzi = 0; kzi < NLY; ++kzi) {
-                const double2 t = dcmulc(P[o * NLY + kzi], tws[mod_n((kzi - KLOW) * z, N)]);
-                acc.x += t.x;
-                acc.y += t.y;
-            }
-            az[o] = acc;
+        for (int kzi = 0; kzi < NLY; ++kzi) {
+            const double2 t = dcmulc(pz[kzi], tws[mod_n((kzi - KLOW) * z, N)]);
+            acc.x += t.x;
+            acc.y += t.y;
         }
+        az[tid] = acc;
     }
     // az is complete before the barrier that ends pack_nyquist and is read
     // only after it
@@ -1089,47 +1142,46 @@ __global__ __launch_bounds__(256) void k_rescore(const uint32_t* __restrict__ nz
     }
 }
 
-// Finish the low block along z: L[kx][ky][kz] = sum_z lowT[z][kx][ky] e^{-2 pi i kz z / n}.
-// One workgroup per (rotation, kx, ky): lane z multiplies its plane's value by
-// the NLY phases, then a fixed-order tree sums over z.
+// Finish the low block along z: L[kx][ky][kz] = sum_z lowT[z][kx][ky] e^{-2 pi i kz z / n},
+// summed in a fixed order (independent of scheduling).
 // MODE 0 (per rotation): out = L * Wlow.  MODE 1 (object): out = conj(L) * scale.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_low_combine(const double2* __restrict__ lowT, int n, const double2* __restrict__ tw64,
                                                      const double2* __restrict__ Wlow, double scale, double2* __restrict__ out) {
-    __shared__ double2 red[4][NLY];
-    const int rot = blockIdx.x / NLOW2, kxy = blockIdx.x % NLOW2;
-    const double2* T = lowT + (size_t)rot * n * NLOW2 + kxy;
-    double2 acc[NLY];
+    // One block per rotation.  Lane l < NLOW2 of each half wave owns the
+    // (kx, ky) pair l; the 8 half waves take the planes z = h, h + 8, ... (the
+    // 28 pairs of a plane are contiguous, so each half wave reads them in one
+    // coalesced load), then the 8 partial sums are added per output.
+    constexpr int HW = 256 / 32;
+    static_assert(NLOW2 <= 32, "one (kx, ky) pair per lane of a half wave");
+    __shared__ double2 red[HW][NLOW2][NLY];
+    const int rot = blockIdx.x, h = threadIdx.x >> 5, l = threadIdx.x & 31;
+    if (l < NLOW2) {
+        const double2* T = lowT + (size_t)rot * n * NLOW2 + l;
+        double2 acc[NLY];
 #pragma unroll
-    for (int k = 0; k < NLY; ++k) acc[k] = make_double2(0.0, 0.0);
-    for (int zz = threadIdx.x; zz < n; zz += 256) {
-        const double2 v = T[(size_t)zz * NLOW2];
+        for (int k = 0; k < NLY; ++k) acc[k] = make_double2(0.0, 0.0);
+        for (int zz = h; zz < n; zz += HW) {
+            const double2 v = T[(size_t)zz * NLOW2];
 #pragma unroll
-        for (int k = 0; k < NLY; ++k) {
-            const double2 t = dcmul(v, tw64[mod_n((k - KLOW) * zz, n)]);
-            acc[k].x += t.x;
-            acc[k].y += t.y;
+            for (int k = 0; k < NLY; ++k) {
+                const double2 t = dcmul(v, tw64[mod_n((k - KLOW) * zz, n)]);
+                acc[k].x += t.x;
+                acc[k].y += t.y;
+            }
         }
+#pragma unroll
+        for (int k = 0; k < NLY; ++k) red[h][l][k] = acc[k];
     }
-#pragma unroll
-    for (int k = 0; k < NLY; ++k)
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            acc[k].x += __shfl_xor(acc[k].x, off, 64);
-            acc[k].y += __shfl_xor(acc[k].y, off, 64);
-        }
-    if ((threadIdx.x & 63) == 0)
-#pragma unroll
-        for (int k = 0; k < NLY; ++k) red[threadIdx.x >> 6][k] = acc[k];
     __syncthreads();
-    if (threadIdx.x < NLY) {
-        const int k = threadIdx.x;
-        double2 L = red[0][k];
-        for (int w = 1; w < 4; ++w) {
-            L.x += red[w][k].x;
-            L.y += red[w][k].y;
+    for (int o = threadIdx.x; o < NLOW3; o += 256) {
+        const int kxy = o / NLY, k = o % NLY;
+        double2 L = red[0][kxy][k];
+#pragma unroll
+        for (int w = 1; w < HW; ++w) {
+            L.x += red[w][kxy][k].x;
+            L.y += red[w][kxy][k].y;
         }
-        const int o = kxy * NLY + k;
         out[(size_t)rot * NLOW3 + o] = MODE == 0 ? dcmul(L, Wlow[o]) : make_double2(L.x * scale, -L.y * scale);
     }
 }
@@ -1636,7 +1688,7 @@ static hipError_t launch_search_pass(int pass, const SearchBatchArgs& a) {
     if (a.m != Canvas<N>::M || a.mp < a.m || a.mp % 4) return hipErrorInvalidValue;
     if (pass == 1) {
         if (!z_variant_valid<N>(a.zv)) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_low_combine<0>), dim3(a.count * NLOW2), dim3(256), 0, a.stream, a.lowT, N, a.tw64, a.Wlow, 1.0,
+        hipLaunchKernelGGL((k_low_combine<0>), dim3(a.count), dim3(256), 0, a.stream, a.lowT, N, a.tw64, a.Wlow, 1.0,
                            a.Plow);
         switch (a.zv) {
             case 0: launch_z<N, 0>(a); break;
@@ -1663,7 +1715,7 @@ static hipError_t launch_object_spectrum(const float* O, float2* spec_tmp, float
     const double scale = 1.0 / ((double)N * N * N);
     hipLaunchKernelGGL(k_grid_fwd_xy<N>, dim3(N), dim3(C::NT), 0, s, O, tw, tw64, spec_tmp, lowT_tmp);
     hipLaunchKernelGGL((k_zpass<N, 1, 256>), dim3(C::TILES), dim3(256), 0, s, spec_tmp, nullptr, W, tw, (float)scale);
-    hipLaunchKernelGGL((k_low_combine<1>), dim3(NLOW2), dim3(256), 0, s, lowT_tmp, N, tw64, nullptr, scale, Wlow);
+    hipLaunchKernelGGL((k_low_combine<1>), dim3(1), dim3(256), 0, s, lowT_tmp, N, tw64, nullptr, scale, Wlow);
     return hipGetLastError();
 }
 
