@@ -977,20 +977,31 @@ __global__ __launch_bounds__(256) void k_select(const unsigned long long* __rest
                                                 uint8_t* __restrict__ ovf, double* __restrict__ best_val,
                                                 int32_t* __restrict__ best_flat, int* __restrict__ stats) {
     __shared__ unsigned long long red[4];
+    __shared__ double red_ss[4];
     __shared__ double thr_s;
     __shared__ int cnt;
     __shared__ unsigned long long list[CMAX];
     __shared__ int overflow;
     const int rot = blockIdx.x, r = base + blockIdx.x;
     const unsigned long long* T = ptop + (size_t)rot * n * KREC;
+    // the best key and the sum of the planes' sums of squares (a fixed
+    // shuffle tree per wave, then the four waves in order)
     unsigned long long mx = 0;
-    for (int zz = threadIdx.x; zz < n; zz += 256) mx = T[zz * KREC] > mx ? T[zz * KREC] : mx;
+    double ss = 0.0;
+    for (int zz = threadIdx.x; zz < n; zz += 256) {
+        mx = T[zz * KREC] > mx ? T[zz * KREC] : mx;
+        ss += pssq[(size_t)rot * n + zz];
+    }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         const unsigned long long o = __shfl_xor(mx, off, 64);
         mx = o > mx ? o : mx;
+        ss += __shfl_xor(ss, off, 64);
     }
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = mx;
+        red_ss[threadIdx.x >> 6] = ss;
+    }
     if (threadIdx.x == 0) {
         cnt = 0;
         overflow = 0;
@@ -998,9 +1009,11 @@ __global__ __launch_bounds__(256) void k_select(const unsigned long long* __rest
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long b = red[0];
-        for (int w = 1; w < 4; ++w) b = red[w] > b ? red[w] : b;
-        double ssq = 0.0;
-        for (int zz = 0; zz < n; ++zz) ssq += pssq[(size_t)rot * n + zz];
+        double ssq = red_ss[0];
+        for (int w = 1; w < 4; ++w) {
+            b = red[w] > b ? red[w] : b;
+            ssq += red_ss[w];
+        }
         const double rms = sqrt(ssq / ((double)n * n * n));
         const double v = key_value(b);
         thr_s = v - 2.0 * eps_per_rms * rms;
@@ -1145,27 +1158,43 @@ __global__ __launch_bounds__(256) void k_rescore(const uint32_t* __restrict__ nz
 // Finish the low block along z: L[kx][ky][kz] = sum_z lowT[z][kx][ky] e^{-2 pi i kz z / n},
 // summed in a fixed order (independent of scheduling).
 // MODE 0 (per rotation): out = L * Wlow.  MODE 1 (object): out = conj(L) * scale.
-template <int MODE>
-__global__ __launch_bounds__(256) void k_low_combine(const double2* __restrict__ lowT, int n, const double2* __restrict__ tw64,
+template <int MODE, int N>
+__global__ __launch_bounds__(256) void k_low_combine(const double2* __restrict__ lowT, const double2* __restrict__ tw64,
                                                      const double2* __restrict__ Wlow, double scale, double2* __restrict__ out) {
     // One block per rotation.  Lane l < NLOW2 of each half wave owns the
     // (kx, ky) pair l; the 8 half waves take the planes z = h, h + 8, ... (the
     // 28 pairs of a plane are contiguous, so each half wave reads them in one
-    // coalesced load), then the 8 partial sums are added per output.
+    // coalesced load), then the 8 partial sums are added per output.  All
+    // loads of a lane are issued before the first is used, and the twiddles
+    // are read from LDS.
     constexpr int HW = 256 / 32;
-    static_assert(NLOW2 <= 32, "one (kx, ky) pair per lane of a half wave");
+    constexpr int ZI = (N + HW - 1) / HW;  // planes per half wave
+    static_assert(NLOW2 <= 32 && N <= 256, "one (kx, ky) pair per lane of a half wave; one twiddle per thread");
     __shared__ double2 red[HW][NLOW2][NLY];
+    __shared__ double2 tws[N];
     const int rot = blockIdx.x, h = threadIdx.x >> 5, l = threadIdx.x & 31;
+    double2 v[ZI];
     if (l < NLOW2) {
-        const double2* T = lowT + (size_t)rot * n * NLOW2 + l;
+        const double2* T = lowT + (size_t)rot * N * NLOW2 + l;
+#pragma unroll
+        for (int i = 0; i < ZI; ++i) {
+            const int zz = h + i * HW;
+            v[i] = (N % HW == 0 || zz < N) ? T[(size_t)zz * NLOW2] : make_double2(0.0, 0.0);
+        }
+    }
+    if (threadIdx.x < N) tws[threadIdx.x] = tw64[threadIdx.x];
+    __syncthreads();
+    if (l < NLOW2) {
         double2 acc[NLY];
 #pragma unroll
         for (int k = 0; k < NLY; ++k) acc[k] = make_double2(0.0, 0.0);
-        for (int zz = h; zz < n; zz += HW) {
-            const double2 v = T[(size_t)zz * NLOW2];
+#pragma unroll
+        for (int i = 0; i < ZI; ++i) {
+            const int zz = h + i * HW;
+            if (N % HW != 0 && zz >= N) break;
 #pragma unroll
             for (int k = 0; k < NLY; ++k) {
-                const double2 t = dcmul(v, tw64[mod_n((k - KLOW) * zz, n)]);
+                const double2 t = dcmul(v[i], tws[mod_n((k - KLOW) * zz, N)]);
                 acc[k].x += t.x;
                 acc[k].y += t.y;
             }
@@ -1688,7 +1717,7 @@ static hipError_t launch_search_pass(int pass, const SearchBatchArgs& a) {
     if (a.m != Canvas<N>::M || a.mp < a.m || a.mp % 4) return hipErrorInvalidValue;
     if (pass == 1) {
         if (!z_variant_valid<N>(a.zv)) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_low_combine<0>), dim3(a.count), dim3(256), 0, a.stream, a.lowT, N, a.tw64, a.Wlow, 1.0,
+        hipLaunchKernelGGL((k_low_combine<0, N>), dim3(a.count), dim3(256), 0, a.stream, a.lowT, a.tw64, a.Wlow, 1.0,
                            a.Plow);
         switch (a.zv) {
             case 0: launch_z<N, 0>(a); break;
@@ -1715,7 +1744,7 @@ static hipError_t launch_object_spectrum(const float* O, float2* spec_tmp, float
     const double scale = 1.0 / ((double)N * N * N);
     hipLaunchKernelGGL(k_grid_fwd_xy<N>, dim3(N), dim3(C::NT), 0, s, O, tw, tw64, spec_tmp, lowT_tmp);
     hipLaunchKernelGGL((k_zpass<N, 1, 256>), dim3(C::TILES), dim3(256), 0, s, spec_tmp, nullptr, W, tw, (float)scale);
-    hipLaunchKernelGGL((k_low_combine<1>), dim3(1), dim3(256), 0, s, lowT_tmp, N, tw64, nullptr, scale, Wlow);
+    hipLaunchKernelGGL((k_low_combine<1, N>), dim3(1), dim3(256), 0, s, lowT_tmp, tw64, nullptr, scale, Wlow);
     return hipGetLastError();
 }
 
