@@ -773,19 +773,24 @@ __global__ void k_ref_start(const double* __restrict__ init, int K, const double
 
 // ------------------------------------------------- distance query (Sec. V-B)
 //
-// Three passes per round:
-//   k_ref_cull     one thread per (start, probe pose): the body -> probe frame,
-//                  the bounding-sphere tests down to the faces, and per kept
-//                  face the bounds ub (best vertex value) and lb (supporting
-//                  planes of the convex f_p at the vertices).  Faces with lb
-//                  above the best ub cannot hold the minimum; faces whose bounds
-//                  meet are settled at their best vertex; the rest go to a pair
-//                  list for a golden-section search.
-//   k_ref_pairs    one thread per (query, face) pair: the face minimum, folded
-//                  into the query's key (value, face index) by atomicMin, so
-//                  the order of the pairs does not matter.
-//   k_ref_resolve  one thread per query: the winning face's witness, the
-//                  normal and the world coordinates.
+// Per round, for every (start, trial, probe pose) query:
+//   k_ref_cull     one wavefront per query: the body -> probe frame, the
+//                  bounding-sphere tests down to the faces, one level of the
+//                  hierarchy at a time, and per kept face the bounds ub (best
+//                  vertex value) and lb (supporting planes of the convex f_p).
+//                  Faces with lb above the best ub cannot hold the minimum;
+//                  faces whose bounds meet are settled at their best vertex;
+//                  the rest go to a pair list.
+//   k_ref_pairs    one thread per (query, face) pair: the face minimum by edge
+//                  searches, the support point and a lower-bound certificate,
+//                  folded into the query's key (value, face index) by
+//                  atomicMin, so the order of the pairs does not matter; pairs
+//                  the certificate cannot settle are handed on.
+//   k_ref_nested   one wavefront per handed-on pair: a parallel nested search.
+//   k_ref_winner   the winning pair's witness to its query.
+//   k_ref_resolve  one thread per query: the winning face placed by the FP64
+//                  pose, the witness polished in FP64, the normal and the
+//                  world coordinates.
 
 // orderable 64-bit key: float value bits (monotone), then the face index
 __device__ unsigned long long face_key(float v, int idx) {
