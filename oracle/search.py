@@ -13,6 +13,8 @@ Readings of the paper taken here (each listed in the design notes):
     (linear_edge), where no shift wraps (linear_correlate is its definition);
   * the swept grid is the one rotated: S_w is built once on a world lattice and
     trilinearly resampled per rotation, while O and its spectrum stay fixed;
+    the paper's own variant, where O rotates and S stays on a world canvas,
+    is at the end of this module;
   * anchor a = mean of the mesh vertices; canvas x_k = a + h (k - n/2);
   * ties: lowest flat index (kz*n + ky)*n + kx inside a rotation, lowest
     rotation index across rotations.
@@ -359,3 +361,106 @@ def top_k(scores, K: int):
     s = np.asarray(scores, dtype=np.float64)
     order = np.lexsort((np.arange(len(s)), -s))
     return order[:K]
+
+
+# ------------------------------- the paper's own variant: the object rotates
+#
+# Sec. IV-D as printed rotates the object grid O into each sampled orientation
+# and resamples it trilinearly onto the common canvas, which holds the swept
+# occupancy S unrotated; the correlation of Eq. (xcorr) then runs between the
+# rotated O and the fixed S.  Here the canvas is z_k = wc + h (k - n/2) in the
+# world frame, O_w is the object grid of Sec. IV-A on the body lattice
+# a + h (j - m/2), and the rotated object has its anchor at the canvas centre.
+
+def object_lattice(vertices, faces, touchable, m: int, h: float, prm: GridParams = GridParams()):
+    """O_w[j] = O(a + h (j - m/2)) on the m^3 body lattice about the anchor,
+    with f_o and d (shape (m,m,m), index [jz,jy,jx]): the object grid of
+    Sec. IV-A on an edge-m lattice."""
+    return object_grid(vertices, faces, touchable, m, h, prm)
+
+
+def swept_canvas(S_w, n: int) -> np.ndarray:
+    """S[k] = S_w at wc + h (k - n/2): the central n^3 block of the world
+    lattice (its points coincide with the canvas points; m - n is even)."""
+    m = S_w.shape[0]
+    o = (m - n) // 2
+    return np.asarray(S_w, dtype=np.float64)[o:o + n, o:o + n, o:o + n].copy()
+
+
+def resample_object(O_w, q, n: int, h: float):
+    """O_q[k] = O_w at the body point a + R^T h (k - n/2), trilinear on the
+    body lattice, taps outside the lattice count as 0: the object rotated by
+    R = R(q) about its anchor, the anchor at the canvas centre (Sec. IV-D).
+    O_w may be a list of lattices of one edge m; each is resampled with the
+    same weights and a list is returned."""
+    grids = list(O_w) if isinstance(O_w, (list, tuple)) else [O_w]
+    m = grids[0].shape[0]
+    R = quat_to_mat(q)
+    k = np.arange(n, dtype=np.float64) - n / 2
+    kz, ky, kx = np.meshgrid(k, k, k, indexing="ij")
+    X = h * np.stack([kx, ky, kz], axis=-1).reshape(-1, 3)         # z_k - wc
+    U = (X @ R) / h + m / 2                                        # R^T (z_k - wc) / h + m/2, as rows
+    I = np.floor(U).astype(np.int64)
+    Fr = U - I
+    outs = [np.zeros(len(U)) for _ in grids]
+    for cz in (0, 1):
+        for cy in (0, 1):
+            for cx in (0, 1):
+                ix, iy, iz = I[:, 0] + cx, I[:, 1] + cy, I[:, 2] + cz
+                w = ((Fr[:, 0] if cx else 1 - Fr[:, 0]) * (Fr[:, 1] if cy else 1 - Fr[:, 1])
+                     * (Fr[:, 2] if cz else 1 - Fr[:, 2]))
+                ok = (ix >= 0) & (ix < m) & (iy >= 0) & (iy < m) & (iz >= 0) & (iz < m)
+                for G, out in zip(grids, outs):
+                    val = np.zeros(len(U))
+                    val[ok] = G[iz[ok], iy[ok], ix[ok]]
+                    out += w * val
+    outs = [o.reshape(n, n, n) for o in outs]
+    return outs if isinstance(O_w, (list, tuple)) else outs[0]
+
+
+def score_rotation_object(S_c, O_w, q, n: int, h: float):
+    """One rotation of the variant: (score, lowest flat index e among the
+    maxima, signed e) of C'[e] = sum_j S[j] O_q[j + e] = F^{-1}(conj(F(S)) F(O_q)).
+    The paper's C[dk] = sum_k O_q[k] S[k + dk] equals C'[-dk]: the shift of
+    Eq. (xcorr) is dk = -e."""
+    return peak(correlate(S_c, resample_object(O_w, q, n, h)))
+
+
+def score_rotations_object(S_c, O_w, so3, n: int, h: float, indices=None):
+    """Scores, flat indices e and signed e of the variant for the selected rotations."""
+    idx = range(len(so3)) if indices is None else indices
+    sc, fl, sh = [], [], []
+    for r in idx:
+        s, f, d = score_rotation_object(S_c, O_w, so3[r], n, h)
+        sc.append(s)
+        fl.append(f)
+        sh.append(d)
+    return np.array(sc), np.array(fl, dtype=np.int64), np.array(sh, dtype=np.int64).reshape(-1, 3)
+
+
+def pose_from_object_shift(q, e, a, wc, h: float):
+    """Object pose x -> R x + t of a peak at e: R = R(q), t = wc - R a + h dk
+    with dk = -e.  The rotated object sits at x -> R (x - a) + wc on the
+    canvas, and the shift dk of Eq. (xcorr) moves it by h dk (Sec. IV-B:
+    t = h dk + o_s - o_o)."""
+    R = quat_to_mat(q)
+    t = np.asarray(wc, float) - R @ np.asarray(a, float) - h * np.asarray(e, float)
+    return R, t
+
+
+def score_bounds_object(S_c, F_c, O_w, dO_w, q, n: int, h: float):
+    """The variant's field C' = corr(S, O_q) of one rotation and a bound
+    B >= |C'' - C'| for every field C'' obtained by moving flagged voxels to
+    their other value: S' differs from S only where F (the canvas block of
+    the swept flags) is 1, and |O_q' - O_q| <= D_q = resample(|dO_w|)
+    (resampling is linear with non-negative weights), so
+        C'' - C' = corr(S' - S, O_q') + corr(S, O_q' - O_q)
+        |C'' - C'| <= corr(F, |O_q| + D_q) + corr(S, D_q) = B."""
+    O_q, D_q = resample_object([O_w, dO_w], q, n, h)
+    C = correlate(S_c, O_q)
+    B = np.zeros_like(C)
+    if np.any(F_c):
+        B += correlate(F_c, np.abs(O_q) + D_q)
+    if np.any(D_q):
+        B += correlate(S_c, D_q)
+    return C, np.maximum(B, 0.0)
