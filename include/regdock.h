@@ -92,7 +92,15 @@ typedef struct {
  * passes, k selecting variant k - 1 of (threads, waves per SIMD) = (256, 1),
  * (256, 2), (512, 4), (1024, 4) (edges up to 80 take the first three, edges
  * up to 128 the last three, larger edges the last); z_variant = threads of the z-pencil workgroup, k
- * selecting 128, 256 or 512. */
+ * selecting 128, 256 or 512.
+ * rotate_object = 1 selects the paper's own search variant (Sec. IV-D as
+ * printed): for each sample the object grid O is rotated about the anchor a
+ * and resampled trilinearly onto the canvas z_k = center_world + h (k - n/2),
+ * from O on the body lattice a + h (j - m/2), and correlated with the swept
+ * occupancy S on that canvas, which stays fixed.  0 (the default) rotates S
+ * instead, against the fixed object canvas.  The variant keeps an m^3
+ * lattice of cell classes and 32-byte corner records per cell (360 MB at
+ * n = 128, 1 GB at 180); pass 1 then runs with the default workgroup. */
 typedef struct {
     double tau_out1, tau_in1, rho;
     double tau_out2, tau_in2, k, lambda;
@@ -103,6 +111,7 @@ typedef struct {
     int32_t lanes;
     int32_t plane_variant;
     int32_t z_variant;
+    int32_t rotate_object;
 } reg_params;
 
 /* Build a registration problem (Sec. IV-A): the object grid O and its spectrum
@@ -148,6 +157,10 @@ int register_linear_edge(const float* vertices, int32_t n_vertices, const reg_pr
  *   out_pose: count x 7 double (unit quaternion, t) or NULL, with
  *   t = center_world - R a + h R shift, so that x -> R x + t maps the object
  *   body frame to world.  Asynchronous on the handle's stream.
+ * With params.rotate_object: O_q[k] = trilinear O at a + R^T (z_k - center_world);
+ * the field is C'[e] = sum_k S[k] O_q[k + e] (circular), whose lowest-index
+ * maximum e* gives the shift of Eq. (xcorr), shift = -e* (components of e*
+ * >= n/2 reduced by n first), and t = center_world - R a + h shift.
  * Errors: REG_EINVAL (range or null out_score), REG_EDEVICE. */
 int score_rotations(reg_handle* h, int32_t first, int32_t count, float* out_score, int32_t* out_shift,
                     double* out_pose);
@@ -263,13 +276,15 @@ int register_debug_object_grid(reg_handle* h, float* out_O, float* out_fo);
 /* Copy the swept occupancy S_w (m^3 uint8, 0/1) to a device buffer. */
 int register_debug_swept(reg_handle* h, uint8_t* out_Sw);
 
-/* Full correlation C (n^3 float) of SO(3) sample `rot` into a device buffer. */
+/* Full correlation C (n^3 float) of SO(3) sample `rot` into a device buffer
+ * (C' of the rotated-object search, indexed by e). */
 int register_debug_correlation(reg_handle* h, int32_t rot, float* out_C);
 
 /* Replace O (n^3 float, device) and/or S_w (m^3 uint8 0/1, device) of a
  * handle by given grids (NULL keeps the current one); the spectrum and the
  * corner masks are rebuilt.  Isolates the per-rotation path from threshold
- * decisions taken while building the grids. */
+ * decisions taken while building the grids.  REG_ENOTSUP on a handle of the
+ * rotated-object search (params.rotate_object). */
 int register_set_grids(reg_handle* h, const float* O, const uint8_t* Sw);
 
 /* Continuous SE(3) refinement of K initial object poses (Sec. V).  Each start

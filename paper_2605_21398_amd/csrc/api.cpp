@@ -251,6 +251,14 @@ struct reg_handle {
     int* nz_boff = nullptr;
     uint8_t* Sw = nullptr;
     uint8_t* cm = nullptr;
+    // rotated-object search (params.rotate_object): cell classes and corner
+    // records of O on the body lattice, and the fixed swept canvas S, whose
+    // spectrum and nonzero list replace O's (W, Wlow, nz_* then point to
+    // buffers of the handle)
+    bool rotobj = false;
+    uint8_t* ocls = nullptr;
+    float4* orec = nullptr;
+    float* Sc = nullptr;
     float2* tw = nullptr;
     double2* tw64 = nullptr;
     double2* lowT = nullptr;
@@ -418,6 +426,46 @@ static int resolve_schedule(int n, const reg_params& p, Schedule& s) {
 }
 
 // spectrum conj(F(O))/n^3 and the nonzero list of O, both derived from h->O
+// The rotated-object search (the paper's variant of Sec. IV-D): O on the body
+// lattice a + h (j - m/2) (the object-grid build at edge m), reduced to cell
+// classes and corner records, and the swept canvas S (the central n^3 block of
+// the swept lattice) with its spectrum conj(F(S))/n^3 and nonzero list, which
+// take the places of the swept corner masks and of O's spectrum.  The lattice
+// build's scratch is released before returning.
+static int build_rotated_object(reg_handle* h) {
+    hipStream_t s = h->stream;
+    const size_t n3 = (size_t)h->n * h->n * h->n, m3 = (size_t)h->m * h->m * h->m;
+    const size_t mp3 = (size_t)h->mp * h->mp * h->mp;
+    const size_t words = (size_t)h->m * h->m * ((h->m + 31) / 32);
+    float *Ow = nullptr, *fow = nullptr;
+    unsigned long long *d2 = nullptr, *dt2 = nullptr;
+    uint32_t* par = nullptr;
+    ALLOC_TRY(h, Ow, m3);
+    ALLOC_TRY(h, fow, m3);
+    ALLOC_TRY(h, d2, m3);
+    ALLOC_TRY(h, dt2, m3);
+    ALLOC_TRY(h, par, words);
+    ALLOC_TRY(h, h->ocls, mp3);
+    ALLOC_TRY(h, h->orec, 2 * mp3);
+    ALLOC_TRY(h, h->Sc, n3);
+    ALLOC_TRY(h, h->W, h->H);
+    ALLOC_TRY(h, h->Wlow, (size_t)NLOW3);
+    ALLOC_TRY(h, h->nz_idx, n3);
+    ALLOC_TRY(h, h->nz_val, n3);
+    ALLOC_TRY(h, h->nz_count, 1);
+    ALLOC_TRY(h, h->nz_bcount, (n3 + 255) / 256);
+    ALLOC_TRY(h, h->nz_boff, (n3 + 255) / 256);
+    DEV_TRY(h, setup_object_grid(h->V, h->F, h->touch, h->nf, h->m, h->h, h->anchor, h->prm.tau_out1, h->prm.tau_in1,
+                                 h->prm.rho, Ow, fow, ObjectScratch{d2, dt2, par}, s));
+    DEV_TRY(h, setup_object_cells(Ow, h->m, h->mp, (float)(-h->prm.rho), h->ocls, h->orec, s));
+    DEV_TRY(h, swept_canvas(h->Sw, h->m, h->n, h->Sc, s));
+    DEV_TRY(h, object_spectrum(h->n, h->Sc, h->spec, h->W, h->tw, h->tw64, h->lowT, h->Wlow, s));
+    DEV_TRY(h, build_nonzero_list(h->Sc, h->n, h->nz_bcount, h->nz_boff, h->nz_idx, h->nz_val, h->nz_count, s));
+    DEV_TRY(h, hipStreamSynchronize(s));
+    for (void* p : {(void*)Ow, (void*)fow, (void*)d2, (void*)dt2, (void*)par}) h->release(p);
+    return REG_OK;
+}
+
 static int build_object_derived(reg_handle* h) {
     DEV_TRY(h, object_spectrum(h->n, h->O, h->spec, h->W, h->tw, h->tw64, h->lowT, h->Wlow, h->stream));
     DEV_TRY(h, build_nonzero_list(h->O, h->n, h->nz_bcount, h->nz_boff, h->nz_idx, h->nz_val, h->nz_count, h->stream));
@@ -712,6 +760,7 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
     h->probe = *probe;
     if (params) h->prm = *params;
     fill_defaults(h->prm);
+    h->rotobj = h->prm.rotate_object != 0;
     h->n_rot = n_rot;
     h->n_poses = n_poses;
     h->nv = mesh->n_vertices;
@@ -835,7 +884,7 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
     DEV_TRY(h, hipMemsetAsync(h->err, 0, sizeof(int), s));
     DEV_TRY(h, hipMemsetAsync(h->stats, 0, 5 * sizeof(int), s));
     DEV_TRY(h, validate_inputs(h->V, h->nv, h->F, h->nf, h->poses, n_poses, h->err, s));
-    DEV_TRY(h, setup_rotations(h->so3, n_rot, h->rots, h->err, s));
+    DEV_TRY(h, setup_rotations(h->so3, n_rot, h->rots, h->err, s, h->rotobj ? 1 : 0));
     int herr = 0;
     DEV_TRY(h, hipMemcpyAsync(&herr, h->err, sizeof(int), hipMemcpyDeviceToHost, s));
     DEV_TRY(h, hipStreamSynchronize(s));
@@ -859,6 +908,10 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
     }
     DEV_TRY(h, setup_swept(h->poses, n_poses, probe->radius_mm, probe->length_mm, h->m, h->mp, h->h, h->wc,
                            h->pose_prep, h->Sw, h->cm, s));
+    if (h->rotobj) {
+        const int rc = build_rotated_object(h);
+        if (rc) return rc;
+    }
     *out = h;
     h = nullptr;  // release the guard
     return REG_OK;
@@ -1286,7 +1339,7 @@ int register_set_rotations(reg_handle* h, const float* so3, int32_t n_rot) {
     }
     DEV_TRY(h, hipMemcpyAsync(h->so3, so3, 16 * (size_t)n_rot, hipMemcpyDeviceToDevice, s));
     DEV_TRY(h, hipMemsetAsync(h->err, 0, sizeof(int), s));
-    DEV_TRY(h, setup_rotations(h->so3, n_rot, h->rots, h->err, s));
+    DEV_TRY(h, setup_rotations(h->so3, n_rot, h->rots, h->err, s, h->rotobj ? 1 : 0));
     int herr = 0;
     DEV_TRY(h, hipMemcpyAsync(&herr, h->err, sizeof(int), hipMemcpyDeviceToHost, s));
     DEV_TRY(h, hipStreamSynchronize(s));
@@ -1324,7 +1377,9 @@ static int enqueue_batch(reg_handle* h, int b0, int cnt, int lane, hipStream_t l
                          hipEvent_t after_plane_pass = nullptr) {
     const bool odd = lane == 1;
     SearchBatchArgs a{};
-    a.cmask = h->cm;
+    a.cmask = h->rotobj ? h->ocls : h->cm;
+    a.crec = h->orec;
+    a.cval = (float)(-h->prm.rho);
     a.m = h->m;
     a.mp = h->mp;
     a.rots = h->rots + 9 * (size_t)b0;
@@ -1365,7 +1420,8 @@ static int enqueue_batch(reg_handle* h, int b0, int cnt, int lane, hipStream_t l
 // certification, exact re-scoring and the outputs of rotations [first, first + count)
 static int enqueue_finish(reg_handle* h, int first, int count, float* out_score, int32_t* out_shift, double* out_pose,
                           hipStream_t s) {
-    const RescoreInputs ri{h->nz_idx, h->nz_val, h->nz_count, h->cm, h->m, h->mp, h->rots};
+    const RescoreInputs ri{h->nz_idx,  h->nz_val, h->nz_count,          h->rotobj ? h->ocls : h->cm, h->m, h->mp,
+                           h->rots,    h->orec,   (float)(-h->prm.rho)};
     DEV_TRY(h, finish_call(h->n, first, count, h->prm.rescore != 0, peak_arrays(h), ri, h->so3 + 4 * (size_t)first,
                            h->h, h->anchor, h->wc, out_score, out_shift, out_pose, s));
     return REG_OK;
@@ -1490,6 +1546,7 @@ int register_debug_correlation(reg_handle* h, int32_t rot, float* out_C) {
 int register_set_grids(reg_handle* h, const float* O, const uint8_t* Sw) {
     if (!h) return fail(REG_EINVAL, "NULL handle");
     if (h->poisoned) return fail(REG_EDEVICE, "handle poisoned by an earlier device error");
+    if (h->rotobj) return fail(REG_ENOTSUP, "grid injection is not offered for the rotated-object search");
     if (O) {
         const size_t n3 = (size_t)h->n * h->n * h->n;
         DEV_TRY(h, hipMemcpyAsync(h->O, O, n3 * sizeof(float), hipMemcpyDeviceToDevice, h->stream));

@@ -46,6 +46,12 @@ struct SearchBatchArgs {
     float* corr_out;           // optional: full float32 field of a 1-rotation batch
     int pv1, pv3, zv;          // schedule variants of pass 1, pass 3 and the z pass
     hipStream_t stream;
+    // rotated-object search: the rotated grid is a real lattice whose cell
+    // classes sit in cmask and whose mixed cells' corner values sit in crec
+    // (two float4 per cell, bricked as cmask), class 1 standing for cval;
+    // rots then hold R^T.  NULL: corner masks of the binary swept lattice.
+    const float4* crec = nullptr;
+    float cval = 0.0f;
 };
 
 // Schedule variants (threads and waves per SIMD of the plane workgroups;
@@ -82,7 +88,12 @@ hipError_t setup_object_grid(const float* V, const int32_t* F, const uint8_t* to
 hipError_t setup_swept(const float* poses, int np, double r, double L, int m, int mp, double h, const double* wc,
                        double* pose_tmp, uint8_t* Sw, uint8_t* cm, hipStream_t s);
 hipError_t setup_cellmask(const uint8_t* Sw, int m, int mp, uint8_t* cm, hipStream_t s);
-hipError_t setup_rotations(const float* so3, int M, double* rots, int* err, hipStream_t s);
+hipError_t setup_rotations(const float* so3, int M, double* rots, int* err, hipStream_t s, int transpose = 0);
+// rotated-object search: cell classes (mp^3 bytes, bricked) and corner records
+// (2 mp^3 float4) of the object grid on the body lattice; the fixed grid S
+// (n^3 float) from the swept lattice
+hipError_t setup_object_cells(const float* G, int m, int mp, float cval, uint8_t* cls, float4* rec, hipStream_t s);
+hipError_t swept_canvas(const uint8_t* Sw, int m, int n, float* S, hipStream_t s);
 hipError_t validate_inputs(const float* V, int nv, const int32_t* F, int nf, const float* poses, int np, int* err,
                            hipStream_t s);
 // per-rotation peak bookkeeping, indexed by absolute rotation
@@ -100,12 +111,14 @@ struct PeakArrays {
 };
 // what the exact re-score reads
 struct RescoreInputs {
-    const uint32_t* nz_idx;  // nonzero voxels of O: packed kx | ky << 8 | kz << 16
+    const uint32_t* nz_idx;  // nonzero voxels of the fixed grid (O; S when O rotates): kx | ky << 8 | kz << 16
     const float* nz_val;
     const int* nz_count;
     const uint8_t* cmask;
     int m, mp;
     const double* rots;      // all rotations
+    const float4* crec;      // rotated-object search (as in SearchBatchArgs), else NULL
+    float cval;
 };
 hipError_t select_batch(int n, const SearchBatchArgs& a, int base, const PeakArrays& pk);
 hipError_t finish_call(int n, int first, int count, int always, const PeakArrays& pk, const RescoreInputs& ri,

@@ -129,6 +129,21 @@ __device__ __forceinline__ float trilinear_mask(uint32_t mk, float fx, float fy,
     return c0 * gz + c1 * fz;
 }
 
+// Trilinear value of a real lattice from the eight corner values of a cell,
+// held as two float4 (corner c = cx + 2 cy + 4 cz is component c % 4 of
+// record c / 4): lerps along x, then y, then z.
+__device__ __forceinline__ float trilinear_rec(float4 a, float4 b, float fx, float fy, float fz) {
+    const float c00 = fmaf(fx, a.y - a.x, a.x), c10 = fmaf(fx, a.w - a.z, a.z);
+    const float c01 = fmaf(fx, b.y - b.x, b.x), c11 = fmaf(fx, b.w - b.z, b.z);
+    const float c0 = fmaf(fy, c10 - c00, c00), c1 = fmaf(fy, c11 - c01, c01);
+    return fmaf(fz, c1 - c0, c0);
+}
+
+// Cell classes of a real lattice (the object grid of the rotated-object
+// search): every corner 0, every corner the constant of the class (the deep
+// penalty -rho), or mixed, with its corner values in a record.
+constexpr uint8_t CELL_ZERO = 0, CELL_CONST = 1, CELL_MIXED = 2;
+
 // Global -> LDS copy of COUNT elements by NTH threads with every thread's
 // loads issued before the first is waited for (a loop that stores each load
 // to LDS before issuing the next pays one memory latency per element):
@@ -465,6 +480,16 @@ struct RotSampler {
         const uint32_t mk = cmask[a];
         return mk ? trilinear_mask(mk, fx, fy, fz) : 0.0f;
     }
+    // the same on a real lattice given by cell classes and corner records
+    __device__ __forceinline__ float sample_rec(const uint8_t* __restrict__ cls, const float4* __restrict__ rec, float cval,
+                                                int m, int mb, int x, int y, int z) const {
+        float fx, fy, fz;
+        const long a = locate(m, mb, x, y, z, fx, fy, fz);
+        if (a < 0) return 0.0f;
+        const uint32_t c = cls[a];
+        if (c == CELL_MIXED) return trilinear_rec(rec[2 * a], rec[2 * a + 1], fx, fy, fz);
+        return c == CELL_CONST ? cval : 0.0f;
+    }
 };
 
 // Trilinear value of a binary lattice cell as a polynomial in the fractions:
@@ -601,13 +626,96 @@ __device__ __forceinline__ void generate_plane(float2* plane, const float4* lut,
     }
 }
 
+// The plane of the rotated object grid (the search that rotates O, Sec.
+// IV-D): the fixed-point walk of generate_plane over a real lattice held as
+// cell classes (bricked bytes, as the corner masks) and corner records.  The
+// class bytes of a batch are gathered first, then the records of its mixed
+// cells; two rows per batch keep the four samples' records in 32
+// registers.
+template <int N, int NT>
+__device__ __forceinline__ void generate_plane_rec(float2* plane, const uint32_t* bax, const uint32_t* bay,
+                                                   const uint32_t* baz, const RotSampler& rs,
+                                                   const uint8_t* __restrict__ cls, const float4* __restrict__ rec,
+                                                   float cval, int z) {
+    using C = Canvas<N>;
+    static_assert(C::N2 <= NT, "a plane workgroup covers every column pair");
+    constexpr int YS = NT / C::N2;
+    constexpr int G = 2;
+    const int j = threadIdx.x % C::N2, y0 = threadIdx.x / C::N2;
+    if (threadIdx.x >= YS * C::N2 || y0 >= N) return;
+    const double two32 = 4294967296.0;
+    const float inv32 = 2.3283064365386963e-10f;  // 2^-32
+    long long U[2][3], D[3];
+    {
+        const double yc = (double)y0 - rs.hn, zc = (double)z - rs.hn;
+        for (int s2 = 0; s2 < 2; ++s2) {
+            const double xc = (double)(2 * j + s2) - rs.hn;
+            U[s2][0] = __double2ll_rn(fma(rs.r00, xc, fma(rs.r01, yc, fma(rs.r02, zc, rs.hm))) * two32);
+            U[s2][1] = __double2ll_rn(fma(rs.r10, xc, fma(rs.r11, yc, fma(rs.r12, zc, rs.hm))) * two32);
+            U[s2][2] = __double2ll_rn(fma(rs.r20, xc, fma(rs.r21, yc, fma(rs.r22, zc, rs.hm))) * two32);
+        }
+        D[0] = __double2ll_rn((double)YS * rs.r01 * two32);
+        D[1] = __double2ll_rn((double)YS * rs.r11 * two32);
+        D[2] = __double2ll_rn((double)YS * rs.r21 * two32);
+    }
+    for (int y = y0; y < N; y += YS * G) {
+        uint32_t addr[2 * G];
+        float fx[2 * G], fy[2 * G], fz[2 * G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2) {
+                const int q = 2 * g + s2;
+                const uint32_t ix = (uint32_t)(U[s2][0] >> 32), iy = (uint32_t)(U[s2][1] >> 32),
+                               iz = (uint32_t)(U[s2][2] >> 32);
+                fx[q] = (float)(uint32_t)U[s2][0] * inv32;
+                fy[q] = (float)(uint32_t)U[s2][1] * inv32;
+                fz[q] = (float)(uint32_t)U[s2][2] * inv32;
+                addr[q] = bax[ix] + bay[iy] + baz[iz];
+                U[s2][0] += D[0];
+                U[s2][1] += D[1];
+                U[s2][2] += D[2];
+            }
+        }
+        uint32_t cl[2 * G];
+#pragma unroll
+        for (int q = 0; q < 2 * G; ++q) {
+            const bool live = (N % (YS * G) == 0) || y + (q / 2) * YS < N;
+            cl[q] = live ? (uint32_t)cls[addr[q]] : (uint32_t)CELL_ZERO;
+        }
+        float4 ra[2 * G], rb[2 * G];
+#pragma unroll
+        for (int q = 0; q < 2 * G; ++q) {
+            ra[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            rb[q] = ra[q];
+            if (cl[q] == CELL_MIXED) {
+                ra[q] = rec[2 * (size_t)addr[q]];
+                rb[q] = rec[2 * (size_t)addr[q] + 1];
+            }
+        }
+        float v[2 * G];
+#pragma unroll
+        for (int q = 0; q < 2 * G; ++q)
+            v[q] = cl[q] == CELL_MIXED ? trilinear_rec(ra[q], rb[q], fx[q], fy[q], fz[q])
+                                       : (cl[q] == CELL_CONST ? cval : 0.0f);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int yy = y + g * YS;
+            if ((N % (YS * G) == 0) || yy < N) plane[yy * C::P + j] = make_float2(v[2 * g], v[2 * g + 1]);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ pass 1
 
-template <int N, int NT, int WPE>
+// REC: the rotated grid is a real lattice (cell classes in cmask, corner
+// records in crec, the class constant cval) instead of corner masks.
+template <int N, int NT, int WPE, bool REC>
 __global__ __launch_bounds__(NT, WPE) void k_rotvox_fwd_xy(const uint8_t* __restrict__ cmask, int m, int mb,
                                                        const double* __restrict__ rots, int count,
                                                        const float2* __restrict__ twg, const double2* __restrict__ tw64,
-                                                       float2* __restrict__ spec, double2* __restrict__ lowT) {
+                                                       float2* __restrict__ spec, double2* __restrict__ lowT,
+                                                       const float4* __restrict__ crec, float cval) {
     using C = Canvas<N>;
     __shared__ float2 plane[N * C::P];
     __shared__ float2 tw[N];
@@ -633,14 +741,17 @@ __global__ __launch_bounds__(NT, WPE) void k_rotvox_fwd_xy(const uint8_t* __rest
     }
     RotSampler rs;
     rs.load(rots + rot * 9, m, N);
-    build_trilinear_lut<NT>(lut);
+    if (!REC) build_trilinear_lut<NT>(lut);
     build_brick_tables<NT>(bax, bay, baz, C::M, mb);
     if (tid < N) {
         tw[tid] = twv;
         tws[tid] = tw64v;
     }
     __syncthreads();
-    generate_plane<N, NT>(plane, lut, bax, bay, baz, rs, cmask, z);
+    if (REC)
+        generate_plane_rec<N, NT>(plane, bax, bay, baz, rs, cmask, crec, cval, z);
+    else
+        generate_plane<N, NT>(plane, lut, bax, bay, baz, rs, cmask, z);
     __syncthreads();
     plane_low_dft<N, NT>(plane, tws, rbuf, lowT + ((size_t)rot * N + z) * NLOW2);
     plane_forward_and_store<N, NT>(plane, tw, spec + (size_t)rot * C::H, z);
@@ -1119,6 +1230,7 @@ __global__ __launch_bounds__(1024) void k_certify(const double* __restrict__ bes
 __global__ __launch_bounds__(256) void k_rescore(const uint32_t* __restrict__ nz_idx, const float* __restrict__ nz_val,
                                                  const int* __restrict__ nz_count, int n, int nslice,
                                                  const uint8_t* __restrict__ cmask, int m, int mb,
+                                                 const float4* __restrict__ crec, float cval,
                                                  const double* __restrict__ rots, const int32_t* __restrict__ need_list,
                                                  const int* __restrict__ need_count, const int32_t* __restrict__ cand_idx,
                                                  const int32_t* __restrict__ cand_n, double* __restrict__ cand_part) {
@@ -1143,7 +1255,7 @@ __global__ __launch_bounds__(256) void k_rescore(const uint32_t* __restrict__ nz
             x -= x >= n ? n : 0;
             y -= y >= n ? n : 0;
             zz -= zz >= n ? n : 0;
-            const float sv = rs.sample(cmask, m, mb, x, y, zz);
+            const float sv = crec ? rs.sample_rec(cmask, crec, cval, m, mb, x, y, zz) : rs.sample(cmask, m, mb, x, y, zz);
             if (sv != 0.0f) acc += (double)nz_val[j] * (double)sv;
         }
 #pragma unroll
@@ -1218,12 +1330,19 @@ __global__ __launch_bounds__(256) void k_low_combine(const double2* __restrict__
 // ------------------------------------------------------------- finalize
 // score, signed shift and FP64 pose of a peak: t = wc - R a + h R shift
 
+// rotobj: the field is C'[e] = sum_j S[j] O_q[j + e] of the rotated-object
+// search, whose shift of Eq. (xcorr) is dk = -e, and the pose is
+// t = center_world - R a + h dk (the object is rotated about its anchor, which
+// sits at the canvas centre); otherwise t = center_world - R a + h R d.
 __device__ __forceinline__ void write_peak(int i, double score, uint32_t flat, const float* __restrict__ quats, int n, double h,
-                                           const double* __restrict__ anchor, const double* wc, float* __restrict__ out_score,
-                                           int32_t* __restrict__ out_shift, double* __restrict__ out_pose) {
+                                           const double* __restrict__ anchor, const double* wc, int rotobj,
+                                           float* __restrict__ out_score, int32_t* __restrict__ out_shift,
+                                           double* __restrict__ out_pose) {
     int d[3] = {(int)(flat % n), (int)((flat / n) % n), (int)(flat / ((uint32_t)n * n))};
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 3; ++a) {
         if (d[a] >= n / 2) d[a] -= n;
+        if (rotobj) d[a] = -d[a];
+    }
     if (out_score) out_score[i] = (float)score;
     if (out_shift) {
         out_shift[3 * i] = d[0];
@@ -1246,7 +1365,7 @@ __device__ __forceinline__ void write_peak(int i, double score, uint32_t flat, c
                 ra += Rm[3 * r + c] * anchor[c];
                 rd += Rm[3 * r + c] * (double)d[c];
             }
-            o[4 + r] = wc[r] - ra + h * rd;
+            o[4 + r] = wc[r] - ra + h * (rotobj ? (double)d[r] : rd);
         }
     }
 }
@@ -1254,12 +1373,12 @@ __device__ __forceinline__ void write_peak(int i, double score, uint32_t flat, c
 // field maxima of a call's rotations -> outputs (arrays offset to the call)
 __global__ void k_finalize(const double* __restrict__ best_val, const int32_t* __restrict__ best_flat, int count,
                            const float* __restrict__ quats, int n, double h, const double* __restrict__ anchor, double wc0,
-                           double wc1, double wc2, float* __restrict__ out_score, int32_t* __restrict__ out_shift,
+                           double wc1, double wc2, int rotobj, float* __restrict__ out_score, int32_t* __restrict__ out_shift,
                            double* __restrict__ out_pose) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     const double wc[3] = {wc0, wc1, wc2};
-    write_peak(i, best_val[i], (uint32_t)best_flat[i], quats, n, h, anchor, wc, out_score, out_shift, out_pose);
+    write_peak(i, best_val[i], (uint32_t)best_flat[i], quats, n, h, anchor, wc, rotobj, out_score, out_shift, out_pose);
 }
 
 // re-scored rotations: the best exact candidate (ties: lowest flat index)
@@ -1267,8 +1386,8 @@ __global__ void k_finalize(const double* __restrict__ best_val, const int32_t* _
 __global__ void k_apply(const int32_t* __restrict__ need_list, const int* __restrict__ need_count,
                         const int32_t* __restrict__ cand_idx, const int32_t* __restrict__ cand_n,
                         const double* __restrict__ cand_part, int nslice, const float* __restrict__ quats, int n, double h,
-                        const double* __restrict__ anchor, double wc0, double wc1, double wc2, float* __restrict__ out_score,
-                        int32_t* __restrict__ out_shift, double* __restrict__ out_pose) {
+                        const double* __restrict__ anchor, double wc0, double wc1, double wc2, int rotobj,
+                        float* __restrict__ out_score, int32_t* __restrict__ out_shift, double* __restrict__ out_pose) {
     const int nc = *need_count;
     const double wc[3] = {wc0, wc1, wc2};
     for (int pos = blockIdx.x * blockDim.x + threadIdx.x; pos < nc; pos += gridDim.x * blockDim.x) {
@@ -1286,7 +1405,7 @@ __global__ void k_apply(const int32_t* __restrict__ need_list, const int* __rest
                 flat = f;
             }
         }
-        if (cn > 0) write_peak(i, best, flat, quats, n, h, anchor, wc, out_score, out_shift, out_pose);
+        if (cn > 0) write_peak(i, best, flat, quats, n, h, anchor, wc, rotobj, out_score, out_shift, out_pose);
     }
 }
 
@@ -1628,7 +1747,10 @@ __global__ void k_cellmask(const uint8_t* __restrict__ Sw, int m, int mp, uint8_
 }
 
 // SO(3) samples -> rotation matrices (double math, float storage) + checks
-__global__ void k_rot_prep(const float* __restrict__ so3, int M, double* __restrict__ rots, int* __restrict__ err) {
+// transpose: store R^T, the map from canvas offsets to body-lattice offsets of
+// the rotated-object search
+__global__ void k_rot_prep(const float* __restrict__ so3, int M, int transpose, double* __restrict__ rots,
+                           int* __restrict__ err) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M) return;
     double q[4] = {so3[4 * i], so3[4 * i + 1], so3[4 * i + 2], so3[4 * i + 3]};
@@ -1640,6 +1762,49 @@ __global__ void k_rot_prep(const float* __restrict__ so3, int M, double* __restr
     o[0] = 1 - 2 * (y * y + z * z); o[1] = 2 * (x * y - w * z); o[2] = 2 * (x * z + w * y);
     o[3] = 2 * (x * y + w * z); o[4] = 1 - 2 * (x * x + z * z); o[5] = 2 * (y * z - w * x);
     o[6] = 2 * (x * z - w * y); o[7] = 2 * (y * z + w * x); o[8] = 1 - 2 * (x * x + y * y);
+    if (transpose) {
+        double t = o[1]; o[1] = o[3]; o[3] = t;
+        t = o[2]; o[2] = o[6]; o[6] = t;
+        t = o[5]; o[5] = o[7]; o[7] = t;
+    }
+}
+
+// Cell classes and corner records of a real lattice over the padded, bricked
+// lattice (the object grid on the body lattice, for the rotated-object
+// search); taps beyond the lattice are 0.  Records are written for mixed
+// cells only.
+__global__ void k_objcells(const float* __restrict__ G, int m, int mp, float cval, uint8_t* __restrict__ cls,
+                           float4* __restrict__ rec) {
+    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t mp3 = (size_t)mp * mp * mp;
+    if (id >= mp3) return;
+    const int ix = (int)(id % mp), iy = (int)((id / mp) % mp), iz = (int)(id / ((size_t)mp * mp));
+    float v[8];
+    bool zero = true, cst = true;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int x = ix + (c & 1), y = iy + ((c >> 1) & 1), z = iz + ((c >> 2) & 1);
+        v[c] = (x < m && y < m && z < m) ? G[((size_t)z * m + y) * m + x] : 0.0f;
+        zero = zero && v[c] == 0.0f;
+        cst = cst && v[c] == cval;
+    }
+    const size_t b = brick_index(ix, iy, iz, mp / 4);
+    cls[b] = zero ? CELL_ZERO : cst ? CELL_CONST : CELL_MIXED;
+    if (!zero && !cst) {
+        rec[2 * b] = make_float4(v[0], v[1], v[2], v[3]);
+        rec[2 * b + 1] = make_float4(v[4], v[5], v[6], v[7]);
+    }
+}
+
+// S[k] = S_w at center_world + h (k - n/2): the central n^3 block of the swept
+// lattice, the fixed grid of the rotated-object search
+__global__ void k_swept_canvas(const uint8_t* __restrict__ Sw, int m, int n, float* __restrict__ S) {
+    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t n3 = (size_t)n * n * n;
+    if (id >= n3) return;
+    const int o = (m - n) / 2;
+    const int kx = (int)(id % n), ky = (int)((id / n) % n), kz = (int)(id / ((size_t)n * n));
+    S[id] = Sw[((size_t)(kz + o) * m + (ky + o)) * m + (kx + o)] ? 1.0f : 0.0f;
 }
 
 // finite vertices and poses, face indices in range, pose quaternions near unit
@@ -1677,6 +1842,8 @@ template <> struct PlaneVariant<2> { static constexpr int NT = 512, WPE = 4; };
 template <> struct PlaneVariant<3> { static constexpr int NT = 1024, WPE = 4; };
 __host__ __device__ constexpr int z_threads_of(int v) { return v == 0 ? 128 : v == 1 ? 256 : 512; }
 
+__host__ __device__ constexpr int default_plane_variant_of(int N) { return N > 128 ? 3 : N >= 96 ? 2 : 0; }
+
 __host__ __device__ constexpr bool plane_variant_valid(int N, int v) {
     // above 128 a plane fills more than half of the LDS, so one workgroup per
     // CU holds the whole plane: only the widest workgroup is offered
@@ -1691,9 +1858,14 @@ template <int N, int V>
 static void launch_plane(int pass, const SearchBatchArgs& a) {
     if constexpr (plane_variant_valid(N, V)) {
         constexpr int NT = PlaneVariant<V>::NT, WPE = PlaneVariant<V>::WPE;
-        if (pass == 0)
-            hipLaunchKernelGGL((k_rotvox_fwd_xy<N, NT, WPE>), dim3(a.count * N), dim3(NT), 0, a.stream, a.cmask, a.m,
-                               a.mp / 4, a.rots, a.count, a.tw, a.tw64, a.spec, a.lowT);
+        if (pass == 0 && a.crec) {
+            // the rotated-object search compiles pass 1 for the default workgroup only
+            if constexpr (V == default_plane_variant_of(N))
+                hipLaunchKernelGGL((k_rotvox_fwd_xy<N, NT, WPE, true>), dim3(a.count * N), dim3(NT), 0, a.stream, a.cmask,
+                                   a.m, a.mp / 4, a.rots, a.count, a.tw, a.tw64, a.spec, a.lowT, a.crec, a.cval);
+        } else if (pass == 0)
+            hipLaunchKernelGGL((k_rotvox_fwd_xy<N, NT, WPE, false>), dim3(a.count * N), dim3(NT), 0, a.stream, a.cmask,
+                               a.m, a.mp / 4, a.rots, a.count, a.tw, a.tw64, a.spec, a.lowT, nullptr, 0.0f);
         else
             hipLaunchKernelGGL((k_inv_xy_argmax<N, NT, WPE>), dim3(a.count * N), dim3(NT), 0, a.stream, a.spec, a.count,
                                a.tw, a.tw64, a.Plow, a.ptop, a.pssq, a.corr_out);
@@ -1726,7 +1898,7 @@ static hipError_t launch_search_pass(int pass, const SearchBatchArgs& a) {
         }
         return hipGetLastError();
     }
-    const int v = pass == 0 ? a.pv1 : a.pv3;
+    const int v = pass == 0 ? (a.crec ? default_plane_variant_of(N) : a.pv1) : a.pv3;
     if (!plane_variant_valid(N, v)) return hipErrorInvalidValue;
     switch (v) {
         case 0: launch_plane<N, 0>(pass, a); break;
@@ -1795,7 +1967,7 @@ bool z_variant_ok(int n, int v) {
     }
 }
 
-int default_plane_variant(int n) { return n > 128 ? 3 : n >= 96 ? 2 : 0; }
+int default_plane_variant(int n) { return default_plane_variant_of(n); }
 int default_z_variant(int) { return 1; }
 int plane_variant_threads(int v) { return v == 0 || v == 1 ? 256 : v == 2 ? 512 : 1024; }
 int z_variant_threads(int v) { return z_threads_of(v); }
@@ -1856,8 +2028,20 @@ hipError_t setup_cellmask(const uint8_t* Sw, int m, int mp, uint8_t* cm, hipStre
     return hipGetLastError();
 }
 
-hipError_t setup_rotations(const float* so3, int M, double* rots, int* err, hipStream_t s) {
-    hipLaunchKernelGGL(k_rot_prep, dim3((M + 255) / 256), dim3(256), 0, s, so3, M, rots, err);
+hipError_t setup_rotations(const float* so3, int M, double* rots, int* err, hipStream_t s, int transpose) {
+    hipLaunchKernelGGL(k_rot_prep, dim3((M + 255) / 256), dim3(256), 0, s, so3, M, transpose, rots, err);
+    return hipGetLastError();
+}
+
+hipError_t setup_object_cells(const float* G, int m, int mp, float cval, uint8_t* cls, float4* rec, hipStream_t s) {
+    const size_t mp3 = (size_t)mp * mp * mp;
+    hipLaunchKernelGGL(k_objcells, dim3((unsigned)((mp3 + 255) / 256)), dim3(256), 0, s, G, m, mp, cval, cls, rec);
+    return hipGetLastError();
+}
+
+hipError_t swept_canvas(const uint8_t* Sw, int m, int n, float* S, hipStream_t s) {
+    const size_t n3 = (size_t)n * n * n;
+    hipLaunchKernelGGL(k_swept_canvas, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, Sw, m, n, S);
     return hipGetLastError();
 }
 
@@ -1883,16 +2067,17 @@ hipError_t select_batch(int n, const SearchBatchArgs& a, int base, const PeakArr
 hipError_t finish_call(int n, int first, int count, int always, const PeakArrays& pk, const RescoreInputs& ri,
                        const float* quats, double h, const double* anchor, const double* wc, float* out_score,
                        int32_t* out_shift, double* out_pose, hipStream_t s) {
+    const int rotobj = ri.crec != nullptr;
     hipLaunchKernelGGL(k_finalize, dim3((count + 127) / 128), dim3(128), 0, s, pk.best_val + first, pk.best_flat + first,
-                       count, quats, n, h, anchor, wc[0], wc[1], wc[2], out_score, out_shift, out_pose);
+                       count, quats, n, h, anchor, wc[0], wc[1], wc[2], rotobj, out_score, out_shift, out_pose);
     hipLaunchKernelGGL(k_certify, dim3(1), dim3(1024), 0, s, pk.best_val + first, pk.window + first, pk.ovf + first, count,
                        always, pk.need_list, pk.need_count, pk.stats);
     const int nslice = rescore_slices(n);
     hipLaunchKernelGGL(k_rescore, dim3(2048), dim3(256), 0, s, ri.nz_idx, ri.nz_val, ri.nz_count, n, nslice, ri.cmask, ri.m,
-                       ri.mp / 4, ri.rots + 9 * (size_t)first, pk.need_list, pk.need_count, pk.cand_idx + (size_t)first * CMAX,
-                       pk.cand_n + first, pk.cand_part);
+                       ri.mp / 4, ri.crec, ri.cval, ri.rots + 9 * (size_t)first, pk.need_list, pk.need_count,
+                       pk.cand_idx + (size_t)first * CMAX, pk.cand_n + first, pk.cand_part);
     hipLaunchKernelGGL(k_apply, dim3(16), dim3(256), 0, s, pk.need_list, pk.need_count, pk.cand_idx + (size_t)first * CMAX,
-                       pk.cand_n + first, pk.cand_part, nslice, quats, n, h, anchor, wc[0], wc[1], wc[2], out_score,
+                       pk.cand_n + first, pk.cand_part, nslice, quats, n, h, anchor, wc[0], wc[1], wc[2], rotobj, out_score,
                        out_shift, out_pose);
     return hipGetLastError();
 }
