@@ -507,6 +507,37 @@ def _linear_one(rd, torch, cfg: int, M: int):
     return res
 
 
+def rotate_object_bench(rd, torch, p, reps: int = 3):
+    """The paper's own form of the search (Sec. IV-D: the object grid rotates
+    onto the canvas of the fixed swept grid) against the default (the swept
+    grid rotates) on the workload's rotation set: rotations/s of the scoring
+    (best of reps whole-set calls), the best peak's pose error and score."""
+    import numpy as np
+
+    out = {"rotations": len(p.so3)}
+    for name, rot_obj in (("rotate_swept", 0), ("rotate_object", 1)):
+        h = rd.register_init(p.vertices, p.faces, p.touchable, p.poses, p.so3, p.n, p.h, p.center, p.radius,
+                             p.length, params=dict(rotate_object=rot_obj))
+        try:
+            rd.score_rotations(h)
+            torch.cuda.synchronize()
+            best = float("inf")
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                sc, _, po = rd.score_rotations(h)
+                torch.cuda.synchronize()
+                best = min(best, time.perf_counter() - t0)
+            sc, po = sc.cpu().numpy(), po.cpu().numpy()
+            b = int(np.argmax(sc))
+            ang, mm = _pose_errors(p, po[b])
+            out[name] = {"rotations_per_s": len(p.so3) / best, "ms_per_call": best * 1e3,
+                         "best": {"deg": ang, "mm": mm, "score": float(sc[b])}}
+        finally:
+            rd.register_free(h)
+    out["cost_ratio"] = out["rotate_swept"]["rotations_per_s"] / out["rotate_object"]["rotations_per_s"]
+    return out
+
+
 def isolated_launches(rd, torch, p, dev_args, reps: int = 8):
     """Mean event-timed launch of each search pass when it runs alone: calls of
     one batch each stay on one lane, so no other pass shares the GPU."""
@@ -754,7 +785,8 @@ def main():
     if args.variants:
         out["samplers"] = sampler_bench(rd, torch, p, len(p.so3))
         out["linear_correlation"] = linear_bench(rd, torch)
-        print("bench: sampler and linear-correlation variants done", file=sys.stderr, flush=True)
+        out["rotate_object"] = rotate_object_bench(rd, torch, p)
+        print("bench: sampler, linear-correlation and rotated-object variants done", file=sys.stderr, flush=True)
     if args.batch > 0:
         out["batch"] = batch_bench(rd, torch, work["batch"], args)
         print("bench: uneven batch done", file=sys.stderr, flush=True)
