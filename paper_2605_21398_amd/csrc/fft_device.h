@@ -1,4 +1,5 @@
-// Mixed-radix (2, 3, 4, 5, 8, 16) complex FFTs on LDS-resident batches, for gfx950.
+// Mixed-radix (2, 3, 4, 5, 8, 16 and the composites 6, 9, 10, 12, 15) complex
+// FFTs on LDS-resident batches, for gfx950.
 //
 // The docking score of Sec. IV-B is a circular cross-correlation evaluated
 // through 3D FFTs (Eq. xcorr and the FFT identity that follows it).  This
@@ -19,20 +20,20 @@
 
 namespace regdock {
 
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+__host__ __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 // a * conj(b)
-__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+__host__ __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
     return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
-__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
-__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__host__ __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__host__ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 // multiply by -i (forward) or +i (inverse)
 template <bool INV>
-__device__ __forceinline__ float2 mul_mi(float2 a) {
+__host__ __device__ __forceinline__ float2 mul_mi(float2 a) {
     return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
 }
 
@@ -42,7 +43,7 @@ __device__ __forceinline__ float2 mul_mi(float2 a) {
 template <int R, bool INV> struct Dft;
 
 template <bool INV> struct Dft<2, INV> {
-    __device__ __forceinline__ static void run(float2* v) {
+    __host__ __device__ __forceinline__ static void run(float2* v) {
         float2 a = v[0], b = v[1];
         v[0] = cadd(a, b);
         v[1] = csub(a, b);
@@ -50,7 +51,7 @@ template <bool INV> struct Dft<2, INV> {
 };
 
 template <bool INV> struct Dft<3, INV> {
-    __device__ __forceinline__ static void run(float2* v) {
+    __host__ __device__ __forceinline__ static void run(float2* v) {
         const float s3 = 0.866025403784438647f;  // sin(2 pi / 3)
         float2 t1 = cadd(v[1], v[2]);
         float2 t2 = csub(v[1], v[2]);
@@ -64,7 +65,7 @@ template <bool INV> struct Dft<3, INV> {
 };
 
 template <bool INV> struct Dft<4, INV> {
-    __device__ __forceinline__ static void run(float2* v) {
+    __host__ __device__ __forceinline__ static void run(float2* v) {
         float2 t0 = cadd(v[0], v[2]);
         float2 t1 = csub(v[0], v[2]);
         float2 t2 = cadd(v[1], v[3]);
@@ -77,7 +78,7 @@ template <bool INV> struct Dft<4, INV> {
 };
 
 template <bool INV> struct Dft<5, INV> {
-    __device__ __forceinline__ static void run(float2* v) {
+    __host__ __device__ __forceinline__ static void run(float2* v) {
         const float c1 = 0.309016994374947424f;   // cos(2 pi / 5)
         const float c2 = -0.809016994374947424f;  // cos(4 pi / 5)
         const float s1 = 0.951056516295153572f;   // sin(2 pi / 5)
@@ -101,7 +102,7 @@ template <bool INV> struct Dft<5, INV> {
 template <bool INV> struct Dft<8, INV> {
     // radix-2 butterflies on (x_j, x_{j+4}), twiddle W8^j on the differences,
     // then a radix-4 DFT on each half: sums give even outputs, differences odd.
-    __device__ __forceinline__ static void run(float2* v) {
+    __host__ __device__ __forceinline__ static void run(float2* v) {
         const float h = 0.707106781186547524f;
         float2 a[4], b[4];
 #pragma unroll
@@ -128,7 +129,7 @@ template <bool INV> struct Dft<8, INV> {
 template <bool INV> struct Dft<16, INV> {
     // 4 x 4: radix-4 DFTs over the residues n2 = j mod 4 (inputs j = 4 n1 + n2),
     // twiddles W16^(n2 k1), radix-4 DFTs over n2; output k = k1 + 4 k2
-    __device__ __forceinline__ static void run(float2* v) {
+    __host__ __device__ __forceinline__ static void run(float2* v) {
         const float h = 0.707106781186547524f;   // cos(pi/4)
         const float c1 = 0.923879532511286756f;  // cos(pi/8)
         const float s1 = 0.382683432365089772f;  // sin(pi/8)
@@ -167,6 +168,85 @@ template <bool INV> struct Dft<16, INV> {
     }
 };
 
+// Composite codelets DFT_{PQ} from DFT_P and DFT_Q: inputs j = Q n1 + n2,
+// DFT_P over n1 for each n2, twiddles W_PQ^(n2 k1), DFT_Q over n2 for each k1;
+// output k = k1 + P k2.  The twiddles are compile-time constants (cosine and
+// sine by their Taylor series in double, rounded to float); multiples of a
+// quarter turn become sign changes and swaps.
+struct CTw {
+    double c, s;
+};
+__host__ __device__ constexpr CTw ct_twiddle(int m, int R) {
+    // cos and sin of 2 pi m / R, the angle reduced to [-pi, pi]
+    int mm = m % R;
+    if (2 * mm > R) mm -= R;
+    const double x = 2.0 * 3.14159265358979323846 * (double)mm / (double)R;
+    double c = 1.0, s = x, tc = 1.0, ts = x;
+    for (int k = 1; k < 30; ++k) {
+        tc *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+        ts *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+        c += tc;
+        s += ts;
+    }
+    return CTw{c, s};
+}
+
+// x * W_R^M, W_R = exp(-+2 pi i / R) (forward, inverse)
+template <int R, int M, bool INV>
+__host__ __device__ __forceinline__ float2 ct_rot(float2 x) {
+    constexpr int m = M % R;
+    if constexpr (m == 0) {
+        return x;
+    } else if constexpr (4 * m == R) {
+        return mul_mi<INV>(x);
+    } else if constexpr (2 * m == R) {
+        return make_float2(-x.x, -x.y);
+    } else if constexpr (4 * m == 3 * R) {
+        return mul_mi<!INV>(x);
+    } else {
+        constexpr CTw t = ct_twiddle(m, R);
+        constexpr float c = (float)t.c, sn = INV ? (float)t.s : -(float)t.s;
+        return make_float2(x.x * c - x.y * sn, x.x * sn + x.y * c);
+    }
+}
+
+template <int P, int Q, bool INV>
+struct DftPQ {
+    template <int I>
+    __host__ __device__ __forceinline__ static void twiddle_all(float2 (&a)[Q][P]) {
+        if constexpr (I < P * Q) {
+            constexpr int n2 = I / P, k1 = I % P;
+            a[n2][k1] = ct_rot<P * Q, n2 * k1, INV>(a[n2][k1]);
+            twiddle_all<I + 1>(a);
+        }
+    }
+    __host__ __device__ __forceinline__ static void run(float2* v) {
+        float2 a[Q][P];
+#pragma unroll
+        for (int n2 = 0; n2 < Q; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < P; ++n1) a[n2][n1] = v[Q * n1 + n2];
+            Dft<P, INV>::run(a[n2]);
+        }
+        twiddle_all<0>(a);
+#pragma unroll
+        for (int k1 = 0; k1 < P; ++k1) {
+            float2 b[Q];
+#pragma unroll
+            for (int n2 = 0; n2 < Q; ++n2) b[n2] = a[n2][k1];
+            Dft<Q, INV>::run(b);
+#pragma unroll
+            for (int k2 = 0; k2 < Q; ++k2) v[k1 + P * k2] = b[k2];
+        }
+    }
+};
+
+template <bool INV> struct Dft<6, INV> : DftPQ<3, 2, INV> {};
+template <bool INV> struct Dft<9, INV> : DftPQ<3, 3, INV> {};
+template <bool INV> struct Dft<10, INV> : DftPQ<5, 2, INV> {};
+template <bool INV> struct Dft<12, INV> : DftPQ<4, 3, INV> {};
+template <bool INV> struct Dft<15, INV> : DftPQ<5, 3, INV> {};
+
 // ------------------------------------------------------- factorisation plan
 
 __host__ __device__ constexpr int pow2_exponent(int L) {
@@ -178,7 +258,7 @@ __host__ __device__ constexpr int pow2_exponent(int L) {
     return e;
 }
 
-__host__ __device__ constexpr int fft_radix(int L, int p) {
+__host__ __device__ constexpr int greedy_radix(int L, int p) {
     // greedy: 8s, then a 4, then a 2, then 5s, then 3s; when the power of two
     // in L is 2^(3k + 1) (k >= 1) one radix-16 stage replaces an 8 and a 2,
     // saving a pass
@@ -194,6 +274,43 @@ __host__ __device__ constexpr int fft_radix(int L, int p) {
         ++i;
     }
     return 1;
+}
+
+__host__ __device__ constexpr int greedy_npass(int L) {
+    int n = 0;
+    while (greedy_radix(L, n) > 1) ++n;
+    return n;
+}
+
+__host__ __device__ constexpr bool is_codelet(int r) {
+    return r == 2 || r == 3 || r == 4 || r == 5 || r == 6 || r == 8 || r == 9 || r == 10 || r == 12 || r == 15 ||
+           r == 16;
+}
+
+// first radix of a two-pass plan L = R1 R2 of codelets, the most balanced
+// (largest min(R1, R2)), the larger R1 among equals; 0 if there is none
+__host__ __device__ constexpr int two_pass_first(int L) {
+    int best = 0, bmin = 0;
+    for (int r1 = 16; r1 >= 2; --r1)
+        if (is_codelet(r1) && L % r1 == 0 && is_codelet(L / r1)) {
+            const int mn = r1 < L / r1 ? r1 : L / r1;
+            if (mn > bmin) {
+                bmin = mn;
+                best = r1;
+            }
+        }
+    return best;
+}
+
+// Radix of pass p of a length-L transform (1 past the last pass, 0 if L has
+// another prime factor): the greedy plan where it takes at most two passes,
+// else a two-pass plan through a composite codelet where one exists (60 =
+// 10 x 6, 96 = 12 x 8, 120 = 12 x 10, 160 = 16 x 10, 180 = 15 x 12, 30 = 6 x 5,
+// 90 = 10 x 9), else the greedy plan.
+__host__ __device__ constexpr int fft_radix(int L, int p) {
+    if (greedy_npass(L) <= 2 || two_pass_first(L) == 0) return greedy_radix(L, p);
+    const int r1 = two_pass_first(L);
+    return p == 0 ? r1 : p == 1 ? L / r1 : 1;
 }
 
 __host__ __device__ constexpr int fft_npass(int L) {
