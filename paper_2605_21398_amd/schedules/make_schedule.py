@@ -8,6 +8,9 @@ batch's draw at that edge (h = 15.36 mm / n), 512 rotations.
 
     python -m paper_2605_21398_amd.schedules.make_schedule            # -> mi355x.json
     python -m paper_2605_21398_amd.schedules.make_schedule --out my.json --edges 64 128
+
+Records of edges not tuned in the run are kept from the output file when it
+exists.
 """
 from __future__ import annotations
 
@@ -39,6 +42,8 @@ def main():
     a = ap.parse_args()
     import paper_2605_21398_amd as rd
     rd.load_library()
+    if os.path.exists(a.out):
+        rd.register_tune_load(a.out)
     for n in a.edges:
         p = problem_for(n)
         h = rd.register_init(p.vertices, p.faces, p.touchable, p.poses, p.so3, p.n, p.h, p.center, p.radius,
