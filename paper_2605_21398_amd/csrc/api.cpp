@@ -1883,7 +1883,7 @@ int enqueue_search_finish(reg_handle* h, float* out_score, int32_t* out_shift, d
 
 size_t object_bytes(const ObjectData* o) { return o ? o->bytes : 0; }
 
-Footprint footprint(int n, int n_rot, int n_poses, int nv, int nf, int batch, int refine_starts) {
+Footprint footprint(int n, int n_rot, int n_poses, int nv, int nf, int batch, int refine_starts, int rotate_object) {
     const size_t n3 = (size_t)n * n * n, H = spectrum_elems(n);
     const size_t m = (size_t)lattice_edge(n), mp = (m + 3) / 4 * 4;
     const size_t B = (size_t)batch, M = (size_t)n_rot, N = (size_t)n_poses;
@@ -1899,6 +1899,9 @@ Footprint footprint(int n, int n_rot, int n_poses, int nv, int nf, int batch, in
                 K * (sizeof(RefineState) + sizeof(LbfgsState) +
                      REF_TMAX * (sizeof(RefineTrial) + REF_EVAL_PARTS * sizeof(RefineEval))) +
                 nq * (sizeof(RefineHit) + 48 + 8 + 4 + 8 + 16 * (8 + 16 + 4)) + 4096;
+    if (rotate_object)  // build_rotated_object: classes, records, S and its spectrum, the lattice build's scratch
+        f.request += 33 * mp * mp * mp + 4 * n3 + 8 * H + 16 * (size_t)NLOW3 + 8 * n3 + 8 * ((n3 + 255) / 256) +
+                     24 * m * m * m + m * m * ((m + 31) / 32) * 4;
     return f;
 }
 

@@ -38,11 +38,13 @@ size_t object_bytes(const ObjectData* o);
 
 // Device bytes of one registration: the object part (grid, spectrum, lists,
 // mesh and its hierarchy) and the request part (swept lattice, spectrum work
-// buffer of one batch, per-rotation arrays, refinement buffers).
+// buffer of one batch, per-rotation arrays, refinement buffers, and with
+// rotate_object the rotated-object search's lattice records and spectra).
 struct Footprint {
     size_t object = 0, request = 0;
 };
-Footprint footprint(int n, int n_rot, int n_poses, int n_vertices, int n_faces, int batch, int refine_starts);
+Footprint footprint(int n, int n_rot, int n_poses, int n_vertices, int n_faces, int batch, int refine_starts,
+                    int rotate_object = 0);
 int default_batch_for(int n, int n_rot);
 
 // the calling thread's last error message
