@@ -189,3 +189,48 @@ def test_rotobj_recovers_the_truth_on_a_fine_canvas():
     err = np.linalg.norm((R @ a + po[r, 4:]) - (Rg @ a + p.t_gt))
     print(f"truth rotation: anchor error {err:.3f} mm (h {p.h}); best rotation {int(np.argmax(sc))}")
     assert err < p.h * math.sqrt(3) / 2 + 1e-9
+
+
+def _eager(rd, h):
+    sc, _, po = rd.score_rotations(h, shift=False)
+    top = rd.register_top_k(h, sc, 16)
+    starts = po[top.long()]
+    out, J, _ = rd.refine_se3(h, starts)
+    return dict(scores=sc.cpu().numpy(), poses=po.cpu().numpy(), top=top.cpu().numpy(), refined=out.cpu().numpy(),
+                J=J.cpu().numpy())
+
+
+def test_rotobj_served_and_batched_equal_the_direct_path():
+    """The rotated-object search through the server (params.rotate_object on
+    the request) and captured in a batch graph gives the direct call's peaks,
+    poses and refined poses bit for bit."""
+    rd = _lib()
+    ps = [synth.batch_problem(i, level=4, lmax=6, N=400, M=128) for i in range(2)]
+    hs = [_handle(rd, p) for p in ps]
+    try:
+        ref = [_eager(rd, h) for h in hs]
+        b = rd.Batch(hs, top_k=16, graph_rounds=8, branches=2)
+        try:
+            for rep in range(2):
+                b.run()
+                for i in range(len(hs)):
+                    got = b.outputs(i)
+                    for k in ("scores", "poses", "top", "refined", "J"):
+                        assert np.array_equal(got[k], ref[i][k]), (rep, i, k)
+        finally:
+            b.close()
+    finally:
+        for h in hs:
+            rd.register_free(h)
+    srv = rd.Server(max_inflight=2)
+    try:
+        got = [srv.wait(srv.submit(p.vertices, p.faces, p.touchable, p.poses, p.so3, p.n, p.h, p.center, p.radius,
+                                   p.length, params=dict(rotate_object=1))) for p in ps]
+    finally:
+        srv.close()
+    for r, e in zip(got, ref):
+        assert r["status"] == 0
+        assert np.array_equal(r["top_rot"], e["top"])
+        assert np.array_equal(r["top_pose"], e["poses"][e["top"]])
+        assert np.array_equal(r["refined_pose"], e["refined"])
+        assert np.array_equal(r["refined_J"], e["J"])
