@@ -234,3 +234,25 @@ def test_rotobj_served_and_batched_equal_the_direct_path():
         assert np.array_equal(r["top_pose"], e["poses"][e["top"]])
         assert np.array_equal(r["refined_pose"], e["refined"])
         assert np.array_equal(r["refined_J"], e["J"])
+
+
+@pytest.mark.parametrize("n,h", [(16, 0.8), (48, 0.3), (60, 0.25), (80, 0.2), (96, 0.16), (120, 0.128), (160, 0.096),
+                                 (180, 0.0853)])
+def test_rotobj_every_edge(n, h):
+    """Every other compiled canvas edge (ragged batches, the composite-radix
+    transforms, one plane workgroup per CU from 160 up): two rotations from
+    the mesh against the oracle's variant."""
+    rd = _lib()
+    p = synth.config_problem(1, 1, n=n, h=h, M=16)
+    p.so3 = p.so3[:2]
+    hd = _handle(rd, p, batch=8)
+    try:
+        sc, sh, po = [t.cpu().numpy() for t in rd.score_rotations(hd)]
+        st = rd.register_search_stats(hd)
+    finally:
+        rd.register_free(hd)
+    sel = [0, 1]
+    CB, nO, nS = _oracle_fields(p, sel)
+    tol = TOL_REL * np.abs(np.array([C.max() for C, _ in CB])).max()
+    _check(p, sc, sh, po, sel, CB, tol, f"rotated object, n = {n} (flagged O {nO}, S {nS})")
+    assert st["uncertain"] == 0
