@@ -122,12 +122,30 @@ def cpu_baseline(p, args, starts, evals: int, small):
     return out
 
 
+SEARCH_SOURCES = ("search_kernels.hip", "search_kernels.h", "fft_device.h")
+
+
+def search_code_digest() -> str:
+    """SHA-256 of the search kernels' code: their sources with comments and
+    blank lines removed, so that an edit of comments alone keeps counters
+    taken on the same code valid."""
+    import hashlib
+    import re
+    csrc = os.path.join(ROOT, "paper_2605_21398_amd", "csrc")
+    sha = hashlib.sha256()
+    for f in SEARCH_SOURCES:
+        text = open(os.path.join(csrc, f)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        lines = [re.sub(r"//.*$", "", l).rstrip() for l in text.splitlines()]
+        sha.update("\n".join(l for l in lines if l.strip()).encode())
+    return sha.hexdigest()
+
+
 def counter_traffic(kernel: str, n: int, rotations_per_launch: float):
     """HBM bytes per launch of `kernel` at edge n from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's counters), or
     None when there is none, its launches held another number of rotations, or
-    the kernel source has changed since."""
-    import hashlib
+    the kernels' code has changed since."""
     import re
     path = os.path.join(ROOT, "profiles", "traffic_search_128.md")
     if not os.path.exists(path):
@@ -136,11 +154,7 @@ def counter_traffic(kernel: str, n: int, rotations_per_launch: float):
     if not m:
         return None
     data = json.loads(m.group(1))
-    csrc = os.path.join(ROOT, "paper_2605_21398_amd", "csrc")
-    sha = hashlib.sha256()
-    for f in ("search_kernels.hip", "search_kernels.h"):
-        sha.update(open(os.path.join(csrc, f), "rb").read())
-    if sha.hexdigest() != data.get("search_kernels_sha256"):
+    if search_code_digest() != data.get("search_code_sha256"):
         return None
     k = data["kernels"].get(f"{kernel}<{n}>")
     if k is None or k.get("rotations_per_launch") != rotations_per_launch:

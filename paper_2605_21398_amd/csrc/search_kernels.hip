@@ -30,6 +30,13 @@
 //   k_rescore, k_finalize    rotation's maximum, exact re-scoring where that
 //                            error exceeds the tolerance; score, shift, pose
 //
+// The paper's own form of the search rotates O instead (Sec. IV-D as printed):
+// k_objcells turns O on the body lattice into cell classes and corner records,
+// k_swept_canvas cuts the fixed swept canvas S out of S_w and S takes O's place
+// in the spectrum; pass 1 then resamples the rotated object grid
+// (k_rotvox_fwd_xy with REC), and the shift and pose follow from the reversed
+// correlation (write_peak).
+//
 // Spectrum layout of one rotation (complex64, H = n (n/2 + 1) n elements):
 //   tile t in [0, n * (n/2)/T): ky = t / (n/2/T), kx in [(t % (n/2/T)) T, +T)
 //   tile t in [n (n/2)/T, +n/T): the Nyquist column kx = n/2, ky in a T-range
