@@ -256,3 +256,23 @@ def test_rotobj_every_edge(n, h):
     tol = TOL_REL * np.abs(np.array([C.max() for C, _ in CB])).max()
     _check(p, sc, sh, po, sel, CB, tol, f"rotated object, n = {n} (flagged O {nO}, S {nS})")
     assert st["uncertain"] == 0
+
+
+def test_rotobj_rotation_set_swap_equals_a_fresh_handle():
+    """register_set_rotations on a rotated-object handle (the local search's
+    path) stores the new set transposed like register_init does: its scores
+    and poses equal a fresh handle's on that set, bit for bit."""
+    rd = _lib()
+    p = synth.config_problem(1, 0, M=16)
+    q2 = synth.config_problem(1, 2, M=16).so3
+    h1 = _handle(rd, p)
+    h2 = _handle(rd, p, so3=q2)
+    try:
+        rd.register_set_rotations(h1, q2)
+        a = [t.cpu().numpy() for t in rd.score_rotations(h1)]
+        b = [t.cpu().numpy() for t in rd.score_rotations(h2)]
+    finally:
+        rd.register_free(h1)
+        rd.register_free(h2)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
