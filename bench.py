@@ -478,16 +478,19 @@ def sampler_bench(rd, torch, p, M: int):
         rd.register_free(h)
 
 
-def linear_bench(rd, torch, M: int = 4096):
-    """The padded variant of the search (Sec. IV-B) on the 32^3 (h 0.4 mm) and
-    64^3 (h 0.25 mm) workloads: the circular search on the workload's canvas
-    against the same search on the edge register_linear_edge gives
-    (n_o + n_s - 1 = 107 -> 120 and 173 -> 180), where the correlation is
-    linear.  Same Super-Fibonacci set; rotations/s of the scoring, model HBM
-    bytes per rotation and the best peak's pose error."""
+def linear_bench(rd, torch, M: int = 4096, M3: int = 1024):
+    """The padded variant of the search (Sec. IV-B) on the 32^3 (h 0.4 mm),
+    64^3 (h 0.25 mm) and 128^3 (h 0.12 mm) workloads: the circular search on
+    the workload's canvas against the same search on the edge
+    register_linear_edge gives (n_o + n_s - 1 = 107 -> 120, 173 -> 180 and
+    359 -> 360, the last on the split plane passes), where the correlation is
+    linear.  Same Super-Fibonacci set (M3 rotations at 128^3); rotations/s of
+    the scoring, model HBM bytes per rotation and the best peak's pose
+    error."""
     out = {}
     for cfg in (1, 2):
         out[f"config{cfg}"] = _linear_one(rd, torch, cfg, M)
+    out["config3"] = _linear_one(rd, torch, 3, M3)
     return out
 
 
@@ -513,7 +516,9 @@ def _linear_one(rd, torch, cfg: int, M: int):
             b = int(np.argmax(sc))
             ang, mm = _pose_errors(p, po[b])
             H8 = info["spectrum_elems"] * 8
-            res[name] = {"n": n, "rotations_per_s": M / dt, "model_bytes_per_rotation": 4 * H8 + H8 / info["batch"],
+            passes = 4 if n <= 180 else 6  # the split plane passes move the plane buffer out and back
+            res[name] = {"n": n, "rotations_per_s": M / dt, "model_bytes_per_rotation": passes * H8 + H8 / info["batch"],
+                         "plane_passes": "fused" if n <= 180 else "split",
                          "best": {"deg": ang, "mm": mm, "score": float(sc[b])}}
         finally:
             rd.register_free(h)

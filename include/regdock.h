@@ -72,7 +72,8 @@ typedef struct {
 /* Common canvas of edge n at spacing h (Sec. IV-A/B).  The object canvas is
  * x_k = a + h (k - n/2) with a the mean of the mesh vertices; the swept
  * lattice is y_j = center_world + h (j - m/2), m = 2 ceil((sqrt(3) n + 2)/2).
- * n must be one of 16, 32, 48, 60, 64, 80, 96, 120, 128, 160, 180. */
+ * n must be one of 16, 32, 48, 60, 64, 80, 96, 120, 128, 160, 180 (plane
+ * passes in one workgroup per plane) or 192, 256, 360 (split plane passes). */
 typedef struct {
     int32_t n;
     double h_mm;
@@ -100,7 +101,12 @@ typedef struct {
  * occupancy S on that canvas, which stays fixed.  0 (the default) rotates S
  * instead, against the fixed object canvas.  The variant keeps an m^3
  * lattice of cell classes and 32-byte corner records per cell (360 MB at
- * n = 128, 1 GB at 180); pass 1 then runs with the default workgroup. */
+ * n = 128, 1 GB at 180); pass 1 then runs with the default workgroup.
+ * split_plane = 1 runs the search's plane passes as split row and column
+ * passes through an HBM plane buffer (n^2 n/2 complex per rotation of a
+ * batch) instead of one workgroup per plane; edges above 180, whose plane does
+ * not fit the LDS, always do.  Compiled for 64, 128, 192, 256 and 360
+ * (REG_ENOTSUP otherwise, and with rotate_object). */
 typedef struct {
     double tau_out1, tau_in1, rho;
     double tau_out2, tau_in2, k, lambda;
@@ -112,6 +118,7 @@ typedef struct {
     int32_t plane_variant;
     int32_t z_variant;
     int32_t rotate_object;
+    int32_t split_plane;
 } reg_params;
 
 /* Build a registration problem (Sec. IV-A): the object grid O and its spectrum
@@ -142,7 +149,7 @@ int register_init(const reg_mesh* mesh, const reg_probe* probe, const float* pos
  *   *needed = n_o + n_s - 1; *edge = the smallest supported edge >= *needed.
  * Passing *edge as grid.n (same h and centre) gives a wrap-free search.
  * Errors: REG_EINVAL (NULL or non-finite input, h or probe size <= 0),
- * REG_ENOTSUP (*needed above 180; *needed is still set, *edge = 0). */
+ * REG_ENOTSUP (*needed above 360; *needed is still set, *edge = 0). */
 int register_linear_edge(const float* vertices, int32_t n_vertices, const reg_probe* probe, const float* poses,
                          int32_t n_poses, const double* center_world, double h_mm, double tau_out1, int32_t* needed,
                          int32_t* edge);

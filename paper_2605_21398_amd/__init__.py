@@ -60,7 +60,8 @@ class reg_params(ctypes.Structure):
                 ("lambda_", ctypes.c_double), ("b_t", ctypes.c_double), ("b_r", ctypes.c_double),
                 ("eps", ctypes.c_double), ("max_iters", ctypes.c_int32), ("batch", ctypes.c_int32),
                 ("rescore", ctypes.c_int32), ("lanes", ctypes.c_int32), ("plane_variant", ctypes.c_int32),
-                ("z_variant", ctypes.c_int32), ("rotate_object", ctypes.c_int32)]
+                ("z_variant", ctypes.c_int32), ("rotate_object", ctypes.c_int32),
+                ("split_plane", ctypes.c_int32)]
 
 
 class reg_server_cfg(ctypes.Structure):

@@ -259,6 +259,15 @@ struct reg_handle {
     uint8_t* ocls = nullptr;
     float4* orec = nullptr;
     float* Sc = nullptr;
+    // split plane passes (edges above 180, or params.split_plane): the plane
+    // buffer and the rows' low-block x sums of each lane; units = peak records
+    // per rotation (n for the fused passes)
+    bool split = false;
+    int units = 0;
+    float2* xbuf = nullptr;
+    float2* xbuf2 = nullptr;
+    double2* lowrow = nullptr;
+    double2* lowrow2 = nullptr;
     float2* tw = nullptr;
     double2* tw64 = nullptr;
     double2* lowT = nullptr;
@@ -406,7 +415,7 @@ static int default_batch(int n, size_t H, int n_rot) {
 
 // the handle's lanes and kernel variants: the params where set, else the
 // recorded schedule for the edge, else the defaults
-static int resolve_schedule(int n, const reg_params& p, Schedule& s) {
+static int resolve_schedule(int n, const reg_params& p, Schedule& s, bool split = false) {
     Schedule t;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -419,7 +428,7 @@ static int resolve_schedule(int n, const reg_params& p, Schedule& s) {
     s.pv1 = p.plane_variant > 0 ? p.plane_variant - 1 : t.pv1 >= 0 ? t.pv1 : dpv;
     s.pv3 = p.plane_variant > 0 ? p.plane_variant - 1 : t.pv3 >= 0 ? t.pv3 : dpv;
     s.zv = p.z_variant > 0 ? p.z_variant - 1 : t.zv >= 0 ? t.zv : dzv;
-    if (!plane_variant_ok(n, s.pv1) || !plane_variant_ok(n, s.pv3))
+    if (!split && (!plane_variant_ok(n, s.pv1) || !plane_variant_ok(n, s.pv3)))
         return fail(REG_EINVAL, "plane_variant %d is not valid for edge %d", p.plane_variant, n);
     if (!z_variant_ok(n, s.zv)) return fail(REG_EINVAL, "z_variant %d is not valid for edge %d", p.z_variant, n);
     return REG_OK;
@@ -467,7 +476,8 @@ static int build_rotated_object(reg_handle* h) {
 }
 
 static int build_object_derived(reg_handle* h) {
-    DEV_TRY(h, object_spectrum(h->n, h->O, h->spec, h->W, h->tw, h->tw64, h->lowT, h->Wlow, h->stream));
+    DEV_TRY(h, object_spectrum(h->n, h->O, h->spec, h->W, h->tw, h->tw64, h->lowT, h->Wlow, h->stream, h->xbuf,
+                               h->lowrow));
     DEV_TRY(h, build_nonzero_list(h->O, h->n, h->nz_bcount, h->nz_boff, h->nz_idx, h->nz_val, h->nz_count, h->stream));
     return REG_OK;
 }
@@ -761,6 +771,12 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
     if (params) h->prm = *params;
     fill_defaults(h->prm);
     h->rotobj = h->prm.rotate_object != 0;
+    h->split = !fused_supported(grid->n) || h->prm.split_plane != 0;
+    if (h->split && !split_supported(grid->n))
+        return fail(REG_ENOTSUP, "no split plane passes are compiled for edge %d", grid->n);
+    if (h->split && h->rotobj)
+        return fail(REG_ENOTSUP, "the rotated-object search runs on the fused plane passes only (edges up to 180)");
+    h->units = h->split ? split_units(grid->n) : grid->n;
     h->n_rot = n_rot;
     h->n_poses = n_poses;
     h->nv = mesh->n_vertices;
@@ -768,7 +784,7 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
     h->H = spectrum_elems(h->n);
     h->batch = h->prm.batch > 0 ? (h->prm.batch + 7) / 8 * 8 : default_batch(h->n, h->H, n_rot);
     {
-        const int rc = resolve_schedule(h->n, h->prm, h->sched);
+        const int rc = resolve_schedule(h->n, h->prm, h->sched, h->split);
         if (rc) return rc;
     }
     h->stream = (hipStream_t)hip_stream;  // NULL: the null stream
@@ -839,8 +855,12 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
         ALLOC_TRY(h, h->opar, (size_t)h->n * h->n * ((h->n + 31) / 32));
     }
     ALLOC_TRY(h, h->spec, h->H * (size_t)h->batch);
-    ALLOC_TRY(h, h->ptop, (size_t)h->batch * h->n * KREC);
-    ALLOC_TRY(h, h->pssq, (size_t)h->batch * h->n);
+    ALLOC_TRY(h, h->ptop, (size_t)h->batch * h->units * KREC);
+    ALLOC_TRY(h, h->pssq, (size_t)h->batch * h->units);
+    if (h->split) {
+        ALLOC_TRY(h, h->xbuf, split_plane_elems(h->n) * (size_t)h->batch);
+        ALLOC_TRY(h, h->lowrow, (size_t)h->n * h->n * NLX * (size_t)h->batch);
+    }
     ALLOC_TRY(h, h->stats, 5);
     ALLOC_TRY(h, h->need_count, 1);
     ALLOC_TRY(h, h->Sw, m3);
@@ -849,8 +869,12 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
     ALLOC_TRY(h, h->Plow, (size_t)h->batch * NLOW3);
     if (n_rot > h->batch && h->sched.lanes > 1) {  // a call can span two batches: the second lane
         ALLOC_TRY(h, h->spec2, h->H * (size_t)h->batch);
-        ALLOC_TRY(h, h->ptop2, (size_t)h->batch * h->n * KREC);
-        ALLOC_TRY(h, h->pssq2, (size_t)h->batch * h->n);
+        ALLOC_TRY(h, h->ptop2, (size_t)h->batch * h->units * KREC);
+        ALLOC_TRY(h, h->pssq2, (size_t)h->batch * h->units);
+        if (h->split) {
+            ALLOC_TRY(h, h->xbuf2, split_plane_elems(h->n) * (size_t)h->batch);
+            ALLOC_TRY(h, h->lowrow2, (size_t)h->n * h->n * NLX * (size_t)h->batch);
+        }
         ALLOC_TRY(h, h->lowT2, (size_t)h->batch * h->n * NLOW2);
         ALLOC_TRY(h, h->Plow2, (size_t)h->batch * NLOW3);
         DEV_TRY(h, hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking));
@@ -1393,6 +1417,9 @@ static int enqueue_batch(reg_handle* h, int b0, int cnt, int lane, hipStream_t l
     a.Plow = odd ? h->Plow2 : h->Plow;
     a.ptop = odd ? h->ptop2 : h->ptop;
     a.pssq = odd ? h->pssq2 : h->pssq;
+    a.units = h->units;
+    a.xbuf = odd ? h->xbuf2 : h->xbuf;
+    a.lowrow = odd ? h->lowrow2 : h->lowrow;
     a.corr_out = corr_out;
     a.pv1 = h->sched.pv1;
     a.pv3 = h->sched.pv3;
@@ -1726,6 +1753,7 @@ int register_autotune(reg_handle* h, int32_t max_rotations, int32_t* out_batch) 
     g_err.clear();
     if (!h || !out_batch) return fail(REG_EINVAL, "NULL argument");
     if (h->poisoned) return fail(REG_EDEVICE, "handle poisoned by an earlier device error");
+    if (h->split) return fail(REG_ENOTSUP, "the split plane passes have no workgroup variants to tune");
     int b = 0;
     int rc = autotune_impl(h, max_rotations, &b);
     if (rc) return rc;
@@ -1883,7 +1911,8 @@ int enqueue_search_finish(reg_handle* h, float* out_score, int32_t* out_shift, d
 
 size_t object_bytes(const ObjectData* o) { return o ? o->bytes : 0; }
 
-Footprint footprint(int n, int n_rot, int n_poses, int nv, int nf, int batch, int refine_starts, int rotate_object) {
+Footprint footprint(int n, int n_rot, int n_poses, int nv, int nf, int batch, int refine_starts, int rotate_object,
+                    int split_plane) {
     const size_t n3 = (size_t)n * n * n, H = spectrum_elems(n);
     const size_t m = (size_t)lattice_edge(n), mp = (m + 3) / 4 * 4;
     const size_t B = (size_t)batch, M = (size_t)n_rot, N = (size_t)n_poses;
@@ -1899,6 +1928,10 @@ Footprint footprint(int n, int n_rot, int n_poses, int nv, int nf, int batch, in
                 K * (sizeof(RefineState) + sizeof(LbfgsState) +
                      REF_TMAX * (sizeof(RefineTrial) + REF_EVAL_PARTS * sizeof(RefineEval))) +
                 nq * (sizeof(RefineHit) + 48 + 8 + 4 + 8 + 16 * (8 + 16 + 4)) + 4096;
+    if (split_plane || !fused_supported(n)) {  // the plane buffers and row sums of each lane; more peak records
+        const size_t units = (size_t)split_units(n);
+        f.request += lanes * B * (split_plane_elems(n) * 8 + (size_t)n * n * NLX * 16 + (units - n) * (KREC * 8 + 8));
+    }
     if (rotate_object)  // build_rotated_object: classes, records, S and its spectrum, the lattice build's scratch
         f.request += 33 * mp * mp * mp + 4 * n3 + 8 * H + 16 * (size_t)NLOW3 + 8 * n3 + 8 * ((n3 + 255) / 256) +
                      24 * m * m * m + m * m * ((m + 31) / 32) * 4;

@@ -44,7 +44,7 @@ struct Footprint {
     size_t object = 0, request = 0;
 };
 Footprint footprint(int n, int n_rot, int n_poses, int n_vertices, int n_faces, int batch, int refine_starts,
-                    int rotate_object = 0);
+                    int rotate_object = 0, int split_plane = 0);
 int default_batch_for(int n, int n_rot);
 
 // the calling thread's last error message

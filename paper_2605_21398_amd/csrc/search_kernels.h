@@ -52,6 +52,12 @@ struct SearchBatchArgs {
     // rots then hold R^T.  NULL: corner masks of the binary swept lattice.
     const float4* crec = nullptr;
     float cval = 0.0f;
+    // peak records per rotation in ptop / pssq (0: n, one per plane)
+    int units = 0;
+    // split plane passes: the plane buffer [count][n][n][n/2] and the rows'
+    // x sums of the low block [count][n][n][NLX]; NULL selects the fused passes
+    float2* xbuf = nullptr;
+    double2* lowrow = nullptr;
 };
 
 // Schedule variants (threads and waves per SIMD of the plane workgroups;
@@ -66,6 +72,10 @@ int plane_variant_threads(int v);
 int z_variant_threads(int v);
 
 bool canvas_supported(int n);
+bool fused_supported(int n);   // the plane fits one workgroup's LDS (edges up to 180)
+bool split_supported(int n);   // split plane passes compiled (64, 128, 192, 256, 360)
+int split_units(int n);        // peak records per rotation of the split passes
+size_t split_plane_elems(int n);  // complex per rotation of the split passes' plane buffer
 int rescore_slices(int n);
 size_t spectrum_elems(int n);
 int tile_width(int n);
@@ -73,7 +83,8 @@ int tile_width(int n);
 // pass 0: rotate+voxelise+FFT xy; 1: z FFT * W * z IFFT; 2: IFFT yx + argmax
 hipError_t search_pass(int n, int pass, const SearchBatchArgs& a);
 hipError_t object_spectrum(int n, const float* O, float2* spec_tmp, float2* W, const float2* tw, const double2* tw64,
-                           double2* lowT_tmp, double2* Wlow, hipStream_t s);
+                           double2* lowT_tmp, double2* Wlow, hipStream_t s, float2* xbuf = nullptr,
+                           double2* lowrow = nullptr);
 hipError_t setup_anchor(const float* V, int nv, double* anchor, hipStream_t s);
 // scratch of the object-grid build: squared distances (double bits, n^3 each)
 // and the inside-parity bit words of every column (n^2 * ceil(n/32))
@@ -111,7 +122,7 @@ struct PeakArrays {
 };
 // what the exact re-score reads
 struct RescoreInputs {
-    const uint32_t* nz_idx;  // nonzero voxels of the fixed grid (O; S when O rotates): kx | ky << 8 | kz << 16
+    const uint32_t* nz_idx;  // nonzero voxels of the fixed grid (O; S when O rotates): kx | ky << 10 | kz << 20
     const float* nz_val;
     const int* nz_count;
     const uint8_t* cmask;

@@ -55,6 +55,9 @@ namespace regdock {
 
 // ------------------------------------------------------------ canvas traits
 
+// index field of the peak keys (see key64): canvases up to 2^26 voxels
+constexpr int FLAT_BITS_MAX = 26;
+
 __host__ __device__ constexpr int largest_divisor_le(int v, int cap) {
     for (int d = cap; d >= 1; --d)
         if (v % d == 0) return d;
@@ -69,24 +72,39 @@ __host__ __device__ constexpr int lattice_edge_of(int n) {
     return m;
 }
 
-template <int N> struct Canvas {
+// Sizes of an edge-N canvas shared by every search path: the half spectrum,
+// its pencil tiles and the swept lattice.
+template <int N> struct Dims {
     static constexpr int N2 = N / 2;
     static constexpr int M = lattice_edge_of(N);          // swept lattice edge
-    static constexpr int P = N2 + 1;                      // LDS row pitch (complex)
+    static constexpr int P = N2 + 1;                      // row pitch (complex)
     static constexpr int T = largest_divisor_le(N2, 16);  // tile width (complex)
     static constexpr int NT2 = N2 / T;                    // main tiles per ky row
     static constexpr int TILES = N * NT2 + N / T;         // tiles per rotation
     static constexpr size_t H = (size_t)N * P * N;        // complex per rotation
+    static_assert(N % 2 == 0 && N % T == 0, "canvas edge must be even and tile the Nyquist column");
+    static_assert(fft_supported(N) && fft_supported(N2), "edge must be 2^a 3^b 5^c");
+    static_assert((size_t)N * N * N <= (1u << FLAT_BITS_MAX),
+                  "flat indices must fit the index field of the peak keys");
+};
+
+// The fused plane passes: a whole plane in the LDS of one workgroup.
+template <int N> struct Canvas : Dims<N> {
+    using D = Dims<N>;
+    using D::N2;
+    using D::M;
+    using D::P;
+    using D::T;
+    using D::NT2;
+    using D::TILES;
+    using D::H;
     // threads of a plane workgroup: from 96^3 up the plane fills enough LDS
     // that only one to three workgroups fit per CU, and workgroups of 8 (16
     // above 128^3, where one fits) waves give each SIMD more waves to hide LDS
     // and barrier latency
     static constexpr int NT = N > 128 ? 1024 : N >= 96 ? 512 : 256;
     static constexpr int WPE = N >= 96 ? 4 : 1;  // waves per SIMD asked of the compiler
-    static_assert(N % 2 == 0, "canvas edge must be even");
-    static_assert(fft_supported(N) && fft_supported(N2), "edge must be 2^a 3^b 5^c");
     static_assert((size_t)N * P * 8 <= 160 * 1024, "plane must fit in LDS");
-    static_assert((size_t)N * N * N <= (1u << 23), "flat indices must fit the 23-bit field of the peak keys");
 };
 
 // Workgroup -> (rotation, plane).  Workgroups are dealt round-robin to the 8
@@ -203,9 +221,9 @@ struct RegStage {
 //   X[k] = ((Z[k] + conj Z[N/2-k]) - i w^k (Z[k] - conj Z[N/2-k])) / 2.
 // X[0] and X[N/2] are real; both go to slot 0 as X[0] + i X[N/2], so that the
 // y transform runs over n/2 columns (unpack_nyquist splits the result).
-template <int N, int NT>
+template <int N, int NT, int ROWS = N>
 __device__ __forceinline__ void r2c_post(float2* plane, const float2* tw) {
-    using C = Canvas<N>;
+    using C = Dims<N>;
     constexpr int Q = C::N2 / 2 + 1;  // pairs (k, N/2 - k), k in [0, N/4]
     constexpr int R = NT / Q;         // rows per step: thread t keeps k = t % Q and its twiddles
     static_assert(R >= 1, "a plane workgroup covers the pairs of a row");
@@ -213,7 +231,7 @@ __device__ __forceinline__ void r2c_post(float2* plane, const float2* tw) {
     if (t < R * Q) {
         const int k = t % Q, kk = C::N2 - k;
         const float2 wk = tw[k], wkk = tw[kk];
-        for (int y = t / Q; y < N; y += R) {
+        for (int y = t / Q; y < ROWS; y += R) {
             float2* row = plane + y * C::P;
             if (k == 0) {
                 const float2 z0 = row[0];
@@ -241,9 +259,9 @@ __device__ __forceinline__ void r2c_post(float2* plane, const float2* tw) {
 //   Z[k] = (X[k] + conj X[N/2-k]) + i conj(w^k) (X[k] - conj X[N/2-k]).
 // Slot 0 holds x[0] + i x[N/2] (pack_nyquist before the y transform), both
 // real after it.
-template <int N, int NT>
+template <int N, int NT, int ROWS = N>
 __device__ __forceinline__ void c2r_pre(float2* plane, const float2* tw) {
-    using C = Canvas<N>;
+    using C = Dims<N>;
     constexpr int Q = C::N2 / 2 + 1;
     constexpr int R = NT / Q;
     static_assert(R >= 1, "a plane workgroup covers the pairs of a row");
@@ -251,7 +269,7 @@ __device__ __forceinline__ void c2r_pre(float2* plane, const float2* tw) {
     if (t < R * Q) {
         const int k = t % Q, kk = C::N2 - k;
         const float2 wk = tw[k], wkk = tw[kk];
-        for (int y = t / Q; y < N; y += R) {
+        for (int y = t / Q; y < ROWS; y += R) {
             float2* row = plane + y * C::P;
             const float2 a = k == 0 ? make_float2(row[0].x, 0.0f) : row[k];
             const float2 b = k == 0 ? make_float2(row[0].y, 0.0f) : row[kk];
@@ -364,12 +382,12 @@ __device__ __forceinline__ int low_slot(int y, int kx) {
     static_assert(NLX == 4, "the rotation assumes four kx entries per row");
     return y * NLX + ((kx + (y >> 2)) & 3);
 }
-template <int N, int NT>
-__device__ __forceinline__ void plane_low_dft(const float2* plane, const double2* tw64, double2* rbuf,
-                                              double2* __restrict__ out) {
-    using C = Canvas<N>;
-    static_assert(N <= NT, "one row task set per pass");
-    constexpr int CH = pow2floor(NT / N);  // lanes per row, a power of two
+// x direction for ROWS rows of pitch N/2 + 1 (rbuf rows local to the block)
+template <int N, int NT, int ROWS>
+__device__ __forceinline__ void low_rows_x(const float2* plane, const double2* tw64, double2* rbuf) {
+    using C = Dims<N>;
+    static_assert(ROWS <= NT, "one row task set per pass");
+    constexpr int CH = pow2floor(NT / ROWS) < 64 ? pow2floor(NT / ROWS) : 64;  // lanes per row, a power of two
     constexpr int JC = (C::N2 + CH - 1) / CH;
     // A wave takes RPW consecutive rows: lane l reads row l % RPW, chunk
     // l / RPW.  The lanes that read together (a half wave) then take distinct
@@ -377,10 +395,10 @@ __device__ __forceinline__ void plane_low_dft(const float2* plane, const double2
     // of one row, which at n = 128 start 16 elements (32 banks of 4 bytes)
     // apart and hit the same banks.
     constexpr int RPW = 64 / CH;
-    static_assert(CH <= 64 && ((N + RPW - 1) / RPW) * 64 <= NT, "low-block x pass layout");
+    static_assert(CH <= 64 && ((ROWS + RPW - 1) / RPW) * 64 <= NT, "low-block x pass layout");
     const int t = threadIdx.x;
     const int y = (t >> 6) * RPW + (t & 63) % RPW, c = (t & 63) / RPW;
-    if (y < N) {
+    if (y < ROWS) {
         const int j0 = c * JC, j1 = min(C::N2, j0 + JC);
         double coef[NLX], s1[NLX], s2[NLX];
         double sum0 = 0.0;
@@ -425,7 +443,12 @@ __device__ __forceinline__ void plane_low_dft(const float2* plane, const double2
 #pragma unroll
             for (int k = 0; k < NLX; ++k) rbuf[low_slot(y, k)] = acc[k];
     }
-    __syncthreads();
+}
+
+// y direction from the row sums of all N rows of a plane
+template <int N, int NT>
+__device__ __forceinline__ void low_cols_y(const double2* rbuf, const double2* tw64, double2* __restrict__ out) {
+    const int t = threadIdx.x;
     // y direction: CB lanes per (kx, ky) (CB a power of two, at most 16, with
     // NLOW2 CB <= NT), lane c taking rows c, c + CB, ...; a shuffle tree adds
     // the CB parts
@@ -451,6 +474,15 @@ __device__ __forceinline__ void plane_low_dft(const float2* plane, const double2
         part.y += __shfl_xor(part.y, off, 64);
     }
     if (t < NLOW2 * CB && (t % CB) == 0) out[t / CB] = part;
+}
+
+// the whole plane: x sums of every row, then the y direction
+template <int N, int NT>
+__device__ __forceinline__ void plane_low_dft(const float2* plane, const double2* tw64, double2* rbuf,
+                                              double2* __restrict__ out) {
+    low_rows_x<N, NT, N>(plane, tw64, rbuf);
+    __syncthreads();
+    low_cols_y<N, NT>(rbuf, tw64, out);
 }
 
 // S_r at canvas voxel (x, y, z) for rotation R: u = R (k - N/2) + m/2 in double
@@ -553,7 +585,8 @@ __device__ __forceinline__ float trilinear_poly(const float4* lut, uint32_t mk, 
     return fmaf(fmaf(yz, Y, zc), Z, fmaf(yc, Y, c0));
 }
 
-// Fill the LDS plane with z[j] = S_r[2j] + i S_r[2j+1] for plane z.  The
+// Fill the LDS plane with z[j] = S_r[2j] + i S_r[2j+1] for plane z (rows
+// ybase .. ybase + ROWS - 1 of it, local row r at plane[r (n/2 + 1)]).  The
 // corner-mask loads of several elements are issued together before any is
 // used, so each lane keeps many gathers in flight.
 //
@@ -573,20 +606,20 @@ __device__ __forceinline__ float trilinear_poly(const float4* lut, uint32_t mk, 
 // three per-axis table entries (bax[ix] + bay[iy] + baz[iz], see
 // build_brick_tables), three LDS reads in place of the shifts, masks and
 // multiplies of brick_index.
-template <int N, int NT>
+template <int N, int NT, int ROWS = N>
 __device__ __forceinline__ void generate_plane(float2* plane, const float4* lut, const uint32_t* bax,
                                                const uint32_t* bay, const uint32_t* baz, const RotSampler& rs,
-                                               const uint8_t* __restrict__ cmask, int z) {
-    using C = Canvas<N>;
+                                               const uint8_t* __restrict__ cmask, int z, int ybase = 0) {
+    using C = Dims<N>;
     static_assert(C::N2 <= NT, "a plane workgroup covers every column pair");
     constexpr int YS = NT / C::N2;  // row step of a lane (YS * N2 lanes work, the rest idle)
     constexpr int G = 8;               // rows per batch of loads
     const int j = threadIdx.x % C::N2, y0 = threadIdx.x / C::N2;
-    if (threadIdx.x >= YS * C::N2 || y0 >= N) return;
+    if (threadIdx.x >= YS * C::N2 || y0 >= ROWS) return;
     const double two32 = 4294967296.0;
     long long U[2][3], D[3];
     {
-        const double yc = (double)y0 - rs.hn, zc = (double)z - rs.hn;
+        const double yc = (double)(ybase + y0) - rs.hn, zc = (double)z - rs.hn;
         for (int s2 = 0; s2 < 2; ++s2) {
             const double xc = (double)(2 * j + s2) - rs.hn;
             U[s2][0] = __double2ll_rn(fma(rs.r00, xc, fma(rs.r01, yc, fma(rs.r02, zc, rs.hm))) * two32);
@@ -597,7 +630,7 @@ __device__ __forceinline__ void generate_plane(float2* plane, const float4* lut,
         D[1] = __double2ll_rn((double)YS * rs.r11 * two32);
         D[2] = __double2ll_rn((double)YS * rs.r21 * two32);
     }
-    for (int y = y0; y < N; y += YS * G) {
+    for (int y = y0; y < ROWS; y += YS * G) {
         uint32_t addr[2 * G];
         float fx[2 * G], fy[2 * G], fz[2 * G];
 #pragma unroll
@@ -619,13 +652,13 @@ __device__ __forceinline__ void generate_plane(float2* plane, const float4* lut,
         uint32_t mk[2 * G];
 #pragma unroll
         for (int q = 0; q < 2 * G; ++q) {
-            const bool live = (N % (YS * G) == 0) || y + (q / 2) * YS < N;
+            const bool live = (ROWS % (YS * G) == 0) || y + (q / 2) * YS < ROWS;
             mk[q] = live ? (uint32_t)cmask[addr[q]] : 0u;
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int yy = y + g * YS;
-            if ((N % (YS * G) == 0) || yy < N)
+            if ((ROWS % (YS * G) == 0) || yy < ROWS)
                 plane[yy * C::P + j] = make_float2(trilinear_poly(lut, mk[2 * g], fx[2 * g], fy[2 * g], fz[2 * g]),
                                                    trilinear_poly(lut, mk[2 * g + 1], fx[2 * g + 1], fy[2 * g + 1],
                                                                   fz[2 * g + 1]));
@@ -795,7 +828,7 @@ __global__ __launch_bounds__(Canvas<N>::NT, Canvas<N>::WPE) void k_grid_fwd_xy(c
 template <int N, int MODE, int ZT>
 __global__ __launch_bounds__(ZT) void k_zpass(float2* __restrict__ spec, const float2* __restrict__ W, float2* __restrict__ wout,
                                                const float2* __restrict__ twg, float scale) {
-    using C = Canvas<N>;
+    using C = Dims<N>;
     constexpr int E = N * C::T;
     constexpr int PER = (E + ZT - 1) / ZT;
     __shared__ float2 buf[E];
@@ -862,9 +895,9 @@ __global__ __launch_bounds__(ZT) void k_zpass(float2* __restrict__ spec, const f
 // its error could exceed the tolerance.
 
 // key = orderable bits of a double, low FLAT_BITS bits replaced by ~flat
-// (flat < 2^FLAT_BITS = 8,388,608 > 180^3); the value keeps 52 - FLAT_BITS
-// mantissa bits (relative truncation below 2^-29, under float32's rounding)
-constexpr int FLAT_BITS = 23;
+// (flat < 2^FLAT_BITS = 67,108,864 > 400^3); the value keeps 52 - FLAT_BITS
+// mantissa bits (relative truncation below 2^-26, under float32's rounding)
+constexpr int FLAT_BITS = FLAT_BITS_MAX;
 constexpr unsigned long long FLAT_MASK = (1ull << FLAT_BITS) - 1;
 __device__ __forceinline__ unsigned long long key64(double v, uint32_t flat) {
     unsigned long long b = (unsigned long long)__double_as_longlong(v);
@@ -878,85 +911,15 @@ __device__ __forceinline__ double key_value(unsigned long long k) {
 }
 __device__ __forceinline__ uint32_t key_flat(unsigned long long k) { return (uint32_t)(FLAT_MASK - (k & FLAT_MASK)); }
 
-template <int N, int NT, int WPE>
-__global__ __launch_bounds__(NT, WPE) void k_inv_xy_argmax(const float2* __restrict__ spec, int count, const float2* __restrict__ twg,
-                                                       const double2* __restrict__ tw64, const double2* __restrict__ Plow,
-                                                       unsigned long long* __restrict__ ptop, double* __restrict__ pssq,
-                                                       float* __restrict__ corr_out) {
-    using C = Canvas<N>;
-    constexpr int NW = NT / 64;
-    __shared__ float2 plane[N * C::P];
-    __shared__ float2 tw[N];
-    __shared__ double2 btab[N * NLX];
-    __shared__ double2 az[NLOW2];
-    __shared__ double2 tws[N];
-    __shared__ unsigned long long wtop[NW][KTOP + 1];
-    __shared__ double wss[NW];
-    __shared__ double wsec[NW];
-    static_assert(N <= NT && NLOW2 <= NT, "one twiddle and one low-block row per thread at most");
-    int rot, z;
-    map_plane_block(blockIdx.x, count, N, rot, z);
-    // every global load of the plane is issued before the first is waited for:
-    // the twiddles, this thread's row of the low-block product, the spectrum
-    const int tid = threadIdx.x;
-    float2 twv;
-    double2 tw64v;
-    if (tid < N) {
-        twv = twg[tid];
-        tw64v = tw64[tid];
-    }
-    double2 pz[NLY];
-    if (tid < NLOW2) {
-        const double2* P = Plow + (size_t)rot * NLOW3 + tid * NLY;
-#pragma unroll
-        for (int kzi = 0; kzi < NLY; ++kzi) pz[kzi] = P[kzi];
-    }
-    const float2* spec_rot = spec + (size_t)rot * C::H;
-    RegStage<N * C::N2, NT> st_main;
-    RegStage<N, NT> st_nyq;
-    st_main.load([&](int e) {
-        const int ky = e / C::N2, kx = e % C::N2;
-        return spec_rot[((size_t)(ky * C::NT2 + kx / C::T) * N + z) * C::T + (kx % C::T)];
-    });
-    const float2* nyq = spec_rot + (size_t)N * C::N2 * N;
-    st_nyq.load([&](int ky) { return nyq[((size_t)(ky / C::T) * N + z) * C::T + (ky % C::T)]; });
-    if (tid < N) {
-        tw[tid] = twv;
-        tws[tid] = tw64v;
-    }
-    st_main.store([&](int e, float2 v) { plane[(e / C::N2) * C::P + e % C::N2] = v; });
-    st_nyq.store([&](int ky, float2 v) { plane[ky * C::P + C::N2] = v; });
-    __syncthreads();
-    // low block of this plane: az[kx][ky] = sum_kz P[kx][ky][kz] e^{+2 pi i kz z / N}
-    if (tid < NLOW2) {
-        double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int kzi = 0; kzi < NLY; ++kzi) {
-            const double2 t = dcmulc(pz[kzi], tws[mod_n((kzi - KLOW) * z, N)]);
-            acc.x += t.x;
-            acc.y += t.y;
-        }
-        az[tid] = acc;
-    }
-    // az is complete before the barrier that ends pack_nyquist and is read
-    // only after it
-    pack_nyquist<N, NT>(plane);
-    fft_lds<N, true, C::N2, NT, true, N>(plane, C::P, 1, tw);
-    // btab[y][kx] = sum_ky az[kx][ky] e^{+2 pi i ky y / N}, doubled for kx > 0
-    // (the field sums Re b_0 + 2 sum_kx Re(b_kx e^{+2 pi i kx x / N}))
-    for (int t = threadIdx.x; t < N * NLX; t += NT) {
-        const int y = t / NLX, kx = t % NLX;
-        double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int kyi = 0; kyi < NLY; ++kyi) {
-            const double2 v = dcmulc(az[kx * NLY + kyi], tws[mod_n((kyi - KLOW) * y, N)]);
-            acc.x += v.x;
-            acc.y += v.y;
-        }
-        btab[t] = kx > 0 ? make_double2(2.0 * acc.x, 2.0 * acc.y) : acc;
-    }
-    c2r_pre<N, NT>(plane, tw);
-    fft_lds<C::N2, true, N, NT, true, N>(plane, 1, C::P, tw);
+// Scan of ROWS field rows (rows y0 .. y0 + ROWS - 1 of plane z; local row r
+// at rows[r * (n/2 + 1)], its low-block row at btab[r * NLX]) and the merges
+// of the lanes' and waves' maxima: one record of KTOP keys and the bound to
+// o, the rows' sum of squares to ss_out.
+template <int N, int NT, int ROWS>
+__device__ __forceinline__ void scan_rows(const float2* rows, const double2* btab, const double2* tws, int z, int y0,
+                                          unsigned long long (*wtop)[KTOP + 1], double* wss, double* wsec,
+                                          unsigned long long* __restrict__ o, double* __restrict__ ss_out,
+                                          float* __restrict__ corr_out) {
     // Every working lane keeps the same columns x = 2j, 2j+1 (YS n/2 lanes
     // work, the rest idle), so its low-block phases live in registers.  Each
     // column of a lane ("virtual lane": x fixed, rows y0, y0 + YS, ...) keeps
@@ -966,6 +929,8 @@ __global__ __launch_bounds__(NT, WPE) void k_inv_xy_argmax(const float2* __restr
     // fifth-best virtual-lane maximum and every virtual lane's second value.
     // No voxel outside the four keys exceeds the bound, so a candidate window
     // that the bound does not reach holds only those keys.
+    using C = Dims<N>;
+    constexpr int NW = NT / 64;
     static_assert(C::N2 <= NT, "a plane workgroup covers every column pair");
     constexpr int YS = NT / C::N2;
     const int j = threadIdx.x % C::N2;
@@ -978,10 +943,11 @@ __global__ __launch_bounds__(NT, WPE) void k_inv_xy_argmax(const float2* __restr
     double m1a = -INFINITY, m2a = -INFINITY, m1b = -INFINITY, m2b = -INFINITY;
     int ya = -1, yb = -1;
     float ss = 0.0f;
-    const int ystart = threadIdx.x < YS * C::N2 ? threadIdx.x / C::N2 : N;
-    for (int y = ystart; y < N; y += YS) {
-        const float2 v = plane[y * C::P + j];
-        const double2* b = btab + y * NLX;
+    const int ystart = threadIdx.x < YS * C::N2 ? threadIdx.x / C::N2 : ROWS;
+    for (int yl = ystart; yl < ROWS; yl += YS) {
+        const int y = y0 + yl;
+        const float2 v = rows[yl * C::P + j];
+        const double2* b = btab + yl * NLX;
         double c0 = b[0].x, c1 = b[0].x;
 #pragma unroll
         for (int k = 1; k < NLX; ++k) {
@@ -1073,13 +1039,95 @@ __global__ __launch_bounds__(NT, WPE) void k_inv_xy_argmax(const float2* __restr
         }
         if (l == 0) {
             if (b[KTOP]) bound = fmax(bound, key_value(b[KTOP]));
-            unsigned long long* o = ptop + ((size_t)rot * N + z) * KREC;
 #pragma unroll
             for (int r = 0; r < KTOP; ++r) o[r] = b[r];
             o[KTOP] = (unsigned long long)__double_as_longlong(bound);
-            pssq[(size_t)rot * N + z] = tot;
+            *ss_out = tot;
         }
     }
+}
+
+template <int N, int NT, int WPE>
+__global__ __launch_bounds__(NT, WPE) void k_inv_xy_argmax(const float2* __restrict__ spec, int count, const float2* __restrict__ twg,
+                                                       const double2* __restrict__ tw64, const double2* __restrict__ Plow,
+                                                       unsigned long long* __restrict__ ptop, double* __restrict__ pssq,
+                                                       float* __restrict__ corr_out) {
+    using C = Canvas<N>;
+    constexpr int NW = NT / 64;
+    __shared__ float2 plane[N * C::P];
+    __shared__ float2 tw[N];
+    __shared__ double2 btab[N * NLX];
+    __shared__ double2 az[NLOW2];
+    __shared__ double2 tws[N];
+    __shared__ unsigned long long wtop[NW][KTOP + 1];
+    __shared__ double wss[NW];
+    __shared__ double wsec[NW];
+    static_assert(N <= NT && NLOW2 <= NT, "one twiddle and one low-block row per thread at most");
+    int rot, z;
+    map_plane_block(blockIdx.x, count, N, rot, z);
+    // every global load of the plane is issued before the first is waited for:
+    // the twiddles, this thread's row of the low-block product, the spectrum
+    const int tid = threadIdx.x;
+    float2 twv;
+    double2 tw64v;
+    if (tid < N) {
+        twv = twg[tid];
+        tw64v = tw64[tid];
+    }
+    double2 pz[NLY];
+    if (tid < NLOW2) {
+        const double2* P = Plow + (size_t)rot * NLOW3 + tid * NLY;
+#pragma unroll
+        for (int kzi = 0; kzi < NLY; ++kzi) pz[kzi] = P[kzi];
+    }
+    const float2* spec_rot = spec + (size_t)rot * C::H;
+    RegStage<N * C::N2, NT> st_main;
+    RegStage<N, NT> st_nyq;
+    st_main.load([&](int e) {
+        const int ky = e / C::N2, kx = e % C::N2;
+        return spec_rot[((size_t)(ky * C::NT2 + kx / C::T) * N + z) * C::T + (kx % C::T)];
+    });
+    const float2* nyq = spec_rot + (size_t)N * C::N2 * N;
+    st_nyq.load([&](int ky) { return nyq[((size_t)(ky / C::T) * N + z) * C::T + (ky % C::T)]; });
+    if (tid < N) {
+        tw[tid] = twv;
+        tws[tid] = tw64v;
+    }
+    st_main.store([&](int e, float2 v) { plane[(e / C::N2) * C::P + e % C::N2] = v; });
+    st_nyq.store([&](int ky, float2 v) { plane[ky * C::P + C::N2] = v; });
+    __syncthreads();
+    // low block of this plane: az[kx][ky] = sum_kz P[kx][ky][kz] e^{+2 pi i kz z / N}
+    if (tid < NLOW2) {
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int kzi = 0; kzi < NLY; ++kzi) {
+            const double2 t = dcmulc(pz[kzi], tws[mod_n((kzi - KLOW) * z, N)]);
+            acc.x += t.x;
+            acc.y += t.y;
+        }
+        az[tid] = acc;
+    }
+    // az is complete before the barrier that ends pack_nyquist and is read
+    // only after it
+    pack_nyquist<N, NT>(plane);
+    fft_lds<N, true, C::N2, NT, true, N>(plane, C::P, 1, tw);
+    // btab[y][kx] = sum_ky az[kx][ky] e^{+2 pi i ky y / N}, doubled for kx > 0
+    // (the field sums Re b_0 + 2 sum_kx Re(b_kx e^{+2 pi i kx x / N}))
+    for (int t = threadIdx.x; t < N * NLX; t += NT) {
+        const int y = t / NLX, kx = t % NLX;
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int kyi = 0; kyi < NLY; ++kyi) {
+            const double2 v = dcmulc(az[kx * NLY + kyi], tws[mod_n((kyi - KLOW) * y, N)]);
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+        btab[t] = kx > 0 ? make_double2(2.0 * acc.x, 2.0 * acc.y) : acc;
+    }
+    c2r_pre<N, NT>(plane, tw);
+    fft_lds<C::N2, true, N, NT, true, N>(plane, 1, C::P, tw);
+    scan_rows<N, NT, N>(plane, btab, tws, z, 0, wtop, wss, wsec, ptop + ((size_t)rot * N + z) * KREC,
+                        pssq + (size_t)rot * N + z, corr_out);
 }
 
 // Per rotation (absolute index base + block): the field maximum v (double,
@@ -1090,7 +1138,7 @@ __global__ __launch_bounds__(NT, WPE) void k_inv_xy_argmax(const float2* __restr
 // plane besides its keys exceeds it) reaches the window, the plane may hold
 // more: the rotation is marked as overflowed.
 __global__ __launch_bounds__(256) void k_select(const unsigned long long* __restrict__ ptop, const double* __restrict__ pssq,
-                                                int n, double eps_per_rms, int base, int32_t* __restrict__ cand_idx,
+                                                int n, int units, double eps_per_rms, int base, int32_t* __restrict__ cand_idx,
                                                 int32_t* __restrict__ cand_n, double* __restrict__ window,
                                                 uint8_t* __restrict__ ovf, double* __restrict__ best_val,
                                                 int32_t* __restrict__ best_flat, int* __restrict__ stats) {
@@ -1101,14 +1149,14 @@ __global__ __launch_bounds__(256) void k_select(const unsigned long long* __rest
     __shared__ unsigned long long list[CMAX];
     __shared__ int overflow;
     const int rot = blockIdx.x, r = base + blockIdx.x;
-    const unsigned long long* T = ptop + (size_t)rot * n * KREC;
-    // the best key and the sum of the planes' sums of squares (a fixed
-    // shuffle tree per wave, then the four waves in order)
+    const unsigned long long* T = ptop + (size_t)rot * units * KREC;
+    // the best key and the sum of the units' (planes' or row blocks') sums of
+    // squares (a fixed shuffle tree per wave, then the four waves in order)
     unsigned long long mx = 0;
     double ss = 0.0;
-    for (int zz = threadIdx.x; zz < n; zz += 256) {
+    for (int zz = threadIdx.x; zz < units; zz += 256) {
         mx = T[zz * KREC] > mx ? T[zz * KREC] : mx;
-        ss += pssq[(size_t)rot * n + zz];
+        ss += pssq[(size_t)rot * units + zz];
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -1141,7 +1189,7 @@ __global__ __launch_bounds__(256) void k_select(const unsigned long long* __rest
     }
     __syncthreads();
     const double thr = thr_s;
-    for (int i = threadIdx.x; i < n * KREC; i += 256) {
+    for (int i = threadIdx.x; i < units * KREC; i += 256) {
         const unsigned long long k = T[i];
         if (i % KREC == KTOP) {
             if (__longlong_as_double((long long)k) >= thr) overflow = 1;
@@ -1258,7 +1306,7 @@ __global__ __launch_bounds__(256) void k_rescore(const uint32_t* __restrict__ nz
         double acc = 0.0;
         for (int j = j0 + threadIdx.x; j < j1; j += 256) {
             const uint32_t k = nz_idx[j];
-            int x = (int)(k & 0xffu) + dx, y = (int)((k >> 8) & 0xffu) + dy, zz = (int)(k >> 16) + dz;
+            int x = (int)(k & 0x3ffu) + dx, y = (int)((k >> 10) & 0x3ffu) + dy, zz = (int)(k >> 20) + dz;
             x -= x >= n ? n : 0;
             y -= y >= n ? n : 0;
             zz -= zz >= n ? n : 0;
@@ -1288,36 +1336,43 @@ __global__ __launch_bounds__(256) void k_low_combine(const double2* __restrict__
     // are read from LDS.
     constexpr int HW = 256 / 32;
     constexpr int ZI = (N + HW - 1) / HW;  // planes per half wave
-    static_assert(NLOW2 <= 32 && N <= 256, "one (kx, ky) pair per lane of a half wave; one twiddle per thread");
+    constexpr int ZC = ZI < 16 ? ZI : 16;  // planes of a half wave loaded at once
+    static_assert(NLOW2 <= 32, "one (kx, ky) pair per lane of a half wave");
     __shared__ double2 red[HW][NLOW2][NLY];
     __shared__ double2 tws[N];
     const int rot = blockIdx.x, h = threadIdx.x >> 5, l = threadIdx.x & 31;
-    double2 v[ZI];
-    if (l < NLOW2) {
-        const double2* T = lowT + (size_t)rot * N * NLOW2 + l;
+    const double2* T = lowT + (size_t)rot * N * NLOW2 + l;
+    double2 acc[NLY];
 #pragma unroll
-        for (int i = 0; i < ZI; ++i) {
-            const int zz = h + i * HW;
-            v[i] = (N % HW == 0 || zz < N) ? T[(size_t)zz * NLOW2] : make_double2(0.0, 0.0);
-        }
-    }
-    if (threadIdx.x < N) tws[threadIdx.x] = tw64[threadIdx.x];
-    __syncthreads();
-    if (l < NLOW2) {
-        double2 acc[NLY];
+    for (int k = 0; k < NLY; ++k) acc[k] = make_double2(0.0, 0.0);
+    for (int c0 = 0; c0 < ZI; c0 += ZC) {
+        double2 v[ZC];
+        if (l < NLOW2) {
 #pragma unroll
-        for (int k = 0; k < NLY; ++k) acc[k] = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int i = 0; i < ZI; ++i) {
-            const int zz = h + i * HW;
-            if (N % HW != 0 && zz >= N) break;
-#pragma unroll
-            for (int k = 0; k < NLY; ++k) {
-                const double2 t = dcmul(v[i], tws[mod_n((k - KLOW) * zz, N)]);
-                acc[k].x += t.x;
-                acc[k].y += t.y;
+            for (int i = 0; i < ZC; ++i) {
+                const int zz = h + (c0 + i) * HW;
+                v[i] = (N % HW == 0 && ZI % ZC == 0) || zz < N ? T[(size_t)zz * NLOW2] : make_double2(0.0, 0.0);
             }
         }
+        if (c0 == 0) {
+            for (int i = threadIdx.x; i < N; i += 256) tws[i] = tw64[i];
+            __syncthreads();
+        }
+        if (l < NLOW2) {
+#pragma unroll
+            for (int i = 0; i < ZC; ++i) {
+                const int zz = h + (c0 + i) * HW;
+                if (!(N % HW == 0 && ZI % ZC == 0) && zz >= N) break;
+#pragma unroll
+                for (int k = 0; k < NLY; ++k) {
+                    const double2 t = dcmul(v[i], tws[mod_n((k - KLOW) * zz, N)]);
+                    acc[k].x += t.x;
+                    acc[k].y += t.y;
+                }
+            }
+        }
+    }
+    if (l < NLOW2) {
 #pragma unroll
         for (int k = 0; k < NLY; ++k) red[h][l][k] = acc[k];
     }
@@ -1470,7 +1525,7 @@ __global__ void k_nz_write(const float* __restrict__ O, size_t n3, int n, const 
     if (nz) {
         const int r = base + __popcll(b & ((1ull << lane) - 1ull));
         const uint32_t kx = (uint32_t)(id % n), ky = (uint32_t)((id / n) % n), kz = (uint32_t)(id / ((size_t)n * n));
-        idx[r] = kx | (ky << 8) | (kz << 16);
+        idx[r] = kx | (ky << 10) | (kz << 20);
         val[r] = v;
     }
 }
@@ -1835,6 +1890,234 @@ __global__ void k_validate(const float* __restrict__ V, int nv, const int32_t* _
     }
 }
 
+// ------------------------------------------------------ split plane passes
+//
+// For canvases whose plane does not fit the LDS of one workgroup (above 180^3;
+// also available at smaller edges, reg_params.split_plane), passes 1 and 3
+// each become a row pass and a column pass that meet in an HBM plane buffer
+// X (per rotation n planes of n rows of n/2 complex; slot 0 of a row holds
+// X0 + i X_{n/2} as in the fused passes):
+//   k_split_rows_fwd   per (rotation, plane, block of RB rows): the rows of
+//                      S_r (or of a real grid), their x sums of the exact low
+//                      block, the real-to-complex x FFT -> X
+//   k_split_cols_fwd   per (rotation, plane, tile of T columns): the y FFT of
+//                      the tile's columns -> the tiled spectrum; the tile of
+//                      column 0 splits X0 and X_{n/2} and finishes the plane's
+//                      low block along y
+//   k_split_cols_inv   per (rotation, plane, tile): inverse y FFT -> X
+//   k_split_rows_inv   per (rotation, plane, block of RB rows): complex-to-
+//                      real x FFT, the exact low field, the block's peak keys
+// The z pass, the low-block combine and the candidate selection are the fused
+// path's (one record of keys per row block instead of per plane).  A rotation
+// moves 6 H8 through HBM instead of 4 H8.
+template <int N> struct Split : Dims<N> {
+    using D = Dims<N>;
+    using D::N2;
+    using D::M;
+    using D::P;
+    using D::T;
+    using D::NT2;
+    static constexpr int RB = largest_divisor_le(N, 32);  // rows per row-pass workgroup
+    static constexpr int NB = N / RB;                     // row blocks per plane
+    // threads of a row-pass workgroup: every column pair busy, two rows at a time
+    static constexpr int RT = 2 * ((N2 + 63) / 64) * 64 < 128 ? 128 : 2 * ((N2 + 63) / 64) * 64;
+    static constexpr int CT = 256;                        // threads of a column-pass workgroup
+    static constexpr size_t XH = (size_t)N * N * N2;      // complex of X per rotation
+    static_assert(RT <= 512 && N2 <= RT && N2 / 2 + 1 <= RT, "row pass layout");
+};
+
+// SRC 0: the rotated swept grid from its corner masks; SRC 1: rows of a real
+// grid (the object grid O, no rotation)
+template <int N, int SRC>
+__global__ __launch_bounds__(Split<N>::RT) void k_split_rows_fwd(const uint8_t* __restrict__ cmask, int m, int mb,
+                                                             const double* __restrict__ rots,
+                                                             const float* __restrict__ grid,
+                                                             const float2* __restrict__ twg,
+                                                             const double2* __restrict__ tw64,
+                                                             float2* __restrict__ xb, double2* __restrict__ lowrow) {
+    using C = Split<N>;
+    constexpr int NT = C::RT, RB = C::RB;
+    __shared__ float2 rows[RB * C::P];
+    __shared__ float2 tw[N];
+    __shared__ double2 tws[N];
+    constexpr int RBB = RB * NLX * (int)sizeof(double2), LB = TRI_LUT * (int)sizeof(float4);
+    __shared__ __align__(16) unsigned char scratch_lds[SRC == 0 ? (RBB > LB ? RBB : LB) : RBB];
+    __shared__ uint32_t bax[SRC == 0 ? C::M : 1], bay[SRC == 0 ? C::M : 1], baz[SRC == 0 ? C::M : 1];
+    double2* rbuf = reinterpret_cast<double2*>(scratch_lds);
+    float4* lut = reinterpret_cast<float4*>(scratch_lds);
+    const int blk = blockIdx.x % C::NB, pl = blockIdx.x / C::NB;  // pl = rot * N + z
+    const int rot = pl / N, z = pl % N, y0 = blk * RB;
+    for (int i = threadIdx.x; i < N; i += NT) {
+        tw[i] = twg[i];
+        tws[i] = tw64[i];
+    }
+    if constexpr (SRC == 0) {
+        RotSampler rs;
+        rs.load(rots + rot * 9, m, N);
+        build_trilinear_lut<NT>(lut);
+        build_brick_tables<NT>(bax, bay, baz, C::M, mb);
+        __syncthreads();
+        generate_plane<N, NT, RB>(rows, lut, bax, bay, baz, rs, cmask, z, y0);
+    } else {
+        for (int e = threadIdx.x; e < RB * C::N2; e += NT) {
+            const int yl = e / C::N2, j = e % C::N2;
+            const float* row = grid + ((size_t)z * N + y0 + yl) * N;
+            rows[yl * C::P + j] = make_float2(row[2 * j], row[2 * j + 1]);
+        }
+    }
+    __syncthreads();
+    low_rows_x<N, NT, RB>(rows, tws, rbuf);
+    fft_lds<C::N2, false, RB, NT, true, N>(rows, 1, C::P, tw);
+    r2c_post<N, NT, RB>(rows, tw);
+    float2* dst = xb + ((size_t)pl * N + y0) * C::N2;
+    for (int e = threadIdx.x; e < RB * C::N2; e += NT) dst[e] = rows[(e / C::N2) * C::P + e % C::N2];
+    double2* lr = lowrow + ((size_t)pl * N + y0) * NLX;
+    for (int e = threadIdx.x; e < RB * NLX; e += NT) lr[e] = rbuf[low_slot(e / NLX, e % NLX)];
+}
+
+template <int N>
+__global__ __launch_bounds__(Split<N>::CT) void k_split_cols_fwd(const float2* __restrict__ xb,
+                                                             const double2* __restrict__ lowrow,
+                                                             const float2* __restrict__ twg,
+                                                             const double2* __restrict__ tw64,
+                                                             float2* __restrict__ spec, double2* __restrict__ lowT) {
+    using C = Split<N>;
+    constexpr int NT = C::CT, TT = C::T;
+    __shared__ float2 buf[N * TT];  // [y][c]
+    __shared__ float2 tw[N];
+    __shared__ float2 nyqb[N];
+    __shared__ double2 tws[N];
+    __shared__ double2 rbuf[N * NLX];
+    const int t = blockIdx.x % C::NT2, pl = blockIdx.x / C::NT2;
+    const int rot = pl / N, z = pl % N;
+    for (int i = threadIdx.x; i < N; i += NT) tw[i] = twg[i];
+    const float2* src = xb + (size_t)pl * N * C::N2 + t * TT;
+    for (int e = threadIdx.x; e < N * TT; e += NT) buf[e] = src[(size_t)(e / TT) * C::N2 + e % TT];
+    if (t == 0) {
+        for (int i = threadIdx.x; i < N; i += NT) tws[i] = tw64[i];
+        const double2* lr = lowrow + (size_t)pl * N * NLX;
+        for (int e = threadIdx.x; e < N * NLX; e += NT) rbuf[low_slot(e / NLX, e % NLX)] = lr[e];
+    }
+    __syncthreads();
+    fft_lds<N, false, TT, NT, true, N>(buf, TT, 1, tw);
+    float2* spec_rot = spec + (size_t)rot * C::H;
+    if (t == 0) {
+        // column 0 holds Z = X0 + i X_{n/2} transformed along y (see unpack_nyquist)
+        for (int k = threadIdx.x; k <= N / 2; k += NT) {
+            const int kk = (N - k) % N;
+            const float2 zk = buf[k * TT], zz = buf[kk * TT];
+            const float2 a = make_float2(0.5f * (zk.x + zz.x), 0.5f * (zk.y - zz.y));
+            const float2 b = make_float2(0.5f * (zk.y + zz.y), 0.5f * (zz.x - zk.x));
+            buf[k * TT] = a;
+            nyqb[k] = b;
+            if (kk != k) {
+                buf[kk * TT] = cconj(a);
+                nyqb[kk] = cconj(b);
+            }
+        }
+        low_cols_y<N, NT>(rbuf, tws, lowT + (size_t)pl * NLOW2);
+        __syncthreads();
+        float2* nyq = spec_rot + (size_t)N * C::N2 * N;
+        for (int ky = threadIdx.x; ky < N; ky += NT) nyq[((size_t)(ky / C::T) * N + z) * C::T + (ky % C::T)] = nyqb[ky];
+    }
+    for (int e = threadIdx.x; e < N * TT; e += NT) {
+        const int ky = e / TT, c = e % TT;
+        spec_rot[((size_t)(ky * C::NT2 + t) * N + z) * C::T + c] = buf[e];
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(Split<N>::CT) void k_split_cols_inv(const float2* __restrict__ spec,
+                                                             const float2* __restrict__ twg, float2* __restrict__ xb) {
+    using C = Split<N>;
+    constexpr int NT = C::CT, TT = C::T;
+    __shared__ float2 buf[N * TT];
+    __shared__ float2 tw[N];
+    const int t = blockIdx.x % C::NT2, pl = blockIdx.x / C::NT2;
+    const int rot = pl / N, z = pl % N;
+    for (int i = threadIdx.x; i < N; i += NT) tw[i] = twg[i];
+    const float2* spec_rot = spec + (size_t)rot * C::H;
+    for (int e = threadIdx.x; e < N * TT; e += NT) {
+        const int ky = e / TT, c = e % TT;
+        buf[e] = spec_rot[((size_t)(ky * C::NT2 + t) * N + z) * C::T + c];
+    }
+    __syncthreads();
+    if (t == 0) {
+        // column 0 (A) and the Nyquist column (B) become A + i B (see pack_nyquist)
+        const float2* nyq = spec_rot + (size_t)N * C::N2 * N;
+        for (int ky = threadIdx.x; ky < N; ky += NT) {
+            const float2 a = buf[ky * TT], b = nyq[((size_t)(ky / C::T) * N + z) * C::T + (ky % C::T)];
+            buf[ky * TT] = make_float2(a.x - b.y, a.y + b.x);
+        }
+        __syncthreads();
+    }
+    fft_lds<N, true, TT, NT, true, N>(buf, TT, 1, tw);
+    float2* dst = xb + (size_t)pl * N * C::N2 + t * TT;
+    for (int e = threadIdx.x; e < N * TT; e += NT) dst[(size_t)(e / TT) * C::N2 + e % TT] = buf[e];
+}
+
+template <int N>
+__global__ __launch_bounds__(Split<N>::RT) void k_split_rows_inv(const float2* __restrict__ xb,
+                                                             const float2* __restrict__ twg,
+                                                             const double2* __restrict__ tw64,
+                                                             const double2* __restrict__ Plow,
+                                                             unsigned long long* __restrict__ ptop,
+                                                             double* __restrict__ pssq, float* __restrict__ corr_out) {
+    using C = Split<N>;
+    constexpr int NT = C::RT, RB = C::RB, NW = NT / 64;
+    __shared__ float2 rows[RB * C::P];
+    __shared__ float2 tw[N];
+    __shared__ double2 tws[N];
+    __shared__ double2 btab[RB * NLX];
+    __shared__ double2 az[NLOW2];
+    __shared__ unsigned long long wtop[NW][KTOP + 1];
+    __shared__ double wss[NW];
+    __shared__ double wsec[NW];
+    static_assert(NLOW2 <= NT, "one low-block row per thread");
+    const int blk = blockIdx.x % C::NB, pl = blockIdx.x / C::NB;
+    const int rot = pl / N, z = pl % N, y0 = blk * RB;
+    const int tid = threadIdx.x;
+    double2 pz[NLY];
+    if (tid < NLOW2) {
+        const double2* Pr = Plow + (size_t)rot * NLOW3 + tid * NLY;
+#pragma unroll
+        for (int kzi = 0; kzi < NLY; ++kzi) pz[kzi] = Pr[kzi];
+    }
+    for (int i = tid; i < N; i += NT) {
+        tw[i] = twg[i];
+        tws[i] = tw64[i];
+    }
+    const float2* src = xb + ((size_t)pl * N + y0) * C::N2;
+    for (int e = tid; e < RB * C::N2; e += NT) rows[(e / C::N2) * C::P + e % C::N2] = src[e];
+    __syncthreads();
+    if (tid < NLOW2) {
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int kzi = 0; kzi < NLY; ++kzi) {
+            const double2 t = dcmulc(pz[kzi], tws[mod_n((kzi - KLOW) * z, N)]);
+            acc.x += t.x;
+            acc.y += t.y;
+        }
+        az[tid] = acc;
+    }
+    __syncthreads();
+    for (int t = tid; t < RB * NLX; t += NT) {
+        const int y = y0 + t / NLX, kx = t % NLX;
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int kyi = 0; kyi < NLY; ++kyi) {
+            const double2 v = dcmulc(az[kx * NLY + kyi], tws[mod_n((kyi - KLOW) * y, N)]);
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+        btab[t] = kx > 0 ? make_double2(2.0 * acc.x, 2.0 * acc.y) : acc;
+    }
+    c2r_pre<N, NT, RB>(rows, tw);
+    fft_lds<C::N2, true, RB, NT, true, N>(rows, 1, C::P, tw);
+    const size_t unit = (size_t)pl * C::NB + blk;
+    scan_rows<N, NT, RB>(rows, btab, tws, z, y0, wtop, wss, wsec, ptop + unit * KREC, pssq + unit, corr_out);
+}
+
 // ------------------------------------------------------------- launchers
 
 // Schedule variants of the search kernels, chosen per canvas edge by the
@@ -1858,7 +2141,7 @@ __host__ __device__ constexpr bool plane_variant_valid(int N, int v) {
 }
 template <int N>
 constexpr bool z_variant_valid(int v) {
-    return v >= 0 && v < Z_VARIANTS && (v == 1 || z_threads_of(v) <= N * Canvas<N>::T);
+    return v >= 0 && v < Z_VARIANTS && (v == 1 || z_threads_of(v) <= N * Dims<N>::T);
 }
 
 template <int N, int V>
@@ -1883,9 +2166,60 @@ template <int N, int V>
 static void launch_z(const SearchBatchArgs& a) {
     if constexpr (z_variant_valid<N>(V)) {
         constexpr int ZT = z_threads_of(V);
-        hipLaunchKernelGGL((k_zpass<N, 0, ZT>), dim3(a.count * Canvas<N>::TILES), dim3(ZT), 0, a.stream, a.spec, a.W,
+        hipLaunchKernelGGL((k_zpass<N, 0, ZT>), dim3(a.count * Dims<N>::TILES), dim3(ZT), 0, a.stream, a.spec, a.W,
                            nullptr, a.tw, 1.0f);
     }
+}
+
+// pass 2 of either path: the low block along z, then the z pencils
+template <int N>
+static hipError_t launch_z_pass(const SearchBatchArgs& a) {
+    if (!z_variant_valid<N>(a.zv)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_low_combine<0, N>), dim3(a.count), dim3(256), 0, a.stream, a.lowT, a.tw64, a.Wlow, 1.0, a.Plow);
+    switch (a.zv) {
+        case 0: launch_z<N, 0>(a); break;
+        case 1: launch_z<N, 1>(a); break;
+        default: launch_z<N, 2>(a); break;
+    }
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_split_pass(int pass, const SearchBatchArgs& a) {
+    using C = Split<N>;
+    // the row pass's sampler needs every rotated canvas point inside the
+    // lattice (edge m) and brick tables of m entries; the split passes take
+    // the corner masks of the swept grid only
+    if (a.m != C::M || a.mp < a.m || a.mp % 4 || !a.xbuf || !a.lowrow || a.crec) return hipErrorInvalidValue;
+    if (pass == 1) return launch_z_pass<N>(a);
+    const unsigned rb = (unsigned)((size_t)a.count * N * C::NB), cb = (unsigned)((size_t)a.count * N * C::NT2);
+    if (pass == 0) {
+        hipLaunchKernelGGL((k_split_rows_fwd<N, 0>), dim3(rb), dim3(C::RT), 0, a.stream, a.cmask, a.m, a.mp / 4, a.rots,
+                           nullptr, a.tw, a.tw64, a.xbuf, a.lowrow);
+        hipLaunchKernelGGL(k_split_cols_fwd<N>, dim3(cb), dim3(C::CT), 0, a.stream, a.xbuf, a.lowrow, a.tw, a.tw64, a.spec,
+                           a.lowT);
+    } else {
+        hipLaunchKernelGGL(k_split_cols_inv<N>, dim3(cb), dim3(C::CT), 0, a.stream, a.spec, a.tw, a.xbuf);
+        hipLaunchKernelGGL(k_split_rows_inv<N>, dim3(rb), dim3(C::RT), 0, a.stream, a.xbuf, a.tw, a.tw64, a.Plow, a.ptop,
+                           a.pssq, a.corr_out);
+    }
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_object_spectrum_split(const float* O, float2* spec_tmp, float2* W, const float2* tw,
+                                               const double2* tw64, double2* lowT_tmp, double2* Wlow, float2* xbuf,
+                                               double2* lowrow, hipStream_t s) {
+    using C = Split<N>;
+    if (!xbuf || !lowrow) return hipErrorInvalidValue;
+    const double scale = 1.0 / ((double)N * N * N);
+    hipLaunchKernelGGL((k_split_rows_fwd<N, 1>), dim3(N * C::NB), dim3(C::RT), 0, s, nullptr, 0, 0, nullptr, O, tw, tw64,
+                       xbuf, lowrow);
+    hipLaunchKernelGGL(k_split_cols_fwd<N>, dim3(N * C::NT2), dim3(C::CT), 0, s, xbuf, lowrow, tw, tw64, spec_tmp,
+                       lowT_tmp);
+    hipLaunchKernelGGL((k_zpass<N, 1, 256>), dim3(C::TILES), dim3(256), 0, s, spec_tmp, nullptr, W, tw, (float)scale);
+    hipLaunchKernelGGL((k_low_combine<1, N>), dim3(1), dim3(256), 0, s, lowT_tmp, tw64, nullptr, scale, Wlow);
+    return hipGetLastError();
 }
 
 template <int N>
@@ -1894,17 +2228,7 @@ static hipError_t launch_search_pass(int pass, const SearchBatchArgs& a) {
     // the lattice (edge m = 2 ceil((sqrt(3) n + 2) / 2)),
     // with a one-cell margin, and its brick-address tables hold m entries
     if (a.m != Canvas<N>::M || a.mp < a.m || a.mp % 4) return hipErrorInvalidValue;
-    if (pass == 1) {
-        if (!z_variant_valid<N>(a.zv)) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_low_combine<0, N>), dim3(a.count), dim3(256), 0, a.stream, a.lowT, a.tw64, a.Wlow, 1.0,
-                           a.Plow);
-        switch (a.zv) {
-            case 0: launch_z<N, 0>(a); break;
-            case 1: launch_z<N, 1>(a); break;
-            default: launch_z<N, 2>(a); break;
-        }
-        return hipGetLastError();
-    }
+    if (pass == 1) return launch_z_pass<N>(a);
     const int v = pass == 0 ? (a.crec ? default_plane_variant_of(N) : a.pv1) : a.pv3;
     if (!plane_variant_valid(N, v)) return hipErrorInvalidValue;
     switch (v) {
@@ -1927,9 +2251,15 @@ static hipError_t launch_object_spectrum(const float* O, float2* spec_tmp, float
     return hipGetLastError();
 }
 
+// edges of the fused plane passes, edges with split passes compiled, and
+// the edges that only the split passes serve (planes above the LDS)
 #define REGDOCK_FOR_EACH_N(X) X(16) X(32) X(48) X(60) X(64) X(80) X(96) X(120) X(128) X(160) X(180)
+#define REGDOCK_FOR_EACH_SPLIT_N(X) X(64) X(128) X(192) X(256) X(360)
+#define REGDOCK_FOR_EACH_SPLIT_ONLY_N(X) X(192) X(256) X(360)
 
-bool canvas_supported(int n) {
+bool canvas_supported(int n) { return fused_supported(n) || split_supported(n); }
+
+bool fused_supported(int n) {
     switch (n) {
 #define CASE(N) case N: return true;
         REGDOCK_FOR_EACH_N(CASE)
@@ -1938,10 +2268,20 @@ bool canvas_supported(int n) {
     }
 }
 
+bool split_supported(int n) {
+    switch (n) {
+#define CASE(N) case N: return true;
+        REGDOCK_FOR_EACH_SPLIT_N(CASE)
+#undef CASE
+        default: return false;
+    }
+}
+
 size_t spectrum_elems(int n) {
     switch (n) {
-#define CASE(N) case N: return Canvas<N>::H;
+#define CASE(N) case N: return Dims<N>::H;
         REGDOCK_FOR_EACH_N(CASE)
+        REGDOCK_FOR_EACH_SPLIT_ONLY_N(CASE)
 #undef CASE
         default: return 0;
     }
@@ -1949,8 +2289,27 @@ size_t spectrum_elems(int n) {
 
 int tile_width(int n) {
     switch (n) {
-#define CASE(N) case N: return Canvas<N>::T;
+#define CASE(N) case N: return Dims<N>::T;
         REGDOCK_FOR_EACH_N(CASE)
+        REGDOCK_FOR_EACH_SPLIT_ONLY_N(CASE)
+#undef CASE
+        default: return 0;
+    }
+}
+
+int split_units(int n) {
+    switch (n) {
+#define CASE(N) case N: return N * Split<N>::NB;
+        REGDOCK_FOR_EACH_SPLIT_N(CASE)
+#undef CASE
+        default: return 0;
+    }
+}
+
+size_t split_plane_elems(int n) {
+    switch (n) {
+#define CASE(N) case N: return Split<N>::XH;
+        REGDOCK_FOR_EACH_SPLIT_N(CASE)
 #undef CASE
         default: return 0;
     }
@@ -1969,6 +2328,7 @@ bool z_variant_ok(int n, int v) {
     switch (n) {
 #define CASE(N) case N: return z_variant_valid<N>(v);
         REGDOCK_FOR_EACH_N(CASE)
+        REGDOCK_FOR_EACH_SPLIT_ONLY_N(CASE)
 #undef CASE
         default: return false;
     }
@@ -1980,6 +2340,14 @@ int plane_variant_threads(int v) { return v == 0 || v == 1 ? 256 : v == 2 ? 512 
 int z_variant_threads(int v) { return z_threads_of(v); }
 
 hipError_t search_pass(int n, int pass, const SearchBatchArgs& a) {
+    if (a.xbuf) {
+        switch (n) {
+#define CASE(N) case N: return launch_split_pass<N>(pass, a);
+            REGDOCK_FOR_EACH_SPLIT_N(CASE)
+#undef CASE
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (n) {
 #define CASE(N) case N: return launch_search_pass<N>(pass, a);
         REGDOCK_FOR_EACH_N(CASE)
@@ -1989,7 +2357,16 @@ hipError_t search_pass(int n, int pass, const SearchBatchArgs& a) {
 }
 
 hipError_t object_spectrum(int n, const float* O, float2* spec_tmp, float2* W, const float2* tw, const double2* tw64,
-                           double2* lowT_tmp, double2* Wlow, hipStream_t s) {
+                           double2* lowT_tmp, double2* Wlow, hipStream_t s, float2* xbuf, double2* lowrow) {
+    if (xbuf) {
+        switch (n) {
+#define CASE(N) \
+    case N: return launch_object_spectrum_split<N>(O, spec_tmp, W, tw, tw64, lowT_tmp, Wlow, xbuf, lowrow, s);
+            REGDOCK_FOR_EACH_SPLIT_N(CASE)
+#undef CASE
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (n) {
 #define CASE(N) case N: return launch_object_spectrum<N>(O, spec_tmp, W, tw, tw64, lowT_tmp, Wlow, s);
         REGDOCK_FOR_EACH_N(CASE)
@@ -2066,7 +2443,8 @@ int rescore_slices(int n) {
 
 hipError_t select_batch(int n, const SearchBatchArgs& a, int base, const PeakArrays& pk) {
     const double eps_per_rms = REGK_EPS_SCALE * std::ldexp(1.0, -24) * std::log2((double)n * n * n);
-    hipLaunchKernelGGL(k_select, dim3(a.count), dim3(256), 0, a.stream, a.ptop, a.pssq, n, eps_per_rms, base, pk.cand_idx,
+    hipLaunchKernelGGL(k_select, dim3(a.count), dim3(256), 0, a.stream, a.ptop, a.pssq, n, a.units > 0 ? a.units : n, eps_per_rms,
+                       base, pk.cand_idx,
                        pk.cand_n, pk.window, pk.ovf, pk.best_val, pk.best_flat, pk.stats);
     return hipGetLastError();
 }

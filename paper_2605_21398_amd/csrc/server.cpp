@@ -567,7 +567,7 @@ int register_submit(reg_server* s, const reg_request* rq, reg_ticket* out) {
     const int batch = j->params.batch > 0 ? (j->params.batch + 7) / 8 * 8
                                           : regdock_rt::default_batch_for(rq->grid.n, rq->n_rot);
     const auto fp = regdock_rt::footprint(rq->grid.n, rq->n_rot, rq->n_poses, m.n_vertices, m.n_faces, batch,
-                                          rq->refine ? j->top_k : 0, j->params.rotate_object);
+                                          rq->refine ? j->top_k : 0, j->params.rotate_object, j->params.split_plane);
     const size_t staging = j->mesh->vertices.size() * 4 + j->mesh->faces.size() * 4 + j->mesh->touchable.size() + j->poses.size() * 4 +
                            j->so3.size() * 4 + (size_t)rq->n_rot * 60 + 16 * 200;
     j->object_part = fp.object;

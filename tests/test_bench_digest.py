@@ -29,8 +29,13 @@ def test_digest_ignores_comments_but_not_code(tmp_path):
     text = k.read_text()
     k.write_text("// a new comment line\n" + text.replace("namespace regdock {", "namespace regdock {  /* note */", 1))
     assert b.search_code_digest() == d0
-    k.write_text(text.replace("constexpr int FLAT_BITS = 23;", "constexpr int FLAT_BITS = 24;", 1))
+    hdr = dst / "search_kernels.h"
+    htext = hdr.read_text()
+    assert "constexpr int KLOW = 3;" in htext
+    k.write_text(text)
+    hdr.write_text(htext.replace("constexpr int KLOW = 3;", "constexpr int KLOW = 2;", 1))
     assert b.search_code_digest() != d0
+    hdr.write_text(htext)
     h = dst / "fft_device.h"
     k.write_text(text)
     h.write_text(h.read_text().replace("r == 15 ||", "r == 14 ||", 1))
