@@ -302,15 +302,45 @@ __host__ __device__ constexpr int two_pass_first(int L) {
     return best;
 }
 
+// first two radices of a three-pass plan L = R1 R2 R3 of codelets, the most
+// balanced (largest min(R1, R2, R3)), the larger R1, then R2, among equals;
+// 0 if there is none.  which = 0 gives R1, 1 gives R2.
+__host__ __device__ constexpr int three_pass_radix(int L, int which) {
+    int b1 = 0, b2 = 0, bmin = 0;
+    for (int r1 = 16; r1 >= 2; --r1) {
+        if (!is_codelet(r1) || L % r1) continue;
+        for (int r2 = 16; r2 >= 2; --r2) {
+            if (!is_codelet(r2) || (L / r1) % r2 || !is_codelet(L / r1 / r2)) continue;
+            const int r3 = L / r1 / r2;
+            const int mn = r1 < r2 ? (r1 < r3 ? r1 : r3) : (r2 < r3 ? r2 : r3);
+            if (mn > bmin) {
+                bmin = mn;
+                b1 = r1;
+                b2 = r2;
+            }
+        }
+    }
+    return which == 0 ? b1 : b2;
+}
+
 // Radix of pass p of a length-L transform (1 past the last pass, 0 if L has
 // another prime factor): the greedy plan where it takes at most two passes,
 // else a two-pass plan through a composite codelet where one exists (60 =
 // 10 x 6, 96 = 12 x 8, 120 = 12 x 10, 160 = 16 x 10, 180 = 15 x 12, 30 = 6 x 5,
-// 90 = 10 x 9), else the greedy plan.
+// 90 = 10 x 9), else a three-pass plan of codelets where the greedy one
+// takes more passes (360 = 10 x 6 x 6 against 8 x 5 x 3 x 3), else the
+// greedy plan.
 __host__ __device__ constexpr int fft_radix(int L, int p) {
-    if (greedy_npass(L) <= 2 || two_pass_first(L) == 0) return greedy_radix(L, p);
-    const int r1 = two_pass_first(L);
-    return p == 0 ? r1 : p == 1 ? L / r1 : 1;
+    if (greedy_npass(L) <= 2) return greedy_radix(L, p);
+    if (two_pass_first(L) != 0) {
+        const int r1 = two_pass_first(L);
+        return p == 0 ? r1 : p == 1 ? L / r1 : 1;
+    }
+    if (greedy_npass(L) > 3 && three_pass_radix(L, 0) != 0) {
+        const int r1 = three_pass_radix(L, 0), r2 = three_pass_radix(L, 1);
+        return p == 0 ? r1 : p == 1 ? r2 : p == 2 ? L / (r1 * r2) : 1;
+    }
+    return greedy_radix(L, p);
 }
 
 __host__ __device__ constexpr int fft_npass(int L) {

@@ -1902,8 +1902,8 @@ __global__ void k_validate(const float* __restrict__ V, int nv, const int32_t* _
 //                      block, the real-to-complex x FFT -> X
 //   k_split_cols_fwd   per (rotation, plane, tile of T columns): the y FFT of
 //                      the tile's columns -> the tiled spectrum; the tile of
-//                      column 0 splits X0 and X_{n/2} and finishes the plane's
-//                      low block along y
+//                      column 0 splits X0 and X_{n/2}
+//   k_split_low_y      per (rotation, plane): the plane's low block along y
 //   k_split_cols_inv   per (rotation, plane, tile): inverse y FFT -> X
 //   k_split_rows_inv   per (rotation, plane, block of RB rows): complex-to-
 //                      real x FFT, the exact low field, the block's peak keys
@@ -1917,11 +1917,16 @@ template <int N> struct Split : Dims<N> {
     using D::P;
     using D::T;
     using D::NT2;
-    static constexpr int RB = largest_divisor_le(N, 32);  // rows per row-pass workgroup
-    static constexpr int NB = N / RB;                     // row blocks per plane
+    // rows per row-pass workgroup: above 180 at most 16, which keeps a row
+    // workgroup's LDS low enough for three (forward) or four (inverse) per CU
+    // (at 360^3: 15 rows against 30 gave 1.2x the rotations/s)
+    static constexpr int RB = largest_divisor_le(N, N > 180 ? 16 : 32);
+    static constexpr int NB = N / RB;  // row blocks per plane
     // threads of a row-pass workgroup: every column pair busy, two rows at a time
     static constexpr int RT = 2 * ((N2 + 63) / 64) * 64 < 128 ? 128 : 2 * ((N2 + 63) / 64) * 64;
-    static constexpr int CT = 256;                        // threads of a column-pass workgroup
+    // threads of a column-pass workgroup: 512 above 180, where the T columns'
+    // transforms are long enough to keep them busy (at 360^3 1.06x against 256)
+    static constexpr int CT = N > 180 ? 512 : 256;
     static constexpr size_t XH = (size_t)N * N * N2;      // complex of X per rotation
     static_assert(RT <= 512 && N2 <= RT && N2 / 2 + 1 <= RT, "row pass layout");
 };
@@ -1977,27 +1982,18 @@ __global__ __launch_bounds__(Split<N>::RT) void k_split_rows_fwd(const uint8_t* 
 
 template <int N>
 __global__ __launch_bounds__(Split<N>::CT) void k_split_cols_fwd(const float2* __restrict__ xb,
-                                                             const double2* __restrict__ lowrow,
                                                              const float2* __restrict__ twg,
-                                                             const double2* __restrict__ tw64,
-                                                             float2* __restrict__ spec, double2* __restrict__ lowT) {
+                                                             float2* __restrict__ spec) {
     using C = Split<N>;
     constexpr int NT = C::CT, TT = C::T;
     __shared__ float2 buf[N * TT];  // [y][c]
     __shared__ float2 tw[N];
     __shared__ float2 nyqb[N];
-    __shared__ double2 tws[N];
-    __shared__ double2 rbuf[N * NLX];
     const int t = blockIdx.x % C::NT2, pl = blockIdx.x / C::NT2;
     const int rot = pl / N, z = pl % N;
     for (int i = threadIdx.x; i < N; i += NT) tw[i] = twg[i];
     const float2* src = xb + (size_t)pl * N * C::N2 + t * TT;
     for (int e = threadIdx.x; e < N * TT; e += NT) buf[e] = src[(size_t)(e / TT) * C::N2 + e % TT];
-    if (t == 0) {
-        for (int i = threadIdx.x; i < N; i += NT) tws[i] = tw64[i];
-        const double2* lr = lowrow + (size_t)pl * N * NLX;
-        for (int e = threadIdx.x; e < N * NLX; e += NT) rbuf[low_slot(e / NLX, e % NLX)] = lr[e];
-    }
     __syncthreads();
     fft_lds<N, false, TT, NT, true, N>(buf, TT, 1, tw);
     float2* spec_rot = spec + (size_t)rot * C::H;
@@ -2015,7 +2011,6 @@ __global__ __launch_bounds__(Split<N>::CT) void k_split_cols_fwd(const float2* _
                 nyqb[kk] = cconj(b);
             }
         }
-        low_cols_y<N, NT>(rbuf, tws, lowT + (size_t)pl * NLOW2);
         __syncthreads();
         float2* nyq = spec_rot + (size_t)N * C::N2 * N;
         for (int ky = threadIdx.x; ky < N; ky += NT) nyq[((size_t)(ky / C::T) * N + z) * C::T + (ky % C::T)] = nyqb[ky];
@@ -2024,6 +2019,23 @@ __global__ __launch_bounds__(Split<N>::CT) void k_split_cols_fwd(const float2* _
         const int ky = e / TT, c = e % TT;
         spec_rot[((size_t)(ky * C::NT2 + t) * N + z) * C::T + c] = buf[e];
     }
+}
+
+// per (rotation, plane): the y direction of the plane's exact low block from
+// the row pass's x sums (kept out of the column pass, whose LDS it would
+// double for one tile in NT2)
+template <int N>
+__global__ __launch_bounds__(256) void k_split_low_y(const double2* __restrict__ lowrow,
+                                                     const double2* __restrict__ tw64, double2* __restrict__ lowT) {
+    constexpr int NT = 256;
+    __shared__ double2 tws[N];
+    __shared__ double2 rbuf[N * NLX];
+    const int pl = blockIdx.x;
+    for (int i = threadIdx.x; i < N; i += NT) tws[i] = tw64[i];
+    const double2* lr = lowrow + (size_t)pl * N * NLX;
+    for (int e = threadIdx.x; e < N * NLX; e += NT) rbuf[low_slot(e / NLX, e % NLX)] = lr[e];
+    __syncthreads();
+    low_cols_y<N, NT>(rbuf, tws, lowT + (size_t)pl * NLOW2);
 }
 
 template <int N>
@@ -2196,7 +2208,8 @@ static hipError_t launch_split_pass(int pass, const SearchBatchArgs& a) {
     if (pass == 0) {
         hipLaunchKernelGGL((k_split_rows_fwd<N, 0>), dim3(rb), dim3(C::RT), 0, a.stream, a.cmask, a.m, a.mp / 4, a.rots,
                            nullptr, a.tw, a.tw64, a.xbuf, a.lowrow);
-        hipLaunchKernelGGL(k_split_cols_fwd<N>, dim3(cb), dim3(C::CT), 0, a.stream, a.xbuf, a.lowrow, a.tw, a.tw64, a.spec,
+        hipLaunchKernelGGL(k_split_cols_fwd<N>, dim3(cb), dim3(C::CT), 0, a.stream, a.xbuf, a.tw, a.spec);
+        hipLaunchKernelGGL(k_split_low_y<N>, dim3((unsigned)a.count * N), dim3(256), 0, a.stream, a.lowrow, a.tw64,
                            a.lowT);
     } else {
         hipLaunchKernelGGL(k_split_cols_inv<N>, dim3(cb), dim3(C::CT), 0, a.stream, a.spec, a.tw, a.xbuf);
@@ -2215,8 +2228,8 @@ static hipError_t launch_object_spectrum_split(const float* O, float2* spec_tmp,
     const double scale = 1.0 / ((double)N * N * N);
     hipLaunchKernelGGL((k_split_rows_fwd<N, 1>), dim3(N * C::NB), dim3(C::RT), 0, s, nullptr, 0, 0, nullptr, O, tw, tw64,
                        xbuf, lowrow);
-    hipLaunchKernelGGL(k_split_cols_fwd<N>, dim3(N * C::NT2), dim3(C::CT), 0, s, xbuf, lowrow, tw, tw64, spec_tmp,
-                       lowT_tmp);
+    hipLaunchKernelGGL(k_split_cols_fwd<N>, dim3(N * C::NT2), dim3(C::CT), 0, s, xbuf, tw, spec_tmp);
+    hipLaunchKernelGGL(k_split_low_y<N>, dim3(N), dim3(256), 0, s, lowrow, tw64, lowT_tmp);
     hipLaunchKernelGGL((k_zpass<N, 1, 256>), dim3(C::TILES), dim3(256), 0, s, spec_tmp, nullptr, W, tw, (float)scale);
     hipLaunchKernelGGL((k_low_combine<1, N>), dim3(1), dim3(256), 0, s, lowT_tmp, tw64, nullptr, scale, Wlow);
     return hipGetLastError();

@@ -1,8 +1,8 @@
 """Host check of the HIP FFT building blocks (csrc/fft_device.h): every radix
 codelet, forward and inverse, against the DFT by its definition in double, and
-the pass plan (at most two LDS passes) of every transform length the canvas
-edges use.  Compiles tests/native/fft_codelets.cpp for the host with hipcc and
-runs it; no GPU."""
+the pass plan of every transform length the canvas edges use (at most two LDS
+passes up to the 180 edge, three above).  Compiles tests/native/fft_codelets.cpp
+for the host with hipcc and runs it; no GPU."""
 import os
 import shutil
 import subprocess
@@ -32,4 +32,4 @@ def test_codelets_and_plans(tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True)
     print(r.stdout)
     assert r.returncode == 0, r.stdout
-    assert r.stdout.count(" ok") == 11 + 22
+    assert r.stdout.count(" ok") == 11 + 28

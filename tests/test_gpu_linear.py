@@ -3,8 +3,9 @@ the C ABI:
 
 * register_linear_edge gives the oracle's n_o + n_s - 1, bit for bit, and the
   smallest supported edge above it (120 for the 32^3 workload, 180 for the
-  64^3 one, whose probe shafts need 173 points, none for the 128^3 one, which
-  needs 359);
+  64^3 one, whose probe shafts need 173 points, 360 for the 128^3 one, which
+  needs 359 and runs on the split plane passes, checked against the oracle in
+  tests/test_gpu_split.py);
 * on that edge the device's circular search is the linear correlation: for
   the 32^3 workload at 120^3 (h 0.4 mm) and the 64^3 workload at 180^3
   (h 0.25 mm), with the oracle's grids injected, scores meet the search's bar
@@ -39,7 +40,8 @@ def test_linear_edge_matches_oracle(cfg):
     n_o, n_s, ref = S.linear_edge(p.vertices, p.poses, p.radius, p.length, p.center, p.h)
     print(f"\nconfig {cfg}: n_o {n_o}, n_s {n_s}, needed {need}, edge {edge}")
     assert need == ref
-    supported = [16, 32, 48, 60, 64, 80, 96, 120, 128, 160, 180]
+    # the fused plane passes' edges, then the split passes' edges above 180
+    supported = [16, 32, 48, 60, 64, 80, 96, 120, 128, 160, 180, 192, 256, 360]
     assert edge == next((n for n in supported if n >= ref), 0)
 
 
