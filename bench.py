@@ -516,7 +516,9 @@ def _linear_one(rd, torch, cfg: int, M: int):
             b = int(np.argmax(sc))
             ang, mm = _pose_errors(p, po[b])
             H8 = info["spectrum_elems"] * 8
-            passes = 4 if n <= 180 else 6  # the split plane passes move the plane buffer out and back
+            # spectrum round trips per rotation: 4 on the fused plane passes;
+            # the split passes write and read the plane buffer in both plane passes
+            passes = 4 if n <= 180 else 8
             res[name] = {"n": n, "rotations_per_s": M / dt, "model_bytes_per_rotation": passes * H8 + H8 / info["batch"],
                          "plane_passes": "fused" if n <= 180 else "split",
                          "best": {"deg": ang, "mm": mm, "score": float(sc[b])}}

@@ -1909,7 +1909,8 @@ __global__ void k_validate(const float* __restrict__ V, int nv, const int32_t* _
 //                      real x FFT, the exact low field, the block's peak keys
 // The z pass, the low-block combine and the candidate selection are the fused
 // path's (one record of keys per row block instead of per plane).  A rotation
-// moves 6 H8 through HBM instead of 4 H8.
+// moves 8 H8 through HBM instead of 4 H8: each split pass writes and reads
+// the plane buffer once more.
 template <int N> struct Split : Dims<N> {
     using D = Dims<N>;
     using D::N2;
