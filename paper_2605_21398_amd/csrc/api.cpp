@@ -268,6 +268,7 @@ struct reg_handle {
     float2* xbuf2 = nullptr;
     double2* lowrow = nullptr;
     double2* lowrow2 = nullptr;
+    unsigned long long* reach4 = nullptr;  // the swept lattice's reach (rows beyond it are skipped)
     float2* tw = nullptr;
     double2* tw64 = nullptr;
     double2* lowT = nullptr;
@@ -860,6 +861,7 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
     if (h->split) {
         ALLOC_TRY(h, h->xbuf, split_plane_elems(h->n) * (size_t)h->batch);
         ALLOC_TRY(h, h->lowrow, (size_t)h->n * h->n * NLX * (size_t)h->batch);
+        ALLOC_TRY(h, h->reach4, 1);
     }
     ALLOC_TRY(h, h->stats, 5);
     ALLOC_TRY(h, h->need_count, 1);
@@ -932,6 +934,7 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
     }
     DEV_TRY(h, setup_swept(h->poses, n_poses, probe->radius_mm, probe->length_mm, h->m, h->mp, h->h, h->wc,
                            h->pose_prep, h->Sw, h->cm, s));
+    if (h->reach4) DEV_TRY(h, swept_reach(h->Sw, h->m, h->reach4, s));
     if (h->rotobj) {
         const int rc = build_rotated_object(h);
         if (rc) return rc;
@@ -1420,6 +1423,7 @@ static int enqueue_batch(reg_handle* h, int b0, int cnt, int lane, hipStream_t l
     a.units = h->units;
     a.xbuf = odd ? h->xbuf2 : h->xbuf;
     a.lowrow = odd ? h->lowrow2 : h->lowrow;
+    a.reach4 = h->reach4;
     a.corr_out = corr_out;
     a.pv1 = h->sched.pv1;
     a.pv3 = h->sched.pv3;
@@ -1584,6 +1588,7 @@ int register_set_grids(reg_handle* h, const float* O, const uint8_t* Sw) {
         const size_t m3 = (size_t)h->m * h->m * h->m;
         DEV_TRY(h, hipMemcpyAsync(h->Sw, Sw, m3, hipMemcpyDeviceToDevice, h->stream));
         DEV_TRY(h, setup_cellmask(h->Sw, h->m, h->mp, h->cm, h->stream));
+        if (h->reach4) DEV_TRY(h, swept_reach(h->Sw, h->m, h->reach4, h->stream));
     }
     return REG_OK;
 }

@@ -58,6 +58,9 @@ struct SearchBatchArgs {
     // x sums of the low block [count][n][n][NLX]; NULL selects the fused passes
     float2* xbuf = nullptr;
     double2* lowrow = nullptr;
+    // split plane passes: the swept lattice's reach (swept_reach); rows and
+    // planes of S_r beyond it are written as zeros unsampled.  NULL: no skip
+    const unsigned long long* reach4 = nullptr;
 };
 
 // Schedule variants (threads and waves per SIMD of the plane workgroups;
@@ -99,6 +102,9 @@ hipError_t setup_object_grid(const float* V, const int32_t* F, const uint8_t* to
 hipError_t setup_swept(const float* poses, int np, double r, double L, int m, int mp, double h, const double* wc,
                        double* pose_tmp, uint8_t* Sw, uint8_t* cm, hipStream_t s);
 hipError_t setup_cellmask(const uint8_t* Sw, int m, int mp, uint8_t* cm, hipStream_t s);
+// the swept lattice's reach: max over occupied points of (2x-m)^2 + (2y-m)^2 +
+// (2z-m)^2 into *reach4 (one device word, cleared first)
+hipError_t swept_reach(const uint8_t* Sw, int m, unsigned long long* reach4, hipStream_t s);
 hipError_t setup_rotations(const float* so3, int M, double* rots, int* err, hipStream_t s, int transpose = 0);
 // rotated-object search: cell classes (mp^3 bytes, bricked) and corner records
 // (2 mp^3 float4) of the object grid on the body lattice; the fixed grid S

@@ -1808,6 +1808,44 @@ __global__ void k_cellmask(const uint8_t* __restrict__ Sw, int m, int mp, uint8_
     cm[brick_index(ix, iy, iz, mp / 4)] = (uint8_t)mk;
 }
 
+// Reach of the swept lattice: the largest (2x - m)^2 + (2y - m)^2 + (2z - m)^2
+// over its occupied points, i.e. four times the squared distance from the
+// lattice centre.  A rotated canvas voxel k samples a cell with an occupied
+// corner only if |k - n/2| <= sqrt(reach4) / 2 + sqrt(3) (rotations keep
+// distances from the centre, and a cell's corners lie within sqrt(3) of any
+// point in it), so rows and planes of the canvas beyond that radius hold
+// exact zeros.  One workgroup per (z, block of 16 rows); reach4 starts at 0.
+__global__ __launch_bounds__(256) void k_lattice_reach(const uint8_t* __restrict__ Sw, int m,
+                                                       unsigned long long* __restrict__ reach4) {
+    const int yb = blockIdx.x % ((m + 15) / 16), z = blockIdx.x / ((m + 15) / 16);
+    const long long dz = 2LL * z - m;
+    unsigned long long best = 0;
+    for (int y = yb * 16; y < m && y < yb * 16 + 16; ++y) {
+        const long long dy = 2LL * y - m, dyz = dy * dy + dz * dz;
+        const uint8_t* row = Sw + ((size_t)z * m + y) * m;
+        for (int x = threadIdx.x; x < m; x += 256) {
+            const long long dx = 2LL * x - m;
+            if (row[x]) best = max(best, (unsigned long long)(dyz + dx * dx));
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) best = max(best, (unsigned long long)__shfl_xor(best, off, 64));
+    __shared__ unsigned long long wbest[4];
+    if ((threadIdx.x & 63) == 0) wbest[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long b = max(max(wbest[0], wbest[1]), max(wbest[2], wbest[3]));
+        if (b) atomicMax(reach4, b);
+    }
+}
+
+// squared canvas radius (in voxels^2) beyond which S_r is zero, from reach4;
+// the small slack covers the rounding of the double rotation
+__device__ __forceinline__ double canvas_reach2(const unsigned long long* reach4) {
+    const double r = 0.5 * sqrt((double)*reach4) + 1.7320508075688772 + 1e-6;
+    return r * r;
+}
+
 // SO(3) samples -> rotation matrices (double math, float storage) + checks
 // transpose: store R^T, the map from canvas offsets to body-lattice offsets of
 // the rotated-object search
@@ -1940,7 +1978,8 @@ __global__ __launch_bounds__(Split<N>::RT) void k_split_rows_fwd(const uint8_t* 
                                                              const float* __restrict__ grid,
                                                              const float2* __restrict__ twg,
                                                              const double2* __restrict__ tw64,
-                                                             float2* __restrict__ xb, double2* __restrict__ lowrow) {
+                                                             float2* __restrict__ xb, double2* __restrict__ lowrow,
+                                                             const unsigned long long* __restrict__ reach4) {
     using C = Split<N>;
     constexpr int NT = C::RT, RB = C::RB;
     __shared__ float2 rows[RB * C::P];
@@ -1953,6 +1992,19 @@ __global__ __launch_bounds__(Split<N>::RT) void k_split_rows_fwd(const uint8_t* 
     float4* lut = reinterpret_cast<float4*>(scratch_lds);
     const int blk = blockIdx.x % C::NB, pl = blockIdx.x / C::NB;  // pl = rot * N + z
     const int rot = pl / N, z = pl % N, y0 = blk * RB;
+    if (SRC == 0 && reach4) {
+        // every row of the block beyond the swept lattice's reach: zero rows
+        // and zero low-block sums, without sampling or transforming them
+        const int yc = N / 2 < y0 ? y0 : N / 2 > y0 + RB - 1 ? y0 + RB - 1 : N / 2;
+        const double dy = yc - N / 2, dz = z - N / 2;
+        if (dy * dy + dz * dz > canvas_reach2(reach4)) {
+            float2* dst = xb + ((size_t)pl * N + y0) * C::N2;
+            for (int e = threadIdx.x; e < RB * C::N2; e += NT) dst[e] = make_float2(0.0f, 0.0f);
+            double2* lr = lowrow + ((size_t)pl * N + y0) * NLX;
+            for (int e = threadIdx.x; e < RB * NLX; e += NT) lr[e] = make_double2(0.0, 0.0);
+            return;
+        }
+    }
     for (int i = threadIdx.x; i < N; i += NT) {
         tw[i] = twg[i];
         tws[i] = tw64[i];
@@ -1984,7 +2036,8 @@ __global__ __launch_bounds__(Split<N>::RT) void k_split_rows_fwd(const uint8_t* 
 template <int N>
 __global__ __launch_bounds__(Split<N>::CT) void k_split_cols_fwd(const float2* __restrict__ xb,
                                                              const float2* __restrict__ twg,
-                                                             float2* __restrict__ spec) {
+                                                             float2* __restrict__ spec,
+                                                             const unsigned long long* __restrict__ reach4) {
     using C = Split<N>;
     constexpr int NT = C::CT, TT = C::T;
     __shared__ float2 buf[N * TT];  // [y][c]
@@ -1992,6 +2045,24 @@ __global__ __launch_bounds__(Split<N>::CT) void k_split_cols_fwd(const float2* _
     __shared__ float2 nyqb[N];
     const int t = blockIdx.x % C::NT2, pl = blockIdx.x / C::NT2;
     const int rot = pl / N, z = pl % N;
+    if (reach4) {
+        // a plane beyond the swept lattice's reach: its X rows are zero, so is
+        // its spectrum tile (and, for the tile of column 0, its Nyquist column)
+        const double dz = z - N / 2;
+        if (dz * dz > canvas_reach2(reach4)) {
+            float2* spec_rot = spec + (size_t)rot * C::H;
+            for (int e = threadIdx.x; e < N * TT; e += NT) {
+                const int ky = e / TT, c = e % TT;
+                spec_rot[((size_t)(ky * C::NT2 + t) * N + z) * C::T + c] = make_float2(0.0f, 0.0f);
+            }
+            if (t == 0) {
+                float2* nyq = spec_rot + (size_t)N * C::N2 * N;
+                for (int ky = threadIdx.x; ky < N; ky += NT)
+                    nyq[((size_t)(ky / C::T) * N + z) * C::T + (ky % C::T)] = make_float2(0.0f, 0.0f);
+            }
+            return;
+        }
+    }
     for (int i = threadIdx.x; i < N; i += NT) tw[i] = twg[i];
     const float2* src = xb + (size_t)pl * N * C::N2 + t * TT;
     for (int e = threadIdx.x; e < N * TT; e += NT) buf[e] = src[(size_t)(e / TT) * C::N2 + e % TT];
@@ -2208,8 +2279,8 @@ static hipError_t launch_split_pass(int pass, const SearchBatchArgs& a) {
     const unsigned rb = (unsigned)((size_t)a.count * N * C::NB), cb = (unsigned)((size_t)a.count * N * C::NT2);
     if (pass == 0) {
         hipLaunchKernelGGL((k_split_rows_fwd<N, 0>), dim3(rb), dim3(C::RT), 0, a.stream, a.cmask, a.m, a.mp / 4, a.rots,
-                           nullptr, a.tw, a.tw64, a.xbuf, a.lowrow);
-        hipLaunchKernelGGL(k_split_cols_fwd<N>, dim3(cb), dim3(C::CT), 0, a.stream, a.xbuf, a.tw, a.spec);
+                           nullptr, a.tw, a.tw64, a.xbuf, a.lowrow, a.reach4);
+        hipLaunchKernelGGL(k_split_cols_fwd<N>, dim3(cb), dim3(C::CT), 0, a.stream, a.xbuf, a.tw, a.spec, a.reach4);
         hipLaunchKernelGGL(k_split_low_y<N>, dim3((unsigned)a.count * N), dim3(256), 0, a.stream, a.lowrow, a.tw64,
                            a.lowT);
     } else {
@@ -2228,8 +2299,8 @@ static hipError_t launch_object_spectrum_split(const float* O, float2* spec_tmp,
     if (!xbuf || !lowrow) return hipErrorInvalidValue;
     const double scale = 1.0 / ((double)N * N * N);
     hipLaunchKernelGGL((k_split_rows_fwd<N, 1>), dim3(N * C::NB), dim3(C::RT), 0, s, nullptr, 0, 0, nullptr, O, tw, tw64,
-                       xbuf, lowrow);
-    hipLaunchKernelGGL(k_split_cols_fwd<N>, dim3(N * C::NT2), dim3(C::CT), 0, s, xbuf, tw, spec_tmp);
+                       xbuf, lowrow, nullptr);
+    hipLaunchKernelGGL(k_split_cols_fwd<N>, dim3(N * C::NT2), dim3(C::CT), 0, s, xbuf, tw, spec_tmp, nullptr);
     hipLaunchKernelGGL(k_split_low_y<N>, dim3(N), dim3(256), 0, s, lowrow, tw64, lowT_tmp);
     hipLaunchKernelGGL((k_zpass<N, 1, 256>), dim3(C::TILES), dim3(256), 0, s, spec_tmp, nullptr, W, tw, (float)scale);
     hipLaunchKernelGGL((k_low_combine<1, N>), dim3(1), dim3(256), 0, s, lowT_tmp, tw64, nullptr, scale, Wlow);
@@ -2423,6 +2494,13 @@ hipError_t setup_swept(const float* poses, int np, double r, double L, int m, in
 hipError_t setup_cellmask(const uint8_t* Sw, int m, int mp, uint8_t* cm, hipStream_t s) {
     const size_t mp3 = (size_t)mp * mp * mp;
     hipLaunchKernelGGL(k_cellmask, dim3((unsigned)((mp3 + 255) / 256)), dim3(256), 0, s, Sw, m, mp, cm);
+    return hipGetLastError();
+}
+
+hipError_t swept_reach(const uint8_t* Sw, int m, unsigned long long* reach4, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u8, dim3(1), dim3(256), 0, s, reinterpret_cast<uint8_t*>(reach4), sizeof(*reach4),
+                       (uint8_t)0);
+    hipLaunchKernelGGL(k_lattice_reach, dim3((unsigned)m * (unsigned)((m + 15) / 16)), dim3(256), 0, s, Sw, m, reach4);
     return hipGetLastError();
 }
 

@@ -4,7 +4,9 @@ plane buffer; edges above 180, or reg_params.split_plane), through the C ABI.
 - At 64^3 and 128^3 the split passes compute what the fused plane passes
   compute: scores within 1e-4 of the largest |score|, the same peaks up to
   ties inside that band, and float32 fields within the candidate window's
-  error bound of each other.
+  error bound of each other; also on a padded canvas (the 32^3 workload on
+  128^3) whose rows and planes beyond the swept lattice's reach the split
+  passes skip.
 - At 192^3 from the mesh, and at 360^3 (the padded, linear canvas of the
   128^3 workload), scores and peaks against the FP64 oracle's intervals.
 """
@@ -38,10 +40,13 @@ def _flat(sh, n):
     return (d[:, 2] * n + d[:, 1]) * n + d[:, 0]
 
 
-@pytest.mark.parametrize("cfg,n,h,M", [(2, 64, 0.25, 128), (3, 128, 0.12, 128)])
+@pytest.mark.parametrize("cfg,n,h,M", [(2, 64, 0.25, 128), (3, 128, 0.12, 128), (1, 128, 0.4, 64)])
 def test_split_passes_equal_the_fused_passes(cfg, n, h, M):
+    """The last case pads the 32^3 workload to 128^3, where most rows and
+    planes of S_r lie beyond the swept lattice's reach: the split passes write
+    them as zeros unsampled, the fused passes sample and transform them."""
     rd = _lib()
-    p = synth.config_problem(cfg, 0, M=M)
+    p = synth.config_problem(cfg, 0, n=n, h=h, M=M)
     hf = _handle(rd, p)
     hs = _handle(rd, p, split_plane=1)
     try:

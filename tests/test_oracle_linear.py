@@ -9,7 +9,12 @@ each canvas axis padded to at least n_o + n_s - 1) in the oracle:
   maxima and peak shifts agree; with the canvas one point short they need not;
 * linear_edge's extents hold the actual supports of the object grid and of
   resampled swept grids on the padded canvas of the smallest workload, and
-  the probe reach is the farthest of densely sampled probe rims.
+  the probe reach is the farthest of densely sampled probe rims;
+* the swept lattice's reach (the farthest occupied lattice point from the
+  lattice centre) bounds the support of every resampled swept grid by that
+  radius plus sqrt(3) voxels about the canvas centre, nearly tightly: the
+  bound by which the split plane passes write rows and planes of S_r as
+  zeros without sampling them.
 """
 import math
 
@@ -130,3 +135,27 @@ def test_linear_edge_holds_the_supports_of_the_smallest_workload():
     assert all(0 < e <= n_s for e in ext)
     # on the workload's own 32^3 canvas the swept grid is clipped: it wraps
     assert n_s > p.n
+
+
+def test_lattice_reach_bounds_the_rotated_swept_support():
+    p = synth.config_problem(1, 0)
+    n = 120                                   # the padded canvas of the smallest workload
+    m = S.lattice_edge(n)
+    Sw = S.swept_occupancy(S.swept_lattice(p.poses, p.radius, p.length, m, p.h, p.center))
+    occ = np.argwhere(Sw > 0)                 # (z, y, x) of occupied lattice points
+    reach4 = int(((2 * occ - m) ** 2).sum(axis=1).max())
+    bound = 0.5 * math.sqrt(reach4) + math.sqrt(3.0)
+    a = S.anchor(p.vertices)
+    k = np.arange(n) - n / 2
+    kz, ky, kx = np.meshgrid(k, k, k, indexing="ij")
+    radius = np.sqrt(kx ** 2 + ky ** 2 + kz ** 2)
+    far = []
+    for q in p.so3[:4]:
+        Sr = S.resample(Sw, q, n, p.h, a, p.center)
+        far.append(float(radius[Sr != 0].max()))
+    print(f"\nlattice reach {0.5 * math.sqrt(reach4):.2f} voxels, bound {bound:.2f}, farthest nonzero {far}")
+    assert max(far) <= bound
+    assert min(far) >= bound - 2.0 * math.sqrt(3.0)
+    # the bound leaves a good part of the padded canvas's rows empty
+    rows = (ky[:, :, 0] ** 2 + kz[:, :, 0] ** 2) > bound ** 2
+    assert rows.mean() > 0.2
