@@ -9,6 +9,8 @@ plane buffer; edges above 180, or reg_params.split_plane), through the C ABI.
   passes skip.
 - At 192^3 from the mesh, and at 360^3 (the padded, linear canvas of the
   128^3 workload), scores and peaks against the FP64 oracle's intervals.
+- Served and captured in a batch graph, the split passes give the direct
+  call's results bit for bit.
 """
 import math
 
@@ -145,3 +147,48 @@ def test_linear_canvas_of_the_128_workload():
     sel = sorted({0, int(np.argmax(sc))})
     _oracle_check(p, sc, sh, sel, "linear 360^3 (128^3 workload)")
     assert st["uncertain"] == 0
+
+
+def _eager(rd, h):
+    sc, _, po = rd.score_rotations(h, shift=False)
+    top = rd.register_top_k(h, sc, 16)
+    out, J, _ = rd.refine_se3(h, po[top.long()])
+    return dict(scores=sc.cpu().numpy(), poses=po.cpu().numpy(), top=top.cpu().numpy(), refined=out.cpu().numpy(),
+                J=J.cpu().numpy())
+
+
+def test_split_served_and_batched_equal_the_direct_path():
+    """The split plane passes through the server (params.split_plane on the
+    request) and captured in a batch graph give the direct call's peaks,
+    poses and refined poses bit for bit (64^3, two registrations of 128
+    rotations, two lanes)."""
+    rd = _lib()
+    ps = [synth.batch_problem(i, level=4, lmax=6, N=400, M=128, n=64, h=0.24) for i in range(2)]
+    hs = [_handle(rd, p, split_plane=1, batch=32) for p in ps]
+    try:
+        ref = [_eager(rd, h) for h in hs]
+        b = rd.Batch(hs, top_k=16, graph_rounds=8, branches=2)
+        try:
+            for rep in range(2):
+                b.run()
+                for i in range(len(hs)):
+                    got = b.outputs(i)
+                    for k in ("scores", "poses", "top", "refined", "J"):
+                        assert np.array_equal(got[k], ref[i][k]), (rep, i, k)
+        finally:
+            b.close()
+    finally:
+        for h in hs:
+            rd.register_free(h)
+    srv = rd.Server(max_inflight=2)
+    try:
+        got = [srv.wait(srv.submit(p.vertices, p.faces, p.touchable, p.poses, p.so3, p.n, p.h, p.center, p.radius,
+                                   p.length, params=dict(split_plane=1, batch=32))) for p in ps]
+    finally:
+        srv.close()
+    for r, e in zip(got, ref):
+        assert r["status"] == 0
+        assert np.array_equal(r["top_rot"], e["top"])
+        assert np.array_equal(r["top_pose"], e["poses"][e["top"]])
+        assert np.array_equal(r["refined_pose"], e["refined"])
+        assert np.array_equal(r["refined_J"], e["J"])
