@@ -283,6 +283,14 @@ int register_debug_object_grid(reg_handle* h, float* out_O, float* out_fo);
 /* Copy the swept occupancy S_w (m^3 uint8, 0/1) to a device buffer. */
 int register_debug_swept(reg_handle* h, uint8_t* out_Sw);
 
+/* The swept lattice's reach as the split plane passes hold it: the largest
+ * (2x - m)^2 + (2y - m)^2 + (2z - m)^2 over the occupied points of S_w (0 for
+ * an empty lattice); rows and planes of S_r farther than sqrt(reach4) / 2 +
+ * sqrt(3) voxels from the canvas centre are zero, and those passes write them
+ * unsampled.  Host pointer; synchronises the stream.  REG_ENOTSUP for a
+ * handle on the fused plane passes, which do not compute it. */
+int register_debug_swept_reach(reg_handle* h, int64_t* out_reach4);
+
 /* Full correlation C (n^3 float) of SO(3) sample `rot` into a device buffer
  * (C' of the rotated-object search, indexed by e). */
 int register_debug_correlation(reg_handle* h, int32_t rot, float* out_C);

@@ -23,7 +23,8 @@ _NAMES = {-1: "REG_EINVAL", -2: "REG_ENOMEM", -3: "REG_EDEVICE", -4: "REG_EBUSY"
 
 # every entry point the header declares
 EXPORTS = ["register_init", "score_rotations", "register_top_k", "register_free", "register_last_error",
-           "register_info", "register_debug_object_grid", "register_debug_swept", "register_debug_correlation",
+           "register_info", "register_debug_object_grid", "register_debug_swept", "register_debug_swept_reach",
+           "register_debug_correlation",
            "register_set_grids", "register_set_timing", "register_get_timing", "register_search_stats",
            "refine_se3", "register_debug_distance", "register_refine_stats", "register_server_create",
            "register_server_destroy", "register_submit", "register_poll", "register_wait", "register_server_stats",
@@ -139,6 +140,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.register_debug_object_grid.argtypes = [p, p, p]
     L.register_debug_swept.restype = ctypes.c_int
     L.register_debug_swept.argtypes = [p, p]
+    L.register_debug_swept_reach.restype = ctypes.c_int
+    L.register_debug_swept_reach.argtypes = [p, ctypes.POINTER(i64)]
     L.register_debug_correlation.restype = ctypes.c_int
     L.register_debug_correlation.argtypes = [p, i32, p]
     L.register_set_grids.restype = ctypes.c_int
@@ -312,6 +315,14 @@ def register_debug_swept(h: Handle):
     S = torch.empty((h.m,) * 3, dtype=torch.uint8, device="cuda")
     _check(load_library().register_debug_swept(h.ptr, _ptr(S)))
     return S
+
+
+def register_debug_swept_reach(h: Handle) -> int:
+    """Max over occupied points of S_w of (2x-m)^2 + (2y-m)^2 + (2z-m)^2, as
+    the split plane passes hold it (REG_ENOTSUP on the fused passes)."""
+    v = ctypes.c_int64()
+    _check(load_library().register_debug_swept_reach(h.ptr, ctypes.byref(v)))
+    return v.value
 
 
 def register_debug_correlation(h: Handle, rot: int):

@@ -1567,6 +1567,17 @@ int register_debug_swept(reg_handle* h, uint8_t* out_Sw) {
     return REG_OK;
 }
 
+int register_debug_swept_reach(reg_handle* h, int64_t* out_reach4) {
+    if (!h || !out_reach4) return fail(REG_EINVAL, "NULL argument");
+    if (h->poisoned) return fail(REG_EDEVICE, "handle poisoned by an earlier device error");
+    if (!h->reach4) return fail(REG_ENOTSUP, "the fused plane passes do not compute the swept lattice's reach");
+    unsigned long long v = 0;
+    DEV_TRY(h, hipMemcpyAsync(&v, h->reach4, sizeof(v), hipMemcpyDeviceToHost, h->stream));
+    DEV_TRY(h, hipStreamSynchronize(h->stream));
+    *out_reach4 = (int64_t)v;
+    return REG_OK;
+}
+
 int register_debug_correlation(reg_handle* h, int32_t rot, float* out_C) {
     if (!h || !out_C) return fail(REG_EINVAL, "NULL argument");
     if (h->poisoned) return fail(REG_EDEVICE, "handle poisoned by an earlier device error");

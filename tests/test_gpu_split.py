@@ -11,6 +11,8 @@ plane buffer; edges above 180, or reg_params.split_plane), through the C ABI.
   128^3 workload), scores and peaks against the FP64 oracle's intervals.
 - Served and captured in a batch graph, the split passes give the direct
   call's results bit for bit.
+- The reach of the swept lattice (by which the split passes skip rows and
+  planes of S_r) equals the host's maximum over the same lattice.
 """
 import math
 
@@ -192,3 +194,27 @@ def test_split_served_and_batched_equal_the_direct_path():
         assert np.array_equal(r["top_pose"], e["poses"][e["top"]])
         assert np.array_equal(r["refined_pose"], e["refined"])
         assert np.array_equal(r["refined_J"], e["J"])
+
+
+def test_swept_reach_equals_the_lattice_maximum():
+    """The reach kernel's integer maximum over the occupied points of the
+    handle's own S_w equals the host's, bit for bit (the 32^3 workload padded
+    to 128^3, m = 224), and the fused passes refuse the query."""
+    rd = _lib()
+    p = synth.config_problem(1, 0, n=128, h=0.4, M=16)
+    hs = _handle(rd, p, split_plane=1)
+    hf = _handle(rd, p)
+    try:
+        got = rd.register_debug_swept_reach(hs)
+        Sw = rd.register_debug_swept(hs).cpu().numpy()
+        with pytest.raises(rd.RegError) as e:
+            rd.register_debug_swept_reach(hf)
+        assert e.value.code == rd.REG_ENOTSUP
+    finally:
+        rd.register_free(hs)
+        rd.register_free(hf)
+    m = Sw.shape[0]
+    occ = np.argwhere(Sw != 0).astype(np.int64)
+    want = int(((2 * occ - m) ** 2).sum(axis=1).max())
+    print(f"m {m}, occupied {len(occ)}, reach {0.5 * math.sqrt(want):.3f} voxels")
+    assert got == want
