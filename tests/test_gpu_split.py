@@ -7,8 +7,9 @@ plane buffer; edges above 180, or reg_params.split_plane), through the C ABI.
   error bound of each other; also on a padded canvas (the 32^3 workload on
   128^3) whose rows and planes beyond the swept lattice's reach the split
   passes skip.
-- At 192^3 from the mesh, and at 360^3 (the padded, linear canvas of the
-  128^3 workload), scores and peaks against the FP64 oracle's intervals.
+- At 192^3 and 256^3 from the mesh, and at 360^3 (the padded, linear canvas
+  of the 128^3 workload), scores and peaks against the FP64 oracle's
+  intervals.
 - Served and captured in a batch graph, the split passes give the direct
   call's results bit for bit.
 - The reach of the swept lattice (by which the split passes skip rows and
@@ -112,11 +113,13 @@ def _oracle_check(p, sc, sh, sel, label):
         assert int(fl[i]) in set(S.peak_admissible(C, B, l, tol).tolist())
 
 
-def test_split_edge_192_from_the_mesh():
-    """A canvas above the fused passes' LDS limit: 192^3 (h = 0.08 mm) from
-    the mesh, two rotations against the oracle's intervals."""
+@pytest.mark.parametrize("n,h", [(192, 0.08), (256, 0.06)])
+def test_split_edge_from_the_mesh(n, h):
+    """Canvases above the fused passes' LDS limit (192^3 at h = 0.08 mm, 256^3
+    at 0.06 mm; the 256-point transforms take radix-16 passes) from the mesh,
+    two rotations against the oracle's intervals."""
     rd = _lib()
-    p = synth.config_problem(1, 1, n=192, h=0.08, M=16)
+    p = synth.config_problem(1, 1, n=n, h=h, M=16)
     so3 = p.so3[:2]
     hd = _handle(rd, p, so3=so3, batch=8)
     try:
@@ -125,7 +128,7 @@ def test_split_edge_192_from_the_mesh():
     finally:
         rd.register_free(hd)
     p.so3 = so3
-    _oracle_check(p, sc, sh, [0, 1], "split 192^3")
+    _oracle_check(p, sc, sh, [0, 1], f"split {n}^3")
     assert st["uncertain"] == 0
 
 
