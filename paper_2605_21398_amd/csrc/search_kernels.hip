@@ -1948,7 +1948,9 @@ __global__ void k_validate(const float* __restrict__ V, int nv, const int32_t* _
 // The z pass, the low-block combine and the candidate selection are the fused
 // path's (one record of keys per row block instead of per plane).  A rotation
 // moves 8 H8 through HBM instead of 4 H8: each split pass writes and reads
-// the plane buffer once more.
+// the plane buffer once more.  Given the swept lattice's reach
+// (k_lattice_reach), the forward row pass writes row blocks beyond it as
+// zeros unsampled, and the forward column pass does the same for planes.
 template <int N> struct Split : Dims<N> {
     using D = Dims<N>;
     using D::N2;
@@ -1957,7 +1959,7 @@ template <int N> struct Split : Dims<N> {
     using D::T;
     using D::NT2;
     // rows per row-pass workgroup: above 180 at most 16, which keeps a row
-    // workgroup's LDS low enough for three (forward) or four (inverse) per CU
+    // workgroup's LDS low enough for three (forward) or more (inverse) per CU
     // (at 360^3: 15 rows against 30 gave 1.2x the rotations/s)
     static constexpr int RB = largest_divisor_le(N, N > 180 ? 16 : 32);
     static constexpr int NB = N / RB;  // row blocks per plane
