@@ -283,12 +283,13 @@ int register_debug_object_grid(reg_handle* h, float* out_O, float* out_fo);
 /* Copy the swept occupancy S_w (m^3 uint8, 0/1) to a device buffer. */
 int register_debug_swept(reg_handle* h, uint8_t* out_Sw);
 
-/* The swept lattice's reach as the split plane passes hold it: the largest
+/* The swept lattice's reach as the search holds it: the largest
  * (2x - m)^2 + (2y - m)^2 + (2z - m)^2 over the occupied points of S_w (0 for
- * an empty lattice); rows and planes of S_r farther than sqrt(reach4) / 2 +
- * sqrt(3) voxels from the canvas centre are zero, and those passes write them
- * unsampled.  Host pointer; synchronises the stream.  REG_ENOTSUP for a
- * handle on the fused plane passes, which do not compute it. */
+ * an empty lattice).  Rows and planes of S_r farther than sqrt(reach4) / 2 +
+ * sqrt(3) voxels from the canvas centre are zero; the split plane passes write
+ * such row blocks and planes unsampled, the fused pass 1 such planes.  Host
+ * pointer; synchronises the stream.  REG_ENOTSUP for the rotated-object
+ * search, which does not compute it. */
 int register_debug_swept_reach(reg_handle* h, int64_t* out_reach4);
 
 /* Full correlation C (n^3 float) of SO(3) sample `rot` into a device buffer

@@ -319,7 +319,7 @@ def register_debug_swept(h: Handle):
 
 def register_debug_swept_reach(h: Handle) -> int:
     """Max over occupied points of S_w of (2x-m)^2 + (2y-m)^2 + (2z-m)^2, as
-    the split plane passes hold it (REG_ENOTSUP on the fused passes)."""
+    the search holds it (REG_ENOTSUP for the rotated-object search)."""
     v = ctypes.c_int64()
     _check(load_library().register_debug_swept_reach(h.ptr, ctypes.byref(v)))
     return v.value

@@ -268,7 +268,7 @@ struct reg_handle {
     float2* xbuf2 = nullptr;
     double2* lowrow = nullptr;
     double2* lowrow2 = nullptr;
-    unsigned long long* reach4 = nullptr;  // the swept lattice's reach (rows beyond it are skipped)
+    unsigned long long* reach4 = nullptr;  // the swept lattice's reach (S_r beyond it is skipped)
     float2* tw = nullptr;
     double2* tw64 = nullptr;
     double2* lowT = nullptr;
@@ -861,8 +861,8 @@ static int init_impl(const reg_mesh* mesh, const reg_probe* probe, const float* 
     if (h->split) {
         ALLOC_TRY(h, h->xbuf, split_plane_elems(h->n) * (size_t)h->batch);
         ALLOC_TRY(h, h->lowrow, (size_t)h->n * h->n * NLX * (size_t)h->batch);
-        ALLOC_TRY(h, h->reach4, 1);
     }
+    if (!h->rotobj) ALLOC_TRY(h, h->reach4, 1);
     ALLOC_TRY(h, h->stats, 5);
     ALLOC_TRY(h, h->need_count, 1);
     ALLOC_TRY(h, h->Sw, m3);
@@ -1570,7 +1570,7 @@ int register_debug_swept(reg_handle* h, uint8_t* out_Sw) {
 int register_debug_swept_reach(reg_handle* h, int64_t* out_reach4) {
     if (!h || !out_reach4) return fail(REG_EINVAL, "NULL argument");
     if (h->poisoned) return fail(REG_EDEVICE, "handle poisoned by an earlier device error");
-    if (!h->reach4) return fail(REG_ENOTSUP, "the fused plane passes do not compute the swept lattice's reach");
+    if (!h->reach4) return fail(REG_ENOTSUP, "the rotated-object search does not compute the swept lattice's reach");
     unsigned long long v = 0;
     DEV_TRY(h, hipMemcpyAsync(&v, h->reach4, sizeof(v), hipMemcpyDeviceToHost, h->stream));
     DEV_TRY(h, hipStreamSynchronize(h->stream));

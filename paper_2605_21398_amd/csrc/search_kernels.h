@@ -58,8 +58,9 @@ struct SearchBatchArgs {
     // x sums of the low block [count][n][n][NLX]; NULL selects the fused passes
     float2* xbuf = nullptr;
     double2* lowrow = nullptr;
-    // split plane passes: the swept lattice's reach (swept_reach); rows and
-    // planes of S_r beyond it are written as zeros unsampled.  NULL: no skip
+    // the swept lattice's reach (swept_reach): the split passes write row
+    // blocks and planes of S_r beyond it as zeros unsampled, the fused pass 1
+    // such planes.  NULL: no skip
     const unsigned long long* reach4 = nullptr;
 };
 

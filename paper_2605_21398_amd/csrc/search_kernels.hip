@@ -488,6 +488,16 @@ __device__ __forceinline__ void plane_low_dft(const float2* plane, const double2
 // S_r at canvas voxel (x, y, z) for rotation R: u = R (k - N/2) + m/2 in double
 // (the lattice spans ~2N voxels, where float32 would leave ~1e-5 voxel of
 // position error), then trilinear weights in float from the corner mask.
+// Squared canvas radius (in voxels^2) beyond which S_r is zero, from the swept
+// lattice's reach4 (k_lattice_reach): a rotated canvas voxel k samples a cell
+// with an occupied corner only if |k - n/2| <= sqrt(reach4) / 2 + sqrt(3).  The
+// small slack covers the rounding of the double rotation and of the
+// generator's fixed-point walk.
+__device__ __forceinline__ double canvas_reach2(const unsigned long long* reach4) {
+    const double r = 0.5 * sqrt((double)*reach4) + 1.7320508075688772 + 1e-6;
+    return r * r;
+}
+
 struct RotSampler {
     double r00, r01, r02, r10, r11, r12, r20, r21, r22;
     double hm, hn;
@@ -755,7 +765,8 @@ __global__ __launch_bounds__(NT, WPE) void k_rotvox_fwd_xy(const uint8_t* __rest
                                                        const double* __restrict__ rots, int count,
                                                        const float2* __restrict__ twg, const double2* __restrict__ tw64,
                                                        float2* __restrict__ spec, double2* __restrict__ lowT,
-                                                       const float4* __restrict__ crec, float cval) {
+                                                       const float4* __restrict__ crec, float cval,
+                                                       const unsigned long long* __restrict__ reach4) {
     using C = Canvas<N>;
     __shared__ float2 plane[N * C::P];
     __shared__ float2 tw[N];
@@ -770,6 +781,24 @@ __global__ __launch_bounds__(NT, WPE) void k_rotvox_fwd_xy(const uint8_t* __rest
     static_assert(N <= NT, "one twiddle per thread at most");
     int rot, z;
     map_plane_block(blockIdx.x, count, N, rot, z);
+    if (!REC && reach4) {
+        // a plane beyond the swept lattice's reach (on a padded canvas): S_r is
+        // zero there, and so are its spectrum slices and low-block sums
+        const double dz = z - N / 2;
+        if (dz * dz > canvas_reach2(reach4)) {
+            float2* spec_rot = spec + (size_t)rot * C::H;
+            for (int e = threadIdx.x; e < N * C::N2; e += NT) {
+                const int ky = e / C::N2, kx = e % C::N2;
+                spec_rot[((size_t)(ky * C::NT2 + kx / C::T) * N + z) * C::T + (kx % C::T)] = make_float2(0.0f, 0.0f);
+            }
+            float2* nyq = spec_rot + (size_t)N * C::N2 * N;
+            for (int ky = threadIdx.x; ky < N; ky += NT)
+                nyq[((size_t)(ky / C::T) * N + z) * C::T + (ky % C::T)] = make_float2(0.0f, 0.0f);
+            double2* lo = lowT + ((size_t)rot * N + z) * NLOW2;
+            for (int e = threadIdx.x; e < NLOW2; e += NT) lo[e] = make_double2(0.0, 0.0);
+            return;
+        }
+    }
     // the global loads (twiddles, rotation) go out first; the tables are built
     // while they are in flight
     const int tid = threadIdx.x;
@@ -1839,13 +1868,6 @@ __global__ __launch_bounds__(256) void k_lattice_reach(const uint8_t* __restrict
     }
 }
 
-// squared canvas radius (in voxels^2) beyond which S_r is zero, from reach4;
-// the small slack covers the rounding of the double rotation
-__device__ __forceinline__ double canvas_reach2(const unsigned long long* reach4) {
-    const double r = 0.5 * sqrt((double)*reach4) + 1.7320508075688772 + 1e-6;
-    return r * r;
-}
-
 // SO(3) samples -> rotation matrices (double math, float storage) + checks
 // transpose: store R^T, the map from canvas offsets to body-lattice offsets of
 // the rotated-object search
@@ -2238,10 +2260,10 @@ static void launch_plane(int pass, const SearchBatchArgs& a) {
             // the rotated-object search compiles pass 1 for the default workgroup only
             if constexpr (V == default_plane_variant_of(N))
                 hipLaunchKernelGGL((k_rotvox_fwd_xy<N, NT, WPE, true>), dim3(a.count * N), dim3(NT), 0, a.stream, a.cmask,
-                                   a.m, a.mp / 4, a.rots, a.count, a.tw, a.tw64, a.spec, a.lowT, a.crec, a.cval);
+                                   a.m, a.mp / 4, a.rots, a.count, a.tw, a.tw64, a.spec, a.lowT, a.crec, a.cval, nullptr);
         } else if (pass == 0)
             hipLaunchKernelGGL((k_rotvox_fwd_xy<N, NT, WPE, false>), dim3(a.count * N), dim3(NT), 0, a.stream, a.cmask,
-                               a.m, a.mp / 4, a.rots, a.count, a.tw, a.tw64, a.spec, a.lowT, nullptr, 0.0f);
+                               a.m, a.mp / 4, a.rots, a.count, a.tw, a.tw64, a.spec, a.lowT, nullptr, 0.0f, a.reach4);
         else
             hipLaunchKernelGGL((k_inv_xy_argmax<N, NT, WPE>), dim3(a.count * N), dim3(NT), 0, a.stream, a.spec, a.count,
                                a.tw, a.tw64, a.Plow, a.ptop, a.pssq, a.corr_out);

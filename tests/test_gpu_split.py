@@ -202,22 +202,26 @@ def test_split_served_and_batched_equal_the_direct_path():
 def test_swept_reach_equals_the_lattice_maximum():
     """The reach kernel's integer maximum over the occupied points of the
     handle's own S_w equals the host's, bit for bit (the 32^3 workload padded
-    to 128^3, m = 224), and the fused passes refuse the query."""
+    to 128^3, m = 224), on the split and the fused passes; the rotated-object
+    search refuses the query."""
     rd = _lib()
     p = synth.config_problem(1, 0, n=128, h=0.4, M=16)
     hs = _handle(rd, p, split_plane=1)
     hf = _handle(rd, p)
+    ho = _handle(rd, p, rotate_object=1)
     try:
         got = rd.register_debug_swept_reach(hs)
+        got_f = rd.register_debug_swept_reach(hf)
         Sw = rd.register_debug_swept(hs).cpu().numpy()
         with pytest.raises(rd.RegError) as e:
-            rd.register_debug_swept_reach(hf)
+            rd.register_debug_swept_reach(ho)
         assert e.value.code == rd.REG_ENOTSUP
     finally:
         rd.register_free(hs)
         rd.register_free(hf)
+        rd.register_free(ho)
     m = Sw.shape[0]
     occ = np.argwhere(Sw != 0).astype(np.int64)
     want = int(((2 * occ - m) ** 2).sum(axis=1).max())
     print(f"m {m}, occupied {len(occ)}, reach {0.5 * math.sqrt(want):.3f} voxels")
-    assert got == want
+    assert got == want and got_f == want
